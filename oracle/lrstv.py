@@ -111,10 +111,10 @@ def grad_w_t(Y: np.ndarray, w: Sequence[float]) -> np.ndarray:
 def diff_kernel(shape: Tuple[int, int, int], n: int) -> np.ndarray:
     """Impulse response of D_n: D_n x = kernel (circular convolution) x."""
     k = np.zeros(shape)
-    k[(0, 0, 0)] = -1.0
+    k[(0, 0, 0)] -= 1.0
     idx = [0, 0, 0]
     idx[AXIS[n]] = -1          # (D_n x)[i] picks x[i + e_n]  <=>  kernel[-e_n] = +1
-    k[tuple(idx)] = 1.0
+    k[tuple(idx)] += 1.0       # on an axis of length 1 both taps coincide: D_n = 0
     return k
 
 

@@ -204,9 +204,9 @@ def test_diff_adjoint_dense(n):
     assert abs((oracle.diff(x, n) * y).sum() - (x * oracle.diff_t(y, n)).sum()) < 1e-12
 
 
-def test_pz_equals_closed_form_spectrum():
+@pytest.mark.parametrize("shape", [(5, 4, 3), (1, 4, 3), (5, 1, 3), (2, 3, 1), (2, 2, 2)])
+def test_pz_equals_closed_form_spectrum(shape):
     """Eigenvalues of sum w_n^2 D_n^T D_n are sum w_n^2 4 sin^2(pi k_n / N_n)."""
-    shape = (5, 4, 3)   # (b, h, w)
     w = (0.7, 1.3, 0.4)
     b, h, wd = shape
     kb, kh, kw = np.meshgrid(np.arange(b), np.arange(h), np.arange(wd), indexing="ij")
