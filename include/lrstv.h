@@ -1,0 +1,189 @@
+/*
+ * lrstv.h -- C ABI of the MI355X (gfx950) LRSTV ADMM library.
+ *
+ * The library runs the per-iteration ADMM sweep of the LRSTV / TDLRSTV
+ * hyperspectral denoiser (Zeng et al., "Low-rank Meets Sparseness",
+ * Sec. III-C, Algorithm 1) at full Tucker rank, for a batch of cubes of
+ * possibly different sizes.  Model: the observed cube Y (the paper's O) is
+ * split as Y = X + S + N with X the denoised cube (the paper's L), S sparse
+ * noise and N = Y - X - S the remaining Gaussian part, by minimising
+ *     2 tau ||D_w X||_1 + alpha sum_n TNN(w_n D_n X) + lambda ||S||_1
+ * subject to Y = X + S (the factor 2 on tau is the weight for which the
+ * paper's printed F-step threshold tau/mu is the exact block minimiser).
+ *
+ * Conventions shared by every call
+ *   - Return value: 0 = success, > 0 = warning with valid outputs,
+ *     < 0 = error (outputs undefined).  lrstv_last_error() gives a message.
+ *   - Every float* / double* argument documented as "device" is a pointer
+ *     to GPU memory of the current HIP device; "host" pointers are CPU memory.
+ *   - A cube is FP32, band-major [b][h][w] with w fastest (a contiguous
+ *     torch tensor of shape (b, h, w)).  A batch of cubes is packed back to
+ *     back in one buffer: cube c starts at element sum_{c' < c} b h w.
+ *   - All GPU work is enqueued asynchronously on the caller's stream
+ *     (a hipStream_t passed as void*); only calls documented as
+ *     synchronising wait for it.
+ *   - The library never allocates device memory in the solver calls: the
+ *     caller provides a workspace of at least lrstv_workspace_size() bytes
+ *     that outlives the handle.  A handle is not thread-safe; separate
+ *     handles are independent.
+ *   - Nothing throws across the ABI.
+ */
+#ifndef LRSTV_H
+#define LRSTV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define LRSTV_OK                   0
+#define LRSTV_WARN_NOT_CONVERGED   1   /* eps not reached within max_iter     */
+#define LRSTV_ERR_INVALID_ARG     -1   /* bad size, weight, pointer or flag   */
+#define LRSTV_ERR_WORKSPACE       -2   /* workspace too small                 */
+#define LRSTV_ERR_UNSUPPORTED     -3   /* size beyond what the kernels handle */
+#define LRSTV_ERR_HIP             -4   /* a HIP runtime call failed           */
+#define LRSTV_ERR_NONFINITE       -5   /* NaN/Inf met in the input or state   */
+
+/* ---- precision of the slice Gram / back-projection products ------------ */
+#define LRSTV_FP32        0   /* plain FP32 products                           */
+#define LRSTV_SPLIT_BF16  1   /* 3-term split-BF16 MFMA products, FP32 accum   */
+
+/* Residuals recorded per iteration and per cube (FP64), in this order:
+ *   0 ||Y - X - S||_inf, 1 ||X - Z||_inf   (Algorithm 1 stopping test)
+ *   2 ||Y - X - S||_F,   3 ||X - Z||_F,   4 ||D_w Z - F||_F,  5 ||E - F||_F
+ *   6 mu ||Z_new - Z_old||_F (dual residual)                                 */
+#define LRSTV_NRES 7
+
+/* Largest slice side (min(h, w)) the t-SVT kernels accept, and the largest
+ * side of any FFT axis. */
+#define LRSTV_MAX_SIDE 512
+
+typedef struct lrstv_problem {
+  int32_t n_cubes;         /* >= 1                                          */
+  const int32_t* h;        /* host [n_cubes], each >= 1                     */
+  const int32_t* w;        /* host [n_cubes], each >= 1                     */
+  const int32_t* b;        /* host [n_cubes], each >= 1 (bands)             */
+} lrstv_problem;
+
+typedef struct lrstv_params {
+  double tau;      /* gradient-sparsity weight  (>= 0)                       */
+  double alpha;    /* gradient low-rank weight  (>= 0), t-SVT threshold alpha/mu */
+  double lambda;   /* sparse-noise weight       (>= 0); the paper's rule is
+                      lambda = C / sqrt(h w)                                 */
+  double w[3];     /* difference weights w_1 (height), w_2 (width),
+                      w_3 (bands), each >= 0                                 */
+  double mu0;      /* initial penalty (> 0)                                  */
+  double rho;      /* penalty growth (>= 1): mu <- min(rho mu, mu_max)       */
+  double mu_max;   /* penalty cap (>= mu0)                                   */
+  int32_t precision;  /* LRSTV_FP32 or LRSTV_SPLIT_BF16                      */
+} lrstv_params;
+
+typedef struct lrstv_state_view {
+  /* Device pointers into the workspace, each a packed batch of cubes, or
+   * for the gradient-shaped variables three packed batches back to back
+   * ([3][batch]: component n of cube c starts at n * total + offset(c),
+   * with total = sum_c b h w).  Valid until lrstv_destroy.               */
+  float* X;     /* L of the last iteration (the denoised estimate)        */
+  float* Y;     /* the observed cube O (read-only for the solver)         */
+  float* Z;
+  float* S;
+  float* G1;
+  float* G2;
+  float* F;     /* [3][batch] */
+  float* E;     /* [3][batch] */
+  float* G3;    /* [3][batch] */
+  float* G4;    /* [3][batch] */
+  double* mu;   /* device scalar: the penalty the next iteration uses     */
+  int64_t total;   /* sum over cubes of b h w                             */
+} lrstv_state_view;
+
+typedef struct lrstv_report {
+  int32_t iters;                 /* iterations run                        */
+  double residuals[LRSTV_NRES];  /* last iteration, max over cubes        */
+  double mu;                     /* penalty after the last iteration      */
+} lrstv_report;
+
+typedef struct lrstv_handle_s* lrstv_handle;
+
+/* Bytes of device workspace a solver handle needs for this batch.
+ * Errors: INVALID_ARG (null pointers, sizes < 1, bad params),
+ * UNSUPPORTED (a side above LRSTV_MAX_SIDE). */
+int lrstv_workspace_size(const lrstv_problem* prob, const lrstv_params* par, size_t* bytes);
+
+/* Create a solver for the batch in `prob`.  `workspace` (device, >= the
+ * queried size, 256-byte aligned) is owned by the caller and must outlive
+ * the handle; `stream` (hipStream_t) is where all work is enqueued.
+ * The host-side handle is allocated by the library and freed by
+ * lrstv_destroy.  Errors: INVALID_ARG, WORKSPACE, UNSUPPORTED, HIP. */
+int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const lrstv_params* par,
+                 void* workspace, size_t ws_bytes, void* stream);
+
+/* Algorithm 1 initialisation: O <- Y (device, packed batch, borrowed for the
+ * call), Z <- Y, S = F = E = Gamma_i = 0, mu <- mu0.
+ * Errors: INVALID_ARG, HIP. */
+int lrstv_reset(lrstv_handle hd, const float* Y);
+
+/* Run n_iter ADMM iterations (Sec. III-C steps 1-7).  If `residuals` is not
+ * NULL it is a device array of n_iter * n_cubes * LRSTV_NRES doubles that
+ * receives [iter][cube][LRSTV_NRES].  Asynchronous; no host sync.
+ * Errors: INVALID_ARG, HIP. */
+int lrstv_iterate(lrstv_handle hd, int32_t n_iter, double* residuals);
+
+/* Copy X = L of the last iteration and S into caller buffers (device,
+ * packed batch).  Either may be NULL.  Asynchronous. */
+int lrstv_read_output(lrstv_handle hd, float* X, float* S);
+
+/* reset + iterate until max{||Y-X-S||_inf, ||X-Z||_inf} <= eps for every
+ * cube (Algorithm 1 stopping test; eps <= 0 runs exactly max_iter) + copy
+ * X and S out (device, may be NULL).  Synchronises the stream to read the
+ * residuals.  `rep` (host) may be NULL.  Returns WARN_NOT_CONVERGED if
+ * eps > 0 was not met, ERR_NONFINITE if a residual is NaN/Inf. */
+int lrstv_solve(lrstv_handle hd, const float* Y, float* X, float* S, int32_t max_iter,
+                double eps, lrstv_report* rep);
+
+/* Device pointers to the state (checkpoint / resume / adjoint). */
+int lrstv_get_state(lrstv_handle hd, lrstv_state_view* view);
+
+/* Copy a state (device pointers with the layout of lrstv_state_view; the
+ * X, Y and mu members may be NULL to leave them) into the handle.
+ * Asynchronous on the handle's stream. */
+int lrstv_set_state(lrstv_handle hd, const lrstv_state_view* src);
+
+void lrstv_destroy(lrstv_handle hd);
+
+/* ---- standalone primitives --------------------------------------------- */
+
+/* Workspace bytes for lrstv_svt on `batch` tensors of shape (b, h, w). */
+int lrstv_svt_workspace_size(int32_t h, int32_t w, int32_t b, int32_t batch, int32_t precision,
+                             size_t* bytes);
+
+/* t-SVT (Sec. III-C, E-update; t-SVD of Theorem 4.2): for each of `batch`
+ * real tensors A (device, packed [batch][b][h][w]) compute
+ *   E = IDFT_b( SVT_thresh( DFT_b(A)_k ) for every Fourier slice k ),
+ * i.e. the prox of thresh * TNN.  Only the floor(b/2)+1 non-redundant
+ * slices are decomposed; the others follow by conjugate symmetry.
+ * E (device) may not alias A.  Errors: INVALID_ARG, WORKSPACE, UNSUPPORTED,
+ * HIP. */
+int lrstv_svt(const float* A, float* E, int32_t h, int32_t w, int32_t b, int32_t batch,
+              float thresh, int32_t precision, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for lrstv_zsolve on one (b, h, w) cube. */
+int lrstv_zsolve_workspace_size(int32_t h, int32_t w, int32_t b, size_t* bytes);
+
+/* Z-update (Sec. III-C): solve mu (I + sum_n w_n^2 D_n^T D_n) Z = T for a
+ * periodic (b, h, w) cube (device T, Z; they may alias).  Errors as above. */
+int lrstv_zsolve(const float* T, float* Z, int32_t h, int32_t w, int32_t b, double mu,
+                 const double wts[3], void* ws, size_t ws_bytes, void* stream);
+
+/* ---- diagnostics ------------------------------------------------------- */
+const char* lrstv_status_string(int status);
+const char* lrstv_last_error(void);   /* thread-local, "" if none */
+int lrstv_version(void);              /* 100 * major + minor */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LRSTV_H */

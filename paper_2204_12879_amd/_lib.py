@@ -1,0 +1,266 @@
+"""ctypes marshalling for liblrstv.so (no arithmetic of the method here)."""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import List, Optional, Sequence, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_NAME = "liblrstv.so"
+
+LRSTV_FP32 = 0
+LRSTV_SPLIT_BF16 = 1
+LRSTV_NRES = 7
+RESIDUAL_NAMES = ("inf_OLS", "inf_LZ", "fro_OLS", "fro_LZ", "fro_DZF", "fro_EF", "dual_Z")
+WARN_NOT_CONVERGED = 1
+
+
+class LrstvError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lrstv error {code}: {msg}")
+        self.code = code
+
+
+class _Problem(C.Structure):
+    _fields_ = [("n_cubes", C.c_int32), ("h", C.POINTER(C.c_int32)), ("w", C.POINTER(C.c_int32)),
+                ("b", C.POINTER(C.c_int32))]
+
+
+class _Params(C.Structure):
+    _fields_ = [("tau", C.c_double), ("alpha", C.c_double), ("lam", C.c_double), ("w", C.c_double * 3),
+                ("mu0", C.c_double), ("rho", C.c_double), ("mu_max", C.c_double), ("precision", C.c_int32)]
+
+
+class _StateView(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("X", "Y", "Z", "S", "G1", "G2", "F", "E", "G3", "G4", "mu")] + \
+               [("total", C.c_int64)]
+
+
+class _Report(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("residuals", C.c_double * LRSTV_NRES), ("mu", C.c_double)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return os.environ.get("LRSTV_LIBRARY", os.path.join(HERE, _LIB_NAME))
+
+
+def load_library():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise LrstvError(-100, f"{path} not found: build it with `python -m paper_2204_12879_amd.build`")
+    lib = C.CDLL(path)
+    vp, i32, f64, f32 = C.c_void_p, C.c_int32, C.c_double, C.c_float
+    sz = C.POINTER(C.c_size_t)
+    sig = {
+        "lrstv_workspace_size": (C.c_int, [C.POINTER(_Problem), C.POINTER(_Params), sz]),
+        "lrstv_create": (C.c_int, [C.POINTER(vp), C.POINTER(_Problem), C.POINTER(_Params), vp, C.c_size_t, vp]),
+        "lrstv_reset": (C.c_int, [vp, vp]),
+        "lrstv_iterate": (C.c_int, [vp, i32, vp]),
+        "lrstv_read_output": (C.c_int, [vp, vp, vp]),
+        "lrstv_solve": (C.c_int, [vp, vp, vp, vp, i32, f64, C.POINTER(_Report)]),
+        "lrstv_get_state": (C.c_int, [vp, C.POINTER(_StateView)]),
+        "lrstv_set_state": (C.c_int, [vp, C.POINTER(_StateView)]),
+        "lrstv_destroy": (None, [vp]),
+        "lrstv_svt_workspace_size": (C.c_int, [i32, i32, i32, i32, i32, sz]),
+        "lrstv_svt": (C.c_int, [vp, vp, i32, i32, i32, i32, f32, i32, vp, C.c_size_t, vp]),
+        "lrstv_zsolve_workspace_size": (C.c_int, [i32, i32, i32, sz]),
+        "lrstv_zsolve": (C.c_int, [vp, vp, i32, i32, i32, f64, C.POINTER(C.c_double), vp, C.c_size_t, vp]),
+        "lrstv_status_string": (C.c_char_p, [C.c_int]),
+        "lrstv_last_error": (C.c_char_p, []),
+        "lrstv_version": (C.c_int, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, allow_warn: bool = False) -> int:
+    if rc < 0 or (rc > 0 and not allow_warn):
+        lib = load_library()
+        raise LrstvError(rc, f"{lib.lrstv_status_string(rc).decode()}: {lib.lrstv_last_error().decode()}")
+    return rc
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _ptr(t) -> int:
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous() or t.dtype.itemsize == 0:
+        raise ValueError("expected a contiguous CUDA tensor")
+    return t.data_ptr()
+
+
+@dataclasses.dataclass
+class Params:
+    """Regularisation weights and penalty schedule (Sec. III-C, Algorithm 1)."""
+    tau: float = 0.02
+    alpha: float = 0.3
+    lam: float = 0.04
+    w: Tuple[float, float, float] = (1.0, 1.0, 1.0)
+    mu0: float = 1e-2
+    rho: float = 1.5
+    mu_max: float = 1e6
+    precision: int = LRSTV_FP32
+
+    def _c(self) -> _Params:
+        return _Params(self.tau, self.alpha, self.lam, (C.c_double * 3)(*self.w), self.mu0, self.rho,
+                       self.mu_max, self.precision)
+
+
+def _problem(shapes: Sequence[Tuple[int, int, int]]):
+    n = len(shapes)
+    hs = (C.c_int32 * n)(*[s[1] for s in shapes])
+    ws = (C.c_int32 * n)(*[s[2] for s in shapes])
+    bs = (C.c_int32 * n)(*[s[0] for s in shapes])
+    return _Problem(n, hs, ws, bs), (hs, ws, bs)
+
+
+class Solver:
+    """ADMM solver handle over a batch of cubes with shapes (b, h, w).
+
+    Cubes are packed back to back in flat float32 CUDA tensors.  The
+    workspace is a torch tensor owned by this object.
+    """
+
+    STATE_NAMES = ("X", "Y", "Z", "S", "G1", "G2", "F", "E", "G3", "G4")
+
+    def __init__(self, shapes: Sequence[Tuple[int, int, int]], params: Params, stream=None):
+        import torch
+        self.lib = load_library()
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.params = params
+        self.total = sum(b * h * w for b, h, w in self.shapes)
+        prob, self._keep = _problem(self.shapes)
+        self._prob = prob
+        nbytes = C.c_size_t(0)
+        _check(self.lib.lrstv_workspace_size(C.byref(prob), C.byref(params._c()), C.byref(nbytes)))
+        self.ws_bytes = int(nbytes.value)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device="cuda")
+        base = self.workspace.data_ptr()
+        self._ws_off = (-base) % 256
+        self.stream = stream
+        h = C.c_void_p()
+        _check(self.lib.lrstv_create(C.byref(h), C.byref(prob), C.byref(params._c()),
+                                     C.c_void_p(base + self._ws_off), C.c_size_t(self.ws_bytes),
+                                     C.c_void_p(_stream(stream))))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.lrstv_destroy(h)
+            self.handle = None
+
+    def offsets(self) -> List[int]:
+        out, o = [], 0
+        for b, h, w in self.shapes:
+            out.append(o)
+            o += b * h * w
+        return out
+
+    def reset(self, Y) -> None:
+        _check(self.lib.lrstv_reset(self.handle, C.c_void_p(_ptr(Y))))
+
+    def iterate(self, n: int, residuals=None) -> None:
+        _check(self.lib.lrstv_iterate(self.handle, int(n),
+                                      C.c_void_p(_ptr(residuals)) if residuals is not None else None))
+
+    def read_output(self, X=None, S=None) -> None:
+        _check(self.lib.lrstv_read_output(self.handle, C.c_void_p(_ptr(X)) if X is not None else None,
+                                          C.c_void_p(_ptr(S)) if S is not None else None))
+
+    def solve(self, Y, X=None, S=None, max_iter: int = 50, eps: float = 0.0):
+        rep = _Report()
+        rc = self.lib.lrstv_solve(self.handle, C.c_void_p(_ptr(Y)),
+                                  C.c_void_p(_ptr(X)) if X is not None else None,
+                                  C.c_void_p(_ptr(S)) if S is not None else None, int(max_iter), float(eps),
+                                  C.byref(rep))
+        _check(rc, allow_warn=True)
+        return {"iters": rep.iters, "residuals": dict(zip(RESIDUAL_NAMES, list(rep.residuals))),
+                "mu": rep.mu, "converged": rc != WARN_NOT_CONVERGED}
+
+    def _view(self, ptr: int, count: int, dtype):
+        import torch
+        base = self.workspace.data_ptr()
+        off = ptr - base
+        nbytes = count * torch.empty((), dtype=dtype).element_size()
+        return self.workspace[off:off + nbytes].view(dtype)
+
+    def state(self) -> dict:
+        """Views (aliasing the workspace) of X (last L), Y, Z, S, Gamma1..4, F, E and mu."""
+        import torch
+        v = _StateView()
+        _check(self.lib.lrstv_get_state(self.handle, C.byref(v)))
+        T = self.total
+        out = {}
+        for name in self.STATE_NAMES:
+            cnt = 3 * T if name in ("F", "E", "G3", "G4") else T
+            out[name] = self._view(getattr(v, name), cnt, torch.float32)
+        out["mu"] = self._view(v.mu, 1, torch.float64)
+        return out
+
+    def set_state(self, st: dict) -> None:
+        """Copy tensors (same packed layout as state()) into the handle."""
+        v = _StateView()
+        for name in self.STATE_NAMES + ("mu",):
+            t = st.get(name)
+            setattr(v, name, _ptr(t) if t is not None else None)
+        v.total = self.total
+        _check(self.lib.lrstv_set_state(self.handle, C.byref(v)))
+
+
+def svt_workspace_bytes(shape: Tuple[int, int, int], batch: int = 1, precision: int = LRSTV_FP32) -> int:
+    lib = load_library()
+    b, h, w = shape
+    n = C.c_size_t(0)
+    _check(lib.lrstv_svt_workspace_size(h, w, b, batch, precision, C.byref(n)))
+    return int(n.value)
+
+
+def svt(A, thresh: float, precision: int = LRSTV_FP32, out=None, stream=None):
+    """t-SVT of a (b, h, w) or (batch, b, h, w) float32 CUDA tensor."""
+    import torch
+    lib = load_library()
+    squeeze = A.dim() == 3
+    A4 = A.unsqueeze(0) if squeeze else A
+    batch, b, h, w = A4.shape
+    A4 = A4.contiguous()
+    E = torch.empty_like(A4) if out is None else out.view(A4.shape)
+    nb = svt_workspace_bytes((b, h, w), batch, precision)
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device=A.device)
+    base = ws.data_ptr() + ((-ws.data_ptr()) % 256)
+    _check(lib.lrstv_svt(C.c_void_p(_ptr(A4)), C.c_void_p(_ptr(E)), h, w, b, batch, float(thresh), precision,
+                         C.c_void_p(base), C.c_size_t(nb), C.c_void_p(_stream(stream))))
+    return E[0] if squeeze else E
+
+
+def zsolve(T, mu: float, wts=(1.0, 1.0, 1.0), out=None, stream=None):
+    """Solve mu (I + sum w_n^2 D_n^T D_n) Z = T for a (b, h, w) float32 CUDA tensor."""
+    import torch
+    lib = load_library()
+    b, h, w = T.shape
+    T = T.contiguous()
+    Z = torch.empty_like(T) if out is None else out
+    n = C.c_size_t(0)
+    _check(lib.lrstv_zsolve_workspace_size(h, w, b, C.byref(n)))
+    ws = torch.empty(int(n.value), dtype=torch.uint8, device=T.device)
+    wv = (C.c_double * 3)(*wts)
+    _check(lib.lrstv_zsolve(C.c_void_p(_ptr(T)), C.c_void_p(_ptr(Z)), h, w, b, float(mu), wv,
+                            C.c_void_p(ws.data_ptr()), C.c_size_t(int(n.value)), C.c_void_p(_stream(stream))))
+    return Z

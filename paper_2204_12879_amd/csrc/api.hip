@@ -1,0 +1,622 @@
+// C ABI of the LRSTV library (declared in include/lrstv.h): argument checks,
+// workspace carve-up, slice tables and the per-iteration launch schedule of
+// Algorithm 1 (Sec. III-C).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lrstv.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace lrstv;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(x)                                                                      \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess) return fail(LRSTV_ERR_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+// ------------------------------------------------------------ workspace ---
+namespace {
+
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* b) : base((char*)b) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct CubeInfo {
+  int h, w, b, s;
+  int64_t off;         // element offset in the packed batch
+  int64_t slice0;      // index of the first slice of this cube
+  int64_t slice_base;  // float offset of this cube's slices
+};
+
+// Slice tables and per-slice scratch sizes for a list of cubes with `nt`
+// tensors each.
+struct SliceLayout {
+  std::vector<SliceDesc> desc;
+  int64_t slices_floats = 0, gram_c = 0, v_floats = 0, b_floats = 0, tri_d = 0, xs_d = 0, f_floats = 0;
+  int max_n1 = 0, max_m1 = 0;
+};
+
+SliceLayout make_slices(std::vector<CubeInfo>& cubes, int nt) {
+  SliceLayout L;
+  for (size_t c = 0; c < cubes.size(); ++c) {
+    CubeInfo& ci = cubes[c];
+    const int h = ci.h, w = ci.w, s = ci.s;
+    const int64_t hw = (int64_t)h * w;
+    const int n1 = h < w ? h : w, m1 = h < w ? w : h;
+    ci.slice0 = (int64_t)L.desc.size();
+    ci.slice_base = L.slices_floats;
+    for (int t = 0; t < nt; ++t)
+      for (int k = 0; k < s; ++k) {
+        SliceDesc d;
+        d.h = h;
+        d.w = w;
+        d.n1 = n1;
+        d.m1 = m1;
+        d.tall = h >= w;
+        d.cube = (int)c;
+        d.a_off = L.slices_floats + ((int64_t)t * s + k) * 2 * hw;
+        d.g_off = L.gram_c;
+        d.v_off = L.v_floats;
+        d.b_off = L.b_floats;
+        d.t_off = L.tri_d;
+        d.x_off = L.xs_d;
+        d.f_off = L.f_floats;
+        L.gram_c += (int64_t)n1 * (n1 + 1) / 2;
+        L.v_floats += 2 * (int64_t)n1 * n1;
+        L.b_floats += 2 * hw;
+        L.tri_d += 6 * (int64_t)n1;
+        L.xs_d += 3 * (int64_t)n1 * n1;
+        L.f_floats += n1;
+        L.desc.push_back(d);
+      }
+    L.slices_floats += (int64_t)nt * s * 2 * hw;
+    if (n1 > L.max_n1) L.max_n1 = n1;
+    if (m1 > L.max_m1) L.max_m1 = m1;
+  }
+  return L;
+}
+
+}  // namespace
+
+struct lrstv_handle_s {
+  std::vector<CubeInfo> cubes;
+  int64_t total = 0, nmax = 0, specmax = 0;
+  lrstv_params par;
+  hipStream_t stream;
+  SliceLayout sl;
+  // state
+  float *O, *L, *Z, *S, *G1, *G2, *F, *E, *G3, *G4;
+  // scratch
+  float *T, *A, *slices, *V, *B, *fval;
+  float2 *spec, *gram;
+  double *tri, *xs, *mu, *part, *res_last;
+  int *rcount, *flag;
+  SliceDesc* desc;
+};
+
+static int check_params(const lrstv_params* p) {
+  if (!p) return fail(LRSTV_ERR_INVALID_ARG, "params is NULL");
+  if (!(p->tau >= 0) || !(p->alpha >= 0) || !(p->lambda >= 0))
+    return fail(LRSTV_ERR_INVALID_ARG, "tau, alpha, lambda must be >= 0");
+  for (int i = 0; i < 3; ++i)
+    if (!(p->w[i] >= 0)) return fail(LRSTV_ERR_INVALID_ARG, "difference weights must be >= 0");
+  if (!(p->mu0 > 0)) return fail(LRSTV_ERR_INVALID_ARG, "mu0 must be > 0");
+  if (!(p->rho >= 1)) return fail(LRSTV_ERR_INVALID_ARG, "rho must be >= 1");
+  if (!(p->mu_max >= p->mu0)) return fail(LRSTV_ERR_INVALID_ARG, "mu_max must be >= mu0");
+  if (p->precision != LRSTV_FP32 && p->precision != LRSTV_SPLIT_BF16)
+    return fail(LRSTV_ERR_INVALID_ARG, "unknown precision %d", p->precision);
+  return LRSTV_OK;
+}
+
+static int check_dims(int h, int w, int b) {
+  if (h < 1 || w < 1 || b < 1) return fail(LRSTV_ERR_INVALID_ARG, "sizes must be >= 1 (got h=%d w=%d b=%d)", h, w, b);
+  if (h > LRSTV_MAX_SIDE || w > LRSTV_MAX_SIDE || b > LRSTV_MAX_SIDE)
+    return fail(LRSTV_ERR_UNSUPPORTED, "side above %d (h=%d w=%d b=%d)", LRSTV_MAX_SIDE, h, w, b);
+  return LRSTV_OK;
+}
+
+static int build_cubes(const lrstv_problem* prob, std::vector<CubeInfo>& cubes, int64_t& total, int64_t& nmax,
+                       int64_t& specmax) {
+  if (!prob || prob->n_cubes < 1 || !prob->h || !prob->w || !prob->b)
+    return fail(LRSTV_ERR_INVALID_ARG, "problem must list n_cubes >= 1 with h, w, b arrays");
+  cubes.clear();
+  total = 0;
+  nmax = 0;
+  specmax = 0;
+  for (int c = 0; c < prob->n_cubes; ++c) {
+    const int h = prob->h[c], w = prob->w[c], b = prob->b[c];
+    int rc = check_dims(h, w, b);
+    if (rc) return rc;
+    CubeInfo ci;
+    ci.h = h;
+    ci.w = w;
+    ci.b = b;
+    ci.s = b / 2 + 1;
+    ci.off = total;
+    const int64_t N = (int64_t)h * w * b;
+    total += N;
+    if (N > nmax) nmax = N;
+    const int64_t sp = (int64_t)b * h * (w / 2 + 1);
+    if (sp > specmax) specmax = sp;
+    cubes.push_back(ci);
+  }
+  return LRSTV_OK;
+}
+
+static void carve_handle(lrstv_handle_s* H, void* base, size_t* used) {
+  Carve cv(base);
+  const int64_t T = H->total, nc = (int64_t)H->cubes.size();
+  H->O = cv.take<float>(T);
+  H->L = cv.take<float>(T);
+  H->Z = cv.take<float>(T);
+  H->S = cv.take<float>(T);
+  H->G1 = cv.take<float>(T);
+  H->G2 = cv.take<float>(T);
+  H->F = cv.take<float>(3 * T);
+  H->E = cv.take<float>(3 * T);
+  H->G3 = cv.take<float>(3 * T);
+  H->G4 = cv.take<float>(3 * T);
+  H->T = cv.take<float>(H->nmax);
+  H->A = cv.take<float>(3 * H->nmax);
+  H->spec = cv.take<float2>(H->specmax);
+  H->slices = cv.take<float>(H->sl.slices_floats);
+  H->gram = cv.take<float2>(H->sl.gram_c);
+  H->V = cv.take<float>(H->sl.v_floats);
+  H->B = cv.take<float>(H->sl.b_floats);
+  H->tri = cv.take<double>(H->sl.tri_d);
+  H->xs = cv.take<double>(H->sl.xs_d);
+  H->fval = cv.take<float>(H->sl.f_floats);
+  H->rcount = cv.take<int>(H->sl.desc.size());
+  H->desc = cv.take<SliceDesc>(H->sl.desc.size());
+  H->mu = cv.take<double>(1);
+  H->part = cv.take<double>(nc * R_COUNT * LRSTV_PARTS);
+  H->res_last = cv.take<double>(nc * R_COUNT);
+  H->flag = cv.take<int>(1);
+  *used = cv.off + 256;
+}
+
+extern "C" int lrstv_workspace_size(const lrstv_problem* prob, const lrstv_params* par, size_t* bytes) {
+  if (!bytes) return fail(LRSTV_ERR_INVALID_ARG, "bytes is NULL");
+  int rc = check_params(par);
+  if (rc) return rc;
+  lrstv_handle_s H;
+  rc = build_cubes(prob, H.cubes, H.total, H.nmax, H.specmax);
+  if (rc) return rc;
+  H.sl = make_slices(H.cubes, 3);
+  carve_handle(&H, nullptr, bytes);
+  return LRSTV_OK;
+}
+
+extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const lrstv_params* par, void* workspace,
+                            size_t ws_bytes, void* stream) {
+  if (!out) return fail(LRSTV_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = check_params(par);
+  if (rc) return rc;
+  if (!workspace) return fail(LRSTV_ERR_INVALID_ARG, "workspace is NULL");
+  if (((uintptr_t)workspace & 255) != 0) return fail(LRSTV_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  lrstv_handle_s* H = new (std::nothrow) lrstv_handle_s();
+  if (!H) return fail(LRSTV_ERR_INVALID_ARG, "out of host memory");
+  rc = build_cubes(prob, H->cubes, H->total, H->nmax, H->specmax);
+  if (rc) { delete H; return rc; }
+  H->par = *par;
+  H->stream = (hipStream_t)stream;
+  H->sl = make_slices(H->cubes, 3);
+  size_t need = 0;
+  carve_handle(H, nullptr, &need);
+  if (ws_bytes < need) {
+    delete H;
+    return fail(LRSTV_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  }
+  carve_handle(H, workspace, &need);
+  hipError_t e = hipMemcpyAsync(H->desc, H->sl.desc.data(), H->sl.desc.size() * sizeof(SliceDesc),
+                                hipMemcpyHostToDevice, H->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(H->stream);
+  if (e != hipSuccess) {
+    delete H;
+    return fail(LRSTV_ERR_HIP, "copying the slice table: %s", hipGetErrorString(e));
+  }
+  launch_set_mu(H->mu, par->mu0, H->stream);
+  *out = H;
+  return LRSTV_OK;
+}
+
+extern "C" void lrstv_destroy(lrstv_handle hd) { delete hd; }
+
+extern "C" int lrstv_reset(lrstv_handle H, const float* Y) {
+  if (!H || !Y) return fail(LRSTV_ERR_INVALID_ARG, "handle or Y is NULL");
+  const int64_t T = H->total;
+  hipStream_t s = H->stream;
+  launch_copy(H->O, Y, T, s);
+  launch_copy(H->Z, Y, T, s);
+  launch_copy(H->L, Y, T, s);
+  launch_fill(H->S, T, 0.f, s);
+  launch_fill(H->G1, T, 0.f, s);
+  launch_fill(H->G2, T, 0.f, s);
+  launch_fill(H->F, 3 * T, 0.f, s);
+  launch_fill(H->E, 3 * T, 0.f, s);
+  launch_fill(H->G3, 3 * T, 0.f, s);
+  launch_fill(H->G4, 3 * T, 0.f, s);
+  launch_set_mu(H->mu, H->par.mu0, s);
+  HIPCHK(hipGetLastError());
+  return LRSTV_OK;
+}
+
+static CubePtrs cube_ptrs(lrstv_handle_s* H, const CubeInfo& c) {
+  CubePtrs p;
+  p.h = c.h;
+  p.w = c.w;
+  p.b = c.b;
+  p.ts = H->total;
+  p.O = H->O + c.off;
+  p.L = H->L + c.off;
+  p.Z = H->Z + c.off;
+  p.S = H->S + c.off;
+  p.G1 = H->G1 + c.off;
+  p.G2 = H->G2 + c.off;
+  p.F = H->F + c.off;
+  p.E = H->E + c.off;
+  p.G3 = H->G3 + c.off;
+  p.G4 = H->G4 + c.off;
+  p.A = H->A;
+  p.T = H->T;
+  return p;
+}
+
+static void run_iteration(lrstv_handle_s* H, double* res_user) {
+  hipStream_t s = H->stream;
+  Weights wt;
+  wt.tau = H->par.tau;
+  wt.alpha = H->par.alpha;
+  wt.lam = H->par.lambda;
+  for (int i = 0; i < 3; ++i) wt.w[i] = H->par.w[i];
+  const int nc = (int)H->cubes.size();
+  for (int c = 0; c < nc; ++c) {
+    const CubeInfo& ci = H->cubes[c];
+    CubePtrs p = cube_ptrs(H, ci);
+    // A is a per-cube scratch with component stride nmax
+    p.ts = H->total;
+    double* part = H->part + (int64_t)c * R_COUNT * LRSTV_PARTS;
+    launch_lrhs(p, wt, H->mu, s);                                   // 1st step + T_z
+    launch_rfft_w(p.T, H->spec, ci.h, ci.w, ci.b, s);               // 2nd step: Z solve
+    launch_fft_h(H->spec, ci.h, ci.w, ci.b, -1, s);
+    launch_tri_b(H->spec, ci.h, ci.w, ci.b, wt.w, H->mu, 0.0, s);
+    launch_fft_h(H->spec, ci.h, ci.w, ci.b, +1, s);
+    launch_irfft_w(H->spec, p.Z, ci.h, ci.w, ci.b, part, s);
+    // 3rd, 5th and 6th steps (F, S, Gamma1..3); A = F - Gamma4/mu into scratch
+    CubePtrs q = p;
+    q.A = H->A;
+    launch_grad_shrink(q, wt, H->mu, part, H->nmax, s);
+    launch_band_dft(H->A, H->nmax, 3, H->slices + ci.slice_base, ci.h, ci.w, ci.b, s);
+  }
+  // 4th step: t-SVT of every Fourier slice of every gradient tensor
+  SvtLaunch sv;
+  sv.desc = H->desc;
+  sv.n_slices = (int)H->sl.desc.size();
+  sv.max_n1 = H->sl.max_n1;
+  sv.max_m1 = H->sl.max_m1;
+  sv.slices = H->slices;
+  sv.gram = H->gram;
+  sv.V = H->V;
+  sv.B = H->B;
+  sv.tri = H->tri;
+  sv.xs = H->xs;
+  sv.fval = H->fval;
+  sv.rcount = H->rcount;
+  sv.mu = H->mu;
+  sv.alpha = H->par.alpha;
+  sv.thresh = 0.f;
+  sv.precision = H->par.precision;
+  launch_svt(sv, s);
+  for (int c = 0; c < nc; ++c) {
+    const CubeInfo& ci = H->cubes[c];
+    double* part = H->part + (int64_t)c * R_COUNT * LRSTV_PARTS;
+    launch_band_idft(H->slices + ci.slice_base, 3, H->E + ci.off, H->total, ci.h, ci.w, ci.b, H->F + ci.off,
+                     H->G4 + ci.off, H->mu, part, s);
+  }
+  launch_finish_iter(H->part, nc, H->mu, H->res_last, res_user, H->flag, s);
+  launch_mu_step(H->mu, H->par.rho, H->par.mu_max, s);               // 7th step
+}
+
+extern "C" int lrstv_iterate(lrstv_handle H, int32_t n_iter, double* residuals) {
+  if (!H) return fail(LRSTV_ERR_INVALID_ARG, "handle is NULL");
+  if (n_iter < 0) return fail(LRSTV_ERR_INVALID_ARG, "n_iter must be >= 0");
+  const int nc = (int)H->cubes.size();
+  for (int it = 0; it < n_iter; ++it)
+    run_iteration(H, residuals ? residuals + (int64_t)it * nc * R_COUNT : nullptr);
+  HIPCHK(hipGetLastError());
+  return LRSTV_OK;
+}
+
+extern "C" int lrstv_read_output(lrstv_handle H, float* X, float* S) {
+  if (!H) return fail(LRSTV_ERR_INVALID_ARG, "handle is NULL");
+  if (X) launch_copy(X, H->L, H->total, H->stream);
+  if (S) launch_copy(S, H->S, H->total, H->stream);
+  HIPCHK(hipGetLastError());
+  return LRSTV_OK;
+}
+
+extern "C" int lrstv_solve(lrstv_handle H, const float* Y, float* X, float* S, int32_t max_iter, double eps,
+                           lrstv_report* rep) {
+  if (!H || !Y) return fail(LRSTV_ERR_INVALID_ARG, "handle or Y is NULL");
+  if (max_iter < 1) return fail(LRSTV_ERR_INVALID_ARG, "max_iter must be >= 1");
+  int rc = lrstv_reset(H, Y);
+  if (rc) return rc;
+  const int nc = (int)H->cubes.size();
+  std::vector<double> res(nc * R_COUNT);
+  int iters = 0, status = LRSTV_OK;
+  HIPCHK(hipMemsetAsync(H->flag, 0, sizeof(int), H->stream));
+  const int chunk = eps > 0 ? 1 : max_iter;
+  bool done = false;
+  while (iters < max_iter && !done) {
+    const int k = (max_iter - iters) < chunk ? (max_iter - iters) : chunk;
+    for (int i = 0; i < k; ++i) run_iteration(H, nullptr);
+    iters += k;
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(res.data(), H->res_last, res.size() * sizeof(double), hipMemcpyDeviceToHost, H->stream));
+    HIPCHK(hipStreamSynchronize(H->stream));
+    double worst = 0.0;
+    bool bad = false;
+    for (double v : res) bad |= !isfinite(v);
+    for (int c = 0; c < nc; ++c) {
+      worst = fmax(worst, res[c * R_COUNT + R_INF_OLS]);
+      worst = fmax(worst, res[c * R_COUNT + R_INF_LZ]);
+    }
+    if (bad) { status = fail(LRSTV_ERR_NONFINITE, "non-finite residual after %d iterations", iters); break; }
+    if (eps > 0 && worst <= eps) done = true;
+  }
+  if (status == LRSTV_OK && eps > 0 && !done) {
+    status = LRSTV_WARN_NOT_CONVERGED;
+    g_err = "stopping test not met within max_iter";
+  }
+  rc = lrstv_read_output(H, X, S);
+  if (rc) return rc;
+  if (rep) {
+    rep->iters = iters;
+    for (int r = 0; r < R_COUNT; ++r) {
+      double m = 0.0;
+      for (int c = 0; c < nc; ++c) m = fmax(m, res[c * R_COUNT + r]);
+      rep->residuals[r] = m;
+    }
+    double mu = 0.0;
+    HIPCHK(hipMemcpyAsync(&mu, H->mu, sizeof(double), hipMemcpyDeviceToHost, H->stream));
+    HIPCHK(hipStreamSynchronize(H->stream));
+    rep->mu = mu;
+  }
+  return status;
+}
+
+extern "C" int lrstv_get_state(lrstv_handle H, lrstv_state_view* v) {
+  if (!H || !v) return fail(LRSTV_ERR_INVALID_ARG, "handle or view is NULL");
+  v->X = H->L;
+  v->Y = H->O;
+  v->Z = H->Z;
+  v->S = H->S;
+  v->G1 = H->G1;
+  v->G2 = H->G2;
+  v->F = H->F;
+  v->E = H->E;
+  v->G3 = H->G3;
+  v->G4 = H->G4;
+  v->mu = H->mu;
+  v->total = H->total;
+  return LRSTV_OK;
+}
+
+extern "C" int lrstv_set_state(lrstv_handle H, const lrstv_state_view* v) {
+  if (!H || !v) return fail(LRSTV_ERR_INVALID_ARG, "handle or view is NULL");
+  if (v->total != H->total) return fail(LRSTV_ERR_INVALID_ARG, "state total %lld != %lld", (long long)v->total,
+                                        (long long)H->total);
+  if (!v->Z || !v->S || !v->G1 || !v->G2 || !v->F || !v->E || !v->G3 || !v->G4)
+    return fail(LRSTV_ERR_INVALID_ARG, "state view lacks a required member");
+  const int64_t T = H->total;
+  hipStream_t s = H->stream;
+  if (v->X) launch_copy(H->L, v->X, T, s);
+  if (v->Y) launch_copy(H->O, v->Y, T, s);
+  launch_copy(H->Z, v->Z, T, s);
+  launch_copy(H->S, v->S, T, s);
+  launch_copy(H->G1, v->G1, T, s);
+  launch_copy(H->G2, v->G2, T, s);
+  launch_copy(H->F, v->F, 3 * T, s);
+  launch_copy(H->E, v->E, 3 * T, s);
+  launch_copy(H->G3, v->G3, 3 * T, s);
+  launch_copy(H->G4, v->G4, 3 * T, s);
+  if (v->mu) HIPCHK(hipMemcpyAsync(H->mu, v->mu, sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipGetLastError());
+  return LRSTV_OK;
+}
+
+// --------------------------------------------------------- primitives ---
+
+namespace {
+struct SvtWs {
+  float *slices, *V, *B, *fval;
+  float2* gram;
+  double *tri, *xs;
+  int* rcount;
+  SliceDesc* desc;
+};
+void carve_svt(const SliceLayout& L, void* base, SvtWs* w, size_t* used) {
+  Carve cv(base);
+  w->slices = cv.take<float>(L.slices_floats);
+  w->gram = cv.take<float2>(L.gram_c);
+  w->V = cv.take<float>(L.v_floats);
+  w->B = cv.take<float>(L.b_floats);
+  w->tri = cv.take<double>(L.tri_d);
+  w->xs = cv.take<double>(L.xs_d);
+  w->fval = cv.take<float>(L.f_floats);
+  w->rcount = cv.take<int>(L.desc.size());
+  w->desc = cv.take<SliceDesc>(L.desc.size());
+  *used = cv.off + 256;
+}
+}  // namespace
+
+__global__ void k_make_desc(SliceDesc* out, int n, const SliceDesc* proto_unused, int h, int w, int s,
+                            int64_t gram_c, int64_t v_f, int64_t b_f, int64_t tri_d, int64_t xs_d, int64_t f_f) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t hw = (int64_t)h * w;
+  const int n1 = h < w ? h : w, m1 = h < w ? w : h;
+  SliceDesc d;
+  d.h = h;
+  d.w = w;
+  d.n1 = n1;
+  d.m1 = m1;
+  d.tall = h >= w;
+  d.cube = i / s;
+  d.a_off = (int64_t)i * 2 * hw;
+  d.g_off = (int64_t)i * gram_c;
+  d.v_off = (int64_t)i * v_f;
+  d.b_off = (int64_t)i * b_f;
+  d.t_off = (int64_t)i * tri_d;
+  d.x_off = (int64_t)i * xs_d;
+  d.f_off = (int64_t)i * f_f;
+  out[i] = d;
+}
+
+static SliceLayout svt_layout(int h, int w, int b, int batch) {
+  std::vector<CubeInfo> cubes(batch);
+  for (int i = 0; i < batch; ++i) {
+    cubes[i].h = h;
+    cubes[i].w = w;
+    cubes[i].b = b;
+    cubes[i].s = b / 2 + 1;
+    cubes[i].off = 0;
+  }
+  return make_slices(cubes, 1);
+}
+
+extern "C" int lrstv_svt_workspace_size(int32_t h, int32_t w, int32_t b, int32_t batch, int32_t precision,
+                                        size_t* bytes) {
+  if (!bytes) return fail(LRSTV_ERR_INVALID_ARG, "bytes is NULL");
+  int rc = check_dims(h, w, b);
+  if (rc) return rc;
+  if (batch < 1) return fail(LRSTV_ERR_INVALID_ARG, "batch must be >= 1");
+  if (precision != LRSTV_FP32 && precision != LRSTV_SPLIT_BF16)
+    return fail(LRSTV_ERR_INVALID_ARG, "unknown precision %d", precision);
+  SliceLayout L = svt_layout(h, w, b, batch);
+  SvtWs ws;
+  carve_svt(L, nullptr, &ws, bytes);
+  return LRSTV_OK;
+}
+
+extern "C" int lrstv_svt(const float* A, float* E, int32_t h, int32_t w, int32_t b, int32_t batch, float thresh,
+                         int32_t precision, void* wsp, size_t ws_bytes, void* stream) {
+  size_t need = 0;
+  int rc = lrstv_svt_workspace_size(h, w, b, batch, precision, &need);
+  if (rc) return rc;
+  if (!A || !E || !wsp) return fail(LRSTV_ERR_INVALID_ARG, "A, E and the workspace must be non-NULL");
+  if (A == E) return fail(LRSTV_ERR_INVALID_ARG, "E may not alias A");
+  if (!(thresh >= 0.f)) return fail(LRSTV_ERR_INVALID_ARG, "thresh must be >= 0");
+  if (ws_bytes < need) return fail(LRSTV_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  if (((uintptr_t)wsp & 255) != 0) return fail(LRSTV_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  SliceLayout L = svt_layout(h, w, b, batch);
+  SvtWs ws;
+  carve_svt(L, wsp, &ws, &need);
+  const int ns = (int)L.desc.size();
+  const int n1 = h < w ? h : w;
+  const int64_t hw = (int64_t)h * w;
+  hipLaunchKernelGGL(k_make_desc, dim3((ns + 255) / 256), dim3(256), 0, s, ws.desc, ns, nullptr, h, w, b / 2 + 1,
+                     (int64_t)n1 * (n1 + 1) / 2, 2 * (int64_t)n1 * n1, 2 * hw, 6 * (int64_t)n1, 3 * (int64_t)n1 * n1,
+                     (int64_t)n1);
+  launch_band_dft(A, (int64_t)b * hw, batch, ws.slices, h, w, b, s);
+  SvtLaunch sv;
+  sv.desc = ws.desc;
+  sv.n_slices = ns;
+  sv.max_n1 = L.max_n1;
+  sv.max_m1 = L.max_m1;
+  sv.slices = ws.slices;
+  sv.gram = ws.gram;
+  sv.V = ws.V;
+  sv.B = ws.B;
+  sv.tri = ws.tri;
+  sv.xs = ws.xs;
+  sv.fval = ws.fval;
+  sv.rcount = ws.rcount;
+  sv.mu = nullptr;
+  sv.alpha = 0.0;
+  sv.thresh = thresh;
+  sv.precision = precision;
+  launch_svt(sv, s);
+  launch_band_idft(ws.slices, batch, E, (int64_t)b * hw, h, w, b, nullptr, nullptr, nullptr, nullptr, s);
+  HIPCHK(hipGetLastError());
+  return LRSTV_OK;
+}
+
+extern "C" int lrstv_zsolve_workspace_size(int32_t h, int32_t w, int32_t b, size_t* bytes) {
+  if (!bytes) return fail(LRSTV_ERR_INVALID_ARG, "bytes is NULL");
+  int rc = check_dims(h, w, b);
+  if (rc) return rc;
+  *bytes = (size_t)b * h * (w / 2 + 1) * sizeof(float2) + 256;
+  return LRSTV_OK;
+}
+
+extern "C" int lrstv_zsolve(const float* T, float* Z, int32_t h, int32_t w, int32_t b, double mu, const double wts[3],
+                            void* wsp, size_t ws_bytes, void* stream) {
+  size_t need = 0;
+  int rc = lrstv_zsolve_workspace_size(h, w, b, &need);
+  if (rc) return rc;
+  if (!T || !Z || !wsp || !wts) return fail(LRSTV_ERR_INVALID_ARG, "NULL pointer argument");
+  if (!(mu > 0)) return fail(LRSTV_ERR_INVALID_ARG, "mu must be > 0");
+  for (int i = 0; i < 3; ++i)
+    if (!(wts[i] >= 0)) return fail(LRSTV_ERR_INVALID_ARG, "weights must be >= 0");
+  if (ws_bytes < need) return fail(LRSTV_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  hipStream_t s = (hipStream_t)stream;
+  float2* spec = (float2*)(((uintptr_t)wsp + 255) & ~(uintptr_t)255);
+  launch_rfft_w(T, spec, h, w, b, s);
+  launch_fft_h(spec, h, w, b, -1, s);
+  launch_tri_b(spec, h, w, b, wts, nullptr, mu, s);
+  launch_fft_h(spec, h, w, b, +1, s);
+  launch_irfft_w(spec, Z, h, w, b, nullptr, s);
+  HIPCHK(hipGetLastError());
+  return LRSTV_OK;
+}
+
+// --------------------------------------------------------- diagnostics ---
+extern "C" const char* lrstv_status_string(int st) {
+  switch (st) {
+    case LRSTV_OK: return "ok";
+    case LRSTV_WARN_NOT_CONVERGED: return "stopping test not met";
+    case LRSTV_ERR_INVALID_ARG: return "invalid argument";
+    case LRSTV_ERR_WORKSPACE: return "workspace too small";
+    case LRSTV_ERR_UNSUPPORTED: return "unsupported size";
+    case LRSTV_ERR_HIP: return "HIP runtime error";
+    case LRSTV_ERR_NONFINITE: return "non-finite value";
+    default: return "unknown status";
+  }
+}
+
+extern "C" const char* lrstv_last_error(void) { return g_err.c_str(); }
+
+extern "C" int lrstv_version(void) { return 100; }

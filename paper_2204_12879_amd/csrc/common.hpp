@@ -1,0 +1,86 @@
+// Shared device helpers and descriptor structs of the LRSTV HIP library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define LRSTV_DEV __device__ __forceinline__
+
+namespace lrstv {
+
+// ---------------------------------------------------------------- complex ---
+LRSTV_DEV float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+LRSTV_DEV float2 cmulc(float2 a, float2 b) {  // conj(a) * b
+  return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+LRSTV_DEV float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+LRSTV_DEV float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+LRSTV_DEV float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+LRSTV_DEV float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+
+LRSTV_DEV float soft_threshold(float x, float t) {
+  // R_t(x) = sign(x) max(|x| - t, 0)
+  float m = fabsf(x) - t;
+  return m > 0.f ? copysignf(m, x) : 0.f;
+}
+
+// ------------------------------------------------------------- reductions ---
+LRSTV_DEV double warp_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+LRSTV_DEV double warp_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+LRSTV_DEV float warp_sumf(float v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide sum in a fixed order (deterministic).  `scratch` holds
+// blockDim/64 doubles.  Every thread gets the result.
+LRSTV_DEV double block_sum(double v, double* scratch) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  v = warp_sum(v);
+  __syncthreads();
+  if (lane == 0) scratch[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int i = 0; i < nw; ++i) r += scratch[i];
+  return r;
+}
+LRSTV_DEV double block_max(double v, double* scratch) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  v = warp_max(v);
+  __syncthreads();
+  if (lane == 0) scratch[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int i = 0; i < nw; ++i) r = fmax(r, scratch[i]);
+  return r;
+}
+
+// ------------------------------------------------------------ descriptors ---
+// Residual slots per cube (same order as the public LRSTV_NRES list).
+enum { R_INF_OLS = 0, R_INF_LZ, R_FRO_OLS, R_FRO_LZ, R_FRO_DZF, R_FRO_EF, R_DUAL_Z, R_COUNT };
+
+// Number of per-block partials each residual-producing kernel writes.
+#define LRSTV_PARTS 512
+
+// One Fourier slice of one gradient tensor of one cube (or of one tensor of
+// the standalone t-SVT batch).
+struct SliceDesc {
+  int h, w;          // slice is h x w complex, row-major, planar (re plane, im plane)
+  int n1, m1;        // min / max of (h, w)
+  int tall;          // 1 if h >= w (Gram = M^H M), else Gram = M M^H
+  int cube;          // owning cube
+  int64_t a_off;     // float offset of the re plane; im plane at a_off + h*w
+  int64_t g_off;     // float2 offset of the packed lower Gram / reflector scratch
+  int64_t v_off;     // float offset of V (planar, n1 x n1, re then im)
+  int64_t b_off;     // float offset of the back-projection intermediate (planar)
+  int64_t t_off;     // double offset of the tridiagonal scratch (d, |e|, phase re/im)
+  int64_t x_off;     // double offset of the eigenvector scratch (3 n1 x n1)
+  int64_t f_off;     // float offset of the n1 shrink factors
+};
+
+}  // namespace lrstv

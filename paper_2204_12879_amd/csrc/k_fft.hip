@@ -1,0 +1,546 @@
+// Transforms of the ADMM sweep.
+//
+// Z-update (Sec. III-C): the system mu (I + sum_n w_n^2 D_n^T D_n) Z = T_z is
+// diagonalised by DFTs along the two spatial axes (the paper's fftn route);
+// what remains for every spatial frequency (k_h, k_w) is a periodic
+// tridiagonal system along the bands,
+//     [a I + beta C] z = t,   C = circulant(2, -1, ..., -1),
+//     a = mu (1 + w_1^2 4 sin^2(pi k_h / h) + w_2^2 4 sin^2(pi k_w / w)),
+//     beta = mu w_3^2,
+// whose solution equals the band DFT route exactly (up to rounding).  It is
+// solved in O(b) with the factorisation a + 2 beta - beta (S + S^-1) =
+// (beta / r)(1 - r S)(1 - r S^-1), 0 < r < 1, i.e. one causal and one
+// anti-causal periodic first-order recursion.  This avoids an FFT of prime
+// length along the bands (b = 191 for the 256x256x191 cube).
+//
+// t-SVT (Sec. III-C E-update): real DFT along the bands of each gradient
+// tensor into the floor(b/2)+1 non-redundant frontal slices, and the inverse
+// with conjugate-symmetric completion, fused with the Gamma4 ascent.
+//
+// FFTs along w and h run in LDS as batched Stockham autosort transforms with
+// radices 4, 2, 3, 5, 7 and a direct-DFT stage for any other prime factor.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace lrstv {
+
+#define MAX_STAGES 24
+
+struct Plan {
+  int ns;
+  int r[MAX_STAGES];
+};
+
+LRSTV_DEV void make_plan(int N, Plan& p) {
+  p.ns = 0;
+  int n = N;
+  const int small[5] = {4, 2, 3, 5, 7};
+  for (int t = 0; t < 5; ++t)
+    while (n % small[t] == 0 && p.ns < MAX_STAGES) {
+      p.r[p.ns++] = small[t];
+      n /= small[t];
+    }
+  for (int q = 11; n > 1 && p.ns < MAX_STAGES; q += 2)
+    while (n % q == 0) {
+      p.r[p.ns++] = q;
+      n /= q;
+    }
+}
+
+// tw[m] = exp(-2 pi i m / N)
+LRSTV_DEV void fill_twiddles(float2* tw, int N) {
+  for (int m = threadIdx.x; m < N; m += blockDim.x) {
+    double s, c;
+    sincospi(-2.0 * (double)m / (double)N, &s, &c);
+    tw[m] = make_float2((float)c, (float)s);
+  }
+}
+
+LRSTV_DEV float2 twid(const float2* tw, int m, int sign) {
+  const float2 t = tw[m];
+  return sign < 0 ? t : make_float2(t.x, -t.y);
+}
+
+template <int R>
+LRSTV_DEV void small_dft(float2* v, const float2* tw, int N, int sign) {
+  if (R == 2) {
+    const float2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if (R == 4) {
+    const float2 a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
+    const float2 s02 = cadd(a0, a2), d02 = csub(a0, a2), s13 = cadd(a1, a3), d13 = csub(a1, a3);
+    // -i * d13 for the forward transform (sign < 0), +i * d13 for the inverse
+    const float2 rot = sign < 0 ? make_float2(d13.y, -d13.x) : make_float2(-d13.y, d13.x);
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, rot);
+    v[3] = csub(d02, rot);
+  } else {
+    float2 o[R];
+    const int step = N / R;
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      float2 acc = v[0];
+#pragma unroll
+      for (int q = 1; q < R; ++q) acc = cadd(acc, cmul(v[q], twid(tw, ((q * s) % R) * step, sign)));
+      o[s] = acc;
+    }
+#pragma unroll
+    for (int s = 0; s < R; ++s) v[s] = o[s];
+  }
+}
+
+template <int R>
+LRSTV_DEV void stage_small(const float2* src, float2* dst, int N, int nb, int Ns, const float2* tw, int sign) {
+  const int NR = N / R;
+  const int tot = nb * NR;
+  const int tstep = N / (Ns * R);
+  for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+    const int f = t / NR, j = t - f * NR, k = j % Ns;
+    const float2* s = src + f * N;
+    float2 v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      v[q] = s[j + q * NR];
+      if (q > 0 && k > 0) v[q] = cmul(v[q], twid(tw, q * k * tstep, sign));
+    }
+    small_dft<R>(v, tw, N, sign);
+    const int idx = (j / Ns) * Ns * R + k;
+    float2* d = dst + f * N + idx;
+#pragma unroll
+    for (int q = 0; q < R; ++q) d[q * Ns] = v[q];
+  }
+}
+
+// Direct DFT stage for a prime factor R > 7: one output per thread.
+LRSTV_DEV void stage_generic(const float2* src, float2* dst, int N, int nb, int Ns, int R, const float2* tw, int sign) {
+  const int NR = N / R;
+  const int tstep = N / (Ns * R), ostep = N / R;
+  for (int t = threadIdx.x; t < nb * N; t += blockDim.x) {
+    const int f = t / N, o = t - f * N;
+    const int k = o % Ns, so = (o / Ns) % R, jd = o / (Ns * R);
+    const int j = jd * Ns + k;
+    const float2* s = src + f * N;
+    float2 acc = make_float2(0.f, 0.f);
+    int oi = 0;  // (q * so) mod R
+    for (int q = 0; q < R; ++q) {
+      float2 a = s[j + q * NR];
+      if (q > 0 && k > 0) a = cmul(a, twid(tw, q * k * tstep, sign));
+      acc = cadd(acc, cmul(a, twid(tw, oi * ostep, sign)));
+      oi += so;
+      if (oi >= R) oi -= R;
+    }
+    dst[f * N + o] = acc;
+  }
+}
+
+// Batched FFT of nb contiguous rows of length N held in bufA; returns the
+// buffer holding the result.  Unnormalised; sign -1 forward, +1 inverse.
+LRSTV_DEV float2* fft_lds(float2* bufA, float2* bufB, int N, int nb, const float2* tw, int sign, const Plan& p) {
+  float2* src = bufA;
+  float2* dst = bufB;
+  int Ns = 1;
+  for (int st = 0; st < p.ns; ++st) {
+    const int R = p.r[st];
+    switch (R) {
+      case 2: stage_small<2>(src, dst, N, nb, Ns, tw, sign); break;
+      case 3: stage_small<3>(src, dst, N, nb, Ns, tw, sign); break;
+      case 4: stage_small<4>(src, dst, N, nb, Ns, tw, sign); break;
+      case 5: stage_small<5>(src, dst, N, nb, Ns, tw, sign); break;
+      case 7: stage_small<7>(src, dst, N, nb, Ns, tw, sign); break;
+      default: stage_generic(src, dst, N, nb, Ns, R, tw, sign); break;
+    }
+    __syncthreads();
+    float2* t = src;
+    src = dst;
+    dst = t;
+    Ns *= R;
+  }
+  return src;
+}
+
+// ---------------------------------------------------------------------------
+// Real FFT along w, two rows packed in one complex transform.
+// T: rows r = j*h + i of length w; spec rows of length wc = w/2 + 1.
+__global__ void __launch_bounds__(256) k_rfft_w(const float* __restrict__ T, float2* __restrict__ spec, int nrows,
+                                                int w, int nb) {
+  extern __shared__ float2 sm[];
+  float2* tw = sm;
+  float2* bA = sm + w;
+  float2* bB = bA + nb * w;
+  const int wc = w / 2 + 1;
+  Plan p;
+  make_plan(w, p);
+  fill_twiddles(tw, w);
+  const int rows_per_block = 2 * nb;
+  for (int r0 = blockIdx.x * rows_per_block; r0 < nrows; r0 += gridDim.x * rows_per_block) {
+    for (int t = threadIdx.x; t < nb * w; t += blockDim.x) {
+      const int f = t / w, x = t - f * w;
+      const int ra = r0 + 2 * f, rb = ra + 1;
+      const float va = ra < nrows ? T[(int64_t)ra * w + x] : 0.f;
+      const float vb = rb < nrows ? T[(int64_t)rb * w + x] : 0.f;
+      bA[t] = make_float2(va, vb);
+    }
+    __syncthreads();
+    const float2* out = fft_lds(bA, bB, w, nb, tw, -1, p);
+    for (int t = threadIdx.x; t < nb * wc; t += blockDim.x) {
+      const int f = t / wc, k = t - f * wc;
+      const float2 zk = out[f * w + k];
+      const float2 zc = cconj(out[f * w + ((w - k) % w)]);
+      const float2 X = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
+      const float2 D = csub(zk, zc);                 // Y = D / (2i)
+      const float2 Y = make_float2(0.5f * D.y, -0.5f * D.x);
+      const int ra = r0 + 2 * f, rb = ra + 1;
+      if (ra < nrows) spec[(int64_t)ra * wc + k] = X;
+      if (rb < nrows) spec[(int64_t)rb * wc + k] = Y;
+    }
+    __syncthreads();
+  }
+}
+
+// Inverse of k_rfft_w (scaled by `scale`), writing real rows into Z.  If
+// `part` is set, also accumulates sum (Z_new - Z_old)^2 per block.
+__global__ void __launch_bounds__(256) k_irfft_w(const float2* __restrict__ spec, float* __restrict__ Z, int nrows,
+                                                 int w, int nb, float scale, double* __restrict__ part) {
+  extern __shared__ float2 sm[];
+  __shared__ double red[8];
+  float2* tw = sm;
+  float2* bA = sm + w;
+  float2* bB = bA + nb * w;
+  const int wc = w / 2 + 1;
+  Plan p;
+  make_plan(w, p);
+  fill_twiddles(tw, w);
+  double acc = 0.0;
+  const int rows_per_block = 2 * nb;
+  for (int r0 = blockIdx.x * rows_per_block; r0 < nrows; r0 += gridDim.x * rows_per_block) {
+    for (int t = threadIdx.x; t < nb * w; t += blockDim.x) {
+      const int f = t / w, k = t - f * w;
+      const int ra = r0 + 2 * f, rb = ra + 1;
+      const bool lo = k < wc;
+      const int kk = lo ? k : w - k;
+      float2 X = ra < nrows ? spec[(int64_t)ra * wc + kk] : make_float2(0.f, 0.f);
+      float2 Y = rb < nrows ? spec[(int64_t)rb * wc + kk] : make_float2(0.f, 0.f);
+      if (!lo) {
+        X = cconj(X);
+        Y = cconj(Y);
+      }
+      bA[t] = make_float2(X.x - Y.y, X.y + Y.x);  // X + i Y
+    }
+    __syncthreads();
+    const float2* out = fft_lds(bA, bB, w, nb, tw, +1, p);
+    for (int t = threadIdx.x; t < nb * w; t += blockDim.x) {
+      const int f = t / w, x = t - f * w;
+      const int ra = r0 + 2 * f, rb = ra + 1;
+      const float2 v = out[t];
+      if (ra < nrows) {
+        const int64_t q = (int64_t)ra * w + x;
+        const float zn = v.x * scale;
+        if (part) {
+          const double d = (double)zn - (double)Z[q];
+          acc += d * d;
+        }
+        Z[q] = zn;
+      }
+      if (rb < nrows) {
+        const int64_t q = (int64_t)rb * w + x;
+        const float zn = v.y * scale;
+        if (part) {
+          const double d = (double)zn - (double)Z[q];
+          acc += d * d;
+        }
+        Z[q] = zn;
+      }
+    }
+    __syncthreads();
+  }
+  if (part) {
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) part[R_DUAL_Z * LRSTV_PARTS + blockIdx.x] = acc;
+  }
+}
+
+// Complex FFT along h of spec [b][h][wc], cw columns per block.
+__global__ void __launch_bounds__(256) k_fft_h(float2* __restrict__ spec, int h, int wc, int b, int cw, int sign) {
+  extern __shared__ float2 sm[];
+  float2* tw = sm;
+  float2* bA = sm + h;
+  float2* bB = bA + cw * h;
+  Plan p;
+  make_plan(h, p);
+  fill_twiddles(tw, h);
+  const int nchunk = (wc + cw - 1) / cw;
+  for (int blk = blockIdx.x; blk < b * nchunk; blk += gridDim.x) {
+    const int j = blk / nchunk, c0 = (blk - j * nchunk) * cw;
+    float2* base = spec + (int64_t)j * h * wc;
+    for (int t = threadIdx.x; t < cw * h; t += blockDim.x) {
+      const int i = t / cw, c = t - i * cw;
+      bA[c * h + i] = (c0 + c < wc) ? base[(int64_t)i * wc + c0 + c] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    const float2* out = fft_lds(bA, bB, h, cw, tw, sign, p);
+    for (int t = threadIdx.x; t < cw * h; t += blockDim.x) {
+      const int i = t / cw, c = t - i * cw;
+      if (c0 + c < wc) base[(int64_t)i * wc + c0 + c] = out[c * h + i];
+    }
+    __syncthreads();
+  }
+}
+
+// Periodic tridiagonal solve along the bands for every (k_h, k_w).
+__global__ void __launch_bounds__(256) k_tri_b(float2* __restrict__ spec, int h, int w, int b, double w1, double w2,
+                                               double w3, const double* __restrict__ mu_dev, double mu_host) {
+  const int wc = w / 2 + 1;
+  const int64_t plane = (int64_t)h * wc;
+  const double mu = mu_dev ? *mu_dev : mu_host;
+  for (int64_t col = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; col < plane;
+       col += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(col / wc), kw = (int)(col - (int64_t)i * wc);
+    const double sh = sinpi((double)i / h), sw = sinpi((double)kw / w);
+    const double a = mu * (1.0 + 4.0 * (w1 * w1 * sh * sh + w2 * w2 * sw * sw));
+    const double beta = mu * w3 * w3;
+    float2* c = spec + col;
+    if (beta <= 0.0 || b == 1) {
+      const float ia = (float)(1.0 / a);
+      for (int j = 0; j < b; ++j) c[j * plane] = cscale(c[j * plane], ia);
+      continue;
+    }
+    const double cc = (a + 2.0 * beta) / (2.0 * beta);
+    const double r = 1.0 / (cc + sqrt(cc * cc - 1.0));
+    const double rb = pow(r, (double)b);
+    const float rf = (float)r;
+    const float inv1 = (float)(1.0 / (1.0 - rb));
+    // causal: y_j - r y_{j-1} = t_j (periodic);  y_0 = sum_m r^m t_{-m} / (1 - r^b)
+    double sx = 0.0, sy = 0.0, pw = 1.0;
+    for (int m = 0; m < b; ++m) {
+      const float2 t = c[(int64_t)((b - m) % b) * plane];
+      sx += pw * t.x;
+      sy += pw * t.y;
+      pw *= r;
+      if (pw < 1e-30) break;
+    }
+    float2 y = make_float2((float)sx * inv1, (float)sy * inv1);
+    c[0] = y;
+    for (int j = 1; j < b; ++j) {
+      const float2 t = c[(int64_t)j * plane];
+      y = make_float2(t.x + rf * y.x, t.y + rf * y.y);
+      c[(int64_t)j * plane] = y;
+    }
+    // anti-causal: z_j - r z_{j+1} = y_j;  z_{b-1} = sum_m r^m y_{b-1+m} / (1 - r^b)
+    sx = 0.0;
+    sy = 0.0;
+    pw = 1.0;
+    for (int m = 0; m < b; ++m) {
+      const float2 t = c[(int64_t)((b - 1 + m) % b) * plane];
+      sx += pw * t.x;
+      sy += pw * t.y;
+      pw *= r;
+      if (pw < 1e-30) break;
+    }
+    const float sc = (float)(r / beta);
+    float2 z = make_float2((float)sx * inv1, (float)sy * inv1);
+    c[(int64_t)(b - 1) * plane] = cscale(z, sc);
+    for (int j = b - 2; j >= 0; --j) {
+      const float2 t = c[(int64_t)j * plane];
+      z = make_float2(t.x + rf * z.x, t.y + rf * z.y);
+      c[(int64_t)j * plane] = cscale(z, sc);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Band DFT of real tensors: X_k = sum_j a_j e^{-2 pi i j k / b}, k < b/2+1,
+// using the pairing a_j +- a_{b-j}.  Output planar slices [t][k][re|im][hw].
+__global__ void __launch_bounds__(256) k_band_dft(const float* __restrict__ A, int64_t a_stride, int n_t,
+                                                  float* __restrict__ out, int hw, int b, int P) {
+  extern __shared__ float smf[];
+  float* ct = smf;           // cos(2 pi m / b)
+  float* st = ct + b;        // sin(2 pi m / b)
+  float* a = st + b;         // [b][P]
+  const int s = b / 2 + 1, J = (b - 1) / 2;
+  for (int m = threadIdx.x; m < b; m += blockDim.x) {
+    double sv, cv;
+    sincospi(2.0 * (double)m / (double)b, &sv, &cv);
+    ct[m] = (float)cv;
+    st[m] = (float)sv;
+  }
+  const int ntile = (hw + P - 1) / P;
+  for (int blk = blockIdx.x; blk < n_t * ntile; blk += gridDim.x) {
+    const int t = blk / ntile, p0 = (blk - t * ntile) * P;
+    const float* src = A + t * a_stride;
+    __syncthreads();
+    for (int e = threadIdx.x; e < b * P; e += blockDim.x) {
+      const int j = e / P, p = e - j * P;
+      a[e] = (p0 + p < hw) ? src[(int64_t)j * hw + p0 + p] : 0.f;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < J * P; e += blockDim.x) {
+      const int j = 1 + e / P, p = e % P;
+      const float u = a[j * P + p], v = a[(b - j) * P + p];
+      a[j * P + p] = u + v;
+      a[(b - j) * P + p] = u - v;
+    }
+    __syncthreads();
+    const int groups = blockDim.x / P;
+    const int p = threadIdx.x % P, g = threadIdx.x / P;
+    if (g < groups && p0 + p < hw) {
+      float* dst = out + (int64_t)t * s * 2 * hw;
+      for (int k = g; k < s; k += groups) {
+        float re = a[p], im = 0.f;
+        int idx = 0;
+        for (int j = 1; j <= J; ++j) {
+          idx += k;
+          if (idx >= b) idx -= b;
+          re += a[j * P + p] * ct[idx];
+          im -= a[(b - j) * P + p] * st[idx];
+        }
+        if ((b & 1) == 0) re += a[(b / 2) * P + p] * ((k & 1) ? -1.f : 1.f);
+        dst[((int64_t)k * 2) * hw + p0 + p] = re;
+        dst[((int64_t)k * 2 + 1) * hw + p0 + p] = im;
+      }
+    }
+  }
+}
+
+// Inverse band DFT (Hermitian completion) + optional Gamma4 ascent.
+// E_j = (1/b) [Re X_0 + 2 sum_{k=1}^{J} (Re X_k cos - Im X_k sin)(2 pi j k / b) + Re X_{b/2} (-1)^j].
+__global__ void __launch_bounds__(256) k_band_idft(const float* __restrict__ X, int n_t, float* __restrict__ E,
+                                                   int64_t e_stride, int hw, int b, int P,
+                                                   const float* __restrict__ F, float* __restrict__ G4,
+                                                   const double* __restrict__ mu_dev, double* __restrict__ part) {
+  extern __shared__ float smf[];
+  __shared__ double red[8];
+  float* ct = smf;
+  float* st = ct + b;
+  float* xr = st + b;        // [s][P]
+  float* xi = xr + (b / 2 + 1) * P;
+  const int s = b / 2 + 1, J = (b - 1) / 2, half = b / 2;
+  const float ib = 1.0f / (float)b;
+  const float mu = G4 ? (float)(*mu_dev) : 0.f;
+  for (int m = threadIdx.x; m < b; m += blockDim.x) {
+    double sv, cv;
+    sincospi(2.0 * (double)m / (double)b, &sv, &cv);
+    ct[m] = (float)cv;
+    st[m] = (float)sv;
+  }
+  double acc = 0.0;
+  const int ntile = (hw + P - 1) / P;
+  for (int blk = blockIdx.x; blk < n_t * ntile; blk += gridDim.x) {
+    const int t = blk / ntile, p0 = (blk - t * ntile) * P;
+    const float* src = X + (int64_t)t * s * 2 * hw;
+    __syncthreads();
+    for (int e = threadIdx.x; e < s * P; e += blockDim.x) {
+      const int k = e / P, p = e - k * P;
+      const bool ok = p0 + p < hw;
+      xr[e] = ok ? src[((int64_t)k * 2) * hw + p0 + p] : 0.f;
+      xi[e] = ok ? src[((int64_t)k * 2 + 1) * hw + p0 + p] : 0.f;
+    }
+    __syncthreads();
+    const int groups = blockDim.x / P;
+    const int p = threadIdx.x % P, g = threadIdx.x / P;
+    if (g < groups && p0 + p < hw) {
+      float* dst = E + t * e_stride;
+      const float* Ft = F ? F + t * e_stride : nullptr;
+      float* G4t = G4 ? G4 + t * e_stride : nullptr;
+      const float x0 = xr[p];
+      const float xn = ((b & 1) == 0) ? xr[half * P + p] : 0.f;
+      for (int j = g; j <= half; j += groups) {
+        float c = 0.f, sn = 0.f;
+        int idx = 0;
+        for (int k = 1; k <= J; ++k) {
+          idx += j;
+          if (idx >= b) idx -= b;
+          c += xr[k * P + p] * ct[idx];
+          sn += xi[k * P + p] * st[idx];
+        }
+        const float ny = xn * ((j & 1) ? -1.f : 1.f);
+        const int jl[2] = {j, b - j};
+        const float ev[2] = {(x0 + 2.f * (c - sn) + ny) * ib, (x0 + 2.f * (c + sn) + ny) * ib};
+        const int cnt = (j == 0 || b - j == j) ? 1 : 2;
+        for (int u = 0; u < cnt; ++u) {
+          const int64_t q = (int64_t)jl[u] * hw + p0 + p;
+          const float e = ev[u];
+          dst[q] = e;
+          if (G4t) {
+            const float f = Ft[q];
+            G4t[q] = G4t[q] + mu * (e - f);
+            const double d = (double)e - (double)f;
+            acc += d * d;
+          }
+        }
+      }
+    }
+  }
+  if (part) {
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) part[R_FRO_EF * LRSTV_PARTS + blockIdx.x] = acc;
+  }
+}
+
+// ------------------------------------------------------------ launchers ---
+
+static int rows_nb(int w) {
+  int nb = 8;
+  while (nb > 1 && (2 * nb + 1) * w * 8 > 48 * 1024) nb >>= 1;
+  return nb;
+}
+
+void launch_rfft_w(const float* T, float2* spec, int h, int w, int b, hipStream_t s) {
+  const int nrows = h * b, nb = rows_nb(w);
+  const size_t lds = (size_t)(2 * nb + 1) * w * sizeof(float2);
+  int grid = (nrows + 2 * nb - 1) / (2 * nb);
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(k_rfft_w, dim3(grid), dim3(256), lds, s, T, spec, nrows, w, nb);
+}
+
+void launch_irfft_w(const float2* spec, float* Z, int h, int w, int b, double* part, hipStream_t s) {
+  const int nrows = h * b, nb = rows_nb(w);
+  const size_t lds = (size_t)(2 * nb + 1) * w * sizeof(float2);
+  const float scale = 1.0f / ((float)h * (float)w);
+  hipLaunchKernelGGL(k_irfft_w, dim3(LRSTV_PARTS), dim3(256), lds, s, spec, Z, nrows, w, nb, scale, part);
+}
+
+void launch_fft_h(float2* spec, int h, int w, int b, int sign, hipStream_t s) {
+  const int wc = w / 2 + 1;
+  int cw = 16;
+  while (cw > 1 && (2 * cw + 1) * h * 8 > 48 * 1024) cw >>= 1;
+  const size_t lds = (size_t)(2 * cw + 1) * h * sizeof(float2);
+  int grid = b * ((wc + cw - 1) / cw);
+  if (grid > 8192) grid = 8192;
+  hipLaunchKernelGGL(k_fft_h, dim3(grid), dim3(256), lds, s, spec, h, wc, b, cw, sign);
+}
+
+void launch_tri_b(float2* spec, int h, int w, int b, const double wts[3], const double* mu, double mu_host,
+                  hipStream_t s) {
+  const int64_t plane = (int64_t)h * (w / 2 + 1);
+  int grid = (int)((plane + 255) / 256);
+  hipLaunchKernelGGL(k_tri_b, dim3(grid), dim3(256), 0, s, spec, h, w, b, wts[0], wts[1], wts[2], mu, mu_host);
+}
+
+static int dft_tile(int b) {
+  int P = 64;
+  while (P > 16 && ((size_t)2 * b + (size_t)b * P) * 4 > 60 * 1024) P >>= 1;
+  return P;
+}
+
+void launch_band_dft(const float* A, int64_t a_stride, int n_t, float* slices, int h, int w, int b, hipStream_t s) {
+  const int hw = h * w, P = dft_tile(b);
+  const size_t lds = ((size_t)2 * b + (size_t)b * P) * sizeof(float);
+  int grid = n_t * ((hw + P - 1) / P);
+  if (grid > 8192) grid = 8192;
+  hipLaunchKernelGGL(k_band_dft, dim3(grid), dim3(256), lds, s, A, a_stride, n_t, slices, hw, b, P);
+}
+
+void launch_band_idft(const float* slices, int n_t, float* E, int64_t e_stride, int h, int w, int b,
+                      const float* F, float* G4, const double* mu, double* part, hipStream_t s) {
+  const int hw = h * w, sN = b / 2 + 1;
+  int P = 64;
+  while (P > 16 && ((size_t)2 * b + (size_t)2 * sN * P) * 4 > 60 * 1024) P >>= 1;
+  const size_t lds = ((size_t)2 * b + (size_t)2 * sN * P) * sizeof(float);
+  int grid = part ? LRSTV_PARTS : n_t * ((hw + P - 1) / P);
+  if (grid > 8192) grid = 8192;
+  hipLaunchKernelGGL(k_band_idft, dim3(grid), dim3(256), lds, s, slices, n_t, E, e_stride, hw, b, P, F, G4, mu, part);
+}
+
+}  // namespace lrstv

@@ -1,0 +1,700 @@
+// Slice singular value thresholding (Sec. III-C, E-update), one complex
+// h x w Fourier slice M per SliceDesc:
+//
+//   Ehat = M V diag(f) V^H   (h >= w, V = right singular vectors)
+//   Ehat = U diag(f) U^H M   (h <  w, U = left singular vectors)
+//   f_i  = max(1 - t / sigma_i, 0)
+//
+// Pipeline (one kernel each, all slices of all cubes batched):
+//   k_gram       G = M^H M or M M^H (n1 x n1, packed lower triangle)
+//   k_tridiag    Householder reduction G = Q T~ Q^H with Hermitian reflectors,
+//                T~ Hermitian tridiagonal; made real by a diagonal phase;
+//                the packed Gram stays in LDS when it fits
+//   k_trieig     FP64 Sturm bisection for the eigenvalues above the
+//                threshold and eigenvectors by twisted factorisations
+//                (per unreduced block), cluster re-orthogonalisation
+//   k_backtrans  V <- Q (phase * z), applying the stored reflectors
+//   k_bp1        B = M V_r  (or U_r^H M)
+//   k_colnorm    sigma_i = ||M v_i|| (taken from M, not from the squared
+//                Gram eigenvalue), f_i = max(1 - t/sigma_i, 0)
+//   k_bp2        Ehat = B diag(f) V_r^H  (or U_r diag(f) B), written over M
+//
+// Eigenpairs whose Gram eigenvalue lies below t^2 - delta (delta a few FP32
+// ulps of ||G||) are discarded: there sigma <= t and the shrink factor is 0.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace lrstv {
+
+// ------------------------------------------------------------- GEMM tile ---
+// 256 threads compute a 32 x 32 complex tile C = sum_k A(m, k) B(k, n).
+// fa(m, k) / fb(k, n) return the operand element (zero outside).
+// AK / BK: whether k is the fast (contiguous) index of A / B in memory, which
+// picks the coalesced load order.
+template <bool AK, bool BK, class FA, class FB>
+LRSTV_DEV void ctile(int m0, int n0, int K, FA fa, FB fb, float2& c00, float2& c01, float2& c10, float2& c11,
+                     float2 (*As)[33], float2 (*Bs)[33]) {
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  c00 = c01 = c10 = c11 = make_float2(0.f, 0.f);
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int e = tid; e < 512; e += 256) {
+      int kk, mm;
+      if (AK) { kk = e & 15; mm = e >> 4; } else { mm = e & 31; kk = e >> 5; }
+      As[kk][mm] = fa(m0 + mm, k0 + kk);
+      int nn;
+      if (BK) { kk = e & 15; nn = e >> 4; } else { nn = e & 31; kk = e >> 5; }
+      Bs[kk][nn] = fb(k0 + kk, n0 + nn);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < 16; ++kk) {
+      const float2 a0 = As[kk][ty], a1 = As[kk][ty + 16];
+      const float2 b0 = Bs[kk][tx], b1 = Bs[kk][tx + 16];
+      c00 = cadd(c00, cmul(a0, b0));
+      c01 = cadd(c01, cmul(a0, b1));
+      c10 = cadd(c10, cmul(a1, b0));
+      c11 = cadd(c11, cmul(a1, b1));
+    }
+    __syncthreads();
+  }
+}
+
+LRSTV_DEV int64_t packed(int r, int c) { return (int64_t)r * (r + 1) / 2 + c; }
+
+// ------------------------------------------------------------------ Gram ---
+__global__ void __launch_bounds__(256) k_gram(const SliceDesc* __restrict__ desc, const float* __restrict__ sl,
+                                              float2* __restrict__ gram) {
+  __shared__ float2 As[16][33], Bs[16][33];
+  const SliceDesc d = desc[blockIdx.y];
+  const int n = d.n1, T = (n + 31) / 32;
+  int ti = 0, rem = blockIdx.x;
+  while (rem > ti) { rem -= ti + 1; ++ti; }
+  const int tj = rem;
+  if (ti >= T) return;
+  const int h = d.h, w = d.w;
+  const float* re = sl + d.a_off;
+  const float* im = re + (int64_t)h * w;
+  float2 c00, c01, c10, c11;
+  if (d.tall) {  // G = M^H M, contraction over the h rows
+    auto fa = [&](int m, int k) -> float2 {
+      if (m >= n || k >= h) return make_float2(0.f, 0.f);
+      const int64_t q = (int64_t)k * w + m;
+      return make_float2(re[q], -im[q]);
+    };
+    auto fb = [&](int k, int c) -> float2 {
+      if (c >= n || k >= h) return make_float2(0.f, 0.f);
+      const int64_t q = (int64_t)k * w + c;
+      return make_float2(re[q], im[q]);
+    };
+    ctile<false, false>(ti * 32, tj * 32, h, fa, fb, c00, c01, c10, c11, As, Bs);
+  } else {  // G = M M^H, contraction over the w columns
+    auto fa = [&](int m, int k) -> float2 {
+      if (m >= n || k >= w) return make_float2(0.f, 0.f);
+      const int64_t q = (int64_t)m * w + k;
+      return make_float2(re[q], im[q]);
+    };
+    auto fb = [&](int k, int c) -> float2 {
+      if (c >= n || k >= w) return make_float2(0.f, 0.f);
+      const int64_t q = (int64_t)c * w + k;
+      return make_float2(re[q], -im[q]);
+    };
+    ctile<true, true>(ti * 32, tj * 32, w, fa, fb, c00, c01, c10, c11, As, Bs);
+  }
+  float2* g = gram + d.g_off;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int r0 = ti * 32 + ty, r1 = r0 + 16, q0 = tj * 32 + tx, q1 = q0 + 16;
+  if (r0 < n && q0 <= r0) g[packed(r0, q0)] = c00;
+  if (r0 < n && q1 <= r0) g[packed(r0, q1)] = c01;
+  if (r1 < n && q0 <= r1) g[packed(r1, q0)] = c10;
+  if (r1 < n && q1 <= r1) g[packed(r1, q1)] = c11;
+}
+
+// ---------------------------------------------------------- tridiagonal ---
+// Householder reduction of the packed Hermitian Gram, one block per slice.
+// Step i: x = A(i+1:, i); H = I - tau v v^H with H x = beta e_1,
+// beta = -phase(x_0) ||x||; p = tau A22 v; w = p - (tau/2)(v^H p) v;
+// A22 <- A22 - v w^H - w v^H.  Output (doubles, at t_off):
+//   [0,n) diag, [n,2n) |beta|, [2n,3n) phase re, [3n,4n) phase im, [4n,5n) tau
+// and reflector i stored in column i of the packed triangle (below diag).
+template <bool ONCHIP>
+__global__ void __launch_bounds__(256) k_tridiag(const SliceDesc* __restrict__ desc, float2* __restrict__ gram,
+                                                 double* __restrict__ tri) {
+  extern __shared__ float2 sm[];
+  __shared__ double red[8];
+  __shared__ double s_tau;
+  __shared__ float2 s_beta, s_scale;
+  const SliceDesc d = desc[blockIdx.x];
+  const int n = d.n1;
+  const int64_t np = (int64_t)n * (n + 1) / 2;
+  float2* gA = gram + d.g_off;
+  float2* A = ONCHIP ? sm : gA;
+  float2* v = ONCHIP ? sm + np : sm;
+  float2* p = v + n;
+  float2* colacc = p + n;            // [nwaves][n]
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double* dg = tri + d.t_off;
+  double* eab = dg + n;
+  double* phr = eab + n;
+  double* phi = phr + n;
+  double* taus = phi + n;
+  if (ONCHIP) {
+    for (int64_t e = threadIdx.x; e < np; e += blockDim.x) A[e] = gA[e];
+    __syncthreads();
+  }
+  double ph_r = 1.0, ph_i = 0.0;  // running phase (thread 0)
+  if (threadIdx.x == 0) { phr[0] = 1.0; phi[0] = 0.0; }
+  for (int i = 0; i < n - 1; ++i) {
+    const int m = n - 1 - i;
+    double nx2 = 0.0;
+    for (int r = threadIdx.x; r < m; r += blockDim.x) {
+      const float2 x = A[packed(i + 1 + r, i)];
+      v[r] = x;
+      nx2 += (double)x.x * x.x + (double)x.y * x.y;
+    }
+    nx2 = block_sum(nx2, red);
+    if (threadIdx.x == 0) {
+      dg[i] = (double)A[packed(i, i)].x;
+      const float2 x0 = v[0];
+      const double ax02 = (double)x0.x * x0.x + (double)x0.y * x0.y;
+      double tau = 0.0;
+      float2 beta = x0;
+      float2 scl = make_float2(0.f, 0.f);
+      if (nx2 - ax02 > 1e-14 * nx2 && nx2 > 0.0) {
+        // v = x - beta e_1 with v_0 = phase (|x_0| + ||x||); normalised to v_0 = 1,
+        // which keeps tau = 1 + |x_0| / ||x|| in [1, 2] whatever the column scale.
+        const double nx = sqrt(nx2), ax0 = sqrt(ax02);
+        const double pr = ax0 > 0.0 ? x0.x / ax0 : 1.0, pi = ax0 > 0.0 ? x0.y / ax0 : 0.0;
+        beta = make_float2((float)(-pr * nx), (float)(-pi * nx));
+        const double inv = 1.0 / (ax0 + nx);                 // 1 / v_0 = conj(phase) / (|x_0| + ||x||)
+        scl = make_float2((float)(pr * inv), (float)(-pi * inv));
+        v[0] = make_float2(1.f, 0.f);
+        tau = 1.0 + ax0 / nx;
+      }
+      s_scale = scl;
+      s_tau = tau;
+      s_beta = beta;
+      taus[i] = tau;
+      const double br = beta.x, bi = beta.y, ab = sqrt(br * br + bi * bi);
+      eab[i] = ab;
+      if (ab > 0.0) {  // ph_{i+1} = ph_i beta / |beta|
+        const double ur = br / ab, ui = bi / ab;
+        const double nr = ph_r * ur - ph_i * ui, ni = ph_r * ui + ph_i * ur;
+        ph_r = nr;
+        ph_i = ni;
+      }
+      phr[i + 1] = ph_r;
+      phi[i + 1] = ph_i;
+    }
+    __syncthreads();
+    const float tau = (float)s_tau;
+    if (tau != 0.f) {
+      const float2 scl = s_scale;
+      for (int r = 1 + threadIdx.x; r < m; r += blockDim.x) v[r] = cmul(v[r], scl);
+      __syncthreads();
+      // p = tau A22 v: wave per row; row part reduced in-wave, column part in registers.
+      float2 cacc[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) cacc[u] = make_float2(0.f, 0.f);
+      for (int rr = wv; rr < m; rr += nw) {
+        const float2* row = A + packed(i + 1 + rr, i + 1);
+        const float2 vr = v[rr];
+        float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int c = lane + 64 * u;
+          if (c <= rr) {
+            const float2 a = row[c];
+            acc = cadd(acc, cmul(a, v[c]));
+            if (c < rr) cacc[u] = cadd(cacc[u], cmulc(a, vr));
+          }
+        }
+        acc.x = warp_sumf(acc.x);
+        acc.y = warp_sumf(acc.y);
+        if (lane == 0) p[rr] = acc;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int c = lane + 64 * u;
+        if (c < m) colacc[wv * n + c] = cacc[u];
+      }
+      __syncthreads();
+      double kv = 0.0;
+      for (int r = threadIdx.x; r < m; r += blockDim.x) {
+        float2 s = p[r];
+        for (int q = 0; q < nw; ++q) s = cadd(s, colacc[q * n + r]);
+        s = cscale(s, tau);
+        p[r] = s;
+        const float2 vr = v[r];
+        kv += (double)vr.x * s.x + (double)vr.y * s.y;  // Re(conj(v) p)
+      }
+      kv = block_sum(kv, red);
+      const float K = (float)(0.5 * (double)tau * kv);
+      for (int r = threadIdx.x; r < m; r += blockDim.x) p[r] = csub(p[r], cscale(v[r], K));
+      __syncthreads();
+      // A22 <- A22 - v w^H - w v^H (lower part)
+      for (int rr = wv; rr < m; rr += nw) {
+        float2* row = A + packed(i + 1 + rr, i + 1);
+        const float2 vr = v[rr], wr = p[rr];
+        for (int c = lane; c <= rr; c += 64) {
+          const float2 vc = v[c], wc = p[c];
+          // v_r conj(w_c) + w_r conj(v_c)
+          const float2 t1 = make_float2(vr.x * wc.x + vr.y * wc.y, vr.y * wc.x - vr.x * wc.y);
+          const float2 t2 = make_float2(wr.x * vc.x + wr.y * vc.y, wr.y * vc.x - wr.x * vc.y);
+          row[c] = csub(row[c], cadd(t1, t2));
+        }
+      }
+    }
+    // store the reflector in column i (below the diagonal)
+    for (int r = threadIdx.x; r < m; r += blockDim.x) A[packed(i + 1 + r, i)] = (tau != 0.f) ? v[r] : make_float2(0.f, 0.f);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    dg[n - 1] = (double)A[packed(n - 1, n - 1)].x;
+    eab[n - 1] = 0.0;
+    taus[n - 1] = 0.0;
+  }
+  if (ONCHIP) {
+    __syncthreads();
+    for (int64_t e = threadIdx.x; e < np; e += blockDim.x) gA[e] = A[e];
+  }
+}
+
+// ------------------------------------------------------ tridiagonal eigen ---
+// Number of eigenvalues of the real symmetric tridiagonal (d, e) below x
+// (Sturm sequence), restricted to rows [p0, p1].
+LRSTV_DEV int sturm_count(const double* dg, const double* e2, int p0, int p1, double x, double pivmin) {
+  int cnt = 0;
+  double q = dg[p0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  if (q < 0.0) ++cnt;
+  for (int i = p0 + 1; i <= p1; ++i) {
+    q = dg[i] - x - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+// One block per slice.  Eigenvalues above (t^2 - delta) by bisection, their
+// eigenvectors by twisted factorisation inside their unreduced block,
+// Gram-Schmidt inside clusters, output column c = eigenvector of the c-th
+// largest kept eigenvalue, multiplied by the phase (V re/im planes).
+__global__ void __launch_bounds__(256) k_trieig(const SliceDesc* __restrict__ desc, double* __restrict__ tri,
+                                                double* __restrict__ xs, float* __restrict__ V,
+                                                int* __restrict__ rcount, const double* __restrict__ mu_dev,
+                                                double alpha, float thresh) {
+  extern __shared__ double smd[];
+  __shared__ double red[8];
+  __shared__ int s_c0, s_nblk;
+  const SliceDesc d = desc[blockIdx.x];
+  const int n = d.n1;
+  double* dg = tri + d.t_off;
+  const double* eab = dg + n;
+  const double* phr = eab + n;
+  const double* phi = phr + n;
+  double* e2 = smd;                 // [n]
+  double* ee = e2 + n;              // [n] off-diagonal with splits zeroed
+  double* lam = ee + n;             // [n]
+  double* ds = lam + n;             // [n] diagonal
+  int* bstart = (int*)(ds + n);     // [n+1] block starts
+  const double t = mu_dev ? alpha / *mu_dev : (double)thresh;
+  // splitting and Gershgorin bounds
+  double gl = 1e300, gu = -1e300;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double e = (i < n - 1) ? eab[i] : 0.0;
+    if (i < n - 1 && e <= 1e-15 * (fabs(dg[i]) + fabs(dg[i + 1]))) e = 0.0;
+    ee[i] = e;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double rad = ee[i] + (i > 0 ? ee[i - 1] : 0.0);
+    gl = fmin(gl, dg[i] - rad);
+    gu = fmax(gu, dg[i] + rad);
+  }
+  gl = -block_max(-gl, red);
+  gu = block_max(gu, red);
+  const double tnorm0 = fmax(fabs(gl), fabs(gu));
+  // work on T / ||T|| so that the pivot guards below stay far from overflow
+  const double sc = tnorm0 > 0.0 ? 1.0 / tnorm0 : 1.0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    ds[i] = dg[i] * sc;
+    ee[i] *= sc;
+    e2[i] = ee[i] * ee[i];
+  }
+  gl *= sc;
+  gu *= sc;
+  __syncthreads();
+  const double tnorm = tnorm0 > 0.0 ? 1.0 : 0.0;
+  const double pivmin = 1e-290;
+  const double delta = 1e-6 * tnorm;                    // FP32 resolution of the Gram
+  const double lo_cut = fmax(t * t * sc - delta, 0.0);
+  dg = ds;
+  if (threadIdx.x == 0) {
+    int nb = 0;
+    bstart[nb++] = 0;
+    for (int i = 0; i < n - 1; ++i)
+      if (ee[i] == 0.0) bstart[nb++] = i + 1;
+    bstart[nb] = n;
+    s_nblk = nb;
+    s_c0 = (tnorm == 0.0) ? n : sturm_count(dg, e2, 0, n - 1, lo_cut, pivmin);
+  }
+  __syncthreads();
+  const int c0 = s_c0, nblk = s_nblk, r = n - c0;
+  // bisection for eigenvalues c0 .. n-1 (ascending index)
+  for (int k = c0 + threadIdx.x; k < n; k += blockDim.x) {
+    double lo = fmax(gl, lo_cut), hi = gu;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (hi - lo <= 2.2e-16 * fmax(fabs(lo), fabs(hi)) + pivmin || mid <= lo || mid >= hi) break;
+      if (sturm_count(dg, e2, 0, n - 1, mid, pivmin) <= k) lo = mid; else hi = mid;
+    }
+    lam[k] = 0.5 * (lo + hi);
+  }
+  __syncthreads();
+  // eigenvectors
+  const int64_t nn = (int64_t)n * n;
+  double* X = xs + d.x_off;    // [3][n][n] : Um, Dm(-> x), Lp ; column index k - c0
+  const double tol_eq = 1e-13 * tnorm + pivmin;
+  for (int k = c0 + threadIdx.x; k < n; k += blockDim.x) {
+    const int col = k - c0;
+    const double lk = lam[k];
+    // locate the block that holds this copy of lk
+    int lt = 0, pick = 0;
+    for (int b = 0; b < nblk; ++b) lt += sturm_count(dg, e2, bstart[b], bstart[b + 1] - 1, lk - tol_eq, pivmin);
+    int m = k - lt;  // which copy among eigenvalues equal to lk
+    for (int b = 0; b < nblk; ++b) {
+      const int p0 = bstart[b], p1 = bstart[b + 1] - 1;
+      const int eq = sturm_count(dg, e2, p0, p1, lk + tol_eq, pivmin) - sturm_count(dg, e2, p0, p1, lk - tol_eq, pivmin);
+      if (eq > 0) {
+        pick = b;
+        if (m < eq) break;
+        m -= eq;
+      }
+    }
+    const int p0 = bstart[pick], p1 = bstart[pick + 1] - 1;
+    double* Um = X + col;
+    double* Dm = X + nn + col;
+    double* Lp = X + 2 * nn + col;
+    // bottom-up U D U^T
+    double dm = dg[p1] - lk;
+    if (fabs(dm) < pivmin) dm = pivmin;
+    Dm[(int64_t)p1 * n] = dm;
+    for (int i = p1 - 1; i >= p0; --i) {
+      const double u = ee[i] / dm;
+      Um[(int64_t)i * n] = u;
+      dm = dg[i] - lk - u * ee[i];
+      if (fabs(dm) < pivmin) dm = pivmin;
+      Dm[(int64_t)i * n] = dm;
+    }
+    // top-down L D L^T and twist index
+    double dp = dg[p0] - lk;
+    if (fabs(dp) < pivmin) dp = pivmin;
+    double best = fabs(Dm[(int64_t)p0 * n]);
+    int rt = p0;
+    for (int i = p0; i < p1; ++i) {
+      const double l = ee[i] / dp;
+      Lp[(int64_t)i * n] = l;
+      dp = dg[i + 1] - lk - l * ee[i];
+      if (fabs(dp) < pivmin) dp = pivmin;
+      const double g = dp + Dm[(int64_t)(i + 1) * n] - (dg[i + 1] - lk);
+      if (fabs(g) < best) { best = fabs(g); rt = i + 1; }
+    }
+    // solve with the twist: x_rt = 1
+    double* x = Dm;
+    for (int i = 0; i < n; ++i)
+      if (i < p0 || i > p1) x[(int64_t)i * n] = 0.0;
+    x[(int64_t)rt * n] = 1.0;
+    double xv = 1.0, nrm = 1.0;
+    for (int i = rt - 1; i >= p0; --i) {
+      xv = -Lp[(int64_t)i * n] * xv;
+      x[(int64_t)i * n] = xv;
+      nrm += xv * xv;
+    }
+    xv = 1.0;
+    for (int i = rt; i < p1; ++i) {
+      xv = -Um[(int64_t)i * n] * xv;
+      x[(int64_t)(i + 1) * n] = xv;
+      nrm += xv * xv;
+    }
+    const double inv = 1.0 / sqrt(nrm);
+    for (int i = p0; i <= p1; ++i) x[(int64_t)i * n] *= inv;
+  }
+  __syncthreads();
+  // Gram-Schmidt inside clusters of nearly equal eigenvalues
+  double* Xv = X + nn;
+  const double gtol = 1e-8 * tnorm;
+  for (int k = c0 + 1; k < n; ++k) {
+    int k0 = k;
+    while (k0 > c0 && lam[k0] - lam[k0 - 1] <= gtol) --k0;
+    if (k0 == k) continue;
+    const int ck = k - c0;
+    for (int kp = k0; kp < k; ++kp) {
+      const int cp = kp - c0;
+      double dot = 0.0;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) dot += Xv[(int64_t)i * n + ck] * Xv[(int64_t)i * n + cp];
+      dot = block_sum(dot, red);
+      for (int i = threadIdx.x; i < n; i += blockDim.x) Xv[(int64_t)i * n + ck] -= dot * Xv[(int64_t)i * n + cp];
+      __syncthreads();
+    }
+    double nr = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) nr += Xv[(int64_t)i * n + ck] * Xv[(int64_t)i * n + ck];
+    nr = block_sum(nr, red);
+    const double inv = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) Xv[(int64_t)i * n + ck] *= inv;
+    __syncthreads();
+  }
+  // V[:, c] = phase .* x for the c-th largest eigenvalue
+  float* Vr = V + d.v_off;
+  float* Vi = Vr + nn;
+  for (int64_t e = threadIdx.x; e < (int64_t)n * r; e += blockDim.x) {
+    const int i = (int)(e / r), c = (int)(e - (int64_t)i * r);
+    const int k = n - 1 - c;
+    const double xv = Xv[(int64_t)i * n + (k - c0)];
+    Vr[(int64_t)i * n + c] = (float)(phr[i] * xv);
+    Vi[(int64_t)i * n + c] = (float)(phi[i] * xv);
+  }
+  if (threadIdx.x == 0) rcount[blockIdx.x] = r;
+}
+
+// ------------------------------------------------------- back-transform ---
+// V[:, c0:c0+cb] <- H_0 H_1 ... H_{n-2} V[:, c0:c0+cb]   (cb divides 256)
+__global__ void __launch_bounds__(256) k_backtrans(const SliceDesc* __restrict__ desc, const float2* __restrict__ gram,
+                                                   const double* __restrict__ tri, float* __restrict__ V,
+                                                   const int* __restrict__ rcount, int cb) {
+  extern __shared__ float2 sm[];
+  __shared__ float2 sdot[64];
+  const SliceDesc d = desc[blockIdx.y];
+  const int n = d.n1, r = rcount[blockIdx.y];
+  const int c0 = blockIdx.x * cb;
+  if (c0 >= r) return;
+  const int nc = min(cb, r - c0);
+  const int ngrp = blockDim.x / cb;
+  float2* Y = sm;                 // [n][cb]
+  float2* vv = Y + n * cb;        // [n]
+  float2* part = vv + n;          // [ngrp][cb]
+  const int64_t nn = (int64_t)n * n;
+  float* Vr = V + d.v_off;
+  float* Vi = Vr + nn;
+  for (int e = threadIdx.x; e < n * cb; e += blockDim.x) {
+    const int i = e / cb, c = e - i * cb;
+    Y[e] = (c < nc) ? make_float2(Vr[(int64_t)i * n + c0 + c], Vi[(int64_t)i * n + c0 + c]) : make_float2(0.f, 0.f);
+  }
+  const float2* g = gram + d.g_off;
+  const double* taus = tri + d.t_off + 4 * n;
+  __syncthreads();
+  const int c = threadIdx.x % cb, grp = threadIdx.x / cb;
+  for (int i = n - 2; i >= 0; --i) {
+    const float tau = (float)taus[i];
+    if (tau == 0.f) continue;
+    const int m = n - 1 - i;
+    for (int rr = threadIdx.x; rr < m; rr += blockDim.x) vv[rr] = g[packed(i + 1 + rr, i)];
+    __syncthreads();
+    float2 s = make_float2(0.f, 0.f);
+    for (int rr = grp; rr < m; rr += ngrp) s = cadd(s, cmulc(vv[rr], Y[(i + 1 + rr) * cb + c]));
+    part[grp * cb + c] = s;
+    __syncthreads();
+    if (threadIdx.x < cb) {
+      float2 t = part[threadIdx.x];
+      for (int q = 1; q < ngrp; ++q) t = cadd(t, part[q * cb + threadIdx.x]);
+      sdot[threadIdx.x] = cscale(t, tau);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < m * cb; e += blockDim.x) {
+      const int rr = e / cb, cc = e - rr * cb;
+      Y[(i + 1 + rr) * cb + cc] = csub(Y[(i + 1 + rr) * cb + cc], cmul(vv[rr], sdot[cc]));
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < n * cb; e += blockDim.x) {
+    const int i = e / cb, cc = e - i * cb;
+    if (cc < nc) {
+      Vr[(int64_t)i * n + c0 + cc] = Y[e].x;
+      Vi[(int64_t)i * n + c0 + cc] = Y[e].y;
+    }
+  }
+}
+
+// ----------------------------------------------------- back-projection ---
+// tall: B (h x r, ld n) = M V_r;  wide: B (r x w, ld w) = U_r^H M
+__global__ void __launch_bounds__(256) k_bp1(const SliceDesc* __restrict__ desc, const float* __restrict__ sl,
+                                             const float* __restrict__ V, float* __restrict__ Bb,
+                                             const int* __restrict__ rcount) {
+  __shared__ float2 As[16][33], Bs[16][33];
+  const SliceDesc d = desc[blockIdx.z];
+  const int r = rcount[blockIdx.z], n = d.n1, h = d.h, w = d.w;
+  const float* mr = sl + d.a_off;
+  const float* mi = mr + (int64_t)h * w;
+  const float* vr = V + d.v_off;
+  const float* vi = vr + (int64_t)n * n;
+  float* br = Bb + d.b_off;
+  float* bi = br + (int64_t)h * w;
+  float2 c00, c01, c10, c11;
+  int M, N, ld;
+  const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
+  if (d.tall) {
+    M = h; N = r; ld = n;
+    if (m0 >= M || n0 >= N) return;
+    auto fa = [&](int m, int k) -> float2 {
+      if (m >= h || k >= w) return make_float2(0.f, 0.f);
+      return make_float2(mr[(int64_t)m * w + k], mi[(int64_t)m * w + k]);
+    };
+    auto fb = [&](int k, int c) -> float2 {
+      if (k >= n || c >= r) return make_float2(0.f, 0.f);
+      return make_float2(vr[(int64_t)k * n + c], vi[(int64_t)k * n + c]);
+    };
+    ctile<true, false>(m0, n0, w, fa, fb, c00, c01, c10, c11, As, Bs);
+  } else {
+    M = r; N = w; ld = w;
+    if (m0 >= M || n0 >= N) return;
+    auto fa = [&](int m, int k) -> float2 {
+      if (m >= r || k >= h) return make_float2(0.f, 0.f);
+      return make_float2(vr[(int64_t)k * n + m], -vi[(int64_t)k * n + m]);
+    };
+    auto fb = [&](int k, int c) -> float2 {
+      if (k >= h || c >= w) return make_float2(0.f, 0.f);
+      return make_float2(mr[(int64_t)k * w + c], mi[(int64_t)k * w + c]);
+    };
+    ctile<false, false>(m0, n0, h, fa, fb, c00, c01, c10, c11, As, Bs);
+  }
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int r0 = m0 + ty, r1 = r0 + 16, q0 = n0 + tx, q1 = q0 + 16;
+  auto st = [&](int a, int b, float2 v) {
+    if (a < M && b < N) { br[(int64_t)a * ld + b] = v.x; bi[(int64_t)a * ld + b] = v.y; }
+  };
+  st(r0, q0, c00); st(r0, q1, c01); st(r1, q0, c10); st(r1, q1, c11);
+}
+
+// sigma_c = ||B[:, c]|| (tall) or ||B[c, :]|| (wide); f_c = max(1 - t/sigma_c, 0)
+__global__ void __launch_bounds__(256) k_colnorm(const SliceDesc* __restrict__ desc, const float* __restrict__ Bb,
+                                                 float* __restrict__ fval, const int* __restrict__ rcount,
+                                                 const double* __restrict__ mu_dev, double alpha, float thresh) {
+  __shared__ double red[8];
+  const SliceDesc d = desc[blockIdx.y];
+  const int r = rcount[blockIdx.y], c = blockIdx.x;
+  if (c >= r) return;
+  const int h = d.h, w = d.w, n = d.n1;
+  const float* br = Bb + d.b_off;
+  const float* bi = br + (int64_t)h * w;
+  double s = 0.0;
+  if (d.tall) {
+    for (int i = threadIdx.x; i < h; i += blockDim.x) {
+      const double a = br[(int64_t)i * n + c], b = bi[(int64_t)i * n + c];
+      s += a * a + b * b;
+    }
+  } else {
+    for (int i = threadIdx.x; i < w; i += blockDim.x) {
+      const double a = br[(int64_t)c * w + i], b = bi[(int64_t)c * w + i];
+      s += a * a + b * b;
+    }
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    const double t = mu_dev ? alpha / *mu_dev : (double)thresh;
+    const double sg = sqrt(s);
+    fval[d.f_off + c] = (sg > t) ? (float)(1.0 - t / sg) : 0.f;
+  }
+}
+
+// tall: Ehat (h x w) = B diag(f) V_r^H;  wide: Ehat = U_r diag(f) B.  Written over M.
+__global__ void __launch_bounds__(256) k_bp2(const SliceDesc* __restrict__ desc, float* __restrict__ sl,
+                                             const float* __restrict__ V, const float* __restrict__ Bb,
+                                             const float* __restrict__ fval, const int* __restrict__ rcount) {
+  __shared__ float2 As[16][33], Bs[16][33];
+  const SliceDesc d = desc[blockIdx.z];
+  const int r = rcount[blockIdx.z], n = d.n1, h = d.h, w = d.w;
+  const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
+  if (m0 >= h || n0 >= w) return;
+  float* er = sl + d.a_off;
+  float* ei = er + (int64_t)h * w;
+  const float* vr = V + d.v_off;
+  const float* vi = vr + (int64_t)n * n;
+  const float* br = Bb + d.b_off;
+  const float* bi = br + (int64_t)h * w;
+  const float* f = fval + d.f_off;
+  float2 c00, c01, c10, c11;
+  if (d.tall) {
+    auto fa = [&](int m, int k) -> float2 {
+      if (m >= h || k >= r) return make_float2(0.f, 0.f);
+      const float s = f[k];
+      return make_float2(br[(int64_t)m * n + k] * s, bi[(int64_t)m * n + k] * s);
+    };
+    auto fb = [&](int k, int c) -> float2 {
+      if (k >= r || c >= w) return make_float2(0.f, 0.f);
+      return make_float2(vr[(int64_t)c * n + k], -vi[(int64_t)c * n + k]);
+    };
+    ctile<true, true>(m0, n0, r, fa, fb, c00, c01, c10, c11, As, Bs);
+  } else {
+    auto fa = [&](int m, int k) -> float2 {
+      if (m >= h || k >= r) return make_float2(0.f, 0.f);
+      const float s = f[k];
+      return make_float2(vr[(int64_t)m * n + k] * s, vi[(int64_t)m * n + k] * s);
+    };
+    auto fb = [&](int k, int c) -> float2 {
+      if (k >= r || c >= w) return make_float2(0.f, 0.f);
+      return make_float2(br[(int64_t)k * w + c], bi[(int64_t)k * w + c]);
+    };
+    ctile<true, false>(m0, n0, r, fa, fb, c00, c01, c10, c11, As, Bs);
+  }
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int r0 = m0 + ty, r1 = r0 + 16, q0 = n0 + tx, q1 = q0 + 16;
+  auto st = [&](int a, int b, float2 v) {
+    if (a < h && b < w) { er[(int64_t)a * w + b] = v.x; ei[(int64_t)a * w + b] = v.y; }
+  };
+  st(r0, q0, c00); st(r0, q1, c01); st(r1, q0, c10); st(r1, q1, c11);
+}
+
+// ------------------------------------------------------------ launcher ---
+static size_t tridiag_onchip_bytes(int n) {
+  return ((size_t)n * (n + 1) / 2 + 2 * (size_t)n + 4 * (size_t)n) * sizeof(float2);
+}
+
+void launch_svt(const SvtLaunch& L, hipStream_t s) {
+  const int ns = L.n_slices, n = L.max_n1, m = L.max_m1;
+  if (ns == 0) return;
+  const int T = (n + 31) / 32;
+  hipLaunchKernelGGL(k_gram, dim3(T * (T + 1) / 2, ns), dim3(256), 0, s, L.desc, L.slices, L.gram);
+  static int lds_max = -1;
+  if (lds_max < 0) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    lds_max = 65536;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      lds_max = (int)prop.sharedMemPerBlock;
+  }
+  const size_t onchip = tridiag_onchip_bytes(n);
+  static size_t onchip_granted = 65536;
+  bool use_onchip = onchip <= onchip_granted;
+  if (!use_onchip && (int)onchip + 1024 <= lds_max) {
+    if (hipFuncSetAttribute((const void*)k_tridiag<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)onchip) ==
+        hipSuccess) {
+      onchip_granted = onchip;
+      use_onchip = true;
+    } else {
+      (void)hipGetLastError();  // clear the sticky error: the global-memory variant is used instead
+    }
+  }
+  if (use_onchip) {
+    hipLaunchKernelGGL(k_tridiag<true>, dim3(ns), dim3(256), onchip, s, L.desc, L.gram, L.tri);
+  } else {
+    hipLaunchKernelGGL(k_tridiag<false>, dim3(ns), dim3(256), (size_t)(2 + 4) * n * sizeof(float2), s, L.desc,
+                       L.gram, L.tri);
+  }
+  const size_t eig_lds = (size_t)4 * n * sizeof(double) + (size_t)(n + 1) * sizeof(int);
+  hipLaunchKernelGGL(k_trieig, dim3(ns), dim3(256), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount, L.mu, L.alpha,
+                     L.thresh);
+  int cb = 64;
+  while (cb > 4 && ((size_t)n * cb + n + 256) * sizeof(float2) > 60 * 1024) cb >>= 1;
+  const size_t bt_lds = ((size_t)n * cb + n + 256) * sizeof(float2);
+  hipLaunchKernelGGL(k_backtrans, dim3((n + cb - 1) / cb, ns), dim3(256), bt_lds, s, L.desc, L.gram, L.tri, L.V,
+                     L.rcount, cb);
+  // B: tall h x r, wide r x w -> tiles over (max(n, m)) both ways
+  hipLaunchKernelGGL(k_bp1, dim3((m + 31) / 32, (m + 31) / 32, ns), dim3(256), 0, s, L.desc, L.slices, L.V, L.B,
+                     L.rcount);
+  hipLaunchKernelGGL(k_colnorm, dim3(n, ns), dim3(256), 0, s, L.desc, L.B, L.fval, L.rcount, L.mu, L.alpha,
+                     L.thresh);
+  hipLaunchKernelGGL(k_bp2, dim3((m + 31) / 32, (m + 31) / 32, ns), dim3(256), 0, s, L.desc, L.slices, L.V, L.B,
+                     L.fval, L.rcount);
+}
+
+}  // namespace lrstv

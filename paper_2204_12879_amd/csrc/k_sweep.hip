@@ -1,0 +1,222 @@
+// Element-wise and stencil kernels of one ADMM iteration (Sec. III-C):
+//   k_lrhs        L-update (1st step, full Tucker rank) fused with the
+//                 right-hand side T_z of the Z-update (adjoint differences);
+//   k_grad_shrink forward differences D_w Z, F-update (soft-threshold),
+//                 Gamma3 / Gamma2 ascent, S-update and Gamma1 ascent, and the
+//                 t-SVT input A = F - Gamma4/mu; Frobenius / max residuals;
+//   k_fill, k_init_state, k_finish_iter, k_mu_step: state set-up,
+//                 fixed-order FP64 residual reduction and the penalty update.
+//
+// Cubes are FP32 [b][h][w] (w fastest); differences are periodic.  The
+// gradient-shaped variables F, E, Gamma3, Gamma4 are three cubes spaced by
+// `ts` floats.  mu lives on the device so that iterations can be replayed
+// without host involvement.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace lrstv {
+
+__global__ void k_fill(float* __restrict__ p, int64_t n, float v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_copy(float* __restrict__ dst, const float* __restrict__ src, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+__global__ void k_set_mu(double* mu, double v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *mu = v;
+}
+
+// L = 1/2 (O - S + Z + (Gamma1 - Gamma2)/mu)
+// T_z = mu L + Gamma2 + sum_n w_n D_n^T (mu F_n - Gamma3_n),
+// (D_n^T y)[v] = y[v - e_n] - y[v].
+__global__ void __launch_bounds__(256) k_lrhs(const float* __restrict__ O, const float* __restrict__ S,
+                                              const float* __restrict__ Z, const float* __restrict__ G1,
+                                              const float* __restrict__ G2, const float* __restrict__ F,
+                                              const float* __restrict__ G3, int64_t ts, float* __restrict__ L,
+                                              float* __restrict__ Tz, int h, int w, int b, float w1, float w2,
+                                              float w3, const double* __restrict__ mu_dev) {
+  const int64_t hw = (int64_t)h * w, N = hw * b;
+  const double mud = *mu_dev;
+  const float mu = (float)mud, imu = (float)(1.0 / mud);
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < N; q += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(q % w);
+    const int i = (int)((q / w) % h);
+    const int j = (int)(q / hw);
+    const float l = 0.5f * (O[q] - S[q] + Z[q] + (G1[q] - G2[q]) * imu);
+    L[q] = l;
+    const int64_t qh = (i == 0) ? q + (int64_t)(h - 1) * w : q - w;
+    const int64_t qw = (x == 0) ? q + (w - 1) : q - 1;
+    const int64_t qb = (j == 0) ? q + (int64_t)(b - 1) * hw : q - hw;
+    const float* F1 = F + ts;
+    const float* F2 = F + 2 * ts;
+    const float* H1 = G3 + ts;
+    const float* H2 = G3 + 2 * ts;
+    const float y0 = mu * F[q] - G3[q], y0n = mu * F[qh] - G3[qh];
+    const float y1 = mu * F1[q] - H1[q], y1n = mu * F1[qw] - H1[qw];
+    const float y2 = mu * F2[q] - H2[q], y2n = mu * F2[qb] - H2[qb];
+    Tz[q] = mu * l + G2[q] + w1 * (y0n - y0) + w2 * (y1n - y1) + w3 * (y2n - y2);
+  }
+}
+
+// G_n = w_n D_n Z (forward, periodic)
+// F_n = R_{tau/mu}( 1/2 (G_n + Gamma3_n/mu + E_n + Gamma4_n/mu) )
+// Gamma3_n += mu (G_n - F_n);   A_n = F_n - Gamma4_n / mu
+// Gamma2 += mu (L - Z)
+// S = R_{lambda/mu}(O - L + Gamma1/mu);   Gamma1 += mu (O - L - S)
+// Residual partials (one per block, fixed grid of LRSTV_PARTS blocks):
+//   max|O-L-S|, max|L-Z|, sum (O-L-S)^2, sum (L-Z)^2, sum_n (G_n - F_n)^2.
+__global__ void __launch_bounds__(256) k_grad_shrink(
+    const float* __restrict__ O, const float* __restrict__ L, const float* __restrict__ Z, float* __restrict__ S,
+    float* __restrict__ G1, float* __restrict__ G2, float* __restrict__ F, const float* __restrict__ E,
+    float* __restrict__ G3, const float* __restrict__ G4, float* __restrict__ A, int64_t ts, int64_t as, int h,
+    int w, int b,
+    float w1, float w2, float w3, float tau, float lam, const double* __restrict__ mu_dev,
+    double* __restrict__ part /* [R_COUNT][LRSTV_PARTS] of this cube */) {
+  __shared__ double red[8];
+  const int64_t hw = (int64_t)h * w, N = hw * b;
+  const double mud = *mu_dev;
+  const float mu = (float)mud, imu = (float)(1.0 / mud);
+  const float tmu = (float)(tau / mud), lmu = (float)(lam / mud);
+  const float wn[3] = {w1, w2, w3};
+  double m_ols = 0, m_lz = 0, s_ols = 0, s_lz = 0, s_dzf = 0;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < N; q += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(q % w);
+    const int i = (int)((q / w) % h);
+    const int j = (int)(q / hw);
+    const float z = Z[q], l = L[q], o = O[q];
+    const int64_t qn[3] = {(i == h - 1) ? q - (int64_t)(h - 1) * w : q + w, (x == w - 1) ? q - (w - 1) : q + 1,
+                           (j == b - 1) ? q - (int64_t)(b - 1) * hw : q + hw};
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      const int64_t o3 = n * ts + q;
+      const float g = wn[n] * (Z[qn[n]] - z);
+      const float g3 = G3[o3], g4 = G4[o3];
+      const float f = soft_threshold(0.5f * (g + g3 * imu + E[o3] + g4 * imu), tmu);
+      F[o3] = f;
+      G3[o3] = g3 + mu * (g - f);
+      A[n * as + q] = f - g4 * imu;
+      const double d = (double)g - (double)f;
+      s_dzf += d * d;
+    }
+    G2[q] = G2[q] + mu * (l - z);
+    const float g1 = G1[q];
+    const float s = soft_threshold(o - l + g1 * imu, lmu);
+    S[q] = s;
+    const float r = o - l - s;
+    G1[q] = g1 + mu * r;
+    const double dr = r, dz = (double)l - (double)z;
+    m_ols = fmax(m_ols, fabs(dr));
+    m_lz = fmax(m_lz, fabs(dz));
+    s_ols += dr * dr;
+    s_lz += dz * dz;
+  }
+  m_ols = block_max(m_ols, red);
+  m_lz = block_max(m_lz, red);
+  s_ols = block_sum(s_ols, red);
+  s_lz = block_sum(s_lz, red);
+  s_dzf = block_sum(s_dzf, red);
+  if (threadIdx.x == 0) {
+    part[R_INF_OLS * LRSTV_PARTS + blockIdx.x] = m_ols;
+    part[R_INF_LZ * LRSTV_PARTS + blockIdx.x] = m_lz;
+    part[R_FRO_OLS * LRSTV_PARTS + blockIdx.x] = s_ols;
+    part[R_FRO_LZ * LRSTV_PARTS + blockIdx.x] = s_lz;
+    part[R_FRO_DZF * LRSTV_PARTS + blockIdx.x] = s_dzf;
+  }
+}
+
+// One block per cube: fixed-order reduction of the residual partials.
+// out[cube][R_COUNT] (and optionally res_user[cube][R_COUNT]); sets *flag to
+// 1 when a residual is not finite.
+__global__ void k_finish_iter(const double* __restrict__ part, int n_cubes, const double* __restrict__ mu_dev,
+                              double* __restrict__ out, double* __restrict__ res_user, int* __restrict__ flag) {
+  __shared__ double red[8];
+  const int c = blockIdx.x;
+  if (c >= n_cubes) return;
+  const double* p = part + (int64_t)c * R_COUNT * LRSTV_PARTS;
+  double v[R_COUNT];
+  double nbad = 0.0;
+  for (int r = 0; r < R_COUNT; ++r) {
+    double a = 0.0;
+    const bool is_max = (r == R_INF_OLS || r == R_INF_LZ);
+    for (int k = threadIdx.x; k < LRSTV_PARTS; k += blockDim.x) {
+      const double x = p[r * LRSTV_PARTS + k];
+      if (!isfinite(x)) nbad += 1.0;
+      else a = is_max ? fmax(a, x) : a + x;
+    }
+    v[r] = is_max ? block_max(a, red) : block_sum(a, red);
+  }
+  nbad = block_sum(nbad, red);
+  if (threadIdx.x == 0) {
+    const double mu = *mu_dev;
+    double o[R_COUNT];
+    o[R_INF_OLS] = v[R_INF_OLS];
+    o[R_INF_LZ] = v[R_INF_LZ];
+    o[R_FRO_OLS] = sqrt(v[R_FRO_OLS]);
+    o[R_FRO_LZ] = sqrt(v[R_FRO_LZ]);
+    o[R_FRO_DZF] = sqrt(v[R_FRO_DZF]);
+    o[R_FRO_EF] = sqrt(v[R_FRO_EF]);
+    o[R_DUAL_Z] = mu * sqrt(v[R_DUAL_Z]);
+    bool bad = nbad > 0.0;
+    for (int r = 0; r < R_COUNT; ++r) {
+      if (nbad > 0.0) o[r] = __longlong_as_double(0x7ff8000000000000ULL);  // NaN
+      out[c * R_COUNT + r] = o[r];
+      if (res_user) res_user[c * R_COUNT + r] = o[r];
+      bad |= !isfinite(o[r]);
+    }
+    if (bad) atomicExch(flag, 1);
+  }
+}
+
+__global__ void k_mu_step(double* mu, double rho, double mu_max) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *mu = fmin(rho * *mu, mu_max);
+}
+
+// ------------------------------------------------------------ launchers ---
+
+void launch_fill(float* p, int64_t n, float v, hipStream_t s) {
+  if (n <= 0) return;
+  int grid = (int)((n + 255) / 256);
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(k_fill, dim3(grid), dim3(256), 0, s, p, n, v);
+}
+
+void launch_copy(float* dst, const float* src, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  int grid = (int)((n + 255) / 256);
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, s, dst, src, n);
+}
+
+void launch_set_mu(double* mu, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_mu, dim3(1), dim3(64), 0, s, mu, v);
+}
+
+void launch_lrhs(const CubePtrs& c, const Weights& wt, const double* mu, hipStream_t s) {
+  const int64_t N = (int64_t)c.h * c.w * c.b;
+  int grid = (int)((N + 255) / 256);
+  if (grid > 8192) grid = 8192;
+  hipLaunchKernelGGL(k_lrhs, dim3(grid), dim3(256), 0, s, c.O, c.S, c.Z, c.G1, c.G2, c.F, c.G3, c.ts, c.L, c.T,
+                     c.h, c.w, c.b, (float)wt.w[0], (float)wt.w[1], (float)wt.w[2], mu);
+}
+
+void launch_grad_shrink(const CubePtrs& c, const Weights& wt, const double* mu, double* part, int64_t a_stride,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_shrink, dim3(LRSTV_PARTS), dim3(256), 0, s, c.O, c.L, c.Z, c.S, c.G1, c.G2, c.F, c.E,
+                     c.G3, c.G4, c.A, c.ts, a_stride, c.h, c.w, c.b, (float)wt.w[0], (float)wt.w[1], (float)wt.w[2],
+                     (float)wt.tau, (float)wt.lam, mu, part);
+}
+
+void launch_finish_iter(const double* part, int n_cubes, const double* mu, double* out, double* res_user,
+                        int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_iter, dim3(n_cubes), dim3(256), 0, s, part, n_cubes, mu, out, res_user, flag);
+}
+
+void launch_mu_step(double* mu, double rho, double mu_max, hipStream_t s) {
+  hipLaunchKernelGGL(k_mu_step, dim3(1), dim3(64), 0, s, mu, rho, mu_max);
+}
+
+}  // namespace lrstv

@@ -1,0 +1,73 @@
+// Host-side launcher declarations shared by the kernel files and the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lrstv {
+
+struct Weights {
+  double tau, alpha, lam;
+  double w[3];
+};
+
+// Device pointers of one cube's state inside the packed batch.  F, E, G3,
+// G4 and A point at component 0; component n is at + n * ts.
+struct CubePtrs {
+  int h, w, b;
+  int64_t ts;
+  const float* O;
+  float *L, *Z, *S, *G1, *G2, *F, *E, *G3, *G4, *A, *T;
+};
+
+struct SliceDesc;
+
+void launch_fill(float* p, int64_t n, float v, hipStream_t s);
+void launch_copy(float* dst, const float* src, int64_t n, hipStream_t s);
+void launch_set_mu(double* mu, double v, hipStream_t s);
+void launch_lrhs(const CubePtrs& c, const Weights& wt, const double* mu, hipStream_t s);
+// A (t-SVT input) has component stride a_stride.
+void launch_grad_shrink(const CubePtrs& c, const Weights& wt, const double* mu, double* part, int64_t a_stride,
+                        hipStream_t s);
+void launch_finish_iter(const double* part, int n_cubes, const double* mu, double* out, double* res_user,
+                        int* flag, hipStream_t s);
+void launch_mu_step(double* mu, double rho, double mu_max, hipStream_t s);
+
+// --- Z-update: FFT along w and h, periodic tridiagonal solve along b -------
+// spec holds b * h * (w/2+1) complex values.
+void launch_rfft_w(const float* T, float2* spec, int h, int w, int b, hipStream_t s);
+void launch_fft_h(float2* spec, int h, int w, int b, int sign, hipStream_t s);
+void launch_tri_b(float2* spec, int h, int w, int b, const double wts[3], const double* mu, double mu_host,
+                  hipStream_t s);
+// Z <- irfft; if part != NULL also writes sum (Z_new - Z_old)^2 partials (slot R_DUAL_Z).
+void launch_irfft_w(const float2* spec, float* Z, int h, int w, int b, double* part, hipStream_t s);
+
+// --- band DFT (t-SVT forward) and inverse (+ Gamma4 ascent) ---------------
+// A: n_t real cubes spaced by a_stride floats; slices: planar complex,
+// [t][k][re|im][h][w] with k < b/2+1.
+void launch_band_dft(const float* A, int64_t a_stride, int n_t, float* slices, int h, int w, int b, hipStream_t s);
+// E_t = IDFT_b(slices); if G4 != NULL: Gamma4 += mu (E - F) and residual partials (slot R_FRO_EF).
+void launch_band_idft(const float* slices, int n_t, float* E, int64_t e_stride, int h, int w, int b,
+                      const float* F, float* G4, const double* mu, double* part, hipStream_t s);
+
+// --- slice SVT ------------------------------------------------------------
+// thresh: t = alpha / mu read on the device (mu != NULL) or the fixed value.
+struct SvtLaunch {
+  const SliceDesc* desc;   // device array [n_slices]
+  int n_slices;
+  int max_n1, max_m1;      // over slices
+  float* slices;           // base of the slice planes (input M, output E_hat)
+  float2* gram;            // packed Grams / reflectors
+  float* V;                // eigenvectors (planar)
+  float* B;                // back-projection intermediate
+  double* tri;             // tridiagonal scratch
+  double* xs;              // eigenvector scratch
+  float* fval;             // shrink factors
+  int* rcount;             // surviving singular values per slice
+  const double* mu;        // device mu or NULL
+  double alpha;            // threshold numerator (t = alpha / mu) when mu != NULL
+  float thresh;            // fixed threshold when mu == NULL
+  int precision;
+};
+void launch_svt(const SvtLaunch& L, hipStream_t s);
+
+}  // namespace lrstv

@@ -1,0 +1,192 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Inputs are seeded; both sides see the same float32 values (the oracle gets
+them widened to float64).  Tolerances: relative Frobenius error <= 1e-4 for
+FP32 results (the bar the full ADMM output must meet), tighter for the
+single linear steps.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2204_12879_amd as L
+    L.load_library()
+    return L
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+# ------------------------------------------------------------ Z-update ---
+@pytest.mark.parametrize("shape,wts,mu", [
+    ((16, 32, 32), (1.0, 1.0, 1.0), 0.7),
+    ((7, 13, 20), (1.0, 0.5, 2.0), 3.0),       # odd / prime sides, ragged tails
+    ((1, 9, 11), (1.0, 1.0, 1.0), 1.0),        # single band
+    ((2, 8, 6), (0.3, 1.0, 1.0), 0.01),        # two bands
+    ((5, 53, 47), (1.0, 1.0, 0.0), 2.0),       # prime spatial sides, no spectral term
+    ((191, 24, 16), (1.0, 1.0, 1.0), 5.0),     # prime band count of the 256x256x191 cube
+])
+def test_zsolve_matches_oracle(shape, wts, mu):
+    L = _lib()
+    say("zsolve", shape, wts, mu)
+    rng = np.random.default_rng(sum(shape))
+    T = rng.normal(size=shape).astype(np.float32)
+    Z = L.zsolve(torch.from_numpy(T).cuda(), mu, wts)
+    torch.cuda.synchronize()
+    ref = oracle.z_solve(T.astype(np.float64), mu, wts)
+    assert rel(Z.cpu().numpy(), ref) < 2e-6
+
+
+# --------------------------------------------------------------- t-SVT ---
+def _lowrank_tensor(shape, rank, seed, noise=0.05):
+    b, h, w = shape
+    rng = np.random.default_rng(seed)
+    U = rng.normal(size=(b, h, rank))
+    V = rng.normal(size=(b, rank, w))
+    A = np.einsum("bhr,brw->bhw", U, V) / np.sqrt(rank) + noise * rng.normal(size=shape)
+    return A.astype(np.float32)
+
+
+def _slice_sv(A):
+    Ah = np.fft.fft(A.astype(np.float64), axis=0)
+    return np.concatenate([np.linalg.svd(Ah[k], compute_uv=False) for k in range(A.shape[0] // 2 + 1)])
+
+
+@pytest.mark.parametrize("shape", [(16, 32, 32), (9, 17, 12), (8, 12, 17), (1, 20, 20), (6, 33, 40),
+                                   (31, 48, 64), (4, 150, 160)])
+def test_svt_matches_oracle(shape):
+    L = _lib()
+    A = _lowrank_tensor(shape, rank=4, seed=shape[1] * 7 + shape[2])
+    sv = _slice_sv(A)
+    for q in (0.0, 0.3, 0.7, 0.95):
+        t = float(np.quantile(sv, q)) if q > 0 else 0.0
+        say("svt", shape, "t =", t)
+        E = L.svt(torch.from_numpy(A).cuda(), t)
+        torch.cuda.synchronize()
+        ref = oracle.tsvt(A.astype(np.float64), t)
+        err = rel(E.cpu().numpy(), ref)
+        assert err < 1e-5, (q, err)
+    big = float(sv.max()) * 1.01
+    E = L.svt(torch.from_numpy(A).cuda(), big)
+    torch.cuda.synchronize()
+    assert float(E.abs().max()) == 0.0
+
+
+def test_svt_batch_equals_single():
+    L = _lib()
+    A = np.stack([_lowrank_tensor((10, 20, 24), 3, s) for s in range(3)])
+    t = 0.5
+    Eb = L.svt(torch.from_numpy(A).cuda(), t).cpu().numpy()
+    for i in range(3):
+        Ei = L.svt(torch.from_numpy(A[i]).cuda(), t).cpu().numpy()
+        assert np.array_equal(Eb[i], Ei)
+
+
+def test_svt_degenerate_spectrum():
+    """Identity-like slices: repeated singular values above the threshold."""
+    L = _lib()
+    b, h, w = 5, 16, 16
+    A = np.zeros((b, h, w), np.float32)
+    A[0] = np.eye(h, dtype=np.float32) * 2.0
+    A[2] = np.eye(h, dtype=np.float32)
+    say("svt degenerate")
+    for t in (0.0, 0.5, 1.5):
+        E = L.svt(torch.from_numpy(A).cuda(), t).cpu().numpy()
+        ref = oracle.tsvt(A.astype(np.float64), t)
+        assert rel(E, ref) < 1e-5, t
+
+
+# ----------------------------------------------------- one ADMM iteration ---
+def _params(shape):
+    b, h, w = shape
+    return oracle.Params(tau=0.02, alpha=0.3, lam=10 / np.sqrt(h * w), w=(1.0, 0.8, 1.2), mu0=0.5)
+
+
+def _state_to_gpu(st):
+    out = {}
+    for k in ("Z", "S", "G1", "G2"):
+        out[k] = torch.from_numpy(np.ascontiguousarray(st[k], np.float32)).cuda().reshape(-1)
+    for k in ("F", "E", "G3", "G4"):
+        out[k] = torch.from_numpy(np.ascontiguousarray(st[k], np.float32)).cuda().reshape(-1)
+    return out
+
+
+@pytest.mark.parametrize("shape", [(16, 32, 32), (10, 20, 24), (7, 18, 13)])
+def test_one_iteration_matches_oracle(shape):
+    L = _lib()
+    say("one iteration", shape)
+    b, h, w = shape
+    clean, noisy = synth.make_cube(synth.CubeSpec(h, w, b, 8, synth.NOISE_SMALL, 3))
+    O = noisy.astype(np.float32)
+    st = synth.random_state(b, h, w, seed=9, scale=0.1)
+    st = {k: v.astype(np.float32) for k, v in st.items()}
+    p = _params(shape)
+    mu = 0.8
+    solver = L.Solver([shape], L.Params(tau=p.tau, alpha=p.alpha, lam=p.lam, w=p.w, mu0=mu))
+    g = _state_to_gpu(st)
+    g["Y"] = torch.from_numpy(O).cuda().reshape(-1)
+    g["mu"] = torch.tensor([mu], dtype=torch.float64, device="cuda")
+    solver.set_state(g)
+    res = torch.zeros(7, dtype=torch.float64, device="cuda")
+    solver.iterate(1, residuals=res)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in solver.state().items()}
+    ost = oracle.State(Z=st["Z"].astype(np.float64), S=st["S"].astype(np.float64),
+                       F=st["F"].astype(np.float64), E=st["E"].astype(np.float64),
+                       G1=st["G1"].astype(np.float64), G2=st["G2"].astype(np.float64),
+                       G3=st["G3"].astype(np.float64), G4=st["G4"].astype(np.float64), mu=mu)
+    new, Lref, rres = oracle.admm_step(O.astype(np.float64), ost, p)
+    checks = {"X": Lref, "Z": new.Z, "S": new.S, "G1": new.G1, "G2": new.G2, "F": new.F, "E": new.E,
+              "G3": new.G3, "G4": new.G4}
+    for k, ref in checks.items():
+        err = rel(got[k].reshape(ref.shape), ref)
+        assert err < 1e-5, (k, err)
+    assert abs(got["mu"][0] - new.mu) <= 1e-12 * new.mu
+    r = res.cpu().numpy()
+    for i, key in enumerate(oracle.RESIDUAL_KEYS):
+        assert abs(r[i] - rres[key]) <= 1e-4 * max(rres[key], 1e-6), (key, r[i], rres[key])
+
+
+# ------------------------------------------------------------- full runs ---
+def _run_gpu(L, cube_list, p, iters, precision=0):
+    shapes = [c.shape for c in cube_list]
+    solver = L.Solver(shapes, L.Params(tau=p.tau, alpha=p.alpha, lam=p.lam, w=p.w, mu0=p.mu0, rho=p.rho,
+                                       mu_max=p.mu_max, precision=precision))
+    Y = torch.from_numpy(np.concatenate([c.astype(np.float32).ravel() for c in cube_list])).cuda()
+    X = torch.empty_like(Y)
+    S = torch.empty_like(Y)
+    info = solver.solve(Y, X=X, S=S, max_iter=iters)
+    torch.cuda.synchronize()
+    return X.cpu().numpy(), S.cpu().numpy(), info
+
+
+def test_small_cube_full_run_matches_oracle():
+    """32x32x16 cube, 20 iterations: rel err <= 1e-4 and |dMPSNR| <= 0.01 dB."""
+    L = _lib()
+    wl = synth.workload("small")
+    spec = wl.cubes[0]
+    clean, noisy = synth.make_cube(spec)
+    O = noisy.astype(np.float32).astype(np.float64)
+    p = oracle.default_params(spec.h, spec.w, tau=0.02, alpha=0.3)
+    say("full run small")
+    Xg, Sg, info = _run_gpu(L, [noisy], p, wl.iters)
+    Xr, Sr, st, hist = oracle.admm(O, p, wl.iters)
+    Xg = Xg.reshape(Xr.shape)
+    err = rel(Xg, Xr)
+    dpsnr = abs(oracle.mpsnr(Xg, clean) - oracle.mpsnr(Xr, clean))
+    say(f"small: rel err {err:.3e}, dMPSNR {dpsnr:.2e} dB")
+    assert err <= 1e-4 and dpsnr <= 0.01
