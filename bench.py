@@ -1,0 +1,219 @@
+"""Benchmark: LRSTV ADMM iterations/s on one MI355X.
+
+Default workload: one 256x256x191 cube (synthetic piecewise-smooth Voronoi
+cube with Gaussian + salt-and-pepper + stripe noise), 50 ADMM iterations
+(the paper's WDC Mall sub-block shape).  One step = one full ADMM iteration
+(L, Z, F, E (t-SVT), S, multipliers, mu) over the cube, inputs resident in
+HBM.  Prints ONE JSON line (rank 0) with the contract fields plus a
+`roofline` entry for the dominant kernel (timed live with hipEvents on the
+library's stream) and a `cpu_baseline` entry (the FP64 oracle timed on a
+bounded sample on this host).
+
+    python bench.py [--steps K] [--warmup W] [--workload wdc|pavia|small]
+                    [--precision fp32|bf16] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "LRSTV ADMM iters/s @256×256×191 FP32 vs split-BF16; t-SVT slices/s; rel err"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def stage_model(shape, ranks_per_slice):
+    """Algorithmic bytes (HBM-bound stages) or flops (compute stages) per launch.
+
+    Per-unit figures (N = b h w voxels, s = b/2+1 slices per gradient tensor,
+    n1 = min(h, w), m1 = max(h, w), r = kept singular values of a slice):
+      lrhs         reads 11 cubes, writes 2            -> 13 * 4N bytes
+      grad_shrink  reads 14 cubes, writes 12           -> 26 * 4N bytes
+      band_dft     reads 3 cubes, writes 3 s h w complex
+      band_idft    reads 3 s h w complex + 6 cubes, writes 6 cubes
+      rfft_w       reads 1 cube, writes b h (w/2+1) complex
+      fft_h        reads + writes the half spectrum (per direction)
+      tri_b        reads + writes the half spectrum
+      irfft_w      reads the half spectrum + old Z, writes Z
+      gram         4 m1 n1 (n1 + 1) flops per slice (packed Hermitian Gram)
+      tridiag      16/3 n1^3 flops per slice (Hermitian Householder reduction)
+      backtrans    8 n1^2 r flops per slice
+      bp1, bp2     8 m1 n1 r flops per slice each
+    """
+    b, h, w = shape
+    N = b * h * w
+    s = b // 2 + 1
+    wc = w // 2 + 1
+    spec = b * h * wc * 8
+    n1, m1 = min(h, w), max(h, w)
+    sl = 3 * s * h * w * 8
+    rs = ranks_per_slice
+    model = {
+        "lrhs": ("hbm", 13 * 4 * N),
+        "grad_shrink": ("hbm", 26 * 4 * N),
+        "band_dft": ("hbm", 3 * 4 * N + sl),
+        "band_idft": ("hbm", sl + 12 * 4 * N),
+        "rfft_w": ("hbm", 4 * N + spec),
+        "fft_h": ("hbm", 2 * spec),
+        "tri_b": ("hbm", 2 * spec),
+        "irfft_w": ("hbm", spec + 8 * N),
+        "gram": ("flops", 3 * s * 4.0 * m1 * n1 * (n1 + 1)),
+        "tridiag": ("flops", 3 * s * 16.0 / 3.0 * n1 ** 3),
+        "backtrans": ("flops", sum(8.0 * n1 * n1 * r for r in rs)),
+        "bp1": ("flops", sum(8.0 * m1 * n1 * r for r in rs)),
+        "bp2": ("flops", sum(8.0 * m1 * n1 * r for r in rs)),
+        # FP64 Sturm bisection: ~52 halvings x n1 recurrence steps x 3 flops per kept eigenvalue
+        "trieig": ("fp64", sum(52 * 3.0 * n1 * r for r in rs)),
+    }
+    return model
+
+
+def cpu_baseline(noisy, params_kw, iters):
+    """FP64 oracle on this host: `iters` ADMM iterations from the initial state."""
+    import numpy as np
+
+    import oracle
+    threads = None
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        threads = max([i.get("num_threads", 1) for i in info] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    p = oracle.Params(**params_kw)
+    O = noisy.astype(np.float32).astype(np.float64)
+    st = oracle.init_state(O, p.mu0)
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        st, _, _ = oracle.admm_step(O, st, p)
+    dt = time.perf_counter() - t0
+    return {"value": iters / dt, "unit": "iters/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{iters} ADMM iterations of the same cube from the initial state "
+                      f"(numpy FP64, {dt:.1f} s; per-iteration cost is roughly constant)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="wdc", choices=["wdc", "pavia", "small"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (the single-GPU share of the workload); "
+              "--gpus above 1 is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2204_12879_amd as L
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    wl = synth.workload(args.workload)
+    spec = wl.cubes[0]
+    clean, noisy = synth.make_cube(spec)
+    shape = (spec.b, spec.h, spec.w)
+    lam = 10.0 / np.sqrt(spec.h * spec.w)
+    pkw = dict(tau=0.02, alpha=0.3, lam=lam, w=(1.0, 1.0, 1.0), mu0=1e-2, rho=1.5, mu_max=1e6)
+    prec = L.LRSTV_FP32 if args.precision == "fp32" else L.LRSTV_SPLIT_BF16
+    solver = L.Solver([shape], L.Params(precision=prec, **pkw))
+    Y = torch.from_numpy(noisy.astype(np.float32)).cuda().reshape(-1)
+    X = torch.empty_like(Y)
+    print(f"bench: {args.workload} {shape} steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
+
+    # warm-up (untimed)
+    solver.reset(Y)
+    solver.iterate(args.warmup)
+    torch.cuda.synchronize()
+    # timed: K iterations of the solve from its initial state
+    solver.reset(Y)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    solver.iterate(args.steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    elapsed = max(wall, gpu_ms / 1e3)
+    solver.read_output(X=X)
+    torch.cuda.synchronize()
+    ranks_last = solver.slice_ranks()
+
+    # per-stage timing (separate instrumented run of the same K iterations)
+    solver.reset(Y)
+    solver.profile(True)
+    solver.iterate(args.steps)
+    st = solver.stage_times()
+    solver.profile(False)
+    ranks_prof = solver.slice_ranks()
+    model = stage_model(shape, ranks_prof)
+    dom = max(st, key=lambda k: st[k][0])
+    dom_ms, dom_n = st[dom]
+    avg_ms = dom_ms / max(dom_n, 1)
+    kind, amount = model.get(dom, ("flops", 0.0))
+    if kind == "hbm":
+        roof = {"bound": "hbm", "achieved": amount / (avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    elif kind == "fp64":
+        roof = {"bound": "alu", "achieved": amount / (avg_ms * 1e-3) / 1e12, "peak": 78.6, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "alu" if dom == "tridiag" else "mfma",
+                "achieved": amount / (avg_ms * 1e-3) / 1e12, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["avg_launch_ms"] = avg_ms
+    svt_stages = ["gram", "tridiag", "trieig", "backtrans", "bp1", "colnorm", "bp2"]
+    svt_ms = sum(st[k][0] for k in svt_stages)
+    n_slices = 3 * (spec.b // 2 + 1)
+    stages = {k: round(v[0] / args.steps, 4) for k, v in st.items()}
+
+    out = {
+        "metric": METRIC,
+        "value": args.steps / elapsed,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == L.LRSTV_FP32 else "bf16x3+f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload} {spec.h}x{spec.w}x{spec.b} single cube, ADMM iterations from the "
+                               f"initial state, tau=0.02 alpha=0.3 lambda=10/sqrt(hw) mu0=1e-2 rho=1.5",
+                   "precision": args.precision, "parallelism": "single GPU"},
+        "tsvt_slices_per_s": n_slices * args.steps / (svt_ms * 1e-3) if svt_ms > 0 else None,
+        "kept_singular_value_fraction_last_iter": float(np.sum(ranks_last)) / (n_slices * min(spec.h, spec.w)),
+        "stage_ms_per_iter": stages,
+        "roofline": roof,
+    }
+    if args.workload == "wdc" and args.steps == 50:
+        gold = os.path.join(ROOT, "tests", "golden", "wdc_k50_oracle_samples.npz")
+        if os.path.exists(gold):
+            g = np.load(gold)
+            Xg = X.cpu().numpy().astype(np.float64)
+            idx = g["index"]
+            ref = g["values"]
+            out["rel_err_vs_oracle_sampled"] = float(np.linalg.norm(Xg[idx] - ref) / np.linalg.norm(ref))
+    if not args.no_cpu:
+        print("bench: timing the FP64 oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(noisy, pkw, args.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -179,6 +179,32 @@ int lrstv_zsolve(const float* T, float* Z, int32_t h, int32_t w, int32_t b, doub
                  const double wts[3], void* ws, size_t ws_bytes, void* stream);
 
 /* ---- diagnostics ------------------------------------------------------- */
+
+/* Stages of one iteration, in launch order (lrstv_stage_name gives the
+ * names): L/T_z, rfft along w, FFT along h (both directions), tridiagonal
+ * band solve, inverse rfft, difference/shrink/multipliers, band DFT, slice
+ * Gram, tridiagonalisation, tridiagonal eigenpairs, back-transform,
+ * back-projection B, shrink factors, back-projection Ehat, inverse band DFT
+ * + Gamma4, residual reduction + mu step. */
+#define LRSTV_NSTAGES 16
+
+/* Start (enable = 1, discarding what was recorded) or stop (0) recording a
+ * pair of hipEvents around every stage launched by lrstv_iterate / solve,
+ * on the handle's stream.  Adds a few microseconds of host work per stage. */
+int lrstv_profile(lrstv_handle hd, int32_t enable);
+
+/* Synchronise the stream and return, per stage, the summed GPU
+ * milliseconds (ms[LRSTV_NSTAGES]) and launch counts (counts, may be NULL)
+ * recorded since lrstv_profile(hd, 1); clears the record.  n >= LRSTV_NSTAGES. */
+int lrstv_stage_times(lrstv_handle hd, double* ms, int32_t* counts, int32_t n);
+const char* lrstv_stage_name(int32_t stage);
+
+/* Number of singular values kept (those not below the threshold, up to the
+ * Gram's FP32 resolution) in each Fourier slice by the last iteration, host
+ * array ranks[n] in slice order (cube, gradient tensor, frequency).
+ * Synchronises the stream.  Returns the number of slices, or an error. */
+int lrstv_slice_ranks(lrstv_handle hd, int32_t* ranks, int32_t n);
+
 const char* lrstv_status_string(int status);
 const char* lrstv_last_error(void);   /* thread-local, "" if none */
 int lrstv_version(void);              /* 100 * major + minor */

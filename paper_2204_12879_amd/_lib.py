@@ -14,6 +14,7 @@ LRSTV_SPLIT_BF16 = 1
 LRSTV_NRES = 7
 RESIDUAL_NAMES = ("inf_OLS", "inf_LZ", "fro_OLS", "fro_LZ", "fro_DZF", "fro_EF", "dual_Z")
 WARN_NOT_CONVERGED = 1
+NSTAGES = 16
 
 
 class LrstvError(RuntimeError):
@@ -73,6 +74,10 @@ def load_library():
         "lrstv_svt": (C.c_int, [vp, vp, i32, i32, i32, i32, f32, i32, vp, C.c_size_t, vp]),
         "lrstv_zsolve_workspace_size": (C.c_int, [i32, i32, i32, sz]),
         "lrstv_zsolve": (C.c_int, [vp, vp, i32, i32, i32, f64, C.POINTER(C.c_double), vp, C.c_size_t, vp]),
+        "lrstv_profile": (C.c_int, [vp, i32]),
+        "lrstv_stage_times": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32), i32]),
+        "lrstv_stage_name": (C.c_char_p, [i32]),
+        "lrstv_slice_ranks": (C.c_int, [vp, C.POINTER(C.c_int32), i32]),
         "lrstv_status_string": (C.c_char_p, [C.c_int]),
         "lrstv_last_error": (C.c_char_p, []),
         "lrstv_version": (C.c_int, []),
@@ -194,6 +199,26 @@ class Solver:
         _check(rc, allow_warn=True)
         return {"iters": rep.iters, "residuals": dict(zip(RESIDUAL_NAMES, list(rep.residuals))),
                 "mu": rep.mu, "converged": rc != WARN_NOT_CONVERGED}
+
+    def profile(self, enable: bool = True) -> None:
+        """Start (discarding earlier records) or stop per-stage GPU event timing."""
+        _check(self.lib.lrstv_profile(self.handle, 1 if enable else 0))
+
+    def stage_times(self) -> dict:
+        """{stage name: (total ms, launches)} recorded since profile(True)."""
+        ms = (C.c_double * NSTAGES)()
+        cnt = (C.c_int32 * NSTAGES)()
+        _check(self.lib.lrstv_stage_times(self.handle, ms, cnt, NSTAGES))
+        return {self.lib.lrstv_stage_name(i).decode(): (ms[i], cnt[i]) for i in range(NSTAGES)}
+
+    def slice_ranks(self):
+        """Kept singular values per Fourier slice in the last iteration (list of int)."""
+        n = sum(3 * (b // 2 + 1) for b, h, w in self.shapes)
+        buf = (C.c_int32 * n)()
+        rc = self.lib.lrstv_slice_ranks(self.handle, buf, n)
+        if rc < 0:
+            _check(rc)
+        return list(buf)
 
     def _view(self, ptr: int, count: int, dtype):
         import torch

@@ -122,6 +122,7 @@ struct lrstv_handle_s {
   double *tri, *xs, *mu, *part, *res_last;
   int *rcount, *flag;
   SliceDesc* desc;
+  StageTimer timer;
 };
 
 static int check_params(const lrstv_params* p) {
@@ -231,6 +232,7 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
   if (rc) { delete H; return rc; }
   H->par = *par;
   H->stream = (hipStream_t)stream;
+  H->timer.s = H->stream;
   H->sl = make_slices(H->cubes, 3);
   size_t need = 0;
   carve_handle(H, nullptr, &need);
@@ -295,6 +297,7 @@ static CubePtrs cube_ptrs(lrstv_handle_s* H, const CubeInfo& c) {
 
 static void run_iteration(lrstv_handle_s* H, double* res_user) {
   hipStream_t s = H->stream;
+  StageTimer& tm = H->timer;
   Weights wt;
   wt.tau = H->par.tau;
   wt.alpha = H->par.alpha;
@@ -304,20 +307,32 @@ static void run_iteration(lrstv_handle_s* H, double* res_user) {
   for (int c = 0; c < nc; ++c) {
     const CubeInfo& ci = H->cubes[c];
     CubePtrs p = cube_ptrs(H, ci);
-    // A is a per-cube scratch with component stride nmax
-    p.ts = H->total;
     double* part = H->part + (int64_t)c * R_COUNT * LRSTV_PARTS;
+    tm.begin(ST_LRHS);
     launch_lrhs(p, wt, H->mu, s);                                   // 1st step + T_z
+    tm.end(ST_LRHS);
+    tm.begin(ST_RFFT_W);
     launch_rfft_w(p.T, H->spec, ci.h, ci.w, ci.b, s);               // 2nd step: Z solve
+    tm.end(ST_RFFT_W);
+    tm.begin(ST_FFT_H);
     launch_fft_h(H->spec, ci.h, ci.w, ci.b, -1, s);
+    tm.end(ST_FFT_H);
+    tm.begin(ST_TRI_B);
     launch_tri_b(H->spec, ci.h, ci.w, ci.b, wt.w, H->mu, 0.0, s);
+    tm.end(ST_TRI_B);
+    tm.begin(ST_FFT_H);
     launch_fft_h(H->spec, ci.h, ci.w, ci.b, +1, s);
+    tm.end(ST_FFT_H);
+    tm.begin(ST_IRFFT_W);
     launch_irfft_w(H->spec, p.Z, ci.h, ci.w, ci.b, part, s);
+    tm.end(ST_IRFFT_W);
     // 3rd, 5th and 6th steps (F, S, Gamma1..3); A = F - Gamma4/mu into scratch
-    CubePtrs q = p;
-    q.A = H->A;
-    launch_grad_shrink(q, wt, H->mu, part, H->nmax, s);
+    tm.begin(ST_GRAD_SHRINK);
+    launch_grad_shrink(p, wt, H->mu, part, H->nmax, s);
+    tm.end(ST_GRAD_SHRINK);
+    tm.begin(ST_BAND_DFT);
     launch_band_dft(H->A, H->nmax, 3, H->slices + ci.slice_base, ci.h, ci.w, ci.b, s);
+    tm.end(ST_BAND_DFT);
   }
   // 4th step: t-SVT of every Fourier slice of every gradient tensor
   SvtLaunch sv;
@@ -337,15 +352,19 @@ static void run_iteration(lrstv_handle_s* H, double* res_user) {
   sv.alpha = H->par.alpha;
   sv.thresh = 0.f;
   sv.precision = H->par.precision;
-  launch_svt(sv, s);
+  launch_svt(sv, s, &tm);
   for (int c = 0; c < nc; ++c) {
     const CubeInfo& ci = H->cubes[c];
     double* part = H->part + (int64_t)c * R_COUNT * LRSTV_PARTS;
+    tm.begin(ST_BAND_IDFT);
     launch_band_idft(H->slices + ci.slice_base, 3, H->E + ci.off, H->total, ci.h, ci.w, ci.b, H->F + ci.off,
                      H->G4 + ci.off, H->mu, part, s);
+    tm.end(ST_BAND_IDFT);
   }
+  tm.begin(ST_FINISH);
   launch_finish_iter(H->part, nc, H->mu, H->res_last, res_user, H->flag, s);
   launch_mu_step(H->mu, H->par.rho, H->par.mu_max, s);               // 7th step
+  tm.end(ST_FINISH);
 }
 
 extern "C" int lrstv_iterate(lrstv_handle H, int32_t n_iter, double* residuals) {
@@ -604,6 +623,39 @@ extern "C" int lrstv_zsolve(const float* T, float* Z, int32_t h, int32_t w, int3
 }
 
 // --------------------------------------------------------- diagnostics ---
+static const char* kStageNames[ST_COUNT] = {"lrhs", "rfft_w", "fft_h", "tri_b", "irfft_w", "grad_shrink",
+                                            "band_dft", "gram", "tridiag", "trieig", "backtrans", "bp1",
+                                            "colnorm", "bp2", "band_idft", "finish"};
+
+extern "C" int lrstv_profile(lrstv_handle H, int32_t enable) {
+  if (!H) return fail(LRSTV_ERR_INVALID_ARG, "handle is NULL");
+  H->timer.collect(nullptr, nullptr);
+  H->timer.on = enable != 0;
+  return LRSTV_OK;
+}
+
+extern "C" int lrstv_stage_times(lrstv_handle H, double* ms, int32_t* counts, int32_t n) {
+  if (!H || !ms || n < LRSTV_NSTAGES) return fail(LRSTV_ERR_INVALID_ARG, "need room for LRSTV_NSTAGES stages");
+  int c[ST_COUNT];
+  H->timer.collect(ms, c);
+  if (counts)
+    for (int i = 0; i < ST_COUNT; ++i) counts[i] = c[i];
+  return LRSTV_OK;
+}
+
+extern "C" int lrstv_slice_ranks(lrstv_handle H, int32_t* ranks, int32_t n) {
+  if (!H || !ranks) return fail(LRSTV_ERR_INVALID_ARG, "handle or ranks is NULL");
+  const int ns = (int)H->sl.desc.size();
+  if (n < ns) return fail(LRSTV_ERR_INVALID_ARG, "need room for %d slices", ns);
+  HIPCHK(hipMemcpyAsync(ranks, H->rcount, ns * sizeof(int), hipMemcpyDeviceToHost, H->stream));
+  HIPCHK(hipStreamSynchronize(H->stream));
+  return ns;
+}
+
+extern "C" const char* lrstv_stage_name(int32_t stage) {
+  return (stage >= 0 && stage < ST_COUNT) ? kStageNames[stage] : "";
+}
+
 extern "C" const char* lrstv_status_string(int st) {
   switch (st) {
     case LRSTV_OK: return "ok";

@@ -649,11 +649,15 @@ static size_t tridiag_onchip_bytes(int n) {
   return ((size_t)n * (n + 1) / 2 + 2 * (size_t)n + 4 * (size_t)n) * sizeof(float2);
 }
 
-void launch_svt(const SvtLaunch& L, hipStream_t s) {
+void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm) {
+  StageTimer dummy;
+  StageTimer& T = tm ? *tm : dummy;
   const int ns = L.n_slices, n = L.max_n1, m = L.max_m1;
   if (ns == 0) return;
-  const int T = (n + 31) / 32;
-  hipLaunchKernelGGL(k_gram, dim3(T * (T + 1) / 2, ns), dim3(256), 0, s, L.desc, L.slices, L.gram);
+  const int TT = (n + 31) / 32;
+  T.begin(ST_GRAM);
+  hipLaunchKernelGGL(k_gram, dim3(TT * (TT + 1) / 2, ns), dim3(256), 0, s, L.desc, L.slices, L.gram);
+  T.end(ST_GRAM);
   static int lds_max = -1;
   if (lds_max < 0) {
     int dev = 0;
@@ -674,27 +678,39 @@ void launch_svt(const SvtLaunch& L, hipStream_t s) {
       (void)hipGetLastError();  // clear the sticky error: the global-memory variant is used instead
     }
   }
+  T.begin(ST_TRIDIAG);
   if (use_onchip) {
     hipLaunchKernelGGL(k_tridiag<true>, dim3(ns), dim3(256), onchip, s, L.desc, L.gram, L.tri);
   } else {
     hipLaunchKernelGGL(k_tridiag<false>, dim3(ns), dim3(256), (size_t)(2 + 4) * n * sizeof(float2), s, L.desc,
                        L.gram, L.tri);
   }
+  T.end(ST_TRIDIAG);
   const size_t eig_lds = (size_t)4 * n * sizeof(double) + (size_t)(n + 1) * sizeof(int);
+  T.begin(ST_TRIEIG);
   hipLaunchKernelGGL(k_trieig, dim3(ns), dim3(256), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount, L.mu, L.alpha,
                      L.thresh);
+  T.end(ST_TRIEIG);
   int cb = 64;
   while (cb > 4 && ((size_t)n * cb + n + 256) * sizeof(float2) > 60 * 1024) cb >>= 1;
   const size_t bt_lds = ((size_t)n * cb + n + 256) * sizeof(float2);
+  T.begin(ST_BACKTRANS);
   hipLaunchKernelGGL(k_backtrans, dim3((n + cb - 1) / cb, ns), dim3(256), bt_lds, s, L.desc, L.gram, L.tri, L.V,
                      L.rcount, cb);
+  T.end(ST_BACKTRANS);
   // B: tall h x r, wide r x w -> tiles over (max(n, m)) both ways
+  T.begin(ST_BP1);
   hipLaunchKernelGGL(k_bp1, dim3((m + 31) / 32, (m + 31) / 32, ns), dim3(256), 0, s, L.desc, L.slices, L.V, L.B,
                      L.rcount);
+  T.end(ST_BP1);
+  T.begin(ST_COLNORM);
   hipLaunchKernelGGL(k_colnorm, dim3(n, ns), dim3(256), 0, s, L.desc, L.B, L.fval, L.rcount, L.mu, L.alpha,
                      L.thresh);
+  T.end(ST_COLNORM);
+  T.begin(ST_BP2);
   hipLaunchKernelGGL(k_bp2, dim3((m + 31) / 32, (m + 31) / 32, ns), dim3(256), 0, s, L.desc, L.slices, L.V, L.B,
                      L.fval, L.rcount);
+  T.end(ST_BP2);
 }
 
 }  // namespace lrstv

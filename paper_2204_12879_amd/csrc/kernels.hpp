@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "timer.hpp"
+
 namespace lrstv {
 
 struct Weights {
@@ -68,6 +70,6 @@ struct SvtLaunch {
   float thresh;            // fixed threshold when mu == NULL
   int precision;
 };
-void launch_svt(const SvtLaunch& L, hipStream_t s);
+void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm = nullptr);
 
 }  // namespace lrstv
