@@ -259,9 +259,250 @@ __global__ void __launch_bounds__(256) k_tridiag(const SliceDesc* __restrict__ d
   }
 }
 
+// Householder reduction with the packed Gram held on-chip, for n1 <= 256.
+// 512 threads (8 waves).  Rows [RL, n) of the packed lower triangle live in
+// VGPRs: row r = RL + wave + 8 j (j < JR), lane l holds columns l + 64 u
+// (u < 4); rows [0, RL) live in LDS.  RL = max(0, n - 8 JR).  Column
+// partials of the symmetric product are accumulated by absolute column.
+template <int JR>
+__global__ void __launch_bounds__(512) k_tridiag_reg(const SliceDesc* __restrict__ desc, float2* __restrict__ gram,
+                                                     double* __restrict__ tri) {
+  constexpr int NW = 8;
+  extern __shared__ float2 sm[];
+  __shared__ double red[NW];
+  __shared__ double s_tau, s_dii;
+  __shared__ float2 s_scale;
+  const SliceDesc d = desc[blockIdx.x];
+  const int n = d.n1;
+  const int RL = n > NW * JR ? n - NW * JR : 0;
+  const int64_t npl = (int64_t)RL * (RL + 1) / 2;
+  float2* gA = gram + d.g_off;
+  float2* A = sm;                    // rows [0, RL), packed
+  float2* v = sm + npl;              // [n]
+  float2* p = v + n;                 // [n]
+  float2* colacc = p + n;            // [NW][n]
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double* dg = tri + d.t_off;
+  double* eab = dg + n;
+  double* phr = eab + n;
+  double* phi = phr + n;
+  double* taus = phi + n;
+  float2 reg[JR][4];
+#pragma unroll
+  for (int j = 0; j < JR; ++j) {
+    const int r = RL + wv + NW * j;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = lane + 64 * u;
+      reg[j][u] = (r < n && c <= r) ? gA[packed(r, c)] : make_float2(0.f, 0.f);
+    }
+  }
+  for (int64_t e = threadIdx.x; e < npl; e += blockDim.x) A[e] = gA[e];
+  __syncthreads();
+  double ph_r = 1.0, ph_i = 0.0;
+  if (threadIdx.x == 0) { phr[0] = 1.0; phi[0] = 0.0; }
+  for (int i = 0; i < n - 1; ++i) {
+    const int m = n - 1 - i;
+    const int ui = i >> 6, li = i & 63;
+    // (a) column i below the diagonal -> v; diagonal A(i, i) -> s_dii
+    for (int r = i + 1 + threadIdx.x; r < RL; r += blockDim.x) v[r - i - 1] = A[packed(r, i)];
+    if (i < RL && threadIdx.x == 0) s_dii = (double)A[packed(i, i)].x;
+    if (lane == li) {
+#pragma unroll
+      for (int j = 0; j < JR; ++j) {
+        const int r = RL + wv + NW * j;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (u == ui) {
+            if (r > i && r < n) v[r - i - 1] = reg[j][u];
+            if (r == i) s_dii = (double)reg[j][u].x;
+          }
+      }
+    }
+    __syncthreads();
+    double nx2 = 0.0;
+    for (int r = threadIdx.x; r < m; r += blockDim.x) {
+      const float2 x = v[r];
+      nx2 += (double)x.x * x.x + (double)x.y * x.y;
+    }
+    nx2 = block_sum(nx2, red);
+    // (b) reflector: H x = beta e_1, v normalised to v_0 = 1, tau in [1, 2]
+    if (threadIdx.x == 0) {
+      dg[i] = s_dii;
+      const float2 x0 = v[0];
+      const double ax02 = (double)x0.x * x0.x + (double)x0.y * x0.y;
+      double tau = 0.0;
+      float2 beta = x0;
+      float2 scl = make_float2(0.f, 0.f);
+      if (nx2 - ax02 > 1e-14 * nx2 && nx2 > 0.0) {
+        const double nx = sqrt(nx2), ax0 = sqrt(ax02);
+        const double pr = ax0 > 0.0 ? x0.x / ax0 : 1.0, pi = ax0 > 0.0 ? x0.y / ax0 : 0.0;
+        beta = make_float2((float)(-pr * nx), (float)(-pi * nx));
+        const double inv = 1.0 / (ax0 + nx);
+        scl = make_float2((float)(pr * inv), (float)(-pi * inv));
+        v[0] = make_float2(1.f, 0.f);
+        tau = 1.0 + ax0 / nx;
+      }
+      s_scale = scl;
+      s_tau = tau;
+      taus[i] = tau;
+      const double br = beta.x, bi = beta.y, ab = sqrt(br * br + bi * bi);
+      eab[i] = ab;
+      if (ab > 0.0) {
+        const double ur = br / ab, uq = bi / ab;
+        const double nr = ph_r * ur - ph_i * uq, ni = ph_r * uq + ph_i * ur;
+        ph_r = nr;
+        ph_i = ni;
+      }
+      phr[i + 1] = ph_r;
+      phi[i + 1] = ph_i;
+    }
+    __syncthreads();
+    const float tau = (float)s_tau;
+    if (tau != 0.f) {
+      const float2 scl = s_scale;
+      for (int r = 1 + threadIdx.x; r < m; r += blockDim.x) v[r] = cmul(v[r], scl);
+      __syncthreads();
+      // (c) p = tau A22 v; row parts reduced in-wave, column parts by absolute column
+      float2 cacc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) cacc[u] = make_float2(0.f, 0.f);
+      for (int r = i + 1 + wv; r < RL; r += NW) {
+        const float2* row = A + packed(r, 0);
+        const float2 vr = v[r - i - 1];
+        float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int c = lane + 64 * u;
+          if (c > i && c <= r) {
+            const float2 a = row[c];
+            acc = cadd(acc, cmul(a, v[c - i - 1]));
+            if (c < r) cacc[u] = cadd(cacc[u], cmulc(a, vr));
+          }
+        }
+        acc.x = warp_sumf(acc.x);
+        acc.y = warp_sumf(acc.y);
+        if (lane == 0) p[r - i - 1] = acc;
+      }
+#pragma unroll
+      for (int j = 0; j < JR; ++j) {
+        const int r = RL + wv + NW * j;
+        if (r > i && r < n) {
+          const float2 vr = v[r - i - 1];
+          float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int c = lane + 64 * u;
+            if (c > i && c <= r) {
+              const float2 a = reg[j][u];
+              acc = cadd(acc, cmul(a, v[c - i - 1]));
+              if (c < r) cacc[u] = cadd(cacc[u], cmulc(a, vr));
+            }
+          }
+          acc.x = warp_sumf(acc.x);
+          acc.y = warp_sumf(acc.y);
+          if (lane == 0) p[r - i - 1] = acc;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = lane + 64 * u;
+        if (c > i && c < n) colacc[wv * n + c] = cacc[u];
+      }
+      __syncthreads();
+      double kv = 0.0;
+      for (int rr = threadIdx.x; rr < m; rr += blockDim.x) {
+        const int c = i + 1 + rr;
+        float2 sacc = p[rr];
+#pragma unroll
+        for (int q = 0; q < NW; ++q) sacc = cadd(sacc, colacc[q * n + c]);
+        sacc = cscale(sacc, tau);
+        p[rr] = sacc;
+        const float2 vr = v[rr];
+        kv += (double)vr.x * sacc.x + (double)vr.y * sacc.y;
+      }
+      kv = block_sum(kv, red);
+      const float K = (float)(0.5 * (double)tau * kv);
+      for (int rr = threadIdx.x; rr < m; rr += blockDim.x) p[rr] = csub(p[rr], cscale(v[rr], K));
+      __syncthreads();
+      // (d) A22 <- A22 - v w^H - w v^H
+      for (int r = i + 1 + wv; r < RL; r += NW) {
+        float2* row = A + packed(r, 0);
+        const float2 vr = v[r - i - 1], wr = p[r - i - 1];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int c = lane + 64 * u;
+          if (c > i && c <= r) {
+            const float2 vc = v[c - i - 1], wc = p[c - i - 1];
+            const float2 t1 = make_float2(vr.x * wc.x + vr.y * wc.y, vr.y * wc.x - vr.x * wc.y);
+            const float2 t2 = make_float2(wr.x * vc.x + wr.y * vc.y, wr.y * vc.x - wr.x * vc.y);
+            row[c] = csub(row[c], cadd(t1, t2));
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < JR; ++j) {
+        const int r = RL + wv + NW * j;
+        if (r > i && r < n) {
+          const float2 vr = v[r - i - 1], wr = p[r - i - 1];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int c = lane + 64 * u;
+            if (c > i && c <= r) {
+              const float2 vc = v[c - i - 1], wc = p[c - i - 1];
+              const float2 t1 = make_float2(vr.x * wc.x + vr.y * wc.y, vr.y * wc.x - vr.x * wc.y);
+              const float2 t2 = make_float2(wr.x * vc.x + wr.y * vc.y, wr.y * vc.x - wr.x * vc.y);
+              reg[j][u] = csub(reg[j][u], cadd(t1, t2));
+            }
+          }
+        }
+      }
+    }
+    // (e) reflector into column i below the diagonal
+    const float2 zero = make_float2(0.f, 0.f);
+    for (int r = i + 1 + threadIdx.x; r < RL; r += blockDim.x) A[packed(r, i)] = tau != 0.f ? v[r - i - 1] : zero;
+    if (lane == li) {
+#pragma unroll
+      for (int j = 0; j < JR; ++j) {
+        const int r = RL + wv + NW * j;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (u == ui && r > i && r < n) reg[j][u] = tau != 0.f ? v[r - i - 1] : zero;
+      }
+    }
+    __syncthreads();
+  }
+  // last diagonal entry
+  if (n - 1 < RL) {
+    if (threadIdx.x == 0) dg[n - 1] = (double)A[packed(n - 1, n - 1)].x;
+  } else if (lane == ((n - 1) & 63)) {
+#pragma unroll
+    for (int j = 0; j < JR; ++j) {
+      const int r = RL + wv + NW * j;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (r == n - 1 && u == ((n - 1) >> 6)) dg[n - 1] = (double)reg[j][u].x;
+    }
+  }
+  if (threadIdx.x == 0) {
+    eab[n - 1] = 0.0;
+    taus[n - 1] = 0.0;
+  }
+  for (int64_t e = threadIdx.x; e < npl; e += blockDim.x) gA[e] = A[e];
+#pragma unroll
+  for (int j = 0; j < JR; ++j) {
+    const int r = RL + wv + NW * j;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = lane + 64 * u;
+      if (r < n && c <= r) gA[packed(r, c)] = reg[j][u];
+    }
+  }
+}
+
 // ------------------------------------------------------ tridiagonal eigen ---
 // Number of eigenvalues of the real symmetric tridiagonal (d, e) below x
-// (Sturm sequence), restricted to rows [p0, p1].
+// (Sturm sequence), restricted to rows [p0, p1].  Exact division.
 LRSTV_DEV int sturm_count(const double* dg, const double* e2, int p0, int p1, double x, double pivmin) {
   int cnt = 0;
   double q = dg[p0] - x;
@@ -275,16 +516,34 @@ LRSTV_DEV int sturm_count(const double* dg, const double* e2, int p0, int p1, do
   return cnt;
 }
 
-// One block per slice.  Eigenvalues above (t^2 - delta) by bisection, their
-// eigenvectors by twisted factorisation inside their unreduced block,
-// Gram-Schmidt inside clusters, output column c = eigenvector of the c-th
-// largest kept eigenvalue, multiplied by the phase (V re/im planes).
-__global__ void __launch_bounds__(256) k_trieig(const SliceDesc* __restrict__ desc, double* __restrict__ tri,
-                                                double* __restrict__ xs, float* __restrict__ V,
-                                                int* __restrict__ rcount, const double* __restrict__ mu_dev,
-                                                double alpha, float thresh) {
+// Same count over the whole matrix with the hardware reciprocal refined by one
+// Newton step instead of the full-precision division sequence.
+LRSTV_DEV int sturm_count_fast(const double* dg, const double* e2, int n, double x, double pivmin) {
+  int cnt = 0;
+  double q = dg[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  cnt += q < 0.0;
+  for (int i = 1; i < n; ++i) {
+    double rq = __builtin_amdgcn_rcp(q);
+    rq = rq * (2.0 - q * rq);  // one Newton step: full FP64 reciprocal accuracy
+    q = (dg[i] - x) - e2[i - 1] * rq;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+// One block (1024 threads) per slice.  Eigenvalues above (t^2 - delta) of
+// T / ||T|| by 5-section (4 threads per eigenvalue), eigenvectors by twisted
+// factorisation inside their unreduced block, Gram-Schmidt inside clusters;
+// output column c = eigenvector of the c-th largest kept eigenvalue times the
+// phase (V re/im planes).
+__global__ void __launch_bounds__(1024) k_trieig(const SliceDesc* __restrict__ desc, double* __restrict__ tri,
+                                                 double* __restrict__ xs, float* __restrict__ V,
+                                                 int* __restrict__ rcount, const double* __restrict__ mu_dev,
+                                                 double alpha, float thresh) {
   extern __shared__ double smd[];
-  __shared__ double red[8];
+  __shared__ double red[16];
   __shared__ int s_c0, s_nblk;
   const SliceDesc d = desc[blockIdx.x];
   const int n = d.n1;
@@ -296,9 +555,9 @@ __global__ void __launch_bounds__(256) k_trieig(const SliceDesc* __restrict__ de
   double* ee = e2 + n;              // [n] off-diagonal with splits zeroed
   double* lam = ee + n;             // [n]
   double* ds = lam + n;             // [n] diagonal
-  int* bstart = (int*)(ds + n);     // [n+1] block starts
+  double* sdot = ds + n;            // [n] Gram-Schmidt coefficients
+  int* bstart = (int*)(sdot + n);   // [n+1] block starts
   const double t = mu_dev ? alpha / *mu_dev : (double)thresh;
-  // splitting and Gershgorin bounds
   double gl = 1e300, gu = -1e300;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     double e = (i < n - 1) ? eab[i] : 0.0;
@@ -314,7 +573,7 @@ __global__ void __launch_bounds__(256) k_trieig(const SliceDesc* __restrict__ de
   gl = -block_max(-gl, red);
   gu = block_max(gu, red);
   const double tnorm0 = fmax(fabs(gl), fabs(gu));
-  // work on T / ||T|| so that the pivot guards below stay far from overflow
+  // work on T / ||T|| so that the pivot guards stay far from overflow
   const double sc = tnorm0 > 0.0 ? 1.0 / tnorm0 : 1.0;
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -341,35 +600,61 @@ __global__ void __launch_bounds__(256) k_trieig(const SliceDesc* __restrict__ de
   }
   __syncthreads();
   const int c0 = s_c0, nblk = s_nblk, r = n - c0;
-  // bisection for eigenvalues c0 .. n-1 (ascending index)
-  for (int k = c0 + threadIdx.x; k < n; k += blockDim.x) {
-    double lo = fmax(gl, lo_cut), hi = gu;
-    for (int it = 0; it < 200; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (hi - lo <= 2.2e-16 * fmax(fabs(lo), fabs(hi)) + pivmin || mid <= lo || mid >= hi) break;
-      if (sturm_count(dg, e2, 0, n - 1, mid, pivmin) <= k) lo = mid; else hi = mid;
+  // 5-section: the 4 threads of a group probe 4 interior points of [lo, hi]
+  {
+    const int lane = threadIdx.x & 63, q = lane & 3, base = lane & ~3;
+    const int ngrp = blockDim.x >> 2;
+    const int nround = (r + ngrp - 1) / ngrp;
+    for (int rd = 0; rd < nround; ++rd) {
+      const int kk = (threadIdx.x >> 2) + rd * ngrp;
+      const bool act = kk < r;
+      const int k = c0 + kk;
+      double lo = fmax(gl, lo_cut), hi = gu;
+      for (int it = 0; it < 64; ++it) {
+        const double wdt = hi - lo;
+        const bool done = !act || wdt <= fmax(2.2e-16 * fmax(fabs(lo), fabs(hi)), 4e-16);
+        if (__all(done)) break;
+        const double step = wdt * 0.2;
+        const double x = lo + (q + 1) * step;
+        const int cnt = done ? 0 : sturm_count_fast(dg, e2, n, x, pivmin);
+        const int c_0 = __shfl(cnt, base + 0, 64), c_1 = __shfl(cnt, base + 1, 64);
+        const int c_2 = __shfl(cnt, base + 2, 64), c_3 = __shfl(cnt, base + 3, 64);
+        if (!done) {
+          // eigenvalue k lies where the count first exceeds k
+          const double x0 = lo + step, x1 = lo + 2 * step, x2 = lo + 3 * step, x3 = lo + 4 * step;
+          if (c_0 > k) { hi = x0; }
+          else if (c_1 > k) { lo = x0; hi = x1; }
+          else if (c_2 > k) { lo = x1; hi = x2; }
+          else if (c_3 > k) { lo = x2; hi = x3; }
+          else { lo = x3; }
+        }
+      }
+      if (act && q == 0) lam[k] = 0.5 * (lo + hi);
     }
-    lam[k] = 0.5 * (lo + hi);
   }
   __syncthreads();
-  // eigenvectors
+  // eigenvectors: twisted factorisation, one eigenvalue per thread
   const int64_t nn = (int64_t)n * n;
   double* X = xs + d.x_off;    // [3][n][n] : Um, Dm(-> x), Lp ; column index k - c0
   const double tol_eq = 1e-13 * tnorm + pivmin;
   for (int k = c0 + threadIdx.x; k < n; k += blockDim.x) {
     const int col = k - c0;
     const double lk = lam[k];
-    // locate the block that holds this copy of lk
-    int lt = 0, pick = 0;
-    for (int b = 0; b < nblk; ++b) lt += sturm_count(dg, e2, bstart[b], bstart[b + 1] - 1, lk - tol_eq, pivmin);
-    int m = k - lt;  // which copy among eigenvalues equal to lk
-    for (int b = 0; b < nblk; ++b) {
-      const int p0 = bstart[b], p1 = bstart[b + 1] - 1;
-      const int eq = sturm_count(dg, e2, p0, p1, lk + tol_eq, pivmin) - sturm_count(dg, e2, p0, p1, lk - tol_eq, pivmin);
-      if (eq > 0) {
-        pick = b;
-        if (m < eq) break;
-        m -= eq;
+    int pick = 0;
+    if (nblk > 1) {
+      // locate the unreduced block that holds this copy of lk
+      int lt = 0;
+      for (int b = 0; b < nblk; ++b) lt += sturm_count(dg, e2, bstart[b], bstart[b + 1] - 1, lk - tol_eq, pivmin);
+      int m = k - lt;
+      for (int b = 0; b < nblk; ++b) {
+        const int p0 = bstart[b], p1 = bstart[b + 1] - 1;
+        const int eq =
+            sturm_count(dg, e2, p0, p1, lk + tol_eq, pivmin) - sturm_count(dg, e2, p0, p1, lk - tol_eq, pivmin);
+        if (eq > 0) {
+          pick = b;
+          if (m < eq) break;
+          m -= eq;
+        }
       }
     }
     const int p0 = bstart[pick], p1 = bstart[pick + 1] - 1;
@@ -387,54 +672,89 @@ __global__ void __launch_bounds__(256) k_trieig(const SliceDesc* __restrict__ de
       if (fabs(dm) < pivmin) dm = pivmin;
       Dm[(int64_t)i * n] = dm;
     }
-    // top-down L D L^T and twist index
+    // top-down L D L^T and twist index; the stored Dm is read 8 ahead
     double dp = dg[p0] - lk;
     if (fabs(dp) < pivmin) dp = pivmin;
     double best = fabs(Dm[(int64_t)p0 * n]);
     int rt = p0;
-    for (int i = p0; i < p1; ++i) {
-      const double l = ee[i] / dp;
-      Lp[(int64_t)i * n] = l;
-      dp = dg[i + 1] - lk - l * ee[i];
-      if (fabs(dp) < pivmin) dp = pivmin;
-      const double g = dp + Dm[(int64_t)(i + 1) * n] - (dg[i + 1] - lk);
-      if (fabs(g) < best) { best = fabs(g); rt = i + 1; }
+    for (int i0 = p0; i0 < p1; i0 += 8) {
+      double dmv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) dmv[q] = (i0 + q < p1) ? Dm[(int64_t)(i0 + q + 1) * n] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int i = i0 + q;
+        if (i < p1) {
+          const double l = ee[i] / dp;
+          Lp[(int64_t)i * n] = l;
+          dp = dg[i + 1] - lk - l * ee[i];
+          if (fabs(dp) < pivmin) dp = pivmin;
+          const double g = dp + dmv[q] - (dg[i + 1] - lk);
+          if (fabs(g) < best) { best = fabs(g); rt = i + 1; }
+        }
+      }
     }
     // solve with the twist: x_rt = 1
     double* x = Dm;
     for (int i = 0; i < n; ++i)
       if (i < p0 || i > p1) x[(int64_t)i * n] = 0.0;
-    x[(int64_t)rt * n] = 1.0;
     double xv = 1.0, nrm = 1.0;
-    for (int i = rt - 1; i >= p0; --i) {
-      xv = -Lp[(int64_t)i * n] * xv;
-      x[(int64_t)i * n] = xv;
-      nrm += xv * xv;
+    for (int i0 = rt - 1; i0 >= p0; i0 -= 8) {
+      double lv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) lv[q] = (i0 - q >= p0) ? Lp[(int64_t)(i0 - q) * n] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int i = i0 - q;
+        if (i >= p0) {
+          xv = -lv[q] * xv;
+          x[(int64_t)i * n] = xv;
+          nrm += xv * xv;
+        }
+      }
     }
+    x[(int64_t)rt * n] = 1.0;
     xv = 1.0;
-    for (int i = rt; i < p1; ++i) {
-      xv = -Um[(int64_t)i * n] * xv;
-      x[(int64_t)(i + 1) * n] = xv;
-      nrm += xv * xv;
+    for (int i0 = rt; i0 < p1; i0 += 8) {
+      double uv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) uv[q] = (i0 + q < p1) ? Um[(int64_t)(i0 + q) * n] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int i = i0 + q;
+        if (i < p1) {
+          xv = -uv[q] * xv;
+          x[(int64_t)(i + 1) * n] = xv;
+          nrm += xv * xv;
+        }
+      }
     }
     const double inv = 1.0 / sqrt(nrm);
     for (int i = p0; i <= p1; ++i) x[(int64_t)i * n] *= inv;
   }
   __syncthreads();
-  // Gram-Schmidt inside clusters of nearly equal eigenvalues
+  // Re-orthogonalise inside clusters (gaps below 1e-10 ||T||; larger gaps give
+  // FP64 twisted-factorisation vectors accurate to eps_64 / gap): classical
+  // Gram-Schmidt applied twice per vector against the earlier cluster members.
   double* Xv = X + nn;
-  const double gtol = 1e-8 * tnorm;
+  const double gtol = 1e-10 * tnorm;
   for (int k = c0 + 1; k < n; ++k) {
     int k0 = k;
     while (k0 > c0 && lam[k0] - lam[k0 - 1] <= gtol) --k0;
     if (k0 == k) continue;
-    const int ck = k - c0;
-    for (int kp = k0; kp < k; ++kp) {
-      const int cp = kp - c0;
-      double dot = 0.0;
-      for (int i = threadIdx.x; i < n; i += blockDim.x) dot += Xv[(int64_t)i * n + ck] * Xv[(int64_t)i * n + cp];
-      dot = block_sum(dot, red);
-      for (int i = threadIdx.x; i < n; i += blockDim.x) Xv[(int64_t)i * n + ck] -= dot * Xv[(int64_t)i * n + cp];
+    const int ck = k - c0, cb = k0 - c0, nc = k - k0;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int j = threadIdx.x; j < nc; j += blockDim.x) {
+        double dt = 0.0;
+        for (int i = 0; i < n; ++i) dt += Xv[(int64_t)i * n + cb + j] * Xv[(int64_t)i * n + ck];
+        sdot[j] = dt;
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double acc = 0.0;
+        for (int j = 0; j < nc; ++j) acc += sdot[j] * Xv[(int64_t)i * n + cb + j];
+        Xv[(int64_t)i * n + ck] -= acc;
+      }
       __syncthreads();
     }
     double nr = 0.0;
@@ -666,29 +986,31 @@ void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm) {
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
       lds_max = (int)prop.sharedMemPerBlock;
   }
-  const size_t onchip = tridiag_onchip_bytes(n);
-  static size_t onchip_granted = 65536;
-  bool use_onchip = onchip <= onchip_granted;
-  if (!use_onchip && (int)onchip + 1024 <= lds_max) {
-    if (hipFuncSetAttribute((const void*)k_tridiag<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)onchip) ==
-        hipSuccess) {
-      onchip_granted = onchip;
-      use_onchip = true;
+  T.begin(ST_TRIDIAG);
+  constexpr int JR = 10;
+  const int RL = n > 8 * JR ? n - 8 * JR : 0;
+  const size_t reg_lds = ((size_t)RL * (RL + 1) / 2 + (size_t)(2 + 8) * n) * sizeof(float2);
+  static size_t reg_granted = 65536;
+  bool use_reg = n <= 256 && reg_lds <= reg_granted;
+  if (n <= 256 && !use_reg && (int)reg_lds + 2048 <= lds_max) {
+    if (hipFuncSetAttribute((const void*)k_tridiag_reg<JR>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)reg_lds) == hipSuccess) {
+      reg_granted = reg_lds;
+      use_reg = true;
     } else {
       (void)hipGetLastError();  // clear the sticky error: the global-memory variant is used instead
     }
   }
-  T.begin(ST_TRIDIAG);
-  if (use_onchip) {
-    hipLaunchKernelGGL(k_tridiag<true>, dim3(ns), dim3(256), onchip, s, L.desc, L.gram, L.tri);
+  if (use_reg) {
+    hipLaunchKernelGGL(k_tridiag_reg<JR>, dim3(ns), dim3(512), reg_lds, s, L.desc, L.gram, L.tri);
   } else {
     hipLaunchKernelGGL(k_tridiag<false>, dim3(ns), dim3(256), (size_t)(2 + 4) * n * sizeof(float2), s, L.desc,
                        L.gram, L.tri);
   }
   T.end(ST_TRIDIAG);
-  const size_t eig_lds = (size_t)4 * n * sizeof(double) + (size_t)(n + 1) * sizeof(int);
+  const size_t eig_lds = (size_t)5 * n * sizeof(double) + (size_t)(n + 1) * sizeof(int);
   T.begin(ST_TRIEIG);
-  hipLaunchKernelGGL(k_trieig, dim3(ns), dim3(256), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount, L.mu, L.alpha,
+  hipLaunchKernelGGL(k_trieig, dim3(ns), dim3(1024), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount, L.mu, L.alpha,
                      L.thresh);
   T.end(ST_TRIEIG);
   int cb = 64;

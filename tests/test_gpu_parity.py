@@ -1,15 +1,22 @@
 """GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
 
 Inputs are seeded; both sides see the same float32 values (the oracle gets
-them widened to float64).  Tolerances: relative Frobenius error <= 1e-4 for
-FP32 results (the bar the full ADMM output must meet), tighter for the
-single linear steps.
+them widened to float64).  Tolerances (relative Frobenius):
+  * 1e-4 for the ADMM output X after a full run (the spec bar);
+  * 2e-6 for the Z-solve (a linear FP32 solve: a few ulps);
+  * SVT_TOL = 5e-5 for t-SVT outputs and quantities derived from them in one
+    iteration: the slice SVT works on the FP32 Gram M^H M whose rounding error
+    is about n eps_32 ||M||^2 (n = 256: 1.5e-5); the tolerance keeps a 3x
+    margin and stays at half of the 1e-4 bar;
+  * 1e-5 for the other state variables of one iteration.
 """
 import numpy as np
 import pytest
 
 import oracle
 import synth
+
+SVT_TOL = 5e-5
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -67,7 +74,7 @@ def _slice_sv(A):
 
 
 @pytest.mark.parametrize("shape", [(16, 32, 32), (9, 17, 12), (8, 12, 17), (1, 20, 20), (6, 33, 40),
-                                   (31, 48, 64), (4, 150, 160)])
+                                   (31, 48, 64), (4, 150, 160), (3, 200, 210), (3, 256, 256), (2, 81, 79)])
 def test_svt_matches_oracle(shape):
     L = _lib()
     A = _lowrank_tensor(shape, rank=4, seed=shape[1] * 7 + shape[2])
@@ -79,7 +86,7 @@ def test_svt_matches_oracle(shape):
         torch.cuda.synchronize()
         ref = oracle.tsvt(A.astype(np.float64), t)
         err = rel(E.cpu().numpy(), ref)
-        assert err < 1e-5, (q, err)
+        assert err < SVT_TOL, (q, err)
     big = float(sv.max()) * 1.01
     E = L.svt(torch.from_numpy(A).cuda(), big)
     torch.cuda.synchronize()
@@ -107,7 +114,7 @@ def test_svt_degenerate_spectrum():
     for t in (0.0, 0.5, 1.5):
         E = L.svt(torch.from_numpy(A).cuda(), t).cpu().numpy()
         ref = oracle.tsvt(A.astype(np.float64), t)
-        assert rel(E, ref) < 1e-5, t
+        assert rel(E, ref) < SVT_TOL, t
 
 
 # ----------------------------------------------------- one ADMM iteration ---
@@ -125,7 +132,7 @@ def _state_to_gpu(st):
     return out
 
 
-@pytest.mark.parametrize("shape", [(16, 32, 32), (10, 20, 24), (7, 18, 13)])
+@pytest.mark.parametrize("shape", [(16, 32, 32), (10, 20, 24), (7, 18, 13), (191, 256, 256)])
 def test_one_iteration_matches_oracle(shape):
     L = _lib()
     say("one iteration", shape)
@@ -154,7 +161,7 @@ def test_one_iteration_matches_oracle(shape):
               "G3": new.G3, "G4": new.G4}
     for k, ref in checks.items():
         err = rel(got[k].reshape(ref.shape), ref)
-        assert err < 1e-5, (k, err)
+        assert err < (SVT_TOL if k in ("E", "G4") else 1e-5), (k, err)
     assert abs(got["mu"][0] - new.mu) <= 1e-12 * new.mu
     r = res.cpu().numpy()
     for i, key in enumerate(oracle.RESIDUAL_KEYS):
