@@ -61,6 +61,10 @@ LRSTV_DEV void ctile(int m0, int n0, int K, FA fa, FB fb, float2& c00, float2& c
 
 LRSTV_DEV int64_t packed(int r, int c) { return (int64_t)r * (r + 1) / 2 + c; }
 
+// Deflation threshold of the Householder reduction: a column with
+// ||x||^2 <= kDeflate2 (G scaled to ||G||_F ~ 1) is treated as zero.
+#define kDeflate2 1e-14
+
 // ------------------------------------------------------------------ Gram ---
 __global__ void __launch_bounds__(256) k_gram(const SliceDesc* __restrict__ desc, const float* __restrict__ sl,
                                               float2* __restrict__ gram) {
@@ -141,6 +145,18 @@ __global__ void __launch_bounds__(256) k_tridiag(const SliceDesc* __restrict__ d
     for (int64_t e = threadIdx.x; e < np; e += blockDim.x) A[e] = gA[e];
     __syncthreads();
   }
+  // exact power-of-two scaling to ||G||_F ~ 1 (see k_tridiag_reg) and deflation
+  double fro = 0.0;
+  for (int64_t e = threadIdx.x; e < np; e += blockDim.x) {
+    const float2 g = A[e];
+    fro += ((double)g.x * g.x + (double)g.y * g.y) * 2.0;
+  }
+  fro = block_sum(fro, red);
+  const int ex = fro > 0.0 ? ilogb(sqrt(fro)) : 0;
+  const float gsc = ldexpf(1.0f, -ex);
+  const double unsc = ldexp(1.0, ex);
+  for (int64_t e = threadIdx.x; e < np; e += blockDim.x) A[e] = cscale(A[e], gsc);
+  __syncthreads();
   double ph_r = 1.0, ph_i = 0.0;  // running phase (thread 0)
   if (threadIdx.x == 0) { phr[0] = 1.0; phi[0] = 0.0; }
   for (int i = 0; i < n - 1; ++i) {
@@ -153,13 +169,14 @@ __global__ void __launch_bounds__(256) k_tridiag(const SliceDesc* __restrict__ d
     }
     nx2 = block_sum(nx2, red);
     if (threadIdx.x == 0) {
-      dg[i] = (double)A[packed(i, i)].x;
-      const float2 x0 = v[0];
+      dg[i] = (double)A[packed(i, i)].x * unsc;
+      float2 x0 = v[0];
       const double ax02 = (double)x0.x * x0.x + (double)x0.y * x0.y;
       double tau = 0.0;
+      if (nx2 <= kDeflate2) x0 = make_float2(0.f, 0.f);
       float2 beta = x0;
       float2 scl = make_float2(0.f, 0.f);
-      if (nx2 - ax02 > 1e-14 * nx2 && nx2 > 0.0) {
+      if (nx2 > kDeflate2 && nx2 - ax02 > 1e-14 * nx2) {
         // v = x - beta e_1 with v_0 = phase (|x_0| + ||x||); normalised to v_0 = 1,
         // which keeps tau = 1 + |x_0| / ||x|| in [1, 2] whatever the column scale.
         const double nx = sqrt(nx2), ax0 = sqrt(ax02);
@@ -175,7 +192,7 @@ __global__ void __launch_bounds__(256) k_tridiag(const SliceDesc* __restrict__ d
       s_beta = beta;
       taus[i] = tau;
       const double br = beta.x, bi = beta.y, ab = sqrt(br * br + bi * bi);
-      eab[i] = ab;
+      eab[i] = ab * unsc;
       if (ab > 0.0) {  // ph_{i+1} = ph_i beta / |beta|
         const double ur = br / ab, ui = bi / ab;
         const double nr = ph_r * ur - ph_i * ui, ni = ph_r * ui + ph_i * ur;
@@ -249,7 +266,7 @@ __global__ void __launch_bounds__(256) k_tridiag(const SliceDesc* __restrict__ d
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    dg[n - 1] = (double)A[packed(n - 1, n - 1)].x;
+    dg[n - 1] = (double)A[packed(n - 1, n - 1)].x * unsc;
     eab[n - 1] = 0.0;
     taus[n - 1] = 0.0;
   }
@@ -262,25 +279,31 @@ __global__ void __launch_bounds__(256) k_tridiag(const SliceDesc* __restrict__ d
 // Householder reduction with the packed Gram held on-chip, for n1 <= 256.
 // 512 threads (8 waves).  Rows [RL, n) of the packed lower triangle live in
 // VGPRs: row r = RL + wave + 8 j (j < JR), lane l holds columns l + 64 u
-// (u < 4); rows [0, RL) live in LDS.  RL = max(0, n - 8 JR).  Column
-// partials of the symmetric product are accumulated by absolute column.
+// (u < 4); rows [0, RL) live in LDS.  RL = max(0, n - 8 JR).
+// Three barriers per step: (1) after the symmetric product, whose pass also
+// accumulates v^H A v, (2) after p and w = p - K v are formed, (3) after the
+// rank-2 update, whose pass also extracts the next column, its norm and the
+// next diagonal.  Every thread forms the reflector itself from the reduced
+// norm; v = [1; scl * x] is applied on the fly from the unscaled column x.
 template <int JR>
 __global__ void __launch_bounds__(512) k_tridiag_reg(const SliceDesc* __restrict__ desc, float2* __restrict__ gram,
                                                      double* __restrict__ tri) {
   constexpr int NW = 8;
   extern __shared__ float2 sm[];
-  __shared__ double red[NW];
-  __shared__ double s_tau, s_dii;
-  __shared__ float2 s_scale;
+  // red_nx and s_dii are written for step i+1 while step i may still read them
+  // (the no-reflection path has no barrier in between): double-buffered by parity.
+  __shared__ double red_nx[2][NW], red_vav[NW];
+  __shared__ double s_dii[2];
   const SliceDesc d = desc[blockIdx.x];
   const int n = d.n1;
   const int RL = n > NW * JR ? n - NW * JR : 0;
   const int64_t npl = (int64_t)RL * (RL + 1) / 2;
   float2* gA = gram + d.g_off;
   float2* A = sm;                    // rows [0, RL), packed
-  float2* v = sm + npl;              // [n]
-  float2* p = v + n;                 // [n]
-  float2* colacc = p + n;            // [NW][n]
+  float2* xb0 = sm + npl;            // [n] column below the diagonal (double-buffered)
+  float2* xb1 = xb0 + n;             // [n]
+  float2* wb = xb1 + n;              // [n] row parts of A v, then w
+  float2* colacc = wb + n;           // [NW][n]
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double* dg = tri + d.t_off;
   double* eab = dg + n;
@@ -298,56 +321,96 @@ __global__ void __launch_bounds__(512) k_tridiag_reg(const SliceDesc* __restrict
     }
   }
   for (int64_t e = threadIdx.x; e < npl; e += blockDim.x) A[e] = gA[e];
+  // Scale by an exact power of two so that ||G||_F ~ 1: no FP32 denormals or
+  // overflow in the reflectors whatever the slice's magnitude.  Columns whose
+  // norm falls below kDeflate (relative to ||G||_F, under the FP32 Gram's own
+  // resolution) are rounding residue and are deflated (beta = 0, a split).
+  double fro = 0.0;
+  for (int64_t e = threadIdx.x; e < npl; e += blockDim.x) {
+    const float2 g = A[e];
+    fro += ((double)g.x * g.x + (double)g.y * g.y) * 2.0;
+  }
+#pragma unroll
+  for (int j = 0; j < JR; ++j)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float2 g = reg[j][u];
+      fro += ((double)g.x * g.x + (double)g.y * g.y) * 2.0;
+    }
+  fro = warp_sum(fro);
+  if (lane == 0) red_vav[wv] = fro;
+  __syncthreads();
+  double fro2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < NW; ++q) fro2 += red_vav[q];
+  const int ex = fro2 > 0.0 ? ilogb(sqrt(fro2)) : 0;
+  const float gsc = ldexpf(1.0f, -ex);
+  const double unsc = ldexp(1.0, ex);
+  for (int64_t e = threadIdx.x; e < npl; e += blockDim.x) A[e] = cscale(A[e], gsc);
+#pragma unroll
+  for (int j = 0; j < JR; ++j)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) reg[j][u] = cscale(reg[j][u], gsc);
+  __syncthreads();
+  // column 0, its norm and the diagonal A(0, 0)
+  {
+    double part = 0.0;
+    for (int r = 1 + threadIdx.x; r < n; r += blockDim.x) {
+      float2 x;
+      if (r < RL) x = A[packed(r, 0)];
+      else x = make_float2(0.f, 0.f);
+      if (r < RL) {
+        xb0[r - 1] = x;
+        part += (double)x.x * x.x + (double)x.y * x.y;
+      }
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < JR; ++j) {
+        const int r = RL + wv + NW * j;
+        if (r >= 1 && r < n) {
+          const float2 x = reg[j][0];
+          xb0[r - 1] = x;
+          part += (double)x.x * x.x + (double)x.y * x.y;
+        }
+        if (r == 0) s_dii[0] = (double)reg[j][0].x;
+      }
+    }
+    if (threadIdx.x == 0 && RL > 0) s_dii[0] = (double)A[0].x;
+    part = warp_sum(part);
+    if (lane == 0) red_nx[0][wv] = part;
+  }
   __syncthreads();
   double ph_r = 1.0, ph_i = 0.0;
   if (threadIdx.x == 0) { phr[0] = 1.0; phi[0] = 0.0; }
   for (int i = 0; i < n - 1; ++i) {
     const int m = n - 1 - i;
-    const int ui = i >> 6, li = i & 63;
-    // (a) column i below the diagonal -> v; diagonal A(i, i) -> s_dii
-    for (int r = i + 1 + threadIdx.x; r < RL; r += blockDim.x) v[r - i - 1] = A[packed(r, i)];
-    if (i < RL && threadIdx.x == 0) s_dii = (double)A[packed(i, i)].x;
-    if (lane == li) {
-#pragma unroll
-      for (int j = 0; j < JR; ++j) {
-        const int r = RL + wv + NW * j;
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (u == ui) {
-            if (r > i && r < n) v[r - i - 1] = reg[j][u];
-            if (r == i) s_dii = (double)reg[j][u].x;
-          }
-      }
-    }
-    __syncthreads();
+    float2* x = (i & 1) ? xb1 : xb0;
+    float2* xn = (i & 1) ? xb0 : xb1;
+    const int cur = i & 1, nxt = cur ^ 1;
     double nx2 = 0.0;
-    for (int r = threadIdx.x; r < m; r += blockDim.x) {
-      const float2 x = v[r];
-      nx2 += (double)x.x * x.x + (double)x.y * x.y;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) nx2 += red_nx[cur][q];
+    const double dii = s_dii[cur];
+    // reflector: H x = beta e_1, v = [1; scl x_{1:}], tau in [1, 2]
+    float2 x0 = x[0];
+    const double ax02 = (double)x0.x * x0.x + (double)x0.y * x0.y;
+    double taud = 0.0;
+    if (nx2 <= kDeflate2) x0 = make_float2(0.f, 0.f);
+    float2 beta = x0, scl = make_float2(0.f, 0.f);
+    if (nx2 > kDeflate2 && nx2 - ax02 > 1e-14 * nx2) {
+      const double nx = sqrt(nx2), ax0 = sqrt(ax02);
+      const double pr = ax0 > 0.0 ? x0.x / ax0 : 1.0, pi = ax0 > 0.0 ? x0.y / ax0 : 0.0;
+      beta = make_float2((float)(-pr * nx), (float)(-pi * nx));
+      const double inv = 1.0 / (ax0 + nx);
+      scl = make_float2((float)(pr * inv), (float)(-pi * inv));
+      taud = 1.0 + ax0 / nx;
     }
-    nx2 = block_sum(nx2, red);
-    // (b) reflector: H x = beta e_1, v normalised to v_0 = 1, tau in [1, 2]
     if (threadIdx.x == 0) {
-      dg[i] = s_dii;
-      const float2 x0 = v[0];
-      const double ax02 = (double)x0.x * x0.x + (double)x0.y * x0.y;
-      double tau = 0.0;
-      float2 beta = x0;
-      float2 scl = make_float2(0.f, 0.f);
-      if (nx2 - ax02 > 1e-14 * nx2 && nx2 > 0.0) {
-        const double nx = sqrt(nx2), ax0 = sqrt(ax02);
-        const double pr = ax0 > 0.0 ? x0.x / ax0 : 1.0, pi = ax0 > 0.0 ? x0.y / ax0 : 0.0;
-        beta = make_float2((float)(-pr * nx), (float)(-pi * nx));
-        const double inv = 1.0 / (ax0 + nx);
-        scl = make_float2((float)(pr * inv), (float)(-pi * inv));
-        v[0] = make_float2(1.f, 0.f);
-        tau = 1.0 + ax0 / nx;
-      }
-      s_scale = scl;
-      s_tau = tau;
-      taus[i] = tau;
+      dg[i] = dii * unsc;
+      taus[i] = taud;
       const double br = beta.x, bi = beta.y, ab = sqrt(br * br + bi * bi);
-      eab[i] = ab;
+      eab[i] = ab * unsc;
       if (ab > 0.0) {
         const double ur = br / ab, uq = bi / ab;
         const double nr = ph_r * ur - ph_i * uq, ni = ph_r * uq + ph_i * ur;
@@ -357,51 +420,66 @@ __global__ void __launch_bounds__(512) k_tridiag_reg(const SliceDesc* __restrict
       phr[i + 1] = ph_r;
       phi[i + 1] = ph_i;
     }
-    __syncthreads();
-    const float tau = (float)s_tau;
+    const float tau = (float)taud;
+    auto vget = [&](int k) -> float2 { return k == 0 ? make_float2(1.f, 0.f) : cmul(scl, x[k]); };
+    // per-lane copies of v at this lane's columns (absolute column c = lane + 64 u)
+    float2 vc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = lane + 64 * u;
+      vc[u] = (c > i && c < n) ? vget(c - i - 1) : make_float2(0.f, 0.f);
+    }
+    double nxp = 0.0;
+    const float2 zero = make_float2(0.f, 0.f);
     if (tau != 0.f) {
-      const float2 scl = s_scale;
-      for (int r = 1 + threadIdx.x; r < m; r += blockDim.x) v[r] = cmul(v[r], scl);
-      __syncthreads();
-      // (c) p = tau A22 v; row parts reduced in-wave, column parts by absolute column
+      // (1) row parts of A v (in-wave reduce), column parts by absolute column, v^H A v
       float2 cacc[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) cacc[u] = make_float2(0.f, 0.f);
+      for (int u = 0; u < 4; ++u) cacc[u] = zero;
+      double vav = 0.0;
       for (int r = i + 1 + wv; r < RL; r += NW) {
         const float2* row = A + packed(r, 0);
-        const float2 vr = v[r - i - 1];
-        float2 acc = make_float2(0.f, 0.f);
+        const float2 vr = vget(r - i - 1);
+        float2 acc = zero;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int c = lane + 64 * u;
           if (c > i && c <= r) {
             const float2 a = row[c];
-            acc = cadd(acc, cmul(a, v[c - i - 1]));
+            acc = cadd(acc, cmul(a, vc[u]));
             if (c < r) cacc[u] = cadd(cacc[u], cmulc(a, vr));
+            else vav -= ((double)vr.x * vr.x + (double)vr.y * vr.y) * a.x;
           }
         }
         acc.x = warp_sumf(acc.x);
         acc.y = warp_sumf(acc.y);
-        if (lane == 0) p[r - i - 1] = acc;
+        if (lane == 0) {
+          wb[r - i - 1] = acc;
+          vav += 2.0 * ((double)vr.x * acc.x + (double)vr.y * acc.y);
+        }
       }
 #pragma unroll
       for (int j = 0; j < JR; ++j) {
         const int r = RL + wv + NW * j;
         if (r > i && r < n) {
-          const float2 vr = v[r - i - 1];
-          float2 acc = make_float2(0.f, 0.f);
+          const float2 vr = vget(r - i - 1);
+          float2 acc = zero;
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int c = lane + 64 * u;
             if (c > i && c <= r) {
               const float2 a = reg[j][u];
-              acc = cadd(acc, cmul(a, v[c - i - 1]));
+              acc = cadd(acc, cmul(a, vc[u]));
               if (c < r) cacc[u] = cadd(cacc[u], cmulc(a, vr));
+              else vav -= ((double)vr.x * vr.x + (double)vr.y * vr.y) * a.x;
             }
           }
           acc.x = warp_sumf(acc.x);
           acc.y = warp_sumf(acc.y);
-          if (lane == 0) p[r - i - 1] = acc;
+          if (lane == 0) {
+            wb[r - i - 1] = acc;
+            vav += 2.0 * ((double)vr.x * acc.x + (double)vr.y * acc.y);
+          }
         }
       }
 #pragma unroll
@@ -409,34 +487,90 @@ __global__ void __launch_bounds__(512) k_tridiag_reg(const SliceDesc* __restrict
         const int c = lane + 64 * u;
         if (c > i && c < n) colacc[wv * n + c] = cacc[u];
       }
+      vav = warp_sum(vav);
+      if (lane == 0) red_vav[wv] = vav;
       __syncthreads();
-      double kv = 0.0;
+      // (2) p = tau A v, K = tau^2 v^H A v / 2, w = p - K v
+      double vAv = 0.0;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) vAv += red_vav[q];
+      const float K = (float)(0.5 * taud * taud * vAv);
       for (int rr = threadIdx.x; rr < m; rr += blockDim.x) {
         const int c = i + 1 + rr;
-        float2 sacc = p[rr];
+        float2 sacc = wb[rr];
 #pragma unroll
         for (int q = 0; q < NW; ++q) sacc = cadd(sacc, colacc[q * n + c]);
-        sacc = cscale(sacc, tau);
-        p[rr] = sacc;
-        const float2 vr = v[rr];
-        kv += (double)vr.x * sacc.x + (double)vr.y * sacc.y;
+        wb[rr] = csub(cscale(sacc, tau), cscale(vget(rr), K));
       }
-      kv = block_sum(kv, red);
-      const float K = (float)(0.5 * (double)tau * kv);
-      for (int rr = threadIdx.x; rr < m; rr += blockDim.x) p[rr] = csub(p[rr], cscale(v[rr], K));
       __syncthreads();
-      // (d) A22 <- A22 - v w^H - w v^H
+      // (3) A22 <- A22 - v w^H - w v^H; column i <- v; next column -> xn
+      float2 wc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = lane + 64 * u;
+        wc[u] = (c > i && c < n) ? wb[c - i - 1] : zero;
+      }
       for (int r = i + 1 + wv; r < RL; r += NW) {
         float2* row = A + packed(r, 0);
-        const float2 vr = v[r - i - 1], wr = p[r - i - 1];
+        const float2 vr = vget(r - i - 1), wr = wb[r - i - 1];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int c = lane + 64 * u;
           if (c > i && c <= r) {
-            const float2 vc = v[c - i - 1], wc = p[c - i - 1];
-            const float2 t1 = make_float2(vr.x * wc.x + vr.y * wc.y, vr.y * wc.x - vr.x * wc.y);
-            const float2 t2 = make_float2(wr.x * vc.x + wr.y * vc.y, wr.y * vc.x - wr.x * vc.y);
-            row[c] = csub(row[c], cadd(t1, t2));
+            const float2 t1 = make_float2(vr.x * wc[u].x + vr.y * wc[u].y, vr.y * wc[u].x - vr.x * wc[u].y);
+            const float2 t2 = make_float2(wr.x * vc[u].x + wr.y * vc[u].y, wr.y * vc[u].x - wr.x * vc[u].y);
+            const float2 a = csub(row[c], cadd(t1, t2));
+            row[c] = a;
+            if (c == i + 1) {
+              if (r > i + 1) {
+                xn[r - i - 2] = a;
+                nxp += (double)a.x * a.x + (double)a.y * a.y;
+              } else {
+                s_dii[nxt] = (double)a.x;
+              }
+            }
+          }
+        }
+        if (lane == (i & 63)) row[i] = vr;   // reflector column (c = i lives in slot i >> 6)
+      }
+#pragma unroll
+      for (int j = 0; j < JR; ++j) {
+        const int r = RL + wv + NW * j;
+        if (r > i && r < n) {
+          const float2 vr = vget(r - i - 1), wr = wb[r - i - 1];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int c = lane + 64 * u;
+            if (c > i && c <= r) {
+              const float2 t1 = make_float2(vr.x * wc[u].x + vr.y * wc[u].y, vr.y * wc[u].x - vr.x * wc[u].y);
+              const float2 t2 = make_float2(wr.x * vc[u].x + wr.y * vc[u].y, wr.y * vc[u].x - wr.x * vc[u].y);
+              const float2 a = csub(reg[j][u], cadd(t1, t2));
+              reg[j][u] = a;
+              if (c == i + 1) {
+                if (r > i + 1) {
+                  xn[r - i - 2] = a;
+                  nxp += (double)a.x * a.x + (double)a.y * a.y;
+                } else {
+                  s_dii[nxt] = (double)a.x;
+                }
+              }
+            }
+            if (c == i) reg[j][u] = vr;    // reflector column
+          }
+        }
+      }
+    } else {
+      // no reflection: column i stores zeros; extract the next column unchanged
+      for (int r = i + 1 + wv; r < RL; r += NW) {
+        float2* row = A + packed(r, 0);
+        if (lane == (i & 63)) row[i] = zero;
+        if (lane == ((i + 1) & 63)) {
+          const float2 a = row[i + 1];
+          if (r > i + 1) {
+            xn[r - i - 2] = a;
+            nxp += (double)a.x * a.x + (double)a.y * a.y;
+          } else {
+            s_dii[nxt] = (double)a.x;
           }
         }
       }
@@ -444,50 +578,33 @@ __global__ void __launch_bounds__(512) k_tridiag_reg(const SliceDesc* __restrict
       for (int j = 0; j < JR; ++j) {
         const int r = RL + wv + NW * j;
         if (r > i && r < n) {
-          const float2 vr = v[r - i - 1], wr = p[r - i - 1];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int c = lane + 64 * u;
-            if (c > i && c <= r) {
-              const float2 vc = v[c - i - 1], wc = p[c - i - 1];
-              const float2 t1 = make_float2(vr.x * wc.x + vr.y * wc.y, vr.y * wc.x - vr.x * wc.y);
-              const float2 t2 = make_float2(wr.x * vc.x + wr.y * vc.y, wr.y * vc.x - wr.x * vc.y);
-              reg[j][u] = csub(reg[j][u], cadd(t1, t2));
+            if (c == i) reg[j][u] = zero;
+            if (c == i + 1) {
+              const float2 a = reg[j][u];
+              if (r > i + 1) {
+                xn[r - i - 2] = a;
+                nxp += (double)a.x * a.x + (double)a.y * a.y;
+              } else {
+                s_dii[nxt] = (double)a.x;
+              }
             }
           }
         }
       }
     }
-    // (e) reflector into column i below the diagonal
-    const float2 zero = make_float2(0.f, 0.f);
-    for (int r = i + 1 + threadIdx.x; r < RL; r += blockDim.x) A[packed(r, i)] = tau != 0.f ? v[r - i - 1] : zero;
-    if (lane == li) {
-#pragma unroll
-      for (int j = 0; j < JR; ++j) {
-        const int r = RL + wv + NW * j;
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (u == ui && r > i && r < n) reg[j][u] = tau != 0.f ? v[r - i - 1] : zero;
-      }
-    }
+    nxp = warp_sum(nxp);
+    if (lane == 0) red_nx[nxt][wv] = nxp;
     __syncthreads();
   }
-  // last diagonal entry
-  if (n - 1 < RL) {
-    if (threadIdx.x == 0) dg[n - 1] = (double)A[packed(n - 1, n - 1)].x;
-  } else if (lane == ((n - 1) & 63)) {
-#pragma unroll
-    for (int j = 0; j < JR; ++j) {
-      const int r = RL + wv + NW * j;
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (r == n - 1 && u == ((n - 1) >> 6)) dg[n - 1] = (double)reg[j][u].x;
-    }
-  }
   if (threadIdx.x == 0) {
+    dg[n - 1] = s_dii[(n - 1) & 1] * unsc;
     eab[n - 1] = 0.0;
     taus[n - 1] = 0.0;
   }
+  // write back: only the reflectors (strict lower part) are used afterwards
   for (int64_t e = threadIdx.x; e < npl; e += blockDim.x) gA[e] = A[e];
 #pragma unroll
   for (int j = 0; j < JR; ++j) {
@@ -989,7 +1106,7 @@ void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm) {
   T.begin(ST_TRIDIAG);
   constexpr int JR = 10;
   const int RL = n > 8 * JR ? n - 8 * JR : 0;
-  const size_t reg_lds = ((size_t)RL * (RL + 1) / 2 + (size_t)(2 + 8) * n) * sizeof(float2);
+  const size_t reg_lds = ((size_t)RL * (RL + 1) / 2 + (size_t)(3 + 8) * n) * sizeof(float2);
   static size_t reg_granted = 65536;
   bool use_reg = n <= 256 && reg_lds <= reg_granted;
   if (n <= 256 && !use_reg && (int)reg_lds + 2048 <= lds_max) {

@@ -93,6 +93,50 @@ def test_svt_matches_oracle(shape):
     assert float(E.abs().max()) == 0.0
 
 
+@pytest.mark.parametrize("shape", [(31, 128, 160), (16, 256, 256), (9, 100, 60)])
+def test_svt_sparse_input(shape):
+    """About 1 % nonzero voxels: Grams with many zero rows and columns, so many
+    Householder steps have nothing to reflect (regression: a race between the
+    per-step scalars of consecutive steps in that path)."""
+    L = _lib()
+    rng = np.random.default_rng(sum(shape))
+    A = np.zeros(shape, np.float32)
+    mask = rng.uniform(size=shape) < 0.01
+    A[mask] = rng.normal(size=mask.sum()).astype(np.float32)
+    sv = _slice_sv(A)
+    for q in (0.0, 0.5, 0.9):
+        t = float(np.quantile(sv[sv > 0], q)) if q > 0 else 0.0
+        say("svt sparse", shape, "t =", t)
+        E = L.svt(torch.from_numpy(A).cuda(), t).cpu().numpy()
+        assert np.all(np.isfinite(E))
+        ref = oracle.tsvt(A.astype(np.float64), t)
+        assert rel(E, ref) < SVT_TOL, (q, rel(E, ref))
+
+
+@pytest.mark.parametrize("shape", [(31, 128, 160), (8, 96, 64), (5, 256, 256)])
+def test_svt_rank_one_sparse_slices(shape):
+    """Every Fourier slice exactly rank one with a handful of nonzero rows:
+    after the first reflection only FP32 rounding residue is left, which must
+    be deflated rather than reflected (regression: residue shrinking into
+    FP32 denormals made the reflector scale overflow)."""
+    L = _lib()
+    b, h, w = shape
+    rng = np.random.default_rng(h + w)
+    A = np.zeros(shape, np.float32)
+    rows = rng.choice(h, size=7, replace=False)
+    col = int(rng.integers(w))
+    A[:, rows, col] = rng.normal(size=(b, 7)).astype(np.float32) * 1e-2
+    for t in (0.0, 1e-4, 1.0):
+        say("svt rank-one", shape, "t =", t)
+        E = L.svt(torch.from_numpy(A).cuda(), t).cpu().numpy()
+        assert np.all(np.isfinite(E))
+        ref = oracle.tsvt(A.astype(np.float64), t)
+        if np.linalg.norm(ref) == 0:
+            assert np.abs(E).max() == 0
+        else:
+            assert rel(E, ref) < SVT_TOL, (t, rel(E, ref))
+
+
 def test_svt_batch_equals_single():
     L = _lib()
     A = np.stack([_lowrank_tensor((10, 20, 24), 3, s) for s in range(3)])
