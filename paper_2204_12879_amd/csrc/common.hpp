@@ -37,6 +37,23 @@ LRSTV_DEV float warp_sumf(float v) {
   return v;
 }
 
+// Wave-wide float sum with DPP row operations (quad permutes, row mirrors,
+// row broadcasts); the total is read from lane 63 and returned to all lanes.
+// The DPP builtin moves 32-bit integers, hence the bit casts.
+template <int CTRL, int ROWMASK>
+LRSTV_DEV float dpp_moved(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xf, false));
+}
+LRSTV_DEV float wave_sumf_dpp(float v) {
+  v += dpp_moved<0xb1, 0xf>(v);    // quad_perm [1,0,3,2]
+  v += dpp_moved<0x4e, 0xf>(v);    // quad_perm [2,3,0,1]
+  v += dpp_moved<0x141, 0xf>(v);   // row_half_mirror
+  v += dpp_moved<0x140, 0xf>(v);   // row_mirror
+  v += dpp_moved<0x142, 0xa>(v);   // row_bcast:15 -> rows 1, 3
+  v += dpp_moved<0x143, 0xc>(v);   // row_bcast:31 -> rows 2, 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // Block-wide sum in a fixed order (deterministic).  `scratch` holds
 // blockDim/64 doubles.  Every thread gets the result.
 LRSTV_DEV double block_sum(double v, double* scratch) {

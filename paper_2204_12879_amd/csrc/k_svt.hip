@@ -304,7 +304,10 @@ __global__ void __launch_bounds__(512) k_tridiag_reg(const SliceDesc* __restrict
   float2* xb1 = xb0 + n;             // [n]
   float2* wb = xb1 + n;              // [n] row parts of A v, then w
   float2* colacc = wb + n;           // [NW][n]
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  // wave index as a wave-uniform (scalar) value, so that row and slot tests
+  // below become scalar branches instead of per-lane predication
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   double* dg = tri + d.t_off;
   double* eab = dg + n;
   double* phr = eab + n;
@@ -427,7 +430,8 @@ __global__ void __launch_bounds__(512) k_tridiag_reg(const SliceDesc* __restrict
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int c = lane + 64 * u;
-      vc[u] = (c > i && c < n) ? vget(c - i - 1) : make_float2(0.f, 0.f);
+      vc[u] = make_float2(0.f, 0.f);
+      if (64 * u + 63 > i && 64 * u < n && c > i && c < n) vc[u] = vget(c - i - 1);
     }
     double nxp = 0.0;
     const float2 zero = make_float2(0.f, 0.f);
@@ -443,6 +447,7 @@ __global__ void __launch_bounds__(512) k_tridiag_reg(const SliceDesc* __restrict
         float2 acc = zero;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
+          if (64 * u + 63 <= i || 64 * u > r) continue;   // uniform: slot outside (i, r]
           const int c = lane + 64 * u;
           if (c > i && c <= r) {
             const float2 a = row[c];
@@ -451,8 +456,8 @@ __global__ void __launch_bounds__(512) k_tridiag_reg(const SliceDesc* __restrict
             else vav -= ((double)vr.x * vr.x + (double)vr.y * vr.y) * a.x;
           }
         }
-        acc.x = warp_sumf(acc.x);
-        acc.y = warp_sumf(acc.y);
+        acc.x = wave_sumf_dpp(acc.x);
+        acc.y = wave_sumf_dpp(acc.y);
         if (lane == 0) {
           wb[r - i - 1] = acc;
           vav += 2.0 * ((double)vr.x * acc.x + (double)vr.y * acc.y);
@@ -466,6 +471,7 @@ __global__ void __launch_bounds__(512) k_tridiag_reg(const SliceDesc* __restrict
           float2 acc = zero;
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
+            if (64 * u + 63 <= i || 64 * u > r) continue;
             const int c = lane + 64 * u;
             if (c > i && c <= r) {
               const float2 a = reg[j][u];
@@ -474,8 +480,8 @@ __global__ void __launch_bounds__(512) k_tridiag_reg(const SliceDesc* __restrict
               else vav -= ((double)vr.x * vr.x + (double)vr.y * vr.y) * a.x;
             }
           }
-          acc.x = warp_sumf(acc.x);
-          acc.y = warp_sumf(acc.y);
+          acc.x = wave_sumf_dpp(acc.x);
+          acc.y = wave_sumf_dpp(acc.y);
           if (lane == 0) {
             wb[r - i - 1] = acc;
             vav += 2.0 * ((double)vr.x * acc.x + (double)vr.y * acc.y);
@@ -484,6 +490,7 @@ __global__ void __launch_bounds__(512) k_tridiag_reg(const SliceDesc* __restrict
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
+        if (64 * u + 63 <= i || 64 * u >= n) continue;
         const int c = lane + 64 * u;
         if (c > i && c < n) colacc[wv * n + c] = cacc[u];
       }
@@ -508,13 +515,15 @@ __global__ void __launch_bounds__(512) k_tridiag_reg(const SliceDesc* __restrict
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int c = lane + 64 * u;
-        wc[u] = (c > i && c < n) ? wb[c - i - 1] : zero;
+        wc[u] = zero;
+        if (64 * u + 63 > i && 64 * u < n && c > i && c < n) wc[u] = wb[c - i - 1];
       }
       for (int r = i + 1 + wv; r < RL; r += NW) {
         float2* row = A + packed(r, 0);
         const float2 vr = vget(r - i - 1), wr = wb[r - i - 1];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
+          if (64 * u + 63 <= i || 64 * u > r) continue;
           const int c = lane + 64 * u;
           if (c > i && c <= r) {
             const float2 t1 = make_float2(vr.x * wc[u].x + vr.y * wc[u].y, vr.y * wc[u].x - vr.x * wc[u].y);
@@ -540,6 +549,7 @@ __global__ void __launch_bounds__(512) k_tridiag_reg(const SliceDesc* __restrict
           const float2 vr = vget(r - i - 1), wr = wb[r - i - 1];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
+            if (64 * u + 63 < i || 64 * u > r) continue;   // slot holds neither column i nor (i, r]
             const int c = lane + 64 * u;
             if (c > i && c <= r) {
               const float2 t1 = make_float2(vr.x * wc[u].x + vr.y * wc[u].y, vr.y * wc[u].x - vr.x * wc[u].y);
