@@ -132,6 +132,12 @@ int lrstv_reset(lrstv_handle hd, const float* Y);
  * Errors: INVALID_ARG, HIP. */
 int lrstv_iterate(lrstv_handle hd, int32_t n_iter, double* residuals);
 
+/* Replay iterations from a hipGraph of one iteration captured on the
+ * handle's stream (enable = 1; captured on first use) or launch them one by
+ * one (0, the default).  Results are bit-identical either way.  Stage
+ * timing (lrstv_profile) forces eager launches while it is on. */
+int lrstv_set_graph(lrstv_handle hd, int32_t enable);
+
 /* Copy X = L of the last iteration and S into caller buffers (device,
  * packed batch).  Either may be NULL.  Asynchronous. */
 int lrstv_read_output(lrstv_handle hd, float* X, float* S);

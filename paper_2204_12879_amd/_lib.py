@@ -75,6 +75,7 @@ def load_library():
         "lrstv_zsolve_workspace_size": (C.c_int, [i32, i32, i32, sz]),
         "lrstv_zsolve": (C.c_int, [vp, vp, i32, i32, i32, f64, C.POINTER(C.c_double), vp, C.c_size_t, vp]),
         "lrstv_profile": (C.c_int, [vp, i32]),
+        "lrstv_set_graph": (C.c_int, [vp, i32]),
         "lrstv_stage_times": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32), i32]),
         "lrstv_stage_name": (C.c_char_p, [i32]),
         "lrstv_slice_ranks": (C.c_int, [vp, C.POINTER(C.c_int32), i32]),
@@ -199,6 +200,10 @@ class Solver:
         _check(rc, allow_warn=True)
         return {"iters": rep.iters, "residuals": dict(zip(RESIDUAL_NAMES, list(rep.residuals))),
                 "mu": rep.mu, "converged": rc != WARN_NOT_CONVERGED}
+
+    def set_graph(self, enable: bool = True) -> None:
+        """Replay iterations from a captured hipGraph (bit-identical to eager launches)."""
+        _check(self.lib.lrstv_set_graph(self.handle, 1 if enable else 0))
 
     def profile(self, enable: bool = True) -> None:
         """Start (discarding earlier records) or stop per-stage GPU event timing."""

@@ -123,6 +123,14 @@ struct lrstv_handle_s {
   int *rcount, *flag;
   SliceDesc* desc;
   StageTimer timer;
+  // hipGraph replay of one iteration (lrstv_set_graph)
+  bool graph_on = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  ~lrstv_handle_s() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
 };
 
 static int check_params(const lrstv_params* p) {
@@ -248,6 +256,7 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
     delete H;
     return fail(LRSTV_ERR_HIP, "copying the slice table: %s", hipGetErrorString(e));
   }
+  prepare_svt(H->sl.max_n1);
   launch_set_mu(H->mu, par->mu0, H->stream);
   *out = H;
   return LRSTV_OK;
@@ -367,12 +376,63 @@ static void run_iteration(lrstv_handle_s* H, double* res_user) {
   tm.end(ST_FINISH);
 }
 
+// Capture one iteration into a graph (once).  Capture runs on a private
+// non-blocking stream (the caller's stream may be the legacy null stream,
+// which cannot be captured); the graph is then launched on the caller's
+// stream.  Every per-iteration scalar (mu, residuals, shrink thresholds)
+// lives on the device, so replays need no host work; fills use kernels.
+static int ensure_graph(lrstv_handle_s* H) {
+  if (H->gexec) return LRSTV_OK;
+  hipStream_t cap = nullptr;
+  HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  // work already queued on the caller's stream must not race the capture's
+  // (never executed) recording: nothing is launched, only recorded
+  const bool timing = H->timer.on;
+  hipStream_t user = H->stream;
+  H->timer.on = false;
+  H->stream = cap;
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+  hipGraph_t g = nullptr;
+  if (e == hipSuccess) {
+    run_iteration(H, nullptr);
+    e = hipStreamEndCapture(cap, &g);
+  }
+  H->stream = user;
+  H->timer.on = timing;
+  (void)hipStreamDestroy(cap);
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(LRSTV_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+  }
+  H->graph = g;
+  HIPCHK(hipGraphInstantiate(&H->gexec, H->graph, nullptr, nullptr, 0));
+  return LRSTV_OK;
+}
+
+extern "C" int lrstv_set_graph(lrstv_handle H, int32_t enable) {
+  if (!H) return fail(LRSTV_ERR_INVALID_ARG, "handle is NULL");
+  H->graph_on = enable != 0;
+  if (H->graph_on) return ensure_graph(H);
+  return LRSTV_OK;
+}
+
 extern "C" int lrstv_iterate(lrstv_handle H, int32_t n_iter, double* residuals) {
   if (!H) return fail(LRSTV_ERR_INVALID_ARG, "handle is NULL");
   if (n_iter < 0) return fail(LRSTV_ERR_INVALID_ARG, "n_iter must be >= 0");
   const int nc = (int)H->cubes.size();
-  for (int it = 0; it < n_iter; ++it)
-    run_iteration(H, residuals ? residuals + (int64_t)it * nc * R_COUNT : nullptr);
+  if (H->graph_on && !H->timer.on) {
+    int rc = ensure_graph(H);
+    if (rc) return rc;
+    for (int it = 0; it < n_iter; ++it) {
+      HIPCHK(hipGraphLaunch(H->gexec, H->stream));
+      if (residuals)
+        launch_copy((float*)(residuals + (int64_t)it * nc * R_COUNT), (const float*)H->res_last, 2 * nc * R_COUNT,
+                    H->stream);
+    }
+  } else {
+    for (int it = 0; it < n_iter; ++it)
+      run_iteration(H, residuals ? residuals + (int64_t)it * nc * R_COUNT : nullptr);
+  }
   HIPCHK(hipGetLastError());
   return LRSTV_OK;
 }
@@ -399,7 +459,8 @@ extern "C" int lrstv_solve(lrstv_handle H, const float* Y, float* X, float* S, i
   bool done = false;
   while (iters < max_iter && !done) {
     const int k = (max_iter - iters) < chunk ? (max_iter - iters) : chunk;
-    for (int i = 0; i < k; ++i) run_iteration(H, nullptr);
+    rc = lrstv_iterate(H, k, nullptr);
+    if (rc) return rc;
     iters += k;
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(res.data(), H->res_last, res.size() * sizeof(double), hipMemcpyDeviceToHost, H->stream));
@@ -566,6 +627,7 @@ extern "C" int lrstv_svt(const float* A, float* E, int32_t h, int32_t w, int32_t
   const int ns = (int)L.desc.size();
   const int n1 = h < w ? h : w;
   const int64_t hw = (int64_t)h * w;
+  prepare_svt(n1);
   hipLaunchKernelGGL(k_make_desc, dim3((ns + 255) / 256), dim3(256), 0, s, ws.desc, ns, nullptr, h, w, b / 2 + 1,
                      (int64_t)n1 * (n1 + 1) / 2, 2 * (int64_t)n1 * n1, 2 * hw, 6 * (int64_t)n1, 3 * (int64_t)n1 * n1,
                      (int64_t)n1);

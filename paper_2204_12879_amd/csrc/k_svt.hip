@@ -1092,6 +1092,29 @@ __global__ void __launch_bounds__(256) k_bp2(const SliceDesc* __restrict__ desc,
 }
 
 // ------------------------------------------------------------ launcher ---
+constexpr int kTridiagRegRows = 10;
+// Dynamic LDS granted to k_tridiag_reg (host-side function attribute, set
+// once outside any stream capture by prepare_svt).
+static size_t g_tridiag_lds_granted = 65536;
+
+void prepare_svt(int max_n1) {
+  const int n = max_n1;
+  constexpr int JR = kTridiagRegRows;
+  const int RL = n > 8 * JR ? n - 8 * JR : 0;
+  const size_t reg_lds = ((size_t)RL * (RL + 1) / 2 + (size_t)(3 + 8) * n) * sizeof(float2);
+  if (n > 256 || reg_lds <= g_tridiag_lds_granted) return;
+  int dev = 0;
+  hipDeviceProp_t prop;
+  int lds_max = 65536;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    lds_max = (int)prop.sharedMemPerBlock;
+  if ((int)reg_lds + 2048 > lds_max) return;
+  if (hipFuncSetAttribute((const void*)k_tridiag_reg<JR>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)reg_lds) == hipSuccess)
+    g_tridiag_lds_granted = reg_lds;
+  else
+    (void)hipGetLastError();  // clear the sticky error: the global-memory variant is used instead
+}
 static size_t tridiag_onchip_bytes(int n) {
   return ((size_t)n * (n + 1) / 2 + 2 * (size_t)n + 4 * (size_t)n) * sizeof(float2);
 }
@@ -1105,29 +1128,11 @@ void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm) {
   T.begin(ST_GRAM);
   hipLaunchKernelGGL(k_gram, dim3(TT * (TT + 1) / 2, ns), dim3(256), 0, s, L.desc, L.slices, L.gram);
   T.end(ST_GRAM);
-  static int lds_max = -1;
-  if (lds_max < 0) {
-    int dev = 0;
-    hipDeviceProp_t prop;
-    lds_max = 65536;
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-      lds_max = (int)prop.sharedMemPerBlock;
-  }
   T.begin(ST_TRIDIAG);
-  constexpr int JR = 10;
+  constexpr int JR = kTridiagRegRows;
   const int RL = n > 8 * JR ? n - 8 * JR : 0;
   const size_t reg_lds = ((size_t)RL * (RL + 1) / 2 + (size_t)(3 + 8) * n) * sizeof(float2);
-  static size_t reg_granted = 65536;
-  bool use_reg = n <= 256 && reg_lds <= reg_granted;
-  if (n <= 256 && !use_reg && (int)reg_lds + 2048 <= lds_max) {
-    if (hipFuncSetAttribute((const void*)k_tridiag_reg<JR>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)reg_lds) == hipSuccess) {
-      reg_granted = reg_lds;
-      use_reg = true;
-    } else {
-      (void)hipGetLastError();  // clear the sticky error: the global-memory variant is used instead
-    }
-  }
+  const bool use_reg = n <= 256 && reg_lds <= g_tridiag_lds_granted;
   if (use_reg) {
     hipLaunchKernelGGL(k_tridiag_reg<JR>, dim3(ns), dim3(512), reg_lds, s, L.desc, L.gram, L.tri);
   } else {
@@ -1140,8 +1145,10 @@ void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm) {
   hipLaunchKernelGGL(k_trieig, dim3(ns), dim3(1024), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount, L.mu, L.alpha,
                      L.thresh);
   T.end(ST_TRIEIG);
-  int cb = 64;
-  while (cb > 4 && ((size_t)n * cb + n + 256) * sizeof(float2) > 60 * 1024) cb >>= 1;
+  // Column chunk fixed per size class (not derived from this batch's largest
+  // slice), so a slice's reduction order, hence its rounding, does not depend
+  // on which other slices share the launch.
+  const int cb = n <= 256 ? 16 : 8;
   const size_t bt_lds = ((size_t)n * cb + n + 256) * sizeof(float2);
   T.begin(ST_BACKTRANS);
   hipLaunchKernelGGL(k_backtrans, dim3((n + cb - 1) / cb, ns), dim3(256), bt_lds, s, L.desc, L.gram, L.tri, L.V,

@@ -71,5 +71,7 @@ struct SvtLaunch {
   int precision;
 };
 void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm = nullptr);
+// Host-side kernel attributes for slices up to max_n1 (call before capture).
+void prepare_svt(int max_n1);
 
 }  // namespace lrstv
