@@ -27,8 +27,9 @@ FP32_PEAK_TFLOPS = 157.3
 BF16_PEAK_TFLOPS = 2500.0
 
 
-def stage_model(shape, ranks_per_slice):
-    """Algorithmic bytes (HBM-bound stages) or flops (compute stages) per launch.
+def stage_model(shapes, ranks_per_slice):
+    """Algorithmic bytes (HBM-bound stages) or flops (compute stages) per launch,
+    summed over the cubes of the batch.
 
     Per-unit figures (N = b h w voxels, s = b/2+1 slices per gradient tensor,
     n1 = min(h, w), m1 = max(h, w), r = kept singular values of a slice):
@@ -42,35 +43,37 @@ def stage_model(shape, ranks_per_slice):
       irfft_w      reads the half spectrum + old Z, writes Z
       gram         4 m1 n1 (n1 + 1) flops per slice (packed Hermitian Gram)
       tridiag      16/3 n1^3 flops per slice (Hermitian Householder reduction)
+      trieig       52 * 3 n1 flops per kept eigenvalue (FP64 Sturm bisection)
       backtrans    8 n1^2 r flops per slice
       bp1, bp2     8 m1 n1 r flops per slice each
     """
-    b, h, w = shape
-    N = b * h * w
-    s = b // 2 + 1
-    wc = w // 2 + 1
-    spec = b * h * wc * 8
-    n1, m1 = min(h, w), max(h, w)
-    sl = 3 * s * h * w * 8
-    rs = ranks_per_slice
-    model = {
-        "lrhs": ("hbm", 13 * 4 * N),
-        "grad_shrink": ("hbm", 26 * 4 * N),
-        "band_dft": ("hbm", 3 * 4 * N + sl),
-        "band_idft": ("hbm", sl + 12 * 4 * N),
-        "rfft_w": ("hbm", 4 * N + spec),
-        "fft_h": ("hbm", 2 * spec),
-        "tri_b": ("hbm", 2 * spec),
-        "irfft_w": ("hbm", spec + 8 * N),
-        "gram": ("flops", 3 * s * 4.0 * m1 * n1 * (n1 + 1)),
-        "tridiag": ("flops", 3 * s * 16.0 / 3.0 * n1 ** 3),
-        "backtrans": ("flops", sum(8.0 * n1 * n1 * r for r in rs)),
-        "bp1": ("flops", sum(8.0 * m1 * n1 * r for r in rs)),
-        "bp2": ("flops", sum(8.0 * m1 * n1 * r for r in rs)),
-        # FP64 Sturm bisection: ~52 halvings x n1 recurrence steps x 3 flops per kept eigenvalue
-        "trieig": ("fp64", sum(52 * 3.0 * n1 * r for r in rs)),
-    }
-    return model
+    tot = {}
+    def add(k, kind, v):
+        tot[k] = (kind, tot.get(k, (kind, 0.0))[1] + v)
+    pos = 0
+    for (b, h, w) in shapes:
+        N = b * h * w
+        s = b // 2 + 1
+        spec = b * h * (w // 2 + 1) * 8
+        n1, m1 = min(h, w), max(h, w)
+        sl = 3 * s * h * w * 8
+        rs = ranks_per_slice[pos:pos + 3 * s]
+        pos += 3 * s
+        add("lrhs", "hbm", 13 * 4 * N)
+        add("grad_shrink", "hbm", 26 * 4 * N)
+        add("band_dft", "hbm", 3 * 4 * N + sl)
+        add("band_idft", "hbm", sl + 12 * 4 * N)
+        add("rfft_w", "hbm", 4 * N + spec)
+        add("fft_h", "hbm", 2 * spec)
+        add("tri_b", "hbm", 2 * spec)
+        add("irfft_w", "hbm", spec + 8 * N)
+        add("gram", "flops", 3 * s * 4.0 * m1 * n1 * (n1 + 1))
+        add("tridiag", "flops", 3 * s * 16.0 / 3.0 * n1 ** 3)
+        add("trieig", "fp64", sum(52 * 3.0 * n1 * r for r in rs))
+        add("backtrans", "flops", sum(8.0 * n1 * n1 * r for r in rs))
+        add("bp1", "flops", sum(8.0 * m1 * n1 * r for r in rs))
+        add("bp2", "flops", sum(8.0 * m1 * n1 * r for r in rs))
+    return tot
 
 
 def cpu_baseline(noisy, params_kw, iters):
@@ -102,7 +105,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="wdc", choices=["wdc", "pavia", "small"])
+    ap.add_argument("--workload", default="wdc", choices=["wdc", "pavia", "small", "ragged"])
+    ap.add_argument("--eager", action="store_true", help="launch kernels one by one instead of graph replay")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
@@ -121,16 +125,22 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     wl = synth.workload(args.workload)
+    cubes = [synth.make_cube(s) for s in wl.cubes]
+    shapes = [(s.b, s.h, s.w) for s in wl.cubes]
     spec = wl.cubes[0]
-    clean, noisy = synth.make_cube(spec)
-    shape = (spec.b, spec.h, spec.w)
-    lam = 10.0 / np.sqrt(spec.h * spec.w)
+    # lambda = C / sqrt(h w) with C = 10; one lambda for a batch (100 x 100 reference plane)
+    hw_ref = spec.h * spec.w if len(shapes) == 1 else 100 * 100
+    lam = 10.0 / np.sqrt(hw_ref)
     pkw = dict(tau=0.02, alpha=0.3, lam=lam, w=(1.0, 1.0, 1.0), mu0=1e-2, rho=1.5, mu_max=1e6)
     prec = L.LRSTV_FP32 if args.precision == "fp32" else L.LRSTV_SPLIT_BF16
-    solver = L.Solver([shape], L.Params(precision=prec, **pkw))
-    Y = torch.from_numpy(noisy.astype(np.float32)).cuda().reshape(-1)
+    solver = L.Solver(shapes, L.Params(precision=prec, **pkw))
+    if not args.eager:
+        solver.set_graph(True)
+    Y = torch.from_numpy(np.concatenate([c[1].astype(np.float32).ravel() for c in cubes])).cuda()
     X = torch.empty_like(Y)
-    print(f"bench: {args.workload} {shape} steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
+    clean, noisy = cubes[0]
+    print(f"bench: {args.workload} {len(shapes)} cube(s), {Y.numel()} voxels, steps={args.steps} "
+          f"warmup={args.warmup}", file=sys.stderr, flush=True)
 
     # warm-up (untimed)
     solver.reset(Y)
@@ -159,7 +169,7 @@ def main():
     st = solver.stage_times()
     solver.profile(False)
     ranks_prof = solver.slice_ranks()
-    model = stage_model(shape, ranks_prof)
+    model = stage_model(shapes, ranks_prof)
     dom = max(st, key=lambda k: st[k][0])
     dom_ms, dom_n = st[dom]
     avg_ms = dom_ms / max(dom_n, 1)
@@ -177,8 +187,9 @@ def main():
     roof["avg_launch_ms"] = avg_ms
     svt_stages = ["gram", "tridiag", "trieig", "backtrans", "bp1", "colnorm", "bp2"]
     svt_ms = sum(st[k][0] for k in svt_stages)
-    n_slices = 3 * (spec.b // 2 + 1)
+    n_slices = sum(3 * (s[0] // 2 + 1) for s in shapes)
     stages = {k: round(v[0] / args.steps, 4) for k, v in st.items()}
+    kept_den = sum(3 * (s[0] // 2 + 1) * min(s[1], s[2]) for s in shapes)
 
     out = {
         "metric": METRIC,
@@ -193,11 +204,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if prec == L.LRSTV_FP32 else "bf16x3+f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload} {spec.h}x{spec.w}x{spec.b} single cube, ADMM iterations from the "
-                               f"initial state, tau=0.02 alpha=0.3 lambda=10/sqrt(hw) mu0=1e-2 rho=1.5",
-                   "precision": args.precision, "parallelism": "single GPU"},
+        "config": {"workload": (f"{args.workload} {spec.h}x{spec.w}x{spec.b} single cube" if len(shapes) == 1 else
+                                f"{args.workload} batch of {len(shapes)} cubes (h, w in [48, 160], b in [31, 191])") +
+                               ", ADMM iterations from the initial state, tau=0.02 alpha=0.3 lambda=10/sqrt(hw) "
+                               "mu0=1e-2 rho=1.5",
+                   "precision": args.precision, "launch": "eager" if args.eager else "hipGraph replay",
+                   "voxels": int(Y.numel()), "parallelism": "single GPU"},
         "tsvt_slices_per_s": n_slices * args.steps / (svt_ms * 1e-3) if svt_ms > 0 else None,
-        "kept_singular_value_fraction_last_iter": float(np.sum(ranks_last)) / (n_slices * min(spec.h, spec.w)),
+        "kept_singular_value_fraction_last_iter": float(np.sum(ranks_last)) / kept_den,
         "stage_ms_per_iter": stages,
         "roofline": roof,
     }
@@ -209,7 +223,7 @@ def main():
             idx = g["index"]
             ref = g["values"]
             out["rel_err_vs_oracle_sampled"] = float(np.linalg.norm(Xg[idx] - ref) / np.linalg.norm(ref))
-    if not args.no_cpu:
+    if not args.no_cpu and len(shapes) == 1:
         print("bench: timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(noisy, pkw, args.cpu_iters)
     print(json.dumps(out), flush=True)
