@@ -6,7 +6,8 @@
 //   f_i  = max(1 - t / sigma_i, 0)
 //
 // Pipeline (one kernel each, all slices of all cubes batched):
-//   k_gram       G = M^H M or M M^H (n1 x n1, packed lower triangle)
+//   k_gram       G = M^H M or M M^H (n1 x n1, packed lower triangle), MFMA,
+//                FP32 or split-BF16 (3 terms) products
 //   k_tridiag    Householder reduction G = Q T~ Q^H with Hermitian reflectors,
 //                T~ Hermitian tridiagonal; made real by a diagonal phase;
 //                the packed Gram stays in LDS when it fits
@@ -14,50 +15,19 @@
 //                threshold and eigenvectors by twisted factorisations
 //                (per unreduced block), cluster re-orthogonalisation
 //   k_backtrans  V <- Q (phase * z), applying the stored reflectors
-//   k_bp1        B = M V_r  (or U_r^H M)
+//   k_bp1        B = M V_r  (or U_r^H M), MFMA as the Gram
 //   k_colnorm    sigma_i = ||M v_i|| (taken from M, not from the squared
 //                Gram eigenvalue), f_i = max(1 - t/sigma_i, 0)
 //   k_bp2        Ehat = B diag(f) V_r^H  (or U_r diag(f) B), written over M
 //
 // Eigenpairs whose Gram eigenvalue lies below t^2 - delta (delta a few FP32
 // ulps of ||G||) are discarded: there sigma <= t and the shrink factor is 0.
+#include "../../include/lrstv.h"
 #include "common.hpp"
 #include "kernels.hpp"
+#include "mfma.hpp"
 
 namespace lrstv {
-
-// ------------------------------------------------------------- GEMM tile ---
-// 256 threads compute a 32 x 32 complex tile C = sum_k A(m, k) B(k, n).
-// fa(m, k) / fb(k, n) return the operand element (zero outside).
-// AK / BK: whether k is the fast (contiguous) index of A / B in memory, which
-// picks the coalesced load order.
-template <bool AK, bool BK, class FA, class FB>
-LRSTV_DEV void ctile(int m0, int n0, int K, FA fa, FB fb, float2& c00, float2& c01, float2& c10, float2& c11,
-                     float2 (*As)[33], float2 (*Bs)[33]) {
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  c00 = c01 = c10 = c11 = make_float2(0.f, 0.f);
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    for (int e = tid; e < 512; e += 256) {
-      int kk, mm;
-      if (AK) { kk = e & 15; mm = e >> 4; } else { mm = e & 31; kk = e >> 5; }
-      As[kk][mm] = fa(m0 + mm, k0 + kk);
-      int nn;
-      if (BK) { kk = e & 15; nn = e >> 4; } else { nn = e & 31; kk = e >> 5; }
-      Bs[kk][nn] = fb(k0 + kk, n0 + nn);
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < 16; ++kk) {
-      const float2 a0 = As[kk][ty], a1 = As[kk][ty + 16];
-      const float2 b0 = Bs[kk][tx], b1 = Bs[kk][tx + 16];
-      c00 = cadd(c00, cmul(a0, b0));
-      c01 = cadd(c01, cmul(a0, b1));
-      c10 = cadd(c10, cmul(a1, b0));
-      c11 = cadd(c11, cmul(a1, b1));
-    }
-    __syncthreads();
-  }
-}
 
 LRSTV_DEV int64_t packed(int r, int c) { return (int64_t)r * (r + 1) / 2 + c; }
 
@@ -66,11 +36,14 @@ LRSTV_DEV int64_t packed(int r, int c) { return (int64_t)r * (r + 1) / 2 + c; }
 #define kDeflate2 1e-14
 
 // ------------------------------------------------------------------ Gram ---
+// G = M^H M (tall) or M M^H (wide), packed lower triangle.  Block x walks the
+// lower 64 x 64 tiles of the slice, block y is the slice.
+template <int MODE>
 __global__ void __launch_bounds__(256) k_gram(const SliceDesc* __restrict__ desc, const float* __restrict__ sl,
                                               float2* __restrict__ gram) {
-  __shared__ float2 As[16][33], Bs[16][33];
+  __shared__ MfmaSmem sm;
   const SliceDesc d = desc[blockIdx.y];
-  const int n = d.n1, T = (n + 31) / 32;
+  const int n = d.n1, T = (n + kMT - 1) / kMT;
   int ti = 0, rem = blockIdx.x;
   while (rem > ti) { rem -= ti + 1; ++ti; }
   const int tj = rem;
@@ -78,8 +51,14 @@ __global__ void __launch_bounds__(256) k_gram(const SliceDesc* __restrict__ desc
   const int h = d.h, w = d.w;
   const float* re = sl + d.a_off;
   const float* im = re + (int64_t)h * w;
-  float2 c00, c01, c10, c11;
-  if (d.tall) {  // G = M^H M, contraction over the h rows
+  const int m0 = ti * kMT, n0 = tj * kMT;
+  const int wv = threadIdx.x >> 6, r0 = m0 + 32 * (wv >> 1), c0 = n0 + 32 * (wv & 1);
+  const bool active = r0 < n && c0 < n && r0 + 31 >= c0;
+  float2* g = gram + d.g_off;
+  auto st = [&](int r, int c, float2 v) {
+    if (r < n && c <= r) g[packed(r, c)] = v;
+  };
+  if (d.tall) {  // contraction over the h rows
     auto fa = [&](int m, int k) -> float2 {
       if (m >= n || k >= h) return make_float2(0.f, 0.f);
       const int64_t q = (int64_t)k * w + m;
@@ -90,8 +69,8 @@ __global__ void __launch_bounds__(256) k_gram(const SliceDesc* __restrict__ desc
       const int64_t q = (int64_t)k * w + c;
       return make_float2(re[q], im[q]);
     };
-    ctile<false, false>(ti * 32, tj * 32, h, fa, fb, c00, c01, c10, c11, As, Bs);
-  } else {  // G = M M^H, contraction over the w columns
+    mfma_ctile<MODE, false, false>(m0, n0, h, fa, fb, st, sm, active);
+  } else {  // contraction over the w columns
     auto fa = [&](int m, int k) -> float2 {
       if (m >= n || k >= w) return make_float2(0.f, 0.f);
       const int64_t q = (int64_t)m * w + k;
@@ -102,15 +81,8 @@ __global__ void __launch_bounds__(256) k_gram(const SliceDesc* __restrict__ desc
       const int64_t q = (int64_t)c * w + k;
       return make_float2(re[q], -im[q]);
     };
-    ctile<true, true>(ti * 32, tj * 32, w, fa, fb, c00, c01, c10, c11, As, Bs);
+    mfma_ctile<MODE, true, true>(m0, n0, w, fa, fb, st, sm, active);
   }
-  float2* g = gram + d.g_off;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int r0 = ti * 32 + ty, r1 = r0 + 16, q0 = tj * 32 + tx, q1 = q0 + 16;
-  if (r0 < n && q0 <= r0) g[packed(r0, q0)] = c00;
-  if (r0 < n && q1 <= r0) g[packed(r0, q1)] = c01;
-  if (r1 < n && q0 <= r1) g[packed(r1, q0)] = c10;
-  if (r1 < n && q1 <= r1) g[packed(r1, q1)] = c11;
 }
 
 // ---------------------------------------------------------- tridiagonal ---
@@ -964,10 +936,11 @@ __global__ void __launch_bounds__(256) k_backtrans(const SliceDesc* __restrict__
 
 // ----------------------------------------------------- back-projection ---
 // tall: B (h x r, ld n) = M V_r;  wide: B (r x w, ld w) = U_r^H M
+template <int MODE>
 __global__ void __launch_bounds__(256) k_bp1(const SliceDesc* __restrict__ desc, const float* __restrict__ sl,
                                              const float* __restrict__ V, float* __restrict__ Bb,
                                              const int* __restrict__ rcount) {
-  __shared__ float2 As[16][33], Bs[16][33];
+  __shared__ MfmaSmem sm;
   const SliceDesc d = desc[blockIdx.z];
   const int r = rcount[blockIdx.z], n = d.n1, h = d.h, w = d.w;
   const float* mr = sl + d.a_off;
@@ -976,12 +949,15 @@ __global__ void __launch_bounds__(256) k_bp1(const SliceDesc* __restrict__ desc,
   const float* vi = vr + (int64_t)n * n;
   float* br = Bb + d.b_off;
   float* bi = br + (int64_t)h * w;
-  float2 c00, c01, c10, c11;
-  int M, N, ld;
-  const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
+  const int m0 = blockIdx.y * kMT, n0 = blockIdx.x * kMT;
+  const int M = d.tall ? h : r, N = d.tall ? r : w, ld = d.tall ? n : w;
+  if (m0 >= M || n0 >= N) return;
+  const int wv = threadIdx.x >> 6;
+  const bool active = m0 + 32 * (wv >> 1) < M && n0 + 32 * (wv & 1) < N;
+  auto st = [&](int a, int b, float2 v) {
+    if (a < M && b < N) { br[(int64_t)a * ld + b] = v.x; bi[(int64_t)a * ld + b] = v.y; }
+  };
   if (d.tall) {
-    M = h; N = r; ld = n;
-    if (m0 >= M || n0 >= N) return;
     auto fa = [&](int m, int k) -> float2 {
       if (m >= h || k >= w) return make_float2(0.f, 0.f);
       return make_float2(mr[(int64_t)m * w + k], mi[(int64_t)m * w + k]);
@@ -990,10 +966,8 @@ __global__ void __launch_bounds__(256) k_bp1(const SliceDesc* __restrict__ desc,
       if (k >= n || c >= r) return make_float2(0.f, 0.f);
       return make_float2(vr[(int64_t)k * n + c], vi[(int64_t)k * n + c]);
     };
-    ctile<true, false>(m0, n0, w, fa, fb, c00, c01, c10, c11, As, Bs);
+    mfma_ctile<MODE, true, false>(m0, n0, w, fa, fb, st, sm, active);
   } else {
-    M = r; N = w; ld = w;
-    if (m0 >= M || n0 >= N) return;
     auto fa = [&](int m, int k) -> float2 {
       if (m >= r || k >= h) return make_float2(0.f, 0.f);
       return make_float2(vr[(int64_t)k * n + m], -vi[(int64_t)k * n + m]);
@@ -1002,14 +976,8 @@ __global__ void __launch_bounds__(256) k_bp1(const SliceDesc* __restrict__ desc,
       if (k >= h || c >= w) return make_float2(0.f, 0.f);
       return make_float2(mr[(int64_t)k * w + c], mi[(int64_t)k * w + c]);
     };
-    ctile<false, false>(m0, n0, h, fa, fb, c00, c01, c10, c11, As, Bs);
+    mfma_ctile<MODE, false, false>(m0, n0, h, fa, fb, st, sm, active);
   }
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int r0 = m0 + ty, r1 = r0 + 16, q0 = n0 + tx, q1 = q0 + 16;
-  auto st = [&](int a, int b, float2 v) {
-    if (a < M && b < N) { br[(int64_t)a * ld + b] = v.x; bi[(int64_t)a * ld + b] = v.y; }
-  };
-  st(r0, q0, c00); st(r0, q1, c01); st(r1, q0, c10); st(r1, q1, c11);
 }
 
 // sigma_c = ||B[:, c]|| (tall) or ||B[c, :]|| (wide); f_c = max(1 - t/sigma_c, 0)
@@ -1044,13 +1012,14 @@ __global__ void __launch_bounds__(256) k_colnorm(const SliceDesc* __restrict__ d
 }
 
 // tall: Ehat (h x w) = B diag(f) V_r^H;  wide: Ehat = U_r diag(f) B.  Written over M.
+template <int MODE>
 __global__ void __launch_bounds__(256) k_bp2(const SliceDesc* __restrict__ desc, float* __restrict__ sl,
                                              const float* __restrict__ V, const float* __restrict__ Bb,
                                              const float* __restrict__ fval, const int* __restrict__ rcount) {
-  __shared__ float2 As[16][33], Bs[16][33];
+  __shared__ MfmaSmem sm;
   const SliceDesc d = desc[blockIdx.z];
   const int r = rcount[blockIdx.z], n = d.n1, h = d.h, w = d.w;
-  const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
+  const int m0 = blockIdx.y * kMT, n0 = blockIdx.x * kMT;
   if (m0 >= h || n0 >= w) return;
   float* er = sl + d.a_off;
   float* ei = er + (int64_t)h * w;
@@ -1059,7 +1028,11 @@ __global__ void __launch_bounds__(256) k_bp2(const SliceDesc* __restrict__ desc,
   const float* br = Bb + d.b_off;
   const float* bi = br + (int64_t)h * w;
   const float* f = fval + d.f_off;
-  float2 c00, c01, c10, c11;
+  const int wv = threadIdx.x >> 6;
+  const bool active = m0 + 32 * (wv >> 1) < h && n0 + 32 * (wv & 1) < w;
+  auto st = [&](int a, int b, float2 v) {
+    if (a < h && b < w) { er[(int64_t)a * w + b] = v.x; ei[(int64_t)a * w + b] = v.y; }
+  };
   if (d.tall) {
     auto fa = [&](int m, int k) -> float2 {
       if (m >= h || k >= r) return make_float2(0.f, 0.f);
@@ -1070,7 +1043,7 @@ __global__ void __launch_bounds__(256) k_bp2(const SliceDesc* __restrict__ desc,
       if (k >= r || c >= w) return make_float2(0.f, 0.f);
       return make_float2(vr[(int64_t)c * n + k], -vi[(int64_t)c * n + k]);
     };
-    ctile<true, true>(m0, n0, r, fa, fb, c00, c01, c10, c11, As, Bs);
+    mfma_ctile<MODE, true, true>(m0, n0, r, fa, fb, st, sm, active);
   } else {
     auto fa = [&](int m, int k) -> float2 {
       if (m >= h || k >= r) return make_float2(0.f, 0.f);
@@ -1081,14 +1054,8 @@ __global__ void __launch_bounds__(256) k_bp2(const SliceDesc* __restrict__ desc,
       if (k >= r || c >= w) return make_float2(0.f, 0.f);
       return make_float2(br[(int64_t)k * w + c], bi[(int64_t)k * w + c]);
     };
-    ctile<true, false>(m0, n0, r, fa, fb, c00, c01, c10, c11, As, Bs);
+    mfma_ctile<MODE, true, false>(m0, n0, r, fa, fb, st, sm, active);
   }
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int r0 = m0 + ty, r1 = r0 + 16, q0 = n0 + tx, q1 = q0 + 16;
-  auto st = [&](int a, int b, float2 v) {
-    if (a < h && b < w) { er[(int64_t)a * w + b] = v.x; ei[(int64_t)a * w + b] = v.y; }
-  };
-  st(r0, q0, c00); st(r0, q1, c01); st(r1, q0, c10); st(r1, q1, c11);
 }
 
 // ------------------------------------------------------------ launcher ---
@@ -1124,9 +1091,13 @@ void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm) {
   StageTimer& T = tm ? *tm : dummy;
   const int ns = L.n_slices, n = L.max_n1, m = L.max_m1;
   if (ns == 0) return;
-  const int TT = (n + 31) / 32;
+  const bool bf = L.precision == LRSTV_SPLIT_BF16;
+  const int TT = (n + kMT - 1) / kMT, TM = (m + kMT - 1) / kMT;
   T.begin(ST_GRAM);
-  hipLaunchKernelGGL(k_gram, dim3(TT * (TT + 1) / 2, ns), dim3(256), 0, s, L.desc, L.slices, L.gram);
+  if (bf)
+    hipLaunchKernelGGL(k_gram<kBF16x3>, dim3(TT * (TT + 1) / 2, ns), dim3(256), 0, s, L.desc, L.slices, L.gram);
+  else
+    hipLaunchKernelGGL(k_gram<kF32>, dim3(TT * (TT + 1) / 2, ns), dim3(256), 0, s, L.desc, L.slices, L.gram);
   T.end(ST_GRAM);
   T.begin(ST_TRIDIAG);
   constexpr int JR = kTridiagRegRows;
@@ -1156,16 +1127,22 @@ void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm) {
   T.end(ST_BACKTRANS);
   // B: tall h x r, wide r x w -> tiles over (max(n, m)) both ways
   T.begin(ST_BP1);
-  hipLaunchKernelGGL(k_bp1, dim3((m + 31) / 32, (m + 31) / 32, ns), dim3(256), 0, s, L.desc, L.slices, L.V, L.B,
-                     L.rcount);
+  if (bf)
+    hipLaunchKernelGGL(k_bp1<kBF16x3>, dim3(TM, TM, ns), dim3(256), 0, s, L.desc, L.slices, L.V, L.B, L.rcount);
+  else
+    hipLaunchKernelGGL(k_bp1<kF32>, dim3(TM, TM, ns), dim3(256), 0, s, L.desc, L.slices, L.V, L.B, L.rcount);
   T.end(ST_BP1);
   T.begin(ST_COLNORM);
   hipLaunchKernelGGL(k_colnorm, dim3(n, ns), dim3(256), 0, s, L.desc, L.B, L.fval, L.rcount, L.mu, L.alpha,
                      L.thresh);
   T.end(ST_COLNORM);
   T.begin(ST_BP2);
-  hipLaunchKernelGGL(k_bp2, dim3((m + 31) / 32, (m + 31) / 32, ns), dim3(256), 0, s, L.desc, L.slices, L.V, L.B,
-                     L.fval, L.rcount);
+  if (bf)
+    hipLaunchKernelGGL(k_bp2<kBF16x3>, dim3(TM, TM, ns), dim3(256), 0, s, L.desc, L.slices, L.V, L.B, L.fval,
+                       L.rcount);
+  else
+    hipLaunchKernelGGL(k_bp2<kF32>, dim3(TM, TM, ns), dim3(256), 0, s, L.desc, L.slices, L.V, L.B, L.fval,
+                       L.rcount);
   T.end(ST_BP2);
 }
 

@@ -1,0 +1,193 @@
+// Complex GEMM tile on the CDNA4 matrix cores.
+//
+// A 256-thread block (4 waves) computes a 64 x 64 complex tile
+// C = sum_k A(m, k) B(k, n); wave q owns the 32 x 32 sub-tile
+// (32 (q >> 1), 32 (q & 1)).  Operands are fetched through accessors
+// fa(m, k), fb(k, n) that return float2 (zero outside the matrix), staged
+// through LDS in chunks of 32 along k with a register prefetch of the next
+// chunk, and multiplied as four real products
+//   Re C += Re A Re B - Im A Im B,   Im C += Re A Im B + Im A Re B.
+//
+// Two arithmetic modes:
+//   kF32   v_mfma_f32_32x32x2f32: FP32 operands, FP32 accumulation.
+//   kBF16x3 split-BF16: every FP32 operand x is stored as hi = bf16(x),
+//          lo = bf16(x - hi); a real product is hi*hi + hi*lo + lo*hi
+//          (the lo*lo term, ~2^-16 relative, is dropped), each term a
+//          v_mfma_f32_32x32x16_bf16 with FP32 accumulation.
+//
+// Lane layouts (checked on gfx950): for both instructions lane l holds
+// A(l % 32, k) and B(k, l % 32) with k = l / 32 (f32, K = 2) or
+// k = 8 (l / 32) + e, e = 0..7 (bf16, K = 16); accumulator element r of
+// lane l is C(8 (r / 4) + 4 (l / 32) + r % 4, l % 32).
+#pragma once
+#include "common.hpp"
+
+namespace lrstv {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+enum MfmaMode { kF32 = 0, kBF16x3 = 1 };
+
+constexpr int kMT = 64;   // block tile (rows and columns)
+constexpr int kKC = 32;   // k chunk staged per pass
+constexpr int kBfPad = 8; // bf16 row padding (keeps 16-byte alignment)
+
+struct MfmaSmemF32 {
+  float ar[kKC][kMT + 1], ai[kKC][kMT + 1], br[kKC][kMT + 1], bi[kKC][kMT + 1];
+};
+struct MfmaSmemBF {
+  // planes: 0 re hi, 1 re lo, 2 im hi, 3 im lo; rows are m (A) or n (B),
+  // k contiguous so a lane's 8 consecutive k are one 16-byte read
+  __bf16 a[4][kMT][kKC + kBfPad];
+  __bf16 b[4][kMT][kKC + kBfPad];
+};
+union MfmaSmem {
+  MfmaSmemF32 f;
+  MfmaSmemBF h;
+};
+
+struct CAcc {
+  f32x16 re, im;
+};
+
+LRSTV_DEV bf16x8 bf_neg(bf16x8 x) {
+  union {
+    bf16x8 v;
+    uint32_t u[4];
+  } t;
+  t.v = x;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) t.u[i] ^= 0x80008000u;
+  return t.v;
+}
+
+// Thread t stages 8 consecutive k of one row (m for A, n for B).  When k is
+// the contiguous memory index (KFAST) a row's 32 k are split over 4 lanes;
+// otherwise lanes run along the row index so each load is coalesced.
+template <bool KFAST>
+LRSTV_DEV void stage_coords(int t, int& row, int& k0) {
+  if (KFAST) {
+    row = t >> 2;
+    k0 = 8 * (t & 3);
+  } else {
+    row = t & 63;
+    k0 = 8 * (t >> 6);
+  }
+}
+
+template <int MODE>
+LRSTV_DEV void stage_store(MfmaSmem& sm, bool isA, int row, int k0, const float2 (&v)[8]) {
+  if (MODE == kF32) {
+    float(*pr)[kMT + 1] = isA ? sm.f.ar : sm.f.br;
+    float(*pi)[kMT + 1] = isA ? sm.f.ai : sm.f.bi;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      pr[k0 + j][row] = v[j].x;
+      pi[k0 + j][row] = v[j].y;
+    }
+  } else {
+    bf16x8 rh, rl, ih, il;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const __bf16 a = (__bf16)v[j].x, b = (__bf16)v[j].y;
+      rh[j] = a;
+      rl[j] = (__bf16)(v[j].x - (float)a);
+      ih[j] = b;
+      il[j] = (__bf16)(v[j].y - (float)b);
+    }
+    __bf16(*p)[kMT][kKC + kBfPad] = isA ? sm.h.a : sm.h.b;
+    *(bf16x8*)&p[0][row][k0] = rh;
+    *(bf16x8*)&p[1][row][k0] = rl;
+    *(bf16x8*)&p[2][row][k0] = ih;
+    *(bf16x8*)&p[3][row][k0] = il;
+  }
+}
+
+template <int MODE>
+LRSTV_DEV void chunk_mma(const MfmaSmem& sm, int wy, int wx, int lane, bool active, CAcc& c) {
+  if (!active) return;
+  const int li = lane & 31, lk = lane >> 5;
+  if (MODE == kF32) {
+#pragma unroll 4
+    for (int kk = 0; kk < kKC / 2; ++kk) {
+      const int k = 2 * kk + lk;
+      const float ar = sm.f.ar[k][32 * wy + li], ai = sm.f.ai[k][32 * wy + li];
+      const float br = sm.f.br[k][32 * wx + li], bi = sm.f.bi[k][32 * wx + li];
+      c.re = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, c.re, 0, 0, 0);
+      c.re = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bi, c.re, 0, 0, 0);
+      c.im = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, c.im, 0, 0, 0);
+      c.im = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, c.im, 0, 0, 0);
+    }
+  } else {
+#pragma unroll
+    for (int ks = 0; ks < kKC / 16; ++ks) {
+      const int ko = 16 * ks + 8 * lk;
+      const int ra = 32 * wy + li, rb = 32 * wx + li;
+      const bf16x8 arh = *(const bf16x8*)&sm.h.a[0][ra][ko], arl = *(const bf16x8*)&sm.h.a[1][ra][ko];
+      const bf16x8 aih = *(const bf16x8*)&sm.h.a[2][ra][ko], ail = *(const bf16x8*)&sm.h.a[3][ra][ko];
+      const bf16x8 brh = *(const bf16x8*)&sm.h.b[0][rb][ko], brl = *(const bf16x8*)&sm.h.b[1][rb][ko];
+      const bf16x8 bih = *(const bf16x8*)&sm.h.b[2][rb][ko], bil = *(const bf16x8*)&sm.h.b[3][rb][ko];
+      const bf16x8 naih = bf_neg(aih), nail = bf_neg(ail);
+      // small terms first, then the hi*hi term
+      c.re = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, brl, c.re, 0, 0, 0);
+      c.re = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, brh, c.re, 0, 0, 0);
+      c.re = __builtin_amdgcn_mfma_f32_32x32x16_bf16(naih, bil, c.re, 0, 0, 0);
+      c.re = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nail, bih, c.re, 0, 0, 0);
+      c.re = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, brh, c.re, 0, 0, 0);
+      c.re = __builtin_amdgcn_mfma_f32_32x32x16_bf16(naih, bih, c.re, 0, 0, 0);
+      c.im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bil, c.im, 0, 0, 0);
+      c.im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, bih, c.im, 0, 0, 0);
+      c.im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, brl, c.im, 0, 0, 0);
+      c.im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail, brh, c.im, 0, 0, 0);
+      c.im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bih, c.im, 0, 0, 0);
+      c.im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, brh, c.im, 0, 0, 0);
+    }
+  }
+}
+
+// C(m0 .. m0+63, n0 .. n0+63) = sum_{k < K} fa(m, k) fb(k, n).
+// AK / BK: k is the contiguous memory index of A / B (selects the staging
+// order).  `active` (wave-uniform) skips the products of a wave whose
+// sub-tile is not needed; every wave still takes part in staging.
+// The result is handed to st(row, col, float2) for rows and columns of the
+// wave's sub-tile.
+template <int MODE, bool AK, bool BK, class FA, class FB, class ST>
+LRSTV_DEV void mfma_ctile(int m0, int n0, int K, FA fa, FB fb, ST st, MfmaSmem& sm, bool active) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, wy = wv >> 1, wx = wv & 1;
+  int ra, ka, rb, kb;
+  stage_coords<AK>(t, ra, ka);
+  stage_coords<BK>(t, rb, kb);
+  CAcc c;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) c.re[i] = c.im[i] = 0.f;
+  float2 va[8], vb[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    va[j] = fa(m0 + ra, ka + j);
+    vb[j] = fb(kb + j, n0 + rb);
+  }
+  for (int k0 = 0; k0 < K; k0 += kKC) {
+    stage_store<MODE>(sm, true, ra, ka, va);
+    stage_store<MODE>(sm, false, rb, kb, vb);
+    __syncthreads();
+    if (k0 + kKC < K) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        va[j] = fa(m0 + ra, k0 + kKC + ka + j);
+        vb[j] = fb(k0 + kKC + kb + j, n0 + rb);
+      }
+    }
+    chunk_mma<MODE>(sm, wy, wx, lane, active, c);
+    __syncthreads();
+  }
+  if (!active) return;
+  const int col = n0 + 32 * wx + (lane & 31);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = m0 + 32 * wy + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    st(row, col, make_float2(c.re[r], c.im[r]));
+  }
+}
+
+}  // namespace lrstv

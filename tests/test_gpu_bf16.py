@@ -1,0 +1,134 @@
+"""GPU parity of the split-BF16 (3-term) product variant against the FP64 oracle.
+
+The Gram and both back-projection products run as hi*hi + hi*lo + lo*hi
+BF16 MFMA terms with FP32 accumulation.  Each FP32 operand keeps 16
+significant bits (hi and lo are each rounded to nearest), so a product
+carries a relative error of at most about 3 * 2^-17 = 2.3e-5 before
+accumulation, against 2^-24 for FP32.  Tolerances (relative Frobenius):
+  * BF16_SVT_TOL = 2.5e-4 for one t-SVT: the Gram error is bounded by that
+    product error times ||M||^2 (a 10x margin over 2.3e-5) and the bar stays
+    at half of the 5e-4 full-run tolerance;
+  * 5e-4 and |dMPSNR| <= 0.01 dB for X after a full run (the spec bar
+    for split-BF16).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+BF16_SVT_TOL = 2.5e-4
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2204_12879_amd as L
+    L.load_library()
+    return L
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _lowrank_tensor(shape, rank, seed):
+    b, h, w = shape
+    g = np.random.default_rng(seed)
+    A = np.einsum("rb,rh,rw->bhw", g.standard_normal((rank, b)), g.standard_normal((rank, h)),
+                  g.standard_normal((rank, w)))
+    return (A + 0.3 * g.standard_normal(shape)).astype(np.float32)
+
+
+def _slice_sv(A):
+    Ah = np.fft.fft(A.astype(np.float64), axis=0)
+    return np.concatenate([np.linalg.svd(Ah[k], compute_uv=False) for k in range(A.shape[0] // 2 + 1)])
+
+
+@pytest.mark.parametrize("shape", [(16, 32, 32), (9, 17, 12), (8, 12, 17), (6, 33, 40), (31, 48, 64),
+                                   (3, 200, 210), (3, 256, 256), (2, 81, 79)])
+def test_bf16_svt_matches_oracle(shape):
+    L = _lib()
+    A = _lowrank_tensor(shape, rank=4, seed=shape[1] * 5 + shape[2])
+    sv = _slice_sv(A)
+    for q in (0.0, 0.3, 0.7, 0.95):
+        t = float(np.quantile(sv, q)) if q > 0 else 0.0
+        E = L.svt(torch.from_numpy(A).cuda(), t, precision=L.LRSTV_SPLIT_BF16)
+        torch.cuda.synchronize()
+        ref = oracle.tsvt(A.astype(np.float64), t)
+        err = rel(E.cpu().numpy(), ref)
+        say("bf16 svt", shape, f"t = {t:.4g} rel err {err:.2e}")
+        assert err < BF16_SVT_TOL, (q, err)
+
+
+def test_bf16_differs_from_fp32_and_is_closer_than_bf16_rounding():
+    """The split path is really in use (its result is not the FP32 one) and is
+    far more accurate than a single BF16 term would be (2^-9 = 2e-3)."""
+    L = _lib()
+    A = _lowrank_tensor((9, 96, 80), rank=4, seed=3)
+    t = float(np.quantile(_slice_sv(A), 0.5))
+    Ag = torch.from_numpy(A).cuda()
+    e32 = L.svt(Ag, t, precision=L.LRSTV_FP32).cpu().numpy()
+    e16 = L.svt(Ag, t, precision=L.LRSTV_SPLIT_BF16).cpu().numpy()
+    ref = oracle.tsvt(A.astype(np.float64), t)
+    d = rel(e16, e32.astype(np.float64))
+    say(f"bf16 vs fp32 {d:.2e}; bf16 vs oracle {rel(e16, ref):.2e}; fp32 vs oracle {rel(e32, ref):.2e}")
+    assert d > 0.0
+    assert rel(e16, ref) < 2e-4
+
+
+def test_bf16_small_cube_full_run_matches_oracle():
+    L = _lib()
+    wl = synth.workload("small")
+    spec = wl.cubes[0]
+    clean, noisy = synth.make_cube(spec)
+    O = noisy.astype(np.float32).astype(np.float64)
+    p = oracle.default_params(spec.h, spec.w, tau=0.02, alpha=0.3)
+    solver = L.Solver([noisy.shape], L.Params(tau=p.tau, alpha=p.alpha, lam=p.lam, w=p.w, mu0=p.mu0, rho=p.rho,
+                                              mu_max=p.mu_max, precision=L.LRSTV_SPLIT_BF16))
+    Y = torch.from_numpy(noisy.astype(np.float32)).cuda().reshape(-1)
+    X = torch.empty_like(Y)
+    solver.solve(Y, X=X, max_iter=wl.iters)
+    torch.cuda.synchronize()
+    Xr, _, _, _ = oracle.admm(O, p, wl.iters)
+    Xg = X.cpu().numpy().reshape(Xr.shape)
+    err = rel(Xg, Xr)
+    dpsnr = abs(oracle.mpsnr(Xg, clean) - oracle.mpsnr(Xr, clean))
+    say(f"bf16 small: rel err {err:.3e}, dMPSNR {dpsnr:.2e} dB")
+    assert err <= 5e-4 and dpsnr <= 0.01
+
+
+@pytest.mark.parametrize("name", ["wdc"])
+def test_bf16_full_size_run_matches_stored_oracle_samples(name):
+    """256x256x191, 50 iterations in split-BF16: X at the stored oracle voxels
+    within 5e-4 relative and |dMPSNR| <= 0.01 dB."""
+    L = _lib()
+    gold = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                f"{name}_k50_oracle_samples.npz"))
+    wl = synth.workload(name)
+    spec = wl.cubes[0]
+    clean, noisy = synth.make_cube(spec)
+    p = oracle.default_params(spec.h, spec.w, tau=0.02, alpha=0.3)
+    solver = L.Solver([(spec.b, spec.h, spec.w)], L.Params(tau=p.tau, alpha=p.alpha, lam=p.lam,
+                                                           precision=L.LRSTV_SPLIT_BF16))
+    Y = torch.from_numpy(noisy.astype(np.float32)).cuda().reshape(-1)
+    solver.set_graph(True)
+    solver.reset(Y)
+    solver.iterate(wl.iters)
+    X = torch.empty_like(Y)
+    solver.read_output(X=X)
+    torch.cuda.synchronize()
+    Xg = X.cpu().numpy().astype(np.float64)
+    err = rel(Xg[gold["index"]], gold["values"])
+    dpsnr = abs(oracle.mpsnr(Xg.reshape(clean.shape), clean) - float(gold["mpsnr"]))
+    say(f"bf16 {name}: sampled rel err {err:.3e}, dMPSNR {dpsnr:.2e} dB")
+    assert err <= 5e-4 and dpsnr <= 0.01
