@@ -158,7 +158,53 @@ int lrstv_get_state(lrstv_handle hd, lrstv_state_view* view);
  * Asynchronous on the handle's stream. */
 int lrstv_set_state(lrstv_handle hd, const lrstv_state_view* src);
 
+/* Copy the handle's state into dst (every member but X, Y and mu required;
+ * those three are copied when non-NULL).  For per-iteration checkpoints
+ * of the adjoint.  Asynchronous on the handle's stream. */
+int lrstv_save_state(lrstv_handle hd, const lrstv_state_view* dst);
+
 void lrstv_destroy(lrstv_handle hd);
+
+/* ---- adjoint of the iteration ------------------------------------------ */
+
+/* Bytes of the extra device workspace lrstv_iterate_vjp needs for this
+ * handle's batch (direction slices and their SVT-derivative products, and
+ * cube-sized cotangent scratch). */
+int lrstv_vjp_workspace_size(lrstv_handle hd, size_t* bytes);
+
+/* Vector-Jacobian product of one iteration of Algorithm 1 (Sec. III-C),
+ * the map (state before, O, tau, alpha, lambda) -> (state after, X = L of
+ * this iteration), taken in reverse with the chain rule:
+ *   soft-threshold R_d(u): mask 1[|u| > d], d-cotangent -sign(u) 1[|u| > d]
+ *     (masks and signs read from the iteration's outputs S', F');
+ *   t-SVT: symmetric Jacobian (prox of a convex function), so the input
+ *     cotangent is the derivative along the output cotangent, computed per
+ *     Fourier slice from the Gram eigendecomposition by the Daleckii-Krein
+ *     rule; threshold cotangent -sum_{s > t} Re<D v, M v>/s per slice;
+ *   Z-update: the solve operator mu (I + D_w^* D_w) is symmetric, so its
+ *     VJP is the same FFT solve; D_w's VJP is D_w^*.
+ * before: state the iteration started from (G4 and mu required: mu is the
+ *   device scalar the iteration used); its Y is not read.
+ * after: state the iteration produced (S and F required).
+ * grad_after: cotangents of the state after (every member but X, Y, mu),
+ *   or NULL for zero.  grad_X: cotangent of X = L of this iteration, or
+ *   NULL for zero.
+ * grad_before (written): cotangents of the state before.  Must not alias
+ *   grad_after or the states.
+ * grad_weights (device, [n_cubes][3] doubles, accumulated): cotangents of
+ *   (tau, alpha, lambda) per cube.  grad_Y (device floats, packed batch,
+ *   accumulated): cotangent of O.
+ * flags: LRSTV_VJP_INITIAL when `before` is the initial state of a reset
+ *   (Z = O), so that the cotangent of Z also flows into grad_Y; else 0.
+ * ws: device workspace of lrstv_vjp_workspace_size bytes, 256-byte aligned.
+ * The solver's slice scratch is reused; the solver state is not touched.
+ * FP32 arithmetic with FP64 parameter sums.  Asynchronous on the handle's
+ * stream.  Errors: INVALID_ARG, WORKSPACE, HIP. */
+#define LRSTV_VJP_INITIAL 1
+int lrstv_iterate_vjp(lrstv_handle hd, const lrstv_state_view* before, const lrstv_state_view* after,
+                      const lrstv_state_view* grad_after, const float* grad_X,
+                      lrstv_state_view* grad_before, double* grad_weights, float* grad_Y,
+                      int32_t flags, void* ws, size_t ws_bytes);
 
 /* ---- standalone primitives --------------------------------------------- */
 
@@ -175,6 +221,20 @@ int lrstv_svt_workspace_size(int32_t h, int32_t w, int32_t b, int32_t batch, int
  * HIP. */
 int lrstv_svt(const float* A, float* E, int32_t h, int32_t w, int32_t b, int32_t batch,
               float thresh, int32_t precision, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for lrstv_svt_vjp on `batch` tensors of shape (b, h, w). */
+int lrstv_svt_vjp_workspace_size(int32_t h, int32_t w, int32_t b, int32_t batch, size_t* bytes);
+
+/* Vector-Jacobian product of the t-SVT (the derivative of lrstv_svt): for
+ * each of `batch` tensors, gA = J(A)^T G = J(A) G (the Jacobian of a prox
+ * map is symmetric) and, when grad_thresh (device, [batch] doubles,
+ * overwritten) is non-NULL, d<E, G>/d thresh.  A, G, gA device, packed
+ * [batch][b][h][w]; gA may not alias A or G.  FP32 products with a full
+ * FP64 eigendecomposition of each slice Gram.  Synchronises the stream
+ * before returning.  Errors: INVALID_ARG, WORKSPACE, UNSUPPORTED, HIP. */
+int lrstv_svt_vjp(const float* A, const float* G, float* gA, int32_t h, int32_t w, int32_t b,
+                  int32_t batch, float thresh, double* grad_thresh, void* ws, size_t ws_bytes,
+                  void* stream);
 
 /* Workspace bytes for lrstv_zsolve on one (b, h, w) cube. */
 int lrstv_zsolve_workspace_size(int32_t h, int32_t w, int32_t b, size_t* bytes);

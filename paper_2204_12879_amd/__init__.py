@@ -7,7 +7,9 @@ provides device memory and streams.  There is no CPU fallback: if the
 shared library is missing, importing the binding's entry points raises.
 """
 from ._lib import (LRSTV_FP32, LRSTV_SPLIT_BF16, LRSTV_NRES, RESIDUAL_NAMES, LrstvError, Params, Solver,
-                   library_path, load_library, svt, svt_workspace_bytes, zsolve)
+                   StateBuffer, library_path, load_library, lrstv_unrolled, svt, svt_vjp, svt_workspace_bytes,
+                   unrolled_class, zsolve)
 
 __all__ = ["LRSTV_FP32", "LRSTV_SPLIT_BF16", "LRSTV_NRES", "RESIDUAL_NAMES", "LrstvError", "Params", "Solver",
-           "library_path", "load_library", "svt", "svt_workspace_bytes", "zsolve"]
+           "StateBuffer", "library_path", "load_library", "lrstv_unrolled", "svt", "svt_vjp", "svt_workspace_bytes",
+           "unrolled_class", "zsolve"]

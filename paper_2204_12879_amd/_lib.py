@@ -12,6 +12,7 @@ _LIB_NAME = "liblrstv.so"
 LRSTV_FP32 = 0
 LRSTV_SPLIT_BF16 = 1
 LRSTV_NRES = 7
+LRSTV_VJP_INITIAL = 1
 RESIDUAL_NAMES = ("inf_OLS", "inf_LZ", "fro_OLS", "fro_LZ", "fro_DZF", "fro_EF", "dual_Z")
 WARN_NOT_CONVERGED = 1
 NSTAGES = 16
@@ -82,6 +83,12 @@ def load_library():
         "lrstv_status_string": (C.c_char_p, [C.c_int]),
         "lrstv_last_error": (C.c_char_p, []),
         "lrstv_version": (C.c_int, []),
+        "lrstv_save_state": (C.c_int, [vp, C.POINTER(_StateView)]),
+        "lrstv_vjp_workspace_size": (C.c_int, [vp, sz]),
+        "lrstv_iterate_vjp": (C.c_int, [vp, C.POINTER(_StateView), C.POINTER(_StateView), C.POINTER(_StateView), vp,
+                                        C.POINTER(_StateView), vp, vp, i32, vp, C.c_size_t]),
+        "lrstv_svt_vjp_workspace_size": (C.c_int, [i32, i32, i32, i32, sz]),
+        "lrstv_svt_vjp": (C.c_int, [vp, vp, vp, i32, i32, i32, i32, f32, vp, vp, C.c_size_t, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -135,6 +142,43 @@ def _problem(shapes: Sequence[Tuple[int, int, int]]):
     ws = (C.c_int32 * n)(*[s[2] for s in shapes])
     bs = (C.c_int32 * n)(*[s[0] for s in shapes])
     return _Problem(n, hs, ws, bs), (hs, ws, bs)
+
+
+# Order of the state variables inside a packed state buffer (16 * total floats).
+_PACK = (("Z", 1), ("S", 1), ("G1", 1), ("G2", 1), ("F", 3), ("E", 3), ("G3", 3), ("G4", 3))
+
+
+class StateBuffer:
+    """A packed copy of the iteration state (Z, S, Gamma1, Gamma2, F, E,
+    Gamma3, Gamma4 back to back, 16 * total float32) and its mu (float64):
+    the per-iteration checkpoint and cotangent layout of the adjoint."""
+
+    def __init__(self, total: int, data=None, mu=None, device="cuda"):
+        import torch
+        self.total = int(total)
+        self.data = torch.zeros(16 * self.total, dtype=torch.float32, device=device) if data is None else data
+        self.mu = torch.zeros(1, dtype=torch.float64, device=device) if mu is None else mu
+
+    def part(self, name: str):
+        o = 0
+        for n, k in _PACK:
+            if n == name:
+                return self.data[o * self.total:(o + k) * self.total]
+            o += k
+        raise KeyError(name)
+
+    def view(self, with_mu: bool = True) -> "_StateView":
+        v = _StateView()
+        base = self.data.data_ptr()
+        o = 0
+        for n, k in _PACK:
+            setattr(v, n, base + 4 * o * self.total)
+            o += k
+        v.X = None
+        v.Y = None
+        v.mu = self.mu.data_ptr() if with_mu else None
+        v.total = self.total
+        return v
 
 
 class Solver:
@@ -245,6 +289,36 @@ class Solver:
         out["mu"] = self._view(v.mu, 1, torch.float64)
         return out
 
+    def save_state(self, buf: "StateBuffer") -> None:
+        """Copy the current state (and mu) into a StateBuffer (library copy kernels)."""
+        v = buf.view()
+        _check(self.lib.lrstv_save_state(self.handle, C.byref(v)))
+
+    def vjp_workspace(self):
+        """Device workspace of the adjoint (allocated once per solver)."""
+        import torch
+        if getattr(self, "_vjp_ws", None) is None:
+            n = C.c_size_t(0)
+            _check(self.lib.lrstv_vjp_workspace_size(self.handle, C.byref(n)))
+            self._vjp_bytes = int(n.value)
+            self._vjp_ws = torch.empty(self._vjp_bytes + 256, dtype=torch.uint8, device="cuda")
+        base = self._vjp_ws.data_ptr()
+        return base + ((-base) % 256), self._vjp_bytes
+
+    def iterate_vjp(self, before: "StateBuffer", after: "StateBuffer", grad_after, grad_X,
+                    grad_before: "StateBuffer", grad_weights, grad_Y, initial: bool = False) -> None:
+        """Adjoint of one iteration (lrstv_iterate_vjp): writes grad_before and
+        accumulates grad_weights ([n_cubes, 3] float64: tau, alpha, lambda) and
+        grad_Y.  grad_after (StateBuffer) and grad_X may be None (zero)."""
+        ws, nb = self.vjp_workspace()
+        vb, va, vgb = before.view(), after.view(), grad_before.view(with_mu=False)
+        vga = grad_after.view(with_mu=False) if grad_after is not None else None
+        _check(self.lib.lrstv_iterate_vjp(self.handle, C.byref(vb), C.byref(va),
+                                          C.byref(vga) if vga is not None else None,
+                                          C.c_void_p(_ptr(grad_X)) if grad_X is not None else None,
+                                          C.byref(vgb), C.c_void_p(_ptr(grad_weights)), C.c_void_p(_ptr(grad_Y)),
+                                          LRSTV_VJP_INITIAL if initial else 0, C.c_void_p(ws), C.c_size_t(nb)))
+
     def set_state(self, st: dict) -> None:
         """Copy tensors (same packed layout as state()) into the handle."""
         v = _StateView()
@@ -294,3 +368,103 @@ def zsolve(T, mu: float, wts=(1.0, 1.0, 1.0), out=None, stream=None):
     _check(lib.lrstv_zsolve(C.c_void_p(_ptr(T)), C.c_void_p(_ptr(Z)), h, w, b, float(mu), wv,
                             C.c_void_p(ws.data_ptr()), C.c_size_t(int(n.value)), C.c_void_p(_stream(stream))))
     return Z
+
+
+def svt_vjp(A, G, thresh: float, stream=None):
+    """VJP of the t-SVT at A along the output cotangent G (both (b, h, w) or
+    (batch, b, h, w) float32 CUDA tensors).  Returns (gA, g_thresh) with
+    g_thresh a float64 tensor [batch]."""
+    import torch
+    lib = load_library()
+    squeeze = A.dim() == 3
+    A4 = (A.unsqueeze(0) if squeeze else A).contiguous()
+    G4 = (G.unsqueeze(0) if squeeze else G).contiguous()
+    batch, b, h, w = A4.shape
+    if tuple(G4.shape) != tuple(A4.shape):
+        raise ValueError("A and G must have the same shape")
+    gA = torch.empty_like(A4)
+    gt = torch.empty(batch, dtype=torch.float64, device=A.device)
+    n = C.c_size_t(0)
+    _check(lib.lrstv_svt_vjp_workspace_size(h, w, b, batch, C.byref(n)))
+    nb = int(n.value)
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device=A.device)
+    base = ws.data_ptr() + ((-ws.data_ptr()) % 256)
+    _check(lib.lrstv_svt_vjp(C.c_void_p(_ptr(A4)), C.c_void_p(_ptr(G4)), C.c_void_p(_ptr(gA)), h, w, b, batch,
+                             float(thresh), C.c_void_p(_ptr(gt)), C.c_void_p(base), C.c_size_t(nb),
+                             C.c_void_p(_stream(stream))))
+    return (gA[0] if squeeze else gA), gt
+
+
+def _make_unrolled():
+    import torch
+
+    class LRSTVUnrolled(torch.autograd.Function):
+        """K unrolled ADMM iterations X = L^(K)(Y; tau, alpha, lambda) with a
+        backward pass through the library's adjoint (lrstv_iterate_vjp).
+
+        apply(Y, tau, alpha, lam, shapes, K, w=(1, 1, 1), mu0=1e-2, rho=1.5,
+        mu_max=1e6): Y is the packed batch (flat float32 CUDA tensor), tau,
+        alpha, lam scalar tensors shared by the cubes; K and the penalty
+        schedule are constants.  The forward keeps the K+1 iteration states
+        (16 cubes each) as checkpoints; the backward walks them in reverse.
+        """
+
+        @staticmethod
+        def forward(ctx, Y, tau, alpha, lam, shapes, K, w=(1.0, 1.0, 1.0), mu0=1e-2, rho=1.5, mu_max=1e6):
+            K = int(K)
+            if K < 1:
+                raise ValueError("K must be >= 1")
+            p = Params(tau=float(tau), alpha=float(alpha), lam=float(lam), w=tuple(w), mu0=mu0, rho=rho,
+                       mu_max=mu_max)
+            solver = Solver(shapes, p)
+            Yc = Y.detach().contiguous()
+            solver.reset(Yc)
+            T = solver.total
+            ckpt = [StateBuffer(T) for _ in range(K + 1)]
+            for k in range(K):
+                solver.save_state(ckpt[k])
+                solver.iterate(1)
+            solver.save_state(ckpt[K])
+            X = torch.empty_like(Yc)
+            solver.read_output(X=X)
+            ctx.solver, ctx.ckpt, ctx.K = solver, ckpt, K
+            ctx.dtypes = (tau.dtype if torch.is_tensor(tau) else torch.float64,
+                          alpha.dtype if torch.is_tensor(alpha) else torch.float64,
+                          lam.dtype if torch.is_tensor(lam) else torch.float64)
+            return X
+
+        @staticmethod
+        def backward(ctx, gX):
+            solver, ckpt, K = ctx.solver, ctx.ckpt, ctx.K
+            T = solver.total
+            nc = len(solver.shapes)
+            gX = gX.detach().contiguous().float()
+            gw = torch.zeros(nc, 3, dtype=torch.float64, device=gX.device)
+            gY = torch.zeros(T, dtype=torch.float32, device=gX.device)
+            cur, nxt = StateBuffer(T), StateBuffer(T)
+            for k in reversed(range(K)):
+                solver.iterate_vjp(ckpt[k], ckpt[k + 1], cur if k < K - 1 else None, gX if k == K - 1 else None,
+                                   nxt, gw, gY, initial=(k == 0))
+                cur, nxt = nxt, cur
+            tot = gw.cpu().sum(dim=0).tolist()
+            dev = gX.device
+            g = [torch.tensor(tot[i], dtype=ctx.dtypes[i], device=dev) for i in range(3)]
+            return (gY, g[0], g[1], g[2]) + (None,) * 6
+
+    return LRSTVUnrolled
+
+
+_unrolled_cls = None
+
+
+def unrolled_class():
+    global _unrolled_cls
+    if _unrolled_cls is None:
+        _unrolled_cls = _make_unrolled()
+    return _unrolled_cls
+
+
+def lrstv_unrolled(Y, tau, alpha, lam, shapes, K, **schedule):
+    """Differentiable X = L^(K) of K ADMM iterations (see LRSTVUnrolled)."""
+    return unrolled_class().apply(Y, tau, alpha, lam, shapes, K, schedule.get("w", (1.0, 1.0, 1.0)),
+                                  schedule.get("mu0", 1e-2), schedule.get("rho", 1.5), schedule.get("mu_max", 1e6))

@@ -84,6 +84,7 @@ SliceLayout make_slices(std::vector<CubeInfo>& cubes, int nt) {
         d.m1 = m1;
         d.tall = h >= w;
         d.cube = (int)c;
+        d.fw = (float)((k == 0 || 2 * k == ci.b) ? 1 : 2) / (float)ci.b;
         d.a_off = L.slices_floats + ((int64_t)t * s + k) * 2 * hw;
         d.g_off = L.gram_c;
         d.v_off = L.v_floats;
@@ -123,6 +124,8 @@ struct lrstv_handle_s {
   int *rcount, *flag;
   SliceDesc* desc;
   StageTimer timer;
+  // per-cube index ranges of the per-column t-SVT threshold terms (adjoint)
+  std::vector<int64_t> acon_range;
   // hipGraph replay of one iteration (lrstv_set_graph)
   bool graph_on = false;
   hipGraph_t graph = nullptr;
@@ -536,6 +539,200 @@ extern "C" int lrstv_set_state(lrstv_handle H, const lrstv_state_view* v) {
   return LRSTV_OK;
 }
 
+// ------------------------------------------------------------ adjoint ---
+namespace {
+struct VjpWs {
+  float *dsl, *C, *R, *W, *sig, *ones, *gL, *gZp, *gFp, *dirE, *gA, *gT;
+  double *acon, *part;
+  int64_t* range;
+};
+void carve_vjp(const SliceLayout& L, int64_t total, int64_t nmax, int nc, void* base, VjpWs* w, size_t* used) {
+  Carve cv(base);
+  w->dsl = cv.take<float>(L.slices_floats);
+  w->C = cv.take<float>(L.b_floats);
+  w->R = cv.take<float>(L.b_floats);
+  w->W = cv.take<float>(L.v_floats);
+  w->sig = cv.take<float>(L.f_floats);
+  w->ones = cv.take<float>(L.f_floats);
+  w->acon = cv.take<double>(L.f_floats);
+  w->gL = cv.take<float>(total);
+  w->gZp = cv.take<float>(total);
+  w->gFp = cv.take<float>(3 * total);
+  w->dirE = cv.take<float>(3 * nmax);
+  w->gA = cv.take<float>(3 * nmax);
+  w->gT = cv.take<float>(nmax);
+  w->part = cv.take<double>((int64_t)nc * 2 * LRSTV_PARTS);
+  w->range = cv.take<int64_t>(2 * (int64_t)nc);
+  *used = cv.off + 256;
+}
+// per cube (or batch element) [first, last) of its slices' columns in the
+// fval-shaped arrays
+std::vector<int64_t> column_ranges(const SliceLayout& L, int nc) {
+  std::vector<int64_t> r(2 * (size_t)nc, 0);
+  std::vector<bool> seen(nc, false);
+  for (const SliceDesc& d : L.desc) {
+    const int64_t a = d.f_off, b = d.f_off + d.n1;
+    if (!seen[d.cube]) { r[2 * d.cube] = a; r[2 * d.cube + 1] = b; seen[d.cube] = true; }
+    else { if (a < r[2 * d.cube]) r[2 * d.cube] = a; if (b > r[2 * d.cube + 1]) r[2 * d.cube + 1] = b; }
+  }
+  return r;
+}
+}  // namespace
+
+extern "C" int lrstv_vjp_workspace_size(lrstv_handle H, size_t* bytes) {
+  if (!H || !bytes) return fail(LRSTV_ERR_INVALID_ARG, "handle or bytes is NULL");
+  VjpWs w;
+  carve_vjp(H->sl, H->total, H->nmax, (int)H->cubes.size(), nullptr, &w, bytes);
+  return LRSTV_OK;
+}
+
+static bool full_view(const lrstv_state_view* v) {
+  return v && v->Z && v->S && v->F && v->E && v->G1 && v->G2 && v->G3 && v->G4;
+}
+
+extern "C" int lrstv_iterate_vjp(lrstv_handle H, const lrstv_state_view* before, const lrstv_state_view* after,
+                                 const lrstv_state_view* grad_after, const float* grad_X,
+                                 lrstv_state_view* grad_before, double* grad_weights, float* grad_Y,
+                                 int32_t flags, void* ws, size_t ws_bytes) {
+  if (!H) return fail(LRSTV_ERR_INVALID_ARG, "handle is NULL");
+  if (!before || !before->G4 || !before->mu) return fail(LRSTV_ERR_INVALID_ARG, "before needs G4 and mu");
+  if (!after || !after->S || !after->F) return fail(LRSTV_ERR_INVALID_ARG, "after needs S and F");
+  if (grad_after && !full_view(grad_after))
+    return fail(LRSTV_ERR_INVALID_ARG, "grad_after must be NULL or give every state member");
+  if (!full_view(grad_before)) return fail(LRSTV_ERR_INVALID_ARG, "grad_before must give every state member");
+  if (!grad_weights || !grad_Y || !ws) return fail(LRSTV_ERR_INVALID_ARG, "grad_weights, grad_Y, ws are required");
+  const lrstv_state_view* views[4] = {before, after, grad_after, grad_before};
+  for (const lrstv_state_view* v : views)
+    if (v && v->total != H->total)
+      return fail(LRSTV_ERR_INVALID_ARG, "state total %lld != %lld", (long long)v->total, (long long)H->total);
+  if (((uintptr_t)ws & 255) != 0) return fail(LRSTV_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (flags & ~LRSTV_VJP_INITIAL) return fail(LRSTV_ERR_INVALID_ARG, "unknown flags 0x%x", (unsigned)flags);
+  const int nc = (int)H->cubes.size();
+  size_t need = 0;
+  VjpWs w;
+  carve_vjp(H->sl, H->total, H->nmax, nc, nullptr, &w, &need);
+  if (ws_bytes < need) return fail(LRSTV_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  carve_vjp(H->sl, H->total, H->nmax, nc, ws, &w, &need);
+  hipStream_t s = H->stream;
+  const double* mu = before->mu;
+  const int64_t T = H->total;
+  if (H->acon_range.empty()) H->acon_range = column_ranges(H->sl, nc);
+  HIPCHK(hipMemcpyAsync(w.range, H->acon_range.data(), H->acon_range.size() * sizeof(int64_t),
+                        hipMemcpyHostToDevice, s));
+  launch_fill(w.ones, H->sl.f_floats, 1.f, s);
+  auto cube_view = [&](const CubeInfo& ci) {
+    VjpCube c;
+    const int64_t o = ci.off;
+    c.h = ci.h;
+    c.w = ci.w;
+    c.b = ci.b;
+    c.ts = T;
+    c.as = H->nmax;
+    c.G4 = before->G4 + o;
+    c.S1 = after->S + o;
+    c.F1 = after->F + o;
+    const bool ga = grad_after != nullptr;
+    c.gaZ = ga ? grad_after->Z + o : nullptr;
+    c.gaS = ga ? grad_after->S + o : nullptr;
+    c.gaF = ga ? grad_after->F + o : nullptr;
+    c.gaE = ga ? grad_after->E + o : nullptr;
+    c.gaG1 = ga ? grad_after->G1 + o : nullptr;
+    c.gaG2 = ga ? grad_after->G2 + o : nullptr;
+    c.gaG3 = ga ? grad_after->G3 + o : nullptr;
+    c.gaG4 = ga ? grad_after->G4 + o : nullptr;
+    c.gX = grad_X ? grad_X + o : nullptr;
+    c.gbZ = grad_before->Z + o;
+    c.gbS = grad_before->S + o;
+    c.gbF = grad_before->F + o;
+    c.gbE = grad_before->E + o;
+    c.gbG1 = grad_before->G1 + o;
+    c.gbG2 = grad_before->G2 + o;
+    c.gbG3 = grad_before->G3 + o;
+    c.gbG4 = grad_before->G4 + o;
+    c.gL = w.gL + o;
+    c.gZp = w.gZp + o;
+    c.gFp = w.gFp + o;
+    c.dirE = w.dirE;
+    c.A = H->A;
+    c.gY = grad_Y + o;
+    c.initial = (flags & LRSTV_VJP_INITIAL) != 0;
+    return c;
+  };
+  // 6th and 5th steps; the t-SVT point and direction into Fourier slices
+  for (int c = 0; c < nc; ++c) {
+    const CubeInfo& ci = H->cubes[c];
+    VjpCube vc = cube_view(ci);
+    launch_vjp_post(vc, mu, w.part + (int64_t)c * 2 * LRSTV_PARTS + LRSTV_PARTS, s);
+    launch_band_dft(H->A, H->nmax, 3, H->slices + ci.slice_base, ci.h, ci.w, ci.b, s);
+    launch_band_dft(w.dirE, H->nmax, 3, w.dsl + ci.slice_base, ci.h, ci.w, ci.b, s);
+  }
+  // 4th step: derivative of every slice SVT along its direction
+  SvtVjpLaunch J;
+  J.fw.desc = H->desc;
+  J.fw.n_slices = (int)H->sl.desc.size();
+  J.fw.max_n1 = H->sl.max_n1;
+  J.fw.max_m1 = H->sl.max_m1;
+  J.fw.slices = H->slices;
+  J.fw.gram = H->gram;
+  J.fw.V = H->V;
+  J.fw.B = H->B;
+  J.fw.tri = H->tri;
+  J.fw.xs = H->xs;
+  J.fw.fval = H->fval;
+  J.fw.rcount = H->rcount;
+  J.fw.mu = mu;
+  J.fw.alpha = H->par.alpha;
+  J.fw.thresh = 0.f;
+  J.fw.precision = LRSTV_FP32;
+  J.dsl = w.dsl;
+  J.C = w.C;
+  J.R = w.R;
+  J.W = w.W;
+  J.sig = w.sig;
+  J.ones = w.ones;
+  J.acon = w.acon;
+  launch_svt_vjp(J, s);
+  // 3rd, 2nd and 1st steps per cube
+  for (int c = 0; c < nc; ++c) {
+    const CubeInfo& ci = H->cubes[c];
+    VjpCube vc = cube_view(ci);
+    launch_band_idft(w.dsl + ci.slice_base, 3, w.gA, H->nmax, ci.h, ci.w, ci.b, nullptr, nullptr, nullptr, nullptr,
+                     s);
+    launch_vjp_shrinkf(vc, w.gA, mu, w.part + (int64_t)c * 2 * LRSTV_PARTS, s);
+    launch_vjp_divt(vc, H->T, H->par.w, s);
+    launch_rfft_w(H->T, H->spec, ci.h, ci.w, ci.b, s);
+    launch_fft_h(H->spec, ci.h, ci.w, ci.b, -1, s);
+    launch_tri_b(H->spec, ci.h, ci.w, ci.b, H->par.w, mu, 0.0, s);
+    launch_fft_h(H->spec, ci.h, ci.w, ci.b, +1, s);
+    launch_irfft_w(H->spec, w.gT, ci.h, ci.w, ci.b, nullptr, s);
+    launch_vjp_pre(vc, w.gT, H->par.w, mu, s);
+  }
+  launch_vjp_finish(w.part, w.acon, w.range, nc, grad_weights, s);
+  HIPCHK(hipGetLastError());
+  return LRSTV_OK;
+}
+
+extern "C" int lrstv_save_state(lrstv_handle H, const lrstv_state_view* dst) {
+  if (!H || !full_view(dst)) return fail(LRSTV_ERR_INVALID_ARG, "handle or a destination member is NULL");
+  if (dst->total != H->total)
+    return fail(LRSTV_ERR_INVALID_ARG, "state total %lld != %lld", (long long)dst->total, (long long)H->total);
+  const int64_t T = H->total;
+  hipStream_t s = H->stream;
+  launch_copy(dst->Z, H->Z, T, s);
+  launch_copy(dst->S, H->S, T, s);
+  launch_copy(dst->G1, H->G1, T, s);
+  launch_copy(dst->G2, H->G2, T, s);
+  launch_copy(dst->F, H->F, 3 * T, s);
+  launch_copy(dst->E, H->E, 3 * T, s);
+  launch_copy(dst->G3, H->G3, 3 * T, s);
+  launch_copy(dst->G4, H->G4, 3 * T, s);
+  if (dst->X) launch_copy(dst->X, H->L, T, s);
+  if (dst->Y) launch_copy(dst->Y, H->O, T, s);
+  if (dst->mu) HIPCHK(hipMemcpyAsync(dst->mu, H->mu, sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipGetLastError());
+  return LRSTV_OK;
+}
+
 // --------------------------------------------------------- primitives ---
 
 namespace {
@@ -561,7 +758,7 @@ void carve_svt(const SliceLayout& L, void* base, SvtWs* w, size_t* used) {
 }
 }  // namespace
 
-__global__ void k_make_desc(SliceDesc* out, int n, const SliceDesc* proto_unused, int h, int w, int s,
+__global__ void k_make_desc(SliceDesc* out, int n, int b, int h, int w, int s,
                             int64_t gram_c, int64_t v_f, int64_t b_f, int64_t tri_d, int64_t xs_d, int64_t f_f) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -574,6 +771,10 @@ __global__ void k_make_desc(SliceDesc* out, int n, const SliceDesc* proto_unused
   d.m1 = m1;
   d.tall = h >= w;
   d.cube = i / s;
+  {
+    const int k = i % s;
+    d.fw = (float)((k == 0 || 2 * k == b) ? 1 : 2) / (float)b;
+  }
   d.a_off = (int64_t)i * 2 * hw;
   d.g_off = (int64_t)i * gram_c;
   d.v_off = (int64_t)i * v_f;
@@ -628,7 +829,7 @@ extern "C" int lrstv_svt(const float* A, float* E, int32_t h, int32_t w, int32_t
   const int n1 = h < w ? h : w;
   const int64_t hw = (int64_t)h * w;
   prepare_svt(n1);
-  hipLaunchKernelGGL(k_make_desc, dim3((ns + 255) / 256), dim3(256), 0, s, ws.desc, ns, nullptr, h, w, b / 2 + 1,
+  hipLaunchKernelGGL(k_make_desc, dim3((ns + 255) / 256), dim3(256), 0, s, ws.desc, ns, (int)b, h, w, b / 2 + 1,
                      (int64_t)n1 * (n1 + 1) / 2, 2 * (int64_t)n1 * n1, 2 * hw, 6 * (int64_t)n1, 3 * (int64_t)n1 * n1,
                      (int64_t)n1);
   launch_band_dft(A, (int64_t)b * hw, batch, ws.slices, h, w, b, s);
@@ -652,6 +853,85 @@ extern "C" int lrstv_svt(const float* A, float* E, int32_t h, int32_t w, int32_t
   launch_svt(sv, s);
   launch_band_idft(ws.slices, batch, E, (int64_t)b * hw, h, w, b, nullptr, nullptr, nullptr, nullptr, s);
   HIPCHK(hipGetLastError());
+  return LRSTV_OK;
+}
+
+extern "C" int lrstv_svt_vjp_workspace_size(int32_t h, int32_t w, int32_t b, int32_t batch, size_t* bytes) {
+  if (!bytes) return fail(LRSTV_ERR_INVALID_ARG, "bytes is NULL");
+  int rc = check_dims(h, w, b);
+  if (rc) return rc;
+  if (batch < 1) return fail(LRSTV_ERR_INVALID_ARG, "batch must be >= 1");
+  SliceLayout L = svt_layout(h, w, b, batch);
+  SvtWs sw;
+  size_t a = 0, c = 0;
+  carve_svt(L, nullptr, &sw, &a);
+  VjpWs vw;
+  carve_vjp(L, 0, 0, batch, nullptr, &vw, &c);
+  *bytes = a + c + 256;
+  return LRSTV_OK;
+}
+
+extern "C" int lrstv_svt_vjp(const float* A, const float* G, float* gA, int32_t h, int32_t w, int32_t b,
+                             int32_t batch, float thresh, double* grad_thresh, void* wsp, size_t ws_bytes,
+                             void* stream) {
+  size_t need = 0;
+  int rc = lrstv_svt_vjp_workspace_size(h, w, b, batch, &need);
+  if (rc) return rc;
+  if (!A || !G || !gA || !wsp) return fail(LRSTV_ERR_INVALID_ARG, "A, G, gA and the workspace must be non-NULL");
+  if (gA == A || gA == G) return fail(LRSTV_ERR_INVALID_ARG, "gA may not alias A or G");
+  if (!(thresh >= 0.f)) return fail(LRSTV_ERR_INVALID_ARG, "thresh must be >= 0");
+  if (ws_bytes < need) return fail(LRSTV_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  if (((uintptr_t)wsp & 255) != 0) return fail(LRSTV_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  SliceLayout L = svt_layout(h, w, b, batch);
+  SvtWs sw;
+  size_t a = 0, c = 0;
+  carve_svt(L, wsp, &sw, &a);
+  VjpWs vw;
+  void* vbase = (void*)(((uintptr_t)wsp + a + 255) & ~(uintptr_t)255);
+  carve_vjp(L, 0, 0, batch, vbase, &vw, &c);
+  const int ns = (int)L.desc.size();
+  const int n1 = h < w ? h : w;
+  const int64_t hw = (int64_t)h * w;
+  prepare_svt(n1);
+  hipLaunchKernelGGL(k_make_desc, dim3((ns + 255) / 256), dim3(256), 0, s, sw.desc, ns, (int)b, h, w, b / 2 + 1,
+                     (int64_t)n1 * (n1 + 1) / 2, 2 * (int64_t)n1 * n1, 2 * hw, 6 * (int64_t)n1, 3 * (int64_t)n1 * n1,
+                     (int64_t)n1);
+  std::vector<int64_t> range = column_ranges(L, batch);
+  HIPCHK(hipMemcpyAsync(vw.range, range.data(), range.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  launch_fill(vw.ones, L.f_floats, 1.f, s);
+  launch_band_dft(A, (int64_t)b * hw, batch, sw.slices, h, w, b, s);
+  launch_band_dft(G, (int64_t)b * hw, batch, vw.dsl, h, w, b, s);
+  SvtVjpLaunch J;
+  J.fw.desc = sw.desc;
+  J.fw.n_slices = ns;
+  J.fw.max_n1 = L.max_n1;
+  J.fw.max_m1 = L.max_m1;
+  J.fw.slices = sw.slices;
+  J.fw.gram = sw.gram;
+  J.fw.V = sw.V;
+  J.fw.B = sw.B;
+  J.fw.tri = sw.tri;
+  J.fw.xs = sw.xs;
+  J.fw.fval = sw.fval;
+  J.fw.rcount = sw.rcount;
+  J.fw.mu = nullptr;
+  J.fw.alpha = 0.0;
+  J.fw.thresh = thresh;
+  J.fw.precision = LRSTV_FP32;
+  J.dsl = vw.dsl;
+  J.C = vw.C;
+  J.R = vw.R;
+  J.W = vw.W;
+  J.sig = vw.sig;
+  J.ones = vw.ones;
+  J.acon = vw.acon;
+  launch_svt_vjp(J, s);
+  launch_band_idft(vw.dsl, batch, gA, (int64_t)b * hw, h, w, b, nullptr, nullptr, nullptr, nullptr, s);
+  if (grad_thresh) launch_sum_ranges(vw.acon, vw.range, batch, grad_thresh, s);
+  HIPCHK(hipGetLastError());
+  // the host range table must outlive the asynchronous copy
+  HIPCHK(hipStreamSynchronize(s));
   return LRSTV_OK;
 }
 

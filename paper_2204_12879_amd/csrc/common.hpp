@@ -91,6 +91,8 @@ struct SliceDesc {
   int n1, m1;        // min / max of (h, w)
   int tall;          // 1 if h >= w (Gram = M^H M), else Gram = M M^H
   int cube;          // owning cube
+  float fw;          // Fourier weight of the slice: (1 or 2) / b, 2 when the slice
+                     // stands for itself and its conjugate partner k' = b - k
   int64_t a_off;     // float offset of the re plane; im plane at a_off + h*w
   int64_t g_off;     // float2 offset of the packed lower Gram / reflector scratch
   int64_t v_off;     // float offset of V (planar, n1 x n1, re then im)

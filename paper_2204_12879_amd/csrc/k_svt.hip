@@ -686,7 +686,10 @@ __global__ void __launch_bounds__(1024) k_trieig(const SliceDesc* __restrict__ d
   const double tnorm = tnorm0 > 0.0 ? 1.0 : 0.0;
   const double pivmin = 1e-290;
   const double delta = 1e-6 * tnorm;                    // FP32 resolution of the Gram
-  const double lo_cut = fmax(t * t * sc - delta, 0.0);
+  // thresh < 0 without a device mu asks for every eigenpair (the t-SVT
+  // derivative needs the full spectrum)
+  const bool all = mu_dev == nullptr && thresh < 0.f;
+  const double lo_cut = all ? gl - 1.0 : fmax(t * t * sc - delta, 0.0);
   dg = ds;
   if (threadIdx.x == 0) {
     int nb = 0;
@@ -695,7 +698,7 @@ __global__ void __launch_bounds__(1024) k_trieig(const SliceDesc* __restrict__ d
       if (ee[i] == 0.0) bstart[nb++] = i + 1;
     bstart[nb] = n;
     s_nblk = nb;
-    s_c0 = (tnorm == 0.0) ? n : sturm_count(dg, e2, 0, n - 1, lo_cut, pivmin);
+    s_c0 = all ? 0 : (tnorm == 0.0) ? n : sturm_count(dg, e2, 0, n - 1, lo_cut, pivmin);
   }
   __syncthreads();
   const int c0 = s_c0, nblk = s_nblk, r = n - c0;
@@ -1058,6 +1061,207 @@ __global__ void __launch_bounds__(256) k_bp2(const SliceDesc* __restrict__ desc,
   }
 }
 
+// ------------------------------------------------ t-SVT derivative (JVP) ---
+// The t-SVT is the prox of a convex function, so its Jacobian is symmetric
+// and the cotangent of the input is the derivative along the output
+// cotangent.  With the Gram G = M^H M = V diag(lambda) V^H (tall slice),
+// SVT(M) = M g(G), g(lambda) = max(1 - t / sqrt(lambda), 0), and the
+// Daleckii-Krein rule for the derivative of a matrix function gives, for a
+// direction D with B = M V, C = D V:
+//   SVT'(M)[D] = (C diag(g) + B W) V^H,  W = g1 o (C^H B + B^H C),
+//   g1_ij = (g_i - g_j) / (lambda_i - lambda_j)   (g' on the diagonal):
+//     both sigma > t:  t / (s_i s_j (s_i + s_j));  one above: g / (s^2 - s'^2);
+//     none: 0.
+// Wide slices use G = M M^H = U diag(lambda) U^H, SVT(M) = g(G) M, with
+// B = U^H M, C = U^H D:  SVT'(M)[D] = U (diag(g) C + W B),
+// W = g1 o (C B^H + B C^H).  sigma_i = ||B e_i|| (the column or row norm of
+// B, taken from M like the forward pass).
+// The threshold derivative is dSVT/dt = -B diag(1[s > t] / s) V^H (or
+// -U diag(1[s > t] / s) B); its inner product with D is
+// -sum_{s_i > t} Re <c_i, b_i> / s_i, weighted by the slice's Fourier weight.
+
+LRSTV_DEV double g1_pair(double si, double sj, double t) {
+  const bool ai = si > t, aj = sj > t;
+  if (ai && aj) return t / (si * sj * (si + sj));
+  if (ai) return (1.0 - t / si) / ((si - sj) * (si + sj));
+  if (aj) return (1.0 - t / sj) / ((sj - si) * (sj + si));
+  return 0.0;
+}
+
+// Per column c of a slice: sigma_c, g_c and the threshold-derivative term
+// acon_c = -1[s > t] Re<c_c, b_c> / s * fw / mu  (d/d alpha of <E, D>).
+__global__ void __launch_bounds__(256) k_vjp_sigma(const SliceDesc* __restrict__ desc, const float* __restrict__ Bb,
+                                                   const float* __restrict__ Cb, float* __restrict__ sig,
+                                                   float* __restrict__ gval, double* __restrict__ acon,
+                                                   const int* __restrict__ rcount, const double* __restrict__ mu_dev,
+                                                   double alpha, float thresh) {
+  __shared__ double red[8];
+  const SliceDesc d = desc[blockIdx.y];
+  const int r = rcount[blockIdx.y], c = blockIdx.x, n = d.n1;
+  if (c >= n) return;
+  if (c >= r) {  // no eigenpair (zero slice): nothing flows through this column
+    if (threadIdx.x == 0) {
+      sig[d.f_off + c] = 0.f;
+      gval[d.f_off + c] = 0.f;
+      acon[d.f_off + c] = 0.0;
+    }
+    return;
+  }
+  const int h = d.h, w = d.w;
+  const float* br = Bb + d.b_off;
+  const float* bi = br + (int64_t)h * w;
+  const float* cr = Cb + d.b_off;
+  const float* ci = cr + (int64_t)h * w;
+  double s2 = 0.0, dt = 0.0;
+  if (d.tall) {
+    for (int i = threadIdx.x; i < h; i += blockDim.x) {
+      const int64_t q = (int64_t)i * n + c;
+      const double a = br[q], b = bi[q];
+      s2 += a * a + b * b;
+      dt += (double)cr[q] * a + (double)ci[q] * b;
+    }
+  } else {
+    for (int i = threadIdx.x; i < w; i += blockDim.x) {
+      const int64_t q = (int64_t)c * w + i;
+      const double a = br[q], b = bi[q];
+      s2 += a * a + b * b;
+      dt += (double)cr[q] * a + (double)ci[q] * b;
+    }
+  }
+  s2 = block_sum(s2, red);
+  dt = block_sum(dt, red);
+  if (threadIdx.x == 0) {
+    const double mu = mu_dev ? *mu_dev : 1.0;
+    const double t = mu_dev ? alpha / mu : (double)thresh;
+    const double sg = sqrt(s2);
+    const bool keep = sg > t;
+    sig[d.f_off + c] = (float)sg;
+    gval[d.f_off + c] = keep ? (float)(1.0 - t / sg) : 0.f;
+    acon[d.f_off + c] = keep ? -dt / sg * (double)d.fw / mu : 0.0;
+  }
+}
+
+// W = g1 o (C^H B + B^H C) (tall) or g1 o (C B^H + B C^H) (wide), r x r,
+// as one product over the stacked contraction [C; B] (rows padded to 32).
+template <int MODE>
+__global__ void __launch_bounds__(256) k_vjp_w(const SliceDesc* __restrict__ desc, const float* __restrict__ Bb,
+                                               const float* __restrict__ Cb, const float* __restrict__ sig,
+                                               float* __restrict__ Wb, const int* __restrict__ rcount,
+                                               const double* __restrict__ mu_dev, double alpha, float thresh) {
+  __shared__ MfmaSmem sm;
+  const SliceDesc d = desc[blockIdx.z];
+  const int r = rcount[blockIdx.z], n = d.n1, h = d.h, w = d.w;
+  const int m0 = blockIdx.y * kMT, n0 = blockIdx.x * kMT;
+  if (m0 >= r || n0 >= r) return;
+  const float* br = Bb + d.b_off;
+  const float* bi = br + (int64_t)h * w;
+  const float* cr = Cb + d.b_off;
+  const float* ci = cr + (int64_t)h * w;
+  const float* sg = sig + d.f_off;
+  float* wr = Wb + d.v_off;
+  float* wi = wr + (int64_t)n * n;
+  const double t = mu_dev ? alpha / *mu_dev : (double)thresh;
+  const int wv = threadIdx.x >> 6;
+  const bool active = m0 + 32 * (wv >> 1) < r && n0 + 32 * (wv & 1) < r;
+  auto st = [&](int i, int j, float2 v) {
+    if (i < r && j < r) {
+      const float g = (float)g1_pair(sg[i], sg[j], t);
+      wr[(int64_t)i * n + j] = g * v.x;
+      wi[(int64_t)i * n + j] = g * v.y;
+    }
+  };
+  if (d.tall) {  // rows k of B, C (ld n), k < h
+    const int mp = (h + 31) & ~31;
+    auto fa = [&](int i, int k) -> float2 {
+      const bool second = k >= mp;
+      const int kk = second ? k - mp : k;
+      if (i >= r || kk >= h) return make_float2(0.f, 0.f);
+      const int64_t q = (int64_t)kk * n + i;
+      return second ? make_float2(br[q], -bi[q]) : make_float2(cr[q], -ci[q]);
+    };
+    auto fb = [&](int k, int j) -> float2 {
+      const bool second = k >= mp;
+      const int kk = second ? k - mp : k;
+      if (j >= r || kk >= h) return make_float2(0.f, 0.f);
+      const int64_t q = (int64_t)kk * n + j;
+      return second ? make_float2(cr[q], ci[q]) : make_float2(br[q], bi[q]);
+    };
+    mfma_ctile<MODE, false, false>(m0, n0, 2 * mp, fa, fb, st, sm, active);
+  } else {  // columns k of B, C (rows i < r, ld w), k < w
+    const int mp = (w + 31) & ~31;
+    auto fa = [&](int i, int k) -> float2 {
+      const bool second = k >= mp;
+      const int kk = second ? k - mp : k;
+      if (i >= r || kk >= w) return make_float2(0.f, 0.f);
+      const int64_t q = (int64_t)i * w + kk;
+      return second ? make_float2(br[q], bi[q]) : make_float2(cr[q], ci[q]);
+    };
+    auto fb = [&](int k, int j) -> float2 {
+      const bool second = k >= mp;
+      const int kk = second ? k - mp : k;
+      if (j >= r || kk >= w) return make_float2(0.f, 0.f);
+      const int64_t q = (int64_t)j * w + kk;
+      return second ? make_float2(cr[q], -ci[q]) : make_float2(br[q], -bi[q]);
+    };
+    mfma_ctile<MODE, true, true>(m0, n0, 2 * mp, fa, fb, st, sm, active);
+  }
+}
+
+// tall: R (h x r, ld n) = B W + C diag(g);  wide: R (r x w, ld w) = W B + diag(g) C
+template <int MODE>
+__global__ void __launch_bounds__(256) k_vjp_r(const SliceDesc* __restrict__ desc, const float* __restrict__ Bb,
+                                               const float* __restrict__ Cb, const float* __restrict__ Wb,
+                                               const float* __restrict__ gval, float* __restrict__ Rb,
+                                               const int* __restrict__ rcount) {
+  __shared__ MfmaSmem sm;
+  const SliceDesc d = desc[blockIdx.z];
+  const int r = rcount[blockIdx.z], n = d.n1, h = d.h, w = d.w;
+  const int M = d.tall ? h : r, N = d.tall ? r : w, ld = d.tall ? n : w;
+  const int m0 = blockIdx.y * kMT, n0 = blockIdx.x * kMT;
+  if (m0 >= M || n0 >= N) return;
+  const float* br = Bb + d.b_off;
+  const float* bi = br + (int64_t)h * w;
+  const float* cr = Cb + d.b_off;
+  const float* ci = cr + (int64_t)h * w;
+  const float* wr = Wb + d.v_off;
+  const float* wi = wr + (int64_t)n * n;
+  const float* g = gval + d.f_off;
+  float* rr = Rb + d.b_off;
+  float* ri = rr + (int64_t)h * w;
+  const int wv = threadIdx.x >> 6;
+  const bool active = m0 + 32 * (wv >> 1) < M && n0 + 32 * (wv & 1) < N;
+  const bool tall = d.tall;
+  auto st = [&](int a, int b, float2 v) {
+    if (a < M && b < N) {
+      const int64_t q = (int64_t)a * ld + b;
+      const float s = tall ? g[b] : g[a];
+      rr[q] = v.x + s * cr[q];
+      ri[q] = v.y + s * ci[q];
+    }
+  };
+  if (tall) {
+    auto fa = [&](int i, int k) -> float2 {
+      if (i >= h || k >= r) return make_float2(0.f, 0.f);
+      return make_float2(br[(int64_t)i * n + k], bi[(int64_t)i * n + k]);
+    };
+    auto fb = [&](int k, int j) -> float2 {
+      if (k >= r || j >= r) return make_float2(0.f, 0.f);
+      return make_float2(wr[(int64_t)k * n + j], wi[(int64_t)k * n + j]);
+    };
+    mfma_ctile<MODE, true, false>(m0, n0, r, fa, fb, st, sm, active);
+  } else {
+    auto fa = [&](int i, int k) -> float2 {
+      if (i >= r || k >= r) return make_float2(0.f, 0.f);
+      return make_float2(wr[(int64_t)i * n + k], wi[(int64_t)i * n + k]);
+    };
+    auto fb = [&](int k, int j) -> float2 {
+      if (k >= r || j >= w) return make_float2(0.f, 0.f);
+      return make_float2(br[(int64_t)k * w + j], bi[(int64_t)k * w + j]);
+    };
+    mfma_ctile<MODE, true, false>(m0, n0, r, fa, fb, st, sm, active);
+  }
+}
+
 // ------------------------------------------------------------ launcher ---
 constexpr int kTridiagRegRows = 10;
 // Dynamic LDS granted to k_tridiag_reg (host-side function attribute, set
@@ -1144,6 +1348,42 @@ void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm) {
     hipLaunchKernelGGL(k_bp2<kF32>, dim3(TM, TM, ns), dim3(256), 0, s, L.desc, L.slices, L.V, L.B, L.fval,
                        L.rcount);
   T.end(ST_BP2);
+}
+
+
+void launch_svt_vjp(const SvtVjpLaunch& J, hipStream_t s) {
+  const SvtLaunch& L = J.fw;
+  const int ns = L.n_slices, n = L.max_n1, m = L.max_m1;
+  if (ns == 0) return;
+  const int TT = (n + kMT - 1) / kMT, TM = (m + kMT - 1) / kMT;
+  // full eigendecomposition of every Gram (thresh < 0: all eigenpairs)
+  hipLaunchKernelGGL(k_gram<kF32>, dim3(TT * (TT + 1) / 2, ns), dim3(256), 0, s, L.desc, L.slices, L.gram);
+  constexpr int JR = kTridiagRegRows;
+  const int RL = n > 8 * JR ? n - 8 * JR : 0;
+  const size_t reg_lds = ((size_t)RL * (RL + 1) / 2 + (size_t)(3 + 8) * n) * sizeof(float2);
+  if (n <= 256 && reg_lds <= g_tridiag_lds_granted)
+    hipLaunchKernelGGL(k_tridiag_reg<JR>, dim3(ns), dim3(512), reg_lds, s, L.desc, L.gram, L.tri);
+  else
+    hipLaunchKernelGGL(k_tridiag<false>, dim3(ns), dim3(256), (size_t)(2 + 4) * n * sizeof(float2), s, L.desc,
+                       L.gram, L.tri);
+  const size_t eig_lds = (size_t)5 * n * sizeof(double) + (size_t)(n + 1) * sizeof(int);
+  hipLaunchKernelGGL(k_trieig, dim3(ns), dim3(1024), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount,
+                     (const double*)nullptr, 0.0, -1.f);
+  const int cb = n <= 256 ? 16 : 8;
+  const size_t bt_lds = ((size_t)n * cb + n + 256) * sizeof(float2);
+  hipLaunchKernelGGL(k_backtrans, dim3((n + cb - 1) / cb, ns), dim3(256), bt_lds, s, L.desc, L.gram, L.tri, L.V,
+                     L.rcount, cb);
+  // B = M V, C = D V (or U^H M, U^H D)
+  hipLaunchKernelGGL(k_bp1<kF32>, dim3(TM, TM, ns), dim3(256), 0, s, L.desc, L.slices, L.V, L.B, L.rcount);
+  hipLaunchKernelGGL(k_bp1<kF32>, dim3(TM, TM, ns), dim3(256), 0, s, L.desc, J.dsl, L.V, J.C, L.rcount);
+  hipLaunchKernelGGL(k_vjp_sigma, dim3(n, ns), dim3(256), 0, s, L.desc, L.B, J.C, J.sig, L.fval, J.acon, L.rcount,
+                     L.mu, L.alpha, L.thresh);
+  hipLaunchKernelGGL(k_vjp_w<kF32>, dim3(TT, TT, ns), dim3(256), 0, s, L.desc, L.B, J.C, J.sig, J.W, L.rcount,
+                     L.mu, L.alpha, L.thresh);
+  hipLaunchKernelGGL(k_vjp_r<kF32>, dim3(TM, TM, ns), dim3(256), 0, s, L.desc, L.B, J.C, J.W, L.fval, J.R,
+                     L.rcount);
+  // result (R V^H or U R) over the direction slices
+  hipLaunchKernelGGL(k_bp2<kF32>, dim3(TM, TM, ns), dim3(256), 0, s, L.desc, J.dsl, L.V, J.R, J.ones, L.rcount);
 }
 
 }  // namespace lrstv

@@ -23,6 +23,23 @@ struct CubePtrs {
 
 struct SliceDesc;
 
+// One cube's pointers for the adjoint of an iteration (all offset to the
+// cube; gradient-shaped arrays are 3 components spaced by ts, the per-cube
+// scratch dirE, A by as).  ga* may all be NULL (zero cotangent), gX too.
+struct VjpCube {
+  int h, w, b;
+  int64_t ts, as;
+  const float *G4;                      // state before: Gamma4
+  const float *S1, *F1;                 // state after: S', F'
+  const float *gaZ, *gaS, *gaF, *gaE, *gaG1, *gaG2, *gaG3, *gaG4;
+  const float* gX;
+  float *gbZ, *gbS, *gbF, *gbE, *gbG1, *gbG2, *gbG3, *gbG4;
+  float *gL, *gZp, *gFp;                // cotangent scratch (batch-sized)
+  float *dirE, *A;                      // t-SVT direction and point (per cube)
+  float* gY;                            // accumulated cotangent of O
+  bool initial;                         // the state before has Z = O (gb.Z also flows into gY)
+};
+
 void launch_fill(float* p, int64_t n, float v, hipStream_t s);
 void launch_copy(float* dst, const float* src, int64_t n, hipStream_t s);
 void launch_set_mu(double* mu, double v, hipStream_t s);
@@ -73,5 +90,33 @@ struct SvtLaunch {
 void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm = nullptr);
 // Host-side kernel attributes for slices up to max_n1 (call before capture).
 void prepare_svt(int max_n1);
+
+// Derivative of the slice SVT at the slices of fw.slices along the
+// direction slices dsl (same layout); the result replaces dsl.  fw.fval
+// receives the shrink factors g, acon the per-column threshold-derivative
+// terms (already weighted by the slice's Fourier weight and 1/mu).
+struct SvtVjpLaunch {
+  SvtLaunch fw;
+  float* dsl;      // direction slices in, derivative slices out
+  float* C;        // D V (B-sized)
+  float* R;        // B W + C diag(g) (B-sized)
+  float* W;        // g1 o H, r x r per slice (V-sized)
+  float* sig;      // singular values (fval-sized)
+  const float* ones;  // fval-sized, every entry 1
+  double* acon;    // fval-sized
+};
+void launch_svt_vjp(const SvtVjpLaunch& J, hipStream_t s);
+
+// --- adjoint of one iteration (k_vjp.hip) ---------------------------------
+void launch_vjp_post(const VjpCube& c, const double* mu, double* part_lam, hipStream_t s);
+void launch_vjp_shrinkf(const VjpCube& c, const float* gA, const double* mu, double* part_tau, hipStream_t s);
+void launch_vjp_divt(const VjpCube& c, float* T, const double w[3], hipStream_t s);
+void launch_vjp_pre(const VjpCube& c, const float* gT, const double w[3], const double* mu, hipStream_t s);
+// gw[c] += (tau, alpha, lambda) cotangents; part [n_cubes][2][LRSTV_PARTS]
+// (tau, lambda block partials), acon_range [n_cubes][2] index ranges of acon.
+void launch_vjp_finish(const double* part, const double* acon, const int64_t* acon_range, int n_cubes, double* gw,
+                       hipStream_t s);
+// out[c] = sum of acon over acon_range[c]
+void launch_sum_ranges(const double* acon, const int64_t* range, int n, double* out, hipStream_t s);
 
 }  // namespace lrstv

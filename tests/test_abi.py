@@ -19,7 +19,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for want in ["lrstv_create", "lrstv_iterate", "lrstv_solve", "lrstv_svt", "lrstv_reset",
                  "lrstv_workspace_size", "lrstv_get_state", "lrstv_set_state", "lrstv_destroy",
-                 "lrstv_zsolve", "lrstv_status_string", "lrstv_last_error"]:
+                 "lrstv_zsolve", "lrstv_status_string", "lrstv_last_error", "lrstv_iterate_vjp",
+                 "lrstv_vjp_workspace_size", "lrstv_svt_vjp", "lrstv_save_state"]:
         assert want in names
 
 
@@ -61,6 +62,11 @@ def test_argument_checks_without_gpu():
     assert lib.lrstv_svt_workspace_size(32, 32, 16, 0, 0, ctypes.byref(n)) == -1
     assert lib.lrstv_svt_workspace_size(32, 32, 16, 2, 0, ctypes.byref(n)) == 0
     assert lib.lrstv_zsolve_workspace_size(32, 32, 16, ctypes.byref(n)) == 0
+    assert lib.lrstv_svt_vjp_workspace_size(32, 32, 16, 0, ctypes.byref(n)) == -1
+    assert lib.lrstv_svt_vjp_workspace_size(32, 40, 16, 3, ctypes.byref(n)) == 0 and n.value > 0
+    assert lib.lrstv_vjp_workspace_size(None, ctypes.byref(n)) == -1
+    assert lib.lrstv_iterate_vjp(None, None, None, None, None, None, None, None, 0, None, 0) == -1
+    assert lib.lrstv_save_state(None, None) == -1
     assert lib.lrstv_status_string(-2) == b"workspace too small"
     assert lib.lrstv_version() >= 100
     with pytest.raises(L.LrstvError):

@@ -1,0 +1,255 @@
+"""GPU parity of the adjoint (lrstv_svt_vjp, lrstv_iterate_vjp and the K-step
+LRSTVUnrolled backward, all through the C ABI) against the FP64 adjoint
+oracle, whose own correctness is pinned by finite differences on the CPU.
+
+Tolerances (relative Frobenius unless stated):
+  * ADJ_SVT_TOL = 1e-3 for the t-SVT derivative: it is assembled from FP32
+    products of B = M V and C = D V, and its divided differences
+    1/(s_i^2 - s_j^2) amplify the FP32 singular-value error (~ n eps_32
+    ||M||^2 / s) by up to ||M|| / gap for pairs on both sides of the
+    threshold; the same bound holds for the threshold cotangent;
+  * ADJ_STEP_TOL = 1e-3 for one iteration's cotangents (the t-SVT part
+    dominates; the elementwise and FFT-solve parts are at a few ulps);
+  * 1e-2 for the K = 10 gradients, where forward FP32 drift over the
+    checkpoints also enters (shrink masks that differ between FP32 and FP64
+    near the threshold move the gradient locally).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import adjoint as adj
+
+ADJ_SVT_TOL = 1e-3
+ADJ_STEP_TOL = 1e-3
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2204_12879_amd as L
+    L.load_library()
+    return L
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _lowrank_tensor(shape, rank, seed, noise=0.05):
+    b, h, w = shape
+    rng = np.random.default_rng(seed)
+    U = rng.normal(size=(b, h, rank))
+    V = rng.normal(size=(b, rank, w))
+    A = np.einsum("bhr,brw->bhw", U, V) / np.sqrt(rank) + noise * rng.normal(size=shape)
+    return A.astype(np.float32)
+
+
+def _mid_gap_threshold(A, q):
+    """A threshold halfway across a resolved gap between neighbouring
+    singular values near the q-quantile.
+
+    The t-SVT is not differentiable where a singular value equals the
+    threshold, and the slices k and b - k share their singular values, so
+    only the non-redundant slices are used.  The GPU derivative works from
+    FP32 Gram eigenpairs, which resolve squared singular values to about
+    n eps_32 ||G|| (1.5e-5 ||G|| at n = 256); its divided differences are
+    only determined by them where the neighbouring squared singular values
+    around the threshold differ by more than that, so the gap is taken in
+    s^2 and must exceed 1e-4 max s^2 (inside an unresolved noise bulk the
+    derivative is ill-conditioned for any FP32 Gram method)."""
+    Ah = np.fft.fft(A.astype(np.float64), axis=0)
+    sv = np.sort(np.concatenate([np.linalg.svd(Ah[k], compute_uv=False) for k in range(A.shape[0] // 2 + 1)]))
+    lam = sv ** 2
+    i0 = min(int(q * sv.size), sv.size - 2)
+    for d in range(sv.size):
+        for i in (i0 + d, i0 - d):
+            if 0 <= i < sv.size - 1 and lam[i + 1] - lam[i] > 1e-4 * lam[-1]:
+                return 0.5 * float(sv[i] + sv[i + 1])
+    raise AssertionError("no resolved gap in the spectrum")
+
+
+@pytest.mark.parametrize("shape", [(8, 24, 20), (9, 17, 30), (5, 64, 64), (3, 128, 96), (2, 256, 256),
+                                   (6, 1, 9)])
+def test_svt_vjp_matches_oracle(shape):
+    L = _lib()
+    A = _lowrank_tensor(shape, rank=3, seed=sum(shape))
+    G = np.random.default_rng(1).standard_normal(shape).astype(np.float32)
+    for q in (0.0, 0.5, 0.9):
+        t = 0.0 if q == 0.0 else _mid_gap_threshold(A, q)
+        gA, gt = L.svt_vjp(torch.from_numpy(A).cuda(), torch.from_numpy(G).cuda(), t)
+        torch.cuda.synchronize()
+        rA, rt = adj.tsvt_vjp(A.astype(np.float64), t, G.astype(np.float64))
+        e = rel(gA.cpu().numpy(), rA)
+        et = abs(float(gt.cpu()[0]) - rt) / max(abs(rt), 1e-3 * np.linalg.norm(G))
+        say(f"svt_vjp {shape} t={t:.4g}: gA rel {e:.2e}, g_t rel {et:.2e}")
+        assert e < ADJ_SVT_TOL, (q, e)
+        # at t = 0 the threshold cotangent sums Re<u_i, D v_i> over every
+        # singular pair, including the noise floor whose FP32 Gram
+        # eigenvectors are not resolved: it is checked for t > 0 only
+        if t > 0:
+            assert et < ADJ_SVT_TOL, (q, et)
+
+
+def test_svt_vjp_batch_and_symmetry():
+    """Batch entries equal single calls, and <u, J v> = <J u, v> with
+    0 <= <v, J v> <= ||v||^2 on the GPU result (Jacobian of a prox map)."""
+    L = _lib()
+    shape = (7, 40, 36)
+    A = np.stack([_lowrank_tensor(shape, 3, 10 + i) for i in range(3)])
+    rng = np.random.default_rng(5)
+    U = rng.standard_normal(A.shape).astype(np.float32)
+    V = rng.standard_normal(A.shape).astype(np.float32)
+    t = _mid_gap_threshold(A[0], 0.5)
+    Ag = torch.from_numpy(A).cuda()
+    Ju, _ = L.svt_vjp(Ag, torch.from_numpy(U).cuda(), t)
+    Jv, _ = L.svt_vjp(Ag, torch.from_numpy(V).cuda(), t)
+    Ju, Jv = Ju.cpu().numpy().astype(np.float64), Jv.cpu().numpy().astype(np.float64)
+    for i in range(3):
+        one, _ = L.svt_vjp(Ag[i], torch.from_numpy(U[i]).cuda(), t)
+        assert np.array_equal(one.cpu().numpy(), Ju[i].astype(np.float32))
+        a = float((U[i] * Jv[i]).sum())
+        b = float((Ju[i] * V[i]).sum())
+        assert abs(a - b) <= 1e-4 * np.linalg.norm(U[i]) * np.linalg.norm(V[i])
+        vjv = float((V[i] * Jv[i]).sum())
+        assert -1e-4 * float((V[i] ** 2).sum()) <= vjv <= (1 + 1e-4) * float((V[i] ** 2).sum())
+
+
+_FIELDS = ("Z", "S", "G1", "G2", "F", "E", "G3", "G4")
+
+
+def _to_buffer(L, st, T):
+    buf = L.StateBuffer(T)
+    for k in _FIELDS:
+        buf.part(k).copy_(torch.from_numpy(np.ascontiguousarray(st[k], np.float32).reshape(-1)))
+    return buf
+
+
+def _from_buffer(buf, shape):
+    out = {}
+    for k in _FIELDS:
+        a = buf.part(k).cpu().numpy().astype(np.float64)
+        out[k] = a.reshape(((3,) if k in ("F", "E", "G3", "G4") else ()) + shape)
+    return out
+
+
+@pytest.mark.parametrize("shape", [(16, 32, 32), (10, 20, 24), (7, 18, 13), (31, 64, 48)])
+def test_iterate_vjp_matches_oracle(shape):
+    L = _lib()
+    b, h, w = shape
+    clean, noisy = synth.make_cube(synth.CubeSpec(h, w, b, 8, synth.NOISE_SMALL, 3))
+    O = noisy.astype(np.float32)
+    st = {k: v.astype(np.float32) for k, v in synth.random_state(b, h, w, seed=9, scale=0.1).items()}
+    ga = {k: v.astype(np.float32) for k, v in synth.random_state(b, h, w, seed=21, scale=1.0).items()}
+    gX = np.random.default_rng(3).standard_normal(shape).astype(np.float32)
+    mu = 0.8
+    p = oracle.Params(tau=0.02, alpha=0.3, lam=10 / np.sqrt(h * w), w=(1.0, 0.8, 1.2), mu0=mu)
+    solver = L.Solver([shape], L.Params(tau=p.tau, alpha=p.alpha, lam=p.lam, w=p.w, mu0=mu))
+    T = b * h * w
+    g = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda().reshape(-1) for k, v in st.items()}
+    g["Y"] = torch.from_numpy(O).cuda().reshape(-1)
+    g["mu"] = torch.tensor([mu], dtype=torch.float64, device="cuda")
+    solver.set_state(g)
+    before, after = L.StateBuffer(T), L.StateBuffer(T)
+    solver.save_state(before)
+    solver.iterate(1)
+    solver.save_state(after)
+    gab = _to_buffer(L, ga, T)
+    gb = L.StateBuffer(T)
+    gw = torch.zeros(1, 3, dtype=torch.float64, device="cuda")
+    gY = torch.zeros(T, dtype=torch.float32, device="cuda")
+    solver.iterate_vjp(before, after, gab, torch.from_numpy(gX).cuda().reshape(-1), gb, gw, gY)
+    torch.cuda.synchronize()
+    fnz = float((after.part("F") != 0).float().mean())
+    say(f"iterate_vjp {shape}: nonzero F' {fnz:.3f}")
+    assert 0.01 < fnz < 0.99
+
+    ost = oracle.State(**{k: st[k].astype(np.float64) for k in _FIELDS}, mu=mu)
+    og = oracle.State(**{k: ga[k].astype(np.float64) for k in _FIELDS}, mu=mu)
+    r_st, r_O, r_t, r_a, r_l = adj.admm_step_vjp(O.astype(np.float64), ost, p, og, gX.astype(np.float64))
+    got = _from_buffer(gb, shape)
+    for k in _FIELDS:
+        e = rel(got[k], getattr(r_st, k))
+        say(f"  g{k}: {e:.2e}")
+        assert e < ADJ_STEP_TOL, (k, e)
+    e = rel(gY.cpu().numpy().reshape(shape), r_O)
+    say(f"  gY: {e:.2e}")
+    assert e < ADJ_STEP_TOL
+    gwh = gw.cpu().numpy()[0]
+    for name, a, r in (("tau", gwh[0], r_t), ("alpha", gwh[1], r_a), ("lambda", gwh[2], r_l)):
+        e = abs(a - r) / max(abs(r), 1e-12)
+        say(f"  g_{name}: {a:.6g} vs {r:.6g} ({e:.2e})")
+        assert e < ADJ_STEP_TOL, (name, a, r)
+
+
+def test_iterate_vjp_zero_cotangent_is_zero():
+    """grad_after = NULL and grad_X = NULL give zero cotangents everywhere."""
+    L = _lib()
+    shape = (6, 16, 12)
+    b, h, w = shape
+    T = b * h * w
+    _, noisy = synth.make_cube(synth.CubeSpec(h, w, b, 4, synth.NOISE_SMALL, 1))
+    solver = L.Solver([shape], L.Params(tau=0.02, alpha=0.3, lam=0.5, mu0=0.7))
+    solver.reset(torch.from_numpy(noisy.astype(np.float32)).cuda().reshape(-1))
+    solver.iterate(2)
+    before, after = L.StateBuffer(T), L.StateBuffer(T)
+    solver.save_state(before)
+    solver.iterate(1)
+    solver.save_state(after)
+    gb = L.StateBuffer(T)
+    gb.data.fill_(7.0)
+    gw = torch.zeros(1, 3, dtype=torch.float64, device="cuda")
+    gY = torch.zeros(T, dtype=torch.float32, device="cuda")
+    solver.iterate_vjp(before, after, None, None, gb, gw, gY)
+    torch.cuda.synchronize()
+    assert float(gb.data.abs().max()) == 0.0 and float(gY.abs().max()) == 0.0
+    assert float(gw.abs().max()) == 0.0
+
+
+def test_unrolled_gradient_matches_oracle_on_the_adjoint_workload():
+    """8 cubes 64x64x32 (seeds 100..107), K = 10: the gradient of <g, X> with
+    respect to Y, tau, alpha and lambda from LRSTVUnrolled's backward equals
+    the FP64 adjoint oracle's (summed over the cubes for the parameters)."""
+    L = _lib()
+    wl = synth.workload("diff")
+    cubes = [synth.make_cube(s)[1].astype(np.float32) for s in wl.cubes]
+    spec = wl.cubes[0]
+    p = oracle.default_params(spec.h, spec.w, tau=0.02, alpha=0.3)
+    K = wl.iters
+    shapes = [c.shape for c in cubes]
+    Y = torch.from_numpy(np.concatenate([c.ravel() for c in cubes])).cuda().requires_grad_(True)
+    tau = torch.tensor(p.tau, dtype=torch.float64, requires_grad=True)
+    alpha = torch.tensor(p.alpha, dtype=torch.float64, requires_grad=True)
+    lam = torch.tensor(p.lam, dtype=torch.float64, requires_grad=True)
+    rng = np.random.default_rng(0)
+    gs = [rng.standard_normal(c.shape) for c in cubes]
+    gflat = torch.from_numpy(np.concatenate([g.ravel() for g in gs]).astype(np.float32)).cuda()
+    X = L.lrstv_unrolled(Y, tau, alpha, lam, shapes, K, mu0=p.mu0, rho=p.rho, mu_max=p.mu_max)
+    (X * gflat).sum().backward()
+    torch.cuda.synchronize()
+    gY = Y.grad.cpu().numpy().astype(np.float64)
+    ref_t = ref_a = ref_l = 0.0
+    off = 0
+    errs = []
+    for c, g in zip(cubes, gs):
+        rO, rt, ra, rl = adj.unrolled_vjp(c.astype(np.float64), p, K, g)
+        n = c.size
+        errs.append(rel(gY[off:off + n].reshape(c.shape), rO))
+        off += n
+        ref_t += rt
+        ref_a += ra
+        ref_l += rl
+    say("unrolled gY rel err per cube", ["%.2e" % e for e in errs])
+    assert max(errs) < 1e-2
+    for name, a, r in (("tau", tau.grad, ref_t), ("alpha", alpha.grad, ref_a), ("lambda", lam.grad, ref_l)):
+        e = abs(float(a) - r) / abs(r)
+        say(f"unrolled g_{name}: {float(a):.6g} vs {r:.6g} ({e:.2e})")
+        assert e < 1e-2, name
