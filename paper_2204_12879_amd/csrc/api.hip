@@ -12,6 +12,8 @@
 
 #include "../../include/lrstv.h"
 #include "common.hpp"
+
+static_assert(LRSTV_MAX_SIDE == LRSTV_MAX_SIDE_DEV, "device-side size bound out of step");
 #include "kernels.hpp"
 
 using namespace lrstv;

@@ -5,6 +5,9 @@
 
 #define LRSTV_DEV __device__ __forceinline__
 
+// Largest cube side (LRSTV_MAX_SIDE of the public header; checked there).
+#define LRSTV_MAX_SIDE_DEV 512
+
 namespace lrstv {
 
 // ---------------------------------------------------------------- complex ---

@@ -21,6 +21,7 @@
 // radices 4, 2, 3, 5, 7 and a direct-DFT stage for any other prime factor.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "mfma.hpp"
 
 namespace lrstv {
 
@@ -350,127 +351,127 @@ __global__ void __launch_bounds__(256) k_tri_b(float2* __restrict__ spec, int h,
 }
 
 // ---------------------------------------------------------------------------
-// Band DFT of real tensors: X_k = sum_j a_j e^{-2 pi i j k / b}, k < b/2+1,
-// using the pairing a_j +- a_{b-j}.  Output planar slices [t][k][re|im][hw].
+// Band DFT of real tensors as a real matrix product on the matrix cores:
+//   X (2s x hw) = F (2s x b) A (b x hw),  s = b/2 + 1,
+//   F[2k][j] = cos(2 pi j k / b),  F[2k+1][j] = -sin(2 pi j k / b),
+// so row 2k / 2k+1 of X is the re / im plane of Fourier slice k: the planar
+// slice layout [t][k][re|im][hw] is X itself.  F is generated while staging
+// from an LDS table of cos / sin(2 pi m / b) (index j k mod b, advanced
+// incrementally).  Tiles are walked with the row tile fastest so that the
+// blocks sharing a column strip of A run together (L2 reuse).
 __global__ void __launch_bounds__(256) k_band_dft(const float* __restrict__ A, int64_t a_stride, int n_t,
-                                                  float* __restrict__ out, int hw, int b, int P) {
-  extern __shared__ float smf[];
-  float* ct = smf;           // cos(2 pi m / b)
-  float* st = ct + b;        // sin(2 pi m / b)
-  float* a = st + b;         // [b][P]
-  const int s = b / 2 + 1, J = (b - 1) / 2;
+                                                  float* __restrict__ out, int hw, int b) {
+  __shared__ MfmaSmemR sm;
+  __shared__ float ct[LRSTV_MAX_SIDE_DEV], st[LRSTV_MAX_SIDE_DEV];
   for (int m = threadIdx.x; m < b; m += blockDim.x) {
     double sv, cv;
     sincospi(2.0 * (double)m / (double)b, &sv, &cv);
     ct[m] = (float)cv;
     st[m] = (float)sv;
   }
-  const int ntile = (hw + P - 1) / P;
-  for (int blk = blockIdx.x; blk < n_t * ntile; blk += gridDim.x) {
-    const int t = blk / ntile, p0 = (blk - t * ntile) * P;
+  __syncthreads();
+  const int M = 2 * (b / 2 + 1);
+  const int TM = (M + kMT - 1) / kMT, TN = (hw + kMT - 1) / kMT;
+  const int ntiles = n_t * TM * TN;
+  const int wv = threadIdx.x >> 6;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int t = tile / (TM * TN), rem = tile - t * TM * TN;
+    const int tn = rem / TM, tm = rem - tn * TM;
+    const int m0 = tm * kMT, n0 = tn * kMT;
     const float* src = A + t * a_stride;
-    __syncthreads();
-    for (int e = threadIdx.x; e < b * P; e += blockDim.x) {
-      const int j = e / P, p = e - j * P;
-      a[e] = (p0 + p < hw) ? src[(int64_t)j * hw + p0 + p] : 0.f;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < J * P; e += blockDim.x) {
-      const int j = 1 + e / P, p = e % P;
-      const float u = a[j * P + p], v = a[(b - j) * P + p];
-      a[j * P + p] = u + v;
-      a[(b - j) * P + p] = u - v;
-    }
-    __syncthreads();
-    const int groups = blockDim.x / P;
-    const int p = threadIdx.x % P, g = threadIdx.x / P;
-    if (g < groups && p0 + p < hw) {
-      float* dst = out + (int64_t)t * s * 2 * hw;
-      for (int k = g; k < s; k += groups) {
-        float re = a[p], im = 0.f;
-        int idx = 0;
-        for (int j = 1; j <= J; ++j) {
-          idx += k;
-          if (idx >= b) idx -= b;
-          re += a[j * P + p] * ct[idx];
-          im -= a[(b - j) * P + p] * st[idx];
-        }
-        if ((b & 1) == 0) re += a[(b / 2) * P + p] * ((k & 1) ? -1.f : 1.f);
-        dst[((int64_t)k * 2) * hw + p0 + p] = re;
-        dst[((int64_t)k * 2 + 1) * hw + p0 + p] = im;
+    float* dst = out + (int64_t)t * M * hw;
+    const bool active = m0 + 32 * (wv >> 1) < M && n0 + 32 * (wv & 1) < hw;
+    auto fa = [&](int m, int k0, float* v) {
+      const int kk = m >> 1;
+      const bool im = m & 1;
+      int idx = (int)((k0 * kk) % b);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const bool ok = m < M && k0 + e < b;
+        v[e] = ok ? (im ? -st[idx] : ct[idx]) : 0.f;
+        idx += kk;
+        if (idx >= b) idx -= b;
       }
-    }
+    };
+    auto fb = [&](int k0, int n, float* v) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = (k0 + e < b && n < hw) ? src[(int64_t)(k0 + e) * hw + n] : 0.f;
+    };
+    auto sto = [&](int m, int n, float v) {
+      if (m < M && n < hw) dst[(int64_t)m * hw + n] = v;
+    };
+    mfma_rtile<true, false>(m0, n0, b, fa, fb, sto, sm, active);
   }
 }
 
-// Inverse band DFT (Hermitian completion) + optional Gamma4 ascent.
-// E_j = (1/b) [Re X_0 + 2 sum_{k=1}^{J} (Re X_k cos - Im X_k sin)(2 pi j k / b) + Re X_{b/2} (-1)^j].
+// Inverse band DFT with Hermitian completion, as the real product
+//   E (b x hw) = G (b x 2s) X (2s x hw),
+//   G[j][2k] = c_k cos(2 pi j k / b) / b,  G[j][2k+1] = -c_k sin(2 pi j k / b) / b,
+// c_k = 1 for k = 0 and k = b/2, else 2 (slice k stands for k and b - k).
+// Epilogue (optional): Gamma4 += mu (E - F) and FP64 partial sums of
+// (E - F)^2, one fixed slot per block (grid = LRSTV_PARTS when part != NULL).
 __global__ void __launch_bounds__(256) k_band_idft(const float* __restrict__ X, int n_t, float* __restrict__ E,
-                                                   int64_t e_stride, int hw, int b, int P,
+                                                   int64_t e_stride, int hw, int b,
                                                    const float* __restrict__ F, float* __restrict__ G4,
                                                    const double* __restrict__ mu_dev, double* __restrict__ part) {
-  extern __shared__ float smf[];
+  __shared__ MfmaSmemR sm;
+  __shared__ float ct[LRSTV_MAX_SIDE_DEV], st[LRSTV_MAX_SIDE_DEV];
   __shared__ double red[8];
-  float* ct = smf;
-  float* st = ct + b;
-  float* xr = st + b;        // [s][P]
-  float* xi = xr + (b / 2 + 1) * P;
-  const int s = b / 2 + 1, J = (b - 1) / 2, half = b / 2;
   const float ib = 1.0f / (float)b;
-  const float mu = G4 ? (float)(*mu_dev) : 0.f;
   for (int m = threadIdx.x; m < b; m += blockDim.x) {
     double sv, cv;
     sincospi(2.0 * (double)m / (double)b, &sv, &cv);
-    ct[m] = (float)cv;
-    st[m] = (float)sv;
+    ct[m] = (float)cv * ib;
+    st[m] = (float)sv * ib;
   }
+  __syncthreads();
+  const float mu = G4 ? (float)(*mu_dev) : 0.f;
+  const int K2 = 2 * (b / 2 + 1);
+  const int TM = (b + kMT - 1) / kMT, TN = (hw + kMT - 1) / kMT;
+  const int ntiles = n_t * TM * TN;
+  const int wv = threadIdx.x >> 6;
   double acc = 0.0;
-  const int ntile = (hw + P - 1) / P;
-  for (int blk = blockIdx.x; blk < n_t * ntile; blk += gridDim.x) {
-    const int t = blk / ntile, p0 = (blk - t * ntile) * P;
-    const float* src = X + (int64_t)t * s * 2 * hw;
-    __syncthreads();
-    for (int e = threadIdx.x; e < s * P; e += blockDim.x) {
-      const int k = e / P, p = e - k * P;
-      const bool ok = p0 + p < hw;
-      xr[e] = ok ? src[((int64_t)k * 2) * hw + p0 + p] : 0.f;
-      xi[e] = ok ? src[((int64_t)k * 2 + 1) * hw + p0 + p] : 0.f;
-    }
-    __syncthreads();
-    const int groups = blockDim.x / P;
-    const int p = threadIdx.x % P, g = threadIdx.x / P;
-    if (g < groups && p0 + p < hw) {
-      float* dst = E + t * e_stride;
-      const float* Ft = F ? F + t * e_stride : nullptr;
-      float* G4t = G4 ? G4 + t * e_stride : nullptr;
-      const float x0 = xr[p];
-      const float xn = ((b & 1) == 0) ? xr[half * P + p] : 0.f;
-      for (int j = g; j <= half; j += groups) {
-        float c = 0.f, sn = 0.f;
-        int idx = 0;
-        for (int k = 1; k <= J; ++k) {
-          idx += j;
-          if (idx >= b) idx -= b;
-          c += xr[k * P + p] * ct[idx];
-          sn += xi[k * P + p] * st[idx];
-        }
-        const float ny = xn * ((j & 1) ? -1.f : 1.f);
-        const int jl[2] = {j, b - j};
-        const float ev[2] = {(x0 + 2.f * (c - sn) + ny) * ib, (x0 + 2.f * (c + sn) + ny) * ib};
-        const int cnt = (j == 0 || b - j == j) ? 1 : 2;
-        for (int u = 0; u < cnt; ++u) {
-          const int64_t q = (int64_t)jl[u] * hw + p0 + p;
-          const float e = ev[u];
-          dst[q] = e;
-          if (G4t) {
-            const float f = Ft[q];
-            G4t[q] = G4t[q] + mu * (e - f);
-            const double d = (double)e - (double)f;
-            acc += d * d;
-          }
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int t = tile / (TM * TN), rem = tile - t * TM * TN;
+    const int tn = rem / TM, tm = rem - tn * TM;
+    const int m0 = tm * kMT, n0 = tn * kMT;
+    const float* src = X + (int64_t)t * K2 * hw;
+    float* dst = E + t * e_stride;
+    const float* Ft = F ? F + t * e_stride : nullptr;
+    float* G4t = G4 ? G4 + t * e_stride : nullptr;
+    const bool active = m0 + 32 * (wv >> 1) < b && n0 + 32 * (wv & 1) < hw;
+    auto fa = [&](int j, int kk0, float* v) {
+      // kk0 is a multiple of 8: four slices k = kk0/2 .. kk0/2 + 3, re and im each
+      const int k0 = kk0 >> 1;
+      int idx = (int)(((int64_t)j * k0) % b);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + q;
+        const bool ok = j < b && 2 * k < K2;
+        const float ck = (k == 0 || 2 * k == b) ? 1.f : 2.f;
+        v[2 * q] = ok ? ck * ct[idx] : 0.f;
+        v[2 * q + 1] = ok ? -ck * st[idx] : 0.f;
+        idx += j;
+        if (idx >= b) idx -= b;
+      }
+    };
+    auto fb = [&](int k0, int n, float* v) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = (k0 + e < K2 && n < hw) ? src[(int64_t)(k0 + e) * hw + n] : 0.f;
+    };
+    auto sto = [&](int j, int n, float e) {
+      if (j < b && n < hw) {
+        const int64_t q = (int64_t)j * hw + n;
+        dst[q] = e;
+        if (G4t) {
+          const float f = Ft[q];
+          G4t[q] = G4t[q] + mu * (e - f);
+          const double d = (double)e - (double)f;
+          acc += d * d;
         }
       }
-    }
+    };
+    mfma_rtile<true, false>(m0, n0, K2, fa, fb, sto, sm, active);
   }
   if (part) {
     acc = block_sum(acc, red);
@@ -525,22 +526,18 @@ static int dft_tile(int b) {
 }
 
 void launch_band_dft(const float* A, int64_t a_stride, int n_t, float* slices, int h, int w, int b, hipStream_t s) {
-  const int hw = h * w, P = dft_tile(b);
-  const size_t lds = ((size_t)2 * b + (size_t)b * P) * sizeof(float);
-  int grid = n_t * ((hw + P - 1) / P);
-  if (grid > 8192) grid = 8192;
-  hipLaunchKernelGGL(k_band_dft, dim3(grid), dim3(256), lds, s, A, a_stride, n_t, slices, hw, b, P);
+  const int hw = h * w, M = 2 * (b / 2 + 1);
+  const int64_t ntiles = (int64_t)n_t * ((M + kMT - 1) / kMT) * ((hw + kMT - 1) / kMT);
+  const int grid = (int)(ntiles < 2048 ? ntiles : 2048);
+  hipLaunchKernelGGL(k_band_dft, dim3(grid), dim3(256), 0, s, A, a_stride, n_t, slices, hw, b);
 }
 
 void launch_band_idft(const float* slices, int n_t, float* E, int64_t e_stride, int h, int w, int b,
                       const float* F, float* G4, const double* mu, double* part, hipStream_t s) {
-  const int hw = h * w, sN = b / 2 + 1;
-  int P = 64;
-  while (P > 16 && ((size_t)2 * b + (size_t)2 * sN * P) * 4 > 60 * 1024) P >>= 1;
-  const size_t lds = ((size_t)2 * b + (size_t)2 * sN * P) * sizeof(float);
-  int grid = part ? LRSTV_PARTS : n_t * ((hw + P - 1) / P);
-  if (grid > 8192) grid = 8192;
-  hipLaunchKernelGGL(k_band_idft, dim3(grid), dim3(256), lds, s, slices, n_t, E, e_stride, hw, b, P, F, G4, mu, part);
+  const int hw = h * w;
+  const int64_t ntiles = (int64_t)n_t * ((b + kMT - 1) / kMT) * ((hw + kMT - 1) / kMT);
+  const int grid = part ? LRSTV_PARTS : (int)(ntiles < 2048 ? ntiles : 2048);
+  hipLaunchKernelGGL(k_band_idft, dim3(grid), dim3(256), 0, s, slices, n_t, E, e_stride, hw, b, F, G4, mu, part);
 }
 
 }  // namespace lrstv

@@ -190,4 +190,54 @@ LRSTV_DEV void mfma_ctile(int m0, int n0, int K, FA fa, FB fb, ST st, MfmaSmem& 
   }
 }
 
+// ----------------------------------------------------------- real tile ---
+// Real FP32 GEMM tile on v_mfma_f32_32x32x2f32: C(m0.., n0..) = sum_k
+// fa(m, k) fb(k, n), same block shape, staging and lane layouts as the
+// complex tile above.
+struct MfmaSmemR {
+  float a[kKC][kMT + 1], b[kKC][kMT + 1];
+};
+
+template <bool AK, bool BK, class FA, class FB, class ST>
+LRSTV_DEV void mfma_rtile(int m0, int n0, int K, FA fa, FB fb, ST st, MfmaSmemR& sm, bool active) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, wy = wv >> 1, wx = wv & 1;
+  const int li = lane & 31, lk = lane >> 5;
+  int ra, ka, rb, kb;
+  stage_coords<AK>(t, ra, ka);
+  stage_coords<BK>(t, rb, kb);
+  f32x16 c;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) c[i] = 0.f;
+  float va[8], vb[8];
+  fa(m0 + ra, ka, va);
+  fb(kb, n0 + rb, vb);
+  for (int k0 = 0; k0 < K; k0 += kKC) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      sm.a[ka + j][ra] = va[j];
+      sm.b[kb + j][rb] = vb[j];
+    }
+    __syncthreads();
+    if (k0 + kKC < K) {
+      fa(m0 + ra, k0 + kKC + ka, va);
+      fb(k0 + kKC + kb, n0 + rb, vb);
+    }
+    if (active) {
+#pragma unroll 4
+      for (int kk = 0; kk < kKC / 2; ++kk) {
+        const int k = 2 * kk + lk;
+        c = __builtin_amdgcn_mfma_f32_32x32x2f32(sm.a[k][32 * wy + li], sm.b[k][32 * wx + li], c, 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  if (!active) return;
+  const int col = n0 + 32 * wx + li;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = m0 + 32 * wy + 8 * (r >> 2) + 4 * lk + (r & 3);
+    st(row, col, c[r]);
+  }
+}
+
 }  // namespace lrstv
