@@ -100,6 +100,49 @@ def cpu_baseline(noisy, params_kw, iters):
                       f"(numpy FP64, {dt:.1f} s; per-iteration cost is roughly constant)"}
 
 
+def adjoint_bench(reps=3):
+    """Forward (K = 10, with per-iteration checkpoints) plus backward of the
+    MSE to the clean cubes, on 8 cubes 64x64x32 (the adjoint workload):
+    gradients with respect to the noisy input and tau, alpha, lambda.  GPU
+    time per forward+backward pair, measured with events on the current
+    stream (the library runs on it)."""
+    import numpy as np
+    import torch
+
+    import paper_2204_12879_amd as L
+    import synth
+    wl = synth.workload("diff")
+    pairs = [synth.make_cube(s) for s in wl.cubes]
+    shapes = [c[1].shape for c in pairs]
+    spec = wl.cubes[0]
+    Y = torch.from_numpy(np.concatenate([c[1].astype(np.float32).ravel() for c in pairs])).cuda()
+    Y.requires_grad_(True)
+    clean = torch.from_numpy(np.concatenate([c[0].astype(np.float32).ravel() for c in pairs])).cuda()
+    lam = 10.0 / np.sqrt(spec.h * spec.w)
+    times = []
+    for r in range(reps + 1):
+        tau = torch.tensor(0.02, dtype=torch.float64, requires_grad=True)
+        alpha = torch.tensor(0.3, dtype=torch.float64, requires_grad=True)
+        lt = torch.tensor(lam, dtype=torch.float64, requires_grad=True)
+        Y.grad = None
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        X = L.lrstv_unrolled(Y, tau, alpha, lt, shapes, wl.iters)
+        ((X - clean) ** 2).mean().backward()
+        e1.record()
+        torch.cuda.synchronize()
+        if r > 0:
+            times.append(e0.elapsed_time(e1))
+    ms = float(np.median(times))
+    return {"workload": f"{len(shapes)} cubes {spec.h}x{spec.w}x{spec.b}, K = {wl.iters} iterations forward "
+                        "(checkpointed) + adjoint backward of the MSE to the clean cubes, gradients w.r.t. Y, "
+                        "tau, alpha, lambda",
+            "ms_per_forward_backward": ms, "gradients_per_s": 1e3 / ms,
+            "grad_tau_alpha_lambda": [float(tau.grad), float(alpha.grad), float(lt.grad)],
+            "note": "includes solver set-up and checkpoint copies; median of %d" % reps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +153,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (the single-GPU share of the workload); "
@@ -223,6 +267,9 @@ def main():
             idx = g["index"]
             ref = g["values"]
             out["rel_err_vs_oracle_sampled"] = float(np.linalg.norm(Xg[idx] - ref) / np.linalg.norm(ref))
+    if not args.no_adjoint and args.workload == "wdc":
+        print("bench: timing the adjoint workload", file=sys.stderr, flush=True)
+        out["adjoint"] = adjoint_bench()
     if not args.no_cpu and len(shapes) == 1:
         print("bench: timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(noisy, pkw, args.cpu_iters)

@@ -64,9 +64,14 @@ struct CubeInfo {
 // tensors each.
 struct SliceLayout {
   std::vector<SliceDesc> desc;
-  int64_t slices_floats = 0, gram_c = 0, v_floats = 0, b_floats = 0, tri_d = 0, xs_d = 0, f_floats = 0;
+  int64_t slices_floats = 0, gram_c = 0, v_floats = 0, b_floats = 0, tri_d = 0, xs_d = 0, f_floats = 0,
+          wy_floats = 0;
   int max_n1 = 0, max_m1 = 0;
 };
+
+// T factors of the blocked back-transform: one 64 x 64 complex block per 64
+// reflectors (planar re / im).
+int64_t wy_block_floats(int n1) { return (int64_t)((n1 - 1 + 63) / 64) * 64 * 64 * 2; }
 
 SliceLayout make_slices(std::vector<CubeInfo>& cubes, int nt) {
   SliceLayout L;
@@ -94,12 +99,14 @@ SliceLayout make_slices(std::vector<CubeInfo>& cubes, int nt) {
         d.t_off = L.tri_d;
         d.x_off = L.xs_d;
         d.f_off = L.f_floats;
+        d.y_off = L.wy_floats;
         L.gram_c += (int64_t)n1 * (n1 + 1) / 2;
         L.v_floats += 2 * (int64_t)n1 * n1;
         L.b_floats += 2 * hw;
         L.tri_d += 6 * (int64_t)n1;
         L.xs_d += 3 * (int64_t)n1 * n1;
         L.f_floats += n1;
+        L.wy_floats += wy_block_floats(n1);
         L.desc.push_back(d);
       }
     L.slices_floats += (int64_t)nt * s * 2 * hw;
@@ -120,7 +127,7 @@ struct lrstv_handle_s {
   // state
   float *O, *L, *Z, *S, *G1, *G2, *F, *E, *G3, *G4;
   // scratch
-  float *T, *A, *slices, *V, *B, *fval;
+  float *T, *A, *slices, *V, *B, *fval, *Twy;
   float2 *spec, *gram;
   double *tri, *xs, *mu, *part, *res_last;
   int *rcount, *flag;
@@ -209,6 +216,7 @@ static void carve_handle(lrstv_handle_s* H, void* base, size_t* used) {
   H->B = cv.take<float>(H->sl.b_floats);
   H->tri = cv.take<double>(H->sl.tri_d);
   H->xs = cv.take<double>(H->sl.xs_d);
+  H->Twy = cv.take<float>(H->sl.wy_floats);
   H->fval = cv.take<float>(H->sl.f_floats);
   H->rcount = cv.take<int>(H->sl.desc.size());
   H->desc = cv.take<SliceDesc>(H->sl.desc.size());
@@ -360,6 +368,7 @@ static void run_iteration(lrstv_handle_s* H, double* res_user) {
   sv.B = H->B;
   sv.tri = H->tri;
   sv.xs = H->xs;
+  sv.Twy = H->Twy;
   sv.fval = H->fval;
   sv.rcount = H->rcount;
   sv.mu = H->mu;
@@ -680,6 +689,7 @@ extern "C" int lrstv_iterate_vjp(lrstv_handle H, const lrstv_state_view* before,
   J.fw.B = H->B;
   J.fw.tri = H->tri;
   J.fw.xs = H->xs;
+  J.fw.Twy = H->Twy;
   J.fw.fval = H->fval;
   J.fw.rcount = H->rcount;
   J.fw.mu = mu;
@@ -739,7 +749,7 @@ extern "C" int lrstv_save_state(lrstv_handle H, const lrstv_state_view* dst) {
 
 namespace {
 struct SvtWs {
-  float *slices, *V, *B, *fval;
+  float *slices, *V, *B, *fval, *Twy;
   float2* gram;
   double *tri, *xs;
   int* rcount;
@@ -753,6 +763,7 @@ void carve_svt(const SliceLayout& L, void* base, SvtWs* w, size_t* used) {
   w->B = cv.take<float>(L.b_floats);
   w->tri = cv.take<double>(L.tri_d);
   w->xs = cv.take<double>(L.xs_d);
+  w->Twy = cv.take<float>(L.wy_floats);
   w->fval = cv.take<float>(L.f_floats);
   w->rcount = cv.take<int>(L.desc.size());
   w->desc = cv.take<SliceDesc>(L.desc.size());
@@ -761,7 +772,8 @@ void carve_svt(const SliceLayout& L, void* base, SvtWs* w, size_t* used) {
 }  // namespace
 
 __global__ void k_make_desc(SliceDesc* out, int n, int b, int h, int w, int s,
-                            int64_t gram_c, int64_t v_f, int64_t b_f, int64_t tri_d, int64_t xs_d, int64_t f_f) {
+                            int64_t gram_c, int64_t v_f, int64_t b_f, int64_t tri_d, int64_t xs_d, int64_t f_f,
+                            int64_t y_f) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t hw = (int64_t)h * w;
@@ -784,6 +796,7 @@ __global__ void k_make_desc(SliceDesc* out, int n, int b, int h, int w, int s,
   d.t_off = (int64_t)i * tri_d;
   d.x_off = (int64_t)i * xs_d;
   d.f_off = (int64_t)i * f_f;
+  d.y_off = (int64_t)i * y_f;
   out[i] = d;
 }
 
@@ -833,7 +846,7 @@ extern "C" int lrstv_svt(const float* A, float* E, int32_t h, int32_t w, int32_t
   prepare_svt(n1);
   hipLaunchKernelGGL(k_make_desc, dim3((ns + 255) / 256), dim3(256), 0, s, ws.desc, ns, (int)b, h, w, b / 2 + 1,
                      (int64_t)n1 * (n1 + 1) / 2, 2 * (int64_t)n1 * n1, 2 * hw, 6 * (int64_t)n1, 3 * (int64_t)n1 * n1,
-                     (int64_t)n1);
+                     (int64_t)n1, wy_block_floats(n1));
   launch_band_dft(A, (int64_t)b * hw, batch, ws.slices, h, w, b, s);
   SvtLaunch sv;
   sv.desc = ws.desc;
@@ -846,6 +859,7 @@ extern "C" int lrstv_svt(const float* A, float* E, int32_t h, int32_t w, int32_t
   sv.B = ws.B;
   sv.tri = ws.tri;
   sv.xs = ws.xs;
+  sv.Twy = ws.Twy;
   sv.fval = ws.fval;
   sv.rcount = ws.rcount;
   sv.mu = nullptr;
@@ -898,7 +912,7 @@ extern "C" int lrstv_svt_vjp(const float* A, const float* G, float* gA, int32_t 
   prepare_svt(n1);
   hipLaunchKernelGGL(k_make_desc, dim3((ns + 255) / 256), dim3(256), 0, s, sw.desc, ns, (int)b, h, w, b / 2 + 1,
                      (int64_t)n1 * (n1 + 1) / 2, 2 * (int64_t)n1 * n1, 2 * hw, 6 * (int64_t)n1, 3 * (int64_t)n1 * n1,
-                     (int64_t)n1);
+                     (int64_t)n1, wy_block_floats(n1));
   std::vector<int64_t> range = column_ranges(L, batch);
   HIPCHK(hipMemcpyAsync(vw.range, range.data(), range.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
   launch_fill(vw.ones, L.f_floats, 1.f, s);
@@ -915,6 +929,7 @@ extern "C" int lrstv_svt_vjp(const float* A, const float* G, float* gA, int32_t 
   J.fw.B = sw.B;
   J.fw.tri = sw.tri;
   J.fw.xs = sw.xs;
+  J.fw.Twy = sw.Twy;
   J.fw.fval = sw.fval;
   J.fw.rcount = sw.rcount;
   J.fw.mu = nullptr;

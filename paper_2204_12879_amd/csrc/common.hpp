@@ -103,6 +103,8 @@ struct SliceDesc {
   int64_t t_off;     // double offset of the tridiagonal scratch (d, |e|, phase re/im)
   int64_t x_off;     // double offset of the eigenvector scratch (3 n1 x n1)
   int64_t f_off;     // float offset of the n1 shrink factors
+  int64_t y_off;     // float offset of the block-reflector T factors
+                     // (ceil((n1-1)/64) blocks of 64 x 64 complex, planar)
 };
 
 }  // namespace lrstv

@@ -14,7 +14,8 @@
 //   k_trieig     FP64 Sturm bisection for the eigenvalues above the
 //                threshold and eigenvectors by twisted factorisations
 //                (per unreduced block), cluster re-orthogonalisation
-//   k_backtrans  V <- Q (phase * z), applying the stored reflectors
+//   k_wy_t,      V <- Q (phase * z): the stored reflectors in blocks of 64
+//   k_wy_apply   (compact WY form), applied with MFMA products
 //   k_bp1        B = M V_r  (or U_r^H M), MFMA as the Gram
 //   k_colnorm    sigma_i = ||M v_i|| (taken from M, not from the squared
 //                Gram eigenvalue), f_i = max(1 - t/sigma_i, 0)
@@ -26,6 +27,17 @@
 #include "common.hpp"
 #include "kernels.hpp"
 #include "mfma.hpp"
+
+// Tridiagonalisation shape: waves per slice and VGPR-resident rows per wave.
+// 16 waves (4 per SIMD) hide the LDS and cross-lane latency of the per-row
+// reductions better than 8 (measured 6.6 vs 8.7 ms per iteration at
+// 288 slices of 256 x 256); 6 rows per wave keep the LDS part under 160 KB.
+#ifndef LRSTV_TRIDIAG_NW
+#define LRSTV_TRIDIAG_NW 16
+#endif
+#ifndef LRSTV_TRIDIAG_JR
+#define LRSTV_TRIDIAG_JR 6
+#endif
 
 namespace lrstv {
 
@@ -249,18 +261,17 @@ __global__ void __launch_bounds__(256) k_tridiag(const SliceDesc* __restrict__ d
 }
 
 // Householder reduction with the packed Gram held on-chip, for n1 <= 256.
-// 512 threads (8 waves).  Rows [RL, n) of the packed lower triangle live in
-// VGPRs: row r = RL + wave + 8 j (j < JR), lane l holds columns l + 64 u
-// (u < 4); rows [0, RL) live in LDS.  RL = max(0, n - 8 JR).
+// NW waves.  Rows [RL, n) of the packed lower triangle live in VGPRs:
+// row r = RL + wave + NW j (j < JR), lane l holds columns l + 64 u (u < 4);
+// rows [0, RL) live in LDS.  RL = max(0, n - NW JR).
 // Three barriers per step: (1) after the symmetric product, whose pass also
 // accumulates v^H A v, (2) after p and w = p - K v are formed, (3) after the
 // rank-2 update, whose pass also extracts the next column, its norm and the
 // next diagonal.  Every thread forms the reflector itself from the reduced
 // norm; v = [1; scl * x] is applied on the fly from the unscaled column x.
-template <int JR>
-__global__ void __launch_bounds__(512) k_tridiag_reg(const SliceDesc* __restrict__ desc, float2* __restrict__ gram,
-                                                     double* __restrict__ tri) {
-  constexpr int NW = 8;
+template <int JR, int NW>
+__global__ void __launch_bounds__(64 * NW) k_tridiag_reg(const SliceDesc* __restrict__ desc,
+                                                         float2* __restrict__ gram, double* __restrict__ tri) {
   extern __shared__ float2 sm[];
   // red_nx and s_dii are written for step i+1 while step i may still read them
   // (the no-reflection path has no barrier in between): double-buffered by parity.
@@ -879,62 +890,131 @@ __global__ void __launch_bounds__(1024) k_trieig(const SliceDesc* __restrict__ d
   if (threadIdx.x == 0) rcount[blockIdx.x] = r;
 }
 
-// ------------------------------------------------------- back-transform ---
-// V[:, c0:c0+cb] <- H_0 H_1 ... H_{n-2} V[:, c0:c0+cb]   (cb divides 256)
-__global__ void __launch_bounds__(256) k_backtrans(const SliceDesc* __restrict__ desc, const float2* __restrict__ gram,
-                                                   const double* __restrict__ tri, float* __restrict__ V,
-                                                   const int* __restrict__ rcount, int cb) {
-  extern __shared__ float2 sm[];
-  __shared__ float2 sdot[64];
+// ------------------------------------------- blocked back-transform (WY) ---
+// V <- H_0 H_1 ... H_{n-2} V with the reflectors grouped 64 at a time:
+// H_{i0} ... H_{i0+63} = I - Y T Y^H (Y: the block's reflectors as columns,
+// T upper triangular, T_jj = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] Y^H y_j),
+// applied from the last block to the first as V -= Y (T (Y^H V)), three
+// complex products on the matrix cores per block.
+
+// Y(k, p) of the block starting at reflector i0: matrix row i0 + 1 + k,
+// reflector i0 + p (zero above its leading 1 and past the last reflector).
+LRSTV_DEV float2 wy_y(const float2* __restrict__ g, int n, int i0, int nbk, int k, int p) {
+  const int row = i0 + 1 + k;
+  if (p >= nbk || row >= n || k < p) return make_float2(0.f, 0.f);
+  return g[packed(row, i0 + p)];
+}
+
+// T factor of reflector block blockIdx.x of slice blockIdx.y.
+__global__ void __launch_bounds__(256) k_wy_t(const SliceDesc* __restrict__ desc, const float2* __restrict__ gram,
+                                              const double* __restrict__ tri, float* __restrict__ Twy,
+                                              const int* __restrict__ rcount) {
+  __shared__ MfmaSmem sm;
+  __shared__ float2 S[64][64];
   const SliceDesc d = desc[blockIdx.y];
-  const int n = d.n1, r = rcount[blockIdx.y];
-  const int c0 = blockIdx.x * cb;
-  if (c0 >= r) return;
-  const int nc = min(cb, r - c0);
-  const int ngrp = blockDim.x / cb;
-  float2* Y = sm;                 // [n][cb]
-  float2* vv = Y + n * cb;        // [n]
-  float2* part = vv + n;          // [ngrp][cb]
-  const int64_t nn = (int64_t)n * n;
-  float* Vr = V + d.v_off;
-  float* Vi = Vr + nn;
-  for (int e = threadIdx.x; e < n * cb; e += blockDim.x) {
-    const int i = e / cb, c = e - i * cb;
-    Y[e] = (c < nc) ? make_float2(Vr[(int64_t)i * n + c0 + c], Vi[(int64_t)i * n + c0 + c]) : make_float2(0.f, 0.f);
-  }
+  const int n = d.n1, nblk = (n - 1 + 63) / 64, b = blockIdx.x;
+  if (b >= nblk || rcount[blockIdx.y] == 0) return;
+  const int i0 = 64 * b, m = n - 1 - i0, nbk = m < 64 ? m : 64;
   const float2* g = gram + d.g_off;
   const double* taus = tri + d.t_off + 4 * n;
+  // S = Y^H Y
+  auto fa = [&](int p, int k) -> float2 {
+    const float2 y = (k < m) ? wy_y(g, n, i0, nbk, k, p) : make_float2(0.f, 0.f);
+    return make_float2(y.x, -y.y);
+  };
+  auto fb = [&](int k, int q) -> float2 { return (k < m) ? wy_y(g, n, i0, nbk, k, q) : make_float2(0.f, 0.f); };
+  auto st = [&](int p, int q, float2 v) { S[p][q] = v; };
+  mfma_ctile<kF32, false, false>(0, 0, m, fa, fb, st, sm, true);
   __syncthreads();
-  const int c = threadIdx.x % cb, grp = threadIdx.x / cb;
-  for (int i = n - 2; i >= 0; --i) {
-    const float tau = (float)taus[i];
-    if (tau == 0.f) continue;
-    const int m = n - 1 - i;
-    for (int rr = threadIdx.x; rr < m; rr += blockDim.x) vv[rr] = g[packed(i + 1 + rr, i)];
-    __syncthreads();
-    float2 s = make_float2(0.f, 0.f);
-    for (int rr = grp; rr < m; rr += ngrp) s = cadd(s, cmulc(vv[rr], Y[(i + 1 + rr) * cb + c]));
-    part[grp * cb + c] = s;
-    __syncthreads();
-    if (threadIdx.x < cb) {
-      float2 t = part[threadIdx.x];
-      for (int q = 1; q < ngrp; ++q) t = cadd(t, part[q * cb + threadIdx.x]);
-      sdot[threadIdx.x] = cscale(t, tau);
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < m * cb; e += blockDim.x) {
-      const int rr = e / cb, cc = e - rr * cb;
-      Y[(i + 1 + rr) * cb + cc] = csub(Y[(i + 1 + rr) * cb + cc], cmul(vv[rr], sdot[cc]));
+  float2(*T)[64] = reinterpret_cast<float2(*)[64]>(&sm);
+  for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) T[e >> 6][e & 63] = make_float2(0.f, 0.f);
+  __syncthreads();
+  for (int j = 0; j < nbk; ++j) {
+    const float tj = (float)taus[i0 + j];
+    const int p = threadIdx.x;
+    if (p < j) {
+      float2 acc = make_float2(0.f, 0.f);
+      for (int q = p; q < j; ++q) acc = cadd(acc, cmul(T[p][q], S[q][j]));
+      T[p][j] = make_float2(-tj * acc.x, -tj * acc.y);
+    } else if (p == j) {
+      T[j][j] = make_float2(tj, 0.f);
     }
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < n * cb; e += blockDim.x) {
-    const int i = e / cb, cc = e - i * cb;
-    if (cc < nc) {
-      Vr[(int64_t)i * n + c0 + cc] = Y[e].x;
-      Vi[(int64_t)i * n + c0 + cc] = Y[e].y;
-    }
+  float* out = Twy + d.y_off + (int64_t)b * 64 * 64 * 2;
+  for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+    out[e] = T[e >> 6][e & 63].x;
+    out[64 * 64 + e] = T[e >> 6][e & 63].y;
   }
+}
+
+// Column tile blockIdx.x (64 columns of V) of slice blockIdx.y: every
+// reflector block, last to first, on the same columns.
+__global__ void __launch_bounds__(256) k_wy_apply(const SliceDesc* __restrict__ desc, const float2* __restrict__ gram,
+                                                  const float* __restrict__ Twy, float* __restrict__ V,
+                                                  const int* __restrict__ rcount) {
+  __shared__ MfmaSmem sm;
+  __shared__ float2 W[64][64];
+  const SliceDesc d = desc[blockIdx.y];
+  const int n = d.n1, r = rcount[blockIdx.y], c0 = 64 * blockIdx.x;
+  if (c0 >= r) return;
+  const int nc = (r - c0) < 64 ? (r - c0) : 64;
+  const int nblk = (n - 1 + 63) / 64;
+  const float2* g = gram + d.g_off;
+  float* Vr = V + d.v_off;
+  float* Vi = Vr + (int64_t)n * n;
+  const int wv = threadIdx.x >> 6;
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int i0 = 64 * b, m = n - 1 - i0, nbk = m < 64 ? m : 64;
+    const float* Tr = Twy + d.y_off + (int64_t)b * 64 * 64 * 2;
+    const float* Ti = Tr + 64 * 64;
+    // (1) W = Y^H V[i0+1:, c0:c0+64]
+    {
+      auto fa = [&](int p, int k) -> float2 {
+        const float2 y = (k < m) ? wy_y(g, n, i0, nbk, k, p) : make_float2(0.f, 0.f);
+        return make_float2(y.x, -y.y);
+      };
+      auto fb = [&](int k, int c) -> float2 {
+        if (k >= m || c >= nc) return make_float2(0.f, 0.f);
+        const int64_t q = (int64_t)(i0 + 1 + k) * n + c0 + c;
+        return make_float2(Vr[q], Vi[q]);
+      };
+      auto st = [&](int p, int c, float2 v) { W[p][c] = v; };
+      mfma_ctile<kF32, false, false>(0, 0, m, fa, fb, st, sm, true);
+    }
+    __syncthreads();
+    // (2) W <- T W
+    {
+      auto fa = [&](int p, int q) -> float2 { return make_float2(Tr[p * 64 + q], Ti[p * 64 + q]); };
+      auto fb = [&](int q, int c) -> float2 { return W[q][c]; };
+      auto st = [&](int p, int c, float2 v) { W[p][c] = v; };
+      mfma_ctile<kF32, true, false>(0, 0, 64, fa, fb, st, sm, true);
+    }
+    __syncthreads();
+    // (3) V[i0+1:, cols] -= Y W, one 64-row tile at a time
+    for (int kt = 0; kt < m; kt += 64) {
+      auto fa = [&](int k, int q) -> float2 { return (k < m) ? wy_y(g, n, i0, nbk, k, q) : make_float2(0.f, 0.f); };
+      auto fb = [&](int q, int c) -> float2 { return W[q][c]; };
+      auto st = [&](int k, int c, float2 v) {
+        if (k < m && c < nc) {
+          const int64_t q = (int64_t)(i0 + 1 + k) * n + c0 + c;
+          Vr[q] -= v.x;
+          Vi[q] -= v.y;
+        }
+      };
+      const bool active = kt + 32 * (wv >> 1) < m;
+      mfma_ctile<kF32, true, false>(kt, 0, 64, fa, fb, st, sm, active);
+    }
+    __syncthreads();
+  }
+}
+
+void launch_backtrans(const SvtLaunch& L, hipStream_t s) {
+  const int n = L.max_n1, ns = L.n_slices;
+  const int nblk = (n - 1 + 63) / 64;
+  if (nblk == 0 || ns == 0) return;
+  hipLaunchKernelGGL(k_wy_t, dim3(nblk, ns), dim3(256), 0, s, L.desc, L.gram, L.tri, L.Twy, L.rcount);
+  hipLaunchKernelGGL(k_wy_apply, dim3((n + 63) / 64, ns), dim3(256), 0, s, L.desc, L.gram, L.Twy, L.V, L.rcount);
 }
 
 // ----------------------------------------------------- back-projection ---
@@ -1263,16 +1343,36 @@ __global__ void __launch_bounds__(256) k_vjp_r(const SliceDesc* __restrict__ des
 }
 
 // ------------------------------------------------------------ launcher ---
-constexpr int kTridiagRegRows = 10;
+constexpr int kTridiagRegRows = LRSTV_TRIDIAG_JR;
+constexpr int kTridiagWaves = LRSTV_TRIDIAG_NW;
 // Dynamic LDS granted to k_tridiag_reg (host-side function attribute, set
 // once outside any stream capture by prepare_svt).
 static size_t g_tridiag_lds_granted = 65536;
+
+// Dynamic LDS of k_tridiag_reg: the packed LDS rows plus (3 + NW) n complex
+// (two columns, w, NW column-part rows).
+static size_t tridiag_reg_lds(int n) {
+  constexpr int JR = kTridiagRegRows, NW = kTridiagWaves;
+  const int RL = n > NW * JR ? n - NW * JR : 0;
+  return ((size_t)RL * (RL + 1) / 2 + (size_t)(3 + NW) * n) * sizeof(float2);
+}
+
+static void launch_tridiag(const SvtLaunch& L, hipStream_t s) {
+  constexpr int JR = kTridiagRegRows, NW = kTridiagWaves;
+  const int n = L.max_n1, ns = L.n_slices;
+  const size_t lds = tridiag_reg_lds(n);
+  if (n <= 256 && lds <= g_tridiag_lds_granted)
+    hipLaunchKernelGGL((k_tridiag_reg<JR, NW>), dim3(ns), dim3(64 * NW), lds, s, L.desc, L.gram, L.tri);
+  else
+    hipLaunchKernelGGL(k_tridiag<false>, dim3(ns), dim3(256), (size_t)(2 + 4) * n * sizeof(float2), s, L.desc,
+                       L.gram, L.tri);
+}
 
 void prepare_svt(int max_n1) {
   const int n = max_n1;
   constexpr int JR = kTridiagRegRows;
   const int RL = n > 8 * JR ? n - 8 * JR : 0;
-  const size_t reg_lds = ((size_t)RL * (RL + 1) / 2 + (size_t)(3 + 8) * n) * sizeof(float2);
+  const size_t reg_lds = tridiag_reg_lds(n);
   if (n > 256 || reg_lds <= g_tridiag_lds_granted) return;
   int dev = 0;
   hipDeviceProp_t prop;
@@ -1280,7 +1380,7 @@ void prepare_svt(int max_n1) {
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
     lds_max = (int)prop.sharedMemPerBlock;
   if ((int)reg_lds + 2048 > lds_max) return;
-  if (hipFuncSetAttribute((const void*)k_tridiag_reg<JR>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  if (hipFuncSetAttribute((const void*)k_tridiag_reg<JR, kTridiagWaves>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)reg_lds) == hipSuccess)
     g_tridiag_lds_granted = reg_lds;
   else
@@ -1304,30 +1404,15 @@ void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm) {
     hipLaunchKernelGGL(k_gram<kF32>, dim3(TT * (TT + 1) / 2, ns), dim3(256), 0, s, L.desc, L.slices, L.gram);
   T.end(ST_GRAM);
   T.begin(ST_TRIDIAG);
-  constexpr int JR = kTridiagRegRows;
-  const int RL = n > 8 * JR ? n - 8 * JR : 0;
-  const size_t reg_lds = ((size_t)RL * (RL + 1) / 2 + (size_t)(3 + 8) * n) * sizeof(float2);
-  const bool use_reg = n <= 256 && reg_lds <= g_tridiag_lds_granted;
-  if (use_reg) {
-    hipLaunchKernelGGL(k_tridiag_reg<JR>, dim3(ns), dim3(512), reg_lds, s, L.desc, L.gram, L.tri);
-  } else {
-    hipLaunchKernelGGL(k_tridiag<false>, dim3(ns), dim3(256), (size_t)(2 + 4) * n * sizeof(float2), s, L.desc,
-                       L.gram, L.tri);
-  }
+  launch_tridiag(L, s);
   T.end(ST_TRIDIAG);
   const size_t eig_lds = (size_t)5 * n * sizeof(double) + (size_t)(n + 1) * sizeof(int);
   T.begin(ST_TRIEIG);
   hipLaunchKernelGGL(k_trieig, dim3(ns), dim3(1024), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount, L.mu, L.alpha,
                      L.thresh);
   T.end(ST_TRIEIG);
-  // Column chunk fixed per size class (not derived from this batch's largest
-  // slice), so a slice's reduction order, hence its rounding, does not depend
-  // on which other slices share the launch.
-  const int cb = n <= 256 ? 16 : 8;
-  const size_t bt_lds = ((size_t)n * cb + n + 256) * sizeof(float2);
   T.begin(ST_BACKTRANS);
-  hipLaunchKernelGGL(k_backtrans, dim3((n + cb - 1) / cb, ns), dim3(256), bt_lds, s, L.desc, L.gram, L.tri, L.V,
-                     L.rcount, cb);
+  launch_backtrans(L, s);
   T.end(ST_BACKTRANS);
   // B: tall h x r, wide r x w -> tiles over (max(n, m)) both ways
   T.begin(ST_BP1);
@@ -1358,21 +1443,11 @@ void launch_svt_vjp(const SvtVjpLaunch& J, hipStream_t s) {
   const int TT = (n + kMT - 1) / kMT, TM = (m + kMT - 1) / kMT;
   // full eigendecomposition of every Gram (thresh < 0: all eigenpairs)
   hipLaunchKernelGGL(k_gram<kF32>, dim3(TT * (TT + 1) / 2, ns), dim3(256), 0, s, L.desc, L.slices, L.gram);
-  constexpr int JR = kTridiagRegRows;
-  const int RL = n > 8 * JR ? n - 8 * JR : 0;
-  const size_t reg_lds = ((size_t)RL * (RL + 1) / 2 + (size_t)(3 + 8) * n) * sizeof(float2);
-  if (n <= 256 && reg_lds <= g_tridiag_lds_granted)
-    hipLaunchKernelGGL(k_tridiag_reg<JR>, dim3(ns), dim3(512), reg_lds, s, L.desc, L.gram, L.tri);
-  else
-    hipLaunchKernelGGL(k_tridiag<false>, dim3(ns), dim3(256), (size_t)(2 + 4) * n * sizeof(float2), s, L.desc,
-                       L.gram, L.tri);
+  launch_tridiag(L, s);
   const size_t eig_lds = (size_t)5 * n * sizeof(double) + (size_t)(n + 1) * sizeof(int);
   hipLaunchKernelGGL(k_trieig, dim3(ns), dim3(1024), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount,
                      (const double*)nullptr, 0.0, -1.f);
-  const int cb = n <= 256 ? 16 : 8;
-  const size_t bt_lds = ((size_t)n * cb + n + 256) * sizeof(float2);
-  hipLaunchKernelGGL(k_backtrans, dim3((n + cb - 1) / cb, ns), dim3(256), bt_lds, s, L.desc, L.gram, L.tri, L.V,
-                     L.rcount, cb);
+  launch_backtrans(L, s);
   // B = M V, C = D V (or U^H M, U^H D)
   hipLaunchKernelGGL(k_bp1<kF32>, dim3(TM, TM, ns), dim3(256), 0, s, L.desc, L.slices, L.V, L.B, L.rcount);
   hipLaunchKernelGGL(k_bp1<kF32>, dim3(TM, TM, ns), dim3(256), 0, s, L.desc, J.dsl, L.V, J.C, L.rcount);

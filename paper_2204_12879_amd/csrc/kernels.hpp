@@ -81,6 +81,7 @@ struct SvtLaunch {
   double* tri;             // tridiagonal scratch
   double* xs;              // eigenvector scratch
   float* fval;             // shrink factors
+  float* Twy;              // T factors of the blocked back-transform
   int* rcount;             // surviving singular values per slice
   const double* mu;        // device mu or NULL
   double alpha;            // threshold numerator (t = alpha / mu) when mu != NULL
