@@ -56,6 +56,7 @@ struct Carve {
 struct CubeInfo {
   int h, w, b, s;
   int64_t off;         // element offset in the packed batch
+  int64_t spec_off;    // complex offset of the half spectrum (Z-solve scratch)
   int64_t slice0;      // index of the first slice of this cube
   int64_t slice_base;  // float offset of this cube's slices
 };
@@ -120,7 +121,7 @@ SliceLayout make_slices(std::vector<CubeInfo>& cubes, int nt) {
 
 struct lrstv_handle_s {
   std::vector<CubeInfo> cubes;
-  int64_t total = 0, nmax = 0, specmax = 0;
+  int64_t total = 0, nmax = 0, specmax = 0, spec_total = 0;
   lrstv_params par;
   hipStream_t stream;
   SliceLayout sl;
@@ -132,6 +133,9 @@ struct lrstv_handle_s {
   double *tri, *xs, *mu, *part, *res_last;
   int *rcount, *flag;
   SliceDesc* desc;
+  CubeGeo* geo;        // device [n_cubes]
+  int* bstart;         // device [PH_COUNT][n_cubes + 1]
+  BatchTab bt[PH_COUNT];
   StageTimer timer;
   // per-cube index ranges of the per-column t-SVT threshold terms (adjoint)
   std::vector<int64_t> acon_range;
@@ -167,13 +171,14 @@ static int check_dims(int h, int w, int b) {
 }
 
 static int build_cubes(const lrstv_problem* prob, std::vector<CubeInfo>& cubes, int64_t& total, int64_t& nmax,
-                       int64_t& specmax) {
+                       int64_t& specmax, int64_t& spec_total) {
   if (!prob || prob->n_cubes < 1 || !prob->h || !prob->w || !prob->b)
     return fail(LRSTV_ERR_INVALID_ARG, "problem must list n_cubes >= 1 with h, w, b arrays");
   cubes.clear();
   total = 0;
   nmax = 0;
   specmax = 0;
+  spec_total = 0;
   for (int c = 0; c < prob->n_cubes; ++c) {
     const int h = prob->h[c], w = prob->w[c], b = prob->b[c];
     int rc = check_dims(h, w, b);
@@ -189,6 +194,8 @@ static int build_cubes(const lrstv_problem* prob, std::vector<CubeInfo>& cubes, 
     if (N > nmax) nmax = N;
     const int64_t sp = (int64_t)b * h * (w / 2 + 1);
     if (sp > specmax) specmax = sp;
+    ci.spec_off = spec_total;
+    spec_total += sp;
     cubes.push_back(ci);
   }
   return LRSTV_OK;
@@ -207,9 +214,9 @@ static void carve_handle(lrstv_handle_s* H, void* base, size_t* used) {
   H->E = cv.take<float>(3 * T);
   H->G3 = cv.take<float>(3 * T);
   H->G4 = cv.take<float>(3 * T);
-  H->T = cv.take<float>(H->nmax);
-  H->A = cv.take<float>(3 * H->nmax);
-  H->spec = cv.take<float2>(H->specmax);
+  H->T = cv.take<float>(T);
+  H->A = cv.take<float>(3 * T);
+  H->spec = cv.take<float2>(H->spec_total);
   H->slices = cv.take<float>(H->sl.slices_floats);
   H->gram = cv.take<float2>(H->sl.gram_c);
   H->V = cv.take<float>(H->sl.v_floats);
@@ -220,6 +227,8 @@ static void carve_handle(lrstv_handle_s* H, void* base, size_t* used) {
   H->fval = cv.take<float>(H->sl.f_floats);
   H->rcount = cv.take<int>(H->sl.desc.size());
   H->desc = cv.take<SliceDesc>(H->sl.desc.size());
+  H->geo = cv.take<CubeGeo>(nc);
+  H->bstart = cv.take<int>(PH_COUNT * (nc + 1));
   H->mu = cv.take<double>(1);
   H->part = cv.take<double>(nc * R_COUNT * LRSTV_PARTS);
   H->res_last = cv.take<double>(nc * R_COUNT);
@@ -232,7 +241,7 @@ extern "C" int lrstv_workspace_size(const lrstv_problem* prob, const lrstv_param
   int rc = check_params(par);
   if (rc) return rc;
   lrstv_handle_s H;
-  rc = build_cubes(prob, H.cubes, H.total, H.nmax, H.specmax);
+  rc = build_cubes(prob, H.cubes, H.total, H.nmax, H.specmax, H.spec_total);
   if (rc) return rc;
   H.sl = make_slices(H.cubes, 3);
   carve_handle(&H, nullptr, bytes);
@@ -249,7 +258,7 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
   if (((uintptr_t)workspace & 255) != 0) return fail(LRSTV_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
   lrstv_handle_s* H = new (std::nothrow) lrstv_handle_s();
   if (!H) return fail(LRSTV_ERR_INVALID_ARG, "out of host memory");
-  rc = build_cubes(prob, H->cubes, H->total, H->nmax, H->specmax);
+  rc = build_cubes(prob, H->cubes, H->total, H->nmax, H->specmax, H->spec_total);
   if (rc) { delete H; return rc; }
   H->par = *par;
   H->stream = (hipStream_t)stream;
@@ -262,8 +271,44 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
     return fail(LRSTV_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
   }
   carve_handle(H, workspace, &need);
+  // cube geometry and per-phase block ranges of the batched launches
+  const int nc = (int)H->cubes.size();
+  std::vector<CubeGeo> geo(nc);
+  std::vector<int> bstart((size_t)PH_COUNT * (nc + 1), 0);
+  size_t lds_w = 0, lds_h = 0;
+  for (int c = 0; c < nc; ++c) {
+    const CubeInfo& ci = H->cubes[c];
+    CubeGeo& g = geo[c];
+    g.h = ci.h;
+    g.w = ci.w;
+    g.b = ci.b;
+    g.nb_w = geo_rows_nb(ci.w);
+    g.cw_h = geo_cols_cw(ci.h);
+    g.off = ci.off;
+    g.spec_off = ci.spec_off;
+    g.slice_base = ci.slice_base;
+    const size_t lw = (size_t)(2 * g.nb_w + 1) * ci.w * sizeof(float2);
+    const size_t lh = (size_t)(2 * g.cw_h + 1) * ci.h * sizeof(float2);
+    if (lw > lds_w) lds_w = lw;
+    if (lh > lds_h) lds_h = lh;
+    for (int ph = 0; ph < PH_COUNT; ++ph)
+      bstart[(size_t)ph * (nc + 1) + c + 1] = bstart[(size_t)ph * (nc + 1) + c] + phase_blocks(ph, ci.h, ci.w, ci.b);
+  }
+  for (int ph = 0; ph < PH_COUNT; ++ph) {
+    BatchTab& bt = H->bt[ph];
+    bt.geo = H->geo;
+    bt.bstart = H->bstart + (size_t)ph * (nc + 1);
+    bt.nc = nc;
+    bt.nblocks = bstart[(size_t)ph * (nc + 1) + nc];
+    bt.lds_w = lds_w;
+    bt.lds_h = lds_h;
+  }
   hipError_t e = hipMemcpyAsync(H->desc, H->sl.desc.data(), H->sl.desc.size() * sizeof(SliceDesc),
                                 hipMemcpyHostToDevice, H->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(H->geo, geo.data(), geo.size() * sizeof(CubeGeo), hipMemcpyHostToDevice, H->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(H->bstart, bstart.data(), bstart.size() * sizeof(int), hipMemcpyHostToDevice, H->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(H->stream);
   if (e != hipSuccess) {
     delete H;
@@ -296,27 +341,27 @@ extern "C" int lrstv_reset(lrstv_handle H, const float* Y) {
   return LRSTV_OK;
 }
 
-static CubePtrs cube_ptrs(lrstv_handle_s* H, const CubeInfo& c) {
-  CubePtrs p;
-  p.h = c.h;
-  p.w = c.w;
-  p.b = c.b;
-  p.ts = H->total;
-  p.O = H->O + c.off;
-  p.L = H->L + c.off;
-  p.Z = H->Z + c.off;
-  p.S = H->S + c.off;
-  p.G1 = H->G1 + c.off;
-  p.G2 = H->G2 + c.off;
-  p.F = H->F + c.off;
-  p.E = H->E + c.off;
-  p.G3 = H->G3 + c.off;
-  p.G4 = H->G4 + c.off;
+static BatchPtrs batch_ptrs(lrstv_handle_s* H) {
+  BatchPtrs p;
+  p.O = H->O;
+  p.L = H->L;
+  p.Z = H->Z;
+  p.S = H->S;
+  p.G1 = H->G1;
+  p.G2 = H->G2;
+  p.F = H->F;
+  p.E = H->E;
+  p.G3 = H->G3;
+  p.G4 = H->G4;
   p.A = H->A;
   p.T = H->T;
+  p.ts = H->total;
   return p;
 }
 
+// One iteration over the whole batch: every stencil, FFT and band-transform
+// phase is one launch over all cubes (per-cube block ranges), the slice SVT
+// one launch per kernel over all slices.
 static void run_iteration(lrstv_handle_s* H, double* res_user) {
   hipStream_t s = H->stream;
   StageTimer& tm = H->timer;
@@ -326,36 +371,32 @@ static void run_iteration(lrstv_handle_s* H, double* res_user) {
   wt.lam = H->par.lambda;
   for (int i = 0; i < 3; ++i) wt.w[i] = H->par.w[i];
   const int nc = (int)H->cubes.size();
-  for (int c = 0; c < nc; ++c) {
-    const CubeInfo& ci = H->cubes[c];
-    CubePtrs p = cube_ptrs(H, ci);
-    double* part = H->part + (int64_t)c * R_COUNT * LRSTV_PARTS;
-    tm.begin(ST_LRHS);
-    launch_lrhs(p, wt, H->mu, s);                                   // 1st step + T_z
-    tm.end(ST_LRHS);
-    tm.begin(ST_RFFT_W);
-    launch_rfft_w(p.T, H->spec, ci.h, ci.w, ci.b, s);               // 2nd step: Z solve
-    tm.end(ST_RFFT_W);
-    tm.begin(ST_FFT_H);
-    launch_fft_h(H->spec, ci.h, ci.w, ci.b, -1, s);
-    tm.end(ST_FFT_H);
-    tm.begin(ST_TRI_B);
-    launch_tri_b(H->spec, ci.h, ci.w, ci.b, wt.w, H->mu, 0.0, s);
-    tm.end(ST_TRI_B);
-    tm.begin(ST_FFT_H);
-    launch_fft_h(H->spec, ci.h, ci.w, ci.b, +1, s);
-    tm.end(ST_FFT_H);
-    tm.begin(ST_IRFFT_W);
-    launch_irfft_w(H->spec, p.Z, ci.h, ci.w, ci.b, part, s);
-    tm.end(ST_IRFFT_W);
-    // 3rd, 5th and 6th steps (F, S, Gamma1..3); A = F - Gamma4/mu into scratch
-    tm.begin(ST_GRAD_SHRINK);
-    launch_grad_shrink(p, wt, H->mu, part, H->nmax, s);
-    tm.end(ST_GRAD_SHRINK);
-    tm.begin(ST_BAND_DFT);
-    launch_band_dft(H->A, H->nmax, 3, H->slices + ci.slice_base, ci.h, ci.w, ci.b, s);
-    tm.end(ST_BAND_DFT);
-  }
+  const BatchPtrs bp = batch_ptrs(H);
+  tm.begin(ST_LRHS);
+  launch_lrhs_batch(H->bt[PH_LRHS], bp, wt, H->mu, s);                  // 1st step + T_z
+  tm.end(ST_LRHS);
+  tm.begin(ST_RFFT_W);
+  launch_rfft_w_batch(H->bt[PH_RFFT_W], H->T, H->spec, s);              // 2nd step: Z solve
+  tm.end(ST_RFFT_W);
+  tm.begin(ST_FFT_H);
+  launch_fft_h_batch(H->bt[PH_FFT_H], H->spec, -1, s);
+  tm.end(ST_FFT_H);
+  tm.begin(ST_TRI_B);
+  launch_tri_b_batch(H->bt[PH_TRI_B], H->spec, wt.w, H->mu, s);
+  tm.end(ST_TRI_B);
+  tm.begin(ST_FFT_H);
+  launch_fft_h_batch(H->bt[PH_FFT_H], H->spec, +1, s);
+  tm.end(ST_FFT_H);
+  tm.begin(ST_IRFFT_W);
+  launch_irfft_w_batch(H->bt[PH_PARTS], H->spec, H->Z, H->part, s);
+  tm.end(ST_IRFFT_W);
+  // 3rd, 5th and 6th steps (F, S, Gamma1..3); A = F - Gamma4/mu into scratch
+  tm.begin(ST_GRAD_SHRINK);
+  launch_grad_shrink_batch(H->bt[PH_PARTS], bp, wt, H->mu, H->part, s);
+  tm.end(ST_GRAD_SHRINK);
+  tm.begin(ST_BAND_DFT);
+  launch_band_dft_batch(H->bt[PH_BAND_DFT], H->A, H->total, H->slices, s);
+  tm.end(ST_BAND_DFT);
   // 4th step: t-SVT of every Fourier slice of every gradient tensor
   SvtLaunch sv;
   sv.desc = H->desc;
@@ -376,14 +417,9 @@ static void run_iteration(lrstv_handle_s* H, double* res_user) {
   sv.thresh = 0.f;
   sv.precision = H->par.precision;
   launch_svt(sv, s, &tm);
-  for (int c = 0; c < nc; ++c) {
-    const CubeInfo& ci = H->cubes[c];
-    double* part = H->part + (int64_t)c * R_COUNT * LRSTV_PARTS;
-    tm.begin(ST_BAND_IDFT);
-    launch_band_idft(H->slices + ci.slice_base, 3, H->E + ci.off, H->total, ci.h, ci.w, ci.b, H->F + ci.off,
-                     H->G4 + ci.off, H->mu, part, s);
-    tm.end(ST_BAND_IDFT);
-  }
+  tm.begin(ST_BAND_IDFT);
+  launch_band_idft_batch(H->bt[PH_PARTS], H->slices, H->E, H->total, H->F, H->G4, H->mu, H->part, s);
+  tm.end(ST_BAND_IDFT);
   tm.begin(ST_FINISH);
   launch_finish_iter(H->part, nc, H->mu, H->res_last, res_user, H->flag, s);
   launch_mu_step(H->mu, H->par.rho, H->par.mu_max, s);               // 7th step
@@ -569,9 +605,10 @@ void carve_vjp(const SliceLayout& L, int64_t total, int64_t nmax, int nc, void* 
   w->gL = cv.take<float>(total);
   w->gZp = cv.take<float>(total);
   w->gFp = cv.take<float>(3 * total);
-  w->dirE = cv.take<float>(3 * nmax);
-  w->gA = cv.take<float>(3 * nmax);
-  w->gT = cv.take<float>(nmax);
+  w->dirE = cv.take<float>(3 * total);
+  w->gA = cv.take<float>(3 * total);
+  w->gT = cv.take<float>(total);
+  (void)nmax;
   w->part = cv.take<double>((int64_t)nc * 2 * LRSTV_PARTS);
   w->range = cv.take<int64_t>(2 * (int64_t)nc);
   *used = cv.off + 256;
@@ -638,7 +675,7 @@ extern "C" int lrstv_iterate_vjp(lrstv_handle H, const lrstv_state_view* before,
     c.w = ci.w;
     c.b = ci.b;
     c.ts = T;
-    c.as = H->nmax;
+    c.as = T;
     c.G4 = before->G4 + o;
     c.S1 = after->S + o;
     c.F1 = after->F + o;
@@ -663,8 +700,8 @@ extern "C" int lrstv_iterate_vjp(lrstv_handle H, const lrstv_state_view* before,
     c.gL = w.gL + o;
     c.gZp = w.gZp + o;
     c.gFp = w.gFp + o;
-    c.dirE = w.dirE;
-    c.A = H->A;
+    c.dirE = w.dirE + o;
+    c.A = H->A + o;
     c.gY = grad_Y + o;
     c.initial = (flags & LRSTV_VJP_INITIAL) != 0;
     return c;
@@ -674,8 +711,8 @@ extern "C" int lrstv_iterate_vjp(lrstv_handle H, const lrstv_state_view* before,
     const CubeInfo& ci = H->cubes[c];
     VjpCube vc = cube_view(ci);
     launch_vjp_post(vc, mu, w.part + (int64_t)c * 2 * LRSTV_PARTS + LRSTV_PARTS, s);
-    launch_band_dft(H->A, H->nmax, 3, H->slices + ci.slice_base, ci.h, ci.w, ci.b, s);
-    launch_band_dft(w.dirE, H->nmax, 3, w.dsl + ci.slice_base, ci.h, ci.w, ci.b, s);
+    launch_band_dft(H->A + ci.off, T, 3, H->slices + ci.slice_base, ci.h, ci.w, ci.b, s);
+    launch_band_dft(w.dirE + ci.off, T, 3, w.dsl + ci.slice_base, ci.h, ci.w, ci.b, s);
   }
   // 4th step: derivative of every slice SVT along its direction
   SvtVjpLaunch J;
@@ -708,16 +745,17 @@ extern "C" int lrstv_iterate_vjp(lrstv_handle H, const lrstv_state_view* before,
   for (int c = 0; c < nc; ++c) {
     const CubeInfo& ci = H->cubes[c];
     VjpCube vc = cube_view(ci);
-    launch_band_idft(w.dsl + ci.slice_base, 3, w.gA, H->nmax, ci.h, ci.w, ci.b, nullptr, nullptr, nullptr, nullptr,
-                     s);
-    launch_vjp_shrinkf(vc, w.gA, mu, w.part + (int64_t)c * 2 * LRSTV_PARTS, s);
-    launch_vjp_divt(vc, H->T, H->par.w, s);
-    launch_rfft_w(H->T, H->spec, ci.h, ci.w, ci.b, s);
-    launch_fft_h(H->spec, ci.h, ci.w, ci.b, -1, s);
-    launch_tri_b(H->spec, ci.h, ci.w, ci.b, H->par.w, mu, 0.0, s);
-    launch_fft_h(H->spec, ci.h, ci.w, ci.b, +1, s);
-    launch_irfft_w(H->spec, w.gT, ci.h, ci.w, ci.b, nullptr, s);
-    launch_vjp_pre(vc, w.gT, H->par.w, mu, s);
+    float* gA = w.gA + ci.off;
+    float2* spec = H->spec + ci.spec_off;
+    launch_band_idft(w.dsl + ci.slice_base, 3, gA, T, ci.h, ci.w, ci.b, nullptr, nullptr, nullptr, nullptr, s);
+    launch_vjp_shrinkf(vc, gA, mu, w.part + (int64_t)c * 2 * LRSTV_PARTS, s);
+    launch_vjp_divt(vc, H->T + ci.off, H->par.w, s);
+    launch_rfft_w(H->T + ci.off, spec, ci.h, ci.w, ci.b, s);
+    launch_fft_h(spec, ci.h, ci.w, ci.b, -1, s);
+    launch_tri_b(spec, ci.h, ci.w, ci.b, H->par.w, mu, 0.0, s);
+    launch_fft_h(spec, ci.h, ci.w, ci.b, +1, s);
+    launch_irfft_w(spec, w.gT + ci.off, ci.h, ci.w, ci.b, nullptr, s);
+    launch_vjp_pre(vc, w.gT + ci.off, H->par.w, mu, s);
   }
   launch_vjp_finish(w.part, w.acon, w.range, nc, grad_weights, s);
   HIPCHK(hipGetLastError());

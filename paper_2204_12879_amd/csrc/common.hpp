@@ -26,6 +26,17 @@ LRSTV_DEV float soft_threshold(float x, float t) {
   return m > 0.f ? copysignf(m, x) : 0.f;
 }
 
+// Cube owning block `blk` of a batched launch: bstart[c] <= blk < bstart[c+1].
+LRSTV_DEV int find_cube(const int* __restrict__ bstart, int nc, int blk) {
+  int lo = 0, hi = nc;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (bstart[mid] <= blk) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // ------------------------------------------------------------- reductions ---
 LRSTV_DEV double warp_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

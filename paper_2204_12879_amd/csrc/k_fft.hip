@@ -164,9 +164,8 @@ LRSTV_DEV float2* fft_lds(float2* bufA, float2* bufB, int N, int nb, const float
 // ---------------------------------------------------------------------------
 // Real FFT along w, two rows packed in one complex transform.
 // T: rows r = j*h + i of length w; spec rows of length wc = w/2 + 1.
-__global__ void __launch_bounds__(256) k_rfft_w(const float* __restrict__ T, float2* __restrict__ spec, int nrows,
+LRSTV_DEV void rfft_w_body(int bid, int nblk, float2* sm, const float* __restrict__ T, float2* __restrict__ spec, int nrows,
                                                 int w, int nb) {
-  extern __shared__ float2 sm[];
   float2* tw = sm;
   float2* bA = sm + w;
   float2* bB = bA + nb * w;
@@ -175,7 +174,7 @@ __global__ void __launch_bounds__(256) k_rfft_w(const float* __restrict__ T, flo
   make_plan(w, p);
   fill_twiddles(tw, w);
   const int rows_per_block = 2 * nb;
-  for (int r0 = blockIdx.x * rows_per_block; r0 < nrows; r0 += gridDim.x * rows_per_block) {
+  for (int r0 = bid * rows_per_block; r0 < nrows; r0 += nblk * rows_per_block) {
     for (int t = threadIdx.x; t < nb * w; t += blockDim.x) {
       const int f = t / w, x = t - f * w;
       const int ra = r0 + 2 * f, rb = ra + 1;
@@ -200,11 +199,16 @@ __global__ void __launch_bounds__(256) k_rfft_w(const float* __restrict__ T, flo
   }
 }
 
+__global__ void __launch_bounds__(256) k_rfft_w(const float* __restrict__ T, float2* __restrict__ spec, int nrows,
+                                                int w, int nb) {
+  extern __shared__ float2 sm[];
+  rfft_w_body(blockIdx.x, gridDim.x, sm, T, spec, nrows, w, nb);
+}
+
 // Inverse of k_rfft_w (scaled by `scale`), writing real rows into Z.  If
 // `part` is set, also accumulates sum (Z_new - Z_old)^2 per block.
-__global__ void __launch_bounds__(256) k_irfft_w(const float2* __restrict__ spec, float* __restrict__ Z, int nrows,
+LRSTV_DEV void irfft_w_body(int bid, int nblk, float2* sm, const float2* __restrict__ spec, float* __restrict__ Z, int nrows,
                                                  int w, int nb, float scale, double* __restrict__ part) {
-  extern __shared__ float2 sm[];
   __shared__ double red[8];
   float2* tw = sm;
   float2* bA = sm + w;
@@ -215,7 +219,7 @@ __global__ void __launch_bounds__(256) k_irfft_w(const float2* __restrict__ spec
   fill_twiddles(tw, w);
   double acc = 0.0;
   const int rows_per_block = 2 * nb;
-  for (int r0 = blockIdx.x * rows_per_block; r0 < nrows; r0 += gridDim.x * rows_per_block) {
+  for (int r0 = bid * rows_per_block; r0 < nrows; r0 += nblk * rows_per_block) {
     for (int t = threadIdx.x; t < nb * w; t += blockDim.x) {
       const int f = t / w, k = t - f * w;
       const int ra = r0 + 2 * f, rb = ra + 1;
@@ -258,13 +262,18 @@ __global__ void __launch_bounds__(256) k_irfft_w(const float2* __restrict__ spec
   }
   if (part) {
     acc = block_sum(acc, red);
-    if (threadIdx.x == 0) part[R_DUAL_Z * LRSTV_PARTS + blockIdx.x] = acc;
+    if (threadIdx.x == 0) part[R_DUAL_Z * LRSTV_PARTS + bid] = acc;
   }
 }
 
-// Complex FFT along h of spec [b][h][wc], cw columns per block.
-__global__ void __launch_bounds__(256) k_fft_h(float2* __restrict__ spec, int h, int wc, int b, int cw, int sign) {
+__global__ void __launch_bounds__(256) k_irfft_w(const float2* __restrict__ spec, float* __restrict__ Z, int nrows,
+                                                 int w, int nb, float scale, double* __restrict__ part) {
   extern __shared__ float2 sm[];
+  irfft_w_body(blockIdx.x, gridDim.x, sm, spec, Z, nrows, w, nb, scale, part);
+}
+
+// Complex FFT along h of spec [b][h][wc], cw columns per block.
+LRSTV_DEV void fft_h_body(int bid, int nblk, float2* sm, float2* __restrict__ spec, int h, int wc, int b, int cw, int sign) {
   float2* tw = sm;
   float2* bA = sm + h;
   float2* bB = bA + cw * h;
@@ -272,7 +281,7 @@ __global__ void __launch_bounds__(256) k_fft_h(float2* __restrict__ spec, int h,
   make_plan(h, p);
   fill_twiddles(tw, h);
   const int nchunk = (wc + cw - 1) / cw;
-  for (int blk = blockIdx.x; blk < b * nchunk; blk += gridDim.x) {
+  for (int blk = bid; blk < b * nchunk; blk += nblk) {
     const int j = blk / nchunk, c0 = (blk - j * nchunk) * cw;
     float2* base = spec + (int64_t)j * h * wc;
     for (int t = threadIdx.x; t < cw * h; t += blockDim.x) {
@@ -289,14 +298,19 @@ __global__ void __launch_bounds__(256) k_fft_h(float2* __restrict__ spec, int h,
   }
 }
 
+__global__ void __launch_bounds__(256) k_fft_h(float2* __restrict__ spec, int h, int wc, int b, int cw, int sign) {
+  extern __shared__ float2 sm[];
+  fft_h_body(blockIdx.x, gridDim.x, sm, spec, h, wc, b, cw, sign);
+}
+
 // Periodic tridiagonal solve along the bands for every (k_h, k_w).
-__global__ void __launch_bounds__(256) k_tri_b(float2* __restrict__ spec, int h, int w, int b, double w1, double w2,
+LRSTV_DEV void tri_b_body(int bid, int nblk, float2* __restrict__ spec, int h, int w, int b, double w1, double w2,
                                                double w3, const double* __restrict__ mu_dev, double mu_host) {
   const int wc = w / 2 + 1;
   const int64_t plane = (int64_t)h * wc;
   const double mu = mu_dev ? *mu_dev : mu_host;
-  for (int64_t col = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; col < plane;
-       col += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t col = bid * (int64_t)blockDim.x + threadIdx.x; col < plane;
+       col += (int64_t)nblk * blockDim.x) {
     const int i = (int)(col / wc), kw = (int)(col - (int64_t)i * wc);
     const double sh = sinpi((double)i / h), sw = sinpi((double)kw / w);
     const double a = mu * (1.0 + 4.0 * (w1 * w1 * sh * sh + w2 * w2 * sw * sw));
@@ -350,6 +364,11 @@ __global__ void __launch_bounds__(256) k_tri_b(float2* __restrict__ spec, int h,
   }
 }
 
+__global__ void __launch_bounds__(256) k_tri_b(float2* __restrict__ spec, int h, int w, int b, double w1, double w2,
+                                               double w3, const double* __restrict__ mu_dev, double mu_host) {
+  tri_b_body(blockIdx.x, gridDim.x, spec, h, w, b, w1, w2, w3, mu_dev, mu_host);
+}
+
 // ---------------------------------------------------------------------------
 // Band DFT of real tensors as a real matrix product on the matrix cores:
 //   X (2s x hw) = F (2s x b) A (b x hw),  s = b/2 + 1,
@@ -359,7 +378,7 @@ __global__ void __launch_bounds__(256) k_tri_b(float2* __restrict__ spec, int h,
 // from an LDS table of cos / sin(2 pi m / b) (index j k mod b, advanced
 // incrementally).  Tiles are walked with the row tile fastest so that the
 // blocks sharing a column strip of A run together (L2 reuse).
-__global__ void __launch_bounds__(256) k_band_dft(const float* __restrict__ A, int64_t a_stride, int n_t,
+LRSTV_DEV void band_dft_body(int bid, int nblk, const float* __restrict__ A, int64_t a_stride, int n_t,
                                                   float* __restrict__ out, int hw, int b) {
   __shared__ MfmaSmemR sm;
   __shared__ float ct[LRSTV_MAX_SIDE_DEV], st[LRSTV_MAX_SIDE_DEV];
@@ -374,7 +393,7 @@ __global__ void __launch_bounds__(256) k_band_dft(const float* __restrict__ A, i
   const int TM = (M + kMT - 1) / kMT, TN = (hw + kMT - 1) / kMT;
   const int ntiles = n_t * TM * TN;
   const int wv = threadIdx.x >> 6;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (int tile = bid; tile < ntiles; tile += nblk) {
     const int t = tile / (TM * TN), rem = tile - t * TM * TN;
     const int tn = rem / TM, tm = rem - tn * TM;
     const int m0 = tm * kMT, n0 = tn * kMT;
@@ -404,13 +423,18 @@ __global__ void __launch_bounds__(256) k_band_dft(const float* __restrict__ A, i
   }
 }
 
+__global__ void __launch_bounds__(256) k_band_dft(const float* __restrict__ A, int64_t a_stride, int n_t,
+                                                  float* __restrict__ out, int hw, int b) {
+  band_dft_body(blockIdx.x, gridDim.x, A, a_stride, n_t, out, hw, b);
+}
+
 // Inverse band DFT with Hermitian completion, as the real product
 //   E (b x hw) = G (b x 2s) X (2s x hw),
 //   G[j][2k] = c_k cos(2 pi j k / b) / b,  G[j][2k+1] = -c_k sin(2 pi j k / b) / b,
 // c_k = 1 for k = 0 and k = b/2, else 2 (slice k stands for k and b - k).
 // Epilogue (optional): Gamma4 += mu (E - F) and FP64 partial sums of
 // (E - F)^2, one fixed slot per block (grid = LRSTV_PARTS when part != NULL).
-__global__ void __launch_bounds__(256) k_band_idft(const float* __restrict__ X, int n_t, float* __restrict__ E,
+LRSTV_DEV void band_idft_body(int bid, int nblk, const float* __restrict__ X, int n_t, float* __restrict__ E,
                                                    int64_t e_stride, int hw, int b,
                                                    const float* __restrict__ F, float* __restrict__ G4,
                                                    const double* __restrict__ mu_dev, double* __restrict__ part) {
@@ -431,7 +455,7 @@ __global__ void __launch_bounds__(256) k_band_idft(const float* __restrict__ X, 
   const int ntiles = n_t * TM * TN;
   const int wv = threadIdx.x >> 6;
   double acc = 0.0;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (int tile = bid; tile < ntiles; tile += nblk) {
     const int t = tile / (TM * TN), rem = tile - t * TM * TN;
     const int tn = rem / TM, tm = rem - tn * TM;
     const int m0 = tm * kMT, n0 = tn * kMT;
@@ -475,16 +499,95 @@ __global__ void __launch_bounds__(256) k_band_idft(const float* __restrict__ X, 
   }
   if (part) {
     acc = block_sum(acc, red);
-    if (threadIdx.x == 0) part[R_FRO_EF * LRSTV_PARTS + blockIdx.x] = acc;
+    if (threadIdx.x == 0) part[R_FRO_EF * LRSTV_PARTS + bid] = acc;
   }
 }
 
+__global__ void __launch_bounds__(256) k_band_idft(const float* __restrict__ X, int n_t, float* __restrict__ E,
+                                                   int64_t e_stride, int hw, int b,
+                                                   const float* __restrict__ F, float* __restrict__ G4,
+                                                   const double* __restrict__ mu_dev, double* __restrict__ part) {
+  band_idft_body(blockIdx.x, gridDim.x, X, n_t, E, e_stride, hw, b, F, G4, mu_dev, part);
+}
+
 // ------------------------------------------------------------ launchers ---
+
+// ------------------------------------------------------ batched phases ---
+// All cubes of a packed ragged batch in one launch per phase.  Block b of the
+// launch belongs to cube c with bt.bstart[c] <= b < bt.bstart[c + 1]; within
+// the cube it runs as block b - bstart[c] of a grid of bstart[c+1] - bstart[c]
+// blocks, the grid that cube would get alone (so its results, reductions
+// included, do not depend on the other cubes).
+struct CubeSel {
+  int c, bid, nblk;
+};
+LRSTV_DEV CubeSel select_cube(const BatchTab& bt) {
+  CubeSel r;
+  r.c = find_cube(bt.bstart, bt.nc, blockIdx.x);
+  r.bid = blockIdx.x - bt.bstart[r.c];
+  r.nblk = bt.bstart[r.c + 1] - bt.bstart[r.c];
+  return r;
+}
+
+__global__ void __launch_bounds__(256) k_rfft_w_batch(BatchTab bt, const float* __restrict__ T,
+                                                      float2* __restrict__ spec) {
+  extern __shared__ float2 sm[];
+  const CubeSel q = select_cube(bt);
+  const CubeGeo g = bt.geo[q.c];
+  rfft_w_body(q.bid, q.nblk, sm, T + g.off, spec + g.spec_off, g.h * g.b, g.w, g.nb_w);
+}
+
+__global__ void __launch_bounds__(256) k_irfft_w_batch(BatchTab bt, const float2* __restrict__ spec,
+                                                       float* __restrict__ Z, double* __restrict__ part) {
+  extern __shared__ float2 sm[];
+  const int c = blockIdx.x / LRSTV_PARTS;
+  const CubeGeo g = bt.geo[c];
+  irfft_w_body(blockIdx.x - c * LRSTV_PARTS, LRSTV_PARTS, sm, spec + g.spec_off, Z + g.off, g.h * g.b, g.w, g.nb_w,
+               1.0f / ((float)g.h * (float)g.w), part ? part + (int64_t)c * R_COUNT * LRSTV_PARTS : nullptr);
+}
+
+__global__ void __launch_bounds__(256) k_fft_h_batch(BatchTab bt, float2* __restrict__ spec, int sign) {
+  extern __shared__ float2 sm[];
+  const CubeSel q = select_cube(bt);
+  const CubeGeo g = bt.geo[q.c];
+  fft_h_body(q.bid, q.nblk, sm, spec + g.spec_off, g.h, g.w / 2 + 1, g.b, g.cw_h, sign);
+}
+
+__global__ void __launch_bounds__(256) k_tri_b_batch(BatchTab bt, float2* __restrict__ spec, double w1, double w2,
+                                                     double w3, const double* __restrict__ mu_dev) {
+  const CubeSel q = select_cube(bt);
+  const CubeGeo g = bt.geo[q.c];
+  tri_b_body(q.bid, q.nblk, spec + g.spec_off, g.h, g.w, g.b, w1, w2, w3, mu_dev, 0.0);
+}
+
+// A: component stride a_stride from the cube's offset; slices at slice_base
+__global__ void __launch_bounds__(256) k_band_dft_batch(BatchTab bt, const float* __restrict__ A, int64_t a_stride,
+                                                        float* __restrict__ slices) {
+  const CubeSel q = select_cube(bt);
+  const CubeGeo g = bt.geo[q.c];
+  band_dft_body(q.bid, q.nblk, A + g.off, a_stride, 3, slices + g.slice_base, g.h * g.w, g.b);
+}
+
+__global__ void __launch_bounds__(256) k_band_idft_batch(BatchTab bt, const float* __restrict__ slices,
+                                                         float* __restrict__ E, int64_t e_stride,
+                                                         const float* __restrict__ F, float* __restrict__ G4,
+                                                         const double* __restrict__ mu_dev, double* __restrict__ part) {
+  const int c = blockIdx.x / LRSTV_PARTS;
+  const CubeGeo g = bt.geo[c];
+  band_idft_body(blockIdx.x - c * LRSTV_PARTS, LRSTV_PARTS, slices + g.slice_base, 3, E + g.off, e_stride,
+                 g.h * g.w, g.b, F + g.off, G4 + g.off, mu_dev, part + (int64_t)c * R_COUNT * LRSTV_PARTS);
+}
 
 static int rows_nb(int w) {
   int nb = 8;
   while (nb > 1 && (2 * nb + 1) * w * 8 > 48 * 1024) nb >>= 1;
   return nb;
+}
+
+static int cols_cw(int h) {
+  int cw = 16;
+  while (cw > 1 && (2 * cw + 1) * h * 8 > 48 * 1024) cw >>= 1;
+  return cw;
 }
 
 void launch_rfft_w(const float* T, float2* spec, int h, int w, int b, hipStream_t s) {
@@ -504,8 +607,7 @@ void launch_irfft_w(const float2* spec, float* Z, int h, int w, int b, double* p
 
 void launch_fft_h(float2* spec, int h, int w, int b, int sign, hipStream_t s) {
   const int wc = w / 2 + 1;
-  int cw = 16;
-  while (cw > 1 && (2 * cw + 1) * h * 8 > 48 * 1024) cw >>= 1;
+  const int cw = cols_cw(h);
   const size_t lds = (size_t)(2 * cw + 1) * h * sizeof(float2);
   int grid = b * ((wc + cw - 1) / cw);
   if (grid > 8192) grid = 8192;
@@ -538,6 +640,63 @@ void launch_band_idft(const float* slices, int n_t, float* E, int64_t e_stride, 
   const int64_t ntiles = (int64_t)n_t * ((b + kMT - 1) / kMT) * ((hw + kMT - 1) / kMT);
   const int grid = part ? LRSTV_PARTS : (int)(ntiles < 2048 ? ntiles : 2048);
   hipLaunchKernelGGL(k_band_idft, dim3(grid), dim3(256), 0, s, slices, n_t, E, e_stride, hw, b, F, G4, mu, part);
+}
+
+// ---------------------------------------------------- batched launchers ---
+// Per-cube block counts of each phase (host), the same as the single-cube
+// launchers would use.
+int phase_blocks(int phase, int h, int w, int b) {
+  const int64_t N = (int64_t)h * w * b;
+  const int wc = w / 2 + 1;
+  switch (phase) {
+    case PH_LRHS: { const int64_t g = (N + 255) / 256; return (int)(g < 8192 ? g : 8192); }
+    case PH_RFFT_W: {
+      const int nb = rows_nb(w);
+      const int64_t g = ((int64_t)h * b + 2 * nb - 1) / (2 * nb);
+      return (int)(g < 4096 ? g : 4096);
+    }
+    case PH_FFT_H: {
+      const int cw = cols_cw(h);
+      const int64_t g = (int64_t)b * ((wc + cw - 1) / cw);
+      return (int)(g < 8192 ? g : 8192);
+    }
+    case PH_TRI_B: return (int)(((int64_t)h * wc + 255) / 256);
+    case PH_BAND_DFT: {
+      const int M = 2 * (b / 2 + 1);
+      const int64_t t = (int64_t)3 * ((M + kMT - 1) / kMT) * (((int64_t)h * w + kMT - 1) / kMT);
+      return (int)(t < 2048 ? t : 2048);
+    }
+    default: return LRSTV_PARTS;
+  }
+}
+
+int geo_rows_nb(int w) { return rows_nb(w); }
+int geo_cols_cw(int h) { return cols_cw(h); }
+
+void launch_rfft_w_batch(const BatchTab& bt, const float* T, float2* spec, hipStream_t s) {
+  hipLaunchKernelGGL(k_rfft_w_batch, dim3(bt.nblocks), dim3(256), bt.lds_w, s, bt, T, spec);
+}
+
+void launch_irfft_w_batch(const BatchTab& bt, const float2* spec, float* Z, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_irfft_w_batch, dim3(bt.nc * LRSTV_PARTS), dim3(256), bt.lds_w, s, bt, spec, Z, part);
+}
+
+void launch_fft_h_batch(const BatchTab& bt, float2* spec, int sign, hipStream_t s) {
+  hipLaunchKernelGGL(k_fft_h_batch, dim3(bt.nblocks), dim3(256), bt.lds_h, s, bt, spec, sign);
+}
+
+void launch_tri_b_batch(const BatchTab& bt, float2* spec, const double wts[3], const double* mu, hipStream_t s) {
+  hipLaunchKernelGGL(k_tri_b_batch, dim3(bt.nblocks), dim3(256), 0, s, bt, spec, wts[0], wts[1], wts[2], mu);
+}
+
+void launch_band_dft_batch(const BatchTab& bt, const float* A, int64_t a_stride, float* slices, hipStream_t s) {
+  hipLaunchKernelGGL(k_band_dft_batch, dim3(bt.nblocks), dim3(256), 0, s, bt, A, a_stride, slices);
+}
+
+void launch_band_idft_batch(const BatchTab& bt, const float* slices, float* E, int64_t e_stride, const float* F,
+                            float* G4, const double* mu, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_band_idft_batch, dim3(bt.nc * LRSTV_PARTS), dim3(256), 0, s, bt, slices, E, e_stride, F, G4,
+                     mu, part);
 }
 
 }  // namespace lrstv

@@ -33,16 +33,15 @@ __global__ void k_set_mu(double* mu, double v) {
 // L = 1/2 (O - S + Z + (Gamma1 - Gamma2)/mu)
 // T_z = mu L + Gamma2 + sum_n w_n D_n^T (mu F_n - Gamma3_n),
 // (D_n^T y)[v] = y[v - e_n] - y[v].
-__global__ void __launch_bounds__(256) k_lrhs(const float* __restrict__ O, const float* __restrict__ S,
-                                              const float* __restrict__ Z, const float* __restrict__ G1,
-                                              const float* __restrict__ G2, const float* __restrict__ F,
-                                              const float* __restrict__ G3, int64_t ts, float* __restrict__ L,
-                                              float* __restrict__ Tz, int h, int w, int b, float w1, float w2,
-                                              float w3, const double* __restrict__ mu_dev) {
+LRSTV_DEV void lrhs_body(int bid, int nblk, const float* __restrict__ O, const float* __restrict__ S,
+                         const float* __restrict__ Z, const float* __restrict__ G1, const float* __restrict__ G2,
+                         const float* __restrict__ F, const float* __restrict__ G3, int64_t ts,
+                         float* __restrict__ L, float* __restrict__ Tz, int h, int w, int b, float w1, float w2,
+                         float w3, const double* __restrict__ mu_dev) {
   const int64_t hw = (int64_t)h * w, N = hw * b;
   const double mud = *mu_dev;
   const float mu = (float)mud, imu = (float)(1.0 / mud);
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < N; q += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t q = bid * (int64_t)blockDim.x + threadIdx.x; q < N; q += (int64_t)nblk * blockDim.x) {
     const int x = (int)(q % w);
     const int i = (int)((q / w) % h);
     const int j = (int)(q / hw);
@@ -62,6 +61,18 @@ __global__ void __launch_bounds__(256) k_lrhs(const float* __restrict__ O, const
   }
 }
 
+
+// All cubes of a packed batch in one launch: block ranges per cube from
+// bt.bstart (each cube keeps the block count it would have alone).
+__global__ void __launch_bounds__(256) k_lrhs_batch(BatchTab bt, BatchPtrs p, float w1, float w2, float w3,
+                                                    const double* __restrict__ mu_dev) {
+  const int c = find_cube(bt.bstart, bt.nc, blockIdx.x);
+  const CubeGeo g = bt.geo[c];
+  const int64_t o = g.off;
+  lrhs_body(blockIdx.x - bt.bstart[c], bt.bstart[c + 1] - bt.bstart[c], p.O + o, p.S + o, p.Z + o, p.G1 + o,
+            p.G2 + o, p.F + o, p.G3 + o, p.ts, p.L + o, p.T + o, g.h, g.w, g.b, w1, w2, w3, mu_dev);
+}
+
 // G_n = w_n D_n Z (forward, periodic)
 // F_n = R_{tau/mu}( 1/2 (G_n + Gamma3_n/mu + E_n + Gamma4_n/mu) )
 // Gamma3_n += mu (G_n - F_n);   A_n = F_n - Gamma4_n / mu
@@ -69,13 +80,13 @@ __global__ void __launch_bounds__(256) k_lrhs(const float* __restrict__ O, const
 // S = R_{lambda/mu}(O - L + Gamma1/mu);   Gamma1 += mu (O - L - S)
 // Residual partials (one per block, fixed grid of LRSTV_PARTS blocks):
 //   max|O-L-S|, max|L-Z|, sum (O-L-S)^2, sum (L-Z)^2, sum_n (G_n - F_n)^2.
-__global__ void __launch_bounds__(256) k_grad_shrink(
-    const float* __restrict__ O, const float* __restrict__ L, const float* __restrict__ Z, float* __restrict__ S,
-    float* __restrict__ G1, float* __restrict__ G2, float* __restrict__ F, const float* __restrict__ E,
-    float* __restrict__ G3, const float* __restrict__ G4, float* __restrict__ A, int64_t ts, int64_t as, int h,
-    int w, int b,
-    float w1, float w2, float w3, float tau, float lam, const double* __restrict__ mu_dev,
-    double* __restrict__ part /* [R_COUNT][LRSTV_PARTS] of this cube */) {
+LRSTV_DEV void grad_shrink_body(
+    int bid, const float* __restrict__ O, const float* __restrict__ L, const float* __restrict__ Z,
+    float* __restrict__ S, float* __restrict__ G1, float* __restrict__ G2, float* __restrict__ F,
+    const float* __restrict__ E, float* __restrict__ G3, const float* __restrict__ G4, float* __restrict__ A,
+    int64_t ts, int64_t as, int h, int w, int b, float w1, float w2, float w3, float tau, float lam,
+    const double* __restrict__ mu_dev, double* __restrict__ part /* [R_COUNT][LRSTV_PARTS] of this cube */) {
+  constexpr int nblk = LRSTV_PARTS;
   __shared__ double red[8];
   const int64_t hw = (int64_t)h * w, N = hw * b;
   const double mud = *mu_dev;
@@ -83,7 +94,7 @@ __global__ void __launch_bounds__(256) k_grad_shrink(
   const float tmu = (float)(tau / mud), lmu = (float)(lam / mud);
   const float wn[3] = {w1, w2, w3};
   double m_ols = 0, m_lz = 0, s_ols = 0, s_lz = 0, s_dzf = 0;
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < N; q += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t q = bid * (int64_t)blockDim.x + threadIdx.x; q < N; q += (int64_t)nblk * blockDim.x) {
     const int x = (int)(q % w);
     const int i = (int)((q / w) % h);
     const int j = (int)(q / hw);
@@ -120,12 +131,25 @@ __global__ void __launch_bounds__(256) k_grad_shrink(
   s_lz = block_sum(s_lz, red);
   s_dzf = block_sum(s_dzf, red);
   if (threadIdx.x == 0) {
-    part[R_INF_OLS * LRSTV_PARTS + blockIdx.x] = m_ols;
-    part[R_INF_LZ * LRSTV_PARTS + blockIdx.x] = m_lz;
-    part[R_FRO_OLS * LRSTV_PARTS + blockIdx.x] = s_ols;
-    part[R_FRO_LZ * LRSTV_PARTS + blockIdx.x] = s_lz;
-    part[R_FRO_DZF * LRSTV_PARTS + blockIdx.x] = s_dzf;
+    part[R_INF_OLS * LRSTV_PARTS + bid] = m_ols;
+    part[R_INF_LZ * LRSTV_PARTS + bid] = m_lz;
+    part[R_FRO_OLS * LRSTV_PARTS + bid] = s_ols;
+    part[R_FRO_LZ * LRSTV_PARTS + bid] = s_lz;
+    part[R_FRO_DZF * LRSTV_PARTS + bid] = s_dzf;
   }
+}
+
+
+// Batch: LRSTV_PARTS blocks per cube, cube c's residual slots at part + c R_COUNT LRSTV_PARTS.
+__global__ void __launch_bounds__(256) k_grad_shrink_batch(BatchTab bt, BatchPtrs p, float w1, float w2, float w3,
+                                                           float tau, float lam, const double* __restrict__ mu_dev,
+                                                           double* __restrict__ part) {
+  const int c = blockIdx.x / LRSTV_PARTS;
+  const CubeGeo g = bt.geo[c];
+  const int64_t o = g.off;
+  grad_shrink_body(blockIdx.x - c * LRSTV_PARTS, p.O + o, p.L + o, p.Z + o, p.S + o, p.G1 + o, p.G2 + o, p.F + o,
+                   p.E + o, p.G3 + o, p.G4 + o, p.A + o, p.ts, p.ts, g.h, g.w, g.b, w1, w2, w3, tau, lam, mu_dev,
+                   part + (int64_t)c * R_COUNT * LRSTV_PARTS);
 }
 
 // One block per cube: fixed-order reduction of the residual partials.
@@ -195,20 +219,7 @@ void launch_set_mu(double* mu, double v, hipStream_t s) {
   hipLaunchKernelGGL(k_set_mu, dim3(1), dim3(64), 0, s, mu, v);
 }
 
-void launch_lrhs(const CubePtrs& c, const Weights& wt, const double* mu, hipStream_t s) {
-  const int64_t N = (int64_t)c.h * c.w * c.b;
-  int grid = (int)((N + 255) / 256);
-  if (grid > 8192) grid = 8192;
-  hipLaunchKernelGGL(k_lrhs, dim3(grid), dim3(256), 0, s, c.O, c.S, c.Z, c.G1, c.G2, c.F, c.G3, c.ts, c.L, c.T,
-                     c.h, c.w, c.b, (float)wt.w[0], (float)wt.w[1], (float)wt.w[2], mu);
-}
 
-void launch_grad_shrink(const CubePtrs& c, const Weights& wt, const double* mu, double* part, int64_t a_stride,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_grad_shrink, dim3(LRSTV_PARTS), dim3(256), 0, s, c.O, c.L, c.Z, c.S, c.G1, c.G2, c.F, c.E,
-                     c.G3, c.G4, c.A, c.ts, a_stride, c.h, c.w, c.b, (float)wt.w[0], (float)wt.w[1], (float)wt.w[2],
-                     (float)wt.tau, (float)wt.lam, mu, part);
-}
 
 void launch_finish_iter(const double* part, int n_cubes, const double* mu, double* out, double* res_user,
                         int* flag, hipStream_t s) {
@@ -217,6 +228,17 @@ void launch_finish_iter(const double* part, int n_cubes, const double* mu, doubl
 
 void launch_mu_step(double* mu, double rho, double mu_max, hipStream_t s) {
   hipLaunchKernelGGL(k_mu_step, dim3(1), dim3(64), 0, s, mu, rho, mu_max);
+}
+
+void launch_lrhs_batch(const BatchTab& bt, const BatchPtrs& p, const Weights& wt, const double* mu, hipStream_t s) {
+  hipLaunchKernelGGL(k_lrhs_batch, dim3(bt.nblocks), dim3(256), 0, s, bt, p, (float)wt.w[0], (float)wt.w[1],
+                     (float)wt.w[2], mu);
+}
+
+void launch_grad_shrink_batch(const BatchTab& bt, const BatchPtrs& p, const Weights& wt, const double* mu,
+                              double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_shrink_batch, dim3(bt.nc * LRSTV_PARTS), dim3(256), 0, s, bt, p, (float)wt.w[0],
+                     (float)wt.w[1], (float)wt.w[2], (float)wt.tau, (float)wt.lam, mu, part);
 }
 
 }  // namespace lrstv

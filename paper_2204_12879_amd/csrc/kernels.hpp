@@ -12,16 +12,35 @@ struct Weights {
   double w[3];
 };
 
-// Device pointers of one cube's state inside the packed batch.  F, E, G3,
-// G4 and A point at component 0; component n is at + n * ts.
-struct CubePtrs {
-  int h, w, b;
-  int64_t ts;
-  const float* O;
-  float *L, *Z, *S, *G1, *G2, *F, *E, *G3, *G4, *A, *T;
-};
 
 struct SliceDesc;
+
+// ---- packed ragged batches: one launch per phase --------------------------
+struct CubeGeo {
+  int h, w, b;
+  int nb_w, cw_h;          // rows per block of the w FFT, columns per block of the h FFT
+  int64_t off;             // element offset of the cube in the packed batch
+  int64_t spec_off;        // complex offset of its half spectrum
+  int64_t slice_base;      // float offset of its Fourier slices
+};
+enum Phase { PH_LRHS = 0, PH_RFFT_W, PH_FFT_H, PH_TRI_B, PH_BAND_DFT, PH_PARTS, PH_COUNT };
+// Block ranges of one phase: cube c owns blocks [bstart[c], bstart[c+1]).
+struct BatchTab {
+  const CubeGeo* geo;      // device [nc]
+  const int* bstart;       // device [nc + 1]
+  int nc, nblocks;
+  size_t lds_w, lds_h;     // dynamic LDS of the w / h FFT phases (max over cubes)
+};
+// Base pointers of the packed batch (gradient-shaped arrays and A: 3
+// components spaced by ts).
+struct BatchPtrs {
+  const float* O;
+  float *L, *Z, *S, *G1, *G2, *F, *E, *G3, *G4, *A, *T;
+  int64_t ts;
+};
+int phase_blocks(int phase, int h, int w, int b);
+int geo_rows_nb(int w);
+int geo_cols_cw(int h);
 
 // One cube's pointers for the adjoint of an iteration (all offset to the
 // cube; gradient-shaped arrays are 3 components spaced by ts, the per-cube
@@ -43,13 +62,19 @@ struct VjpCube {
 void launch_fill(float* p, int64_t n, float v, hipStream_t s);
 void launch_copy(float* dst, const float* src, int64_t n, hipStream_t s);
 void launch_set_mu(double* mu, double v, hipStream_t s);
-void launch_lrhs(const CubePtrs& c, const Weights& wt, const double* mu, hipStream_t s);
-// A (t-SVT input) has component stride a_stride.
-void launch_grad_shrink(const CubePtrs& c, const Weights& wt, const double* mu, double* part, int64_t a_stride,
-                        hipStream_t s);
 void launch_finish_iter(const double* part, int n_cubes, const double* mu, double* out, double* res_user,
                         int* flag, hipStream_t s);
 void launch_mu_step(double* mu, double rho, double mu_max, hipStream_t s);
+void launch_lrhs_batch(const BatchTab& bt, const BatchPtrs& p, const Weights& wt, const double* mu, hipStream_t s);
+void launch_grad_shrink_batch(const BatchTab& bt, const BatchPtrs& p, const Weights& wt, const double* mu,
+                              double* part, hipStream_t s);
+void launch_rfft_w_batch(const BatchTab& bt, const float* T, float2* spec, hipStream_t s);
+void launch_irfft_w_batch(const BatchTab& bt, const float2* spec, float* Z, double* part, hipStream_t s);
+void launch_fft_h_batch(const BatchTab& bt, float2* spec, int sign, hipStream_t s);
+void launch_tri_b_batch(const BatchTab& bt, float2* spec, const double wts[3], const double* mu, hipStream_t s);
+void launch_band_dft_batch(const BatchTab& bt, const float* A, int64_t a_stride, float* slices, hipStream_t s);
+void launch_band_idft_batch(const BatchTab& bt, const float* slices, float* E, int64_t e_stride, const float* F,
+                            float* G4, const double* mu, double* part, hipStream_t s);
 
 // --- Z-update: FFT along w and h, periodic tridiagonal solve along b -------
 // spec holds b * h * (w/2+1) complex values.
