@@ -154,6 +154,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (skip the autotuner)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (the single-GPU share of the workload); "
@@ -178,6 +179,9 @@ def main():
     pkw = dict(tau=0.02, alpha=0.3, lam=lam, w=(1.0, 1.0, 1.0), mu0=1e-2, rho=1.5, mu_max=1e6)
     prec = L.LRSTV_FP32 if args.precision == "fp32" else L.LRSTV_SPLIT_BF16
     solver = L.Solver(shapes, L.Params(precision=prec, **pkw))
+    tuning = None
+    if not args.no_tune:
+        tuning = solver.autotune(reps=2)   # before capture; the timed region replays the tuned shapes
     if not args.eager:
         solver.set_graph(True)
     Y = torch.from_numpy(np.concatenate([c[1].astype(np.float32).ravel() for c in cubes])).cuda()
@@ -253,7 +257,8 @@ def main():
                                ", ADMM iterations from the initial state, tau=0.02 alpha=0.3 lambda=10/sqrt(hw) "
                                "mu0=1e-2 rho=1.5",
                    "precision": args.precision, "launch": "eager" if args.eager else "hipGraph replay",
-                   "voxels": int(Y.numel()), "parallelism": "single GPU"},
+                   "voxels": int(Y.numel()), "parallelism": "single GPU",
+                   "tuning": tuning if tuning is not None else "default shapes"},
         "tsvt_slices_per_s": n_slices * args.steps / (svt_ms * 1e-3) if svt_ms > 0 else None,
         "kept_singular_value_fraction_last_iter": float(np.sum(ranks_last)) / kept_den,
         "stage_ms_per_iter": stages,

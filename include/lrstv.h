@@ -244,6 +244,36 @@ int lrstv_zsolve_workspace_size(int32_t h, int32_t w, int32_t b, size_t* bytes);
 int lrstv_zsolve(const float* T, float* Z, int32_t h, int32_t w, int32_t b, double mu,
                  const double wts[3], void* ws, size_t ws_bytes, void* stream);
 
+/* ---- autotuner ---------------------------------------------------------- */
+
+/* Launch shapes chosen per handle.  The slice tridiagonalisation (the
+ * dominant kernel) has compiled shapes of 8, 12 and 16 waves per slice
+ * (with 10, 7 and 6 VGPR-resident rows per wave); which is fastest depends
+ * on the slice sizes of the batch. */
+typedef struct lrstv_tuning {
+  int32_t tridiag_waves;            /* chosen shape: 8, 12 or 16            */
+  int32_t n_variants;               /* shapes tried (filled by autotune)    */
+  int32_t tridiag_waves_tried[4];
+  double  tridiag_ms[4];            /* mean ms per launch over the handle's
+                                       slices, -1 if the shape cannot hold
+                                       them on chip                         */
+} lrstv_tuning;
+
+/* Time every tridiagonalisation shape on this handle's slice sizes (slices
+ * filled with hashed values, so the timing does not depend on the state;
+ * `reps` timed launches each after one warm-up) and keep the fastest.  The
+ * solver state is not touched (the slice scratch is overwritten); a
+ * captured iteration graph is dropped and recaptured on the next iterate.
+ * Synchronises the stream.  out may be NULL.  Errors: INVALID_ARG, HIP. */
+int lrstv_autotune(lrstv_handle hd, int32_t reps, lrstv_tuning* out);
+
+/* Apply a stored choice (only tridiag_waves is read).  INVALID_ARG for a
+ * shape that does not exist. */
+int lrstv_set_tuning(lrstv_handle hd, const lrstv_tuning* t);
+
+/* The handle's current choice (timings -1). */
+int lrstv_get_tuning(lrstv_handle hd, lrstv_tuning* t);
+
 /* ---- diagnostics ------------------------------------------------------- */
 
 /* Stages of one iteration, in launch order (lrstv_stage_name gives the

@@ -39,6 +39,11 @@ class _StateView(C.Structure):
                [("total", C.c_int64)]
 
 
+class _Tuning(C.Structure):
+    _fields_ = [("tridiag_waves", C.c_int32), ("n_variants", C.c_int32), ("tridiag_waves_tried", C.c_int32 * 4),
+                ("tridiag_ms", C.c_double * 4)]
+
+
 class _Report(C.Structure):
     _fields_ = [("iters", C.c_int32), ("residuals", C.c_double * LRSTV_NRES), ("mu", C.c_double)]
 
@@ -88,6 +93,9 @@ def load_library():
         "lrstv_iterate_vjp": (C.c_int, [vp, C.POINTER(_StateView), C.POINTER(_StateView), C.POINTER(_StateView), vp,
                                         C.POINTER(_StateView), vp, vp, i32, vp, C.c_size_t]),
         "lrstv_svt_vjp_workspace_size": (C.c_int, [i32, i32, i32, i32, sz]),
+        "lrstv_autotune": (C.c_int, [vp, i32, C.POINTER(_Tuning)]),
+        "lrstv_set_tuning": (C.c_int, [vp, C.POINTER(_Tuning)]),
+        "lrstv_get_tuning": (C.c_int, [vp, C.POINTER(_Tuning)]),
         "lrstv_svt_vjp": (C.c_int, [vp, vp, vp, i32, i32, i32, i32, f32, vp, vp, C.c_size_t, vp]),
     }
     for name, (res, args) in sig.items():
@@ -244,6 +252,25 @@ class Solver:
         _check(rc, allow_warn=True)
         return {"iters": rep.iters, "residuals": dict(zip(RESIDUAL_NAMES, list(rep.residuals))),
                 "mu": rep.mu, "converged": rc != WARN_NOT_CONVERGED}
+
+    def autotune(self, reps: int = 3) -> dict:
+        """Time the tridiagonalisation shapes on this batch's slice sizes and
+        keep the fastest (lrstv_autotune).  Returns {"tridiag_waves": w,
+        "tridiag_ms": {waves: ms}} (ms -1: shape cannot run on chip)."""
+        t = _Tuning()
+        _check(self.lib.lrstv_autotune(self.handle, int(reps), C.byref(t)))
+        return {"tridiag_waves": t.tridiag_waves,
+                "tridiag_ms": {int(t.tridiag_waves_tried[i]): float(t.tridiag_ms[i]) for i in range(t.n_variants)}}
+
+    def set_tuning(self, tridiag_waves: int) -> None:
+        t = _Tuning()
+        t.tridiag_waves = int(tridiag_waves)
+        _check(self.lib.lrstv_set_tuning(self.handle, C.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = _Tuning()
+        _check(self.lib.lrstv_get_tuning(self.handle, C.byref(t)))
+        return {"tridiag_waves": t.tridiag_waves}
 
     def set_graph(self, enable: bool = True) -> None:
         """Replay iterations from a captured hipGraph (bit-identical to eager launches)."""

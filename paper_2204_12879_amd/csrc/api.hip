@@ -136,6 +136,7 @@ struct lrstv_handle_s {
   CubeGeo* geo;        // device [n_cubes]
   int* bstart;         // device [PH_COUNT][n_cubes + 1]
   BatchTab bt[PH_COUNT];
+  int tri_variant = kTriDefault;   // tridiagonalisation shape (lrstv_autotune / lrstv_set_tuning)
   StageTimer timer;
   // per-cube index ranges of the per-column t-SVT threshold terms (adjoint)
   std::vector<int64_t> acon_range;
@@ -416,6 +417,7 @@ static void run_iteration(lrstv_handle_s* H, double* res_user) {
   sv.alpha = H->par.alpha;
   sv.thresh = 0.f;
   sv.precision = H->par.precision;
+  sv.tri_variant = H->tri_variant;
   launch_svt(sv, s, &tm);
   tm.begin(ST_BAND_IDFT);
   launch_band_idft_batch(H->bt[PH_PARTS], H->slices, H->E, H->total, H->F, H->G4, H->mu, H->part, s);
@@ -733,6 +735,7 @@ extern "C" int lrstv_iterate_vjp(lrstv_handle H, const lrstv_state_view* before,
   J.fw.alpha = H->par.alpha;
   J.fw.thresh = 0.f;
   J.fw.precision = LRSTV_FP32;
+  J.fw.tri_variant = H->tri_variant;
   J.dsl = w.dsl;
   J.C = w.C;
   J.R = w.R;
@@ -1016,6 +1019,112 @@ extern "C" int lrstv_zsolve(const float* T, float* Z, int32_t h, int32_t w, int3
   launch_fft_h(spec, h, w, b, +1, s);
   launch_irfft_w(spec, Z, h, w, b, nullptr, s);
   HIPCHK(hipGetLastError());
+  return LRSTV_OK;
+}
+
+// ----------------------------------------------------------- autotuner ---
+static void drop_graph(lrstv_handle_s* H) {
+  if (H->gexec) (void)hipGraphExecDestroy(H->gexec);
+  if (H->graph) (void)hipGraphDestroy(H->graph);
+  H->gexec = nullptr;
+  H->graph = nullptr;
+}
+
+static SvtLaunch handle_svt(lrstv_handle_s* H) {
+  SvtLaunch sv;
+  sv.desc = H->desc;
+  sv.n_slices = (int)H->sl.desc.size();
+  sv.max_n1 = H->sl.max_n1;
+  sv.max_m1 = H->sl.max_m1;
+  sv.slices = H->slices;
+  sv.gram = H->gram;
+  sv.V = H->V;
+  sv.B = H->B;
+  sv.tri = H->tri;
+  sv.xs = H->xs;
+  sv.Twy = H->Twy;
+  sv.fval = H->fval;
+  sv.rcount = H->rcount;
+  sv.mu = H->mu;
+  sv.alpha = H->par.alpha;
+  sv.thresh = 0.f;
+  sv.precision = H->par.precision;
+  sv.tri_variant = H->tri_variant;
+  return sv;
+}
+
+extern "C" int lrstv_autotune(lrstv_handle H, int32_t reps, lrstv_tuning* out) {
+  if (!H) return fail(LRSTV_ERR_INVALID_ARG, "handle is NULL");
+  if (reps < 1 || reps > 100) return fail(LRSTV_ERR_INVALID_ARG, "reps must be in [1, 100]");
+  hipStream_t s = H->stream;
+  SvtLaunch sv = handle_svt(H);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  lrstv_tuning t;
+  memset(&t, 0, sizeof t);
+  t.n_variants = kTriVariants;
+  int best = -1;
+  double best_ms = 0.0;
+  hipError_t err = hipSuccess;
+  for (int v = 0; v < kTriVariants && err == hipSuccess; ++v) {
+    t.tridiag_waves_tried[v] = tri_variant_waves(v);
+    t.tridiag_ms[v] = -1.0;  // not runnable on chip for this batch
+    if (!tri_variant_onchip(v, sv.max_n1)) continue;
+    sv.tri_variant = v;
+    double tot = 0.0;
+    for (int r = 0; r <= reps && err == hipSuccess; ++r) {
+      // slices of hashed values: full-rank Grams, so no column deflates
+      launch_fill_hash(H->slices, H->sl.slices_floats, 0x5eed0000u + (uint32_t)r, s);
+      launch_svt_gram(sv, s);
+      err = hipEventRecord(e0, s);
+      launch_svt_tridiag(sv, s);
+      if (err == hipSuccess) err = hipEventRecord(e1, s);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (r > 0) tot += ms;   // the first run warms up
+    }
+    t.tridiag_ms[v] = tot / reps;
+    if (best < 0 || t.tridiag_ms[v] < best_ms) {
+      best = v;
+      best_ms = t.tridiag_ms[v];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(LRSTV_ERR_HIP, "autotune: %s", hipGetErrorString(err));
+  if (best >= 0 && best != H->tri_variant) {
+    H->tri_variant = best;
+    drop_graph(H);
+  }
+  t.tridiag_waves = tri_variant_waves(H->tri_variant);
+  if (out) *out = t;
+  return LRSTV_OK;
+}
+
+extern "C" int lrstv_set_tuning(lrstv_handle H, const lrstv_tuning* t) {
+  if (!H || !t) return fail(LRSTV_ERR_INVALID_ARG, "handle or tuning is NULL");
+  int v = -1;
+  for (int i = 0; i < kTriVariants; ++i)
+    if (tri_variant_waves(i) == t->tridiag_waves) v = i;
+  if (v < 0) return fail(LRSTV_ERR_INVALID_ARG, "no tridiagonalisation shape with %d waves", t->tridiag_waves);
+  if (v != H->tri_variant) {
+    H->tri_variant = v;
+    drop_graph(H);
+  }
+  return LRSTV_OK;
+}
+
+extern "C" int lrstv_get_tuning(lrstv_handle H, lrstv_tuning* t) {
+  if (!H || !t) return fail(LRSTV_ERR_INVALID_ARG, "handle or tuning is NULL");
+  memset(t, 0, sizeof *t);
+  t->tridiag_waves = tri_variant_waves(H->tri_variant);
+  t->n_variants = kTriVariants;
+  for (int v = 0; v < kTriVariants; ++v) {
+    t->tridiag_waves_tried[v] = tri_variant_waves(v);
+    t->tridiag_ms[v] = -1.0;
+  }
   return LRSTV_OK;
 }
 

@@ -28,16 +28,6 @@
 #include "kernels.hpp"
 #include "mfma.hpp"
 
-// Tridiagonalisation shape: waves per slice and VGPR-resident rows per wave.
-// 16 waves (4 per SIMD) hide the LDS and cross-lane latency of the per-row
-// reductions better than 8 (measured 6.6 vs 8.7 ms per iteration at
-// 288 slices of 256 x 256); 6 rows per wave keep the LDS part under 160 KB.
-#ifndef LRSTV_TRIDIAG_NW
-#define LRSTV_TRIDIAG_NW 16
-#endif
-#ifndef LRSTV_TRIDIAG_JR
-#define LRSTV_TRIDIAG_JR 6
-#endif
 
 namespace lrstv {
 
@@ -1343,48 +1333,81 @@ __global__ void __launch_bounds__(256) k_vjp_r(const SliceDesc* __restrict__ des
 }
 
 // ------------------------------------------------------------ launcher ---
-constexpr int kTridiagRegRows = LRSTV_TRIDIAG_JR;
-constexpr int kTridiagWaves = LRSTV_TRIDIAG_NW;
-// Dynamic LDS granted to k_tridiag_reg (host-side function attribute, set
-// once outside any stream capture by prepare_svt).
-static size_t g_tridiag_lds_granted = 65536;
+// Tridiagonalisation shapes (waves per slice, VGPR-resident rows per wave),
+// chosen per handle by the autotuner.  More waves hide the LDS and
+// cross-lane latency of the per-row reductions (at 288 slices of 256 x 256:
+// 8 waves 8.7, 12 waves 7.1, 16 waves 6.6 ms per iteration); the rows per
+// wave keep the LDS part of the packed Gram under 160 KB.
+struct TriShape {
+  int nw, jr;
+};
+static const TriShape kTriShapes[kTriVariants] = {{8, 10}, {12, 7}, {16, 6}};
+// Dynamic LDS granted per variant (host-side function attribute, set
+// outside any stream capture by prepare_svt).
+static size_t g_tri_granted[kTriVariants] = {65536, 65536, 65536};
+
+int tri_variant_waves(int v) { return kTriShapes[v].nw; }
 
 // Dynamic LDS of k_tridiag_reg: the packed LDS rows plus (3 + NW) n complex
 // (two columns, w, NW column-part rows).
-static size_t tridiag_reg_lds(int n) {
-  constexpr int JR = kTridiagRegRows, NW = kTridiagWaves;
+static size_t tridiag_reg_lds(int n, int v) {
+  const int NW = kTriShapes[v].nw, JR = kTriShapes[v].jr;
   const int RL = n > NW * JR ? n - NW * JR : 0;
   return ((size_t)RL * (RL + 1) / 2 + (size_t)(3 + NW) * n) * sizeof(float2);
 }
 
-static void launch_tridiag(const SvtLaunch& L, hipStream_t s) {
-  constexpr int JR = kTridiagRegRows, NW = kTridiagWaves;
+static const void* tri_kernel(int v) {
+  switch (v) {
+    case 0: return (const void*)k_tridiag_reg<10, 8>;
+    case 1: return (const void*)k_tridiag_reg<7, 12>;
+    default: return (const void*)k_tridiag_reg<6, 16>;
+  }
+}
+
+bool tri_variant_onchip(int v, int n) { return n <= 256 && tridiag_reg_lds(n, v) <= g_tri_granted[v]; }
+
+void launch_svt_tridiag(const SvtLaunch& L, hipStream_t s) {
   const int n = L.max_n1, ns = L.n_slices;
-  const size_t lds = tridiag_reg_lds(n);
-  if (n <= 256 && lds <= g_tridiag_lds_granted)
-    hipLaunchKernelGGL((k_tridiag_reg<JR, NW>), dim3(ns), dim3(64 * NW), lds, s, L.desc, L.gram, L.tri);
-  else
+  const int v = (L.tri_variant >= 0 && L.tri_variant < kTriVariants) ? L.tri_variant : kTriDefault;
+  if (tri_variant_onchip(v, n)) {
+    const size_t lds = tridiag_reg_lds(n, v);
+    switch (v) {
+      case 0: hipLaunchKernelGGL((k_tridiag_reg<10, 8>), dim3(ns), dim3(512), lds, s, L.desc, L.gram, L.tri); break;
+      case 1: hipLaunchKernelGGL((k_tridiag_reg<7, 12>), dim3(ns), dim3(768), lds, s, L.desc, L.gram, L.tri); break;
+      default: hipLaunchKernelGGL((k_tridiag_reg<6, 16>), dim3(ns), dim3(1024), lds, s, L.desc, L.gram, L.tri); break;
+    }
+  } else {
     hipLaunchKernelGGL(k_tridiag<false>, dim3(ns), dim3(256), (size_t)(2 + 4) * n * sizeof(float2), s, L.desc,
                        L.gram, L.tri);
+  }
+}
+static void launch_tridiag(const SvtLaunch& L, hipStream_t s) { launch_svt_tridiag(L, s); }
+
+void launch_svt_gram(const SvtLaunch& L, hipStream_t s) {
+  const int ns = L.n_slices, n = L.max_n1;
+  const int TT = (n + kMT - 1) / kMT;
+  if (L.precision == LRSTV_SPLIT_BF16)
+    hipLaunchKernelGGL(k_gram<kBF16x3>, dim3(TT * (TT + 1) / 2, ns), dim3(256), 0, s, L.desc, L.slices, L.gram);
+  else
+    hipLaunchKernelGGL(k_gram<kF32>, dim3(TT * (TT + 1) / 2, ns), dim3(256), 0, s, L.desc, L.slices, L.gram);
 }
 
 void prepare_svt(int max_n1) {
   const int n = max_n1;
-  constexpr int JR = kTridiagRegRows;
-  const int RL = n > 8 * JR ? n - 8 * JR : 0;
-  const size_t reg_lds = tridiag_reg_lds(n);
-  if (n > 256 || reg_lds <= g_tridiag_lds_granted) return;
+  if (n > 256) return;
   int dev = 0;
   hipDeviceProp_t prop;
   int lds_max = 65536;
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
     lds_max = (int)prop.sharedMemPerBlock;
-  if ((int)reg_lds + 2048 > lds_max) return;
-  if (hipFuncSetAttribute((const void*)k_tridiag_reg<JR, kTridiagWaves>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)reg_lds) == hipSuccess)
-    g_tridiag_lds_granted = reg_lds;
-  else
-    (void)hipGetLastError();  // clear the sticky error: the global-memory variant is used instead
+  for (int v = 0; v < kTriVariants; ++v) {
+    const size_t need = tridiag_reg_lds(n, v);
+    if (need <= g_tri_granted[v] || (int)need + 2048 > lds_max) continue;
+    if (hipFuncSetAttribute(tri_kernel(v), hipFuncAttributeMaxDynamicSharedMemorySize, (int)need) == hipSuccess)
+      g_tri_granted[v] = need;
+    else
+      (void)hipGetLastError();  // clear the sticky error: the global-memory variant is used instead
+  }
 }
 static size_t tridiag_onchip_bytes(int n) {
   return ((size_t)n * (n + 1) / 2 + 2 * (size_t)n + 4 * (size_t)n) * sizeof(float2);

@@ -26,6 +26,20 @@ __global__ void k_copy(float* __restrict__ dst, const float* __restrict__ src, i
     dst[i] = src[i];
 }
 
+// p[i] = a value in [-1, 1) from a 32-bit integer hash of (i, seed)
+// (lowbias32 mixing), for timing runs on data that is not all zeros.
+__global__ void k_fill_hash(float* __restrict__ p, int64_t n, uint32_t seed) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t x = (uint32_t)i ^ (uint32_t)(i >> 32) * 0x9e3779b9u ^ seed;
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    p[i] = (float)(x >> 8) * (2.0f / 16777216.0f) - 1.0f;
+  }
+}
+
 __global__ void k_set_mu(double* mu, double v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *mu = v;
 }
@@ -213,6 +227,13 @@ void launch_copy(float* dst, const float* src, int64_t n, hipStream_t s) {
   int grid = (int)((n + 255) / 256);
   if (grid > 4096) grid = 4096;
   hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, s, dst, src, n);
+}
+
+void launch_fill_hash(float* p, int64_t n, uint32_t seed, hipStream_t s) {
+  if (n <= 0) return;
+  int grid = (int)((n + 255) / 256);
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(k_fill_hash, dim3(grid), dim3(256), 0, s, p, n, seed);
 }
 
 void launch_set_mu(double* mu, double v, hipStream_t s) {

@@ -62,6 +62,7 @@ struct VjpCube {
 void launch_fill(float* p, int64_t n, float v, hipStream_t s);
 void launch_copy(float* dst, const float* src, int64_t n, hipStream_t s);
 void launch_set_mu(double* mu, double v, hipStream_t s);
+void launch_fill_hash(float* p, int64_t n, uint32_t seed, hipStream_t s);
 void launch_finish_iter(const double* part, int n_cubes, const double* mu, double* out, double* res_user,
                         int* flag, hipStream_t s);
 void launch_mu_step(double* mu, double rho, double mu_max, hipStream_t s);
@@ -94,6 +95,10 @@ void launch_band_idft(const float* slices, int n_t, float* E, int64_t e_stride, 
                       const float* F, float* G4, const double* mu, double* part, hipStream_t s);
 
 // --- slice SVT ------------------------------------------------------------
+constexpr int kTriVariants = 3;   // tridiagonalisation shapes: 8, 12, 16 waves
+constexpr int kTriDefault = 2;
+int tri_variant_waves(int v);
+bool tri_variant_onchip(int v, int n);
 // thresh: t = alpha / mu read on the device (mu != NULL) or the fixed value.
 struct SvtLaunch {
   const SliceDesc* desc;   // device array [n_slices]
@@ -112,8 +117,12 @@ struct SvtLaunch {
   double alpha;            // threshold numerator (t = alpha / mu) when mu != NULL
   float thresh;            // fixed threshold when mu == NULL
   int precision;
+  int tri_variant = kTriDefault;  // tridiagonalisation shape (autotuned)
 };
 void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm = nullptr);
+// Single stages of launch_svt (the autotuner times them in isolation).
+void launch_svt_gram(const SvtLaunch& L, hipStream_t s);
+void launch_svt_tridiag(const SvtLaunch& L, hipStream_t s);
 // Host-side kernel attributes for slices up to max_n1 (call before capture).
 void prepare_svt(int max_n1);
 

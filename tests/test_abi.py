@@ -67,6 +67,8 @@ def test_argument_checks_without_gpu():
     assert lib.lrstv_vjp_workspace_size(None, ctypes.byref(n)) == -1
     assert lib.lrstv_iterate_vjp(None, None, None, None, None, None, None, None, 0, None, 0) == -1
     assert lib.lrstv_save_state(None, None) == -1
+    assert lib.lrstv_autotune(None, 1, None) == -1
+    assert lib.lrstv_set_tuning(None, None) == -1
     assert lib.lrstv_status_string(-2) == b"workspace too small"
     assert lib.lrstv_version() >= 100
     with pytest.raises(L.LrstvError):
