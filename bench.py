@@ -44,6 +44,7 @@ def stage_model(shapes, ranks_per_slice):
       gram         4 m1 n1 (n1 + 1) flops per slice (packed Hermitian Gram)
       tridiag      16/3 n1^3 flops per slice (Hermitian Householder reduction)
       trieig       52 * 3 n1 flops per kept eigenvalue (FP64 Sturm bisection)
+      trivec       12 n1 flops per kept eigenvalue (twisted factorisation)
       backtrans    8 n1^2 r flops per slice
       bp1, bp2     8 m1 n1 r flops per slice each
     """
@@ -70,6 +71,7 @@ def stage_model(shapes, ranks_per_slice):
         add("gram", "flops", 3 * s * 4.0 * m1 * n1 * (n1 + 1))
         add("tridiag", "flops", 3 * s * 16.0 / 3.0 * n1 ** 3)
         add("trieig", "fp64", sum(52 * 3.0 * n1 * r for r in rs))
+        add("trivec", "fp64", sum(12.0 * n1 * r for r in rs))
         add("backtrans", "flops", sum(8.0 * n1 * n1 * r for r in rs))
         add("bp1", "flops", sum(8.0 * m1 * n1 * r for r in rs))
         add("bp2", "flops", sum(8.0 * m1 * n1 * r for r in rs))
@@ -233,7 +235,7 @@ def main():
     roof["traffic"] = None
     roof["kernel"] = dom
     roof["avg_launch_ms"] = avg_ms
-    svt_stages = ["gram", "tridiag", "trieig", "backtrans", "bp1", "colnorm", "bp2"]
+    svt_stages = ["gram", "tridiag", "trieig", "trivec", "backtrans", "bp1", "colnorm", "bp2"]
     svt_ms = sum(st[k][0] for k in svt_stages)
     n_slices = sum(3 * (s[0] // 2 + 1) for s in shapes)
     stages = {k: round(v[0] / args.steps, 4) for k, v in st.items()}

@@ -279,10 +279,11 @@ int lrstv_get_tuning(lrstv_handle hd, lrstv_tuning* t);
 /* Stages of one iteration, in launch order (lrstv_stage_name gives the
  * names): L/T_z, rfft along w, FFT along h (both directions), tridiagonal
  * band solve, inverse rfft, difference/shrink/multipliers, band DFT, slice
- * Gram, tridiagonalisation, tridiagonal eigenpairs, back-transform,
+ * Gram, tridiagonalisation, tridiagonal eigenvalues, tridiagonal
+ * eigenvectors, back-transform,
  * back-projection B, shrink factors, back-projection Ehat, inverse band DFT
  * + Gamma4, residual reduction + mu step. */
-#define LRSTV_NSTAGES 16
+#define LRSTV_NSTAGES 17
 
 /* Start (enable = 1, discarding what was recorded) or stop (0) recording a
  * pair of hipEvents around every stage launched by lrstv_iterate / solve,

@@ -15,7 +15,7 @@ LRSTV_NRES = 7
 LRSTV_VJP_INITIAL = 1
 RESIDUAL_NAMES = ("inf_OLS", "inf_LZ", "fro_OLS", "fro_LZ", "fro_DZF", "fro_EF", "dual_Z")
 WARN_NOT_CONVERGED = 1
-NSTAGES = 16
+NSTAGES = 17
 
 
 class LrstvError(RuntimeError):

@@ -1130,7 +1130,7 @@ extern "C" int lrstv_get_tuning(lrstv_handle H, lrstv_tuning* t) {
 
 // --------------------------------------------------------- diagnostics ---
 static const char* kStageNames[ST_COUNT] = {"lrhs", "rfft_w", "fft_h", "tri_b", "irfft_w", "grad_shrink",
-                                            "band_dft", "gram", "tridiag", "trieig", "backtrans", "bp1",
+                                            "band_dft", "gram", "tridiag", "trieig", "trivec", "backtrans", "bp1",
                                             "colnorm", "bp2", "band_idft", "finish"};
 
 extern "C" int lrstv_profile(lrstv_handle H, int32_t enable) {

@@ -616,6 +616,14 @@ LRSTV_DEV int sturm_count(const double* dg, const double* e2, int p0, int p1, do
   return cnt;
 }
 
+// 1/q from the hardware reciprocal refined by one Newton step (full FP64
+// accuracy for the normal numbers used here; q is kept away from zero by
+// the pivot guards).
+LRSTV_DEV double fast_rcp(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  return r * (2.0 - q * r);
+}
+
 // Same count over the whole matrix with the hardware reciprocal refined by one
 // Newton step instead of the full-precision division sequence.
 LRSTV_DEV int sturm_count_fast(const double* dg, const double* e2, int n, double x, double pivmin) {
@@ -638,6 +646,10 @@ LRSTV_DEV int sturm_count_fast(const double* dg, const double* e2, int n, double
 // factorisation inside their unreduced block, Gram-Schmidt inside clusters;
 // output column c = eigenvector of the c-th largest kept eigenvalue times the
 // phase (V re/im planes).
+// PHASE 0 computes the eigenvalues (kept in the tridiagonal scratch at 5n,
+// scaled by 1 / ||T||), PHASE 1 the eigenvectors from them; both redo the
+// O(n) set-up (scaling, splits, the count of eigenvalues below the cut).
+template <int PHASE>
 __global__ void __launch_bounds__(1024) k_trieig(const SliceDesc* __restrict__ desc, double* __restrict__ tri,
                                                  double* __restrict__ xs, float* __restrict__ V,
                                                  int* __restrict__ rcount, const double* __restrict__ mu_dev,
@@ -657,6 +669,7 @@ __global__ void __launch_bounds__(1024) k_trieig(const SliceDesc* __restrict__ d
   double* ds = lam + n;             // [n] diagonal
   double* sdot = ds + n;            // [n] Gram-Schmidt coefficients
   int* bstart = (int*)(sdot + n);   // [n+1] block starts
+  int* gcnt = bstart + n + 1;       // [blockDim] eigenvalue counts on the coarse grid
   const double t = mu_dev ? alpha / *mu_dev : (double)thresh;
   double gl = 1e300, gu = -1e300;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -703,8 +716,20 @@ __global__ void __launch_bounds__(1024) k_trieig(const SliceDesc* __restrict__ d
   }
   __syncthreads();
   const int c0 = s_c0, nblk = s_nblk, r = n - c0;
-  // 5-section: the 4 threads of a group probe 4 interior points of [lo, hi]
-  {
+  double* lam_g = tri + d.t_off + 5 * n;   // eigenvalues between the two phases
+  if (PHASE == 1) {
+    for (int k = c0 + threadIdx.x; k < n; k += blockDim.x) lam[k] = lam_g[k];
+  }
+  // Shared first step: the counts at G = blockDim points spread over
+  // [lo0, gu] bracket every eigenvalue in one grid cell.  Then 5-section:
+  // the 4 threads of a group probe 4 interior points of the cell, until it is
+  // below max(eps_64 |lambda|, 1e-13 ||T||) (the FP32 Gram resolves its
+  // eigenvalues to ~1e-7 ||T||; clusters are gaps below 1e-10 ||T||).
+  if (PHASE == 0) {
+    const int G = blockDim.x;
+    const double lo0 = fmax(gl, lo_cut), cell = (gu - lo0) / G;
+    if (r > 0) gcnt[threadIdx.x] = sturm_count_fast(dg, e2, n, lo0 + (threadIdx.x + 1) * cell, pivmin);
+    __syncthreads();
     const int lane = threadIdx.x & 63, q = lane & 3, base = lane & ~3;
     const int ngrp = blockDim.x >> 2;
     const int nround = (r + ngrp - 1) / ngrp;
@@ -712,10 +737,17 @@ __global__ void __launch_bounds__(1024) k_trieig(const SliceDesc* __restrict__ d
       const int kk = (threadIdx.x >> 2) + rd * ngrp;
       const bool act = kk < r;
       const int k = c0 + kk;
-      double lo = fmax(gl, lo_cut), hi = gu;
+      // first grid point whose count exceeds k: lambda_k in [x_{j-1}, x_j)
+      int jl = 0, jh = G;
+      while (jl < jh) {
+        const int mid = (jl + jh) >> 1;
+        if (gcnt[mid] > k) jh = mid;
+        else jl = mid + 1;
+      }
+      double lo = lo0 + jl * cell, hi = lo0 + (jl + 1) * cell;
       for (int it = 0; it < 64; ++it) {
         const double wdt = hi - lo;
-        const bool done = !act || wdt <= fmax(2.2e-16 * fmax(fabs(lo), fabs(hi)), 4e-16);
+        const bool done = !act || wdt <= fmax(2.2e-16 * fmax(fabs(lo), fabs(hi)), 1e-13 * tnorm);
         if (__all(done)) break;
         const double step = wdt * 0.2;
         const double x = lo + (q + 1) * step;
@@ -732,8 +764,9 @@ __global__ void __launch_bounds__(1024) k_trieig(const SliceDesc* __restrict__ d
           else { lo = x3; }
         }
       }
-      if (act && q == 0) lam[k] = 0.5 * (lo + hi);
+      if (act && q == 0) lam_g[k] = 0.5 * (lo + hi);
     }
+    return;
   }
   __syncthreads();
   // eigenvectors: twisted factorisation, one eigenvalue per thread
@@ -769,7 +802,7 @@ __global__ void __launch_bounds__(1024) k_trieig(const SliceDesc* __restrict__ d
     if (fabs(dm) < pivmin) dm = pivmin;
     Dm[(int64_t)p1 * n] = dm;
     for (int i = p1 - 1; i >= p0; --i) {
-      const double u = ee[i] / dm;
+      const double u = ee[i] * fast_rcp(dm);
       Um[(int64_t)i * n] = u;
       dm = dg[i] - lk - u * ee[i];
       if (fabs(dm) < pivmin) dm = pivmin;
@@ -788,7 +821,7 @@ __global__ void __launch_bounds__(1024) k_trieig(const SliceDesc* __restrict__ d
       for (int q = 0; q < 8; ++q) {
         const int i = i0 + q;
         if (i < p1) {
-          const double l = ee[i] / dp;
+          const double l = ee[i] * fast_rcp(dp);
           Lp[(int64_t)i * n] = l;
           dp = dg[i + 1] - lk - l * ee[i];
           if (fabs(dp) < pivmin) dp = pivmin;
@@ -1429,11 +1462,15 @@ void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm) {
   T.begin(ST_TRIDIAG);
   launch_tridiag(L, s);
   T.end(ST_TRIDIAG);
-  const size_t eig_lds = (size_t)5 * n * sizeof(double) + (size_t)(n + 1) * sizeof(int);
+  const size_t eig_lds = (size_t)5 * n * sizeof(double) + (size_t)(n + 1 + 1024) * sizeof(int);
   T.begin(ST_TRIEIG);
-  hipLaunchKernelGGL(k_trieig, dim3(ns), dim3(1024), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount, L.mu, L.alpha,
-                     L.thresh);
+  hipLaunchKernelGGL(k_trieig<0>, dim3(ns), dim3(1024), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount, L.mu,
+                     L.alpha, L.thresh);
   T.end(ST_TRIEIG);
+  T.begin(ST_TRIVEC);
+  hipLaunchKernelGGL(k_trieig<1>, dim3(ns), dim3(1024), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount, L.mu,
+                     L.alpha, L.thresh);
+  T.end(ST_TRIVEC);
   T.begin(ST_BACKTRANS);
   launch_backtrans(L, s);
   T.end(ST_BACKTRANS);
@@ -1467,8 +1504,10 @@ void launch_svt_vjp(const SvtVjpLaunch& J, hipStream_t s) {
   // full eigendecomposition of every Gram (thresh < 0: all eigenpairs)
   hipLaunchKernelGGL(k_gram<kF32>, dim3(TT * (TT + 1) / 2, ns), dim3(256), 0, s, L.desc, L.slices, L.gram);
   launch_tridiag(L, s);
-  const size_t eig_lds = (size_t)5 * n * sizeof(double) + (size_t)(n + 1) * sizeof(int);
-  hipLaunchKernelGGL(k_trieig, dim3(ns), dim3(1024), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount,
+  const size_t eig_lds = (size_t)5 * n * sizeof(double) + (size_t)(n + 1 + 1024) * sizeof(int);
+  hipLaunchKernelGGL(k_trieig<0>, dim3(ns), dim3(1024), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount,
+                     (const double*)nullptr, 0.0, -1.f);
+  hipLaunchKernelGGL(k_trieig<1>, dim3(ns), dim3(1024), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount,
                      (const double*)nullptr, 0.0, -1.f);
   launch_backtrans(L, s);
   // B = M V, C = D V (or U^H M, U^H D)
