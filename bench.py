@@ -78,6 +78,30 @@ def stage_model(shapes, ranks_per_slice):
     return tot
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there is
+    none or the kernel's source has changed since it was measured."""
+    import glob
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2204_12879_amd", "csrc", "k_svt.hip")).read()
+    try:
+        a = src.index("// Householder reduction with the packed Gram held on-chip")
+        b = src.index("// ------", a)
+    except ValueError:
+        return None
+    digest = hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*traffic*.md")):
+        fields = {}
+        for line in open(path):
+            parts = line.strip().split(":", 1)
+            if len(parts) == 2:
+                fields[parts[0].strip()] = parts[1].strip()
+        if fields.get("kernel") == kernel and fields.get("source") == digest:
+            return float(fields["traffic_bytes_per_launch"])
+    return None
+
+
 def cpu_baseline(noisy, params_kw, iters):
     """FP64 oracle on this host: `iters` ADMM iterations from the initial state."""
     import numpy as np
@@ -157,6 +181,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (skip the autotuner)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also copy the solver state once (library copy kernels of known size, for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (the single-GPU share of the workload); "
@@ -212,6 +238,14 @@ def main():
     torch.cuda.synchronize()
     ranks_last = solver.slice_ranks()
 
+    if args.copy_calibration:
+        # 16 state cubes through k_copy: 4 launches of N floats, 4 of 3N floats
+        buf = L.StateBuffer(solver.total)
+        solver.save_state(buf)
+        torch.cuda.synchronize()
+        print(f"bench: copy calibration, {solver.total * 4} and {solver.total * 12} bytes per launch",
+              file=sys.stderr, flush=True)
+
     # per-stage timing (separate instrumented run of the same K iterations)
     solver.reset(Y)
     solver.profile(True)
@@ -232,7 +266,13 @@ def main():
         roof = {"bound": "alu" if dom == "tridiag" else "mfma",
                 "achieved": amount / (avg_ms * 1e-3) / 1e12, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    traffic = measured_traffic(dom) if args.workload == "wdc" else None
+    roof["traffic"] = traffic                        # HBM bytes per launch (rocprofv3 counters), or None
+    roof["traffic_unit"] = "bytes per launch"
+    if dom == "tridiag":
+        # the packed Gram read once, reflectors written over it, 5 n doubles out
+        roof["algorithmic_bytes"] = float(sum(3 * (b // 2 + 1) * (2 * 8 * min(h, w) * (min(h, w) + 1) / 2
+                                                                  + 5 * 8 * min(h, w)) for b, h, w in shapes))
     roof["kernel"] = dom
     roof["avg_launch_ms"] = avg_ms
     svt_stages = ["gram", "tridiag", "trieig", "trivec", "backtrans", "bp1", "colnorm", "bp2"]

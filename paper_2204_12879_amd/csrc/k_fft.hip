@@ -523,9 +523,9 @@ struct CubeSel {
 };
 LRSTV_DEV CubeSel select_cube(const BatchTab& bt) {
   CubeSel r;
-  r.c = find_cube(bt.bstart, bt.nc, blockIdx.x);
-  r.bid = blockIdx.x - bt.bstart[r.c];
-  r.nblk = bt.bstart[r.c + 1] - bt.bstart[r.c];
+  r.c = __builtin_amdgcn_readfirstlane(find_cube(bt.bstart, bt.nc, blockIdx.x));
+  r.bid = blockIdx.x - __builtin_amdgcn_readfirstlane(bt.bstart[r.c]);
+  r.nblk = __builtin_amdgcn_readfirstlane(bt.bstart[r.c + 1] - bt.bstart[r.c]);
   return r;
 }
 
@@ -533,7 +533,7 @@ __global__ void __launch_bounds__(256) k_rfft_w_batch(BatchTab bt, const float* 
                                                       float2* __restrict__ spec) {
   extern __shared__ float2 sm[];
   const CubeSel q = select_cube(bt);
-  const CubeGeo g = bt.geo[q.c];
+  const CubeGeo g = uniform_geo(bt.geo, q.c);
   rfft_w_body(q.bid, q.nblk, sm, T + g.off, spec + g.spec_off, g.h * g.b, g.w, g.nb_w);
 }
 
@@ -541,7 +541,7 @@ __global__ void __launch_bounds__(256) k_irfft_w_batch(BatchTab bt, const float2
                                                        float* __restrict__ Z, double* __restrict__ part) {
   extern __shared__ float2 sm[];
   const int c = blockIdx.x / LRSTV_PARTS;
-  const CubeGeo g = bt.geo[c];
+  const CubeGeo g = uniform_geo(bt.geo, c);
   irfft_w_body(blockIdx.x - c * LRSTV_PARTS, LRSTV_PARTS, sm, spec + g.spec_off, Z + g.off, g.h * g.b, g.w, g.nb_w,
                1.0f / ((float)g.h * (float)g.w), part ? part + (int64_t)c * R_COUNT * LRSTV_PARTS : nullptr);
 }
@@ -549,14 +549,14 @@ __global__ void __launch_bounds__(256) k_irfft_w_batch(BatchTab bt, const float2
 __global__ void __launch_bounds__(256) k_fft_h_batch(BatchTab bt, float2* __restrict__ spec, int sign) {
   extern __shared__ float2 sm[];
   const CubeSel q = select_cube(bt);
-  const CubeGeo g = bt.geo[q.c];
+  const CubeGeo g = uniform_geo(bt.geo, q.c);
   fft_h_body(q.bid, q.nblk, sm, spec + g.spec_off, g.h, g.w / 2 + 1, g.b, g.cw_h, sign);
 }
 
 __global__ void __launch_bounds__(256) k_tri_b_batch(BatchTab bt, float2* __restrict__ spec, double w1, double w2,
                                                      double w3, const double* __restrict__ mu_dev) {
   const CubeSel q = select_cube(bt);
-  const CubeGeo g = bt.geo[q.c];
+  const CubeGeo g = uniform_geo(bt.geo, q.c);
   tri_b_body(q.bid, q.nblk, spec + g.spec_off, g.h, g.w, g.b, w1, w2, w3, mu_dev, 0.0);
 }
 
@@ -564,7 +564,7 @@ __global__ void __launch_bounds__(256) k_tri_b_batch(BatchTab bt, float2* __rest
 __global__ void __launch_bounds__(256) k_band_dft_batch(BatchTab bt, const float* __restrict__ A, int64_t a_stride,
                                                         float* __restrict__ slices) {
   const CubeSel q = select_cube(bt);
-  const CubeGeo g = bt.geo[q.c];
+  const CubeGeo g = uniform_geo(bt.geo, q.c);
   band_dft_body(q.bid, q.nblk, A + g.off, a_stride, 3, slices + g.slice_base, g.h * g.w, g.b);
 }
 
@@ -573,7 +573,7 @@ __global__ void __launch_bounds__(256) k_band_idft_batch(BatchTab bt, const floa
                                                          const float* __restrict__ F, float* __restrict__ G4,
                                                          const double* __restrict__ mu_dev, double* __restrict__ part) {
   const int c = blockIdx.x / LRSTV_PARTS;
-  const CubeGeo g = bt.geo[c];
+  const CubeGeo g = uniform_geo(bt.geo, c);
   band_idft_body(blockIdx.x - c * LRSTV_PARTS, LRSTV_PARTS, slices + g.slice_base, 3, E + g.off, e_stride,
                  g.h * g.w, g.b, F + g.off, G4 + g.off, mu_dev, part + (int64_t)c * R_COUNT * LRSTV_PARTS);
 }

@@ -647,8 +647,11 @@ LRSTV_DEV int sturm_count_fast(const double* dg, const double* e2, int n, double
 // output column c = eigenvector of the c-th largest kept eigenvalue times the
 // phase (V re/im planes).
 // PHASE 0 computes the eigenvalues (kept in the tridiagonal scratch at 5n,
-// scaled by 1 / ||T||), PHASE 1 the eigenvectors from them; both redo the
-// O(n) set-up (scaling, splits, the count of eigenvalues below the cut).
+// scaled by 1 / ||T||); PHASE 1 the eigenvectors from them, spread over
+// blocks of 64 eigenvalues (grid: vector blocks x slices), so that more
+// waves hide the latency of their sequential recurrences; PHASE 2
+// re-orthogonalises clusters and writes V.  Each redoes the O(n) set-up
+// (scaling, splits, the count of eigenvalues below the cut).
 template <int PHASE>
 __global__ void __launch_bounds__(1024) k_trieig(const SliceDesc* __restrict__ desc, double* __restrict__ tri,
                                                  double* __restrict__ xs, float* __restrict__ V,
@@ -657,7 +660,9 @@ __global__ void __launch_bounds__(1024) k_trieig(const SliceDesc* __restrict__ d
   extern __shared__ double smd[];
   __shared__ double red[16];
   __shared__ int s_c0, s_nblk;
-  const SliceDesc d = desc[blockIdx.x];
+  // PHASE 1 runs a grid of (vector blocks, slices); the others one block per slice
+  const int slice = PHASE == 1 ? blockIdx.y : blockIdx.x;
+  const SliceDesc d = desc[slice];
   const int n = d.n1;
   double* dg = tri + d.t_off;
   const double* eab = dg + n;
@@ -717,7 +722,7 @@ __global__ void __launch_bounds__(1024) k_trieig(const SliceDesc* __restrict__ d
   __syncthreads();
   const int c0 = s_c0, nblk = s_nblk, r = n - c0;
   double* lam_g = tri + d.t_off + 5 * n;   // eigenvalues between the two phases
-  if (PHASE == 1) {
+  if (PHASE != 0) {
     for (int k = c0 + threadIdx.x; k < n; k += blockDim.x) lam[k] = lam_g[k];
   }
   // Shared first step: the counts at G = blockDim points spread over
@@ -773,7 +778,8 @@ __global__ void __launch_bounds__(1024) k_trieig(const SliceDesc* __restrict__ d
   const int64_t nn = (int64_t)n * n;
   double* X = xs + d.x_off;    // [3][n][n] : Um, Dm(-> x), Lp ; column index k - c0
   const double tol_eq = 1e-13 * tnorm + pivmin;
-  for (int k = c0 + threadIdx.x; k < n; k += blockDim.x) {
+  if (PHASE == 2) goto reorth;
+  for (int k = c0 + blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
     const int col = k - c0;
     const double lk = lam[k];
     int pick = 0;
@@ -868,6 +874,8 @@ __global__ void __launch_bounds__(1024) k_trieig(const SliceDesc* __restrict__ d
     const double inv = 1.0 / sqrt(nrm);
     for (int i = p0; i <= p1; ++i) x[(int64_t)i * n] *= inv;
   }
+  if (PHASE == 1) return;
+reorth:
   __syncthreads();
   // Re-orthogonalise inside clusters (gaps below 1e-10 ||T||; larger gaps give
   // FP64 twisted-factorisation vectors accurate to eps_64 / gap): classical
@@ -910,7 +918,7 @@ __global__ void __launch_bounds__(1024) k_trieig(const SliceDesc* __restrict__ d
     Vr[(int64_t)i * n + c] = (float)(phr[i] * xv);
     Vi[(int64_t)i * n + c] = (float)(phi[i] * xv);
   }
-  if (threadIdx.x == 0) rcount[blockIdx.x] = r;
+  if (threadIdx.x == 0) rcount[slice] = r;
 }
 
 // ------------------------------------------- blocked back-transform (WY) ---
@@ -1442,6 +1450,15 @@ void prepare_svt(int max_n1) {
       (void)hipGetLastError();  // clear the sticky error: the global-memory variant is used instead
   }
 }
+static void launch_trivec(const SvtLaunch& L, hipStream_t s, size_t eig_lds, const double* mu, float thresh) {
+  const int ns = L.n_slices, n = L.max_n1;
+  constexpr int VB = 64;
+  hipLaunchKernelGGL(k_trieig<1>, dim3((n + VB - 1) / VB, ns), dim3(VB), eig_lds, s, L.desc, L.tri, L.xs, L.V,
+                     L.rcount, mu, L.alpha, thresh);
+  hipLaunchKernelGGL(k_trieig<2>, dim3(ns), dim3(1024), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount, mu, L.alpha,
+                     thresh);
+}
+
 static size_t tridiag_onchip_bytes(int n) {
   return ((size_t)n * (n + 1) / 2 + 2 * (size_t)n + 4 * (size_t)n) * sizeof(float2);
 }
@@ -1468,8 +1485,7 @@ void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm) {
                      L.alpha, L.thresh);
   T.end(ST_TRIEIG);
   T.begin(ST_TRIVEC);
-  hipLaunchKernelGGL(k_trieig<1>, dim3(ns), dim3(1024), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount, L.mu,
-                     L.alpha, L.thresh);
+  launch_trivec(L, s, eig_lds, L.mu, L.thresh);
   T.end(ST_TRIVEC);
   T.begin(ST_BACKTRANS);
   launch_backtrans(L, s);
@@ -1507,8 +1523,7 @@ void launch_svt_vjp(const SvtVjpLaunch& J, hipStream_t s) {
   const size_t eig_lds = (size_t)5 * n * sizeof(double) + (size_t)(n + 1 + 1024) * sizeof(int);
   hipLaunchKernelGGL(k_trieig<0>, dim3(ns), dim3(1024), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount,
                      (const double*)nullptr, 0.0, -1.f);
-  hipLaunchKernelGGL(k_trieig<1>, dim3(ns), dim3(1024), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount,
-                     (const double*)nullptr, 0.0, -1.f);
+  launch_trivec(L, s, eig_lds, nullptr, -1.f);
   launch_backtrans(L, s);
   // B = M V, C = D V (or U^H M, U^H D)
   hipLaunchKernelGGL(k_bp1<kF32>, dim3(TM, TM, ns), dim3(256), 0, s, L.desc, L.slices, L.V, L.B, L.rcount);

@@ -81,7 +81,7 @@ LRSTV_DEV void lrhs_body(int bid, int nblk, const float* __restrict__ O, const f
 __global__ void __launch_bounds__(256) k_lrhs_batch(BatchTab bt, BatchPtrs p, float w1, float w2, float w3,
                                                     const double* __restrict__ mu_dev) {
   const int c = find_cube(bt.bstart, bt.nc, blockIdx.x);
-  const CubeGeo g = bt.geo[c];
+  const CubeGeo g = uniform_geo(bt.geo, c);
   const int64_t o = g.off;
   lrhs_body(blockIdx.x - bt.bstart[c], bt.bstart[c + 1] - bt.bstart[c], p.O + o, p.S + o, p.Z + o, p.G1 + o,
             p.G2 + o, p.F + o, p.G3 + o, p.ts, p.L + o, p.T + o, g.h, g.w, g.b, w1, w2, w3, mu_dev);
@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(256) k_grad_shrink_batch(BatchTab bt, BatchPtr
                                                            float tau, float lam, const double* __restrict__ mu_dev,
                                                            double* __restrict__ part) {
   const int c = blockIdx.x / LRSTV_PARTS;
-  const CubeGeo g = bt.geo[c];
+  const CubeGeo g = uniform_geo(bt.geo, c);
   const int64_t o = g.off;
   grad_shrink_body(blockIdx.x - c * LRSTV_PARTS, p.O + o, p.L + o, p.Z + o, p.S + o, p.G1 + o, p.G2 + o, p.F + o,
                    p.E + o, p.G3 + o, p.G4 + o, p.A + o, p.ts, p.ts, g.h, g.w, g.b, w1, w2, w3, tau, lam, mu_dev,

@@ -39,6 +39,28 @@ struct BatchPtrs {
   int64_t ts;
 };
 int phase_blocks(int phase, int h, int w, int b);
+
+// The geometry of cube c as wave-uniform (scalar-register) values: the
+// table is read once per block and every field is made uniform explicitly,
+// so the per-cube sizes and offsets do not occupy vector registers.
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffff));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return ((int64_t)hi << 32) | (uint32_t)lo;
+}
+__device__ __forceinline__ CubeGeo uniform_geo(const CubeGeo* geo, int c) {
+  const CubeGeo g = geo[c];
+  CubeGeo u;
+  u.h = __builtin_amdgcn_readfirstlane(g.h);
+  u.w = __builtin_amdgcn_readfirstlane(g.w);
+  u.b = __builtin_amdgcn_readfirstlane(g.b);
+  u.nb_w = __builtin_amdgcn_readfirstlane(g.nb_w);
+  u.cw_h = __builtin_amdgcn_readfirstlane(g.cw_h);
+  u.off = uniform_i64(g.off);
+  u.spec_off = uniform_i64(g.spec_off);
+  u.slice_base = uniform_i64(g.slice_base);
+  return u;
+}
 int geo_rows_nb(int w);
 int geo_cols_cw(int h);
 
