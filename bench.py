@@ -78,17 +78,26 @@ def stage_model(shapes, ranks_per_slice):
     return tot
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there is
-    none or the kernel's source has changed since it was measured."""
+# Source text that the traffic summaries are keyed on, per tridiagonalisation
+# kind (shape code // 100): from the marker to the next section rule.
+TRIDIAG_SOURCE_MARKERS = {0: "// Householder reduction with the packed Gram held on-chip",
+                          1: "// ------------------------------------ tridiagonalisation on MFMA tiles ---"}
+
+
+def measured_traffic(kernel, shape_code=None):
+    """HBM bytes per launch of `kernel` (for the tridiagonalisation, of shape
+    `shape_code`) from the committed rocprofv3 counter summary (FETCH_SIZE +
+    WRITE_SIZE, copy-calibrated), or None when there is none or the kernel's
+    source has changed since it was measured."""
     import glob
     import hashlib
+    if kernel != "tridiag" or shape_code is None:
+        return None
     src = open(os.path.join(ROOT, "paper_2204_12879_amd", "csrc", "k_svt.hip")).read()
     try:
-        a = src.index("// Householder reduction with the packed Gram held on-chip")
-        b = src.index("// ------", a)
-    except ValueError:
+        a = src.index(TRIDIAG_SOURCE_MARKERS[shape_code // 100])
+        b = src.index("// ------", a + 1)
+    except (KeyError, ValueError):
         return None
     digest = hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
     for path in glob.glob(os.path.join(ROOT, "profiles", "*traffic*.md")):
@@ -97,7 +106,8 @@ def measured_traffic(kernel):
             parts = line.strip().split(":", 1)
             if len(parts) == 2:
                 fields[parts[0].strip()] = parts[1].strip()
-        if fields.get("kernel") == kernel and fields.get("source") == digest:
+        if (fields.get("kernel") == kernel and fields.get("source") == digest
+                and fields.get("shape", str(shape_code)) == str(shape_code)):
             return float(fields["traffic_bytes_per_launch"])
     return None
 
@@ -266,14 +276,15 @@ def main():
         roof = {"bound": "alu" if dom == "tridiag" else "mfma",
                 "achieved": amount / (avg_ms * 1e-3) / 1e12, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    traffic = measured_traffic(dom) if args.workload == "wdc" else None
+    shape_code = solver.get_tuning()["tridiag_shape"]
+    traffic = measured_traffic(dom, shape_code) if args.workload == "wdc" else None
     roof["traffic"] = traffic                        # HBM bytes per launch (rocprofv3 counters), or None
     roof["traffic_unit"] = "bytes per launch"
     if dom == "tridiag":
         # the packed Gram read once, reflectors written over it, 5 n doubles out
         roof["algorithmic_bytes"] = float(sum(3 * (b // 2 + 1) * (2 * 8 * min(h, w) * (min(h, w) + 1) / 2
                                                                   + 5 * 8 * min(h, w)) for b, h, w in shapes))
-    roof["kernel"] = dom
+    roof["kernel"] = dom if dom != "tridiag" else f"tridiag (shape {shape_code})"
     roof["avg_launch_ms"] = avg_ms
     svt_stages = ["gram", "tridiag", "trieig", "trivec", "backtrans", "bp1", "colnorm", "bp2"]
     svt_ms = sum(st[k][0] for k in svt_stages)

@@ -247,16 +247,21 @@ int lrstv_zsolve(const float* T, float* Z, int32_t h, int32_t w, int32_t b, doub
 /* ---- autotuner ---------------------------------------------------------- */
 
 /* Launch shapes chosen per handle.  The slice tridiagonalisation (the
- * dominant kernel) has compiled shapes of 8, 12 and 16 waves per slice
- * (with 10, 7 and 6 VGPR-resident rows per wave); which is fastest depends
- * on the slice sizes of the batch. */
+ * dominant kernel) has compiled shapes, each named by a code 100 k + w:
+ * k = 0 keeps the packed Gram's rows in registers and LDS and reduces them
+ * on the vector units (w = 8, 12, 16 waves per slice); k = 1 keeps the
+ * whole Gram in 32 x 32 register tiles and applies the rank-2 update on the
+ * matrix cores (w = 12, 8; slices up to 256).  Which is fastest depends on
+ * the slice sizes of the batch. */
+#define LRSTV_MAX_TRI_SHAPES 8
 typedef struct lrstv_tuning {
-  int32_t tridiag_waves;            /* chosen shape: 8, 12 or 16            */
-  int32_t n_variants;               /* shapes tried (filled by autotune)    */
-  int32_t tridiag_waves_tried[4];
-  double  tridiag_ms[4];            /* mean ms per launch over the handle's
-                                       slices, -1 if the shape cannot hold
-                                       them on chip                         */
+  int32_t tridiag_shape;                        /* chosen shape code        */
+  int32_t n_shapes;                             /* entries below            */
+  int32_t shapes_tried[LRSTV_MAX_TRI_SHAPES];   /* codes                    */
+  double  tridiag_ms[LRSTV_MAX_TRI_SHAPES];     /* mean ms per launch over the
+                                                   handle's slices, -1 if the
+                                                   shape cannot hold them on
+                                                   chip                     */
 } lrstv_tuning;
 
 /* Time every tridiagonalisation shape on this handle's slice sizes (slices
@@ -267,7 +272,7 @@ typedef struct lrstv_tuning {
  * Synchronises the stream.  out may be NULL.  Errors: INVALID_ARG, HIP. */
 int lrstv_autotune(lrstv_handle hd, int32_t reps, lrstv_tuning* out);
 
-/* Apply a stored choice (only tridiag_waves is read).  INVALID_ARG for a
+/* Apply a stored choice (only tridiag_shape is read).  INVALID_ARG for a
  * shape that does not exist. */
 int lrstv_set_tuning(lrstv_handle hd, const lrstv_tuning* t);
 

@@ -13,6 +13,7 @@ LRSTV_FP32 = 0
 LRSTV_SPLIT_BF16 = 1
 LRSTV_NRES = 7
 LRSTV_VJP_INITIAL = 1
+LRSTV_MAX_TRI_SHAPES = 8
 RESIDUAL_NAMES = ("inf_OLS", "inf_LZ", "fro_OLS", "fro_LZ", "fro_DZF", "fro_EF", "dual_Z")
 WARN_NOT_CONVERGED = 1
 NSTAGES = 17
@@ -40,8 +41,8 @@ class _StateView(C.Structure):
 
 
 class _Tuning(C.Structure):
-    _fields_ = [("tridiag_waves", C.c_int32), ("n_variants", C.c_int32), ("tridiag_waves_tried", C.c_int32 * 4),
-                ("tridiag_ms", C.c_double * 4)]
+    _fields_ = [("tridiag_shape", C.c_int32), ("n_shapes", C.c_int32),
+                ("shapes_tried", C.c_int32 * LRSTV_MAX_TRI_SHAPES), ("tridiag_ms", C.c_double * LRSTV_MAX_TRI_SHAPES)]
 
 
 class _Report(C.Structure):
@@ -255,22 +256,25 @@ class Solver:
 
     def autotune(self, reps: int = 3) -> dict:
         """Time the tridiagonalisation shapes on this batch's slice sizes and
-        keep the fastest (lrstv_autotune).  Returns {"tridiag_waves": w,
-        "tridiag_ms": {waves: ms}} (ms -1: shape cannot run on chip)."""
+        keep the fastest (lrstv_autotune).  Returns {"tridiag_shape": code,
+        "tridiag_ms": {code: ms}} (ms -1: shape cannot run on chip).  Shape
+        codes: 8, 12, 16 (rows on the vector units, that many waves), 112,
+        108 (register tiles on the matrix cores, 12 or 8 waves)."""
         t = _Tuning()
         _check(self.lib.lrstv_autotune(self.handle, int(reps), C.byref(t)))
-        return {"tridiag_waves": t.tridiag_waves,
-                "tridiag_ms": {int(t.tridiag_waves_tried[i]): float(t.tridiag_ms[i]) for i in range(t.n_variants)}}
+        return {"tridiag_shape": t.tridiag_shape,
+                "tridiag_ms": {int(t.shapes_tried[i]): float(t.tridiag_ms[i]) for i in range(t.n_shapes)}}
 
-    def set_tuning(self, tridiag_waves: int) -> None:
+    def set_tuning(self, tridiag_shape: int) -> None:
         t = _Tuning()
-        t.tridiag_waves = int(tridiag_waves)
+        t.tridiag_shape = int(tridiag_shape)
         _check(self.lib.lrstv_set_tuning(self.handle, C.byref(t)))
 
     def get_tuning(self) -> dict:
         t = _Tuning()
         _check(self.lib.lrstv_get_tuning(self.handle, C.byref(t)))
-        return {"tridiag_waves": t.tridiag_waves}
+        return {"tridiag_shape": t.tridiag_shape,
+                "shapes": [int(t.shapes_tried[i]) for i in range(t.n_shapes)]}
 
     def set_graph(self, enable: bool = True) -> None:
         """Replay iterations from a captured hipGraph (bit-identical to eager launches)."""

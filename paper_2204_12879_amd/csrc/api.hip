@@ -15,6 +15,7 @@
 
 static_assert(LRSTV_MAX_SIDE == LRSTV_MAX_SIDE_DEV, "device-side size bound out of step");
 #include "kernels.hpp"
+static_assert(lrstv::kTriVariants <= LRSTV_MAX_TRI_SHAPES, "tuning record too small for the shape table");
 
 using namespace lrstv;
 
@@ -1063,12 +1064,12 @@ extern "C" int lrstv_autotune(lrstv_handle H, int32_t reps, lrstv_tuning* out) {
   HIPCHK(hipEventCreate(&e1));
   lrstv_tuning t;
   memset(&t, 0, sizeof t);
-  t.n_variants = kTriVariants;
+  t.n_shapes = kTriVariants;
   int best = -1;
   double best_ms = 0.0;
   hipError_t err = hipSuccess;
   for (int v = 0; v < kTriVariants && err == hipSuccess; ++v) {
-    t.tridiag_waves_tried[v] = tri_variant_waves(v);
+    t.shapes_tried[v] = tri_variant_code(v);
     t.tridiag_ms[v] = -1.0;  // not runnable on chip for this batch
     if (!tri_variant_onchip(v, sv.max_n1)) continue;
     sv.tri_variant = v;
@@ -1098,7 +1099,7 @@ extern "C" int lrstv_autotune(lrstv_handle H, int32_t reps, lrstv_tuning* out) {
     H->tri_variant = best;
     drop_graph(H);
   }
-  t.tridiag_waves = tri_variant_waves(H->tri_variant);
+  t.tridiag_shape = tri_variant_code(H->tri_variant);
   if (out) *out = t;
   return LRSTV_OK;
 }
@@ -1107,8 +1108,8 @@ extern "C" int lrstv_set_tuning(lrstv_handle H, const lrstv_tuning* t) {
   if (!H || !t) return fail(LRSTV_ERR_INVALID_ARG, "handle or tuning is NULL");
   int v = -1;
   for (int i = 0; i < kTriVariants; ++i)
-    if (tri_variant_waves(i) == t->tridiag_waves) v = i;
-  if (v < 0) return fail(LRSTV_ERR_INVALID_ARG, "no tridiagonalisation shape with %d waves", t->tridiag_waves);
+    if (tri_variant_code(i) == t->tridiag_shape) v = i;
+  if (v < 0) return fail(LRSTV_ERR_INVALID_ARG, "no tridiagonalisation shape %d", t->tridiag_shape);
   if (v != H->tri_variant) {
     H->tri_variant = v;
     drop_graph(H);
@@ -1119,10 +1120,10 @@ extern "C" int lrstv_set_tuning(lrstv_handle H, const lrstv_tuning* t) {
 extern "C" int lrstv_get_tuning(lrstv_handle H, lrstv_tuning* t) {
   if (!H || !t) return fail(LRSTV_ERR_INVALID_ARG, "handle or tuning is NULL");
   memset(t, 0, sizeof *t);
-  t->tridiag_waves = tri_variant_waves(H->tri_variant);
-  t->n_variants = kTriVariants;
+  t->tridiag_shape = tri_variant_code(H->tri_variant);
+  t->n_shapes = kTriVariants;
   for (int v = 0; v < kTriVariants; ++v) {
-    t->tridiag_waves_tried[v] = tri_variant_waves(v);
+    t->shapes_tried[v] = tri_variant_code(v);
     t->tridiag_ms[v] = -1.0;
   }
   return LRSTV_OK;

@@ -600,6 +600,269 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_reg(const SliceDesc* __rest
   }
 }
 
+// ------------------------------------ tridiagonalisation on MFMA tiles ---
+// The same Householder reduction (same reflector convention and outputs as
+// k_tridiag_reg) with the whole Hermitian Gram held in registers as 32 x 32
+// tiles in the matrix-core accumulator layout: lane l, element r of tile
+// (R, C) is G(32 R + rho(r, l / 32), 32 C + l % 32), rho(r, h) =
+// 8 (r / 4) + 4 h + r % 4.  Lower tiles (R >= C) only; the diagonal tiles
+// hold both triangles.  NW waves hold TPW tiles each, dealt column-major.
+// Per step i (v and w vanish at indices <= i, so nothing outside the
+// trailing block changes and no masking is needed):
+//   A  column i below the diagonal from the lanes holding it, its norm
+//   B  reflector (every thread), v into LDS, reflector column to the Gram
+//   C  p = A v: the column sums conj(a) v_row are lane-local (two halves
+//      combined), and give the whole product of a diagonal tile; the row
+//      sums a v_col of an off-diagonal tile go through an LDS transpose.
+//      Partial sums per wave, v^H A v from the lane-local pieces
+//   D  w = tau p - (tau^2 v^H A v / 2) v
+//   E  A -= v w^H + w v^H: per tile four v_mfma_f32_32x32x2f32 (real and
+//      imaginary parts as rank-4 real products).
+LRSTV_DEV int mt_rho(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
+
+// tile t of the column-major enumeration of the lower tiles of an NT x NT grid
+LRSTV_DEV void mt_tile(int t, int NT, int& R, int& C) {
+  C = 0;
+  while (t >= NT - C) {
+    t -= NT - C;
+    ++C;
+  }
+  R = C + t;
+}
+
+template <int NW, int TPW>
+__global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __restrict__ desc,
+                                                         float2* __restrict__ gram, double* __restrict__ tri) {
+  constexpr int NMAX = 256;
+  static_assert(NW * TPW >= 36, "the 36 lower tiles of a 256 x 256 Gram");
+  __shared__ float2 xb[2][NMAX];
+  __shared__ float2 vb[NMAX], wb[NMAX];
+  __shared__ float2 P[NW][NMAX];              // per-wave partial sums of A v
+  // per-wave transpose of the row products; entry (r, l) at r * 68 + l + l / 16,
+  // which keeps both the row-wise writes and the chunk-wise reads conflict-free
+  __shared__ float2 scr[NW][16 * 68];
+  __shared__ double red_nx[2][NW], red_vav[NW];
+  __shared__ double s_dii[2];
+  const SliceDesc d = desc[blockIdx.x];
+  const int n = d.n1;
+  if (n <= 0) return;
+  const int NT = (n + 31) >> 5, ntile = NT * (NT + 1) / 2;
+  float2* gA = gram + d.g_off;
+  const int lane = threadIdx.x & 63, li = lane & 31, h = lane >> 5;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double* dg = tri + d.t_off;
+  double* eab = dg + n;
+  double* phr = eab + n;
+  double* phi = phr + n;
+  double* taus = phi + n;
+  const float2 zero = make_float2(0.f, 0.f);
+  // ---- load the tiles ----------------------------------------------------
+  f32x16 tre[TPW], tim[TPW];
+  int tR[TPW], tC[TPW];
+#pragma unroll
+  for (int s = 0; s < TPW; ++s) {
+    const int t = wv + NW * s;
+    int R = -1, C = -1;
+    if (t < ntile) mt_tile(t, NT, R, C);
+    tR[s] = R;
+    tC[s] = C;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      float2 a = zero;
+      if (R >= 0) {
+        const int row = 32 * R + mt_rho(r, h), col = 32 * C + li;
+        if (row < n && col < n) a = row >= col ? gA[packed(row, col)] : cconj(gA[packed(col, row)]);
+      }
+      tre[s][r] = a.x;
+      tim[s][r] = a.y;
+    }
+  }
+  // ---- exact power-of-two scaling to ||G||_F ~ 1 (as in k_tridiag_reg) ----
+  double fro = 0.0;
+#pragma unroll
+  for (int s = 0; s < TPW; ++s) {
+    const double wgt = tR[s] == tC[s] ? 1.0 : 2.0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) fro += wgt * ((double)tre[s][r] * tre[s][r] + (double)tim[s][r] * tim[s][r]);
+  }
+  fro = warp_sum(fro);
+  if (lane == 0) red_vav[wv] = fro;
+  __syncthreads();
+  double fro2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < NW; ++q) fro2 += red_vav[q];
+  const int ex = fro2 > 0.0 ? ilogb(sqrt(fro2)) : 0;
+  const float gsc = ldexpf(1.0f, -ex);
+  const double unsc = ldexp(1.0, ex);
+#pragma unroll
+  for (int s = 0; s < TPW; ++s)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      tre[s][r] *= gsc;
+      tim[s][r] *= gsc;
+    }
+  double ph_r = 1.0, ph_i = 0.0;
+  if (threadIdx.x == 0) { phr[0] = 1.0; phi[0] = 0.0; }
+  __syncthreads();
+  for (int i = 0; i < n; ++i) {
+    const int cb = i >> 5, cl = i & 31;
+    float2* xc = xb[i & 1];
+    // ---- A: column i of the current matrix below the diagonal; A(i, i) ----
+    {
+      double nrm = 0.0;
+#pragma unroll
+      for (int s = 0; s < TPW; ++s) {
+        if (tC[s] == cb && li == cl) {
+          // element r sits at row 32 R + 4 h + mt_rho(r, 0); compared through
+          // rel, which changes every step, so that no per-element row index
+          // stays live across the loop.  Padding rows (>= n) hold zeros.
+          const int rel = i - 32 * tR[s] - 4 * h;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int c = mt_rho(r, 0);
+            const float2 a = make_float2(tre[s][r], tim[s][r]);
+            if (c > rel) {
+              xc[i + c - rel] = a;
+              nrm += (double)a.x * a.x + (double)a.y * a.y;
+            } else if (c == rel) {
+              s_dii[i & 1] = (double)a.x;
+            }
+          }
+        }
+      }
+      nrm = warp_sum(nrm);
+      if (lane == 0) red_nx[i & 1][wv] = nrm;
+    }
+    __syncthreads();
+    if (i == n - 1) break;
+    // ---- B: reflector H x = beta e_1, v = [1; scl x], tau in [1, 2] -------
+    double nx2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) nx2 += red_nx[i & 1][q];
+    const double dii = s_dii[i & 1];
+    float2 x0 = xc[i + 1];
+    const double ax02 = (double)x0.x * x0.x + (double)x0.y * x0.y;
+    double taud = 0.0;
+    if (nx2 <= kDeflate2) x0 = zero;
+    float2 beta = x0, scl = zero;
+    if (nx2 > kDeflate2 && nx2 - ax02 > 1e-14 * nx2) {
+      const double nx = sqrt(nx2), ax0 = sqrt(ax02);
+      const double pr = ax0 > 0.0 ? x0.x / ax0 : 1.0, pim = ax0 > 0.0 ? x0.y / ax0 : 0.0;
+      beta = make_float2((float)(-pr * nx), (float)(-pim * nx));
+      const double inv = 1.0 / (ax0 + nx);
+      scl = make_float2((float)(pr * inv), (float)(-pim * inv));
+      taud = 1.0 + ax0 / nx;
+    }
+    if (threadIdx.x == 0) {
+      dg[i] = dii * unsc;
+      taus[i] = taud;
+      const double br = beta.x, bi = beta.y, ab = sqrt(br * br + bi * bi);
+      eab[i] = ab * unsc;
+      if (ab > 0.0) {
+        const double ur = br / ab, uq = bi / ab;
+        const double nr = ph_r * ur - ph_i * uq, ni = ph_r * uq + ph_i * ur;
+        ph_r = nr;
+        ph_i = ni;
+      }
+      phr[i + 1] = ph_r;
+      phi[i + 1] = ph_i;
+    }
+    const float tau = (float)taud;
+    const bool refl = tau != 0.f;
+    for (int t = threadIdx.x; t < NMAX; t += 64 * NW) {
+      float2 v = zero;
+      if (refl && t > i && t < n) v = (t == i + 1) ? make_float2(1.f, 0.f) : cmul(scl, xc[t]);
+      vb[t] = v;
+      if (t > i && t < n) gA[packed(t, i)] = v;   // reflector column (zeros without a reflection)
+    }
+    __syncthreads();
+    if (!refl) continue;
+    // ---- C: p = A v (per-wave partial sums) and v^H A v --------------------
+    for (int t = lane; t < NMAX; t += 64) P[wv][t] = zero;
+    float vavl = 0.f;
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+      const int R = tR[s], C = tC[s];
+      if (R < 0 || 32 * C + 31 <= i) continue;   // no element in the trailing block
+      const float2 vC = vb[32 * C + li];
+      float2 cacc = zero;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) cacc = cadd(cacc, cmulc(make_float2(tre[s][r], tim[s][r]), vb[32 * R + mt_rho(r, h)]));
+      // Re(conj(v_col) (A^H v)_col); twice for an off-diagonal tile (its mirror)
+      vavl += (R == C ? 1.f : 2.f) * (cacc.x * vC.x + cacc.y * vC.y);
+      const float2 co = make_float2(__shfl_xor(cacc.x, 32, 64), __shfl_xor(cacc.y, 32, 64));
+      if (h == 0) {
+        const int col = 32 * C + li;
+        P[wv][col] = cadd(P[wv][col], cadd(cacc, co));
+      }
+      if (R != C) {
+        // row sums: scr(r, lane) = a v_col; lane j then sums chunk q = j & 3
+        // (16 columns of half q >> 1) of row j >> 2
+        const int wpos = lane + (lane >> 4);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) scr[wv][r * 68 + wpos] = cmul(make_float2(tre[s][r], tim[s][r]), vC);
+        const int tr = lane >> 2, th = (lane >> 1) & 1, part = lane & 1;
+        const float2* src = &scr[wv][tr * 68 + 17 * (lane & 3)];
+        float2 sum = zero;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) sum = cadd(sum, src[e]);
+        sum.x += __shfl_xor(sum.x, 1, 64);
+        sum.y += __shfl_xor(sum.y, 1, 64);
+        if (part == 0) {
+          const int row = 32 * R + mt_rho(tr, th);
+          P[wv][row] = cadd(P[wv][row], sum);
+        }
+      }
+    }
+    {
+      const double vav = warp_sum((double)vavl);
+      if (lane == 0) red_vav[wv] = vav;
+    }
+    __syncthreads();
+    // ---- D: w = tau p - K v ------------------------------------------------
+    {
+      double vAv = 0.0;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) vAv += red_vav[q];
+      const float K = (float)(0.5 * taud * taud * vAv);
+      for (int t = threadIdx.x; t < NMAX; t += 64 * NW) {
+        float2 w = zero;
+        if (t > i && t < n) {
+          float2 pt = zero;
+#pragma unroll
+          for (int q = 0; q < NW; ++q) pt = cadd(pt, P[q][t]);
+          const float2 vt = vb[t];
+          w = make_float2(tau * pt.x - K * vt.x, tau * pt.y - K * vt.y);
+        }
+        wb[t] = w;
+      }
+    }
+    __syncthreads();
+    // ---- E: A -= v w^H + w v^H on the matrix cores -------------------------
+    // real part: [-v_R | -w_R] (re in half 0, im in half 1) times [w_C ; v_C];
+    // imaginary part: [-Im v, Re v] and [-Im w, Re w] against the same B.
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+      const int R = tR[s], C = tC[s];
+      if (R < 0 || 32 * C + 31 <= i) continue;
+      const float2 vR = vb[32 * R + li], wR = wb[32 * R + li];
+      const float2 vC = vb[32 * C + li], wC = wb[32 * C + li];
+      const float b0 = h ? wC.y : wC.x, b1 = h ? vC.y : vC.x;
+      const float ar0 = h ? -vR.y : -vR.x, ar1 = h ? -wR.y : -wR.x;
+      const float ai0 = h ? vR.x : -vR.y, ai1 = h ? wR.x : -wR.y;
+      tre[s] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar0, b0, tre[s], 0, 0, 0);
+      tre[s] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar1, b1, tre[s], 0, 0, 0);
+      tim[s] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai0, b0, tim[s], 0, 0, 0);
+      tim[s] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai1, b1, tim[s], 0, 0, 0);
+    }
+  }
+  if (threadIdx.x == 0) {
+    dg[n - 1] = s_dii[(n - 1) & 1] * unsc;
+    eab[n - 1] = 0.0;
+    taus[n - 1] = 0.0;
+  }
+}
+
 // ------------------------------------------------------ tridiagonal eigen ---
 // Number of eigenvalues of the real symmetric tridiagonal (d, e) below x
 // (Sturm sequence), restricted to rows [p0, p1].  Exact division.
@@ -1374,20 +1637,22 @@ __global__ void __launch_bounds__(256) k_vjp_r(const SliceDesc* __restrict__ des
 }
 
 // ------------------------------------------------------------ launcher ---
-// Tridiagonalisation shapes (waves per slice, VGPR-resident rows per wave),
-// chosen per handle by the autotuner.  More waves hide the LDS and
-// cross-lane latency of the per-row reductions (at 288 slices of 256 x 256:
-// 8 waves 8.7, 12 waves 7.1, 16 waves 6.6 ms per iteration); the rows per
-// wave keep the LDS part of the packed Gram under 160 KB.
+// Tridiagonalisation shapes, chosen per handle by the autotuner.  Shape code
+// 100 kind + waves: kind 0 is k_tridiag_reg (rows in VGPRs and LDS; more
+// waves hide the LDS and cross-lane latency of the per-row reductions, the
+// rows per wave keep the LDS part of the packed Gram under 160 KB), kind 1
+// is k_tridiag_mfma (32 x 32 register tiles, rank-2 update on the matrix
+// cores; static LDS, slices up to 256).
 struct TriShape {
-  int nw, jr;
+  int kind, nw, jr;
 };
-static const TriShape kTriShapes[kTriVariants] = {{8, 10}, {12, 7}, {16, 6}};
-// Dynamic LDS granted per variant (host-side function attribute, set
-// outside any stream capture by prepare_svt).
-static size_t g_tri_granted[kTriVariants] = {65536, 65536, 65536};
+static const TriShape kTriShapes[kTriVariants] = {{0, 8, 10}, {0, 12, 7}, {0, 16, 6}, {1, 12, 3}, {1, 8, 5}};
+// Dynamic LDS granted per row variant (host-side function attribute, set
+// outside any stream capture by prepare_svt), and the device's LDS per block.
+static size_t g_tri_granted[kTriVariants] = {65536, 65536, 65536, 0, 0};
+static int g_lds_max = 65536;
 
-int tri_variant_waves(int v) { return kTriShapes[v].nw; }
+int tri_variant_code(int v) { return 100 * kTriShapes[v].kind + kTriShapes[v].nw; }
 
 // Dynamic LDS of k_tridiag_reg: the packed LDS rows plus (3 + NW) n complex
 // (two columns, w, NW column-part rows).
@@ -1396,26 +1661,37 @@ static size_t tridiag_reg_lds(int n, int v) {
   const int RL = n > NW * JR ? n - NW * JR : 0;
   return ((size_t)RL * (RL + 1) / 2 + (size_t)(3 + NW) * n) * sizeof(float2);
 }
+// Static LDS of k_tridiag_mfma<NW, TPW>: two columns, v, w, NW partial rows
+// (256 complex each) and NW transposes of 16 x 68 complex.
+static size_t tridiag_mfma_lds(int nw) { return (size_t)(4 + nw) * 256 * sizeof(float2) + (size_t)nw * 16 * 68 * sizeof(float2) + 1024; }
 
 static const void* tri_kernel(int v) {
   switch (v) {
     case 0: return (const void*)k_tridiag_reg<10, 8>;
     case 1: return (const void*)k_tridiag_reg<7, 12>;
-    default: return (const void*)k_tridiag_reg<6, 16>;
+    case 2: return (const void*)k_tridiag_reg<6, 16>;
+    case 3: return (const void*)k_tridiag_mfma<12, 3>;
+    default: return (const void*)k_tridiag_mfma<8, 5>;
   }
 }
 
-bool tri_variant_onchip(int v, int n) { return n <= 256 && tridiag_reg_lds(n, v) <= g_tri_granted[v]; }
+bool tri_variant_onchip(int v, int n) {
+  if (n > 256) return false;
+  if (kTriShapes[v].kind == 1) return (int)tridiag_mfma_lds(kTriShapes[v].nw) <= g_lds_max;
+  return tridiag_reg_lds(n, v) <= g_tri_granted[v];
+}
 
 void launch_svt_tridiag(const SvtLaunch& L, hipStream_t s) {
   const int n = L.max_n1, ns = L.n_slices;
   const int v = (L.tri_variant >= 0 && L.tri_variant < kTriVariants) ? L.tri_variant : kTriDefault;
   if (tri_variant_onchip(v, n)) {
-    const size_t lds = tridiag_reg_lds(n, v);
+    const size_t lds = kTriShapes[v].kind == 0 ? tridiag_reg_lds(n, v) : 0;
     switch (v) {
       case 0: hipLaunchKernelGGL((k_tridiag_reg<10, 8>), dim3(ns), dim3(512), lds, s, L.desc, L.gram, L.tri); break;
       case 1: hipLaunchKernelGGL((k_tridiag_reg<7, 12>), dim3(ns), dim3(768), lds, s, L.desc, L.gram, L.tri); break;
-      default: hipLaunchKernelGGL((k_tridiag_reg<6, 16>), dim3(ns), dim3(1024), lds, s, L.desc, L.gram, L.tri); break;
+      case 2: hipLaunchKernelGGL((k_tridiag_reg<6, 16>), dim3(ns), dim3(1024), lds, s, L.desc, L.gram, L.tri); break;
+      case 3: hipLaunchKernelGGL((k_tridiag_mfma<12, 3>), dim3(ns), dim3(768), 0, s, L.desc, L.gram, L.tri); break;
+      default: hipLaunchKernelGGL((k_tridiag_mfma<8, 5>), dim3(ns), dim3(512), 0, s, L.desc, L.gram, L.tri); break;
     }
   } else {
     hipLaunchKernelGGL(k_tridiag<false>, dim3(ns), dim3(256), (size_t)(2 + 4) * n * sizeof(float2), s, L.desc,
@@ -1438,12 +1714,12 @@ void prepare_svt(int max_n1) {
   if (n > 256) return;
   int dev = 0;
   hipDeviceProp_t prop;
-  int lds_max = 65536;
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-    lds_max = (int)prop.sharedMemPerBlock;
+    g_lds_max = (int)prop.sharedMemPerBlock;
   for (int v = 0; v < kTriVariants; ++v) {
+    if (kTriShapes[v].kind != 0) continue;
     const size_t need = tridiag_reg_lds(n, v);
-    if (need <= g_tri_granted[v] || (int)need + 2048 > lds_max) continue;
+    if (need <= g_tri_granted[v] || (int)need + 2048 > g_lds_max) continue;
     if (hipFuncSetAttribute(tri_kernel(v), hipFuncAttributeMaxDynamicSharedMemorySize, (int)need) == hipSuccess)
       g_tri_granted[v] = need;
     else

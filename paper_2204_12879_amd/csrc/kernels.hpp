@@ -117,9 +117,9 @@ void launch_band_idft(const float* slices, int n_t, float* E, int64_t e_stride, 
                       const float* F, float* G4, const double* mu, double* part, hipStream_t s);
 
 // --- slice SVT ------------------------------------------------------------
-constexpr int kTriVariants = 3;   // tridiagonalisation shapes: 8, 12, 16 waves
-constexpr int kTriDefault = 2;
-int tri_variant_waves(int v);
+constexpr int kTriVariants = 5;   // tridiagonalisation shapes (codes 8, 12, 16, 112, 108)
+constexpr int kTriDefault = 4;
+int tri_variant_code(int v);      // 100 kind + waves
 bool tri_variant_onchip(int v, int n);
 // thresh: t = alpha / mu read on the device (mu != NULL) or the fixed value.
 struct SvtLaunch {

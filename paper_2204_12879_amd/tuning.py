@@ -45,11 +45,12 @@ def autotune(solver, cache_path: Optional[str] = None, reps: int = 3, refresh: b
     path = cache_path or default_cache_path()
     key = batch_key(solver)
     cache = _load(path)
-    if not refresh and key in cache:
-        solver.set_tuning(cache[key]["tridiag_waves"])
-        return dict(cache[key], cached=True)
+    hit = cache.get(key) if not refresh else None
+    if isinstance(hit, dict) and hit.get("tridiag_shape") in solver.get_tuning()["shapes"]:
+        solver.set_tuning(hit["tridiag_shape"])
+        return dict(hit, cached=True)
     res = solver.autotune(reps)
-    entry = {"tridiag_waves": res["tridiag_waves"],
+    entry = {"tridiag_shape": res["tridiag_shape"],
              "tridiag_ms": {str(k): v for k, v in res["tridiag_ms"].items()}}
     cache = _load(path)
     cache[key] = entry

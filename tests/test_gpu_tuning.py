@@ -13,6 +13,9 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 SVT_TOL = 5e-5
+# tridiagonalisation shape codes: rows on the vector units (8, 12, 16 waves),
+# register tiles on the matrix cores (112: 12 waves, 108: 8 waves)
+SHAPES = [8, 12, 16, 112, 108]
 
 
 def _lib():
@@ -33,19 +36,19 @@ def test_autotune_measures_every_shape_and_keeps_the_fastest():
     res = solver.autotune(reps=2)
     print("autotune", res, flush=True)
     ms = res["tridiag_ms"]
-    assert sorted(ms) == [8, 12, 16]
+    assert sorted(ms) == sorted(SHAPES)
     runnable = {w: t for w, t in ms.items() if t > 0}
     assert runnable, ms
-    assert res["tridiag_waves"] == min(runnable, key=runnable.get)
-    assert solver.get_tuning()["tridiag_waves"] == res["tridiag_waves"]
+    assert res["tridiag_shape"] == min(runnable, key=runnable.get)
+    assert solver.get_tuning()["tridiag_shape"] == res["tridiag_shape"]
     with pytest.raises(L.LrstvError):
         solver.set_tuning(10)
 
 
-@pytest.mark.parametrize("waves", [8, 12, 16])
-def test_every_shape_matches_the_oracle(waves):
+@pytest.mark.parametrize("shape", [(9, 130, 110), (5, 256, 256), (4, 40, 7)])
+@pytest.mark.parametrize("code", SHAPES)
+def test_every_shape_matches_the_oracle(code, shape):
     L = _lib()
-    shape = (9, 130, 110)
     b, h, w = shape
     _, noisy = synth.make_cube(synth.CubeSpec(h, w, b, 8, synth.NOISE_SMALL, 3))
     O = noisy.astype(np.float32)
@@ -53,7 +56,7 @@ def test_every_shape_matches_the_oracle(waves):
     mu = 0.8
     p = oracle.Params(tau=0.02, alpha=0.3, lam=10 / np.sqrt(h * w), w=(1.0, 1.0, 1.0), mu0=mu)
     solver = L.Solver([shape], L.Params(tau=p.tau, alpha=p.alpha, lam=p.lam, mu0=mu))
-    solver.set_tuning(waves)
+    solver.set_tuning(code)
     g = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda().reshape(-1) for k, v in st.items()}
     g["Y"] = torch.from_numpy(O).cuda().reshape(-1)
     g["mu"] = torch.tensor([mu], dtype=torch.float64, device="cuda")
@@ -64,7 +67,7 @@ def test_every_shape_matches_the_oracle(waves):
     ost = oracle.State(**{k: st[k].astype(np.float64) for k in ("Z", "S", "F", "E", "G1", "G2", "G3", "G4")}, mu=mu)
     new, _, _ = oracle.admm_step(O.astype(np.float64), ost, p)
     e = rel(got["E"].reshape(new.E.shape), new.E)
-    print(f"{waves} waves: E rel err {e:.2e}", flush=True)
+    print(f"shape code {code}, cube {shape}: E rel err {e:.2e}", flush=True)
     assert e < SVT_TOL
     assert rel(got["Z"].reshape(new.Z.shape), new.Z) < 1e-5
 
@@ -81,10 +84,10 @@ def test_cache_round_trip_and_graph_follows_the_shape(tmp_path):
     assert first["cached"] is False and os.path.exists(cache)
     s2 = L.Solver([noisy.shape], L.Params())
     second = L.autotune(s2, cache_path=cache)
-    assert second["cached"] is True and second["tridiag_waves"] == first["tridiag_waves"]
-    assert s2.get_tuning()["tridiag_waves"] == first["tridiag_waves"]
+    assert second["cached"] is True and second["tridiag_shape"] == first["tridiag_shape"]
+    assert s2.get_tuning()["tridiag_shape"] == first["tridiag_shape"]
     # graph captured with one shape, then the shape changes: replay equals eager
-    other = 8 if first["tridiag_waves"] != 8 else 16
+    other = 112 if first["tridiag_shape"] != 112 else 16
     s2.set_graph(True)
     s2.reset(Y)
     s2.iterate(2)
@@ -93,7 +96,7 @@ def test_cache_round_trip_and_graph_follows_the_shape(tmp_path):
     Xg = torch.empty_like(Y)
     s2.read_output(X=Xg)
     s3 = L.Solver([noisy.shape], L.Params())
-    s3.set_tuning(first["tridiag_waves"])
+    s3.set_tuning(first["tridiag_shape"])
     s3.reset(Y)
     s3.iterate(2)
     s3.set_tuning(other)
