@@ -145,9 +145,14 @@ struct lrstv_handle_s {
   bool graph_on = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  // second stream of the slice SVT (the slices beyond the last full round)
+  SvtSplit split;
   ~lrstv_handle_s() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
+    if (split.fork) (void)hipEventDestroy(split.fork);
+    if (split.join) (void)hipEventDestroy(split.join);
+    if (split.s2) (void)hipStreamDestroy(split.s2);
   }
 };
 
@@ -317,6 +322,16 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
     return fail(LRSTV_ERR_HIP, "copying the slice table: %s", hipGetErrorString(e));
   }
   prepare_svt(H->sl.max_n1);
+  H->split.first = svt_split_point((int)H->sl.desc.size());
+  if (H->split.first > 0) {
+    e = hipStreamCreateWithFlags(&H->split.s2, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&H->split.fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&H->split.join, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      delete H;
+      return fail(LRSTV_ERR_HIP, "creating the second stream: %s", hipGetErrorString(e));
+    }
+  }
   launch_set_mu(H->mu, par->mu0, H->stream);
   *out = H;
   return LRSTV_OK;
@@ -419,7 +434,7 @@ static void run_iteration(lrstv_handle_s* H, double* res_user) {
   sv.thresh = 0.f;
   sv.precision = H->par.precision;
   sv.tri_variant = H->tri_variant;
-  launch_svt(sv, s, &tm);
+  launch_svt(sv, s, &tm, &H->split);
   tm.begin(ST_BAND_IDFT);
   launch_band_idft_batch(H->bt[PH_PARTS], H->slices, H->E, H->total, H->F, H->G4, H->mu, H->part, s);
   tm.end(ST_BAND_IDFT);

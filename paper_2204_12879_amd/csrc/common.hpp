@@ -68,6 +68,49 @@ LRSTV_DEV float wave_sumf_dpp(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Double-precision wave sum by the same DPP pattern, both 32-bit halves
+// moved with the same control.
+template <int CTRL, int ROWMASK>
+LRSTV_DEV double dpp_moved_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, ROWMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+LRSTV_DEV double wave_sum_dpp(double v) {
+  v += dpp_moved_d<0xb1, 0xf>(v);
+  v += dpp_moved_d<0x4e, 0xf>(v);
+  v += dpp_moved_d<0x141, 0xf>(v);
+  v += dpp_moved_d<0x140, 0xf>(v);
+  v += dpp_moved_d<0x142, 0xa>(v);
+  v += dpp_moved_d<0x143, 0xc>(v);
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Values known to be equal in every lane, moved to scalar registers.
+LRSTV_DEV float uniform_f(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+LRSTV_DEV double uniform_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// An opaque copy: the compiler may not assume it equals v, so values derived
+// from it inside a loop are recomputed there instead of being kept live
+// across the loop.
+LRSTV_DEV int opaque_i(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// Block barrier for LDS traffic only: waits for this wave's LDS (and
+// scalar) operations, not for its global stores, which nothing in the block
+// reads back.  Every wave of the block must reach it.
+LRSTV_DEV void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // Block-wide sum in a fixed order (deterministic).  `scratch` holds
 // blockDim/64 doubles.  Every thread gets the result.
 LRSTV_DEV double block_sum(double v, double* scratch) {

@@ -607,17 +607,26 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_reg(const SliceDesc* __rest
 // (R, C) is G(32 R + rho(r, l / 32), 32 C + l % 32), rho(r, h) =
 // 8 (r / 4) + 4 h + r % 4.  Lower tiles (R >= C) only; the diagonal tiles
 // hold both triangles.  NW waves hold TPW tiles each, dealt column-major.
-// Per step i (v and w vanish at indices <= i, so nothing outside the
-// trailing block changes and no masking is needed):
-//   A  column i below the diagonal from the lanes holding it, its norm
-//   B  reflector (every thread), v into LDS, reflector column to the Gram
-//   C  p = A v: the column sums conj(a) v_row are lane-local (two halves
-//      combined), and give the whole product of a diagonal tile; the row
-//      sums a v_col of an off-diagonal tile go through an LDS transpose.
-//      Partial sums per wave, v^H A v from the lane-local pieces
-//   D  w = tau p - (tau^2 v^H A v / 2) v
-//   E  A -= v w^H + w v^H: per tile four v_mfma_f32_32x32x2f32 (real and
-//      imaginary parts as rank-4 real products).
+//
+// The product is formed with the raw column x (column i below the
+// diagonal) instead of the reflector v = scl x + gamma e_{i+1} (gamma =
+// 1 - scl x_{i+1}, real, in [1/2, 1]):
+//   A v = scl (A x) + gamma a,   a = column i+1 of the trailing matrix,
+//   v^H A v = |scl|^2 x^H A x + 2 gamma Re(conj(scl) x^H a) + gamma^2 a_{i+1},
+// and the next step's columns are formed from this step's, without waiting
+// for the update on the matrix cores: column c of the updated matrix is
+// a_c - v conj(w_c) - w conj(v_c).  Two barriers per step i:
+//   C  per tile the column sums conj(a) x_row are lane-local (halves
+//      combined) and give the whole product of a diagonal tile; the row sums
+//      a x_col of an off-diagonal tile go through an LDS transpose.  Partial
+//      sums per wave, x^H A x partials; column i+2 out of the tiles
+//   D  one index per thread of the first four waves: v, w = tau A v -
+//      (tau^2 v^H A v / 2) v, the reflector column to the Gram; the next x
+//      (column i+1 of the updated matrix), a (column i+2), diagonal, ||x||^2
+//      and x^H a partials
+//   E  A -= v w^H + w v^H on the matrix cores (per tile four
+//      v_mfma_f32_32x32x2f32: real and imaginary parts as rank-4 real
+//      products); meanwhile every thread forms the next reflector.
 LRSTV_DEV int mt_rho(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
 
 // tile t of the column-major enumeration of the lower tiles of an NT x NT grid
@@ -630,25 +639,88 @@ LRSTV_DEV void mt_tile(int t, int NT, int& R, int& C) {
   R = C + t;
 }
 
+// Column c of the register tiles (all rows of the tiles holding it) into
+// dst; with below, rows <= c within its block are written as zeros and the
+// diagonal goes to *dii.  The element rows are compared through rel, which
+// changes with c, so that no per-element row index stays live across the
+// step loop.
+template <int TPW>
+LRSTV_DEV void mt_column(const f32x16 (&tre)[TPW], const f32x16 (&tim)[TPW], const int (&tR)[TPW],
+                         const int (&tC)[TPW], int c, int li, int h, float2* dst, bool below, double* dii) {
+  const int cb = c >> 5, cl = c & 31;
+#pragma unroll
+  for (int s = 0; s < TPW; ++s) {
+    if (tC[s] != cb) continue;   // uniform
+    if (li == cl) {
+      const int rel = c - 32 * tR[s] - 4 * h;
+      float2* d = dst + 32 * tR[s] + 4 * h;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int cr = mt_rho(r, 0);
+        float2 a = make_float2(tre[s][r], tim[s][r]);
+        if (below && cr <= rel) {
+          if (cr == rel) *dii = (double)a.x;
+          a = make_float2(0.f, 0.f);
+        }
+        d[cr] = a;
+      }
+    }
+  }
+}
+
+// Reflector H x = beta e_1, v = [1; scl x], tau in [1, 2], from ||x||^2, x_0
+// (equal in every lane: kept in scalar registers).  The deflation tests in
+// FP64, the factors in FP32, the precision of the tiles they apply to.
+struct MtRefl {
+  float ax0, pr, pim, nx, tau, gam;
+  float2 scl;
+  bool refl, defl;
+};
+LRSTV_DEV MtRefl mt_reflector(double nx2, float2 x0) {
+  MtRefl f;
+  const double ax02 = (double)x0.x * x0.x + (double)x0.y * x0.y;
+  f.defl = nx2 <= kDeflate2;
+  f.refl = !f.defl && nx2 - ax02 > 1e-14 * nx2;
+  f.ax0 = uniform_f(sqrtf((float)ax02));
+  const float rax = f.ax0 > 0.f ? 1.f / f.ax0 : 0.f;
+  f.pr = uniform_f(f.ax0 > 0.f ? x0.x * rax : 1.f);
+  f.pim = uniform_f(f.ax0 > 0.f ? x0.y * rax : 0.f);
+  f.nx = 0.f;
+  f.tau = 0.f;
+  f.gam = 0.f;
+  f.scl = make_float2(0.f, 0.f);
+  if (f.refl) {
+    f.nx = uniform_f(sqrtf((float)nx2));
+    const float inv = 1.f / (f.ax0 + f.nx);
+    f.scl = make_float2(uniform_f(f.pr * inv), uniform_f(-f.pim * inv));
+    f.tau = uniform_f(1.f + f.ax0 / f.nx);
+    f.gam = uniform_f(f.nx * inv);
+  }
+  return f;
+}
+
 template <int NW, int TPW>
 __global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __restrict__ desc,
                                                          float2* __restrict__ gram, double* __restrict__ tri) {
-  constexpr int NMAX = 256;
+  constexpr int NMAX = 256, SCR = 16 * 68, NDW = NMAX / 64;   // waves of D, one index per thread
   static_assert(NW * TPW >= 36, "the 36 lower tiles of a 256 x 256 Gram");
-  __shared__ float2 xb[2][NMAX];
+  static_assert(NW >= NDW, "one index per thread in D");
+  // columns i, i+1 (by step parity) and i+2 of the current matrix
+  __shared__ float2 xb[2][NMAX], ab[2][NMAX], bb[NMAX];
   __shared__ float2 vb[NMAX], wb[NMAX];
-  __shared__ float2 P[NW][NMAX];              // per-wave partial sums of A v
+  __shared__ float2 P[NW][NMAX];               // per-wave partial sums of A x
   // per-wave transpose of the row products; entry (r, l) at r * 68 + l + l / 16,
   // which keeps both the row-wise writes and the chunk-wise reads conflict-free
-  __shared__ float2 scr[NW][16 * 68];
-  __shared__ double red_nx[2][NW], red_vav[NW];
+  __shared__ float2 scr[NW][SCR];
+  // per-wave partial sums (FP32 within a wave, summed over the waves in FP64)
+  __shared__ float red_nx[2][NW], red_xa[2][NW][2], red_xax[NW];
+  __shared__ double red_fro[NW];
   __shared__ double s_dii[2];
   const SliceDesc d = desc[blockIdx.x];
   const int n = d.n1;
   if (n <= 0) return;
   const int NT = (n + 31) >> 5, ntile = NT * (NT + 1) / 2;
   float2* gA = gram + d.g_off;
-  const int lane = threadIdx.x & 63, li = lane & 31, h = lane >> 5;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   double* dg = tri + d.t_off;
   double* eab = dg + n;
@@ -659,22 +731,25 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __res
   // ---- load the tiles ----------------------------------------------------
   f32x16 tre[TPW], tim[TPW];
   int tR[TPW], tC[TPW];
+  {
+    const int lane = threadIdx.x & 63, li = lane & 31, h = lane >> 5;
 #pragma unroll
-  for (int s = 0; s < TPW; ++s) {
-    const int t = wv + NW * s;
-    int R = -1, C = -1;
-    if (t < ntile) mt_tile(t, NT, R, C);
-    tR[s] = R;
-    tC[s] = C;
+    for (int s = 0; s < TPW; ++s) {
+      const int t = wv + NW * s;
+      int R = -1, C = -1;
+      if (t < ntile) mt_tile(t, NT, R, C);
+      tR[s] = R;
+      tC[s] = C;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      float2 a = zero;
-      if (R >= 0) {
-        const int row = 32 * R + mt_rho(r, h), col = 32 * C + li;
-        if (row < n && col < n) a = row >= col ? gA[packed(row, col)] : cconj(gA[packed(col, row)]);
+      for (int r = 0; r < 16; ++r) {
+        float2 a = zero;
+        if (R >= 0) {
+          const int row = 32 * R + mt_rho(r, h), col = 32 * C + li;
+          if (row < n && col < n) a = row >= col ? gA[packed(row, col)] : cconj(gA[packed(col, row)]);
+        }
+        tre[s][r] = a.x;
+        tim[s][r] = a.y;
       }
-      tre[s][r] = a.x;
-      tim[s][r] = a.y;
     }
   }
   // ---- exact power-of-two scaling to ||G||_F ~ 1 (as in k_tridiag_reg) ----
@@ -685,12 +760,12 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __res
 #pragma unroll
     for (int r = 0; r < 16; ++r) fro += wgt * ((double)tre[s][r] * tre[s][r] + (double)tim[s][r] * tim[s][r]);
   }
-  fro = warp_sum(fro);
-  if (lane == 0) red_vav[wv] = fro;
+  fro = wave_sum_dpp(fro);
+  if ((threadIdx.x & 63) == 0) red_fro[wv] = fro;
   __syncthreads();
   double fro2 = 0.0;
 #pragma unroll
-  for (int q = 0; q < NW; ++q) fro2 += red_vav[q];
+  for (int q = 0; q < NW; ++q) fro2 += red_fro[q];
   const int ex = fro2 > 0.0 ? ilogb(sqrt(fro2)) : 0;
   const float gsc = ldexpf(1.0f, -ex);
   const double unsc = ldexp(1.0, ex);
@@ -701,65 +776,195 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __res
       tre[s][r] *= gsc;
       tim[s][r] *= gsc;
     }
-  double ph_r = 1.0, ph_i = 0.0;
+  double ph_r = 1.0, ph_i = 0.0;   // running phase (thread 0)
   if (threadIdx.x == 0) { phr[0] = 1.0; phi[0] = 0.0; }
+  // columns 0 and 1; ||x||^2 and x^H a of step 0; its reflector
+  {
+    const int lane = threadIdx.x & 63, li = lane & 31, h = lane >> 5;
+    mt_column<TPW>(tre, tim, tR, tC, 0, li, h, xb[0], true, &s_dii[0]);
+    mt_column<TPW>(tre, tim, tR, tC, 1, li, h, ab[0], false, nullptr);
+  }
   __syncthreads();
-  for (int i = 0; i < n; ++i) {
-    const int cb = i >> 5, cl = i & 31;
-    float2* xc = xb[i & 1];
-    // ---- A: column i of the current matrix below the diagonal; A(i, i) ----
-    {
-      double nrm = 0.0;
+  {
+    const int t = threadIdx.x;
+    float nn = 0.f, xr = 0.f, xi = 0.f;
+    if (t < NMAX && t > 0 && t < n) {
+      const float2 x = xb[0][t], a1 = ab[0][t];
+      nn = x.x * x.x + x.y * x.y;
+      const float2 p = cmulc(x, a1);
+      xr = p.x;
+      xi = p.y;
+    }
+    nn = wave_sumf_dpp(nn);
+    xr = wave_sumf_dpp(xr);
+    xi = wave_sumf_dpp(xi);
+    if ((threadIdx.x & 63) == 0) {
+      red_nx[0][wv] = nn;
+      red_xa[0][wv][0] = xr;
+      red_xa[0][wv][1] = xi;
+    }
+  }
+  __syncthreads();
+  MtRefl f;
+  {
+    double nx2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < NDW; ++q) nx2 += red_nx[0][q];
+    f = mt_reflector(uniform_d(nx2), make_float2(uniform_f(xb[0][1].x), uniform_f(xb[0][1].y)));
+  }
+  for (int i = 0; i < n - 1; ++i) {
+    const int par = i & 1;
+    const float2* xv = xb[par];
+    const float2* av = ab[par];
+    // lane-derived indices are recomputed every step from this copy rather
+    // than kept live across the loop next to the tiles
+    const int lane = opaque_i(threadIdx.x & 63), li = lane & 31, h = lane >> 5;
+    const float tau = f.tau;
+    // ---- C: A x per wave, x^H A x ----------------------------------------
+    if (f.refl) {
+      for (int t = lane; t < NMAX; t += 64) P[wv][t] = zero;
+      float xaxd = 0.f, xaxo = 0.f;   // diagonal-tile and off-diagonal-tile parts
 #pragma unroll
       for (int s = 0; s < TPW; ++s) {
-        if (tC[s] == cb && li == cl) {
-          // element r sits at row 32 R + 4 h + mt_rho(r, 0); compared through
-          // rel, which changes every step, so that no per-element row index
-          // stays live across the loop.  Padding rows (>= n) hold zeros.
-          const int rel = i - 32 * tR[s] - 4 * h;
+        const int R = tR[s], C = tC[s];
+        if (R < 0 || 32 * C + 31 <= i) continue;   // no element in the trailing block
+        const float2 xC = xv[32 * C + li];
+        float2 cacc = zero;
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int c = mt_rho(r, 0);
-            const float2 a = make_float2(tre[s][r], tim[s][r]);
-            if (c > rel) {
-              xc[i + c - rel] = a;
-              nrm += (double)a.x * a.x + (double)a.y * a.y;
-            } else if (c == rel) {
-              s_dii[i & 1] = (double)a.x;
-            }
+        for (int r = 0; r < 16; ++r)
+          cacc = cadd(cacc, cmulc(make_float2(tre[s][r], tim[s][r]), xv[32 * R + mt_rho(r, h)]));
+        // Re(conj(x_col) (A^H x)_col); twice for an off-diagonal tile (its mirror)
+        if (R == C) xaxd += cacc.x * xC.x + cacc.y * xC.y;
+        else xaxo += cacc.x * xC.x + cacc.y * xC.y;
+        const float2 co = make_float2(__shfl_xor(cacc.x, 32, 64), __shfl_xor(cacc.y, 32, 64));
+        if (h == 0) {
+          const int col = 32 * C + li;
+          P[wv][col] = cadd(P[wv][col], cadd(cacc, co));
+        }
+        if (R != C) {
+          // row sums: scr(r, lane) = a x_col; lane j then sums chunk q = j & 3
+          // (16 columns of half q >> 1) of row j >> 2
+          const int wpos = lane + (lane >> 4);
+#pragma unroll
+          for (int r = 0; r < 16; ++r) scr[wv][r * 68 + wpos] = cmul(make_float2(tre[s][r], tim[s][r]), xC);
+          const int tr = lane >> 2, th = (lane >> 1) & 1, part = lane & 1;
+          const float2* src = &scr[wv][tr * 68 + 17 * (lane & 3)];
+          float2 sum = zero;
+#pragma unroll
+          for (int e = 0; e < 16; ++e) sum = cadd(sum, src[e]);
+          sum.x += __shfl_xor(sum.x, 1, 64);
+          sum.y += __shfl_xor(sum.y, 1, 64);
+          if (part == 0) {
+            const int row = 32 * R + mt_rho(tr, th);
+            P[wv][row] = cadd(P[wv][row], sum);
           }
         }
       }
-      nrm = warp_sum(nrm);
-      if (lane == 0) red_nx[i & 1][wv] = nrm;
+      const float sx = wave_sumf_dpp(xaxd + 2.f * xaxo);
+      if (lane == 0) red_xax[wv] = sx;
     }
-    __syncthreads();
-    if (i == n - 1) break;
-    // ---- B: reflector H x = beta e_1, v = [1; scl x], tau in [1, 2] -------
-    double nx2 = 0.0;
+    // column i+2 of the current matrix
+    if (i + 2 < n) mt_column<TPW>(tre, tim, tR, tC, i + 2, li, h, bb, false, nullptr);
+    lds_barrier();
+    // ---- D: v, w; the reflector column; the next x, a, diagonal ------------
+    // Without a reflection v and w are zero (selects, so that stale partial
+    // sums do not enter).
+    if (wv < NDW) {
+      const int t = threadIdx.x;
+      const int i1 = i + 1, i2 = i + 2 < n ? i + 2 : i + 1;
+      // Values equal for every index (the reduced scalars, the partial sums at
+      // i+1 and i+2) are summed across the wave, lane q holding wave q's
+      // part, and land in scalar registers.
+      double xAx = 0.0, xar = 0.0, xai = 0.0;
 #pragma unroll
-    for (int q = 0; q < NW; ++q) nx2 += red_nx[i & 1][q];
-    const double dii = s_dii[i & 1];
-    float2 x0 = xc[i + 1];
-    const double ax02 = (double)x0.x * x0.x + (double)x0.y * x0.y;
-    double taud = 0.0;
-    if (nx2 <= kDeflate2) x0 = zero;
-    float2 beta = x0, scl = zero;
-    if (nx2 > kDeflate2 && nx2 - ax02 > 1e-14 * nx2) {
-      const double nx = sqrt(nx2), ax0 = sqrt(ax02);
-      const double pr = ax0 > 0.0 ? x0.x / ax0 : 1.0, pim = ax0 > 0.0 ? x0.y / ax0 : 0.0;
-      beta = make_float2((float)(-pr * nx), (float)(-pim * nx));
-      const double inv = 1.0 / (ax0 + nx);
-      scl = make_float2((float)(pr * inv), (float)(-pim * inv));
-      taud = 1.0 + ax0 / nx;
+      for (int q = 0; q < NW; ++q) xAx += red_xax[q];
+#pragma unroll
+      for (int q = 0; q < NDW; ++q) {
+        xar += red_xa[par][q][0];
+        xai += red_xa[par][q][1];
+      }
+      const int ql = lane < NW ? lane : 0;
+      const bool qa = lane < NW;
+      const float2 p1 = qa ? P[ql][i1] : zero, p2 = qa ? P[ql][i2] : zero;
+      const float2 S1 = make_float2(wave_sumf_dpp(p1.x), wave_sumf_dpp(p1.y));
+      const float2 S2 = make_float2(wave_sumf_dpp(p2.x), wave_sumf_dpp(p2.y));
+      const float2 a1 = make_float2(uniform_f(av[i1].x), uniform_f(av[i1].y));
+      const float2 a2 = make_float2(uniform_f(av[i2].x), uniform_f(av[i2].y));
+      const float2 x2 = make_float2(uniform_f(xv[i2].x), uniform_f(xv[i2].y));
+      float2 St = zero;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) St = cadd(St, P[q][t]);
+      const float2 at = av[t], xt = xv[t], bt = bb[t];
+      const double sr = f.scl.x, si = f.scl.y;
+      const double gd = f.gam, td = f.tau;
+      const double vAv = (sr * sr + si * si) * xAx + 2.0 * gd * (sr * xar + si * xai) + gd * gd * (double)a1.x;
+      const float K = (float)(0.5 * td * td * vAv), g = f.gam;
+      // w_u = tau (scl S_u + gamma a_u) - K v_u
+      auto w_of = [&](float2 S, float2 au, float2 vu) {
+        const float2 pu = cadd(cmul(f.scl, S), make_float2(g * au.x, g * au.y));
+        return make_float2(tau * pu.x - K * vu.x, tau * pu.y - K * vu.y);
+      };
+      const bool in = f.refl && t > i && t < n;
+      const float2 v2 = (f.refl && i + 2 < n) ? cmul(f.scl, x2) : zero;
+      const float2 v = !in ? zero : t == i1 ? make_float2(1.f, 0.f) : cmul(f.scl, xt);
+      const float2 w1 = f.refl ? w_of(S1, a1, make_float2(1.f, 0.f)) : zero;
+      const float2 w2 = (f.refl && i + 2 < n) ? w_of(S2, a2, v2) : zero;
+      const float2 w = in ? w_of(St, at, v) : zero;
+      // updated columns i+1 and i+2: a_c - v conj(w_c) - w conj(v_c)
+      const bool nxt = t > i1 && t < n;
+      const float2 xn = !nxt ? zero : make_float2(at.x - (v.x * w1.x + v.y * w1.y) - w.x, at.y - (v.y * w1.x - v.x * w1.y) - w.y);
+      const float2 an = !nxt ? zero : make_float2(bt.x - (v.x * w2.x + v.y * w2.y) - (w.x * v2.x + w.y * v2.y),
+                                                  bt.y - (v.y * w2.x - v.x * w2.y) - (w.y * v2.x - w.x * v2.y));
+      float nn = 0.f, xr = 0.f, xi = 0.f;
+      if (nxt) {
+        nn = xn.x * xn.x + xn.y * xn.y;
+        const float2 pxa = cmulc(xn, an);
+        xr = pxa.x;
+        xi = pxa.y;
+      }
+      vb[t] = v;
+      wb[t] = w;
+      xb[par ^ 1][t] = xn;
+      ab[par ^ 1][t] = an;
+      if (t == i1) s_dii[par ^ 1] = (double)a1.x - 2.0 * (double)w1.x;
+      if (t > i && t < n) gA[packed(t, i)] = v;   // reflector column (zeros without a reflection)
+      nn = wave_sumf_dpp(nn);
+      xr = wave_sumf_dpp(xr);
+      xi = wave_sumf_dpp(xi);
+      if (lane == 0) {
+        red_nx[par ^ 1][wv] = nn;
+        red_xa[par ^ 1][wv][0] = xr;
+        red_xa[par ^ 1][wv][1] = xi;
+      }
     }
+    lds_barrier();
+    // ---- E: A -= v w^H + w v^H on the matrix cores ------------------------
+    // real part: [-v_R | -w_R] (re in half 0, im in half 1) times [w_C ; v_C];
+    // imaginary part: [-Im v, Re v] and [-Im w, Re w] against the same B.
+    if (f.refl) {
+#pragma unroll
+      for (int s = 0; s < TPW; ++s) {
+        const int R = tR[s], C = tC[s];
+        if (R < 0 || 32 * C + 31 <= i) continue;
+        const float2 vR = vb[32 * R + li], wR = wb[32 * R + li];
+        const float2 vC = vb[32 * C + li], wC = wb[32 * C + li];
+        const float b0 = h ? wC.y : wC.x, b1 = h ? vC.y : vC.x;
+        const float ar0 = h ? -vR.y : -vR.x, ar1 = h ? -wR.y : -wR.x;
+        const float ai0 = h ? vR.x : -vR.y, ai1 = h ? wR.x : -wR.y;
+        tre[s] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar0, b0, tre[s], 0, 0, 0);
+        tre[s] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar1, b1, tre[s], 0, 0, 0);
+        tim[s] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai0, b0, tim[s], 0, 0, 0);
+        tim[s] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai1, b1, tim[s], 0, 0, 0);
+      }
+    }
+    // outputs of step i; beta = -phase ||x|| (reflection), x_0 (column already
+    // reduced) or 0 (deflated)
     if (threadIdx.x == 0) {
-      dg[i] = dii * unsc;
-      taus[i] = taud;
-      const double br = beta.x, bi = beta.y, ab = sqrt(br * br + bi * bi);
-      eab[i] = ab * unsc;
-      if (ab > 0.0) {
-        const double ur = br / ab, uq = bi / ab;
+      dg[i] = s_dii[par] * unsc;
+      taus[i] = f.tau;
+      eab[i] = (double)(f.refl ? f.nx : f.defl ? 0.f : f.ax0) * unsc;
+      if (!f.defl) {
+        const double ur = f.refl ? -f.pr : f.pr, uq = f.refl ? -f.pim : f.pim;
         const double nr = ph_r * ur - ph_i * uq, ni = ph_r * uq + ph_i * ur;
         ph_r = nr;
         ph_i = ni;
@@ -767,93 +972,12 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __res
       phr[i + 1] = ph_r;
       phi[i + 1] = ph_i;
     }
-    const float tau = (float)taud;
-    const bool refl = tau != 0.f;
-    for (int t = threadIdx.x; t < NMAX; t += 64 * NW) {
-      float2 v = zero;
-      if (refl && t > i && t < n) v = (t == i + 1) ? make_float2(1.f, 0.f) : cmul(scl, xc[t]);
-      vb[t] = v;
-      if (t > i && t < n) gA[packed(t, i)] = v;   // reflector column (zeros without a reflection)
-    }
-    __syncthreads();
-    if (!refl) continue;
-    // ---- C: p = A v (per-wave partial sums) and v^H A v --------------------
-    for (int t = lane; t < NMAX; t += 64) P[wv][t] = zero;
-    float vavl = 0.f;
+    // the next reflector, while the update runs
+    if (i + 2 < n) {
+      double nx2 = 0.0;
 #pragma unroll
-    for (int s = 0; s < TPW; ++s) {
-      const int R = tR[s], C = tC[s];
-      if (R < 0 || 32 * C + 31 <= i) continue;   // no element in the trailing block
-      const float2 vC = vb[32 * C + li];
-      float2 cacc = zero;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) cacc = cadd(cacc, cmulc(make_float2(tre[s][r], tim[s][r]), vb[32 * R + mt_rho(r, h)]));
-      // Re(conj(v_col) (A^H v)_col); twice for an off-diagonal tile (its mirror)
-      vavl += (R == C ? 1.f : 2.f) * (cacc.x * vC.x + cacc.y * vC.y);
-      const float2 co = make_float2(__shfl_xor(cacc.x, 32, 64), __shfl_xor(cacc.y, 32, 64));
-      if (h == 0) {
-        const int col = 32 * C + li;
-        P[wv][col] = cadd(P[wv][col], cadd(cacc, co));
-      }
-      if (R != C) {
-        // row sums: scr(r, lane) = a v_col; lane j then sums chunk q = j & 3
-        // (16 columns of half q >> 1) of row j >> 2
-        const int wpos = lane + (lane >> 4);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) scr[wv][r * 68 + wpos] = cmul(make_float2(tre[s][r], tim[s][r]), vC);
-        const int tr = lane >> 2, th = (lane >> 1) & 1, part = lane & 1;
-        const float2* src = &scr[wv][tr * 68 + 17 * (lane & 3)];
-        float2 sum = zero;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) sum = cadd(sum, src[e]);
-        sum.x += __shfl_xor(sum.x, 1, 64);
-        sum.y += __shfl_xor(sum.y, 1, 64);
-        if (part == 0) {
-          const int row = 32 * R + mt_rho(tr, th);
-          P[wv][row] = cadd(P[wv][row], sum);
-        }
-      }
-    }
-    {
-      const double vav = warp_sum((double)vavl);
-      if (lane == 0) red_vav[wv] = vav;
-    }
-    __syncthreads();
-    // ---- D: w = tau p - K v ------------------------------------------------
-    {
-      double vAv = 0.0;
-#pragma unroll
-      for (int q = 0; q < NW; ++q) vAv += red_vav[q];
-      const float K = (float)(0.5 * taud * taud * vAv);
-      for (int t = threadIdx.x; t < NMAX; t += 64 * NW) {
-        float2 w = zero;
-        if (t > i && t < n) {
-          float2 pt = zero;
-#pragma unroll
-          for (int q = 0; q < NW; ++q) pt = cadd(pt, P[q][t]);
-          const float2 vt = vb[t];
-          w = make_float2(tau * pt.x - K * vt.x, tau * pt.y - K * vt.y);
-        }
-        wb[t] = w;
-      }
-    }
-    __syncthreads();
-    // ---- E: A -= v w^H + w v^H on the matrix cores -------------------------
-    // real part: [-v_R | -w_R] (re in half 0, im in half 1) times [w_C ; v_C];
-    // imaginary part: [-Im v, Re v] and [-Im w, Re w] against the same B.
-#pragma unroll
-    for (int s = 0; s < TPW; ++s) {
-      const int R = tR[s], C = tC[s];
-      if (R < 0 || 32 * C + 31 <= i) continue;
-      const float2 vR = vb[32 * R + li], wR = wb[32 * R + li];
-      const float2 vC = vb[32 * C + li], wC = wb[32 * C + li];
-      const float b0 = h ? wC.y : wC.x, b1 = h ? vC.y : vC.x;
-      const float ar0 = h ? -vR.y : -vR.x, ar1 = h ? -wR.y : -wR.x;
-      const float ai0 = h ? vR.x : -vR.y, ai1 = h ? wR.x : -wR.y;
-      tre[s] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar0, b0, tre[s], 0, 0, 0);
-      tre[s] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar1, b1, tre[s], 0, 0, 0);
-      tim[s] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai0, b0, tim[s], 0, 0, 0);
-      tim[s] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai1, b1, tim[s], 0, 0, 0);
+      for (int q = 0; q < NDW; ++q) nx2 += red_nx[par ^ 1][q];
+      f = mt_reflector(uniform_d(nx2), make_float2(uniform_f(xb[par ^ 1][i + 2].x), uniform_f(xb[par ^ 1][i + 2].y)));
     }
   }
   if (threadIdx.x == 0) {
@@ -1661,9 +1785,10 @@ static size_t tridiag_reg_lds(int n, int v) {
   const int RL = n > NW * JR ? n - NW * JR : 0;
   return ((size_t)RL * (RL + 1) / 2 + (size_t)(3 + NW) * n) * sizeof(float2);
 }
-// Static LDS of k_tridiag_mfma<NW, TPW>: two columns, v, w, NW partial rows
-// (256 complex each) and NW transposes of 16 x 68 complex.
-static size_t tridiag_mfma_lds(int nw) { return (size_t)(4 + nw) * 256 * sizeof(float2) + (size_t)nw * 16 * 68 * sizeof(float2) + 1024; }
+// Static LDS of k_tridiag_mfma<NW, TPW>: seven columns (x and a per step
+// parity, the column after them, v, w) and NW partial rows (256 complex
+// each), NW transposes of 16 x 68 complex.
+static size_t tridiag_mfma_lds(int nw) { return (size_t)(7 + nw) * 256 * sizeof(float2) + (size_t)nw * 16 * 68 * sizeof(float2) + 1024; }
 
 static const void* tri_kernel(int v) {
   switch (v) {
@@ -1739,22 +1864,11 @@ static size_t tridiag_onchip_bytes(int n) {
   return ((size_t)n * (n + 1) / 2 + 2 * (size_t)n + 4 * (size_t)n) * sizeof(float2);
 }
 
-void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm) {
-  StageTimer dummy;
-  StageTimer& T = tm ? *tm : dummy;
+// Every stage after the tridiagonalisation, on one stream.
+static void svt_after_tridiag(const SvtLaunch& L, hipStream_t s, StageTimer& T) {
   const int ns = L.n_slices, n = L.max_n1, m = L.max_m1;
-  if (ns == 0) return;
   const bool bf = L.precision == LRSTV_SPLIT_BF16;
-  const int TT = (n + kMT - 1) / kMT, TM = (m + kMT - 1) / kMT;
-  T.begin(ST_GRAM);
-  if (bf)
-    hipLaunchKernelGGL(k_gram<kBF16x3>, dim3(TT * (TT + 1) / 2, ns), dim3(256), 0, s, L.desc, L.slices, L.gram);
-  else
-    hipLaunchKernelGGL(k_gram<kF32>, dim3(TT * (TT + 1) / 2, ns), dim3(256), 0, s, L.desc, L.slices, L.gram);
-  T.end(ST_GRAM);
-  T.begin(ST_TRIDIAG);
-  launch_tridiag(L, s);
-  T.end(ST_TRIDIAG);
+  const int TM = (m + kMT - 1) / kMT;
   const size_t eig_lds = (size_t)5 * n * sizeof(double) + (size_t)(n + 1 + 1024) * sizeof(int);
   T.begin(ST_TRIEIG);
   hipLaunchKernelGGL(k_trieig<0>, dim3(ns), dim3(1024), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount, L.mu,
@@ -1785,6 +1899,51 @@ void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm) {
     hipLaunchKernelGGL(k_bp2<kF32>, dim3(TM, TM, ns), dim3(256), 0, s, L.desc, L.slices, L.V, L.B, L.fval,
                        L.rcount);
   T.end(ST_BP2);
+}
+
+int svt_split_point(int n_slices) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    return 0;
+  if (n_slices <= cus || n_slices % cus == 0) return 0;
+  return n_slices - n_slices % cus;
+}
+
+void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm, const SvtSplit* sp) {
+  StageTimer dummy;
+  StageTimer& T = tm ? *tm : dummy;
+  const int ns = L.n_slices, n = L.max_n1;
+  if (ns == 0) return;
+  const bool bf = L.precision == LRSTV_SPLIT_BF16;
+  const int TT = (n + kMT - 1) / kMT;
+  T.begin(ST_GRAM);
+  if (bf)
+    hipLaunchKernelGGL(k_gram<kBF16x3>, dim3(TT * (TT + 1) / 2, ns), dim3(256), 0, s, L.desc, L.slices, L.gram);
+  else
+    hipLaunchKernelGGL(k_gram<kF32>, dim3(TT * (TT + 1) / 2, ns), dim3(256), 0, s, L.desc, L.slices, L.gram);
+  T.end(ST_GRAM);
+  // per-stage timing keeps one stream (every stage times all the slices)
+  if (sp && sp->s2 && sp->first > 0 && sp->first < ns && !T.on) {
+    SvtLaunch A = L, B = L;
+    A.n_slices = sp->first;
+    B.desc = L.desc + sp->first;
+    B.rcount = L.rcount + sp->first;
+    B.n_slices = ns - sp->first;
+    launch_tridiag(A, s);
+    (void)hipEventRecord(sp->fork, s);
+    (void)hipStreamWaitEvent(sp->s2, sp->fork, 0);
+    svt_after_tridiag(A, s, T);
+    launch_tridiag(B, sp->s2);
+    svt_after_tridiag(B, sp->s2, T);
+    (void)hipEventRecord(sp->join, sp->s2);
+    (void)hipStreamWaitEvent(s, sp->join, 0);
+    return;
+  }
+  T.begin(ST_TRIDIAG);
+  launch_tridiag(L, s);
+  T.end(ST_TRIDIAG);
+  svt_after_tridiag(L, s, T);
 }
 
 

@@ -141,7 +141,19 @@ struct SvtLaunch {
   int precision;
   int tri_variant = kTriDefault;  // tridiagonalisation shape (autotuned)
 };
-void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm = nullptr);
+// Slices beyond the last full round of the one-block-per-slice kernels run
+// on a second stream from the tridiagonalisation on, after the first group's
+// tridiagonalisation, so that they overlap the first group's later stages
+// instead of occupying a few compute units while the rest wait.
+struct SvtSplit {
+  hipStream_t s2 = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  int first = 0;   // slices [0, first) on the main stream, the rest on s2; 0: no split
+};
+// The first group's size for n_slices slices (0: no split), from the
+// device's compute-unit count.
+int svt_split_point(int n_slices);
+void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm = nullptr, const SvtSplit* sp = nullptr);
 // Single stages of launch_svt (the autotuner times them in isolation).
 void launch_svt_gram(const SvtLaunch& L, hipStream_t s);
 void launch_svt_tridiag(const SvtLaunch& L, hipStream_t s);
