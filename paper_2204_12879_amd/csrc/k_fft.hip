@@ -434,13 +434,17 @@ __global__ void __launch_bounds__(256) k_band_dft(const float* __restrict__ A, i
 // c_k = 1 for k = 0 and k = b/2, else 2 (slice k stands for k and b - k).
 // Epilogue (optional): Gamma4 += mu (E - F) and FP64 partial sums of
 // (E - F)^2, one fixed slot per block (grid = LRSTV_PARTS when part != NULL).
+// kIdftGroups groups of 256 threads per block work on consecutive tiles, so
+// that the fixed grid keeps enough loads in flight.
+constexpr int kIdftGroups = 4;
 LRSTV_DEV void band_idft_body(int bid, int nblk, const float* __restrict__ X, int n_t, float* __restrict__ E,
                                                    int64_t e_stride, int hw, int b,
                                                    const float* __restrict__ F, float* __restrict__ G4,
                                                    const double* __restrict__ mu_dev, double* __restrict__ part) {
-  __shared__ MfmaSmemR sm;
+  constexpr int G = kIdftGroups;
+  __shared__ MfmaSmemR sm[G];
   __shared__ float ct[LRSTV_MAX_SIDE_DEV], st[LRSTV_MAX_SIDE_DEV];
-  __shared__ double red[8];
+  __shared__ double red[4 * G];
   const float ib = 1.0f / (float)b;
   for (int m = threadIdx.x; m < b; m += blockDim.x) {
     double sv, cv;
@@ -453,21 +457,23 @@ LRSTV_DEV void band_idft_body(int bid, int nblk, const float* __restrict__ X, in
   const int K2 = 2 * (b / 2 + 1);
   const int TM = (b + kMT - 1) / kMT, TN = (hw + kMT - 1) / kMT;
   const int ntiles = n_t * TM * TN;
-  const int wv = threadIdx.x >> 6;
-  double acc = 0.0;
-  for (int tile = bid; tile < ntiles; tile += nblk) {
-    const int t = tile / (TM * TN), rem = tile - t * TM * TN;
+  const int grp = threadIdx.x >> 8, t = threadIdx.x & 255, wv = t >> 6;
+  float acc = 0.f;   // per-thread partial of (E - F)^2 (FP64 from the block sum on)
+  for (int base = bid * G; base < ntiles; base += nblk * G) {   // same trip count in every group
+    const int tile = base + grp < ntiles ? base + grp : ntiles - 1;
+    const bool tv = base + grp < ntiles;
+    const int tt = tile / (TM * TN), rem = tile - tt * TM * TN;
     const int tn = rem / TM, tm = rem - tn * TM;
     const int m0 = tm * kMT, n0 = tn * kMT;
-    const float* src = X + (int64_t)t * K2 * hw;
-    float* dst = E + t * e_stride;
-    const float* Ft = F ? F + t * e_stride : nullptr;
-    float* G4t = G4 ? G4 + t * e_stride : nullptr;
-    const bool active = m0 + 32 * (wv >> 1) < b && n0 + 32 * (wv & 1) < hw;
+    const float* src = X + (int64_t)tt * K2 * hw;
+    float* dst = E + tt * e_stride;
+    const float* Ft = F ? F + tt * e_stride : nullptr;
+    float* G4t = G4 ? G4 + tt * e_stride : nullptr;
+    const bool active = tv && m0 + 32 * (wv >> 1) < b && n0 + 32 * (wv & 1) < hw;
     auto fa = [&](int j, int kk0, float* v) {
       // kk0 is a multiple of 8: four slices k = kk0/2 .. kk0/2 + 3, re and im each
       const int k0 = kk0 >> 1;
-      int idx = (int)(((int64_t)j * k0) % b);
+      int idx = (j * k0) % b;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int k = k0 + q;
@@ -490,23 +496,25 @@ LRSTV_DEV void band_idft_body(int bid, int nblk, const float* __restrict__ X, in
         if (G4t) {
           const float f = Ft[q];
           G4t[q] = G4t[q] + mu * (e - f);
-          const double d = (double)e - (double)f;
+          const float d = e - f;
           acc += d * d;
         }
       }
     };
-    mfma_rtile<true, false>(m0, n0, K2, fa, fb, sto, sm, active);
+    mfma_rtile_t<true, false>(t, m0, n0, K2, fa, fb, sto, sm[grp], active);
   }
   if (part) {
-    acc = block_sum(acc, red);
-    if (threadIdx.x == 0) part[R_FRO_EF * LRSTV_PARTS + bid] = acc;
+    const double tot = block_sum((double)acc, red);
+    if (threadIdx.x == 0) part[R_FRO_EF * LRSTV_PARTS + bid] = tot;
   }
 }
 
-__global__ void __launch_bounds__(256) k_band_idft(const float* __restrict__ X, int n_t, float* __restrict__ E,
-                                                   int64_t e_stride, int hw, int b,
-                                                   const float* __restrict__ F, float* __restrict__ G4,
-                                                   const double* __restrict__ mu_dev, double* __restrict__ part) {
+__global__ void __launch_bounds__(256 * kIdftGroups) k_band_idft(const float* __restrict__ X, int n_t,
+                                                                 float* __restrict__ E, int64_t e_stride, int hw,
+                                                                 int b, const float* __restrict__ F,
+                                                                 float* __restrict__ G4,
+                                                                 const double* __restrict__ mu_dev,
+                                                                 double* __restrict__ part) {
   band_idft_body(blockIdx.x, gridDim.x, X, n_t, E, e_stride, hw, b, F, G4, mu_dev, part);
 }
 
@@ -568,7 +576,7 @@ __global__ void __launch_bounds__(256) k_band_dft_batch(BatchTab bt, const float
   band_dft_body(q.bid, q.nblk, A + g.off, a_stride, 3, slices + g.slice_base, g.h * g.w, g.b);
 }
 
-__global__ void __launch_bounds__(256) k_band_idft_batch(BatchTab bt, const float* __restrict__ slices,
+__global__ void __launch_bounds__(256 * kIdftGroups) k_band_idft_batch(BatchTab bt, const float* __restrict__ slices,
                                                          float* __restrict__ E, int64_t e_stride,
                                                          const float* __restrict__ F, float* __restrict__ G4,
                                                          const double* __restrict__ mu_dev, double* __restrict__ part) {
@@ -638,8 +646,10 @@ void launch_band_idft(const float* slices, int n_t, float* E, int64_t e_stride, 
                       const float* F, float* G4, const double* mu, double* part, hipStream_t s) {
   const int hw = h * w;
   const int64_t ntiles = (int64_t)n_t * ((b + kMT - 1) / kMT) * ((hw + kMT - 1) / kMT);
-  const int grid = part ? LRSTV_PARTS : (int)(ntiles < 2048 ? ntiles : 2048);
-  hipLaunchKernelGGL(k_band_idft, dim3(grid), dim3(256), 0, s, slices, n_t, E, e_stride, hw, b, F, G4, mu, part);
+  const int64_t ng = (ntiles + kIdftGroups - 1) / kIdftGroups;
+  const int grid = part ? LRSTV_PARTS : (int)(ng < 2048 ? ng : 2048);
+  hipLaunchKernelGGL(k_band_idft, dim3(grid), dim3(256 * kIdftGroups), 0, s, slices, n_t, E, e_stride, hw, b, F, G4,
+                     mu, part);
 }
 
 // ---------------------------------------------------- batched launchers ---
@@ -695,8 +705,8 @@ void launch_band_dft_batch(const BatchTab& bt, const float* A, int64_t a_stride,
 
 void launch_band_idft_batch(const BatchTab& bt, const float* slices, float* E, int64_t e_stride, const float* F,
                             float* G4, const double* mu, double* part, hipStream_t s) {
-  hipLaunchKernelGGL(k_band_idft_batch, dim3(bt.nc * LRSTV_PARTS), dim3(256), 0, s, bt, slices, E, e_stride, F, G4,
-                     mu, part);
+  hipLaunchKernelGGL(k_band_idft_batch, dim3(bt.nc * LRSTV_PARTS), dim3(256 * kIdftGroups), 0, s, bt, slices, E,
+                     e_stride, F, G4, mu, part);
 }
 
 }  // namespace lrstv

@@ -1029,7 +1029,7 @@ LRSTV_DEV int sturm_count_fast(const double* dg, const double* e2, int n, double
 }
 
 // One block (1024 threads) per slice.  Eigenvalues above (t^2 - delta) of
-// T / ||T|| by 5-section (4 threads per eigenvalue), eigenvectors by twisted
+// T / ||T|| by bisection (one thread per eigenvalue), eigenvectors by twisted
 // factorisation inside their unreduced block, Gram-Schmidt inside clusters;
 // output column c = eigenvector of the c-th largest kept eigenvalue times the
 // phase (V re/im planes).
@@ -1113,21 +1113,17 @@ __global__ void __launch_bounds__(1024) k_trieig(const SliceDesc* __restrict__ d
     for (int k = c0 + threadIdx.x; k < n; k += blockDim.x) lam[k] = lam_g[k];
   }
   // Shared first step: the counts at G = blockDim points spread over
-  // [lo0, gu] bracket every eigenvalue in one grid cell.  Then 5-section:
-  // the 4 threads of a group probe 4 interior points of the cell, until it is
-  // below max(eps_64 |lambda|, 1e-13 ||T||) (the FP32 Gram resolves its
-  // eigenvalues to ~1e-7 ||T||; clusters are gaps below 1e-10 ||T||).
+  // [lo0, gu] bracket every eigenvalue in one grid cell.  Then bisection, one
+  // thread per eigenvalue (the count is issue-bound, and bisection needs the
+  // fewest counts per bit), until the cell is below max(eps_64 |lambda|,
+  // 1e-13 ||T||) (the FP32 Gram resolves its eigenvalues to ~1e-7 ||T||;
+  // clusters are gaps below 1e-10 ||T||).
   if (PHASE == 0) {
     const int G = blockDim.x;
     const double lo0 = fmax(gl, lo_cut), cell = (gu - lo0) / G;
     if (r > 0) gcnt[threadIdx.x] = sturm_count_fast(dg, e2, n, lo0 + (threadIdx.x + 1) * cell, pivmin);
     __syncthreads();
-    const int lane = threadIdx.x & 63, q = lane & 3, base = lane & ~3;
-    const int ngrp = blockDim.x >> 2;
-    const int nround = (r + ngrp - 1) / ngrp;
-    for (int rd = 0; rd < nround; ++rd) {
-      const int kk = (threadIdx.x >> 2) + rd * ngrp;
-      const bool act = kk < r;
+    for (int kk = threadIdx.x; kk < r; kk += blockDim.x) {
       const int k = c0 + kk;
       // first grid point whose count exceeds k: lambda_k in [x_{j-1}, x_j)
       int jl = 0, jh = G;
@@ -1138,25 +1134,15 @@ __global__ void __launch_bounds__(1024) k_trieig(const SliceDesc* __restrict__ d
       }
       double lo = lo0 + jl * cell, hi = lo0 + (jl + 1) * cell;
       for (int it = 0; it < 64; ++it) {
-        const double wdt = hi - lo;
-        const bool done = !act || wdt <= fmax(2.2e-16 * fmax(fabs(lo), fabs(hi)), 1e-13 * tnorm);
+        const bool done = hi - lo <= fmax(2.2e-16 * fmax(fabs(lo), fabs(hi)), 1e-13 * tnorm);
         if (__all(done)) break;
-        const double step = wdt * 0.2;
-        const double x = lo + (q + 1) * step;
-        const int cnt = done ? 0 : sturm_count_fast(dg, e2, n, x, pivmin);
-        const int c_0 = __shfl(cnt, base + 0, 64), c_1 = __shfl(cnt, base + 1, 64);
-        const int c_2 = __shfl(cnt, base + 2, 64), c_3 = __shfl(cnt, base + 3, 64);
         if (!done) {
-          // eigenvalue k lies where the count first exceeds k
-          const double x0 = lo + step, x1 = lo + 2 * step, x2 = lo + 3 * step, x3 = lo + 4 * step;
-          if (c_0 > k) { hi = x0; }
-          else if (c_1 > k) { lo = x0; hi = x1; }
-          else if (c_2 > k) { lo = x1; hi = x2; }
-          else if (c_3 > k) { lo = x2; hi = x3; }
-          else { lo = x3; }
+          const double x = 0.5 * (lo + hi);
+          if (sturm_count_fast(dg, e2, n, x, pivmin) > k) hi = x;
+          else lo = x;
         }
       }
-      if (act && q == 0) lam_g[k] = 0.5 * (lo + hi);
+      lam_g[k] = 0.5 * (lo + hi);
     }
     return;
   }
@@ -1344,25 +1330,58 @@ __global__ void __launch_bounds__(256) k_wy_t(const SliceDesc* __restrict__ desc
   auto st = [&](int p, int q, float2 v) { S[p][q] = v; };
   mfma_ctile<kF32, false, false>(0, 0, m, fa, fb, st, sm, true);
   __syncthreads();
-  float2(*T)[64] = reinterpret_cast<float2(*)[64]>(&sm);
-  for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) T[e >> 6][e & 63] = make_float2(0.f, 0.f);
+  // T from its inverse: for reflectors I - tau_j y_j y_j^H, T^-1 =
+  // diag(1 / tau) + (strict upper part of Y^H Y) (the compact-WY identity of
+  // Puglisi, and of Joffrain, Low, Quintana-Orti, van de Geijn and van Zee).
+  // The upper triangular inverse by doubling: with the inverses of two
+  // adjacent diagonal blocks A and C of size s known, the block between them
+  // is -A B C (B the block of the inverse's argument), six levels of small
+  // products instead of a 64-step sequential recurrence.  A reflector with
+  // tau = 0 (or past the block's last) has a zero column in Y: its diagonal
+  // entry is 1 during the inversion (its off-diagonal entries are zero) and
+  // 0 in the result.
+  float2(*U)[64] = S;                                             // argument; its lower half holds B C
+  float2(*T)[65] = reinterpret_cast<float2(*)[65]>(&sm);          // result, rows padded to 65
+  static_assert(sizeof(MfmaSmem) >= 64 * 65 * sizeof(float2), "T factor scratch");
+  for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+    const int p = e >> 6, q = e & 63;
+    const float tp = p < nbk ? (float)taus[i0 + p] : 0.f;
+    if (p == q) {
+      U[p][p] = make_float2(tp != 0.f ? 1.f / tp : 1.f, 0.f);
+      T[p][p] = make_float2(tp != 0.f ? tp : 1.f, 0.f);
+    } else {
+      T[p][q] = make_float2(0.f, 0.f);
+    }
+  }
   __syncthreads();
-  for (int j = 0; j < nbk; ++j) {
-    const float tj = (float)taus[i0 + j];
-    const int p = threadIdx.x;
-    if (p < j) {
+  for (int s2 = 1; s2 < 64; s2 <<= 1) {
+    const int E = 32 * s2;   // (32 / s2) block pairs of s2 x s2 entries
+    // M = B C into the (free) mirrored lower block of U, stored transposed
+    for (int e = threadIdx.x; e < E; e += blockDim.x) {
+      const int pr = e / (s2 * s2), rem = e - pr * s2 * s2, r = rem / s2, c = rem - r * s2;
+      const int b0 = 2 * s2 * pr, b1 = b0 + s2;
       float2 acc = make_float2(0.f, 0.f);
-      for (int q = p; q < j; ++q) acc = cadd(acc, cmul(T[p][q], S[q][j]));
-      T[p][j] = make_float2(-tj * acc.x, -tj * acc.y);
-    } else if (p == j) {
-      T[j][j] = make_float2(tj, 0.f);
+      for (int k = 0; k <= c; ++k) acc = cadd(acc, cmul(U[b0 + r][b1 + k], T[b1 + k][b1 + c]));
+      U[b1 + c][b0 + r] = acc;
+    }
+    __syncthreads();
+    // X = -A M into the upper block of T
+    for (int e = threadIdx.x; e < E; e += blockDim.x) {
+      const int pr = e / (s2 * s2), rem = e - pr * s2 * s2, r = rem / s2, c = rem - r * s2;
+      const int b0 = 2 * s2 * pr, b1 = b0 + s2;
+      float2 acc = make_float2(0.f, 0.f);
+      for (int k = r; k < s2; ++k) acc = cadd(acc, cmul(T[b0 + r][b0 + k], U[b1 + c][b0 + k]));
+      T[b0 + r][b1 + c] = make_float2(-acc.x, -acc.y);
     }
     __syncthreads();
   }
   float* out = Twy + d.y_off + (int64_t)b * 64 * 64 * 2;
   for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
-    out[e] = T[e >> 6][e & 63].x;
-    out[64 * 64 + e] = T[e >> 6][e & 63].y;
+    const int p = e >> 6, q = e & 63;
+    float2 t = T[p][q];
+    if (p == q && !(p < nbk && taus[i0 + p] != 0.0)) t = make_float2(0.f, 0.f);
+    out[e] = t.x;
+    out[64 * 64 + e] = t.y;
   }
 }
 

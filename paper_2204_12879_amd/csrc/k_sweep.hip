@@ -107,11 +107,15 @@ LRSTV_DEV void grad_shrink_body(
   const float mu = (float)mud, imu = (float)(1.0 / mud);
   const float tmu = (float)(tau / mud), lmu = (float)(lam / mud);
   const float wn[3] = {w1, w2, w3};
-  double m_ols = 0, m_lz = 0, s_ols = 0, s_lz = 0, s_dzf = 0;
-  for (int64_t q = bid * (int64_t)blockDim.x + threadIdx.x; q < N; q += (int64_t)nblk * blockDim.x) {
-    const int x = (int)(q % w);
-    const int i = (int)((q / w) % h);
-    const int j = (int)(q / hw);
+  // per-thread partials in FP32 (about N / (nblk blockDim) terms each), the
+  // block and grid reductions in FP64
+  float m_ols = 0.f, m_lz = 0.f, s_ols = 0.f, s_lz = 0.f, s_dzf = 0.f;
+  // (x, i, j) of q advanced incrementally by the grid stride (no divisions
+  // per element): stride = dz h w + dy w + dx with dx < w, dy < h
+  const int64_t q0 = bid * (int64_t)blockDim.x + threadIdx.x, stride = (int64_t)nblk * blockDim.x;
+  const int dx = (int)(stride % w), dy = (int)((stride / w) % h), dz = (int)(stride / hw);
+  int x = (int)(q0 % w), i = (int)((q0 / w) % h), j = (int)(q0 / hw);
+  for (int64_t q = q0; q < N; q += stride) {
     const float z = Z[q], l = L[q], o = O[q];
     const int64_t qn[3] = {(i == h - 1) ? q - (int64_t)(h - 1) * w : q + w, (x == w - 1) ? q - (w - 1) : q + 1,
                            (j == b - 1) ? q - (int64_t)(b - 1) * hw : q + hw};
@@ -124,38 +128,42 @@ LRSTV_DEV void grad_shrink_body(
       F[o3] = f;
       G3[o3] = g3 + mu * (g - f);
       A[n * as + q] = f - g4 * imu;
-      const double d = (double)g - (double)f;
+      const float d = g - f;
       s_dzf += d * d;
     }
     G2[q] = G2[q] + mu * (l - z);
     const float g1 = G1[q];
     const float s = soft_threshold(o - l + g1 * imu, lmu);
     S[q] = s;
-    const float r = o - l - s;
+    const float r = o - l - s, dz2 = l - z;
     G1[q] = g1 + mu * r;
-    const double dr = r, dz = (double)l - (double)z;
-    m_ols = fmax(m_ols, fabs(dr));
-    m_lz = fmax(m_lz, fabs(dz));
-    s_ols += dr * dr;
-    s_lz += dz * dz;
+    m_ols = fmaxf(m_ols, fabsf(r));
+    m_lz = fmaxf(m_lz, fabsf(dz2));
+    s_ols += r * r;
+    s_lz += dz2 * dz2;
+    x += dx;
+    if (x >= w) { x -= w; ++i; }
+    i += dy;
+    if (i >= h) { i -= h; ++j; }
+    j += dz;
   }
-  m_ols = block_max(m_ols, red);
-  m_lz = block_max(m_lz, red);
-  s_ols = block_sum(s_ols, red);
-  s_lz = block_sum(s_lz, red);
-  s_dzf = block_sum(s_dzf, red);
+  const double bm_ols = block_max((double)m_ols, red);
+  const double bm_lz = block_max((double)m_lz, red);
+  const double bs_ols = block_sum((double)s_ols, red);
+  const double bs_lz = block_sum((double)s_lz, red);
+  const double bs_dzf = block_sum((double)s_dzf, red);
   if (threadIdx.x == 0) {
-    part[R_INF_OLS * LRSTV_PARTS + bid] = m_ols;
-    part[R_INF_LZ * LRSTV_PARTS + bid] = m_lz;
-    part[R_FRO_OLS * LRSTV_PARTS + bid] = s_ols;
-    part[R_FRO_LZ * LRSTV_PARTS + bid] = s_lz;
-    part[R_FRO_DZF * LRSTV_PARTS + bid] = s_dzf;
+    part[R_INF_OLS * LRSTV_PARTS + bid] = bm_ols;
+    part[R_INF_LZ * LRSTV_PARTS + bid] = bm_lz;
+    part[R_FRO_OLS * LRSTV_PARTS + bid] = bs_ols;
+    part[R_FRO_LZ * LRSTV_PARTS + bid] = bs_lz;
+    part[R_FRO_DZF * LRSTV_PARTS + bid] = bs_dzf;
   }
 }
 
 
 // Batch: LRSTV_PARTS blocks per cube, cube c's residual slots at part + c R_COUNT LRSTV_PARTS.
-__global__ void __launch_bounds__(256) k_grad_shrink_batch(BatchTab bt, BatchPtrs p, float w1, float w2, float w3,
+__global__ void __launch_bounds__(512) k_grad_shrink_batch(BatchTab bt, BatchPtrs p, float w1, float w2, float w3,
                                                            float tau, float lam, const double* __restrict__ mu_dev,
                                                            double* __restrict__ part) {
   const int c = blockIdx.x / LRSTV_PARTS;
@@ -258,7 +266,7 @@ void launch_lrhs_batch(const BatchTab& bt, const BatchPtrs& p, const Weights& wt
 
 void launch_grad_shrink_batch(const BatchTab& bt, const BatchPtrs& p, const Weights& wt, const double* mu,
                               double* part, hipStream_t s) {
-  hipLaunchKernelGGL(k_grad_shrink_batch, dim3(bt.nc * LRSTV_PARTS), dim3(256), 0, s, bt, p, (float)wt.w[0],
+  hipLaunchKernelGGL(k_grad_shrink_batch, dim3(bt.nc * LRSTV_PARTS), dim3(512), 0, s, bt, p, (float)wt.w[0],
                      (float)wt.w[1], (float)wt.w[2], (float)wt.tau, (float)wt.lam, mu, part);
 }
 

@@ -198,9 +198,12 @@ struct MfmaSmemR {
   float a[kKC][kMT + 1], b[kKC][kMT + 1];
 };
 
+// t: the thread's index within its group of 256 (a block may run several
+// groups on separate tiles; every group calls this the same number of times
+// with the same K, since the routine synchronises the whole block).
 template <bool AK, bool BK, class FA, class FB, class ST>
-LRSTV_DEV void mfma_rtile(int m0, int n0, int K, FA fa, FB fb, ST st, MfmaSmemR& sm, bool active) {
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, wy = wv >> 1, wx = wv & 1;
+LRSTV_DEV void mfma_rtile_t(int t, int m0, int n0, int K, FA fa, FB fb, ST st, MfmaSmemR& sm, bool active) {
+  const int lane = t & 63, wv = t >> 6, wy = wv >> 1, wx = wv & 1;
   const int li = lane & 31, lk = lane >> 5;
   int ra, ka, rb, kb;
   stage_coords<AK>(t, ra, ka);
@@ -238,6 +241,10 @@ LRSTV_DEV void mfma_rtile(int m0, int n0, int K, FA fa, FB fb, ST st, MfmaSmemR&
     const int row = m0 + 32 * wy + 8 * (r >> 2) + 4 * lk + (r & 3);
     st(row, col, c[r]);
   }
+}
+template <bool AK, bool BK, class FA, class FB, class ST>
+LRSTV_DEV void mfma_rtile(int m0, int n0, int K, FA fa, FB fb, ST st, MfmaSmemR& sm, bool active) {
+  mfma_rtile_t<AK, BK>(threadIdx.x, m0, n0, K, fa, fb, st, sm, active);
 }
 
 }  // namespace lrstv
