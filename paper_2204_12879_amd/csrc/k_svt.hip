@@ -1037,10 +1037,10 @@ LRSTV_DEV int sturm_count_fast(const double* dg, const double* e2, int n, double
 // scaled by 1 / ||T||); PHASE 1 the eigenvectors from them, spread over
 // blocks of 64 eigenvalues (grid: vector blocks x slices), so that more
 // waves hide the latency of their sequential recurrences; PHASE 2
-// re-orthogonalises clusters and writes V.  Each redoes the O(n) set-up
-// (scaling, splits, the count of eigenvalues below the cut).
+// normalises them, re-orthogonalises clusters and writes V.  Each redoes the
+// O(n) set-up (scaling, splits, the count of eigenvalues below the cut).
 template <int PHASE>
-__global__ void __launch_bounds__(1024) k_trieig(const SliceDesc* __restrict__ desc, double* __restrict__ tri,
+__global__ void __launch_bounds__(PHASE == 1 ? 64 : 1024) k_trieig(const SliceDesc* __restrict__ desc, double* __restrict__ tri,
                                                  double* __restrict__ xs, float* __restrict__ V,
                                                  int* __restrict__ rcount, const double* __restrict__ mu_dev,
                                                  double alpha, float thresh) {
@@ -1097,14 +1097,24 @@ __global__ void __launch_bounds__(1024) k_trieig(const SliceDesc* __restrict__ d
   const bool all = mu_dev == nullptr && thresh < 0.f;
   const double lo_cut = all ? gl - 1.0 : fmax(t * t * sc - delta, 0.0);
   dg = ds;
-  if (threadIdx.x == 0) {
-    int nb = 0;
-    bstart[nb++] = 0;
-    for (int i = 0; i < n - 1; ++i)
-      if (ee[i] == 0.0) bstart[nb++] = i + 1;
-    bstart[nb] = n;
-    s_nblk = nb;
-    s_c0 = all ? 0 : (tnorm == 0.0) ? n : sturm_count(dg, e2, 0, n - 1, lo_cut, pivmin);
+  // unreduced blocks (starts after each zero off-diagonal) by a ballot scan
+  // in the first wave, and the count of eigenvalues below the cut
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    int nb = 1;
+    for (int i0 = 0; i0 < n - 1; i0 += 64) {
+      const int i = i0 + lane;
+      const bool split = i < n - 1 && ee[i] == 0.0;
+      const unsigned long long m = __ballot(split);
+      if (split) bstart[nb + __popcll(m & ((1ull << lane) - 1ull))] = i + 1;
+      nb += __popcll(m);
+    }
+    if (lane == 0) {
+      bstart[0] = 0;
+      bstart[nb] = n;
+      s_nblk = nb;
+      s_c0 = all ? 0 : (tnorm == 0.0) ? n : sturm_count_fast(dg, e2, n, lo_cut, pivmin);
+    }
   }
   __syncthreads();
   const int c0 = s_c0, nblk = s_nblk, r = n - c0;
@@ -1204,26 +1214,42 @@ __global__ void __launch_bounds__(1024) k_trieig(const SliceDesc* __restrict__ d
       if (fabs(dm) < pivmin) dm = pivmin;
       Dm[(int64_t)i * n] = dm;
     }
-    // top-down L D L^T and twist index; the stored Dm is read 8 ahead
+    // top-down L D L^T and twist index.  The stored values of the earlier
+    // pass are read in batches of 16 with the next batch in flight while one
+    // is used (the recurrences are sequential, so the loads would otherwise
+    // expose their latency every few steps).
+    constexpr int PB = 16;
     double dp = dg[p0] - lk;
     if (fabs(dp) < pivmin) dp = pivmin;
     double best = fabs(Dm[(int64_t)p0 * n]);
     int rt = p0;
-    for (int i0 = p0; i0 < p1; i0 += 8) {
-      double dmv[8];
+    {
+      double buf[2][PB];
+      auto load_dm = [&](double (&v)[PB], int i0) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) dmv[q] = (i0 + q < p1) ? Dm[(int64_t)(i0 + q + 1) * n] : 0.0;
+        for (int q = 0; q < PB; ++q) v[q] = (i0 + q < p1) ? Dm[(int64_t)(i0 + q + 1) * n] : 0.0;
+      };
+      auto step_dm = [&](const double (&v)[PB], int i0) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int i = i0 + q;
-        if (i < p1) {
-          const double l = ee[i] * fast_rcp(dp);
-          Lp[(int64_t)i * n] = l;
-          dp = dg[i + 1] - lk - l * ee[i];
-          if (fabs(dp) < pivmin) dp = pivmin;
-          const double g = dp + dmv[q] - (dg[i + 1] - lk);
-          if (fabs(g) < best) { best = fabs(g); rt = i + 1; }
+        for (int q = 0; q < PB; ++q) {
+          const int i = i0 + q;
+          if (i < p1) {
+            const double l = ee[i] * fast_rcp(dp);
+            Lp[(int64_t)i * n] = l;
+            dp = dg[i + 1] - lk - l * ee[i];
+            if (fabs(dp) < pivmin) dp = pivmin;
+            const double g = dp + v[q] - (dg[i + 1] - lk);
+            if (fabs(g) < best) { best = fabs(g); rt = i + 1; }
+          }
         }
+      };
+      load_dm(buf[0], p0);
+      for (int i0 = p0; i0 < p1; i0 += 2 * PB) {
+        if (i0 + PB < p1) load_dm(buf[1], i0 + PB);
+        step_dm(buf[0], i0);
+        if (i0 + PB >= p1) break;
+        if (i0 + 2 * PB < p1) load_dm(buf[0], i0 + 2 * PB);
+        step_dm(buf[1], i0 + PB);
       }
     }
     // solve with the twist: x_rt = 1
@@ -1231,41 +1257,90 @@ __global__ void __launch_bounds__(1024) k_trieig(const SliceDesc* __restrict__ d
     for (int i = 0; i < n; ++i)
       if (i < p0 || i > p1) x[(int64_t)i * n] = 0.0;
     double xv = 1.0, nrm = 1.0;
-    for (int i0 = rt - 1; i0 >= p0; i0 -= 8) {
-      double lv[8];
+    {
+      double buf[2][PB];
+      // rows rt-1 down to p0: x_i = -l_i x_{i+1}
+      auto load_l = [&](double (&v)[PB], int i0) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) lv[q] = (i0 - q >= p0) ? Lp[(int64_t)(i0 - q) * n] : 0.0;
+        for (int q = 0; q < PB; ++q) v[q] = (i0 - q >= p0) ? Lp[(int64_t)(i0 - q) * n] : 0.0;
+      };
+      auto step_l = [&](const double (&v)[PB], int i0) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int i = i0 - q;
-        if (i >= p0) {
-          xv = -lv[q] * xv;
-          x[(int64_t)i * n] = xv;
-          nrm += xv * xv;
+        for (int q = 0; q < PB; ++q) {
+          const int i = i0 - q;
+          if (i >= p0) {
+            xv = -v[q] * xv;
+            x[(int64_t)i * n] = xv;
+            nrm += xv * xv;
+          }
         }
+      };
+      if (rt - 1 >= p0) load_l(buf[0], rt - 1);
+      for (int i0 = rt - 1; i0 >= p0; i0 -= 2 * PB) {
+        if (i0 - PB >= p0) load_l(buf[1], i0 - PB);
+        step_l(buf[0], i0);
+        if (i0 - PB < p0) break;
+        if (i0 - 2 * PB >= p0) load_l(buf[0], i0 - 2 * PB);
+        step_l(buf[1], i0 - PB);
+      }
+      x[(int64_t)rt * n] = 1.0;
+      xv = 1.0;
+      // rows rt+1 .. p1: x_{i+1} = -u_i x_i
+      auto load_u = [&](double (&v)[PB], int i0) {
+#pragma unroll
+        for (int q = 0; q < PB; ++q) v[q] = (i0 + q < p1) ? Um[(int64_t)(i0 + q) * n] : 0.0;
+      };
+      auto step_u = [&](const double (&v)[PB], int i0) {
+#pragma unroll
+        for (int q = 0; q < PB; ++q) {
+          const int i = i0 + q;
+          if (i < p1) {
+            xv = -v[q] * xv;
+            x[(int64_t)(i + 1) * n] = xv;
+            nrm += xv * xv;
+          }
+        }
+      };
+      if (rt < p1) load_u(buf[0], rt);
+      for (int i0 = rt; i0 < p1; i0 += 2 * PB) {
+        if (i0 + PB < p1) load_u(buf[1], i0 + PB);
+        step_u(buf[0], i0);
+        if (i0 + PB >= p1) break;
+        if (i0 + 2 * PB < p1) load_u(buf[0], i0 + 2 * PB);
+        step_u(buf[1], i0 + PB);
       }
     }
-    x[(int64_t)rt * n] = 1.0;
-    xv = 1.0;
-    for (int i0 = rt; i0 < p1; i0 += 8) {
-      double uv[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) uv[q] = (i0 + q < p1) ? Um[(int64_t)(i0 + q) * n] : 0.0;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int i = i0 + q;
-        if (i < p1) {
-          xv = -uv[q] * xv;
-          x[(int64_t)(i + 1) * n] = xv;
-          nrm += xv * xv;
-        }
-      }
-    }
-    const double inv = 1.0 / sqrt(nrm);
-    for (int i = p0; i <= p1; ++i) x[(int64_t)i * n] *= inv;
+    // the vector stays unscaled here: 1 / ||x|| goes to the first row of the
+    // (no longer needed) U scratch, and PHASE 2 scales all columns at once
+    // (a per-thread pass over its own column would serialise on the global
+    // loads)
+    Um[0] = 1.0 / sqrt(nrm);
   }
   if (PHASE == 1) return;
 reorth:
+  __syncthreads();
+  {
+    double* Xs = X + nn;
+    const int tot = n * r;
+    constexpr int U8 = 8;
+    for (int e0 = threadIdx.x; e0 < tot; e0 += U8 * blockDim.x) {
+      double v[U8];
+      int64_t ofs[U8];
+#pragma unroll
+      for (int u = 0; u < U8; ++u) {
+        const int e = e0 + u * blockDim.x;
+        ofs[u] = -1;
+        if (e < tot) {
+          const int i = e / r, c = e - i * r;
+          ofs[u] = (int64_t)i * n + c;
+          v[u] = Xs[ofs[u]] * X[c];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U8; ++u)
+        if (ofs[u] >= 0) Xs[ofs[u]] = v[u];
+    }
+  }
   __syncthreads();
   // Re-orthogonalise inside clusters (gaps below 1e-10 ||T||; larger gaps give
   // FP64 twisted-factorisation vectors accurate to eps_64 / gap): classical
@@ -1356,9 +1431,11 @@ __global__ void __launch_bounds__(256) k_wy_t(const SliceDesc* __restrict__ desc
   // products instead of a 64-step sequential recurrence.  A reflector with
   // tau = 0 (or past the block's last) has a zero column in Y: its diagonal
   // entry is 1 during the inversion (its off-diagonal entries are zero) and
-  // 0 in the result.
-  float2(*U)[64] = S;                                             // argument; its lower half holds B C
-  float2(*T)[65] = reinterpret_cast<float2(*)[65]>(&sm);          // result, rows padded to 65
+  // 0 in the result.  The products B C go to the (free) mirrored lower
+  // block of T, transposed; T's rows are padded to 65 so that neither the
+  // row-wise nor the column-wise accesses conflict in the LDS banks.
+  float2(*U)[64] = S;                                             // argument (upper part used)
+  float2(*T)[65] = reinterpret_cast<float2(*)[65]>(&sm);          // result (upper), products (lower)
   static_assert(sizeof(MfmaSmem) >= 64 * 65 * sizeof(float2), "T factor scratch");
   for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
     const int p = e >> 6, q = e & 63;
@@ -1373,13 +1450,13 @@ __global__ void __launch_bounds__(256) k_wy_t(const SliceDesc* __restrict__ desc
   __syncthreads();
   for (int s2 = 1; s2 < 64; s2 <<= 1) {
     const int E = 32 * s2;   // (32 / s2) block pairs of s2 x s2 entries
-    // M = B C into the (free) mirrored lower block of U, stored transposed
+    // M = B C, stored as T[b1 + c][b0 + r] = M(r, c)
     for (int e = threadIdx.x; e < E; e += blockDim.x) {
       const int pr = e / (s2 * s2), rem = e - pr * s2 * s2, r = rem / s2, c = rem - r * s2;
       const int b0 = 2 * s2 * pr, b1 = b0 + s2;
       float2 acc = make_float2(0.f, 0.f);
       for (int k = 0; k <= c; ++k) acc = cadd(acc, cmul(U[b0 + r][b1 + k], T[b1 + k][b1 + c]));
-      U[b1 + c][b0 + r] = acc;
+      T[b1 + c][b0 + r] = acc;
     }
     __syncthreads();
     // X = -A M into the upper block of T
@@ -1387,7 +1464,7 @@ __global__ void __launch_bounds__(256) k_wy_t(const SliceDesc* __restrict__ desc
       const int pr = e / (s2 * s2), rem = e - pr * s2 * s2, r = rem / s2, c = rem - r * s2;
       const int b0 = 2 * s2 * pr, b1 = b0 + s2;
       float2 acc = make_float2(0.f, 0.f);
-      for (int k = r; k < s2; ++k) acc = cadd(acc, cmul(T[b0 + r][b0 + k], U[b1 + c][b0 + k]));
+      for (int k = r; k < s2; ++k) acc = cadd(acc, cmul(T[b0 + r][b0 + k], T[b1 + c][b0 + k]));
       T[b0 + r][b1 + c] = make_float2(-acc.x, -acc.y);
     }
     __syncthreads();
@@ -1395,7 +1472,7 @@ __global__ void __launch_bounds__(256) k_wy_t(const SliceDesc* __restrict__ desc
   float* out = Twy + d.y_off + (int64_t)b * 64 * 64 * 2;
   for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
     const int p = e >> 6, q = e & 63;
-    float2 t = T[p][q];
+    float2 t = p <= q ? T[p][q] : make_float2(0.f, 0.f);
     if (p == q && !(p < nbk && taus[i0 + p] != 0.0)) t = make_float2(0.f, 0.f);
     out[e] = t.x;
     out[64 * 64 + e] = t.y;
