@@ -283,6 +283,7 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
   std::vector<CubeGeo> geo(nc);
   std::vector<int> bstart((size_t)PH_COUNT * (nc + 1), 0);
   size_t lds_w = 0, lds_h = 0;
+  int max_b = 0;
   for (int c = 0; c < nc; ++c) {
     const CubeInfo& ci = H->cubes[c];
     CubeGeo& g = geo[c];
@@ -298,6 +299,7 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
     const size_t lh = (size_t)(2 * g.cw_h + 1) * ci.h * sizeof(float2);
     if (lw > lds_w) lds_w = lw;
     if (lh > lds_h) lds_h = lh;
+    if (ci.b > max_b) max_b = ci.b;
     for (int ph = 0; ph < PH_COUNT; ++ph)
       bstart[(size_t)ph * (nc + 1) + c + 1] = bstart[(size_t)ph * (nc + 1) + c] + phase_blocks(ph, ci.h, ci.w, ci.b);
   }
@@ -309,6 +311,7 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
     bt.nblocks = bstart[(size_t)ph * (nc + 1) + nc];
     bt.lds_w = lds_w;
     bt.lds_h = lds_h;
+    bt.max_b = max_b;
   }
   hipError_t e = hipMemcpyAsync(H->desc, H->sl.desc.data(), H->sl.desc.size() * sizeof(SliceDesc),
                                 hipMemcpyHostToDevice, H->stream);

@@ -304,69 +304,180 @@ __global__ void __launch_bounds__(256) k_fft_h(float2* __restrict__ spec, int h,
 }
 
 // Periodic tridiagonal solve along the bands for every (k_h, k_w).
+//
+// A block takes kTriCols columns with consecutive k_w (each band row of the
+// block is then one coalesced segment) and splits every column's b bands
+// into kTriChunks chunks of L = ceil(b / kTriChunks), one chunk per thread,
+// held in registers: the half spectrum is read and written once.  Each
+// periodic first-order recursion x_j = s_j + r x_{j -/+ 1} runs as a chunked
+// scan: a local pass with zero carry gives u_j and the chunk's end value;
+// the end values are exchanged through LDS; the carry into chunk q follows
+// in FP64 from the periodic closure
+//   x_{-1} (1 - r^b) = sum_q E_q r^(b - j1_q)         (causal pass),
+//   x_b    (1 - r^b) = sum_q F_q r^(j0_q)             (anti-causal pass),
+// propagated chunk by chunk, and x_j = u_j + r^d C with d the distance to
+// the chunk's carry end.
+constexpr int kTriCols = 32, kTriChunks = 16;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// r^k for k >= 0 by binary powering (a few FP64 roundings)
+LRSTV_DEV double pow_int(double r, int k) {
+  double p = 1.0;
+  while (k > 0) {
+    if (k & 1) p *= r;
+    r *= r;
+    k >>= 1;
+  }
+  return p;
+}
+
+LRSTV_DEV double tri_chunk_pow(int q, int L, int b, double rL, double rlast) {
+  const int len = min(b - q * L, L);
+  return len <= 0 ? 1.0 : (len == L ? rL : rlast);
+}
+
+template <int MAXL>
 LRSTV_DEV void tri_b_body(int bid, int nblk, float2* __restrict__ spec, int h, int w, int b, double w1, double w2,
-                                               double w3, const double* __restrict__ mu_dev, double mu_host) {
+                          double w3, const double* __restrict__ mu_dev, double mu_host) {
+  __shared__ float2 sE[kTriChunks][kTriCols], sF[kTriChunks][kTriCols];
   const int wc = w / 2 + 1;
   const int64_t plane = (int64_t)h * wc;
   const double mu = mu_dev ? *mu_dev : mu_host;
-  for (int64_t col = bid * (int64_t)blockDim.x + threadIdx.x; col < plane;
-       col += (int64_t)nblk * blockDim.x) {
-    const int i = (int)(col / wc), kw = (int)(col - (int64_t)i * wc);
+  const double beta = mu * w3 * w3;
+  const int cl = threadIdx.x % kTriCols, q = threadIdx.x / kTriCols;
+  const int L = (b + kTriChunks - 1) / kTriChunks;
+  const int j0 = min(q * L, b), len = min(j0 + L, b) - j0;
+  const int64_t ngroups = (plane + kTriCols - 1) / kTriCols;
+  // The cube's half spectrum (< 2^31 bytes for sides up to 512) is addressed
+  // as a raw buffer: an element outside the chunk gets an offset beyond the
+  // buffer, whose load returns 0 and whose store is dropped, so the chunk
+  // loops need no per-element branches.
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(spec, 0, (int)(plane * b * (int64_t)sizeof(float2)), 0x00020000);
+  const int kOut = 0x7ffffff0, pl8 = (int)(plane * (int64_t)sizeof(float2));
+  for (int64_t grp = bid; grp < ngroups; grp += nblk) {
+    const int64_t col = grp * kTriCols + cl;
+    const bool ok = col < plane;
+    const int i = ok ? (int)(col / wc) : 0, kw = ok ? (int)(col - (int64_t)i * wc) : 0;
     const double sh = sinpi((double)i / h), sw = sinpi((double)kw / w);
     const double a = mu * (1.0 + 4.0 * (w1 * w1 * sh * sh + w2 * w2 * sw * sw));
-    const double beta = mu * w3 * w3;
-    float2* c = spec + col;
-    if (beta <= 0.0 || b == 1) {
+    const int n = ok ? len : 0;
+    const bool rec = beta > 0.0 && b > 1;  // uniform over the launch
+    double r = 0.0, rL = 0.0, rlast = 0.0, inv = 1.0;
+    if (rec) {
+      const double cc = (a + 2.0 * beta) / (2.0 * beta);
+      r = 1.0 / (cc + sqrt(cc * cc - 1.0));
+      rL = pow_int(r, L);
+      rlast = pow_int(r, b - (b - 1) / L * L);
+      inv = 1.0 / (1.0 - pow_int(r, b));
+    }
+    int base = (int)((col + (int64_t)j0 * plane) * (int64_t)sizeof(float2));
+    // the loads wait for the coefficients, so that the temporaries of their
+    // evaluation are not live beside the chunk
+    asm volatile("" : "+v"(base) : "v"(r), "v"(rL), "v"(rlast), "v"(inv), "v"(a));
+    // element e of the chunk is at byte base + e * pl8; the offset is stepped
+    // in a register that is opaque to the optimiser, so that no table of
+    // MAXL addresses stays live from the loads to the stores
+    float2 v[MAXL];
+    int off = base;
+#pragma unroll
+    for (int e = 0; e < MAXL; ++e) {
+      const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(rs, e < n ? off : kOut, 0, 0);
+      v[e] = make_float2(__uint_as_float(x.x), __uint_as_float(x.y));
+      off = opaque_i(off + pl8);
+    }
+    auto store = [&](int e, int o, float2 z) {
+      const u32x2 x = {__float_as_uint(z.x), __float_as_uint(z.y)};
+      __builtin_amdgcn_raw_buffer_store_b64(x, rs, e < n ? o : kOut, 0, 0);
+    };
+    if (!rec) {  // no recursion along the bands
       const float ia = (float)(1.0 / a);
-      for (int j = 0; j < b; ++j) c[j * plane] = cscale(c[j * plane], ia);
+      off = base;
+#pragma unroll
+      for (int e = 0; e < MAXL; ++e) {
+        store(e, off, cscale(v[e], ia));
+        off = opaque_i(off + pl8);
+      }
       continue;
     }
-    const double cc = (a + 2.0 * beta) / (2.0 * beta);
-    const double r = 1.0 / (cc + sqrt(cc * cc - 1.0));
-    const double rb = pow(r, (double)b);
     const float rf = (float)r;
-    const float inv1 = (float)(1.0 / (1.0 - rb));
-    // causal: y_j - r y_{j-1} = t_j (periodic);  y_0 = sum_m r^m t_{-m} / (1 - r^b)
-    double sx = 0.0, sy = 0.0, pw = 1.0;
-    for (int m = 0; m < b; ++m) {
-      const float2 t = c[(int64_t)((b - m) % b) * plane];
-      sx += pw * t.x;
-      sy += pw * t.y;
-      pw *= r;
-      if (pw < 1e-30) break;
+    // causal: y_j = t_j + r y_{j-1}; u holds the chunk's end value
+    float2 u = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int e = 0; e < MAXL; ++e) {
+      const float2 y = make_float2(fmaf(rf, u.x, v[e].x), fmaf(rf, u.y, v[e].y));
+      u = e < n ? y : u;
+      v[e] = y;
     }
-    float2 y = make_float2((float)sx * inv1, (float)sy * inv1);
-    c[0] = y;
-    for (int j = 1; j < b; ++j) {
-      const float2 t = c[(int64_t)j * plane];
-      y = make_float2(t.x + rf * y.x, t.y + rf * y.y);
-      c[(int64_t)j * plane] = y;
+    sE[q][cl] = u;
+    __syncthreads();
+    // one pass over the end values: S = sum_p E_p r^(b - j1_p) (closure),
+    // T = sum_{p<q} E_p r^(j0_q - j1_p), R = r^(j0_q); C_q = T + R y_{-1}
+    double sx = 0.0, sy = 0.0, tx = 0.0, ty = 0.0, R = 1.0;
+#pragma unroll
+    for (int p = 0; p < kTriChunks; ++p) {
+      const double P = tri_chunk_pow(p, L, b, rL, rlast);
+      const float2 E = sE[p][cl];
+      sx = sx * P + E.x;
+      sy = sy * P + E.y;
+      if (p < q) {
+        tx = tx * P + E.x;
+        ty = ty * P + E.y;
+        R *= P;
+      }
     }
-    // anti-causal: z_j - r z_{j+1} = y_j;  z_{b-1} = sum_m r^m y_{b-1+m} / (1 - r^b)
-    sx = 0.0;
-    sy = 0.0;
-    pw = 1.0;
-    for (int m = 0; m < b; ++m) {
-      const float2 t = c[(int64_t)((b - 1 + m) % b) * plane];
-      sx += pw * t.x;
-      sy += pw * t.y;
-      pw *= r;
-      if (pw < 1e-30) break;
+    const double cx = tx + R * (sx * inv), cy = ty + R * (sy * inv);
+    double pe = r;
+#pragma unroll
+    for (int e = 0; e < MAXL; ++e) {
+      v[e] = make_float2(v[e].x + (float)(pe * cx), v[e].y + (float)(pe * cy));
+      pe *= r;
     }
+    // anti-causal: z_j = y_j + r z_{j+1}; u holds the chunk's start value
+    u = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int e = MAXL - 1; e >= 0; --e) {
+      const float2 z = make_float2(fmaf(rf, u.x, v[e].x), fmaf(rf, u.y, v[e].y));
+      u = e < n ? z : make_float2(0.f, 0.f);
+      v[e] = u;
+    }
+    sF[q][cl] = u;
+    __syncthreads();
+    // S = sum_p F_p r^(j0_p), T = sum_{p>q} F_p r^(j0_p - j1_q),
+    // R = r^(b - j1_q); D_q = z_{j1_q} = T + R z_b, z_b = z_0
+    sx = sy = tx = ty = 0.0;
+    R = 1.0;
+#pragma unroll
+    for (int p = kTriChunks - 1; p >= 0; --p) {
+      const double P = tri_chunk_pow(p, L, b, rL, rlast);
+      const float2 F = sF[p][cl];
+      sx = sx * P + F.x;
+      sy = sy * P + F.y;
+      if (p > q) {
+        tx = tx * P + F.x;
+        ty = ty * P + F.y;
+        R *= P;
+      }
+    }
+    const double dx = tx + R * (sx * inv), dy = ty + R * (sy * inv);
     const float sc = (float)(r / beta);
-    float2 z = make_float2((float)sx * inv1, (float)sy * inv1);
-    c[(int64_t)(b - 1) * plane] = cscale(z, sc);
-    for (int j = b - 2; j >= 0; --j) {
-      const float2 t = c[(int64_t)j * plane];
-      z = make_float2(t.x + rf * z.x, t.y + rf * z.y);
-      c[(int64_t)j * plane] = cscale(z, sc);
+    pe = r;  // r^(j1 - j) at element j; held at r above the chunk's end
+    off = opaque_i(base + (MAXL - 1) * pl8);
+#pragma unroll
+    for (int e = MAXL - 1; e >= 0; --e) {
+      const float2 z = make_float2(v[e].x + (float)(pe * dx), v[e].y + (float)(pe * dy));
+      store(e, off, cscale(z, sc));
+      off = opaque_i(off - pl8);
+      pe = e < n ? pe * r : r;
     }
   }
 }
 
-__global__ void __launch_bounds__(256) k_tri_b(float2* __restrict__ spec, int h, int w, int b, double w1, double w2,
-                                               double w3, const double* __restrict__ mu_dev, double mu_host) {
-  tri_b_body(blockIdx.x, gridDim.x, spec, h, w, b, w1, w2, w3, mu_dev, mu_host);
+template <int MAXL>
+__global__ void __launch_bounds__(kTriCols * kTriChunks, MAXL <= 16 ? 4 : 2) k_tri_b(float2* __restrict__ spec, int h, int w, int b,
+                                                                 double w1, double w2, double w3,
+                                                                 const double* __restrict__ mu_dev, double mu_host) {
+  tri_b_body<MAXL>(blockIdx.x, gridDim.x, spec, h, w, b, w1, w2, w3, mu_dev, mu_host);
 }
 
 // ---------------------------------------------------------------------------
@@ -561,11 +672,13 @@ __global__ void __launch_bounds__(256) k_fft_h_batch(BatchTab bt, float2* __rest
   fft_h_body(q.bid, q.nblk, sm, spec + g.spec_off, g.h, g.w / 2 + 1, g.b, g.cw_h, sign);
 }
 
-__global__ void __launch_bounds__(256) k_tri_b_batch(BatchTab bt, float2* __restrict__ spec, double w1, double w2,
-                                                     double w3, const double* __restrict__ mu_dev) {
+template <int MAXL>
+__global__ void __launch_bounds__(kTriCols * kTriChunks, MAXL <= 16 ? 4 : 2) k_tri_b_batch(BatchTab bt, float2* __restrict__ spec,
+                                                                       double w1, double w2, double w3,
+                                                                       const double* __restrict__ mu_dev) {
   const CubeSel q = select_cube(bt);
   const CubeGeo g = uniform_geo(bt.geo, q.c);
-  tri_b_body(q.bid, q.nblk, spec + g.spec_off, g.h, g.w, g.b, w1, w2, w3, mu_dev, 0.0);
+  tri_b_body<MAXL>(q.bid, q.nblk, spec + g.spec_off, g.h, g.w, g.b, w1, w2, w3, mu_dev, 0.0);
 }
 
 // A: component stride a_stride from the cube's offset; slices at slice_base
@@ -622,11 +735,22 @@ void launch_fft_h(float2* spec, int h, int w, int b, int sign, hipStream_t s) {
   hipLaunchKernelGGL(k_fft_h, dim3(grid), dim3(256), lds, s, spec, h, wc, b, cw, sign);
 }
 
+// Register chunk length of the band solve: L = ceil(b / kTriChunks) <= 16
+// for b <= 256, else <= 32 (LRSTV_MAX_SIDE = 512).
+static int tri_groups(int h, int w) {
+  const int64_t g = ((int64_t)h * (w / 2 + 1) + kTriCols - 1) / kTriCols;
+  return (int)(g < 16384 ? g : 16384);
+}
+
 void launch_tri_b(float2* spec, int h, int w, int b, const double wts[3], const double* mu, double mu_host,
                   hipStream_t s) {
-  const int64_t plane = (int64_t)h * (w / 2 + 1);
-  int grid = (int)((plane + 255) / 256);
-  hipLaunchKernelGGL(k_tri_b, dim3(grid), dim3(256), 0, s, spec, h, w, b, wts[0], wts[1], wts[2], mu, mu_host);
+  const int grid = tri_groups(h, w);
+  if ((b + kTriChunks - 1) / kTriChunks <= 16)
+    hipLaunchKernelGGL(k_tri_b<16>, dim3(grid), dim3(kTriCols * kTriChunks), 0, s, spec, h, w, b, wts[0], wts[1],
+                       wts[2], mu, mu_host);
+  else
+    hipLaunchKernelGGL(k_tri_b<32>, dim3(grid), dim3(kTriCols * kTriChunks), 0, s, spec, h, w, b, wts[0], wts[1],
+                       wts[2], mu, mu_host);
 }
 
 static int dft_tile(int b) {
@@ -670,7 +794,7 @@ int phase_blocks(int phase, int h, int w, int b) {
       const int64_t g = (int64_t)b * ((wc + cw - 1) / cw);
       return (int)(g < 8192 ? g : 8192);
     }
-    case PH_TRI_B: return (int)(((int64_t)h * wc + 255) / 256);
+    case PH_TRI_B: return tri_groups(h, w);
     case PH_BAND_DFT: {
       const int M = 2 * (b / 2 + 1);
       const int64_t t = (int64_t)3 * ((M + kMT - 1) / kMT) * (((int64_t)h * w + kMT - 1) / kMT);
@@ -696,7 +820,12 @@ void launch_fft_h_batch(const BatchTab& bt, float2* spec, int sign, hipStream_t 
 }
 
 void launch_tri_b_batch(const BatchTab& bt, float2* spec, const double wts[3], const double* mu, hipStream_t s) {
-  hipLaunchKernelGGL(k_tri_b_batch, dim3(bt.nblocks), dim3(256), 0, s, bt, spec, wts[0], wts[1], wts[2], mu);
+  if (bt.max_b <= 16 * kTriChunks)
+    hipLaunchKernelGGL(k_tri_b_batch<16>, dim3(bt.nblocks), dim3(kTriCols * kTriChunks), 0, s, bt, spec, wts[0],
+                       wts[1], wts[2], mu);
+  else
+    hipLaunchKernelGGL(k_tri_b_batch<32>, dim3(bt.nblocks), dim3(kTriCols * kTriChunks), 0, s, bt, spec, wts[0],
+                       wts[1], wts[2], mu);
 }
 
 void launch_band_dft_batch(const BatchTab& bt, const float* A, int64_t a_stride, float* slices, hipStream_t s) {

@@ -30,6 +30,7 @@ struct BatchTab {
   const int* bstart;       // device [nc + 1]
   int nc, nblocks;
   size_t lds_w, lds_h;     // dynamic LDS of the w / h FFT phases (max over cubes)
+  int max_b;               // largest band count over cubes
 };
 // Base pointers of the packed batch (gradient-shaped arrays and A: 3
 // components spaced by ts).

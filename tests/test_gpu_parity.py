@@ -46,6 +46,9 @@ def say(*a):
     ((2, 8, 6), (0.3, 1.0, 1.0), 0.01),        # two bands
     ((5, 53, 47), (1.0, 1.0, 0.0), 2.0),       # prime spatial sides, no spectral term
     ((191, 24, 16), (1.0, 1.0, 1.0), 5.0),     # prime band count of the 256x256x191 cube
+    ((17, 10, 12), (1.0, 1.0, 8.0), 0.3),      # one-element and empty band chunks, r near 1
+    ((256, 4, 66), (0.5, 1.0, 2.0), 1.0),      # full band chunks, ragged column groups
+    ((300, 6, 5), (1.0, 1.0, 1.0), 1.5),       # more than 256 bands (longer chunks)
 ])
 def test_zsolve_matches_oracle(shape, wts, mu):
     L = _lib()
