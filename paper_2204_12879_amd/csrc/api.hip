@@ -296,7 +296,7 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
     g.spec_off = ci.spec_off;
     g.slice_base = ci.slice_base;
     const size_t lw = (size_t)(2 * g.nb_w + 1) * ci.w * sizeof(float2);
-    const size_t lh = (size_t)(2 * g.cw_h + 1) * ci.h * sizeof(float2);
+    const size_t lh = geo_fft_h_lds(ci.h);
     if (lw > lds_w) lds_w = lw;
     if (lh > lds_h) lds_h = lh;
     if (ci.b > max_b) max_b = ci.b;
@@ -325,6 +325,7 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
     return fail(LRSTV_ERR_HIP, "copying the slice table: %s", hipGetErrorString(e));
   }
   prepare_svt(H->sl.max_n1);
+  prepare_fft_h(lds_h);
   H->split.first = svt_split_point((int)H->sl.desc.size());
   if (H->split.first > 0) {
     e = hipStreamCreateWithFlags(&H->split.s2, hipStreamNonBlocking);

@@ -26,6 +26,10 @@
 namespace lrstv {
 
 #define MAX_STAGES 24
+constexpr int kFftHThreads = 512;  // a multiple of every column count cw <= 16
+// The inverse w transform has one block per residual slot (LRSTV_PARTS per
+// cube), so it takes large blocks to keep enough waves in flight.
+constexpr int kIrfftThreads = 1024;
 
 struct Plan {
   int ns;
@@ -93,13 +97,13 @@ LRSTV_DEV void small_dft(float2* v, const float2* tw, int N, int sign) {
 }
 
 template <int R>
-LRSTV_DEV void stage_small(const float2* src, float2* dst, int N, int nb, int Ns, const float2* tw, int sign) {
+LRSTV_DEV void stage_small(const float2* src, float2* dst, int N, int ld, int nb, int Ns, const float2* tw, int sign) {
   const int NR = N / R;
   const int tot = nb * NR;
   const int tstep = N / (Ns * R);
   for (int t = threadIdx.x; t < tot; t += blockDim.x) {
     const int f = t / NR, j = t - f * NR, k = j % Ns;
-    const float2* s = src + f * N;
+    const float2* s = src + f * ld;
     float2 v[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
@@ -108,21 +112,22 @@ LRSTV_DEV void stage_small(const float2* src, float2* dst, int N, int nb, int Ns
     }
     small_dft<R>(v, tw, N, sign);
     const int idx = (j / Ns) * Ns * R + k;
-    float2* d = dst + f * N + idx;
+    float2* d = dst + f * ld + idx;
 #pragma unroll
     for (int q = 0; q < R; ++q) d[q * Ns] = v[q];
   }
 }
 
 // Direct DFT stage for a prime factor R > 7: one output per thread.
-LRSTV_DEV void stage_generic(const float2* src, float2* dst, int N, int nb, int Ns, int R, const float2* tw, int sign) {
+LRSTV_DEV void stage_generic(const float2* src, float2* dst, int N, int ld, int nb, int Ns, int R, const float2* tw,
+                             int sign) {
   const int NR = N / R;
   const int tstep = N / (Ns * R), ostep = N / R;
   for (int t = threadIdx.x; t < nb * N; t += blockDim.x) {
     const int f = t / N, o = t - f * N;
     const int k = o % Ns, so = (o / Ns) % R, jd = o / (Ns * R);
     const int j = jd * Ns + k;
-    const float2* s = src + f * N;
+    const float2* s = src + f * ld;
     float2 acc = make_float2(0.f, 0.f);
     int oi = 0;  // (q * so) mod R
     for (int q = 0; q < R; ++q) {
@@ -132,25 +137,26 @@ LRSTV_DEV void stage_generic(const float2* src, float2* dst, int N, int nb, int 
       oi += so;
       if (oi >= R) oi -= R;
     }
-    dst[f * N + o] = acc;
+    dst[f * ld + o] = acc;
   }
 }
 
-// Batched FFT of nb contiguous rows of length N held in bufA; returns the
-// buffer holding the result.  Unnormalised; sign -1 forward, +1 inverse.
-LRSTV_DEV float2* fft_lds(float2* bufA, float2* bufB, int N, int nb, const float2* tw, int sign, const Plan& p) {
+// Batched FFT of nb rows of length N held in bufA at row stride ld; returns
+// the buffer holding the result.  Unnormalised; sign -1 forward, +1 inverse.
+LRSTV_DEV float2* fft_lds(float2* bufA, float2* bufB, int N, int ld, int nb, const float2* tw, int sign,
+                          const Plan& p) {
   float2* src = bufA;
   float2* dst = bufB;
   int Ns = 1;
   for (int st = 0; st < p.ns; ++st) {
     const int R = p.r[st];
     switch (R) {
-      case 2: stage_small<2>(src, dst, N, nb, Ns, tw, sign); break;
-      case 3: stage_small<3>(src, dst, N, nb, Ns, tw, sign); break;
-      case 4: stage_small<4>(src, dst, N, nb, Ns, tw, sign); break;
-      case 5: stage_small<5>(src, dst, N, nb, Ns, tw, sign); break;
-      case 7: stage_small<7>(src, dst, N, nb, Ns, tw, sign); break;
-      default: stage_generic(src, dst, N, nb, Ns, R, tw, sign); break;
+      case 2: stage_small<2>(src, dst, N, ld, nb, Ns, tw, sign); break;
+      case 3: stage_small<3>(src, dst, N, ld, nb, Ns, tw, sign); break;
+      case 4: stage_small<4>(src, dst, N, ld, nb, Ns, tw, sign); break;
+      case 5: stage_small<5>(src, dst, N, ld, nb, Ns, tw, sign); break;
+      case 7: stage_small<7>(src, dst, N, ld, nb, Ns, tw, sign); break;
+      default: stage_generic(src, dst, N, ld, nb, Ns, R, tw, sign); break;
     }
     __syncthreads();
     float2* t = src;
@@ -183,7 +189,7 @@ LRSTV_DEV void rfft_w_body(int bid, int nblk, float2* sm, const float* __restric
       bA[t] = make_float2(va, vb);
     }
     __syncthreads();
-    const float2* out = fft_lds(bA, bB, w, nb, tw, -1, p);
+    const float2* out = fft_lds(bA, bB, w, w, nb, tw, -1, p);
     for (int t = threadIdx.x; t < nb * wc; t += blockDim.x) {
       const int f = t / wc, k = t - f * wc;
       const float2 zk = out[f * w + k];
@@ -209,7 +215,7 @@ __global__ void __launch_bounds__(256) k_rfft_w(const float* __restrict__ T, flo
 // `part` is set, also accumulates sum (Z_new - Z_old)^2 per block.
 LRSTV_DEV void irfft_w_body(int bid, int nblk, float2* sm, const float2* __restrict__ spec, float* __restrict__ Z, int nrows,
                                                  int w, int nb, float scale, double* __restrict__ part) {
-  __shared__ double red[8];
+  __shared__ double red[kIrfftThreads / 64];
   float2* tw = sm;
   float2* bA = sm + w;
   float2* bB = bA + nb * w;
@@ -234,7 +240,7 @@ LRSTV_DEV void irfft_w_body(int bid, int nblk, float2* sm, const float2* __restr
       bA[t] = make_float2(X.x - Y.y, X.y + Y.x);  // X + i Y
     }
     __syncthreads();
-    const float2* out = fft_lds(bA, bB, w, nb, tw, +1, p);
+    const float2* out = fft_lds(bA, bB, w, w, nb, tw, +1, p);
     for (int t = threadIdx.x; t < nb * w; t += blockDim.x) {
       const int f = t / w, x = t - f * w;
       const int ra = r0 + 2 * f, rb = ra + 1;
@@ -266,39 +272,46 @@ LRSTV_DEV void irfft_w_body(int bid, int nblk, float2* sm, const float2* __restr
   }
 }
 
-__global__ void __launch_bounds__(256) k_irfft_w(const float2* __restrict__ spec, float* __restrict__ Z, int nrows,
+__global__ void __launch_bounds__(kIrfftThreads) k_irfft_w(const float2* __restrict__ spec, float* __restrict__ Z, int nrows,
                                                  int w, int nb, float scale, double* __restrict__ part) {
   extern __shared__ float2 sm[];
   irfft_w_body(blockIdx.x, gridDim.x, sm, spec, Z, nrows, w, nb, scale, part);
 }
 
-// Complex FFT along h of spec [b][h][wc], cw columns per block.
+// Complex FFT along h of spec [b][h][wc].  The b * wc columns are taken as
+// one flat list, cw consecutive ones per block (a block reads whole 128-byte
+// row segments and no column is wasted at a band edge).  In LDS each column
+// is a row of stride ld = h + ((2 - h) mod 32): ld = 2 (mod 32) makes the
+// transposing loads and stores free of bank conflicts.
+LRSTV_DEV int fft_h_ld(int h) { return h + (((2 - h) % 32) + 32) % 32; }
+
 LRSTV_DEV void fft_h_body(int bid, int nblk, float2* sm, float2* __restrict__ spec, int h, int wc, int b, int cw, int sign) {
+  const int ld = fft_h_ld(h);
   float2* tw = sm;
   float2* bA = sm + h;
-  float2* bB = bA + cw * h;
+  float2* bB = bA + cw * ld;
   Plan p;
   make_plan(h, p);
   fill_twiddles(tw, h);
-  const int nchunk = (wc + cw - 1) / cw;
-  for (int blk = bid; blk < b * nchunk; blk += nblk) {
-    const int j = blk / nchunk, c0 = (blk - j * nchunk) * cw;
-    float2* base = spec + (int64_t)j * h * wc;
-    for (int t = threadIdx.x; t < cw * h; t += blockDim.x) {
-      const int i = t / cw, c = t - i * cw;
-      bA[c * h + i] = (c0 + c < wc) ? base[(int64_t)i * wc + c0 + c] : make_float2(0.f, 0.f);
-    }
+  const int64_t ncol = (int64_t)b * wc, plane = (int64_t)h * wc;
+  const int64_t nchunk = (ncol + cw - 1) / cw;
+  // blockDim is a multiple of cw, so a thread keeps its column f
+  const int f = threadIdx.x % cw, i0 = threadIdx.x / cw, di = blockDim.x / cw;
+  for (int64_t blk = bid; blk < nchunk; blk += nblk) {
+    const int64_t g = blk * cw + f;
+    const bool ok = g < ncol;
+    const int64_t j = ok ? g / wc : 0;
+    float2* base = spec + j * plane + (ok ? g - j * wc : 0);
+    for (int i = i0; i < h; i += di) bA[f * ld + i] = ok ? base[(int64_t)i * wc] : make_float2(0.f, 0.f);
     __syncthreads();
-    const float2* out = fft_lds(bA, bB, h, cw, tw, sign, p);
-    for (int t = threadIdx.x; t < cw * h; t += blockDim.x) {
-      const int i = t / cw, c = t - i * cw;
-      if (c0 + c < wc) base[(int64_t)i * wc + c0 + c] = out[c * h + i];
-    }
+    const float2* out = fft_lds(bA, bB, h, ld, cw, tw, sign, p);
+    if (ok)
+      for (int i = i0; i < h; i += di) base[(int64_t)i * wc] = out[f * ld + i];
     __syncthreads();
   }
 }
 
-__global__ void __launch_bounds__(256) k_fft_h(float2* __restrict__ spec, int h, int wc, int b, int cw, int sign) {
+__global__ void __launch_bounds__(kFftHThreads) k_fft_h(float2* __restrict__ spec, int h, int wc, int b, int cw, int sign) {
   extern __shared__ float2 sm[];
   fft_h_body(blockIdx.x, gridDim.x, sm, spec, h, wc, b, cw, sign);
 }
@@ -656,7 +669,7 @@ __global__ void __launch_bounds__(256) k_rfft_w_batch(BatchTab bt, const float* 
   rfft_w_body(q.bid, q.nblk, sm, T + g.off, spec + g.spec_off, g.h * g.b, g.w, g.nb_w);
 }
 
-__global__ void __launch_bounds__(256) k_irfft_w_batch(BatchTab bt, const float2* __restrict__ spec,
+__global__ void __launch_bounds__(kIrfftThreads) k_irfft_w_batch(BatchTab bt, const float2* __restrict__ spec,
                                                        float* __restrict__ Z, double* __restrict__ part) {
   extern __shared__ float2 sm[];
   const int c = blockIdx.x / LRSTV_PARTS;
@@ -665,7 +678,7 @@ __global__ void __launch_bounds__(256) k_irfft_w_batch(BatchTab bt, const float2
                1.0f / ((float)g.h * (float)g.w), part ? part + (int64_t)c * R_COUNT * LRSTV_PARTS : nullptr);
 }
 
-__global__ void __launch_bounds__(256) k_fft_h_batch(BatchTab bt, float2* __restrict__ spec, int sign) {
+__global__ void __launch_bounds__(kFftHThreads) k_fft_h_batch(BatchTab bt, float2* __restrict__ spec, int sign) {
   extern __shared__ float2 sm[];
   const CubeSel q = select_cube(bt);
   const CubeGeo g = uniform_geo(bt.geo, q.c);
@@ -705,9 +718,13 @@ static int rows_nb(int w) {
   return nb;
 }
 
+// Columns per block of the h FFT: 16 (whole 128-byte row segments) while the
+// two LDS buffers and the twiddles stay within 80 KB (two blocks per CU).
+static int fft_h_stride(int h) { return h + (((2 - h) % 32) + 32) % 32; }
+static size_t fft_h_lds_bytes(int h, int cw) { return ((size_t)2 * cw * fft_h_stride(h) + h) * sizeof(float2); }
 static int cols_cw(int h) {
   int cw = 16;
-  while (cw > 1 && (2 * cw + 1) * h * 8 > 48 * 1024) cw >>= 1;
+  while (cw > 1 && fft_h_lds_bytes(h, cw) > 80 * 1024) cw >>= 1;
   return cw;
 }
 
@@ -723,16 +740,27 @@ void launch_irfft_w(const float2* spec, float* Z, int h, int w, int b, double* p
   const int nrows = h * b, nb = rows_nb(w);
   const size_t lds = (size_t)(2 * nb + 1) * w * sizeof(float2);
   const float scale = 1.0f / ((float)h * (float)w);
-  hipLaunchKernelGGL(k_irfft_w, dim3(LRSTV_PARTS), dim3(256), lds, s, spec, Z, nrows, w, nb, scale, part);
+  hipLaunchKernelGGL(k_irfft_w, dim3(LRSTV_PARTS), dim3(kIrfftThreads), lds, s, spec, Z, nrows, w, nb, scale, part);
+}
+
+// Dynamic LDS above the 64 KB default is granted once per process (before any
+// capture: the handle's set-up and the stand-alone Z-solve call this).
+static size_t g_fft_h_granted = 65536;
+void prepare_fft_h(size_t lds) {
+  if (lds <= g_fft_h_granted) return;
+  if (hipFuncSetAttribute((const void*)k_fft_h, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess &&
+      hipFuncSetAttribute((const void*)k_fft_h_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) ==
+          hipSuccess)
+    g_fft_h_granted = lds;
 }
 
 void launch_fft_h(float2* spec, int h, int w, int b, int sign, hipStream_t s) {
   const int wc = w / 2 + 1;
   const int cw = cols_cw(h);
-  const size_t lds = (size_t)(2 * cw + 1) * h * sizeof(float2);
-  int grid = b * ((wc + cw - 1) / cw);
-  if (grid > 8192) grid = 8192;
-  hipLaunchKernelGGL(k_fft_h, dim3(grid), dim3(256), lds, s, spec, h, wc, b, cw, sign);
+  const int64_t g = ((int64_t)b * wc + cw - 1) / cw;
+  const int grid = (int)(g < 8192 ? g : 8192);
+  prepare_fft_h(fft_h_lds_bytes(h, cw));
+  hipLaunchKernelGGL(k_fft_h, dim3(grid), dim3(kFftHThreads), fft_h_lds_bytes(h, cw), s, spec, h, wc, b, cw, sign);
 }
 
 // Register chunk length of the band solve: L = ceil(b / kTriChunks) <= 16
@@ -791,7 +819,7 @@ int phase_blocks(int phase, int h, int w, int b) {
     }
     case PH_FFT_H: {
       const int cw = cols_cw(h);
-      const int64_t g = (int64_t)b * ((wc + cw - 1) / cw);
+      const int64_t g = ((int64_t)b * wc + cw - 1) / cw;
       return (int)(g < 8192 ? g : 8192);
     }
     case PH_TRI_B: return tri_groups(h, w);
@@ -806,17 +834,18 @@ int phase_blocks(int phase, int h, int w, int b) {
 
 int geo_rows_nb(int w) { return rows_nb(w); }
 int geo_cols_cw(int h) { return cols_cw(h); }
+size_t geo_fft_h_lds(int h) { return fft_h_lds_bytes(h, cols_cw(h)); }
 
 void launch_rfft_w_batch(const BatchTab& bt, const float* T, float2* spec, hipStream_t s) {
   hipLaunchKernelGGL(k_rfft_w_batch, dim3(bt.nblocks), dim3(256), bt.lds_w, s, bt, T, spec);
 }
 
 void launch_irfft_w_batch(const BatchTab& bt, const float2* spec, float* Z, double* part, hipStream_t s) {
-  hipLaunchKernelGGL(k_irfft_w_batch, dim3(bt.nc * LRSTV_PARTS), dim3(256), bt.lds_w, s, bt, spec, Z, part);
+  hipLaunchKernelGGL(k_irfft_w_batch, dim3(bt.nc * LRSTV_PARTS), dim3(kIrfftThreads), bt.lds_w, s, bt, spec, Z, part);
 }
 
 void launch_fft_h_batch(const BatchTab& bt, float2* spec, int sign, hipStream_t s) {
-  hipLaunchKernelGGL(k_fft_h_batch, dim3(bt.nblocks), dim3(256), bt.lds_h, s, bt, spec, sign);
+  hipLaunchKernelGGL(k_fft_h_batch, dim3(bt.nblocks), dim3(kFftHThreads), bt.lds_h, s, bt, spec, sign);
 }
 
 void launch_tri_b_batch(const BatchTab& bt, float2* spec, const double wts[3], const double* mu, hipStream_t s) {

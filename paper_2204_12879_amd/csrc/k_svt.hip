@@ -1028,8 +1028,8 @@ LRSTV_DEV int sturm_count_fast(const double* dg, const double* e2, int n, double
   return cnt;
 }
 
-// One block (1024 threads) per slice.  Eigenvalues above (t^2 - delta) of
-// T / ||T|| by 5-section (4 threads per eigenvalue), eigenvectors by twisted
+// Eigenvalues above (t^2 - delta) of T / ||T|| by 5-section (4 threads per
+// eigenvalue, blocks of 256 threads over 64 eigenvalues), eigenvectors by twisted
 // factorisation inside their unreduced block, Gram-Schmidt inside clusters;
 // output column c = eigenvector of the c-th largest kept eigenvalue times the
 // phase (V re/im planes).
@@ -1040,15 +1040,16 @@ LRSTV_DEV int sturm_count_fast(const double* dg, const double* e2, int n, double
 // normalises them, re-orthogonalises clusters and writes V.  Each redoes the
 // O(n) set-up (scaling, splits, the count of eigenvalues below the cut).
 template <int PHASE>
-__global__ void __launch_bounds__(PHASE == 1 ? 64 : 1024) k_trieig(const SliceDesc* __restrict__ desc, double* __restrict__ tri,
+__global__ void __launch_bounds__(PHASE == 1 ? 64 : (PHASE == 0 ? 256 : 1024)) k_trieig(const SliceDesc* __restrict__ desc, double* __restrict__ tri,
                                                  double* __restrict__ xs, float* __restrict__ V,
                                                  int* __restrict__ rcount, const double* __restrict__ mu_dev,
                                                  double alpha, float thresh) {
   extern __shared__ double smd[];
   __shared__ double red[16];
   __shared__ int s_c0, s_nblk;
-  // PHASE 1 runs a grid of (vector blocks, slices); the others one block per slice
-  const int slice = PHASE == 1 ? blockIdx.y : blockIdx.x;
+  // PHASES 0 and 1 run a grid of (eigenvalue blocks, slices), PHASE 2 one
+  // block per slice
+  const int slice = PHASE == 2 ? blockIdx.x : blockIdx.y;
   const SliceDesc d = desc[slice];
   const int n = d.n1;
   double* dg = tri + d.t_off;
@@ -1131,15 +1132,18 @@ __global__ void __launch_bounds__(PHASE == 1 ? 64 : 1024) k_trieig(const SliceDe
   // 1.7 times the counts: the slices beyond the last full round, which run
   // beside other work, are latency-bound.
   if (PHASE == 0) {
-    const int G = blockDim.x;
+    // block x takes the eigenvalues c0 + [64 x, 64 x + 64) (and every
+    // gridDim.x * 64-th block of them beyond), so that a slice's work spreads
+    // over several CUs and the launch balances around busy ones
+    const int G = blockDim.x, ngrp = blockDim.x >> 2, stride = ngrp * gridDim.x;
+    if (blockIdx.x * ngrp >= r) return;
     const double lo0 = fmax(gl, lo_cut), cell = (gu - lo0) / G;
-    if (r > 0) gcnt[threadIdx.x] = sturm_count_fast(dg, e2, n, lo0 + (threadIdx.x + 1) * cell, pivmin);
+    gcnt[threadIdx.x] = sturm_count_fast(dg, e2, n, lo0 + (threadIdx.x + 1) * cell, pivmin);
     __syncthreads();
     const int lane = threadIdx.x & 63, q = lane & 3, base = lane & ~3;
-    const int ngrp = blockDim.x >> 2;
-    const int nround = (r + ngrp - 1) / ngrp;
+    const int nround = (r - blockIdx.x * ngrp + stride - 1) / stride;
     for (int rd = 0; rd < nround; ++rd) {
-      const int kk = (threadIdx.x >> 2) + rd * ngrp;
+      const int kk = (threadIdx.x >> 2) + blockIdx.x * ngrp + rd * stride;
       const bool act = kk < r;
       const int k = c0 + kk;
       // first grid point whose count exceeds k: lambda_k in [x_{j-1}, x_j)
@@ -1997,7 +2001,7 @@ static void svt_after_tridiag(const SvtLaunch& L, hipStream_t s, StageTimer& T) 
   const int TM = (m + kMT - 1) / kMT;
   const size_t eig_lds = (size_t)5 * n * sizeof(double) + (size_t)(n + 1 + 1024) * sizeof(int);
   T.begin(ST_TRIEIG);
-  hipLaunchKernelGGL(k_trieig<0>, dim3(ns), dim3(1024), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount, L.mu,
+  hipLaunchKernelGGL(k_trieig<0>, dim3((n + 63) / 64, ns), dim3(256), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount, L.mu,
                      L.alpha, L.thresh);
   T.end(ST_TRIEIG);
   T.begin(ST_TRIVEC);
@@ -2081,7 +2085,7 @@ void launch_svt_vjp(const SvtVjpLaunch& J, hipStream_t s) {
   hipLaunchKernelGGL(k_gram<kF32>, dim3(TT * (TT + 1) / 2, ns), dim3(256), 0, s, L.desc, L.slices, L.gram);
   launch_tridiag(L, s);
   const size_t eig_lds = (size_t)5 * n * sizeof(double) + (size_t)(n + 1 + 1024) * sizeof(int);
-  hipLaunchKernelGGL(k_trieig<0>, dim3(ns), dim3(1024), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount,
+  hipLaunchKernelGGL(k_trieig<0>, dim3((n + 63) / 64, ns), dim3(256), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount,
                      (const double*)nullptr, 0.0, -1.f);
   launch_trivec(L, s, eig_lds, nullptr, -1.f);
   launch_backtrans(L, s);

@@ -64,6 +64,8 @@ __device__ __forceinline__ CubeGeo uniform_geo(const CubeGeo* geo, int c) {
 }
 int geo_rows_nb(int w);
 int geo_cols_cw(int h);
+size_t geo_fft_h_lds(int h);  // dynamic LDS bytes of the h FFT
+void prepare_fft_h(size_t lds);  // grants that LDS to the h FFT kernels
 
 // One cube's pointers for the adjoint of an iteration (all offset to the
 // cube; gradient-shaped arrays are 3 components spaced by ts, the per-cube
