@@ -1473,9 +1473,10 @@ __global__ void __launch_bounds__(256) k_wy_t(const SliceDesc* __restrict__ desc
     }
     __syncthreads();
   }
+  // stored transposed: T(p, q) at q * 64 + p
   float* out = Twy + d.y_off + (int64_t)b * 64 * 64 * 2;
   for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
-    const int p = e >> 6, q = e & 63;
+    const int q = e >> 6, p = e & 63;
     float2 t = p <= q ? T[p][q] : make_float2(0.f, 0.f);
     if (p == q && !(p < nbk && taus[i0 + p] != 0.0)) t = make_float2(0.f, 0.f);
     out[e] = t.x;
@@ -1484,12 +1485,36 @@ __global__ void __launch_bounds__(256) k_wy_t(const SliceDesc* __restrict__ desc
 }
 
 // Column tile blockIdx.x (64 columns of V) of slice blockIdx.y: every
-// reflector block, last to first, on the same columns.
-__global__ void __launch_bounds__(256) k_wy_apply(const SliceDesc* __restrict__ desc, const float2* __restrict__ gram,
-                                                  const float* __restrict__ Twy, float* __restrict__ V,
-                                                  const int* __restrict__ rcount) {
-  __shared__ MfmaSmem sm;
-  __shared__ float2 W[64][64];
+// reflector block, last to first, on the same columns, as
+//   W = Y^H V,  W' = T W,  V -= Y W'.
+// Wave q owns the 16 columns 16 q .. 16 q + 15 and keeps W and W' (64 x 16
+// complex) in the accumulators of v_mfma_f32_16x16x4f32: element r of lane l
+// of row tile t is row 16 t + 4 (l / 16) + r, column l % 16, which is exactly
+// the B operand (row l / 16, column l % 16) of the step that contracts over
+// the rows {16 t + 4 g + r, g = 0..3}.  So W and W' never leave the registers;
+// only the A operands (Y^H, T, Y) and the V rows of the first product are
+// staged through LDS, shared by the four waves.  LDS row strides are chosen
+// so that the operand reads are free of bank conflicts: 80 where a lane's
+// row is 4 s + l / 16 (16 (l / 16) + l % 16 distinct mod 64), 68 where it is
+// 16 t + 4 (l / 16) + r (16 (l / 16) + l % 16 again).
+struct WySmem {
+  union {
+    struct {
+      float yr[32][80], yi[32][80], vr[32][80], vi[32][80];   // Y(k, p), V(k, c), k in the chunk
+    } a;
+    struct {
+      float tr[64][68], ti[64][68];                           // T(p, q) at [q][p]
+    } t;
+    struct {
+      float yr[64][68], yi[64][68];                           // Y(k, p) at [p][k], k in the chunk
+    } y;
+  };
+};
+
+__global__ void __launch_bounds__(256, 4) k_wy_apply(const SliceDesc* __restrict__ desc, const float2* __restrict__ gram,
+                                                     const float* __restrict__ Twy, float* __restrict__ V,
+                                                     const int* __restrict__ rcount) {
+  __shared__ WySmem sm;
   const SliceDesc d = desc[blockIdx.y];
   const int n = d.n1, r = rcount[blockIdx.y], c0 = 64 * blockIdx.x;
   if (c0 >= r) return;
@@ -1498,49 +1523,141 @@ __global__ void __launch_bounds__(256) k_wy_apply(const SliceDesc* __restrict__ 
   const float2* g = gram + d.g_off;
   float* Vr = V + d.v_off;
   float* Vi = Vr + (int64_t)n * n;
-  const int wv = threadIdx.x >> 6;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, li = lane & 15, lg = lane >> 4;
+  const int ccol = 16 * wv + li;       // this lane's column within the tile
+  const bool act = 16 * wv < nc;       // wave-uniform: the wave has columns to update
   for (int b = nblk - 1; b >= 0; --b) {
     const int i0 = 64 * b, m = n - 1 - i0, nbk = m < 64 ? m : 64;
-    const float* Tr = Twy + d.y_off + (int64_t)b * 64 * 64 * 2;
-    const float* Ti = Tr + 64 * 64;
-    // (1) W = Y^H V[i0+1:, c0:c0+64]
-    {
-      auto fa = [&](int p, int k) -> float2 {
-        const float2 y = (k < m) ? wy_y(g, n, i0, nbk, k, p) : make_float2(0.f, 0.f);
-        return make_float2(y.x, -y.y);
-      };
-      auto fb = [&](int k, int c) -> float2 {
-        if (k >= m || c >= nc) return make_float2(0.f, 0.f);
-        const int64_t q = (int64_t)(i0 + 1 + k) * n + c0 + c;
-        return make_float2(Vr[q], Vi[q]);
-      };
-      auto st = [&](int p, int c, float2 v) { W[p][c] = v; };
-      mfma_ctile<kF32, false, false>(0, 0, m, fa, fb, st, sm, true);
-    }
-    __syncthreads();
-    // (2) W <- T W
-    {
-      auto fa = [&](int p, int q) -> float2 { return make_float2(Tr[p * 64 + q], Ti[p * 64 + q]); };
-      auto fb = [&](int q, int c) -> float2 { return W[q][c]; };
-      auto st = [&](int p, int c, float2 v) { W[p][c] = v; };
-      mfma_ctile<kF32, true, false>(0, 0, 64, fa, fb, st, sm, true);
-    }
-    __syncthreads();
-    // (3) V[i0+1:, cols] -= Y W, one 64-row tile at a time
-    for (int kt = 0; kt < m; kt += 64) {
-      auto fa = [&](int k, int q) -> float2 { return (k < m) ? wy_y(g, n, i0, nbk, k, q) : make_float2(0.f, 0.f); };
-      auto fb = [&](int q, int c) -> float2 { return W[q][c]; };
-      auto st = [&](int k, int c, float2 v) {
-        if (k < m && c < nc) {
-          const int64_t q = (int64_t)(i0 + 1 + k) * n + c0 + c;
-          Vr[q] -= v.x;
-          Vi[q] -= v.y;
+    // ---- W = Y^H V[i0+1:, cols]: chunks of 32 rows, staged with the next
+    // chunk's loads in flight.  Staged element e = t + 256 j: row e / 64,
+    // column e % 64 (coalesced along the row).
+    f32x4 wr[4], wi[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wr[q] = wi[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float2 ys[8], vs[8];
+    auto load1 = [&](int k0) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int e = t + 256 * j, kk = e >> 6, cc = e & 63, k = k0 + kk;
+        ys[j] = k < m ? wy_y(g, n, i0, nbk, k, cc) : make_float2(0.f, 0.f);
+        vs[j] = make_float2(0.f, 0.f);
+        if (k < m && cc < nc) {
+          const int64_t q = (int64_t)(i0 + 1 + k) * n + c0 + cc;
+          vs[j] = make_float2(Vr[q], Vi[q]);
         }
-      };
-      const bool active = kt + 32 * (wv >> 1) < m;
-      mfma_ctile<kF32, true, false>(kt, 0, 64, fa, fb, st, sm, active);
+      }
+    };
+    load1(0);
+    for (int k0 = 0; k0 < m; k0 += 32) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int e = t + 256 * j, kk = e >> 6, cc = e & 63;
+        sm.a.yr[kk][cc] = ys[j].x;
+        sm.a.yi[kk][cc] = ys[j].y;
+        sm.a.vr[kk][cc] = vs[j].x;
+        sm.a.vi[kk][cc] = vs[j].y;
+      }
+      __syncthreads();
+      if (k0 + 32 < m) load1(k0 + 32);
+      if (act) {
+#pragma unroll 1
+        for (int s = 0; s < 8; ++s) {
+          const int kk = 4 * s + lg;
+          const float br = sm.a.vr[kk][ccol], bi = sm.a.vi[kk][ccol];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            // conj(Y) V: re += Yr Vr + Yi Vi, im += Yr Vi - Yi Vr
+            const float ar = sm.a.yr[kk][16 * q + li], ai = sm.a.yi[kk][16 * q + li];
+            wr[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, wr[q], 0, 0, 0);
+            wi[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, wi[q], 0, 0, 0);
+            wr[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bi, wr[q], 0, 0, 0);
+            wi[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, br, wi[q], 0, 0, 0);
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // ---- W' = T W (T upper triangular: row tile p of W' takes row tiles
+    // q >= p of W).  T is stored transposed, T(p, q) at [q][p].
+    {
+      const float* Tt = Twy + d.y_off + (int64_t)b * 64 * 64 * 2;
+#pragma unroll 4
+      for (int j = 0; j < 16; ++j) {
+        const int e = t + 256 * j;
+        sm.t.tr[e >> 6][e & 63] = Tt[e];
+        sm.t.ti[e >> 6][e & 63] = Tt[64 * 64 + e];
+      }
     }
     __syncthreads();
+    f32x4 xr[4], xi[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) xr[q] = xi[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (act) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int row = 16 * q + 4 * lg + rr;
+          const float br = wr[q][rr], bi = wi[q][rr];
+#pragma unroll
+          for (int p = 0; p <= q; ++p) {
+            const float ar = sm.t.tr[row][16 * p + li], ai = sm.t.ti[row][16 * p + li];
+            xr[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, xr[p], 0, 0, 0);
+            xi[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, xi[p], 0, 0, 0);
+            xr[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, xr[p], 0, 0, 0);
+            xi[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, xi[p], 0, 0, 0);
+          }
+          // keep the operand reads of one row step together (register budget)
+          __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    __syncthreads();
+    // ---- V[i0+1:, cols] -= Y W': chunks of 64 rows.
+    for (int k0 = 0; k0 < m; k0 += 64) {
+#pragma unroll 4
+      for (int j = 0; j < 16; ++j) {
+        const int e = t + 256 * j, kk = e >> 6, p = e & 63, k = k0 + kk;
+        const float2 y = k < m ? wy_y(g, n, i0, nbk, k, p) : make_float2(0.f, 0.f);
+        sm.y.yr[p][kk] = y.x;
+        sm.y.yi[p][kk] = y.y;
+      }
+      __syncthreads();
+      if (act) {
+        f32x4 ur[4], ui[4];
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt) ur[kt] = ui[kt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const int p = 16 * q + 4 * lg + rr;
+            const float br = xr[q][rr], bi = xi[q][rr];
+#pragma unroll
+            for (int kt = 0; kt < 4; ++kt) {
+              const float ar = sm.y.yr[p][16 * kt + li], ai = sm.y.yi[p][16 * kt + li];
+              ur[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, ur[kt], 0, 0, 0);
+              ui[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, ui[kt], 0, 0, 0);
+              ur[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, ur[kt], 0, 0, 0);
+              ui[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, ui[kt], 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        if (ccol < nc) {
+#pragma unroll
+          for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+              const int k = k0 + 16 * kt + 4 * lg + rr;
+              if (k < m) {
+                const int64_t q = (int64_t)(i0 + 1 + k) * n + c0 + ccol;
+                Vr[q] -= ur[kt][rr];
+                Vi[q] -= ui[kt][rr];
+              }
+            }
+        }
+      }
+      __syncthreads();
+    }
   }
 }
 

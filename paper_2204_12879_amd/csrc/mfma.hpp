@@ -25,6 +25,9 @@
 namespace lrstv {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+// v_mfma_f32_16x16x4f32: lane l holds A(l % 16, l / 16) and B(l / 16, l % 16);
+// accumulator element r of lane l is C(4 (l / 16) + r, l % 16).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 enum MfmaMode { kF32 = 0, kBF16x3 = 1 };
