@@ -1693,15 +1693,19 @@ __global__ void __launch_bounds__(256) k_bp1(const SliceDesc* __restrict__ desc,
     if (a < M && b < N) { br[(int64_t)a * ld + b] = v.x; bi[(int64_t)a * ld + b] = v.y; }
   };
   if (d.tall) {
-    auto fa = [&](int m, int k) -> float2 {
-      if (m >= h || k >= w) return make_float2(0.f, 0.f);
-      return make_float2(mr[(int64_t)m * w + k], mi[(int64_t)m * w + k]);
+    auto fa = [&](int m, int k0, float2(&v)[8]) {
+      const int nv = m < h ? w - k0 : 0;
+      float a[8], b[8];
+      load8(mr + (int64_t)m * w + k0, nv, a);
+      load8(mi + (int64_t)m * w + k0, nv, b);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = make_float2(a[j], b[j]);
     };
     auto fb = [&](int k, int c) -> float2 {
       if (k >= n || c >= r) return make_float2(0.f, 0.f);
       return make_float2(vr[(int64_t)k * n + c], vi[(int64_t)k * n + c]);
     };
-    mfma_ctile<MODE, true, false>(m0, n0, w, fa, fb, st, sm, active);
+    mfma_ctile<MODE, true, false, true, false>(m0, n0, w, fa, fb, st, sm, active);
   } else {
     auto fa = [&](int m, int k) -> float2 {
       if (m >= r || k >= h) return make_float2(0.f, 0.f);
@@ -1719,30 +1723,49 @@ __global__ void __launch_bounds__(256) k_bp1(const SliceDesc* __restrict__ desc,
 __global__ void __launch_bounds__(256) k_colnorm(const SliceDesc* __restrict__ desc, const float* __restrict__ Bb,
                                                  float* __restrict__ fval, const int* __restrict__ rcount,
                                                  const double* __restrict__ mu_dev, double alpha, float thresh) {
-  __shared__ double red[8];
+  // Block (x, slice) takes the singular indices 64 x .. 64 x + 63; squares
+  // are summed in FP64.  Tall: B is h x r at row stride n, thread t takes
+  // column 64 x + t % 64 and rows t / 64 + 4 j, so each row read of a wave is
+  // 64 consecutive floats.  Wide: B is r x w, wave q takes the rows
+  // 64 x + 16 q .. + 15, one contiguous row at a time.
+  __shared__ double part[4][64];
   const SliceDesc d = desc[blockIdx.y];
-  const int r = rcount[blockIdx.y], c = blockIdx.x;
-  if (c >= r) return;
+  const int r = rcount[blockIdx.y], c0 = 64 * blockIdx.x;
+  if (c0 >= r) return;
   const int h = d.h, w = d.w, n = d.n1;
   const float* br = Bb + d.b_off;
   const float* bi = br + (int64_t)h * w;
-  double s = 0.0;
+  const double t = mu_dev ? alpha / *mu_dev : (double)thresh;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  auto shrink = [&](double s2) {
+    const double sg = sqrt(s2);
+    return (sg > t) ? (float)(1.0 - t / sg) : 0.f;
+  };
   if (d.tall) {
-    for (int i = threadIdx.x; i < h; i += blockDim.x) {
-      const double a = br[(int64_t)i * n + c], b = bi[(int64_t)i * n + c];
-      s += a * a + b * b;
+    const int c = c0 + lane;
+    double s = 0.0;
+    if (c < r) {
+#pragma unroll 8
+      for (int i = wv; i < h; i += 4) {
+        const double a = br[(int64_t)i * n + c], b = bi[(int64_t)i * n + c];
+        s += a * a + b * b;
+      }
     }
+    part[wv][lane] = s;
+    __syncthreads();
+    if (wv == 0 && c < r) fval[d.f_off + c] = shrink(part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]);
   } else {
-    for (int i = threadIdx.x; i < w; i += blockDim.x) {
-      const double a = br[(int64_t)c * w + i], b = bi[(int64_t)c * w + i];
-      s += a * a + b * b;
+    for (int cc = 0; cc < 16; ++cc) {
+      const int c = c0 + 16 * wv + cc;
+      if (c >= r) break;  // wave-uniform
+      double s = 0.0;
+      for (int i = lane; i < w; i += 64) {
+        const double a = br[(int64_t)c * w + i], b = bi[(int64_t)c * w + i];
+        s += a * a + b * b;
+      }
+      s = warp_sum(s);
+      if (lane == 0) fval[d.f_off + c] = shrink(s);
     }
-  }
-  s = block_sum(s, red);
-  if (threadIdx.x == 0) {
-    const double t = mu_dev ? alpha / *mu_dev : (double)thresh;
-    const double sg = sqrt(s);
-    fval[d.f_off + c] = (sg > t) ? (float)(1.0 - t / sg) : 0.f;
   }
 }
 
@@ -1768,28 +1791,35 @@ __global__ void __launch_bounds__(256) k_bp2(const SliceDesc* __restrict__ desc,
   auto st = [&](int a, int b, float2 v) {
     if (a < h && b < w) { er[(int64_t)a * w + b] = v.x; ei[(int64_t)a * w + b] = v.y; }
   };
+  // rows of B (tall) or V (wide) scaled by f, and rows of V: k-contiguous,
+  // fetched eight at a time
+  auto scaled_rows = [&](const float* xr, const float* xi, int m, int k0, float2(&v)[8]) {
+    const int nv = m < h ? r - k0 : 0;
+    float a[8], b[8], s8[8];
+    load8(xr + (int64_t)m * n + k0, nv, a);
+    load8(xi + (int64_t)m * n + k0, nv, b);
+    load8(f + k0, nv, s8);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = make_float2(a[j] * s8[j], b[j] * s8[j]);
+  };
   if (d.tall) {
-    auto fa = [&](int m, int k) -> float2 {
-      if (m >= h || k >= r) return make_float2(0.f, 0.f);
-      const float s = f[k];
-      return make_float2(br[(int64_t)m * n + k] * s, bi[(int64_t)m * n + k] * s);
+    auto fa = [&](int m, int k0, float2(&v)[8]) { scaled_rows(br, bi, m, k0, v); };
+    auto fb = [&](int k0, int c, float2(&v)[8]) {
+      const int nv = c < w ? r - k0 : 0;
+      float a[8], b[8];
+      load8(vr + (int64_t)c * n + k0, nv, a);
+      load8(vi + (int64_t)c * n + k0, nv, b);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = make_float2(a[j], -b[j]);
     };
-    auto fb = [&](int k, int c) -> float2 {
-      if (k >= r || c >= w) return make_float2(0.f, 0.f);
-      return make_float2(vr[(int64_t)c * n + k], -vi[(int64_t)c * n + k]);
-    };
-    mfma_ctile<MODE, true, true>(m0, n0, r, fa, fb, st, sm, active);
+    mfma_ctile<MODE, true, true, true, true>(m0, n0, r, fa, fb, st, sm, active);
   } else {
-    auto fa = [&](int m, int k) -> float2 {
-      if (m >= h || k >= r) return make_float2(0.f, 0.f);
-      const float s = f[k];
-      return make_float2(vr[(int64_t)m * n + k] * s, vi[(int64_t)m * n + k] * s);
-    };
+    auto fa = [&](int m, int k0, float2(&v)[8]) { scaled_rows(vr, vi, m, k0, v); };
     auto fb = [&](int k, int c) -> float2 {
       if (k >= r || c >= w) return make_float2(0.f, 0.f);
       return make_float2(br[(int64_t)k * w + c], bi[(int64_t)k * w + c]);
     };
-    mfma_ctile<MODE, true, false>(m0, n0, r, fa, fb, st, sm, active);
+    mfma_ctile<MODE, true, false, true, false>(m0, n0, r, fa, fb, st, sm, active);
   }
 }
 
@@ -2135,7 +2165,7 @@ static void svt_after_tridiag(const SvtLaunch& L, hipStream_t s, StageTimer& T) 
     hipLaunchKernelGGL(k_bp1<kF32>, dim3(TM, TM, ns), dim3(256), 0, s, L.desc, L.slices, L.V, L.B, L.rcount);
   T.end(ST_BP1);
   T.begin(ST_COLNORM);
-  hipLaunchKernelGGL(k_colnorm, dim3(n, ns), dim3(256), 0, s, L.desc, L.B, L.fval, L.rcount, L.mu, L.alpha,
+  hipLaunchKernelGGL(k_colnorm, dim3((n + 63) / 64, ns), dim3(256), 0, s, L.desc, L.B, L.fval, L.rcount, L.mu, L.alpha,
                      L.thresh);
   T.end(ST_COLNORM);
   T.begin(ST_BP2);

@@ -149,13 +149,29 @@ LRSTV_DEV void chunk_mma(const MfmaSmem& sm, int wy, int wx, int lane, bool acti
   }
 }
 
+// Eight consecutive floats p[0 .. 7], of which the first nvalid exist (the
+// rest read as 0): two float4 loads when all eight exist and p is 16-byte
+// aligned, element loads otherwise.
+LRSTV_DEV void load8(const float* p, int nvalid, float (&v)[8]) {
+  if (nvalid >= 8 && ((reinterpret_cast<uintptr_t>(p) & 15) == 0)) {
+    const float4 a = reinterpret_cast<const float4*>(p)[0], b = reinterpret_cast<const float4*>(p)[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = j < nvalid ? p[j] : 0.f;
+  }
+}
+
 // C(m0 .. m0+63, n0 .. n0+63) = sum_{k < K} fa(m, k) fb(k, n).
 // AK / BK: k is the contiguous memory index of A / B (selects the staging
-// order).  `active` (wave-uniform) skips the products of a wave whose
-// sub-tile is not needed; every wave still takes part in staging.
-// The result is handed to st(row, col, float2) for rows and columns of the
-// wave's sub-tile.
-template <int MODE, bool AK, bool BK, class FA, class FB, class ST>
+// order).  With VA / VB the accessor is eight-wide instead, fa(m, k, v) /
+// fb(k, n, v) filling v[j] with the values at k + j (for a k-contiguous
+// operand this lets it use vector loads; see load8).  `active`
+// (wave-uniform) skips the products of a wave whose sub-tile is not needed;
+// every wave still takes part in staging.  The result is handed to
+// st(row, col, float2) for rows and columns of the wave's sub-tile.
+template <int MODE, bool AK, bool BK, bool VA = false, bool VB = false, class FA, class FB, class ST>
 LRSTV_DEV void mfma_ctile(int m0, int n0, int K, FA fa, FB fb, ST st, MfmaSmem& sm, bool active) {
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6, wy = wv >> 1, wx = wv & 1;
   int ra, ka, rb, kb;
@@ -165,22 +181,26 @@ LRSTV_DEV void mfma_ctile(int m0, int n0, int K, FA fa, FB fb, ST st, MfmaSmem& 
 #pragma unroll
   for (int i = 0; i < 16; ++i) c.re[i] = c.im[i] = 0.f;
   float2 va[8], vb[8];
+  auto fetch = [&](int kc) {
+    if constexpr (VA) {
+      fa(m0 + ra, kc + ka, va);
+    } else {
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    va[j] = fa(m0 + ra, ka + j);
-    vb[j] = fb(kb + j, n0 + rb);
-  }
+      for (int j = 0; j < 8; ++j) va[j] = fa(m0 + ra, kc + ka + j);
+    }
+    if constexpr (VB) {
+      fb(kc + kb, n0 + rb, vb);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) vb[j] = fb(kc + kb + j, n0 + rb);
+    }
+  };
+  fetch(0);
   for (int k0 = 0; k0 < K; k0 += kKC) {
     stage_store<MODE>(sm, true, ra, ka, va);
     stage_store<MODE>(sm, false, rb, kb, vb);
     __syncthreads();
-    if (k0 + kKC < K) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        va[j] = fa(m0 + ra, k0 + kKC + ka + j);
-        vb[j] = fb(k0 + kKC + kb + j, n0 + rb);
-      }
-    }
+    if (k0 + kKC < K) fetch(k0 + kKC);
     chunk_mma<MODE>(sm, wy, wx, lane, active, c);
     __syncthreads();
   }
