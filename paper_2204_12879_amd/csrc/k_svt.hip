@@ -1323,10 +1323,24 @@ __global__ void __launch_bounds__(PHASE == 1 ? 64 : (PHASE == 0 ? 256 : 1024)) k
   if (PHASE == 1) return;
 reorth:
   __syncthreads();
-  {
-    double* Xs = X + nn;
+  // Re-orthogonalise inside clusters (gaps below 1e-10 ||T||; larger gaps give
+  // FP64 twisted-factorisation vectors accurate to eps_64 / gap): classical
+  // Gram-Schmidt applied twice per vector against the earlier cluster members.
+  // That needs the normalised vectors in place; a slice without a cluster
+  // (the usual case) applies the scale while V is written instead, one pass
+  // over the vectors instead of three.
+  double* Xv = X + nn;
+  const double gtol = 1e-10 * tnorm;
+  __shared__ int s_cluster;
+  if (threadIdx.x == 0) s_cluster = 0;
+  __syncthreads();
+  for (int k = c0 + 1 + threadIdx.x; k < n; k += blockDim.x)
+    if (lam[k] - lam[k - 1] <= gtol) s_cluster = 1;
+  __syncthreads();
+  const bool cluster = s_cluster != 0;
+  constexpr int U8 = 8;
+  if (cluster) {
     const int tot = n * r;
-    constexpr int U8 = 8;
     for (int e0 = threadIdx.x; e0 < tot; e0 += U8 * blockDim.x) {
       double v[U8];
       int64_t ofs[U8];
@@ -1337,55 +1351,67 @@ reorth:
         if (e < tot) {
           const int i = e / r, c = e - i * r;
           ofs[u] = (int64_t)i * n + c;
-          v[u] = Xs[ofs[u]] * X[c];
+          v[u] = Xv[ofs[u]] * X[c];
         }
       }
 #pragma unroll
       for (int u = 0; u < U8; ++u)
-        if (ofs[u] >= 0) Xs[ofs[u]] = v[u];
+        if (ofs[u] >= 0) Xv[ofs[u]] = v[u];
     }
-  }
-  __syncthreads();
-  // Re-orthogonalise inside clusters (gaps below 1e-10 ||T||; larger gaps give
-  // FP64 twisted-factorisation vectors accurate to eps_64 / gap): classical
-  // Gram-Schmidt applied twice per vector against the earlier cluster members.
-  double* Xv = X + nn;
-  const double gtol = 1e-10 * tnorm;
-  for (int k = c0 + 1; k < n; ++k) {
-    int k0 = k;
-    while (k0 > c0 && lam[k0] - lam[k0 - 1] <= gtol) --k0;
-    if (k0 == k) continue;
-    const int ck = k - c0, cb = k0 - c0, nc = k - k0;
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int j = threadIdx.x; j < nc; j += blockDim.x) {
-        double dt = 0.0;
-        for (int i = 0; i < n; ++i) dt += Xv[(int64_t)i * n + cb + j] * Xv[(int64_t)i * n + ck];
-        sdot[j] = dt;
-      }
-      __syncthreads();
-      for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        double acc = 0.0;
-        for (int j = 0; j < nc; ++j) acc += sdot[j] * Xv[(int64_t)i * n + cb + j];
-        Xv[(int64_t)i * n + ck] -= acc;
-      }
-      __syncthreads();
-    }
-    double nr = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) nr += Xv[(int64_t)i * n + ck] * Xv[(int64_t)i * n + ck];
-    nr = block_sum(nr, red);
-    const double inv = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) Xv[(int64_t)i * n + ck] *= inv;
     __syncthreads();
+    for (int k = c0 + 1; k < n; ++k) {
+      int k0 = k;
+      while (k0 > c0 && lam[k0] - lam[k0 - 1] <= gtol) --k0;
+      if (k0 == k) continue;
+      const int ck = k - c0, cb = k0 - c0, nc = k - k0;
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int j = threadIdx.x; j < nc; j += blockDim.x) {
+          double dt = 0.0;
+          for (int i = 0; i < n; ++i) dt += Xv[(int64_t)i * n + cb + j] * Xv[(int64_t)i * n + ck];
+          sdot[j] = dt;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+          double acc = 0.0;
+          for (int j = 0; j < nc; ++j) acc += sdot[j] * Xv[(int64_t)i * n + cb + j];
+          Xv[(int64_t)i * n + ck] -= acc;
+        }
+        __syncthreads();
+      }
+      double nr = 0.0;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) nr += Xv[(int64_t)i * n + ck] * Xv[(int64_t)i * n + ck];
+      nr = block_sum(nr, red);
+      const double inv = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) Xv[(int64_t)i * n + ck] *= inv;
+      __syncthreads();
+    }
   }
-  // V[:, c] = phase .* x for the c-th largest eigenvalue
+  // V[:, c] = phase .* x for the c-th largest eigenvalue (times 1 / ||x||
+  // when it was not applied above), eight loads in flight per thread
   float* Vr = V + d.v_off;
   float* Vi = Vr + nn;
-  for (int64_t e = threadIdx.x; e < (int64_t)n * r; e += blockDim.x) {
-    const int i = (int)(e / r), c = (int)(e - (int64_t)i * r);
-    const int k = n - 1 - c;
-    const double xv = Xv[(int64_t)i * n + (k - c0)];
-    Vr[(int64_t)i * n + c] = (float)(phr[i] * xv);
-    Vi[(int64_t)i * n + c] = (float)(phi[i] * xv);
+  const int tot = n * r;
+  for (int e0 = threadIdx.x; e0 < tot; e0 += U8 * blockDim.x) {
+    double xv[U8];
+#pragma unroll
+    for (int u = 0; u < U8; ++u) {
+      const int e = e0 + u * blockDim.x;
+      xv[u] = 0.0;
+      if (e < tot) {
+        const int i = e / r, c = e - i * r, col = n - 1 - c - c0;
+        xv[u] = Xv[(int64_t)i * n + col];
+        if (!cluster) xv[u] *= X[col];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U8; ++u) {
+      const int e = e0 + u * blockDim.x;
+      if (e < tot) {
+        const int i = e / r, c = e - i * r;
+        Vr[(int64_t)i * n + c] = (float)(phr[i] * xv[u]);
+        Vi[(int64_t)i * n + c] = (float)(phi[i] * xv[u]);
+      }
+    }
   }
   if (threadIdx.x == 0) rcount[slice] = r;
 }
