@@ -500,8 +500,9 @@ __global__ void __launch_bounds__(kTriCols * kTriChunks, MAXL <= 16 ? 4 : 2) k_t
 // so row 2k / 2k+1 of X is the re / im plane of Fourier slice k: the planar
 // slice layout [t][k][re|im][hw] is X itself.  F is generated while staging
 // from an LDS table of cos / sin(2 pi m / b) (index j k mod b, advanced
-// incrementally).  Tiles are walked with the row tile fastest so that the
-// blocks sharing a column strip of A run together (L2 reuse).
+// incrementally).  A block takes a column strip of A and walks its row tiles
+// itself, so that the strip is fetched from HBM once and re-read from the
+// block's own L2 (consecutive blocks run on different XCDs).
 LRSTV_DEV void band_dft_body(int bid, int nblk, const float* __restrict__ A, int64_t a_stride, int n_t,
                                                   float* __restrict__ out, int hw, int b) {
   __shared__ MfmaSmemR sm;
@@ -515,11 +516,11 @@ LRSTV_DEV void band_dft_body(int bid, int nblk, const float* __restrict__ A, int
   __syncthreads();
   const int M = 2 * (b / 2 + 1);
   const int TM = (M + kMT - 1) / kMT, TN = (hw + kMT - 1) / kMT;
-  const int ntiles = n_t * TM * TN;
+  const int nstrips = n_t * TN;
   const int wv = threadIdx.x >> 6;
-  for (int tile = bid; tile < ntiles; tile += nblk) {
-    const int t = tile / (TM * TN), rem = tile - t * TM * TN;
-    const int tn = rem / TM, tm = rem - tn * TM;
+  for (int strip = bid; strip < nstrips; strip += nblk)
+  for (int tm = 0; tm < TM; ++tm) {
+    const int t = strip / TN, tn = strip - t * TN;
     const int m0 = tm * kMT, n0 = tn * kMT;
     const float* src = A + t * a_stride;
     float* dst = out + (int64_t)t * M * hw;
@@ -788,9 +789,9 @@ static int dft_tile(int b) {
 }
 
 void launch_band_dft(const float* A, int64_t a_stride, int n_t, float* slices, int h, int w, int b, hipStream_t s) {
-  const int hw = h * w, M = 2 * (b / 2 + 1);
-  const int64_t ntiles = (int64_t)n_t * ((M + kMT - 1) / kMT) * ((hw + kMT - 1) / kMT);
-  const int grid = (int)(ntiles < 2048 ? ntiles : 2048);
+  const int hw = h * w;
+  const int64_t nstrips = (int64_t)n_t * ((hw + kMT - 1) / kMT);
+  const int grid = (int)(nstrips < 8192 ? nstrips : 8192);
   hipLaunchKernelGGL(k_band_dft, dim3(grid), dim3(256), 0, s, A, a_stride, n_t, slices, hw, b);
 }
 
@@ -824,9 +825,8 @@ int phase_blocks(int phase, int h, int w, int b) {
     }
     case PH_TRI_B: return tri_groups(h, w);
     case PH_BAND_DFT: {
-      const int M = 2 * (b / 2 + 1);
-      const int64_t t = (int64_t)3 * ((M + kMT - 1) / kMT) * (((int64_t)h * w + kMT - 1) / kMT);
-      return (int)(t < 2048 ? t : 2048);
+      const int64_t t = (int64_t)3 * (((int64_t)h * w + kMT - 1) / kMT);
+      return (int)(t < 8192 ? t : 8192);
     }
     default: return LRSTV_PARTS;
   }

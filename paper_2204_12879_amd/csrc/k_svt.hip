@@ -38,15 +38,31 @@ LRSTV_DEV int64_t packed(int r, int c) { return (int64_t)r * (r + 1) / 2 + c; }
 #define kDeflate2 1e-14
 
 // ------------------------------------------------------------------ Gram ---
-// G = M^H M (tall) or M M^H (wide), packed lower triangle.  Block x walks the
-// lower 64 x 64 tiles of the slice, block y is the slice.
+// XCD-aware placement of a (tile, slice) grid launched as one dimension of
+// ntile * round_up(ns, 8) blocks.  Workgroups are dispatched to the 8 XCDs
+// in turn (block L to XCD L mod 8), each with its own L2; with slice =
+// 8 (q / ntile) + L mod 8 and tile = q mod ntile (q = L / 8) the tiles of a
+// slice run on one XCD at nearly the same time and share its L2.  Returns
+// false for the padding slices.
+LRSTV_DEV bool xcd_tile_slice(int ntile, int ns, int& tile, int& slice) {
+  const int L = blockIdx.x, q = L >> 3, g = q / ntile;
+  slice = 8 * g + (L & 7);
+  tile = q - g * ntile;
+  return slice < ns;
+}
+inline int xcd_grid(int ntile, int ns) { return ntile * ((ns + 7) / 8) * 8; }
+
+// G = M^H M (tall) or M M^H (wide), packed lower triangle, one block per
+// lower 64 x 64 tile (placed by xcd_tile_slice).
 template <int MODE>
 __global__ void __launch_bounds__(256) k_gram(const SliceDesc* __restrict__ desc, const float* __restrict__ sl,
-                                              float2* __restrict__ gram) {
+                                              float2* __restrict__ gram, int ntile, int ns) {
   __shared__ MfmaSmem sm;
-  const SliceDesc d = desc[blockIdx.y];
+  int tile, slice;
+  if (!xcd_tile_slice(ntile, ns, tile, slice)) return;
+  const SliceDesc d = desc[slice];
   const int n = d.n1, T = (n + kMT - 1) / kMT;
-  int ti = 0, rem = blockIdx.x;
+  int ti = 0, rem = tile;
   while (rem > ti) { rem -= ti + 1; ++ti; }
   const int tj = rem;
   if (ti >= T) return;
@@ -1431,15 +1447,18 @@ LRSTV_DEV float2 wy_y(const float2* __restrict__ g, int n, int i0, int nbk, int 
   return g[packed(row, i0 + p)];
 }
 
-// T factor of reflector block blockIdx.x of slice blockIdx.y.
+// T factor of one reflector block (placed by xcd_tile_slice over
+// (reflector block, slice), so that the blocks of a slice share an L2).
 __global__ void __launch_bounds__(256) k_wy_t(const SliceDesc* __restrict__ desc, const float2* __restrict__ gram,
                                               const double* __restrict__ tri, float* __restrict__ Twy,
-                                              const int* __restrict__ rcount) {
+                                              const int* __restrict__ rcount, int ntile, int ns) {
   __shared__ MfmaSmem sm;
   __shared__ float2 S[64][64];
-  const SliceDesc d = desc[blockIdx.y];
-  const int n = d.n1, nblk = (n - 1 + 63) / 64, b = blockIdx.x;
-  if (b >= nblk || rcount[blockIdx.y] == 0) return;
+  int b, slice;
+  if (!xcd_tile_slice(ntile, ns, b, slice)) return;
+  const SliceDesc d = desc[slice];
+  const int n = d.n1, nblk = (n - 1 + 63) / 64;
+  if (b >= nblk || rcount[slice] == 0) return;
   const int i0 = 64 * b, m = n - 1 - i0, nbk = m < 64 ? m : 64;
   const float2* g = gram + d.g_off;
   const double* taus = tri + d.t_off + 4 * n;
@@ -1510,8 +1529,9 @@ __global__ void __launch_bounds__(256) k_wy_t(const SliceDesc* __restrict__ desc
   }
 }
 
-// Column tile blockIdx.x (64 columns of V) of slice blockIdx.y: every
-// reflector block, last to first, on the same columns, as
+// One column tile (64 columns of V) of a slice, placed by xcd_tile_slice
+// over (column tile, slice): every reflector block, last to first, on the
+// same columns, as
 //   W = Y^H V,  W' = T W,  V -= Y W'.
 // Wave q owns the 16 columns 16 q .. 16 q + 15 and keeps W and W' (64 x 16
 // complex) in the accumulators of v_mfma_f32_16x16x4f32: element r of lane l
@@ -1539,10 +1559,12 @@ struct WySmem {
 
 __global__ void __launch_bounds__(256, 4) k_wy_apply(const SliceDesc* __restrict__ desc, const float2* __restrict__ gram,
                                                      const float* __restrict__ Twy, float* __restrict__ V,
-                                                     const int* __restrict__ rcount) {
+                                                     const int* __restrict__ rcount, int ntile, int ns) {
   __shared__ WySmem sm;
-  const SliceDesc d = desc[blockIdx.y];
-  const int n = d.n1, r = rcount[blockIdx.y], c0 = 64 * blockIdx.x;
+  int ct, slice;
+  if (!xcd_tile_slice(ntile, ns, ct, slice)) return;
+  const SliceDesc d = desc[slice];
+  const int n = d.n1, r = rcount[slice], c0 = 64 * ct;
   if (c0 >= r) return;
   const int nc = (r - c0) < 64 ? (r - c0) : 64;
   const int nblk = (n - 1 + 63) / 64;
@@ -1691,8 +1713,11 @@ void launch_backtrans(const SvtLaunch& L, hipStream_t s) {
   const int n = L.max_n1, ns = L.n_slices;
   const int nblk = (n - 1 + 63) / 64;
   if (nblk == 0 || ns == 0) return;
-  hipLaunchKernelGGL(k_wy_t, dim3(nblk, ns), dim3(256), 0, s, L.desc, L.gram, L.tri, L.Twy, L.rcount);
-  hipLaunchKernelGGL(k_wy_apply, dim3((n + 63) / 64, ns), dim3(256), 0, s, L.desc, L.gram, L.Twy, L.V, L.rcount);
+  hipLaunchKernelGGL(k_wy_t, dim3(xcd_grid(nblk, ns)), dim3(256), 0, s, L.desc, L.gram, L.tri, L.Twy, L.rcount, nblk,
+                     ns);
+  const int ncb = (n + 63) / 64;
+  hipLaunchKernelGGL(k_wy_apply, dim3(xcd_grid(ncb, ns)), dim3(256), 0, s, L.desc, L.gram, L.Twy, L.V, L.rcount, ncb,
+                     ns);
 }
 
 // ----------------------------------------------------- back-projection ---
@@ -1700,17 +1725,20 @@ void launch_backtrans(const SvtLaunch& L, hipStream_t s) {
 template <int MODE>
 __global__ void __launch_bounds__(256) k_bp1(const SliceDesc* __restrict__ desc, const float* __restrict__ sl,
                                              const float* __restrict__ V, float* __restrict__ Bb,
-                                             const int* __restrict__ rcount) {
+                                             const int* __restrict__ rcount, int tdim, int ns) {
   __shared__ MfmaSmem sm;
-  const SliceDesc d = desc[blockIdx.z];
-  const int r = rcount[blockIdx.z], n = d.n1, h = d.h, w = d.w;
+  int tile, slice;
+  if (!xcd_tile_slice(tdim * tdim, ns, tile, slice)) return;
+  const int bx = tile % tdim, by = tile / tdim;
+  const SliceDesc d = desc[slice];
+  const int r = rcount[slice], n = d.n1, h = d.h, w = d.w;
   const float* mr = sl + d.a_off;
   const float* mi = mr + (int64_t)h * w;
   const float* vr = V + d.v_off;
   const float* vi = vr + (int64_t)n * n;
   float* br = Bb + d.b_off;
   float* bi = br + (int64_t)h * w;
-  const int m0 = blockIdx.y * kMT, n0 = blockIdx.x * kMT;
+  const int m0 = by * kMT, n0 = bx * kMT;
   const int M = d.tall ? h : r, N = d.tall ? r : w, ld = d.tall ? n : w;
   if (m0 >= M || n0 >= N) return;
   const int wv = threadIdx.x >> 6;
@@ -1799,11 +1827,15 @@ __global__ void __launch_bounds__(256) k_colnorm(const SliceDesc* __restrict__ d
 template <int MODE>
 __global__ void __launch_bounds__(256) k_bp2(const SliceDesc* __restrict__ desc, float* __restrict__ sl,
                                              const float* __restrict__ V, const float* __restrict__ Bb,
-                                             const float* __restrict__ fval, const int* __restrict__ rcount) {
+                                             const float* __restrict__ fval, const int* __restrict__ rcount, int tdim,
+                                             int ns) {
   __shared__ MfmaSmem sm;
-  const SliceDesc d = desc[blockIdx.z];
-  const int r = rcount[blockIdx.z], n = d.n1, h = d.h, w = d.w;
-  const int m0 = blockIdx.y * kMT, n0 = blockIdx.x * kMT;
+  int tile, slice;
+  if (!xcd_tile_slice(tdim * tdim, ns, tile, slice)) return;
+  const int bx = tile % tdim, by = tile / tdim;
+  const SliceDesc d = desc[slice];
+  const int r = rcount[slice], n = d.n1, h = d.h, w = d.w;
+  const int m0 = by * kMT, n0 = bx * kMT;
   if (m0 >= h || n0 >= w) return;
   float* er = sl + d.a_off;
   float* ei = er + (int64_t)h * w;
@@ -2119,9 +2151,11 @@ void launch_svt_gram(const SvtLaunch& L, hipStream_t s) {
   const int ns = L.n_slices, n = L.max_n1;
   const int TT = (n + kMT - 1) / kMT;
   if (L.precision == LRSTV_SPLIT_BF16)
-    hipLaunchKernelGGL(k_gram<kBF16x3>, dim3(TT * (TT + 1) / 2, ns), dim3(256), 0, s, L.desc, L.slices, L.gram);
+    hipLaunchKernelGGL(k_gram<kBF16x3>, dim3(xcd_grid(TT * (TT + 1) / 2, ns)), dim3(256), 0, s, L.desc, L.slices, L.gram,
+                       TT * (TT + 1) / 2, ns);
   else
-    hipLaunchKernelGGL(k_gram<kF32>, dim3(TT * (TT + 1) / 2, ns), dim3(256), 0, s, L.desc, L.slices, L.gram);
+    hipLaunchKernelGGL(k_gram<kF32>, dim3(xcd_grid(TT * (TT + 1) / 2, ns)), dim3(256), 0, s, L.desc, L.slices, L.gram,
+                       TT * (TT + 1) / 2, ns);
 }
 
 void prepare_svt(int max_n1) {
@@ -2186,9 +2220,11 @@ static void svt_after_tridiag(const SvtLaunch& L, hipStream_t s, StageTimer& T) 
   // B: tall h x r, wide r x w -> tiles over (max(n, m)) both ways
   T.begin(ST_BP1);
   if (bf)
-    hipLaunchKernelGGL(k_bp1<kBF16x3>, dim3(TM, TM, ns), dim3(256), 0, s, L.desc, L.slices, L.V, L.B, L.rcount);
+    hipLaunchKernelGGL(k_bp1<kBF16x3>, dim3(xcd_grid(TM * TM, ns)), dim3(256), 0, s, L.desc, L.slices, L.V, L.B,
+                       L.rcount, TM, ns);
   else
-    hipLaunchKernelGGL(k_bp1<kF32>, dim3(TM, TM, ns), dim3(256), 0, s, L.desc, L.slices, L.V, L.B, L.rcount);
+    hipLaunchKernelGGL(k_bp1<kF32>, dim3(xcd_grid(TM * TM, ns)), dim3(256), 0, s, L.desc, L.slices, L.V, L.B, L.rcount,
+                       TM, ns);
   T.end(ST_BP1);
   T.begin(ST_COLNORM);
   hipLaunchKernelGGL(k_colnorm, dim3((n + 63) / 64, ns), dim3(256), 0, s, L.desc, L.B, L.fval, L.rcount, L.mu, L.alpha,
@@ -2196,11 +2232,11 @@ static void svt_after_tridiag(const SvtLaunch& L, hipStream_t s, StageTimer& T) 
   T.end(ST_COLNORM);
   T.begin(ST_BP2);
   if (bf)
-    hipLaunchKernelGGL(k_bp2<kBF16x3>, dim3(TM, TM, ns), dim3(256), 0, s, L.desc, L.slices, L.V, L.B, L.fval,
-                       L.rcount);
+    hipLaunchKernelGGL(k_bp2<kBF16x3>, dim3(xcd_grid(TM * TM, ns)), dim3(256), 0, s, L.desc, L.slices, L.V, L.B,
+                       L.fval, L.rcount, TM, ns);
   else
-    hipLaunchKernelGGL(k_bp2<kF32>, dim3(TM, TM, ns), dim3(256), 0, s, L.desc, L.slices, L.V, L.B, L.fval,
-                       L.rcount);
+    hipLaunchKernelGGL(k_bp2<kF32>, dim3(xcd_grid(TM * TM, ns)), dim3(256), 0, s, L.desc, L.slices, L.V, L.B,
+                       L.fval, L.rcount, TM, ns);
   T.end(ST_BP2);
 }
 
@@ -2219,9 +2255,11 @@ void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm, const SvtSpli
   const int TT = (n + kMT - 1) / kMT;
   T.begin(ST_GRAM);
   if (bf)
-    hipLaunchKernelGGL(k_gram<kBF16x3>, dim3(TT * (TT + 1) / 2, ns), dim3(256), 0, s, L.desc, L.slices, L.gram);
+    hipLaunchKernelGGL(k_gram<kBF16x3>, dim3(xcd_grid(TT * (TT + 1) / 2, ns)), dim3(256), 0, s, L.desc, L.slices, L.gram,
+                       TT * (TT + 1) / 2, ns);
   else
-    hipLaunchKernelGGL(k_gram<kF32>, dim3(TT * (TT + 1) / 2, ns), dim3(256), 0, s, L.desc, L.slices, L.gram);
+    hipLaunchKernelGGL(k_gram<kF32>, dim3(xcd_grid(TT * (TT + 1) / 2, ns)), dim3(256), 0, s, L.desc, L.slices, L.gram,
+                       TT * (TT + 1) / 2, ns);
   T.end(ST_GRAM);
   // per-stage timing keeps one stream (every stage times all the slices)
   if (sp && sp->s2 && sp->first > 0 && sp->first < ns && !T.on) {
@@ -2255,7 +2293,8 @@ void launch_svt_vjp(const SvtVjpLaunch& J, hipStream_t s) {
   if (ns == 0) return;
   const int TT = (n + kMT - 1) / kMT, TM = (m + kMT - 1) / kMT;
   // full eigendecomposition of every Gram (thresh < 0: all eigenpairs)
-  hipLaunchKernelGGL(k_gram<kF32>, dim3(TT * (TT + 1) / 2, ns), dim3(256), 0, s, L.desc, L.slices, L.gram);
+  hipLaunchKernelGGL(k_gram<kF32>, dim3(xcd_grid(TT * (TT + 1) / 2, ns)), dim3(256), 0, s, L.desc, L.slices, L.gram,
+                       TT * (TT + 1) / 2, ns);
   launch_tridiag(L, s);
   const size_t eig_lds = (size_t)5 * n * sizeof(double) + (size_t)(n + 1 + 1024) * sizeof(int);
   hipLaunchKernelGGL(k_trieig<0>, dim3((n + 63) / 64, ns), dim3(256), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount,
@@ -2263,8 +2302,10 @@ void launch_svt_vjp(const SvtVjpLaunch& J, hipStream_t s) {
   launch_trivec(L, s, eig_lds, nullptr, -1.f);
   launch_backtrans(L, s);
   // B = M V, C = D V (or U^H M, U^H D)
-  hipLaunchKernelGGL(k_bp1<kF32>, dim3(TM, TM, ns), dim3(256), 0, s, L.desc, L.slices, L.V, L.B, L.rcount);
-  hipLaunchKernelGGL(k_bp1<kF32>, dim3(TM, TM, ns), dim3(256), 0, s, L.desc, J.dsl, L.V, J.C, L.rcount);
+  hipLaunchKernelGGL(k_bp1<kF32>, dim3(xcd_grid(TM * TM, ns)), dim3(256), 0, s, L.desc, L.slices, L.V, L.B, L.rcount,
+                       TM, ns);
+  hipLaunchKernelGGL(k_bp1<kF32>, dim3(xcd_grid(TM * TM, ns)), dim3(256), 0, s, L.desc, J.dsl, L.V, J.C, L.rcount, TM,
+                     ns);
   hipLaunchKernelGGL(k_vjp_sigma, dim3(n, ns), dim3(256), 0, s, L.desc, L.B, J.C, J.sig, L.fval, J.acon, L.rcount,
                      L.mu, L.alpha, L.thresh);
   hipLaunchKernelGGL(k_vjp_w<kF32>, dim3(TT, TT, ns), dim3(256), 0, s, L.desc, L.B, J.C, J.sig, J.W, L.rcount,
@@ -2272,7 +2313,8 @@ void launch_svt_vjp(const SvtVjpLaunch& J, hipStream_t s) {
   hipLaunchKernelGGL(k_vjp_r<kF32>, dim3(TM, TM, ns), dim3(256), 0, s, L.desc, L.B, J.C, J.W, L.fval, J.R,
                      L.rcount);
   // result (R V^H or U R) over the direction slices
-  hipLaunchKernelGGL(k_bp2<kF32>, dim3(TM, TM, ns), dim3(256), 0, s, L.desc, J.dsl, L.V, J.R, J.ones, L.rcount);
+  hipLaunchKernelGGL(k_bp2<kF32>, dim3(xcd_grid(TM * TM, ns)), dim3(256), 0, s, L.desc, J.dsl, L.V, J.R, J.ones,
+                     L.rcount, TM, ns);
 }
 
 }  // namespace lrstv
