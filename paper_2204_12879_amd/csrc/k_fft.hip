@@ -498,15 +498,18 @@ __global__ void __launch_bounds__(kTriCols * kTriChunks, MAXL <= 16 ? 4 : 2) k_t
 //   X (2s x hw) = F (2s x b) A (b x hw),  s = b/2 + 1,
 //   F[2k][j] = cos(2 pi j k / b),  F[2k+1][j] = -sin(2 pi j k / b),
 // so row 2k / 2k+1 of X is the re / im plane of Fourier slice k: the planar
-// slice layout [t][k][re|im][hw] is X itself.  F is generated while staging
-// from an LDS table of cos / sin(2 pi m / b) (index j k mod b, advanced
-// incrementally).  A block takes a column strip of A and walks its row tiles
-// itself, so that the strip is fetched from HBM once and re-read from the
-// block's own L2 (consecutive blocks run on different XCDs).
+// slice layout [t][k][re|im][hw] is X itself.
+//
+// A block (4 waves, v_mfma_f32_32x32x2f32) takes a 64-column strip of A and
+// up to three 64-row tiles of X at once: the strip is staged through LDS in
+// chunks of 32 rows once and feeds all three tiles, and F is never staged:
+// each lane forms its operand F[m][j] from an LDS table of cos / sin
+// (2 pi i / b), its index (m/2) j mod b advanced by (m/2) 2 mod b per step.
+constexpr int kDftRowTiles = 3;
 LRSTV_DEV void band_dft_body(int bid, int nblk, const float* __restrict__ A, int64_t a_stride, int n_t,
-                                                  float* __restrict__ out, int hw, int b) {
-  __shared__ MfmaSmemR sm;
+                             float* __restrict__ out, int hw, int b) {
   __shared__ float ct[LRSTV_MAX_SIDE_DEV], st[LRSTV_MAX_SIDE_DEV];
+  __shared__ float sB[kKC][kMT + 4];
   for (int m = threadIdx.x; m < b; m += blockDim.x) {
     double sv, cv;
     sincospi(2.0 * (double)m / (double)b, &sv, &cv);
@@ -517,38 +520,69 @@ LRSTV_DEV void band_dft_body(int bid, int nblk, const float* __restrict__ A, int
   const int M = 2 * (b / 2 + 1);
   const int TM = (M + kMT - 1) / kMT, TN = (hw + kMT - 1) / kMT;
   const int nstrips = n_t * TN;
-  const int wv = threadIdx.x >> 6;
-  for (int strip = bid; strip < nstrips; strip += nblk)
-  for (int tm = 0; tm < TM; ++tm) {
-    const int t = strip / TN, tn = strip - t * TN;
-    const int m0 = tm * kMT, n0 = tn * kMT;
-    const float* src = A + t * a_stride;
-    float* dst = out + (int64_t)t * M * hw;
-    const bool active = m0 + 32 * (wv >> 1) < M && n0 + 32 * (wv & 1) < hw;
-    auto fa = [&](int m, int k0, float* v) {
-      const int kk = m >> 1;
-      const bool im = m & 1;
-      int idx = (int)((k0 * kk) % b);
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, wy = wv >> 1, wx = wv & 1, li = lane & 31, lk = lane >> 5;
+  const int sc = t & 63, sr = t >> 6;   // staging: column sc, rows sr + 4 e
+  for (int strip = bid; strip < nstrips; strip += nblk) {
+    const int tt = strip / TN, tn = strip - tt * TN, n0 = tn * kMT;
+    const float* src = A + tt * a_stride;
+    float* dst = out + (int64_t)tt * M * hw;
+    const bool colok = n0 + sc < hw;
+    for (int tg = 0; tg < TM; tg += kDftRowTiles) {
+      f32x16 acc[kDftRowTiles];
+      int idx[kDftRowTiles], stp[kDftRowTiles];
+      bool rok[kDftRowTiles], odd[kDftRowTiles];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const bool ok = m < M && k0 + e < b;
-        v[e] = ok ? (im ? -st[idx] : ct[idx]) : 0.f;
-        idx += kk;
-        if (idx >= b) idx -= b;
+      for (int q = 0; q < kDftRowTiles; ++q) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[q][e] = 0.f;
+        const int m = (tg + q) * kMT + 32 * wy + li, kq = m >> 1;
+        rok[q] = m < M;
+        odd[q] = m & 1;
+        idx[q] = (int)(((int64_t)kq * lk) % b);      // j = lk at the first step
+        stp[q] = (int)(((int64_t)2 * kq) % b);
       }
-    };
-    auto fb = [&](int k0, int n, float* v) {
+      float pre[8];
+      auto fetch = [&](int k0) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = (k0 + e < b && n < hw) ? src[(int64_t)(k0 + e) * hw + n] : 0.f;
-    };
-    auto sto = [&](int m, int n, float v) {
-      if (m < M && n < hw) dst[(int64_t)m * hw + n] = v;
-    };
-    mfma_rtile<true, false>(m0, n0, b, fa, fb, sto, sm, active);
+        for (int e = 0; e < 8; ++e) {
+          const int k = k0 + sr + 4 * e;
+          pre[e] = (colok && k < b) ? src[(int64_t)k * hw + n0 + sc] : 0.f;
+        }
+      };
+      fetch(0);
+      for (int k0 = 0; k0 < b; k0 += kKC) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) sB[sr + 4 * e][sc] = pre[e];
+        __syncthreads();
+        if (k0 + kKC < b) fetch(k0 + kKC);
+#pragma unroll 4
+        for (int kk = 0; kk < kKC / 2; ++kk) {
+          const int j = k0 + 2 * kk + lk;
+          const float bv = sB[2 * kk + lk][32 * wx + li];
+#pragma unroll
+          for (int q = 0; q < kDftRowTiles; ++q) {
+            const float f = odd[q] ? -st[idx[q]] : ct[idx[q]];
+            const float av = (rok[q] && j < b) ? f : 0.f;
+            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[q], 0, 0, 0);
+            idx[q] += stp[q];
+            if (idx[q] >= b) idx[q] -= b;
+          }
+        }
+        __syncthreads();
+      }
+      const int n = n0 + 32 * wx + li;
+#pragma unroll
+      for (int q = 0; q < kDftRowTiles; ++q)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int m = (tg + q) * kMT + 32 * wy + 8 * (e >> 2) + 4 * lk + (e & 3);
+          if (m < M && n < hw) dst[(int64_t)m * hw + n] = acc[q][e];
+        }
+    }
   }
 }
 
-__global__ void __launch_bounds__(256) k_band_dft(const float* __restrict__ A, int64_t a_stride, int n_t,
+__global__ void __launch_bounds__(256, 4) k_band_dft(const float* __restrict__ A, int64_t a_stride, int n_t,
                                                   float* __restrict__ out, int hw, int b) {
   band_dft_body(blockIdx.x, gridDim.x, A, a_stride, n_t, out, hw, b);
 }
@@ -696,7 +730,7 @@ __global__ void __launch_bounds__(kTriCols * kTriChunks, MAXL <= 16 ? 4 : 2) k_t
 }
 
 // A: component stride a_stride from the cube's offset; slices at slice_base
-__global__ void __launch_bounds__(256) k_band_dft_batch(BatchTab bt, const float* __restrict__ A, int64_t a_stride,
+__global__ void __launch_bounds__(256, 4) k_band_dft_batch(BatchTab bt, const float* __restrict__ A, int64_t a_stride,
                                                         float* __restrict__ slices) {
   const CubeSel q = select_cube(bt);
   const CubeGeo g = uniform_geo(bt.geo, q.c);
