@@ -316,6 +316,107 @@ __global__ void __launch_bounds__(kFftHThreads) k_fft_h(float2* __restrict__ spe
   fft_h_body(blockIdx.x, gridDim.x, sm, spec, h, wc, b, cw, sign);
 }
 
+// ------------------------------------------------- register FFT along h ---
+// For h = P Q with P, Q in {8, 16} (h = 64, 128, 256) the column transforms
+// run in registers: with n = Q p + q and k = k1 + P k2,
+//   X[k1 + P k2] = sum_q w_Q^(q k2) w_h^(q k1) sum_p x[Q p + q] w_P^(p k1),
+// thread (column, q) forms the inner P-point DFT of its column's elements
+// Q p + q, multiplies by w_h^(q k1) and writes them to LDS; after one barrier
+// thread (column, k1) reads the Q values y[q][k1] and forms the outer
+// Q-point DFT, writing X[k1 + P k2].  Two passes over LDS per transform
+// instead of one per Stockham stage.  The in-register DFTs split R = A B the
+// same way (down to radix 2).  Unnormalised; S = -1 forward, +1 inverse.
+__constant__ constexpr float kCos16[16] = {1.f, 0.9238795325f, 0.7071067812f, 0.3826834324f, 0.f, -0.3826834324f,
+                                           -0.7071067812f, -0.9238795325f, -1.f, -0.9238795325f, -0.7071067812f,
+                                           -0.3826834324f, 0.f, 0.3826834324f, 0.7071067812f, 0.9238795325f};
+__constant__ constexpr float kSin16[16] = {0.f, 0.3826834324f, 0.7071067812f, 0.9238795325f, 1.f, 0.9238795325f,
+                                           0.7071067812f, 0.3826834324f, 0.f, -0.3826834324f, -0.7071067812f,
+                                           -0.9238795325f, -1.f, -0.9238795325f, -0.7071067812f, -0.3826834324f};
+
+template <int R, int S>
+LRSTV_DEV void dft_reg(float2 (&v)[R]) {
+  if constexpr (R == 2) {
+    const float2 a = v[0];
+    v[0] = cadd(a, v[1]);
+    v[1] = csub(a, v[1]);
+  } else {
+    constexpr int A = (R == 4) ? 2 : 4, B = R / A;   // n = B n1 + n2, k = k1 + A k2
+    float2 t[B][A];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) {
+      float2 u[A];
+#pragma unroll
+      for (int n1 = 0; n1 < A; ++n1) u[n1] = v[B * n1 + n2];
+      dft_reg<A, S>(u);
+#pragma unroll
+      for (int k1 = 0; k1 < A; ++k1) {
+        const int m = (n2 * k1) % R;   // w_R^(n2 k1)
+        t[n2][k1] = m == 0 ? u[k1] : cmul(u[k1], make_float2(kCos16[m * (16 / R)], S * kSin16[m * (16 / R)]));
+      }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+      float2 u[B];
+#pragma unroll
+      for (int n2 = 0; n2 < B; ++n2) u[n2] = t[n2][k1];
+      dft_reg<B, S>(u);
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) v[k1 + A * k2] = u[k2];
+    }
+  }
+}
+
+constexpr int kFftRegCols = 16;   // columns per block (one 128-byte row segment)
+template <int P, int Q>
+constexpr int fft_reg_threads() { return kFftRegCols * (P > Q ? P : Q); }
+
+template <int P, int Q, int S>
+LRSTV_DEV void fft_h_reg_body(int bid, int nblk, float2* __restrict__ spec, int wc, int b) {
+  constexpr int N = P * Q, C = kFftRegCols;
+  __shared__ float2 Y[P][Q][C];
+  __shared__ float2 tw[N];   // w_N^m
+  for (int m = threadIdx.x; m < N; m += blockDim.x) {
+    double sv, cv;
+    sincospi(2.0 * (double)m / (double)N, &sv, &cv);
+    tw[m] = make_float2((float)cv, (float)(S * sv));
+  }
+  const int c = threadIdx.x % C, rr = threadIdx.x / C;
+  const int64_t ncol = (int64_t)b * wc, plane = (int64_t)N * wc;
+  const int64_t nchunk = (ncol + C - 1) / C;
+  for (int64_t blk = bid; blk < nchunk; blk += nblk) {
+    const int64_t g = blk * C + c;
+    const bool ok = g < ncol;
+    const int64_t j = ok ? g / wc : 0;
+    float2* base = spec + j * plane + (ok ? g - j * wc : 0);
+    __syncthreads();   // the twiddle table (first pass) and the previous pass's reads of Y
+    if (rr < Q) {
+      float2 v[P];
+#pragma unroll
+      for (int p = 0; p < P; ++p) v[p] = ok ? base[(int64_t)(Q * p + rr) * wc] : make_float2(0.f, 0.f);
+      dft_reg<P, S>(v);
+#pragma unroll
+      for (int k1 = 0; k1 < P; ++k1) Y[k1][rr][c] = k1 == 0 ? v[0] : cmul(v[k1], tw[rr * k1]);
+    }
+    __syncthreads();
+    if (rr < P) {
+      float2 u[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) u[q] = Y[rr][q][c];
+      dft_reg<Q, S>(u);
+      if (ok) {
+#pragma unroll
+        for (int k2 = 0; k2 < Q; ++k2) base[(int64_t)(rr + P * k2) * wc] = u[k2];
+      }
+    }
+  }
+}
+
+template <int P, int Q, int S>
+__global__ void __launch_bounds__(kFftRegCols * (P > Q ? P : Q)) k_fft_h_reg(float2* __restrict__ spec, int wc, int b) {
+  fft_h_reg_body<P, Q, S>(blockIdx.x, gridDim.x, spec, wc, b);
+}
+
+
 // Periodic tridiagonal solve along the bands for every (k_h, k_w).
 //
 // A block takes kTriCols columns with consecutive k_w (each band row of the
@@ -717,6 +818,7 @@ __global__ void __launch_bounds__(kFftHThreads) k_fft_h_batch(BatchTab bt, float
   extern __shared__ float2 sm[];
   const CubeSel q = select_cube(bt);
   const CubeGeo g = uniform_geo(bt.geo, q.c);
+  if (fft_h_reg_bit(g.h) != 0) return;   // that cube runs the register FFT
   fft_h_body(q.bid, q.nblk, sm, spec + g.spec_off, g.h, g.w / 2 + 1, g.b, g.cw_h, sign);
 }
 
@@ -778,6 +880,33 @@ void launch_irfft_w(const float2* spec, float* Z, int h, int w, int b, double* p
   hipLaunchKernelGGL(k_irfft_w, dim3(LRSTV_PARTS), dim3(kIrfftThreads), lds, s, spec, Z, nrows, w, nb, scale, part);
 }
 
+template <int P, int Q, int S>
+__global__ void __launch_bounds__(kFftRegCols * (P > Q ? P : Q)) k_fft_h_reg_batch(BatchTab bt, float2* __restrict__ spec) {
+  const CubeSel q = select_cube(bt);
+  const CubeGeo g = uniform_geo(bt.geo, q.c);
+  if (g.h != P * Q) return;   // another length (or the Stockham path) takes that cube
+  fft_h_reg_body<P, Q, S>(q.bid, q.nblk, spec + g.spec_off, g.w / 2 + 1, g.b);
+}
+
+// Launches the register FFT when h is one of its lengths; false otherwise.
+template <int S>
+static bool launch_fft_h_reg(float2* spec, int h, int wc, int b, int grid, const BatchTab* bt, hipStream_t s) {
+#define LRSTV_FFT_REG(P, Q)                                                                                   \
+  if (h == P * Q) {                                                                                           \
+    if (bt)                                                                                                   \
+      hipLaunchKernelGGL((k_fft_h_reg_batch<P, Q, S>), dim3(bt->nblocks), dim3(fft_reg_threads<P, Q>()), 0, s, \
+                         *bt, spec);                                                                          \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_fft_h_reg<P, Q, S>), dim3(grid), dim3(fft_reg_threads<P, Q>()), 0, s, spec, wc, b); \
+    return true;                                                                                              \
+  }
+  LRSTV_FFT_REG(16, 16)
+  LRSTV_FFT_REG(16, 8)
+  LRSTV_FFT_REG(8, 8)
+#undef LRSTV_FFT_REG
+  return false;
+}
+
 // Dynamic LDS above the 64 KB default is granted once per process (before any
 // capture: the handle's set-up and the stand-alone Z-solve call this).
 static size_t g_fft_h_granted = 65536;
@@ -794,6 +923,8 @@ void launch_fft_h(float2* spec, int h, int w, int b, int sign, hipStream_t s) {
   const int cw = cols_cw(h);
   const int64_t g = ((int64_t)b * wc + cw - 1) / cw;
   const int grid = (int)(g < 8192 ? g : 8192);
+  if (sign < 0 ? launch_fft_h_reg<-1>(spec, h, wc, b, grid, nullptr, s) : launch_fft_h_reg<1>(spec, h, wc, b, grid, nullptr, s))
+    return;
   prepare_fft_h(fft_h_lds_bytes(h, cw));
   hipLaunchKernelGGL(k_fft_h, dim3(grid), dim3(kFftHThreads), fft_h_lds_bytes(h, cw), s, spec, h, wc, b, cw, sign);
 }
@@ -879,7 +1010,15 @@ void launch_irfft_w_batch(const BatchTab& bt, const float2* spec, float* Z, doub
 }
 
 void launch_fft_h_batch(const BatchTab& bt, float2* spec, int sign, hipStream_t s) {
-  hipLaunchKernelGGL(k_fft_h_batch, dim3(bt.nblocks), dim3(kFftHThreads), bt.lds_h, s, bt, spec, sign);
+  // every cube takes the path of its own h (as it would alone): one launch
+  // per register length present, one Stockham launch for the other cubes
+  for (int h : {64, 128, 256})
+    if (bt.reg_h_mask & fft_h_reg_bit(h)) {
+      if (sign < 0) launch_fft_h_reg<-1>(spec, h, 0, 0, 0, &bt, s);
+      else launch_fft_h_reg<1>(spec, h, 0, 0, 0, &bt, s);
+    }
+  if (bt.stockham_h)
+    hipLaunchKernelGGL(k_fft_h_batch, dim3(bt.nblocks), dim3(kFftHThreads), bt.lds_h, s, bt, spec, sign);
 }
 
 void launch_tri_b_batch(const BatchTab& bt, float2* spec, const double wts[3], const double* mu, hipStream_t s) {

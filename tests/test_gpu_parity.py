@@ -49,6 +49,9 @@ def say(*a):
     ((17, 10, 12), (1.0, 1.0, 8.0), 0.3),      # one-element and empty band chunks, r near 1
     ((256, 4, 66), (0.5, 1.0, 2.0), 1.0),      # full band chunks, ragged column groups
     ((300, 6, 5), (1.0, 1.0, 1.0), 1.5),       # more than 256 bands (longer chunks)
+    ((9, 64, 20), (1.0, 0.7, 1.5), 2.0),       # h = 64, 128, 256: the register FFT along h
+    ((4, 128, 33), (1.0, 1.0, 1.0), 0.5),
+    ((3, 256, 18), (0.5, 1.0, 1.0), 1.0),
 ])
 def test_zsolve_matches_oracle(shape, wts, mu):
     L = _lib()
