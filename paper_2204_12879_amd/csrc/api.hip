@@ -283,7 +283,7 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
   std::vector<CubeGeo> geo(nc);
   std::vector<int> bstart((size_t)PH_COUNT * (nc + 1), 0);
   size_t lds_w = 0, lds_h = 0;
-  int max_b = 0, reg_h_mask = 0, stockham_h = 0;
+  int max_b = 0, reg_h_mask = 0, stockham_h = 0, reg_w_mask = 0, stockham_w = 0;
   for (int c = 0; c < nc; ++c) {
     const CubeInfo& ci = H->cubes[c];
     CubeGeo& g = geo[c];
@@ -302,6 +302,8 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
     if (ci.b > max_b) max_b = ci.b;
     reg_h_mask |= fft_h_reg_bit(ci.h);
     if (fft_h_reg_bit(ci.h) == 0) stockham_h = 1;
+    reg_w_mask |= fft_h_reg_bit(ci.w);
+    if (fft_h_reg_bit(ci.w) == 0) stockham_w = 1;
     for (int ph = 0; ph < PH_COUNT; ++ph)
       bstart[(size_t)ph * (nc + 1) + c + 1] = bstart[(size_t)ph * (nc + 1) + c] + phase_blocks(ph, ci.h, ci.w, ci.b);
   }
@@ -316,6 +318,8 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
     bt.max_b = max_b;
     bt.reg_h_mask = reg_h_mask;
     bt.stockham_h = stockham_h;
+    bt.reg_w_mask = reg_w_mask;
+    bt.stockham_w = stockham_w;
   }
   hipError_t e = hipMemcpyAsync(H->desc, H->sl.desc.data(), H->sl.desc.size() * sizeof(SliceDesc),
                                 hipMemcpyHostToDevice, H->stream);

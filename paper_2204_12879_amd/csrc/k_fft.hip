@@ -417,6 +417,149 @@ __global__ void __launch_bounds__(kFftRegCols * (P > Q ? P : Q)) k_fft_h_reg(flo
 }
 
 
+// ---------------------------------------------- register real FFTs along w ---
+// Two real rows a, b of length w = P Q (64, 128, 256) as one complex
+// transform z = a + i b, computed as the h transform above (16 threads per
+// row pair).  Forward: A[k] = (Z[k] + conj Z[w-k]) / 2,
+// B[k] = (Z[k] - conj Z[w-k]) / (2 i) for k <= w/2 (Z goes through LDS for the
+// mirrored index).  Inverse: Z[k] = A[k] + i B[k] with A[w-k] = conj A[k];
+// a = Re z, b = Im z, times `scale`, into Z, with the FP64 partial of
+// (Z_new - Z_old)^2 when `part` is set.
+constexpr int kPairThreads = 16;
+template <int PPB, int P, int Q, int S>
+struct RowFft {
+  static constexpr int N = P * Q;
+  float2 Y[PPB][N];   // the pair's y[q][k1] at k1 * Q + q, then Z[k] at k
+  float2 tw[N];
+};
+
+template <int P, int Q, int S, int PPB>
+LRSTV_DEV void row_fft_inner(RowFft<PPB, P, Q, S>& sm, int f, int r, const float2 (&in)[P], float2 (&out)[Q]) {
+  // first pass (threads r < Q): in = z[Q p + r]; second (threads r < P): out = Z[r + P k2]
+  constexpr int N = P * Q;
+  if (r < Q) {
+    float2 v[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) v[p] = in[p];
+    dft_reg<P, S>(v);
+#pragma unroll
+    for (int k1 = 0; k1 < P; ++k1) sm.Y[f][k1 * Q + r] = k1 == 0 ? v[0] : cmul(v[k1], sm.tw[r * k1]);
+  }
+  __syncthreads();
+  if (r < P) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) out[q] = sm.Y[f][r * Q + q];
+    dft_reg<Q, S>(out);
+  }
+  (void)N;
+}
+
+template <int P, int Q, int PPB>
+LRSTV_DEV void rfft_w_reg_body(int bid, int nblk, const float* __restrict__ T, float2* __restrict__ spec, int nrows) {
+  constexpr int N = P * Q, wc = N / 2 + 1;
+  __shared__ RowFft<PPB, P, Q, -1> sm;
+  for (int m = threadIdx.x; m < N; m += blockDim.x) {
+    double sv, cv;
+    sincospi(2.0 * (double)m / (double)N, &sv, &cv);
+    sm.tw[m] = make_float2((float)cv, (float)(-sv));
+  }
+  const int f = threadIdx.x / kPairThreads, r = threadIdx.x % kPairThreads;
+  const int npairs = (nrows + 1) / 2;
+  for (int pb = bid * PPB; pb < npairs; pb += nblk * PPB) {
+    const int pair = pb + f, ra = 2 * pair, rb = ra + 1;
+    const bool oka = pair < npairs, okb = rb < nrows;
+    float2 in[P], out[Q];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int n = Q * p + r;
+      in[p] = make_float2(oka && r < Q ? T[(int64_t)ra * N + n] : 0.f, okb && r < Q ? T[(int64_t)rb * N + n] : 0.f);
+    }
+    __syncthreads();   // twiddles ready, previous pair block's reads of Y done
+    row_fft_inner<P, Q, -1, PPB>(sm, f, r, in, out);
+    __syncthreads();
+    if (r < P) {
+#pragma unroll
+      for (int k2 = 0; k2 < Q; ++k2) sm.Y[f][r + P * k2] = out[k2];
+    }
+    __syncthreads();
+    for (int k = r; k < wc; k += kPairThreads) {
+      const float2 zk = sm.Y[f][k];
+      const float2 zc = cconj(sm.Y[f][(N - k) % N]);
+      const float2 A = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
+      const float2 D = csub(zk, zc);
+      const float2 B = make_float2(0.5f * D.y, -0.5f * D.x);
+      if (oka) spec[(int64_t)ra * wc + k] = A;
+      if (okb) spec[(int64_t)rb * wc + k] = B;
+    }
+  }
+}
+
+template <int P, int Q, int PPB>
+LRSTV_DEV void irfft_w_reg_body(int bid, int nblk, const float2* __restrict__ spec, float* __restrict__ Z, int nrows,
+                                float scale, double* __restrict__ part) {
+  constexpr int N = P * Q, wc = N / 2 + 1;
+  __shared__ RowFft<PPB, P, Q, 1> sm;
+  __shared__ double red[PPB * kPairThreads / 64];
+  for (int m = threadIdx.x; m < N; m += blockDim.x) {
+    double sv, cv;
+    sincospi(2.0 * (double)m / (double)N, &sv, &cv);
+    sm.tw[m] = make_float2((float)cv, (float)sv);
+  }
+  const int f = threadIdx.x / kPairThreads, r = threadIdx.x % kPairThreads;
+  const int npairs = (nrows + 1) / 2;
+  double acc = 0.0;
+  for (int pb = bid * PPB; pb < npairs; pb += nblk * PPB) {
+    const int pair = pb + f, ra = 2 * pair, rb = ra + 1;
+    const bool oka = pair < npairs, okb = rb < nrows;
+    float2 in[P], out[Q];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int n = Q * p + r;
+      const bool lo = n <= N / 2;
+      const int kk = lo ? n : N - n;
+      float2 X = (oka && r < Q) ? spec[(int64_t)ra * wc + kk] : make_float2(0.f, 0.f);
+      float2 Yb = (okb && r < Q) ? spec[(int64_t)rb * wc + kk] : make_float2(0.f, 0.f);
+      if (!lo) {
+        X = cconj(X);
+        Yb = cconj(Yb);
+      }
+      in[p] = make_float2(X.x - Yb.y, X.y + Yb.x);   // X + i Y
+    }
+    __syncthreads();
+    row_fft_inner<P, Q, 1, PPB>(sm, f, r, in, out);
+    if (r < P) {
+#pragma unroll
+      for (int k2 = 0; k2 < Q; ++k2) {
+        const int x = r + P * k2;
+        if (oka) {
+          const int64_t q = (int64_t)ra * N + x;
+          const float zn = out[k2].x * scale;
+          if (part) {
+            const double d = (double)zn - (double)Z[q];
+            acc += d * d;
+          }
+          Z[q] = zn;
+        }
+        if (okb) {
+          const int64_t q = (int64_t)rb * N + x;
+          const float zn = out[k2].y * scale;
+          if (part) {
+            const double d = (double)zn - (double)Z[q];
+            acc += d * d;
+          }
+          Z[q] = zn;
+        }
+      }
+    }
+  }
+  if (part) {
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) part[R_DUAL_Z * LRSTV_PARTS + bid] = acc;
+  }
+}
+
+constexpr int kRfftPairs = 16, kIrfftPairs = 32;   // row pairs per block
+
 // Periodic tridiagonal solve along the bands for every (k_h, k_w).
 //
 // A block takes kTriCols columns with consecutive k_w (each band row of the
@@ -802,6 +945,7 @@ __global__ void __launch_bounds__(256) k_rfft_w_batch(BatchTab bt, const float* 
   extern __shared__ float2 sm[];
   const CubeSel q = select_cube(bt);
   const CubeGeo g = uniform_geo(bt.geo, q.c);
+  if (fft_h_reg_bit(g.w) != 0) return;   // that cube runs the register transform
   rfft_w_body(q.bid, q.nblk, sm, T + g.off, spec + g.spec_off, g.h * g.b, g.w, g.nb_w);
 }
 
@@ -810,6 +954,7 @@ __global__ void __launch_bounds__(kIrfftThreads) k_irfft_w_batch(BatchTab bt, co
   extern __shared__ float2 sm[];
   const int c = blockIdx.x / LRSTV_PARTS;
   const CubeGeo g = uniform_geo(bt.geo, c);
+  if (fft_h_reg_bit(g.w) != 0) return;   // that cube runs the register transform
   irfft_w_body(blockIdx.x - c * LRSTV_PARTS, LRSTV_PARTS, sm, spec + g.spec_off, Z + g.off, g.h * g.b, g.w, g.nb_w,
                1.0f / ((float)g.h * (float)g.w), part ? part + (int64_t)c * R_COUNT * LRSTV_PARTS : nullptr);
 }
@@ -865,7 +1010,80 @@ static int cols_cw(int h) {
   return cw;
 }
 
+template <int P, int Q>
+__global__ void __launch_bounds__(kRfftPairs * kPairThreads) k_rfft_w_reg(const float* __restrict__ T,
+                                                                       float2* __restrict__ spec, int nrows) {
+  rfft_w_reg_body<P, Q, kRfftPairs>(blockIdx.x, gridDim.x, T, spec, nrows);
+}
+template <int P, int Q>
+__global__ void __launch_bounds__(kRfftPairs * kPairThreads) k_rfft_w_reg_batch(BatchTab bt, const float* __restrict__ T,
+                                                                             float2* __restrict__ spec) {
+  const CubeSel q = select_cube(bt);
+  const CubeGeo g = uniform_geo(bt.geo, q.c);
+  if (g.w != P * Q) return;   // another length (or the Stockham path) takes that cube
+  rfft_w_reg_body<P, Q, kRfftPairs>(q.bid, q.nblk, T + g.off, spec + g.spec_off, g.h * g.b);
+}
+template <int P, int Q>
+__global__ void __launch_bounds__(kIrfftPairs * kPairThreads) k_irfft_w_reg(const float2* __restrict__ spec,
+                                                                         float* __restrict__ Z, int nrows, float scale,
+                                                                         double* __restrict__ part) {
+  irfft_w_reg_body<P, Q, kIrfftPairs>(blockIdx.x, gridDim.x, spec, Z, nrows, scale, part);
+}
+template <int P, int Q>
+__global__ void __launch_bounds__(kIrfftPairs * kPairThreads) k_irfft_w_reg_batch(BatchTab bt,
+                                                                               const float2* __restrict__ spec,
+                                                                               float* __restrict__ Z,
+                                                                               double* __restrict__ part) {
+  const int c = blockIdx.x / LRSTV_PARTS;
+  const CubeGeo g = uniform_geo(bt.geo, c);
+  if (g.w != P * Q) return;
+  irfft_w_reg_body<P, Q, kIrfftPairs>(blockIdx.x - c * LRSTV_PARTS, LRSTV_PARTS, spec + g.spec_off, Z + g.off,
+                                      g.h * g.b, 1.0f / ((float)g.h * (float)g.w),
+                                      part ? part + (int64_t)c * R_COUNT * LRSTV_PARTS : nullptr);
+}
+
+// The register w transforms for w = 64, 128, 256 (false for other widths).
+// Single cube when bt is null, else every cube of that width in the batch.
+static bool launch_rfft_w_reg(const float* T, float2* spec, int w, int nrows, const BatchTab* bt, hipStream_t s) {
+#define LRSTV_RFFT_REG(P, Q)                                                                                    \
+  if (w == P * Q) {                                                                                             \
+    if (bt) {                                                                                                   \
+      hipLaunchKernelGGL((k_rfft_w_reg_batch<P, Q>), dim3(bt->nblocks), dim3(kRfftPairs * kPairThreads), 0, s, *bt, \
+                         T, spec);                                                                              \
+    } else {                                                                                                    \
+      const int npairs = (nrows + 1) / 2, g = (npairs + kRfftPairs - 1) / kRfftPairs;                           \
+      hipLaunchKernelGGL((k_rfft_w_reg<P, Q>), dim3(g < 4096 ? g : 4096), dim3(kRfftPairs * kPairThreads), 0, s, T, \
+                         spec, nrows);                                                                          \
+    }                                                                                                           \
+    return true;                                                                                                \
+  }
+  LRSTV_RFFT_REG(16, 16)
+  LRSTV_RFFT_REG(16, 8)
+  LRSTV_RFFT_REG(8, 8)
+#undef LRSTV_RFFT_REG
+  return false;
+}
+static bool launch_irfft_w_reg(const float2* spec, float* Z, int w, int nrows, float scale, double* part,
+                               const BatchTab* bt, hipStream_t s) {
+#define LRSTV_IRFFT_REG(P, Q)                                                                                      \
+  if (w == P * Q) {                                                                                                \
+    if (bt)                                                                                                        \
+      hipLaunchKernelGGL((k_irfft_w_reg_batch<P, Q>), dim3(bt->nc * LRSTV_PARTS), dim3(kIrfftPairs * kPairThreads), 0, \
+                         s, *bt, spec, Z, part);                                                                   \
+    else                                                                                                           \
+      hipLaunchKernelGGL((k_irfft_w_reg<P, Q>), dim3(LRSTV_PARTS), dim3(kIrfftPairs * kPairThreads), 0, s, spec, Z,  \
+                         nrows, scale, part);                                                                      \
+    return true;                                                                                                   \
+  }
+  LRSTV_IRFFT_REG(16, 16)
+  LRSTV_IRFFT_REG(16, 8)
+  LRSTV_IRFFT_REG(8, 8)
+#undef LRSTV_IRFFT_REG
+  return false;
+}
+
 void launch_rfft_w(const float* T, float2* spec, int h, int w, int b, hipStream_t s) {
+  if (launch_rfft_w_reg(T, spec, w, h * b, nullptr, s)) return;
   const int nrows = h * b, nb = rows_nb(w);
   const size_t lds = (size_t)(2 * nb + 1) * w * sizeof(float2);
   int grid = (nrows + 2 * nb - 1) / (2 * nb);
@@ -877,8 +1095,10 @@ void launch_irfft_w(const float2* spec, float* Z, int h, int w, int b, double* p
   const int nrows = h * b, nb = rows_nb(w);
   const size_t lds = (size_t)(2 * nb + 1) * w * sizeof(float2);
   const float scale = 1.0f / ((float)h * (float)w);
+  if (launch_irfft_w_reg(spec, Z, w, nrows, scale, part, nullptr, s)) return;
   hipLaunchKernelGGL(k_irfft_w, dim3(LRSTV_PARTS), dim3(kIrfftThreads), lds, s, spec, Z, nrows, w, nb, scale, part);
 }
+
 
 template <int P, int Q, int S>
 __global__ void __launch_bounds__(kFftRegCols * (P > Q ? P : Q)) k_fft_h_reg_batch(BatchTab bt, float2* __restrict__ spec) {
@@ -1001,12 +1221,19 @@ int geo_rows_nb(int w) { return rows_nb(w); }
 int geo_cols_cw(int h) { return cols_cw(h); }
 size_t geo_fft_h_lds(int h) { return fft_h_lds_bytes(h, cols_cw(h)); }
 
+// As for the h transform, every cube takes the path of its own w.
 void launch_rfft_w_batch(const BatchTab& bt, const float* T, float2* spec, hipStream_t s) {
-  hipLaunchKernelGGL(k_rfft_w_batch, dim3(bt.nblocks), dim3(256), bt.lds_w, s, bt, T, spec);
+  for (int w : {64, 128, 256})
+    if (bt.reg_w_mask & fft_h_reg_bit(w)) launch_rfft_w_reg(T, spec, w, 0, &bt, s);
+  if (bt.stockham_w) hipLaunchKernelGGL(k_rfft_w_batch, dim3(bt.nblocks), dim3(256), bt.lds_w, s, bt, T, spec);
 }
 
 void launch_irfft_w_batch(const BatchTab& bt, const float2* spec, float* Z, double* part, hipStream_t s) {
-  hipLaunchKernelGGL(k_irfft_w_batch, dim3(bt.nc * LRSTV_PARTS), dim3(kIrfftThreads), bt.lds_w, s, bt, spec, Z, part);
+  for (int w : {64, 128, 256})
+    if (bt.reg_w_mask & fft_h_reg_bit(w)) launch_irfft_w_reg(spec, Z, w, 0, 0.f, part, &bt, s);
+  if (bt.stockham_w)
+    hipLaunchKernelGGL(k_irfft_w_batch, dim3(bt.nc * LRSTV_PARTS), dim3(kIrfftThreads), bt.lds_w, s, bt, spec, Z,
+                       part);
 }
 
 void launch_fft_h_batch(const BatchTab& bt, float2* spec, int sign, hipStream_t s) {

@@ -33,8 +33,9 @@ struct BatchTab {
   int max_b;               // largest band count over cubes
   int reg_h_mask;          // h FFT lengths present that run in registers (bit 0: 64, 1: 128, 2: 256)
   int stockham_h;          // 1 when some cube's h FFT runs through the LDS Stockham path
+  int reg_w_mask, stockham_w;   // the same for the w transforms
 };
-// Bit of an h FFT length that runs in registers (64, 128, 256), else 0.
+// Bit of an FFT length that runs in registers (64, 128, 256), else 0.
 __host__ __device__ inline int fft_h_reg_bit(int h) { return h == 64 ? 1 : h == 128 ? 2 : h == 256 ? 4 : 0; }
 // Base pointers of the packed batch (gradient-shaped arrays and A: 3
 // components spaced by ts).

@@ -52,6 +52,10 @@ def say(*a):
     ((9, 64, 20), (1.0, 0.7, 1.5), 2.0),       # h = 64, 128, 256: the register FFT along h
     ((4, 128, 33), (1.0, 1.0, 1.0), 0.5),
     ((3, 256, 18), (0.5, 1.0, 1.0), 1.0),
+    ((5, 21, 64), (1.0, 1.0, 2.0), 1.5),       # w = 64, 128, 256: register real FFTs along w
+    ((3, 17, 128), (1.0, 0.5, 1.0), 0.8),      # (odd row counts: the last row pair has one row)
+    ((2, 12, 256), (1.0, 1.0, 1.0), 3.0),
+    ((6, 64, 128), (1.0, 1.0, 1.0), 1.0),      # both axes in registers
 ])
 def test_zsolve_matches_oracle(shape, wts, mu):
     L = _lib()
