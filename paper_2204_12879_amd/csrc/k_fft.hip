@@ -892,17 +892,33 @@ LRSTV_DEV void band_idft_body(int bid, int nblk, const float* __restrict__ X, in
 #pragma unroll
       for (int e = 0; e < 8; ++e) v[e] = (k0 + e < K2 && n < hw) ? src[(int64_t)(k0 + e) * hw + n] : 0.f;
     };
+    // F and Gamma4 of the tile's outputs (accumulator layout) are loaded
+    // before the product, so that their latency is hidden behind it
+    float fv[16], gv[16];
+    const int ocol = n0 + 32 * (wv & 1) + (t & 31);
+    if (G4t && active) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int orow = m0 + 32 * (wv >> 1) + 8 * (r >> 2) + 4 * ((t & 63) >> 5) + (r & 3);
+        const bool ok = orow < b && ocol < hw;
+        const int64_t q = (int64_t)orow * hw + ocol;
+        fv[r] = ok ? Ft[q] : 0.f;
+        gv[r] = ok ? G4t[q] : 0.f;
+      }
+    }
+    int ri = 0;   // the tile routine hands the outputs over in accumulator order
     auto sto = [&](int j, int n, float e) {
       if (j < b && n < hw) {
         const int64_t q = (int64_t)j * hw + n;
         dst[q] = e;
         if (G4t) {
-          const float f = Ft[q];
-          G4t[q] = G4t[q] + mu * (e - f);
+          const float f = fv[ri];
+          G4t[q] = gv[ri] + mu * (e - f);
           const float d = e - f;
           acc += d * d;
         }
       }
+      ++ri;
     };
     mfma_rtile_t<true, false>(t, m0, n0, K2, fa, fb, sto, sm[grp], active);
   }
