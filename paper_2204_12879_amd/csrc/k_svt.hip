@@ -1452,8 +1452,11 @@ LRSTV_DEV float2 wy_y(const float2* __restrict__ g, int n, int i0, int nbk, int 
 __global__ void __launch_bounds__(256) k_wy_t(const SliceDesc* __restrict__ desc, const float2* __restrict__ gram,
                                               const double* __restrict__ tri, float* __restrict__ Twy,
                                               const int* __restrict__ rcount, int ntile, int ns) {
+  // one LDS buffer (40 KB, four blocks per CU): the product's staging, then
+  // S = Y^H Y and the in-place inversion (T below)
   __shared__ MfmaSmem sm;
-  __shared__ float2 S[64][64];
+  float2(*T)[65] = reinterpret_cast<float2(*)[65]>(&sm);
+  static_assert(sizeof(MfmaSmem) >= 64 * 65 * sizeof(float2), "T factor scratch");
   int b, slice;
   if (!xcd_tile_slice(ntile, ns, b, slice)) return;
   const SliceDesc d = desc[slice];
@@ -1468,7 +1471,9 @@ __global__ void __launch_bounds__(256) k_wy_t(const SliceDesc* __restrict__ desc
     return make_float2(y.x, -y.y);
   };
   auto fb = [&](int k, int q) -> float2 { return (k < m) ? wy_y(g, n, i0, nbk, k, q) : make_float2(0.f, 0.f); };
-  auto st = [&](int p, int q, float2 v) { S[p][q] = v; };
+  // the stores come after the product's last barrier, so S may overwrite
+  // the staging buffer
+  auto st = [&](int p, int q, float2 v) { T[p][q] = v; };
   mfma_ctile<kF32, false, false>(0, 0, m, fa, fb, st, sm, true);
   __syncthreads();
   // T from its inverse: for reflectors I - tau_j y_j y_j^H, T^-1 =
@@ -1480,21 +1485,15 @@ __global__ void __launch_bounds__(256) k_wy_t(const SliceDesc* __restrict__ desc
   // products instead of a 64-step sequential recurrence.  A reflector with
   // tau = 0 (or past the block's last) has a zero column in Y: its diagonal
   // entry is 1 during the inversion (its off-diagonal entries are zero) and
-  // 0 in the result.  The products B C go to the (free) mirrored lower
-  // block of T, transposed; T's rows are padded to 65 so that neither the
-  // row-wise nor the column-wise accesses conflict in the LDS banks.
-  float2(*U)[64] = S;                                             // argument (upper part used)
-  float2(*T)[65] = reinterpret_cast<float2(*)[65]>(&sm);          // result (upper), products (lower)
-  static_assert(sizeof(MfmaSmem) >= 64 * 65 * sizeof(float2), "T factor scratch");
-  for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
-    const int p = e >> 6, q = e & 63;
+  // 0 in the result.  The inversion runs in place: the strict upper part of
+  // T holds the argument's blocks B until the level that replaces them by
+  // -A B C, the diagonal holds the inverses tau_j, and the products B C go to
+  // the (free) mirrored lower block, transposed.  Rows are padded to 65 so
+  // that neither the row-wise nor the column-wise accesses conflict in the
+  // LDS banks.
+  for (int p = threadIdx.x; p < 64; p += blockDim.x) {
     const float tp = p < nbk ? (float)taus[i0 + p] : 0.f;
-    if (p == q) {
-      U[p][p] = make_float2(tp != 0.f ? 1.f / tp : 1.f, 0.f);
-      T[p][p] = make_float2(tp != 0.f ? tp : 1.f, 0.f);
-    } else {
-      T[p][q] = make_float2(0.f, 0.f);
-    }
+    T[p][p] = make_float2(tp != 0.f ? tp : 1.f, 0.f);
   }
   __syncthreads();
   for (int s2 = 1; s2 < 64; s2 <<= 1) {
@@ -1504,7 +1503,7 @@ __global__ void __launch_bounds__(256) k_wy_t(const SliceDesc* __restrict__ desc
       const int pr = e / (s2 * s2), rem = e - pr * s2 * s2, r = rem / s2, c = rem - r * s2;
       const int b0 = 2 * s2 * pr, b1 = b0 + s2;
       float2 acc = make_float2(0.f, 0.f);
-      for (int k = 0; k <= c; ++k) acc = cadd(acc, cmul(U[b0 + r][b1 + k], T[b1 + k][b1 + c]));
+      for (int k = 0; k <= c; ++k) acc = cadd(acc, cmul(T[b0 + r][b1 + k], T[b1 + k][b1 + c]));
       T[b1 + c][b0 + r] = acc;
     }
     __syncthreads();
