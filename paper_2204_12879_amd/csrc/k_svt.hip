@@ -1223,53 +1223,54 @@ __global__ void __launch_bounds__(PHASE == 1 ? 64 : (PHASE == 0 ? 256 : 1024)) k
     double* Um = X + col;
     double* Dm = X + nn + col;
     double* Lp = X + 2 * nn + col;
-    // bottom-up U D U^T
+    // bottom-up U D U^T (only U is stored: the twist criterion below is
+    // formed from U and L)
     double dm = dg[p1] - lk;
     if (fabs(dm) < pivmin) dm = pivmin;
-    Dm[(int64_t)p1 * n] = dm;
     for (int i = p1 - 1; i >= p0; --i) {
       const double u = ee[i] * fast_rcp(dm);
       Um[(int64_t)i * n] = u;
       dm = dg[i] - lk - u * ee[i];
       if (fabs(dm) < pivmin) dm = pivmin;
-      Dm[(int64_t)i * n] = dm;
     }
-    // top-down L D L^T and twist index.  The stored values of the earlier
-    // pass are read in batches of 16 with the next batch in flight while one
-    // is used (the recurrences are sequential, so the loads would otherwise
-    // expose their latency every few steps).
+    // top-down L D L^T and twist index: gamma_i = dm_i + dp_i - (d_i - lk)
+    // = (d_i - lk) - u_i e_i - l_{i-1} e_{i-1} (gamma_p0 = dm_p0, and no u
+    // term at p1).  The u of the earlier pass are read in batches of 16 with
+    // the next batch in flight while one is used (the recurrences are
+    // sequential, so the loads would otherwise expose their latency every few
+    // steps).
     constexpr int PB = 16;
     double dp = dg[p0] - lk;
     if (fabs(dp) < pivmin) dp = pivmin;
-    double best = fabs(Dm[(int64_t)p0 * n]);
+    double best = fabs(dm);
     int rt = p0;
     {
       double buf[2][PB];
-      auto load_dm = [&](double (&v)[PB], int i0) {
+      auto load_unext = [&](double (&v)[PB], int i0) {
 #pragma unroll
-        for (int q = 0; q < PB; ++q) v[q] = (i0 + q < p1) ? Dm[(int64_t)(i0 + q + 1) * n] : 0.0;
+        for (int q = 0; q < PB; ++q) v[q] = (i0 + q + 1 < p1) ? Um[(int64_t)(i0 + q + 1) * n] : 0.0;
       };
-      auto step_dm = [&](const double (&v)[PB], int i0) {
+      auto step_top = [&](const double (&v)[PB], int i0) {
 #pragma unroll
         for (int q = 0; q < PB; ++q) {
           const int i = i0 + q;
           if (i < p1) {
             const double l = ee[i] * fast_rcp(dp);
             Lp[(int64_t)i * n] = l;
-            dp = dg[i + 1] - lk - l * ee[i];
-            if (fabs(dp) < pivmin) dp = pivmin;
-            const double g = dp + v[q] - (dg[i + 1] - lk);
+            const double dpr = dg[i + 1] - lk - l * ee[i];
+            dp = fabs(dpr) < pivmin ? pivmin : dpr;
+            const double g = dpr - v[q] * ee[i + 1];
             if (fabs(g) < best) { best = fabs(g); rt = i + 1; }
           }
         }
       };
-      load_dm(buf[0], p0);
+      load_unext(buf[0], p0);
       for (int i0 = p0; i0 < p1; i0 += 2 * PB) {
-        if (i0 + PB < p1) load_dm(buf[1], i0 + PB);
-        step_dm(buf[0], i0);
+        if (i0 + PB < p1) load_unext(buf[1], i0 + PB);
+        step_top(buf[0], i0);
         if (i0 + PB >= p1) break;
-        if (i0 + 2 * PB < p1) load_dm(buf[0], i0 + 2 * PB);
-        step_dm(buf[1], i0 + PB);
+        if (i0 + 2 * PB < p1) load_unext(buf[0], i0 + 2 * PB);
+        step_top(buf[1], i0 + PB);
       }
     }
     // solve with the twist: x_rt = 1
