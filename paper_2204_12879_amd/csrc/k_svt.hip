@@ -77,17 +77,32 @@ __global__ void __launch_bounds__(256) k_gram(const SliceDesc* __restrict__ desc
     if (r < n && c <= r) g[packed(r, c)] = v;
   };
   if (d.tall) {  // contraction over the h rows
-    auto fa = [&](int m, int k) -> float2 {
-      if (m >= n || k >= h) return make_float2(0.f, 0.f);
-      const int64_t q = (int64_t)k * w + m;
-      return make_float2(re[q], -im[q]);
-    };
-    auto fb = [&](int k, int c) -> float2 {
-      if (c >= n || k >= h) return make_float2(0.f, 0.f);
-      const int64_t q = (int64_t)k * w + c;
-      return make_float2(re[q], im[q]);
-    };
-    mfma_ctile<MODE, false, false>(m0, n0, h, fa, fb, st, sm, active);
+    if constexpr (MODE == kF32) {
+      // rows of M four columns at a time (float4 loads when aligned)
+      auto row4 = [&](int k, int c, float sg, float2(&v)[4]) {
+        const int nv = k < h ? n - c : 0;
+        float a[4], b[4];
+        load4(re + (int64_t)k * w + c, nv, a);
+        load4(im + (int64_t)k * w + c, nv, b);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = make_float2(a[j], sg * b[j]);
+      };
+      auto fa = [&](int m, int k, float2(&v)[4]) { row4(k, m, -1.f, v); };
+      auto fb = [&](int k, int c, float2(&v)[4]) { row4(k, c, 1.f, v); };
+      mfma_ctile<MODE, false, false, true, true>(m0, n0, h, fa, fb, st, sm, active);
+    } else {
+      auto fa = [&](int m, int k) -> float2 {
+        if (m >= n || k >= h) return make_float2(0.f, 0.f);
+        const int64_t q = (int64_t)k * w + m;
+        return make_float2(re[q], -im[q]);
+      };
+      auto fb = [&](int k, int c) -> float2 {
+        if (c >= n || k >= h) return make_float2(0.f, 0.f);
+        const int64_t q = (int64_t)k * w + c;
+        return make_float2(re[q], im[q]);
+      };
+      mfma_ctile<MODE, false, false>(m0, n0, h, fa, fb, st, sm, active);
+    }
   } else {  // contraction over the w columns
     auto fa = [&](int m, int k) -> float2 {
       if (m >= n || k >= w) return make_float2(0.f, 0.f);

@@ -163,42 +163,85 @@ LRSTV_DEV void load8(const float* p, int nvalid, float (&v)[8]) {
   }
 }
 
+// Four consecutive floats p[0 .. 3], of which the first nvalid exist: one
+// float4 load when all four exist and p is 16-byte aligned.
+LRSTV_DEV void load4(const float* p, int nvalid, float (&v)[4]) {
+  if (nvalid >= 4 && ((reinterpret_cast<uintptr_t>(p) & 15) == 0)) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = j < nvalid ? p[j] : 0.f;
+  }
+}
+
 // C(m0 .. m0+63, n0 .. n0+63) = sum_{k < K} fa(m, k) fb(k, n).
 // AK / BK: k is the contiguous memory index of A / B (selects the staging
-// order).  With VA / VB the accessor is eight-wide instead, fa(m, k, v) /
-// fb(k, n, v) filling v[j] with the values at k + j (for a k-contiguous
-// operand this lets it use vector loads; see load8).  `active`
-// (wave-uniform) skips the products of a wave whose sub-tile is not needed;
-// every wave still takes part in staging.  The result is handed to
-// st(row, col, float2) for rows and columns of the wave's sub-tile.
+// order).  With VA / VB the accessor is wide instead: for a k-contiguous
+// operand eight-wide along k, fa(m, k, v) / fb(k, n, v) filling v[j] with the
+// values at k + j (see load8); for the other operands (FP32 mode only)
+// four-wide along the row / column index, fa(m, k, v) / fb(k, n, v) filling
+// v[j] with the values at m + j / n + j (see load4), a thread staging four
+// consecutive rows (columns) of two k.  `active` (wave-uniform) skips the
+// products of a wave whose sub-tile is not needed; every wave still takes
+// part in staging.  The result is handed to st(row, col, float2) for rows and
+// columns of the wave's sub-tile.
 template <int MODE, bool AK, bool BK, bool VA = false, bool VB = false, class FA, class FB, class ST>
 LRSTV_DEV void mfma_ctile(int m0, int n0, int K, FA fa, FB fb, ST st, MfmaSmem& sm, bool active) {
+  constexpr bool A4 = VA && !AK, B4 = VB && !BK;   // four-wide along the row / column index
+  static_assert(MODE == kF32 || !(A4 || B4), "four-wide staging is for the FP32 layout");
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6, wy = wv >> 1, wx = wv & 1;
   int ra, ka, rb, kb;
   stage_coords<AK>(t, ra, ka);
   stage_coords<BK>(t, rb, kb);
+  if constexpr (A4) {
+    ra = 4 * (t & 15);
+    ka = t >> 4;   // rows ka and ka + 16 of the chunk
+  }
+  if constexpr (B4) {
+    rb = 4 * (t & 15);
+    kb = t >> 4;
+  }
   CAcc c;
 #pragma unroll
   for (int i = 0; i < 16; ++i) c.re[i] = c.im[i] = 0.f;
   float2 va[8], vb[8];
   auto fetch = [&](int kc) {
-    if constexpr (VA) {
+    if constexpr (A4) {
+#pragma unroll
+      for (int e = 0; e < 2; ++e) fa(m0 + ra, kc + ka + 16 * e, *reinterpret_cast<float2(*)[4]>(&va[4 * e]));
+    } else if constexpr (VA) {
       fa(m0 + ra, kc + ka, va);
     } else {
 #pragma unroll
       for (int j = 0; j < 8; ++j) va[j] = fa(m0 + ra, kc + ka + j);
     }
-    if constexpr (VB) {
+    if constexpr (B4) {
+#pragma unroll
+      for (int e = 0; e < 2; ++e) fb(kc + kb + 16 * e, n0 + rb, *reinterpret_cast<float2(*)[4]>(&vb[4 * e]));
+    } else if constexpr (VB) {
       fb(kc + kb, n0 + rb, vb);
     } else {
 #pragma unroll
       for (int j = 0; j < 8; ++j) vb[j] = fb(kc + kb + j, n0 + rb);
     }
   };
+  // four-wide staging: element (row r + j, k + 16 e) of the chunk
+  auto store4 = [&](float (*pr)[kMT + 1], float (*pi)[kMT + 1], int r, int k, const float2 (&v)[8]) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        pr[k + 16 * e][r + j] = v[4 * e + j].x;
+        pi[k + 16 * e][r + j] = v[4 * e + j].y;
+      }
+  };
   fetch(0);
   for (int k0 = 0; k0 < K; k0 += kKC) {
-    stage_store<MODE>(sm, true, ra, ka, va);
-    stage_store<MODE>(sm, false, rb, kb, vb);
+    if constexpr (A4) store4(sm.f.ar, sm.f.ai, ra, ka, va);
+    else stage_store<MODE>(sm, true, ra, ka, va);
+    if constexpr (B4) store4(sm.f.br, sm.f.bi, rb, kb, vb);
+    else stage_store<MODE>(sm, false, rb, kb, vb);
     __syncthreads();
     if (k0 + kKC < K) fetch(k0 + kKC);
     chunk_mma<MODE>(sm, wy, wx, lane, active, c);
