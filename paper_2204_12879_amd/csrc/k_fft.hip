@@ -753,7 +753,7 @@ constexpr int kDftRowTiles = 3;
 LRSTV_DEV void band_dft_body(int bid, int nblk, const float* __restrict__ A, int64_t a_stride, int n_t,
                              float* __restrict__ out, int hw, int b) {
   __shared__ float ct[LRSTV_MAX_SIDE_DEV], st[LRSTV_MAX_SIDE_DEV];
-  __shared__ float sB[kKC][kMT + 4];
+  __shared__ __align__(16) float sB[kKC][kMT + 4];
   for (int m = threadIdx.x; m < b; m += blockDim.x) {
     double sv, cv;
     sincospi(2.0 * (double)m / (double)b, &sv, &cv);
@@ -765,12 +765,12 @@ LRSTV_DEV void band_dft_body(int bid, int nblk, const float* __restrict__ A, int
   const int TM = (M + kMT - 1) / kMT, TN = (hw + kMT - 1) / kMT;
   const int nstrips = n_t * TN;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6, wy = wv >> 1, wx = wv & 1, li = lane & 31, lk = lane >> 5;
-  const int sc = t & 63, sr = t >> 6;   // staging: column sc, rows sr + 4 e
+  const int sc = 4 * (t & 15), sr = t >> 4;   // staging: columns sc .. sc+3, rows sr and sr + 16
   for (int strip = bid; strip < nstrips; strip += nblk) {
     const int tt = strip / TN, tn = strip - tt * TN, n0 = tn * kMT;
     const float* src = A + tt * a_stride;
     float* dst = out + (int64_t)tt * M * hw;
-    const bool colok = n0 + sc < hw;
+    const int ncol = hw - n0 - sc;   // columns of this thread's four that exist
     for (int tg = 0; tg < TM; tg += kDftRowTiles) {
       f32x16 acc[kDftRowTiles];
       int idx[kDftRowTiles], stp[kDftRowTiles];
@@ -785,18 +785,19 @@ LRSTV_DEV void band_dft_body(int bid, int nblk, const float* __restrict__ A, int
         idx[q] = (int)(((int64_t)kq * lk) % b);      // j = lk at the first step
         stp[q] = (int)(((int64_t)2 * kq) % b);
       }
-      float pre[8];
+      float pre[2][4];
       auto fetch = [&](int k0) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int k = k0 + sr + 4 * e;
-          pre[e] = (colok && k < b) ? src[(int64_t)k * hw + n0 + sc] : 0.f;
+        for (int e = 0; e < 2; ++e) {
+          const int k = k0 + sr + 16 * e;
+          load4(src + (int64_t)k * hw + n0 + sc, k < b ? ncol : 0, pre[e]);
         }
       };
       fetch(0);
       for (int k0 = 0; k0 < b; k0 += kKC) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) sB[sr + 4 * e][sc] = pre[e];
+        for (int e = 0; e < 2; ++e)
+          *reinterpret_cast<float4*>(&sB[sr + 16 * e][sc]) = make_float4(pre[e][0], pre[e][1], pre[e][2], pre[e][3]);
         __syncthreads();
         if (k0 + kKC < b) fetch(k0 + kKC);
 #pragma unroll 4
@@ -888,9 +889,8 @@ LRSTV_DEV void band_idft_body(int bid, int nblk, const float* __restrict__ X, in
         if (idx >= b) idx -= b;
       }
     };
-    auto fb = [&](int k0, int n, float* v) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = (k0 + e < K2 && n < hw) ? src[(int64_t)(k0 + e) * hw + n] : 0.f;
+    auto fb = [&](int k, int n, float(&v)[4]) {   // four columns of slice row k
+      load4(src + (int64_t)k * hw + n, k < K2 ? hw - n : 0, v);
     };
     // F and Gamma4 of the tile's outputs (accumulator layout) are loaded
     // before the product, so that their latency is hidden behind it
@@ -920,7 +920,7 @@ LRSTV_DEV void band_idft_body(int bid, int nblk, const float* __restrict__ X, in
       }
       ++ri;
     };
-    mfma_rtile_t<true, false>(t, m0, n0, K2, fa, fb, sto, sm[grp], active);
+    mfma_rtile_t<true, false, true>(t, m0, n0, K2, fa, fb, sto, sm[grp], active);
   }
   if (part) {
     const double tot = block_sum((double)acc, red);

@@ -267,29 +267,50 @@ struct MfmaSmemR {
 // t: the thread's index within its group of 256 (a block may run several
 // groups on separate tiles; every group calls this the same number of times
 // with the same K, since the routine synchronises the whole block).
-template <bool AK, bool BK, class FA, class FB, class ST>
+// With B4, B (not k-contiguous) is fetched four-wide along n: fb(k, n, v)
+// fills v[j] with the values at n + j, a thread staging four columns of two k.
+template <bool AK, bool BK, bool B4 = false, class FA, class FB, class ST>
 LRSTV_DEV void mfma_rtile_t(int t, int m0, int n0, int K, FA fa, FB fb, ST st, MfmaSmemR& sm, bool active) {
+  static_assert(!(B4 && BK), "four-wide B staging is for an n-contiguous B");
   const int lane = t & 63, wv = t >> 6, wy = wv >> 1, wx = wv & 1;
   const int li = lane & 31, lk = lane >> 5;
   int ra, ka, rb, kb;
   stage_coords<AK>(t, ra, ka);
   stage_coords<BK>(t, rb, kb);
+  if constexpr (B4) {
+    rb = 4 * (t & 15);
+    kb = t >> 4;   // rows kb and kb + 16 of the chunk
+  }
   f32x16 c;
 #pragma unroll
   for (int i = 0; i < 16; ++i) c[i] = 0.f;
   float va[8], vb[8];
+  auto fetch_b = [&](int kc) {
+    if constexpr (B4) {
+#pragma unroll
+      for (int e = 0; e < 2; ++e) fb(kc + kb + 16 * e, n0 + rb, *reinterpret_cast<float(*)[4]>(&vb[4 * e]));
+    } else {
+      fb(kc + kb, n0 + rb, vb);
+    }
+  };
   fa(m0 + ra, ka, va);
-  fb(kb, n0 + rb, vb);
+  fetch_b(0);
   for (int k0 = 0; k0 < K; k0 += kKC) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      sm.a[ka + j][ra] = va[j];
-      sm.b[kb + j][rb] = vb[j];
+    for (int j = 0; j < 8; ++j) sm.a[ka + j][ra] = va[j];
+    if constexpr (B4) {
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sm.b[kb + 16 * e][rb + j] = vb[4 * e + j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sm.b[kb + j][rb] = vb[j];
     }
     __syncthreads();
     if (k0 + kKC < K) {
       fa(m0 + ra, k0 + kKC + ka, va);
-      fb(k0 + kKC + kb, n0 + rb, vb);
+      fetch_b(k0 + kKC);
     }
     if (active) {
 #pragma unroll 4
