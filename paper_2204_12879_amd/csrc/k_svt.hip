@@ -660,6 +660,18 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_reg(const SliceDesc* __rest
 //      products); meanwhile every thread forms the next reflector.
 LRSTV_DEV int mt_rho(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
 
+// x of lane l plus x of lane l ^ 32, in every lane (the two halves swapped
+// across the wave by v_permlane32_swap)
+LRSTV_DEV float half_pair_sum(float x) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// x of lane l ^ 1 (a DPP quad permutation, no LDS round trip)
+LRSTV_DEV float lane_xor1(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xf, 0xf, false));
+}
+
 // tile t of the column-major enumeration of the lower tiles of an NT x NT grid
 LRSTV_DEV void mt_tile(int t, int NT, int& R, int& C) {
   C = 0;
@@ -859,36 +871,44 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __res
       for (int s = 0; s < TPW; ++s) {
         const int R = tR[s], C = tC[s];
         if (R < 0 || 32 * C + 31 <= i) continue;   // no element in the trailing block
-        const float2 xC = xv[32 * C + li];
-        float2 cacc = zero;
+        const int col = 32 * C + li;
+        const int tr = lane >> 2, th = (lane >> 1) & 1, part = lane & 1;
+        const int row = 32 * R + mt_rho(tr, th);
+        // the partial sums this tile adds to, read first so that their
+        // latency is covered by the products
+        const float2 pcol = P[wv][col];
+        const float2 prow = R != C ? P[wv][row] : zero;
+        const float2 xC = xv[col];
+        // column sums conj(a) x_row as four FMAs per element
+        float cr = 0.f, ci = 0.f;
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-          cacc = cadd(cacc, cmulc(make_float2(tre[s][r], tim[s][r]), xv[32 * R + mt_rho(r, h)]));
-        // Re(conj(x_col) (A^H x)_col); twice for an off-diagonal tile (its mirror)
-        if (R == C) xaxd += cacc.x * xC.x + cacc.y * xC.y;
-        else xaxo += cacc.x * xC.x + cacc.y * xC.y;
-        const float2 co = make_float2(__shfl_xor(cacc.x, 32, 64), __shfl_xor(cacc.y, 32, 64));
-        if (h == 0) {
-          const int col = 32 * C + li;
-          P[wv][col] = cadd(P[wv][col], cadd(cacc, co));
+        for (int r = 0; r < 16; ++r) {
+          const float ar = tre[s][r], ai = tim[s][r];
+          const float2 xr = xv[32 * R + mt_rho(r, h)];
+          cr = fmaf(ar, xr.x, cr);
+          cr = fmaf(ai, xr.y, cr);
+          ci = fmaf(ar, xr.y, ci);
+          ci = fmaf(-ai, xr.x, ci);
         }
+        // Re(conj(x_col) (A^H x)_col); twice for an off-diagonal tile (its mirror)
+        if (R == C) xaxd += cr * xC.x + ci * xC.y;
+        else xaxo += cr * xC.x + ci * xC.y;
+        // both halves of the column (lanes l and l + 32) summed in every lane
+        const float2 csum = make_float2(half_pair_sum(cr), half_pair_sum(ci));
+        if (h == 0) P[wv][col] = cadd(pcol, csum);
         if (R != C) {
           // row sums: scr(r, lane) = a x_col; lane j then sums chunk q = j & 3
           // (16 columns of half q >> 1) of row j >> 2
           const int wpos = lane + (lane >> 4);
 #pragma unroll
           for (int r = 0; r < 16; ++r) scr[wv][r * 68 + wpos] = cmul(make_float2(tre[s][r], tim[s][r]), xC);
-          const int tr = lane >> 2, th = (lane >> 1) & 1, part = lane & 1;
           const float2* src = &scr[wv][tr * 68 + 17 * (lane & 3)];
           float2 sum = zero;
 #pragma unroll
           for (int e = 0; e < 16; ++e) sum = cadd(sum, src[e]);
-          sum.x += __shfl_xor(sum.x, 1, 64);
-          sum.y += __shfl_xor(sum.y, 1, 64);
-          if (part == 0) {
-            const int row = 32 * R + mt_rho(tr, th);
-            P[wv][row] = cadd(P[wv][row], sum);
-          }
+          sum.x += lane_xor1(sum.x);
+          sum.y += lane_xor1(sum.y);
+          if (part == 0) P[wv][row] = cadd(prow, sum);
         }
       }
       const float sx = wave_sumf_dpp(xaxd + 2.f * xaxo);
