@@ -649,8 +649,9 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_reg(const SliceDesc* __rest
 // a_c - v conj(w_c) - w conj(v_c).  Two barriers per step i:
 //   C  per tile the column sums conj(a) x_row are lane-local (halves
 //      combined) and give the whole product of a diagonal tile; the row sums
-//      a x_col of an off-diagonal tile go through an LDS transpose.  Partial
-//      sums per wave, x^H A x partials; column i+2 out of the tiles
+//      a x_col of an off-diagonal tile are reduced across the lanes in
+//      registers (lane exchanges, no LDS traffic).  Partial sums per wave,
+//      x^H A x partials; column i+2 out of the tiles
 //   D  one index per thread of the first four waves: v, w = tau A v -
 //      (tau^2 v^H A v / 2) v, the reflector column to the Gram; the next x
 //      (column i+1 of the updated matrix), a (column i+2), diagonal, ||x||^2
@@ -667,10 +668,26 @@ LRSTV_DEV float half_pair_sum(float x) {
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// x of lane l ^ 1 (a DPP quad permutation, no LDS round trip)
-LRSTV_DEV float lane_xor1(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xf, 0xf, false));
+// Lanes 0-15 of each 32-lane half: x + x of lane l + 16; lanes 16-31: y + y
+// of lane l - 16 (v_permlane16_swap exchanges lanes 16-31 of x with lanes
+// 0-15 of y).
+LRSTV_DEV float lane_pair16_sum(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
+
+// One halving step of a register reduction: of v[0 .. 2M), the lane keeps
+// v[m + M sel] and adds the partner's copy of it (the partner, given by the
+// DPP control CTRL, has the other sel and sends v[m + M (1 - sel)] in turn).
+template <int M, int CTRL>
+LRSTV_DEV void row_halve(float* v, int sel) {
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const float keep = sel ? v[m + M] : v[m], send = sel ? v[m] : v[m + M];
+    v[m] = keep + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(send), CTRL, 0xf, 0xf, false));
+  }
+}
+
 
 // tile t of the column-major enumeration of the lower tiles of an NT x NT grid
 LRSTV_DEV void mt_tile(int t, int NT, int& R, int& C) {
@@ -745,16 +762,13 @@ LRSTV_DEV MtRefl mt_reflector(double nx2, float2 x0) {
 template <int NW, int TPW>
 __global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __restrict__ desc,
                                                          float2* __restrict__ gram, double* __restrict__ tri) {
-  constexpr int NMAX = 256, SCR = 16 * 68, NDW = NMAX / 64;   // waves of D, one index per thread
+  constexpr int NMAX = 256, NDW = NMAX / 64;   // waves of D, one index per thread
   static_assert(NW * TPW >= 36, "the 36 lower tiles of a 256 x 256 Gram");
   static_assert(NW >= NDW, "one index per thread in D");
   // columns i, i+1 (by step parity) and i+2 of the current matrix
   __shared__ float2 xb[2][NMAX], ab[2][NMAX], bb[NMAX];
   __shared__ float2 vb[NMAX], wb[NMAX];
   __shared__ float2 P[NW][NMAX];               // per-wave partial sums of A x
-  // per-wave transpose of the row products; entry (r, l) at r * 68 + l + l / 16,
-  // which keeps both the row-wise writes and the chunk-wise reads conflict-free
-  __shared__ float2 scr[NW][SCR];
   // per-wave partial sums (FP32 within a wave, summed over the waves in FP64)
   __shared__ float red_nx[2][NW], red_xa[2][NW][2], red_xax[NW];
   __shared__ double red_fro[NW];
@@ -872,12 +886,12 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __res
         const int R = tR[s], C = tC[s];
         if (R < 0 || 32 * C + 31 <= i) continue;   // no element in the trailing block
         const int col = 32 * C + li;
-        const int tr = lane >> 2, th = (lane >> 1) & 1, part = lane & 1;
-        const int row = 32 * R + mt_rho(tr, th);
         // the partial sums this tile adds to, read first so that their
         // latency is covered by the products
+        float* Pf = reinterpret_cast<float*>(P[wv]);
+        const int rsel = 2 * (32 * R + mt_rho(li >> 1, h)) + (li & 1);   // see the row sums below
         const float2 pcol = P[wv][col];
-        const float2 prow = R != C ? P[wv][row] : zero;
+        const float prow = R != C ? Pf[rsel] : 0.f;
         const float2 xC = xv[col];
         // column sums conj(a) x_row as four FMAs per element
         float cr = 0.f, ci = 0.f;
@@ -897,18 +911,25 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __res
         const float2 csum = make_float2(half_pair_sum(cr), half_pair_sum(ci));
         if (h == 0) P[wv][col] = cadd(pcol, csum);
         if (R != C) {
-          // row sums: scr(r, lane) = a x_col; lane j then sums chunk q = j & 3
-          // (16 columns of half q >> 1) of row j >> 2
-          const int wpos = lane + (lane >> 4);
+          // row sums of a x_col over the 32 lanes of each half, in registers:
+          // value k = 2 r + c (c: real / imaginary part of row rho(r, h)) is
+          // halved five times, lane bit 4, 3, 2, 1, 0 choosing the half it
+          // keeps while the partner (lane ^ 16, ^ 15, ^ 7, ^ 3, ^ 1) adds the
+          // other, so that lane li ends with the sum of value k = li
+          float v[32];
 #pragma unroll
-          for (int r = 0; r < 16; ++r) scr[wv][r * 68 + wpos] = cmul(make_float2(tre[s][r], tim[s][r]), xC);
-          const float2* src = &scr[wv][tr * 68 + 17 * (lane & 3)];
-          float2 sum = zero;
+          for (int r = 0; r < 16; ++r) {
+            const float2 pr = cmul(make_float2(tre[s][r], tim[s][r]), xC);
+            v[2 * r] = pr.x;
+            v[2 * r + 1] = pr.y;
+          }
 #pragma unroll
-          for (int e = 0; e < 16; ++e) sum = cadd(sum, src[e]);
-          sum.x += lane_xor1(sum.x);
-          sum.y += lane_xor1(sum.y);
-          if (part == 0) P[wv][row] = cadd(prow, sum);
+          for (int j = 0; j < 16; ++j) v[j] = lane_pair16_sum(v[j], v[j + 16]);
+          row_halve<8, 0x140>(v, (li >> 3) & 1);   // partner lane ^ 15 (row mirror)
+          row_halve<4, 0x141>(v, (li >> 2) & 1);   // lane ^ 7 (half-row mirror)
+          row_halve<2, 0x1B>(v, (li >> 1) & 1);    // lane ^ 3
+          row_halve<1, 0xB1>(v, li & 1);           // lane ^ 1
+          Pf[rsel] = prow + v[0];
         }
       }
       const float sx = wave_sumf_dpp(xaxd + 2.f * xaxo);
@@ -2144,8 +2165,8 @@ static size_t tridiag_reg_lds(int n, int v) {
 }
 // Static LDS of k_tridiag_mfma<NW, TPW>: seven columns (x and a per step
 // parity, the column after them, v, w) and NW partial rows (256 complex
-// each), NW transposes of 16 x 68 complex.
-static size_t tridiag_mfma_lds(int nw) { return (size_t)(7 + nw) * 256 * sizeof(float2) + (size_t)nw * 16 * 68 * sizeof(float2) + 1024; }
+// each).
+static size_t tridiag_mfma_lds(int nw) { return (size_t)(7 + nw) * 256 * sizeof(float2) + 1024; }
 
 static const void* tri_kernel(int v) {
   switch (v) {
