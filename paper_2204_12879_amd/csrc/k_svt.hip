@@ -741,8 +741,10 @@ LRSTV_DEV MtRefl mt_reflector(double nx2, float2 x0) {
   const double ax02 = (double)x0.x * x0.x + (double)x0.y * x0.y;
   f.defl = nx2 <= kDeflate2;
   f.refl = !f.defl && nx2 - ax02 > 1e-14 * nx2;
-  f.ax0 = uniform_f(sqrtf((float)ax02));
-  const float rax = f.ax0 > 0.f ? 1.f / f.ax0 : 0.f;
+  // hardware square root and reciprocal (about 1 ulp): FP32 factors of an
+  // FP32 reduction
+  f.ax0 = uniform_f(__builtin_amdgcn_sqrtf((float)ax02));
+  const float rax = f.ax0 > 0.f ? __builtin_amdgcn_rcpf(f.ax0) : 0.f;
   f.pr = uniform_f(f.ax0 > 0.f ? x0.x * rax : 1.f);
   f.pim = uniform_f(f.ax0 > 0.f ? x0.y * rax : 0.f);
   f.nx = 0.f;
@@ -750,10 +752,10 @@ LRSTV_DEV MtRefl mt_reflector(double nx2, float2 x0) {
   f.gam = 0.f;
   f.scl = make_float2(0.f, 0.f);
   if (f.refl) {
-    f.nx = uniform_f(sqrtf((float)nx2));
-    const float inv = 1.f / (f.ax0 + f.nx);
+    f.nx = uniform_f(__builtin_amdgcn_sqrtf((float)nx2));
+    const float inv = __builtin_amdgcn_rcpf(f.ax0 + f.nx);
     f.scl = make_float2(uniform_f(f.pr * inv), uniform_f(-f.pim * inv));
-    f.tau = uniform_f(1.f + f.ax0 / f.nx);
+    f.tau = uniform_f(1.f + f.ax0 * __builtin_amdgcn_rcpf(f.nx));
     f.gam = uniform_f(f.nx * inv);
   }
   return f;
@@ -1014,12 +1016,22 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __res
     // real part: [-v_R | -w_R] (re in half 0, im in half 1) times [w_C ; v_C];
     // imaginary part: [-Im v, Re v] and [-Im w, Re w] against the same B.
     if (f.refl) {
+      // every tile's v and w entries are read before the first product, so
+      // that one LDS latency covers them all
+      float2 vRs[TPW], wRs[TPW], vCs[TPW], wCs[TPW];
+#pragma unroll
+      for (int s = 0; s < TPW; ++s) {
+        const int R = tR[s] < 0 ? 0 : tR[s], C = tC[s] < 0 ? 0 : tC[s];
+        vRs[s] = vb[32 * R + li];
+        wRs[s] = wb[32 * R + li];
+        vCs[s] = vb[32 * C + li];
+        wCs[s] = wb[32 * C + li];
+      }
 #pragma unroll
       for (int s = 0; s < TPW; ++s) {
         const int R = tR[s], C = tC[s];
         if (R < 0 || 32 * C + 31 <= i) continue;
-        const float2 vR = vb[32 * R + li], wR = wb[32 * R + li];
-        const float2 vC = vb[32 * C + li], wC = wb[32 * C + li];
+        const float2 vR = vRs[s], wR = wRs[s], vC = vCs[s], wC = wCs[s];
         const float b0 = h ? wC.y : wC.x, b1 = h ? vC.y : vC.x;
         const float ar0 = h ? -vR.y : -vR.x, ar1 = h ? -wR.y : -wR.x;
         const float ai0 = h ? vR.x : -vR.y, ai1 = h ? wR.x : -wR.y;
