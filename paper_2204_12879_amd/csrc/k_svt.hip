@@ -1102,6 +1102,9 @@ LRSTV_DEV int sturm_count_fast(const double* dg, const double* e2, int n, double
   double q = dg[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   cnt += q < 0.0;
+  // unrolled so that the loads of d and e^2 (the same for every lane) take
+  // immediate offsets instead of an address computed per step
+#pragma unroll 4
   for (int i = 1; i < n; ++i) {
     double rq = __builtin_amdgcn_rcp(q);
     rq = rq * (2.0 - q * rq);  // one Newton step: full FP64 reciprocal accuracy
