@@ -1115,6 +1115,145 @@ LRSTV_DEV int sturm_count_fast(const double* dg, const double* e2, int n, double
   return cnt;
 }
 
+// Top-down L D L^T of (T - lk) over rows [p0, p1] (L to column Lp) and the
+// twist index minimising gamma_i = (d_i - lk) - u_i e_i - l_{i-1} e_{i-1},
+// from the bottom-up U of the same block (column Um) and gamma_p0 = best.
+// The u are read 16 rows ahead (rows clamped into the block, unconditional
+// loads) and every step is predicated rather than branched, so that the
+// loads of the next batch stay in flight across the stores of this one.
+LRSTV_DEV int twisted_top(const double* __restrict__ dg, const double* __restrict__ ee,
+                          const double* __restrict__ Um, double* __restrict__ Lp, int n, int p0, int p1,
+                          double lk, double pivmin, double best) {
+  constexpr int PB = 16;
+  double dp = dg[p0] - lk;
+  if (fabs(dp) < pivmin) dp = pivmin;
+  int rt = p0;
+  double lkeep = 0.0;
+  double v[PB], vn[PB];
+  auto load = [&](double (&w)[PB], int i0) {
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      const int r = i0 + q + 1;
+      w[q] = Um[(int64_t)(r < p1 ? r : p1 - 1) * n];
+    }
+  };
+  if (p1 <= p0) return rt;   // a 1 x 1 block: nothing to factor (and no row p1 - 1)
+  load(v, p0);
+  for (int i0 = p0; i0 < p1; i0 += PB) {
+    load(vn, i0 + PB);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      const int i = i0 + q;
+      const bool in = i < p1;
+      const int ic = in ? i : p1 - 1;
+      const double l = ee[ic] * fast_rcp(dp);
+      lkeep = in ? l : lkeep;   // past p1 - 1 the row p1 - 1 is stored again
+      Lp[(int64_t)ic * n] = lkeep;
+      const double dpr = dg[ic + 1] - lk - l * ee[ic];
+      dp = in ? (fabs(dpr) < pivmin ? pivmin : dpr) : dp;
+      const double u = i + 1 < p1 ? v[q] : 0.0;
+      const double g = fabs(dpr - u * ee[ic + 1]);
+      const bool better = in && g < best;
+      best = better ? g : best;
+      rt = better ? i + 1 : rt;
+    }
+#pragma unroll
+    for (int q = 0; q < PB; ++q) v[q] = vn[q];
+  }
+  return rt;
+}
+
+// Column x of a twisted solve with x_rt = 1 over rows [p0, p1], from the
+// factors L (rows below the twist) and U (rows above it); returns ||x||^2.
+// Rows are taken 32 at a time: a batch's factors are loaded (rows clamped
+// into the block, so every load is unconditional), the batch is solved in
+// registers, and its stores are issued after the next batch's loads, so that
+// waiting for those loads does not wait for the stores as well.  The three
+// columns are separate parts of one scratch array; restrict lets the loads
+// of a batch be issued while the stores of the previous one are in flight.
+LRSTV_DEV double twisted_solve(const double* __restrict__ Lp, const double* __restrict__ Um, double* __restrict__ x,
+                               int n, int p0, int p1, int rt) {
+  double nrm = 1.0;
+  constexpr int XB = 32;
+  double v[XB], xs[XB];
+  // rows rt-1 down to p0: x_i = -l_i x_{i+1}
+  auto load_l = [&](int i0) {
+#pragma unroll
+    for (int q = 0; q < XB; ++q) v[q] = Lp[(int64_t)(i0 - q >= p0 ? i0 - q : p0) * n];
+  };
+  double xv = 1.0;
+  int i0 = rt - 1;
+  if (i0 >= p0) load_l(i0);
+  while (i0 >= p0) {
+#pragma unroll
+    for (int q = 0; q < XB; ++q) {
+      const bool in = i0 - q >= p0;
+      const double nx = -v[q] * xv;
+      xv = in ? nx : xv;
+      nrm += in ? nx * nx : 0.0;
+      xs[q] = xv;   // rows past p0 repeat x_p0, stored to row p0 below
+    }
+    const int b0 = i0;
+    i0 -= XB;
+    load_l(i0);   // unconditional (past the end every row clamps to p0)
+    __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the stores
+    // unconditional stores (a fixed count per batch keeps the wait for
+    // the next loads exact)
+#pragma unroll
+    for (int q = 0; q < XB; ++q) x[(int64_t)(b0 - q >= p0 ? b0 - q : p0) * n] = xs[q];
+  }
+  x[(int64_t)rt * n] = 1.0;
+  // rows rt+1 .. p1: x_{i+1} = -u_i x_i
+  auto load_u = [&](int i0) {
+#pragma unroll
+    for (int q = 0; q < XB; ++q) v[q] = Um[(int64_t)(i0 + q < p1 ? i0 + q : p1 - 1) * n];
+  };
+  xv = 1.0;
+  i0 = rt;
+  if (i0 < p1) load_u(i0);
+  while (i0 < p1) {
+#pragma unroll
+    for (int q = 0; q < XB; ++q) {
+      const bool in = i0 + q < p1;
+      const double nx = -v[q] * xv;
+      xv = in ? nx : xv;
+      nrm += in ? nx * nx : 0.0;
+      xs[q] = xv;   // rows past p1 repeat x_p1, stored to row p1 below
+    }
+    const int b0 = i0;
+    i0 += XB;
+    load_u(i0);   // unconditional (past the end every row clamps to p1 - 1)
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < XB; ++q) x[(int64_t)(b0 + q < p1 ? b0 + q + 1 : p1) * n] = xs[q];
+  }
+  return nrm;
+}
+
+// Counts below xa and below xb over rows [p0, p1], the two recurrences
+// interleaved, with the same arithmetic as sturm_count_fast (so that counts
+// of blocks add up to its count over the whole matrix).
+LRSTV_DEV void sturm_count_pair(const double* dg, const double* e2, int p0, int p1, double xa, double xb,
+                                double pivmin, int& ca, int& cb) {
+  double qa = dg[p0] - xa, qb = dg[p0] - xb;
+  if (fabs(qa) < pivmin) qa = -pivmin;
+  if (fabs(qb) < pivmin) qb = -pivmin;
+  ca = qa < 0.0;
+  cb = qb < 0.0;
+  for (int i = p0 + 1; i <= p1; ++i) {
+    double ra = __builtin_amdgcn_rcp(qa), rb = __builtin_amdgcn_rcp(qb);
+    ra = ra * (2.0 - qa * ra);
+    rb = rb * (2.0 - qb * rb);
+    qa = (dg[i] - xa) - e2[i - 1] * ra;
+    qb = (dg[i] - xb) - e2[i - 1] * rb;
+    if (fabs(qa) < pivmin) qa = -pivmin;
+    if (fabs(qb) < pivmin) qb = -pivmin;
+    ca += qa < 0.0;
+    cb += qb < 0.0;
+  }
+}
+
 // Eigenvalues above (t^2 - delta) of T / ||T|| by 5-section (4 threads per
 // eigenvalue, blocks of 256 threads over 64 eigenvalues), eigenvectors by twisted
 // factorisation inside their unreduced block, Gram-Schmidt inside clusters;
@@ -1275,14 +1414,16 @@ __global__ void __launch_bounds__(PHASE == 1 ? 64 : (PHASE == 0 ? 256 : 1024)) k
     const double lk = lam[k];
     int pick = 0;
     if (nblk > 1) {
-      // locate the unreduced block that holds this copy of lk
-      int lt = 0;
-      for (int b = 0; b < nblk; ++b) lt += sturm_count(dg, e2, bstart[b], bstart[b + 1] - 1, lk - tol_eq, pivmin);
-      int m = k - lt;
+      // locate the unreduced block that holds this copy of lk: the count
+      // below lk - tol over the whole matrix is the sum of the blocks'
+      // counts (the recurrence restarts exactly where e^2 = 0), then the
+      // blocks' counts at lk -+ tol (two interleaved recurrences) until the
+      // copy is reached
+      int m = k - sturm_count_fast(dg, e2, n, lk - tol_eq, pivmin);
       for (int b = 0; b < nblk; ++b) {
-        const int p0 = bstart[b], p1 = bstart[b + 1] - 1;
-        const int eq =
-            sturm_count(dg, e2, p0, p1, lk + tol_eq, pivmin) - sturm_count(dg, e2, p0, p1, lk - tol_eq, pivmin);
+        int clo, chi;
+        sturm_count_pair(dg, e2, bstart[b], bstart[b + 1] - 1, lk - tol_eq, lk + tol_eq, pivmin, clo, chi);
+        const int eq = chi - clo;
         if (eq > 0) {
           pick = b;
           if (m < eq) break;
@@ -1298,6 +1439,7 @@ __global__ void __launch_bounds__(PHASE == 1 ? 64 : (PHASE == 0 ? 256 : 1024)) k
     // formed from U and L)
     double dm = dg[p1] - lk;
     if (fabs(dm) < pivmin) dm = pivmin;
+#pragma unroll 4
     for (int i = p1 - 1; i >= p0; --i) {
       const double u = ee[i] * fast_rcp(dm);
       Um[(int64_t)i * n] = u;
@@ -1306,102 +1448,14 @@ __global__ void __launch_bounds__(PHASE == 1 ? 64 : (PHASE == 0 ? 256 : 1024)) k
     }
     // top-down L D L^T and twist index: gamma_i = dm_i + dp_i - (d_i - lk)
     // = (d_i - lk) - u_i e_i - l_{i-1} e_{i-1} (gamma_p0 = dm_p0, and no u
-    // term at p1).  The u of the earlier pass are read in batches of 16 with
-    // the next batch in flight while one is used (the recurrences are
-    // sequential, so the loads would otherwise expose their latency every few
-    // steps).
-    constexpr int PB = 16;
-    double dp = dg[p0] - lk;
-    if (fabs(dp) < pivmin) dp = pivmin;
-    double best = fabs(dm);
-    int rt = p0;
-    {
-      double buf[2][PB];
-      auto load_unext = [&](double (&v)[PB], int i0) {
-#pragma unroll
-        for (int q = 0; q < PB; ++q) v[q] = (i0 + q + 1 < p1) ? Um[(int64_t)(i0 + q + 1) * n] : 0.0;
-      };
-      auto step_top = [&](const double (&v)[PB], int i0) {
-#pragma unroll
-        for (int q = 0; q < PB; ++q) {
-          const int i = i0 + q;
-          if (i < p1) {
-            const double l = ee[i] * fast_rcp(dp);
-            Lp[(int64_t)i * n] = l;
-            const double dpr = dg[i + 1] - lk - l * ee[i];
-            dp = fabs(dpr) < pivmin ? pivmin : dpr;
-            const double g = dpr - v[q] * ee[i + 1];
-            if (fabs(g) < best) { best = fabs(g); rt = i + 1; }
-          }
-        }
-      };
-      load_unext(buf[0], p0);
-      for (int i0 = p0; i0 < p1; i0 += 2 * PB) {
-        if (i0 + PB < p1) load_unext(buf[1], i0 + PB);
-        step_top(buf[0], i0);
-        if (i0 + PB >= p1) break;
-        if (i0 + 2 * PB < p1) load_unext(buf[0], i0 + 2 * PB);
-        step_top(buf[1], i0 + PB);
-      }
-    }
+    // term at p1)
+    const int rt = twisted_top(dg, ee, Um, Lp, n, p0, p1, lk, pivmin, fabs(dm));
     // solve with the twist: x_rt = 1
     double* x = Dm;
-    for (int i = 0; i < n; ++i)
-      if (i < p0 || i > p1) x[(int64_t)i * n] = 0.0;
-    double xv = 1.0, nrm = 1.0;
-    {
-      double buf[2][PB];
-      // rows rt-1 down to p0: x_i = -l_i x_{i+1}
-      auto load_l = [&](double (&v)[PB], int i0) {
-#pragma unroll
-        for (int q = 0; q < PB; ++q) v[q] = (i0 - q >= p0) ? Lp[(int64_t)(i0 - q) * n] : 0.0;
-      };
-      auto step_l = [&](const double (&v)[PB], int i0) {
-#pragma unroll
-        for (int q = 0; q < PB; ++q) {
-          const int i = i0 - q;
-          if (i >= p0) {
-            xv = -v[q] * xv;
-            x[(int64_t)i * n] = xv;
-            nrm += xv * xv;
-          }
-        }
-      };
-      if (rt - 1 >= p0) load_l(buf[0], rt - 1);
-      for (int i0 = rt - 1; i0 >= p0; i0 -= 2 * PB) {
-        if (i0 - PB >= p0) load_l(buf[1], i0 - PB);
-        step_l(buf[0], i0);
-        if (i0 - PB < p0) break;
-        if (i0 - 2 * PB >= p0) load_l(buf[0], i0 - 2 * PB);
-        step_l(buf[1], i0 - PB);
-      }
-      x[(int64_t)rt * n] = 1.0;
-      xv = 1.0;
-      // rows rt+1 .. p1: x_{i+1} = -u_i x_i
-      auto load_u = [&](double (&v)[PB], int i0) {
-#pragma unroll
-        for (int q = 0; q < PB; ++q) v[q] = (i0 + q < p1) ? Um[(int64_t)(i0 + q) * n] : 0.0;
-      };
-      auto step_u = [&](const double (&v)[PB], int i0) {
-#pragma unroll
-        for (int q = 0; q < PB; ++q) {
-          const int i = i0 + q;
-          if (i < p1) {
-            xv = -v[q] * xv;
-            x[(int64_t)(i + 1) * n] = xv;
-            nrm += xv * xv;
-          }
-        }
-      };
-      if (rt < p1) load_u(buf[0], rt);
-      for (int i0 = rt; i0 < p1; i0 += 2 * PB) {
-        if (i0 + PB < p1) load_u(buf[1], i0 + PB);
-        step_u(buf[0], i0);
-        if (i0 + PB >= p1) break;
-        if (i0 + 2 * PB < p1) load_u(buf[0], i0 + 2 * PB);
-        step_u(buf[1], i0 + PB);
-      }
-    }
+    if (p0 > 0 || p1 < n - 1)
+      for (int i = 0; i < n; ++i)
+        if (i < p0 || i > p1) x[(int64_t)i * n] = 0.0;
+    const double nrm = twisted_solve(Lp, Um, x, n, p0, p1, rt);
     // the vector stays unscaled here: 1 / ||x|| goes to the first row of the
     // (no longer needed) U scratch, and PHASE 2 scales all columns at once
     // (a per-thread pass over its own column would serialise on the global
