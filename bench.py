@@ -191,6 +191,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (skip the autotuner)")
+    ap.add_argument("--tri-shape", type=int, default=None,
+                    help="fix the tridiagonalisation shape code (8, 12, 16, 108, 112) instead of tuning it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also copy the solver state once (library copy kernels of known size, for counter scaling)")
     args = ap.parse_args()
@@ -218,7 +220,9 @@ def main():
     prec = L.LRSTV_FP32 if args.precision == "fp32" else L.LRSTV_SPLIT_BF16
     solver = L.Solver(shapes, L.Params(precision=prec, **pkw))
     tuning = None
-    if not args.no_tune:
+    if args.tri_shape is not None:
+        solver.set_tuning(args.tri_shape)
+    elif not args.no_tune:
         tuning = solver.autotune(reps=2)   # before capture; the timed region replays the tuned shapes
     if not args.eager:
         solver.set_graph(True)
@@ -311,7 +315,8 @@ def main():
                                "mu0=1e-2 rho=1.5",
                    "precision": args.precision, "launch": "eager" if args.eager else "hipGraph replay",
                    "voxels": int(Y.numel()), "parallelism": "single GPU",
-                   "tuning": tuning if tuning is not None else "default shapes"},
+                   "tuning": tuning if tuning is not None else
+                   (f"fixed shape {args.tri_shape}" if args.tri_shape is not None else "default shapes")},
         "tsvt_slices_per_s": n_slices * args.steps / (svt_ms * 1e-3) if svt_ms > 0 else None,
         "kept_singular_value_fraction_last_iter": float(np.sum(ranks_last)) / kept_den,
         "stage_ms_per_iter": stages,
