@@ -1507,10 +1507,15 @@ reorth:
       if (k0 == k) continue;
       const int ck = k - c0, cb = k0 - c0, nc = k - k0;
       for (int pass = 0; pass < 2; ++pass) {
-        for (int j = threadIdx.x; j < nc; j += blockDim.x) {
-          double dt = 0.0;
-          for (int i = 0; i < n; ++i) dt += Xv[(int64_t)i * n + cb + j] * Xv[(int64_t)i * n + ck];
-          sdot[j] = dt;
+        // one wave per coefficient, its lanes over the rows
+        {
+          const int lane = threadIdx.x & 63, nwv = blockDim.x >> 6;
+          for (int j = threadIdx.x >> 6; j < nc; j += nwv) {
+            double dt = 0.0;
+            for (int i = lane; i < n; i += 64) dt += Xv[(int64_t)i * n + cb + j] * Xv[(int64_t)i * n + ck];
+            dt = wave_sum_dpp(dt);
+            if (lane == 0) sdot[j] = dt;
+          }
         }
         __syncthreads();
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -1529,29 +1534,39 @@ reorth:
     }
   }
   // V[:, c] = phase .* x for the c-th largest eigenvalue (times 1 / ||x||
-  // when it was not applied above), eight loads in flight per thread
+  // when it was not applied above).  A thread keeps one column (its scale
+  // loaded once) and every (blockDim / 256)-th row, eight loads in flight;
+  // the phases are staged in LDS (e^2 and e are no longer needed).
   float* Vr = V + d.v_off;
   float* Vi = Vr + nn;
-  const int tot = n * r;
-  for (int e0 = threadIdx.x; e0 < tot; e0 += U8 * blockDim.x) {
-    double xv[U8];
+  double* sphr = e2;
+  double* sphi = ee;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    sphr[i] = phr[i];
+    sphi[i] = phi[i];
+  }
+  __syncthreads();
+  const int ngr = blockDim.x >> 8;
+  for (int cb0 = 0; cb0 < r; cb0 += 256) {
+    const int c = cb0 + (threadIdx.x & 255);
+    if (c >= r) continue;
+    const int col = n - 1 - c - c0;
+    const double scl = cluster ? 1.0 : X[col];
+    for (int i0 = threadIdx.x >> 8; i0 < n; i0 += U8 * ngr) {
+      double xv[U8];
 #pragma unroll
-    for (int u = 0; u < U8; ++u) {
-      const int e = e0 + u * blockDim.x;
-      xv[u] = 0.0;
-      if (e < tot) {
-        const int i = e / r, c = e - i * r, col = n - 1 - c - c0;
-        xv[u] = Xv[(int64_t)i * n + col];
-        if (!cluster) xv[u] *= X[col];
+      for (int u = 0; u < U8; ++u) {
+        const int i = i0 + u * ngr;
+        xv[u] = i < n ? Xv[(int64_t)i * n + col] : 0.0;
       }
-    }
 #pragma unroll
-    for (int u = 0; u < U8; ++u) {
-      const int e = e0 + u * blockDim.x;
-      if (e < tot) {
-        const int i = e / r, c = e - i * r;
-        Vr[(int64_t)i * n + c] = (float)(phr[i] * xv[u]);
-        Vi[(int64_t)i * n + c] = (float)(phi[i] * xv[u]);
+      for (int u = 0; u < U8; ++u) {
+        const int i = i0 + u * ngr;
+        if (i < n) {
+          const double x = cluster ? xv[u] : xv[u] * scl;
+          Vr[(int64_t)i * n + c] = (float)(sphr[i] * x);
+          Vi[(int64_t)i * n + c] = (float)(sphi[i] * x);
+        }
       }
     }
   }
