@@ -1340,7 +1340,16 @@ __global__ void __launch_bounds__(PHASE == 1 ? 64 : (PHASE == 0 ? 256 : 1024)) k
       bstart[0] = 0;
       bstart[nb] = n;
       s_nblk = nb;
-      s_c0 = all ? 0 : (tnorm == 0.0) ? n : sturm_count_fast(dg, e2, n, lo_cut, pivmin);
+      // the count below the cut: computed once per slice by the eigenvalue
+      // phase, which publishes r = n - c0 in rcount (the kernels after the
+      // eigen-solve read the rank there); the later phases take it back
+      if (PHASE == 0) {
+        const int c0v = all ? 0 : (tnorm == 0.0) ? n : sturm_count_fast(dg, e2, n, lo_cut, pivmin);
+        s_c0 = c0v;
+        if (blockIdx.x == 0) rcount[slice] = n - c0v;
+      } else {
+        s_c0 = n - rcount[slice];
+      }
     }
   }
   __syncthreads();
