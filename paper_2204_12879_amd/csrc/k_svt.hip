@@ -1164,69 +1164,74 @@ LRSTV_DEV int twisted_top(const double* __restrict__ dg, const double* __restric
   return rt;
 }
 
-// Column x of a twisted solve with x_rt = 1 over rows [p0, p1], from the
-// factors L (rows below the twist) and U (rows above it); returns ||x||^2.
-// Rows are taken 32 at a time: a batch's factors are loaded (rows clamped
-// into the block, so every load is unconditional), the batch is solved in
-// registers, and its stores are issued after the next batch's loads, so that
-// waiting for those loads does not wait for the stores as well.  The three
-// columns are separate parts of one scratch array; restrict lets the loads
-// of a batch be issued while the stores of the previous one are in flight.
+// Column x of a twisted solve with x_rt = 1 over rows [p0, p1] (zero
+// outside), from the factors L (rows below the twist) and U (rows above it);
+// returns ||x||^2.  The lanes of a wave hold different eigenvalues, with
+// their own twist rows and blocks, so both sweeps run over rows common to
+// the wave (each lane masking its own range): every load and store of a
+// batch then touches one row of 64 consecutive columns.  The downward sweep
+// covers every row and stores unconditionally (its value, 1 at the twist, 0
+// elsewhere), which also clears the rows outside the block; the upward sweep
+// then stores the rows above the twist.  Rows are taken 32 at a time, the
+// next batch's loads issued before this batch's stores.
 LRSTV_DEV double twisted_solve(const double* __restrict__ Lp, const double* __restrict__ Um, double* __restrict__ x,
                                int n, int p0, int p1, int rt) {
   double nrm = 1.0;
   constexpr int XB = 32;
   double v[XB], xs[XB];
-  // rows rt-1 down to p0: x_i = -l_i x_{i+1}
+  // rows n-1 down to 0: x_i = -l_i x_{i+1} for p0 <= i < rt
   auto load_l = [&](int i0) {
 #pragma unroll
-    for (int q = 0; q < XB; ++q) v[q] = Lp[(int64_t)(i0 - q >= p0 ? i0 - q : p0) * n];
+    for (int q = 0; q < XB; ++q) v[q] = Lp[(int64_t)(i0 - q >= 0 ? i0 - q : 0) * n];
   };
   double xv = 1.0;
-  int i0 = rt - 1;
-  if (i0 >= p0) load_l(i0);
-  while (i0 >= p0) {
+  int i0 = n - 1;
+  load_l(i0);
+  while (i0 >= 0) {
 #pragma unroll
     for (int q = 0; q < XB; ++q) {
-      const bool in = i0 - q >= p0;
+      const int i = i0 - q;
+      const bool in = i >= p0 && i < rt;
       const double nx = -v[q] * xv;
       xv = in ? nx : xv;
       nrm += in ? nx * nx : 0.0;
-      xs[q] = xv;   // rows past p0 repeat x_p0, stored to row p0 below
+      xs[q] = in ? nx : (i == rt ? 1.0 : 0.0);
     }
     const int b0 = i0;
     i0 -= XB;
-    load_l(i0);   // unconditional (past the end every row clamps to p0)
+    load_l(i0);   // unconditional (past row 0 every row clamps to 0)
     __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the stores
-    // unconditional stores (a fixed count per batch keeps the wait for
-    // the next loads exact)
 #pragma unroll
-    for (int q = 0; q < XB; ++q) x[(int64_t)(b0 - q >= p0 ? b0 - q : p0) * n] = xs[q];
+    for (int q = 0; q < XB; ++q)
+      if (b0 - q >= 0) x[(int64_t)(b0 - q) * n] = xs[q];
   }
-  x[(int64_t)rt * n] = 1.0;
-  // rows rt+1 .. p1: x_{i+1} = -u_i x_i
+  // rows 0 .. n-2 upward: x_{i+1} = -u_i x_i for rt <= i < p1
   auto load_u = [&](int i0) {
 #pragma unroll
-    for (int q = 0; q < XB; ++q) v[q] = Um[(int64_t)(i0 + q < p1 ? i0 + q : p1 - 1) * n];
+    for (int q = 0; q < XB; ++q) v[q] = Um[(int64_t)(i0 + q < n - 1 ? i0 + q : n - 2) * n];
   };
   xv = 1.0;
-  i0 = rt;
-  if (i0 < p1) load_u(i0);
-  while (i0 < p1) {
+  i0 = 0;
+  if (n > 1) load_u(i0);
+  while (i0 < n - 1) {
 #pragma unroll
     for (int q = 0; q < XB; ++q) {
-      const bool in = i0 + q < p1;
+      const int i = i0 + q;
+      const bool in = i >= rt && i < p1;
       const double nx = -v[q] * xv;
       xv = in ? nx : xv;
       nrm += in ? nx * nx : 0.0;
-      xs[q] = xv;   // rows past p1 repeat x_p1, stored to row p1 below
+      xs[q] = nx;
     }
     const int b0 = i0;
     i0 += XB;
-    load_u(i0);   // unconditional (past the end every row clamps to p1 - 1)
+    load_u(i0);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int q = 0; q < XB; ++q) x[(int64_t)(b0 + q < p1 ? b0 + q + 1 : p1) * n] = xs[q];
+    for (int q = 0; q < XB; ++q) {
+      const int i = b0 + q;
+      if (i >= rt && i < p1) x[(int64_t)(i + 1) * n] = xs[q];
+    }
   }
   return nrm;
 }
@@ -1461,9 +1466,6 @@ __global__ void __launch_bounds__(PHASE == 1 ? 64 : (PHASE == 0 ? 256 : 1024)) k
     const int rt = twisted_top(dg, ee, Um, Lp, n, p0, p1, lk, pivmin, fabs(dm));
     // solve with the twist: x_rt = 1
     double* x = Dm;
-    if (p0 > 0 || p1 < n - 1)
-      for (int i = 0; i < n; ++i)
-        if (i < p0 || i > p1) x[(int64_t)i * n] = 0.0;
     const double nrm = twisted_solve(Lp, Um, x, n, p0, p1, rt);
     // the vector stays unscaled here: 1 / ||x|| goes to the first row of the
     // (no longer needed) U scratch, and PHASE 2 scales all columns at once
