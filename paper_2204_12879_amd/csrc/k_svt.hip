@@ -1270,11 +1270,26 @@ LRSTV_DEV void sturm_count_pair(const double* dg, const double* e2, int p0, int 
 // waves hide the latency of their sequential recurrences; PHASE 2
 // normalises them, re-orthogonalises clusters and writes V.  Each redoes the
 // O(n) set-up (scaling, splits, the count of eigenvalues below the cut).
+// Threads per eigenvalue in the eigenvalue phase (interior probe points of
+// each section step): 2 where the launch gives at least two waves per SIMD
+// (the phase is then bound by FP64 issue, and trisection needs the fewest
+// counts: about 22 rounds of 2 from the grid cell), 4 for smaller launches
+// (5-section, 15 rounds of 4).  Measured at 256x256x191: 0.60 -> 0.55 ms for
+// the 256-slice launch with 2; the 32 slices run beside the other group's
+// kernels and share its CUs, so fewer rounds at more counts did not pay
+// there (8 probes: 0.37 -> 1.10 ms).
+static int device_cus();
+static int eig_probes(int ns, int n) {
+  const long long waves2 = (long long)ns * n * 2 / 64;
+  const int simds = 4 * device_cus();
+  return waves2 >= 2 * simds ? 2 : 4;
+}
+
 template <int PHASE>
 __global__ void __launch_bounds__(PHASE == 1 ? 64 : (PHASE == 0 ? 256 : 1024)) k_trieig(const SliceDesc* __restrict__ desc, double* __restrict__ tri,
                                                  double* __restrict__ xs, float* __restrict__ V,
                                                  int* __restrict__ rcount, const double* __restrict__ mu_dev,
-                                                 double alpha, float thresh) {
+                                                 double alpha, float thresh, int probes) {
   extern __shared__ double smd[];
   __shared__ double red[16];
   __shared__ int s_c0, s_nblk;
@@ -1364,26 +1379,26 @@ __global__ void __launch_bounds__(PHASE == 1 ? 64 : (PHASE == 0 ? 256 : 1024)) k
     for (int k = c0 + threadIdx.x; k < n; k += blockDim.x) lam[k] = lam_g[k];
   }
   // Shared first step: the counts at G = blockDim points spread over
-  // [lo0, gu] bracket every eigenvalue in one grid cell.  Then 5-section:
-  // the 4 threads of a group probe 4 interior points of the cell, until it is
-  // below max(eps_64 |lambda|, 1e-13 ||T||) (the FP32 Gram resolves its
-  // eigenvalues to ~1e-7 ||T||; clusters are gaps below 1e-10 ||T||).  Fewer
-  // sequential rounds than bisection (15 against 34 from the grid cell) at
-  // 1.7 times the counts: the slices beyond the last full round, which run
-  // beside other work, are latency-bound.
+  // [lo0, gu] bracket every eigenvalue in one grid cell.  Then
+  // (probes + 1)-section: the probes threads of a group probe as many
+  // interior points of the cell, until it is below max(eps_64 |lambda|,
+  // 1e-13 ||T||) (the FP32 Gram resolves its eigenvalues to ~1e-7 ||T||;
+  // clusters are gaps below 1e-10 ||T||); probes from eig_probes.
   if (PHASE == 0) {
-    // block x takes the eigenvalues c0 + [64 x, 64 x + 64) (and every
-    // gridDim.x * 64-th block of them beyond), so that a slice's work spreads
-    // over several CUs and the launch balances around busy ones
-    const int G = blockDim.x, ngrp = blockDim.x >> 2, stride = ngrp * gridDim.x;
+    // block x takes the eigenvalues c0 + [E x, E x + E), E = blockDim /
+    // probes (and every gridDim.x * E-th block of them beyond), so that a
+    // slice's work spreads over several CUs and the launch balances around
+    // busy ones
+    const int PR = probes;
+    const int G = blockDim.x, ngrp = blockDim.x / PR, stride = ngrp * gridDim.x;
     if (blockIdx.x * ngrp >= r) return;
     const double lo0 = fmax(gl, lo_cut), cell = (gu - lo0) / G;
     gcnt[threadIdx.x] = sturm_count_fast(dg, e2, n, lo0 + (threadIdx.x + 1) * cell, pivmin);
     __syncthreads();
-    const int lane = threadIdx.x & 63, q = lane & 3, base = lane & ~3;
+    const int lane = threadIdx.x & 63, q = lane % PR, base = lane - q;
     const int nround = (r - blockIdx.x * ngrp + stride - 1) / stride;
     for (int rd = 0; rd < nround; ++rd) {
-      const int kk = (threadIdx.x >> 2) + blockIdx.x * ngrp + rd * stride;
+      const int kk = threadIdx.x / PR + blockIdx.x * ngrp + rd * stride;
       const bool act = kk < r;
       const int k = c0 + kk;
       // first grid point whose count exceeds k: lambda_k in [x_{j-1}, x_j)
@@ -1394,26 +1409,36 @@ __global__ void __launch_bounds__(PHASE == 1 ? 64 : (PHASE == 0 ? 256 : 1024)) k
         else jl = mid + 1;
       }
       double lo = lo0 + jl * cell, hi = lo0 + (jl + 1) * cell;
-      for (int it = 0; it < 64; ++it) {
+      for (int it = 0; it < 128; ++it) {
         const double wdt = hi - lo;
         const bool done = !act || wdt <= fmax(2.2e-16 * fmax(fabs(lo), fabs(hi)), 1e-13 * tnorm);
         if (__all(done)) break;
-        const double step = wdt * 0.2;
+        const double step = wdt * (1.0 / (PR + 1));
         const double x = lo + (q + 1) * step;
         const int cnt = done ? 0 : sturm_count_fast(dg, e2, n, x, pivmin);
-        const int c_0 = __shfl(cnt, base + 0, 64), c_1 = __shfl(cnt, base + 1, 64);
-        const int c_2 = __shfl(cnt, base + 2, 64), c_3 = __shfl(cnt, base + 3, 64);
+        // eigenvalue k lies in the first section whose upper count exceeds k
+        int j = PR;
+        for (int pp = PR - 1; pp >= 0; --pp)
+          if (__shfl(cnt, base + pp, 64) > k) j = pp;
         if (!done) {
-          // eigenvalue k lies where the count first exceeds k
-          const double x0 = lo + step, x1 = lo + 2 * step, x2 = lo + 3 * step, x3 = lo + 4 * step;
-          if (c_0 > k) { hi = x0; }
-          else if (c_1 > k) { lo = x0; hi = x1; }
-          else if (c_2 > k) { lo = x1; hi = x2; }
-          else if (c_3 > k) { lo = x2; hi = x3; }
-          else { lo = x3; }
+          const double nlo = lo + j * step;
+          hi = j < PR ? lo + (j + 1) * step : hi;
+          lo = nlo;
         }
       }
-      if (act && q == 0) lam_g[k] = 0.5 * (lo + hi);
+      // The value stored is canonical, independent of the search path (the
+      // probe count follows the launch size, and a cube must give the same
+      // result alone and in a batch): the midpoint of the cell of a fixed
+      // lattice of spacing h = 2^-43 ||T|| (above the stopping width, so
+      // that [lo, hi] holds at most one lattice point) that holds the
+      // eigenvalue, the cell decided by the count at that point.
+      const double h = 0x1p-43;   // T is scaled to ||T|| = 1
+      double cl = floor(lo / h) * h;
+      const double g = cl + h;
+      const bool gin = act && g <= hi;
+      const int cg = gin ? sturm_count_fast(dg, e2, n, g, pivmin) : 0;
+      if (gin && cg <= k) cl = g;   // lambda_k >= g
+      if (act && q == 0) lam_g[k] = cl + 0.5 * h;
     }
     return;
   }
@@ -2330,9 +2355,9 @@ static void launch_trivec(const SvtLaunch& L, hipStream_t s, size_t eig_lds, con
   const int ns = L.n_slices, n = L.max_n1;
   constexpr int VB = 64;
   hipLaunchKernelGGL(k_trieig<1>, dim3((n + VB - 1) / VB, ns), dim3(VB), eig_lds, s, L.desc, L.tri, L.xs, L.V,
-                     L.rcount, mu, L.alpha, thresh);
+                     L.rcount, mu, L.alpha, thresh, 0);
   hipLaunchKernelGGL(k_trieig<2>, dim3(ns), dim3(1024), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount, mu, L.alpha,
-                     thresh);
+                     thresh, 0);
 }
 
 static size_t tridiag_onchip_bytes(int n) {
@@ -2359,8 +2384,9 @@ static void svt_after_tridiag(const SvtLaunch& L, hipStream_t s, StageTimer& T) 
   const int TM = (m + kMT - 1) / kMT;
   const size_t eig_lds = (size_t)5 * n * sizeof(double) + (size_t)(n + 1 + 1024) * sizeof(int);
   T.begin(ST_TRIEIG);
-  hipLaunchKernelGGL(k_trieig<0>, dim3((n + 63) / 64, ns), dim3(256), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount, L.mu,
-                     L.alpha, L.thresh);
+  const int probes = eig_probes(ns, n), epb = 256 / probes;
+  hipLaunchKernelGGL(k_trieig<0>, dim3((n + epb - 1) / epb, ns), dim3(256), eig_lds, s, L.desc, L.tri, L.xs, L.V,
+                     L.rcount, L.mu, L.alpha, L.thresh, probes);
   T.end(ST_TRIEIG);
   T.begin(ST_TRIVEC);
   launch_trivec(L, s, eig_lds, L.mu, L.thresh);
@@ -2448,8 +2474,9 @@ void launch_svt_vjp(const SvtVjpLaunch& J, hipStream_t s) {
                        TT * (TT + 1) / 2, ns);
   launch_tridiag(L, s);
   const size_t eig_lds = (size_t)5 * n * sizeof(double) + (size_t)(n + 1 + 1024) * sizeof(int);
-  hipLaunchKernelGGL(k_trieig<0>, dim3((n + 63) / 64, ns), dim3(256), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount,
-                     (const double*)nullptr, 0.0, -1.f);
+  const int probes = eig_probes(ns, n), epb = 256 / probes;
+  hipLaunchKernelGGL(k_trieig<0>, dim3((n + epb - 1) / epb, ns), dim3(256), eig_lds, s, L.desc, L.tri, L.xs, L.V,
+                     L.rcount, (const double*)nullptr, 0.0, -1.f, probes);
   launch_trivec(L, s, eig_lds, nullptr, -1.f);
   launch_backtrans(L, s);
   // B = M V, C = D V (or U^H M, U^H D)
