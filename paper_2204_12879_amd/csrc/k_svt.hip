@@ -1259,17 +1259,6 @@ LRSTV_DEV void sturm_count_pair(const double* dg, const double* e2, int p0, int 
   }
 }
 
-// Eigenvalues above (t^2 - delta) of T / ||T|| by 5-section (4 threads per
-// eigenvalue, blocks of 256 threads over 64 eigenvalues), eigenvectors by twisted
-// factorisation inside their unreduced block, Gram-Schmidt inside clusters;
-// output column c = eigenvector of the c-th largest kept eigenvalue times the
-// phase (V re/im planes).
-// PHASE 0 computes the eigenvalues (kept in the tridiagonal scratch at 5n,
-// scaled by 1 / ||T||); PHASE 1 the eigenvectors from them, spread over
-// blocks of 64 eigenvalues (grid: vector blocks x slices), so that more
-// waves hide the latency of their sequential recurrences; PHASE 2
-// normalises them, re-orthogonalises clusters and writes V.  Each redoes the
-// O(n) set-up (scaling, splits, the count of eigenvalues below the cut).
 // Threads per eigenvalue in the eigenvalue phase (interior probe points of
 // each section step): 2 where the launch gives at least two waves per SIMD
 // (the phase is then bound by FP64 issue, and trisection needs the fewest
@@ -1285,6 +1274,18 @@ static int eig_probes(int ns, int n) {
   return waves2 >= 2 * simds ? 2 : 4;
 }
 
+// Eigenvalues above (t^2 - delta) of T / ||T|| by multisection (2 or 4
+// threads per eigenvalue, blocks of 256 threads), eigenvectors by twisted
+// factorisation inside their unreduced block, Gram-Schmidt inside clusters;
+// output column c = eigenvector of the c-th largest kept eigenvalue times the
+// phase (V re/im planes).
+// PHASE 0 computes the eigenvalues (kept in the tridiagonal scratch at 5n,
+// scaled by 1 / ||T||); PHASE 1 the eigenvectors from them, spread over
+// blocks of 64 eigenvalues (grid: vector blocks x slices), so that more
+// waves hide the latency of their sequential recurrences; PHASE 2
+// normalises them, re-orthogonalises clusters and writes V.  Each redoes the
+// O(n) set-up (scaling, splits); PHASE 0 also counts the eigenvalues below
+// the cut and publishes the rank, which the later phases read back.
 template <int PHASE>
 __global__ void __launch_bounds__(PHASE == 1 ? 64 : (PHASE == 0 ? 256 : 1024)) k_trieig(const SliceDesc* __restrict__ desc, double* __restrict__ tri,
                                                  double* __restrict__ xs, float* __restrict__ V,
