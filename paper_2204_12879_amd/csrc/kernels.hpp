@@ -126,7 +126,7 @@ void launch_band_idft(const float* slices, int n_t, float* E, int64_t e_stride, 
 
 // --- slice SVT ------------------------------------------------------------
 constexpr int kTriVariants = 5;   // tridiagonalisation shapes (codes 8, 12, 16, 112, 108)
-constexpr int kTriDefault = 4;
+constexpr int kTriDefault = 3;   // 112: register tiles, 12 waves (the tuned shape at 256 x 256)
 int tri_variant_code(int v);      // 100 kind + waves
 bool tri_variant_onchip(int v, int n);
 // thresh: t = alpha / mu read on the device (mu != NULL) or the fixed value.
