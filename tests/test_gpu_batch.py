@@ -6,6 +6,9 @@
 * Iterations replayed from a captured hipGraph are bit-identical to eager
   launches, also when eager work and synchronisations run between replays.
 * A few cubes of the 32-cube ragged workload match the FP64 oracle.
+* The t-SVT of a cube is the same alone and in a larger batch, whose
+  eigenvalue launch takes another search (trisection instead of 5-section):
+  the eigenvalues are stored canonically, independent of the search path.
 """
 import numpy as np
 import pytest
@@ -119,3 +122,16 @@ def test_ragged_cubes_match_oracle(idx):
     dps = abs(oracle.mpsnr(Xg.astype(np.float64), clean) - oracle.mpsnr(Xr, clean))
     say(f"rel err {err:.3e} dMPSNR {dps:.2e}")
     assert err <= 1e-4 and dps <= 0.01
+
+
+def test_svt_same_alone_and_in_a_larger_launch():
+    """96 slices of 256 x 256 alone (5-section) and as part of 288 (trisection)."""
+    L = _lib()
+    g = torch.Generator().manual_seed(11)
+    A = torch.randn(3, 191, 256, 256, generator=g).cuda()
+    say("svt: 1 cube alone, then in a batch of 3")
+    single = L.svt(A[1].contiguous(), 40.0)
+    batch = L.svt(A, 40.0)
+    torch.cuda.synchronize()
+    assert torch.isfinite(single).all()
+    assert torch.equal(batch[1], single)
