@@ -307,6 +307,69 @@ def test_admm_step_uses_the_blocks_in_order():
     assert new.mu == min(p.rho * st.mu, p.mu_max)
 
 
+def test_residuals_are_the_multiplier_increments_and_the_change_of_z():
+    """The residuals of an iteration, recomputed from two stored states of a
+    hand-driven run instead of from the iterate: the multiplier ascent adds mu
+    times each constraint violation (Algorithm 1, 6th step; Gamma4 by the same
+    rule), so ||O - L - S|| = ||Gamma1' - Gamma1|| / mu (also in the max
+    norm), ||L - Z|| from Gamma2, ||D_w Z - F|| from Gamma3, ||E - F|| from
+    Gamma4, and the dual residual is mu ||Z' - Z|| with the mu the iteration
+    used (before the 7th step raises it)."""
+    O, p, st = _tiny_problem(seed=10, shape=(5, 4, 3))
+    p.rho = 1.3
+    for _ in range(4):
+        new, L, res = oracle.admm_step(O, st, p)
+        mu = st.mu
+        d = [(new.G1 - st.G1) / mu, (new.G2 - st.G2) / mu, (new.G3 - st.G3) / mu, (new.G4 - st.G4) / mu]
+        assert res["inf_OLS"] == pytest.approx(np.abs(d[0]).max(), rel=1e-10)
+        assert res["inf_LZ"] == pytest.approx(np.abs(d[1]).max(), rel=1e-10)
+        assert res["fro_OLS"] == pytest.approx(np.linalg.norm(d[0]), rel=1e-10)
+        assert res["fro_LZ"] == pytest.approx(np.linalg.norm(d[1]), rel=1e-10)
+        assert res["fro_DZF"] == pytest.approx(np.linalg.norm(d[2]), rel=1e-10)
+        assert res["fro_EF"] == pytest.approx(np.linalg.norm(d[3]), rel=1e-10)
+        assert res["dual_Z"] == pytest.approx(mu * np.linalg.norm(new.Z - st.Z), rel=1e-12)
+        assert min(res.values()) > 0          # every residual is exercised
+        st = new
+
+
+def test_eps_stopping_ends_at_the_first_iteration_meeting_the_test():
+    """Algorithm 1's convergence check, max(||O-L-S||_inf, ||L-Z||_inf) <= eps
+    after an iteration, ends the run there: the stopping iteration is found
+    from a hand-driven run (its test quantity from the multiplier increments)
+    and admm(eps) must return exactly that many iterations and that L."""
+    clean, noisy = synth.make_cube(synth.CubeSpec(6, 5, 8, 4, synth.NOISE_SMALL, 13))
+    p = oracle.Params(tau=0.05, alpha=0.2, lam=0.3, mu0=0.05, rho=1.3)
+    K = 25
+    st = oracle.init_state(noisy, p.mu0)
+    q, Ls = [], []
+    for _ in range(K):
+        new, L, _ = oracle.admm_step(noisy, st, p)
+        q.append(max(np.abs(new.G1 - st.G1).max(), np.abs(new.G2 - st.G2).max()) / st.mu)
+        Ls.append(L)
+        st = new
+    q = np.array(q)
+    # record lows of the test quantity, clear of their predecessors, past the start
+    lows = [j for j in range(3, K - 2) if q[j] * (1 + 1e-6) < q[:j].min()]
+    assert len(lows) >= 3
+    for j in lows[:3] + lows[-1:]:
+        eps = q[j] * (1 + 1e-9)
+        X, S, st_e, hist = oracle.admm(noisy, p, K, eps=eps)
+        assert len(hist) == j + 1, (j, len(hist))
+        np.testing.assert_array_equal(X, Ls[j])
+    # the test is "<=": eps equal to the quantity at a record low stops there
+    _, _, _, full = oracle.admm(noisy, p, K)
+    j = lows[1]
+    eps = max(full[j]["inf_OLS"], full[j]["inf_LZ"])
+    assert eps == pytest.approx(q[j], rel=1e-12)
+    X, S, st_e, hist = oracle.admm(noisy, p, K, eps=eps)
+    assert len(hist) == j + 1
+    X, S, st_e, hist = oracle.admm(noisy, p, K, eps=q[0] * 2)      # met at once
+    assert len(hist) == 1
+    X, S, st_e, hist = oracle.admm(noisy, p, K, eps=q.min() * 0.5)  # never met
+    assert len(hist) == K
+    np.testing.assert_array_equal(X, Ls[-1])
+
+
 def test_constant_cube_is_a_fixed_point():
     O = np.full((6, 5, 4), 0.37)
     p = oracle.Params(tau=0.1, alpha=0.2, lam=0.3)
