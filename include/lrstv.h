@@ -129,8 +129,17 @@ int lrstv_reset(lrstv_handle hd, const float* Y);
 /* Run n_iter ADMM iterations (Sec. III-C steps 1-7).  If `residuals` is not
  * NULL it is a device array of n_iter * n_cubes * LRSTV_NRES doubles that
  * receives [iter][cube][LRSTV_NRES].  Asynchronous; no host sync.
- * Errors: INVALID_ARG, HIP. */
+ * A non-finite residual latches a device flag (until lrstv_reset); after the
+ * iterations the flag is copied to host memory asynchronously, and any later
+ * lrstv_iterate / lrstv_read_output whose copy has already landed returns
+ * ERR_NONFINITE without running (lrstv_check waits for it).
+ * Errors: INVALID_ARG, NONFINITE, HIP. */
 int lrstv_iterate(lrstv_handle hd, int32_t n_iter, double* residuals);
+
+/* Synchronise with the last lrstv_iterate's copy of the non-finite flag and
+ * return ERR_NONFINITE if an iteration since the last reset met a NaN/Inf
+ * residual (an input with NaN/Inf does), else OK. */
+int lrstv_check(lrstv_handle hd);
 
 /* Replay iterations from a hipGraph of one iteration captured on the
  * handle's stream (enable = 1; captured on first use) or launch them one by
@@ -139,7 +148,8 @@ int lrstv_iterate(lrstv_handle hd, int32_t n_iter, double* residuals);
 int lrstv_set_graph(lrstv_handle hd, int32_t enable);
 
 /* Copy X = L of the last iteration and S into caller buffers (device,
- * packed batch).  Either may be NULL.  Asynchronous. */
+ * packed batch).  Either may be NULL.  Asynchronous.  Returns ERR_NONFINITE
+ * (copying nothing) when the non-finite latch is already known to be set. */
 int lrstv_read_output(lrstv_handle hd, float* X, float* S);
 
 /* reset + iterate until max{||Y-X-S||_inf, ||X-Z||_inf} <= eps for every

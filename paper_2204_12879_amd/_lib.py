@@ -81,6 +81,7 @@ def load_library():
         "lrstv_svt": (C.c_int, [vp, vp, i32, i32, i32, i32, f32, i32, vp, C.c_size_t, vp]),
         "lrstv_zsolve_workspace_size": (C.c_int, [i32, i32, i32, sz]),
         "lrstv_zsolve": (C.c_int, [vp, vp, i32, i32, i32, f64, C.POINTER(C.c_double), vp, C.c_size_t, vp]),
+        "lrstv_check": (C.c_int, [vp]),
         "lrstv_profile": (C.c_int, [vp, i32]),
         "lrstv_set_graph": (C.c_int, [vp, i32]),
         "lrstv_stage_times": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32), i32]),
@@ -239,6 +240,11 @@ class Solver:
     def iterate(self, n: int, residuals=None) -> None:
         _check(self.lib.lrstv_iterate(self.handle, int(n),
                                       C.c_void_p(_ptr(residuals)) if residuals is not None else None))
+
+    def check(self) -> None:
+        """Raise LrstvError (ERR_NONFINITE) if an iteration since the last
+        reset met a non-finite residual (waits for the latest flag copy)."""
+        _check(self.lib.lrstv_check(self.handle))
 
     def read_output(self, X=None, S=None) -> None:
         _check(self.lib.lrstv_read_output(self.handle, C.c_void_p(_ptr(X)) if X is not None else None,

@@ -147,7 +147,16 @@ struct lrstv_handle_s {
   hipGraphExec_t gexec = nullptr;
   // second stream of the slice SVT (the slices beyond the last full round)
   SvtSplit split;
+  // Non-finite latch: k_finish_iter sets *flag; after every lrstv_iterate
+  // the flag is copied to pinned host memory asynchronously and the copy
+  // marked by flag_ev, so that a later call can see it without a sync.
+  int* flag_host = nullptr;
+  hipEvent_t flag_ev = nullptr;
+  bool flag_pending = false;   // a copy has been enqueued since the last reset
+  bool flag_known = false;     // a completed copy read 1
   ~lrstv_handle_s() {
+    if (flag_ev) (void)hipEventDestroy(flag_ev);
+    if (flag_host) (void)hipHostFree(flag_host);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     if (split.fork) (void)hipEventDestroy(split.fork);
@@ -344,8 +353,34 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
       return fail(LRSTV_ERR_HIP, "creating the second stream: %s", hipGetErrorString(e));
     }
   }
+  e = hipHostMalloc((void**)&H->flag_host, sizeof(int), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&H->flag_ev, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    delete H;
+    return fail(LRSTV_ERR_HIP, "creating the non-finite latch: %s", hipGetErrorString(e));
+  }
+  *H->flag_host = 0;
+  launch_fill((float*)H->flag, 1, 0.f, H->stream);   // the bit pattern of int 0
   launch_set_mu(H->mu, par->mu0, H->stream);
   *out = H;
+  return LRSTV_OK;
+}
+
+// True when a completed copy of the device latch has shown a non-finite
+// residual since the last reset (no synchronisation).
+static bool nonfinite_seen(lrstv_handle_s* H) {
+  if (H->flag_pending && hipEventQuery(H->flag_ev) == hipSuccess) {
+    H->flag_pending = false;
+    H->flag_known = H->flag_known || *H->flag_host != 0;
+  }
+  return H->flag_known;
+}
+
+// Enqueue the copy of the device latch behind the work already queued.
+static int post_flag_copy(lrstv_handle_s* H) {
+  HIPCHK(hipMemcpyAsync(H->flag_host, H->flag, sizeof(int), hipMemcpyDeviceToHost, H->stream));
+  HIPCHK(hipEventRecord(H->flag_ev, H->stream));
+  H->flag_pending = true;
   return LRSTV_OK;
 }
 
@@ -366,6 +401,11 @@ extern "C" int lrstv_reset(lrstv_handle H, const float* Y) {
   launch_fill(H->G3, 3 * T, 0.f, s);
   launch_fill(H->G4, 3 * T, 0.f, s);
   launch_set_mu(H->mu, H->par.mu0, s);
+  launch_fill((float*)H->flag, 1, 0.f, s);
+  // copies enqueued before this reset are no longer looked at: the next
+  // lrstv_iterate enqueues a copy behind them and re-records the event
+  H->flag_pending = false;
+  H->flag_known = false;
   HIPCHK(hipGetLastError());
   return LRSTV_OK;
 }
@@ -499,6 +539,8 @@ extern "C" int lrstv_set_graph(lrstv_handle H, int32_t enable) {
 extern "C" int lrstv_iterate(lrstv_handle H, int32_t n_iter, double* residuals) {
   if (!H) return fail(LRSTV_ERR_INVALID_ARG, "handle is NULL");
   if (n_iter < 0) return fail(LRSTV_ERR_INVALID_ARG, "n_iter must be >= 0");
+  if (nonfinite_seen(H))
+    return fail(LRSTV_ERR_NONFINITE, "an earlier iteration met a non-finite residual (latched until reset)");
   const int nc = (int)H->cubes.size();
   if (H->graph_on && !H->timer.on) {
     int rc = ensure_graph(H);
@@ -514,11 +556,20 @@ extern "C" int lrstv_iterate(lrstv_handle H, int32_t n_iter, double* residuals) 
       run_iteration(H, residuals ? residuals + (int64_t)it * nc * R_COUNT : nullptr);
   }
   HIPCHK(hipGetLastError());
+  return n_iter > 0 ? post_flag_copy(H) : LRSTV_OK;
+}
+
+extern "C" int lrstv_check(lrstv_handle H) {
+  if (!H) return fail(LRSTV_ERR_INVALID_ARG, "handle is NULL");
+  if (H->flag_pending) HIPCHK(hipEventSynchronize(H->flag_ev));
+  if (nonfinite_seen(H)) return fail(LRSTV_ERR_NONFINITE, "an iteration met a non-finite residual");
   return LRSTV_OK;
 }
 
 extern "C" int lrstv_read_output(lrstv_handle H, float* X, float* S) {
   if (!H) return fail(LRSTV_ERR_INVALID_ARG, "handle is NULL");
+  if (nonfinite_seen(H))
+    return fail(LRSTV_ERR_NONFINITE, "an earlier iteration met a non-finite residual (latched until reset)");
   if (X) launch_copy(X, H->L, H->total, H->stream);
   if (S) launch_copy(S, H->S, H->total, H->stream);
   HIPCHK(hipGetLastError());

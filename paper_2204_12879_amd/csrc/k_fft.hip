@@ -862,7 +862,7 @@ LRSTV_DEV void band_idft_body(int bid, int nblk, const float* __restrict__ X, in
   const int TM = (b + kMT - 1) / kMT, TN = (hw + kMT - 1) / kMT;
   const int ntiles = n_t * TM * TN;
   const int grp = threadIdx.x >> 8, t = threadIdx.x & 255, wv = t >> 6;
-  float acc = 0.f;   // per-thread partial of (E - F)^2 (FP64 from the block sum on)
+  double acc = 0.0;   // per-thread partial of (E - F)^2 in FP64
   for (int base = bid * G; base < ntiles; base += nblk * G) {   // same trip count in every group
     const int tile = base + grp < ntiles ? base + grp : ntiles - 1;
     const bool tv = base + grp < ntiles;
@@ -914,7 +914,7 @@ LRSTV_DEV void band_idft_body(int bid, int nblk, const float* __restrict__ X, in
         if (G4t) {
           const float f = fv[ri];
           G4t[q] = gv[ri] + mu * (e - f);
-          const float d = e - f;
+          const double d = (double)e - (double)f;
           acc += d * d;
         }
       }
@@ -923,7 +923,7 @@ LRSTV_DEV void band_idft_body(int bid, int nblk, const float* __restrict__ X, in
     mfma_rtile_t<true, false, true>(t, m0, n0, K2, fa, fb, sto, sm[grp], active);
   }
   if (part) {
-    const double tot = block_sum((double)acc, red);
+    const double tot = block_sum(acc, red);
     if (threadIdx.x == 0) part[R_FRO_EF * LRSTV_PARTS + bid] = tot;
   }
 }

@@ -107,9 +107,9 @@ LRSTV_DEV void grad_shrink_body(
   const float mu = (float)mud, imu = (float)(1.0 / mud);
   const float tmu = (float)(tau / mud), lmu = (float)(lam / mud);
   const float wn[3] = {w1, w2, w3};
-  // per-thread partials in FP32 (about N / (nblk blockDim) terms each), the
-  // block and grid reductions in FP64
-  float m_ols = 0.f, m_lz = 0.f, s_ols = 0.f, s_lz = 0.f, s_dzf = 0.f;
+  // maxima in FP32 (exact), sums of squares in FP64 from the first term on
+  float m_ols = 0.f, m_lz = 0.f;
+  double s_ols = 0.0, s_lz = 0.0, s_dzf = 0.0;
   // (x, i, j) of q advanced incrementally by the grid stride (no divisions
   // per element): stride = dz h w + dy w + dx with dx < w, dy < h
   const int64_t q0 = bid * (int64_t)blockDim.x + threadIdx.x, stride = (int64_t)nblk * blockDim.x;
@@ -128,7 +128,7 @@ LRSTV_DEV void grad_shrink_body(
       F[o3] = f;
       G3[o3] = g3 + mu * (g - f);
       A[n * as + q] = f - g4 * imu;
-      const float d = g - f;
+      const double d = (double)g - (double)f;
       s_dzf += d * d;
     }
     G2[q] = G2[q] + mu * (l - z);
@@ -139,8 +139,8 @@ LRSTV_DEV void grad_shrink_body(
     G1[q] = g1 + mu * r;
     m_ols = fmaxf(m_ols, fabsf(r));
     m_lz = fmaxf(m_lz, fabsf(dz2));
-    s_ols += r * r;
-    s_lz += dz2 * dz2;
+    s_ols += (double)r * (double)r;
+    s_lz += (double)dz2 * (double)dz2;
     x += dx;
     if (x >= w) { x -= w; ++i; }
     i += dy;
@@ -149,9 +149,9 @@ LRSTV_DEV void grad_shrink_body(
   }
   const double bm_ols = block_max((double)m_ols, red);
   const double bm_lz = block_max((double)m_lz, red);
-  const double bs_ols = block_sum((double)s_ols, red);
-  const double bs_lz = block_sum((double)s_lz, red);
-  const double bs_dzf = block_sum((double)s_dzf, red);
+  const double bs_ols = block_sum(s_ols, red);
+  const double bs_lz = block_sum(s_lz, red);
+  const double bs_dzf = block_sum(s_dzf, red);
   if (threadIdx.x == 0) {
     part[R_INF_OLS * LRSTV_PARTS + bid] = bm_ols;
     part[R_INF_LZ * LRSTV_PARTS + bid] = bm_lz;
