@@ -10,7 +10,13 @@ library's stream) and a `cpu_baseline` entry (the FP64 oracle timed on a
 bounded sample on this host).
 
     python bench.py [--steps K] [--warmup W] [--workload wdc|pavia|small]
-                    [--precision fp32|bf16] [--no-cpu]
+                    [--precision fp32|bf16] [--no-cpu] [--no-bf16-leg]
+
+The timed region is the last K iterations of the configuration's 50-iteration
+solve (iterations 51-K .. 50 after a reset), so that early iterations, in
+which most slices deflate to rank 0, do not flatter the rate; the error
+against the stored FP64 oracle samples is taken at iteration 50 every time.
+A split-BF16 leg (same window) is reported beside the FP32 line.
 """
 import argparse
 import json
@@ -179,14 +185,89 @@ def adjoint_bench(reps=3):
             "note": "includes solver set-up and checkpoint copies; median of %d" % reps}
 
 
+K_CONFIG = 50   # iterations of the headline configuration (256x256x191, 50 ADMM iterations)
+
+
+def run_leg(L, shapes, Y, pkw, prec, steps, warmup, eager, tri_shape, no_tune, k_run):
+    """One precision: the k_run-iteration solve from the initial state, of
+    which the last `steps` iterations are timed (graph replay, events on the
+    library's stream), then the same window again eager with per-stage
+    events.  Returns the measurements and X = L of the last iteration."""
+    import numpy as np
+    import torch
+    solver = L.Solver(shapes, L.Params(precision=prec, **pkw))
+    tuning = None
+    if tri_shape is not None:
+        solver.set_tuning(tri_shape)
+    elif not no_tune:
+        tuning = solver.autotune(reps=2)   # before capture; the timed region replays the tuned shapes
+    if not eager:
+        solver.set_graph(True)
+    X = torch.empty_like(Y)
+    # warm-up (untimed)
+    solver.reset(Y)
+    solver.iterate(warmup)
+    torch.cuda.synchronize()
+    # the solve from its initial state; iterations k_run - steps + 1 .. k_run timed
+    solver.reset(Y)
+    solver.iterate(k_run - steps)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    solver.iterate(steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    elapsed = max(wall, gpu_ms / 1e3)
+    solver.read_output(X=X)
+    torch.cuda.synchronize()
+    ranks_last = solver.slice_ranks()
+    # per-stage timing over the same window (separate eager, instrumented run)
+    solver.reset(Y)
+    solver.iterate(k_run - steps)
+    solver.profile(True)
+    solver.iterate(steps)
+    st = solver.stage_times()
+    solver.profile(False)
+    ranks_prof = solver.slice_ranks()
+    return {"solver": solver, "elapsed": elapsed, "X": X, "ranks_last": ranks_last, "stages": st,
+            "ranks_prof": ranks_prof, "tuning": tuning}
+
+
+def sampled_error(X, workload, k_run):
+    """Relative error of X = L^(50) against the stored FP64 oracle samples."""
+    import numpy as np
+    if k_run != K_CONFIG:
+        return None
+    names = {"wdc": "wdc_k50_oracle_samples.npz", "pavia": "pavia_k50_oracle_samples.npz"}
+    if workload not in names:
+        return None
+    gold = os.path.join(ROOT, "tests", "golden", names[workload])
+    if not os.path.exists(gold):
+        return None
+    g = np.load(gold)
+    Xg = X.cpu().numpy().astype(np.float64)
+    idx, ref = g["index"], g["values"]
+    return float(np.linalg.norm(Xg[idx] - ref) / np.linalg.norm(ref))
+
+
+def gram_flops(shapes):
+    """FP32-equivalent flops of the packed Hermitian Grams of one iteration."""
+    return sum(3 * (b // 2 + 1) * 4.0 * max(h, w) * min(h, w) * (min(h, w) + 1) for b, h, w in shapes)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20,
+                    help="timed iterations: the last STEPS of the 50-iteration solve")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="wdc", choices=["wdc", "pavia", "small", "ragged"])
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one instead of graph replay")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--no-bf16-leg", action="store_true", help="skip the split-BF16 comparison leg")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--no-adjoint", action="store_true")
@@ -199,6 +280,9 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (the single-GPU share of the workload); "
               "--gpus above 1 is not supported", file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1:
+        print("bench.py: --steps must be >= 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -218,39 +302,17 @@ def main():
     lam = 10.0 / np.sqrt(hw_ref)
     pkw = dict(tau=0.02, alpha=0.3, lam=lam, w=(1.0, 1.0, 1.0), mu0=1e-2, rho=1.5, mu_max=1e6)
     prec = L.LRSTV_FP32 if args.precision == "fp32" else L.LRSTV_SPLIT_BF16
-    solver = L.Solver(shapes, L.Params(precision=prec, **pkw))
-    tuning = None
-    if args.tri_shape is not None:
-        solver.set_tuning(args.tri_shape)
-    elif not args.no_tune:
-        tuning = solver.autotune(reps=2)   # before capture; the timed region replays the tuned shapes
-    if not args.eager:
-        solver.set_graph(True)
+    k_run = max(K_CONFIG, args.steps)
     Y = torch.from_numpy(np.concatenate([c[1].astype(np.float32).ravel() for c in cubes])).cuda()
-    X = torch.empty_like(Y)
     clean, noisy = cubes[0]
-    print(f"bench: {args.workload} {len(shapes)} cube(s), {Y.numel()} voxels, steps={args.steps} "
-          f"warmup={args.warmup}", file=sys.stderr, flush=True)
+    print(f"bench: {args.workload} {len(shapes)} cube(s), {Y.numel()} voxels, iterations "
+          f"{k_run - args.steps + 1}..{k_run} of {k_run} timed, warmup={args.warmup}", file=sys.stderr, flush=True)
 
-    # warm-up (untimed)
-    solver.reset(Y)
-    solver.iterate(args.warmup)
-    torch.cuda.synchronize()
-    # timed: K iterations of the solve from its initial state
-    solver.reset(Y)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record()
-    solver.iterate(args.steps)
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    elapsed = max(wall, gpu_ms / 1e3)
-    solver.read_output(X=X)
-    torch.cuda.synchronize()
-    ranks_last = solver.slice_ranks()
+    leg = run_leg(L, shapes, Y, pkw, prec, args.steps, args.warmup, args.eager, args.tri_shape, args.no_tune,
+                  k_run)
+    solver, elapsed, X, st = leg["solver"], leg["elapsed"], leg["X"], leg["stages"]
+    print(f"bench: {args.precision} leg done ({1e3 * elapsed / args.steps:.3f} ms per iteration)",
+          file=sys.stderr, flush=True)
 
     if args.copy_calibration:
         # 16 state cubes through k_copy: 4 launches of N floats, 4 of 3N floats
@@ -260,14 +322,7 @@ def main():
         print(f"bench: copy calibration, {solver.total * 4} and {solver.total * 12} bytes per launch",
               file=sys.stderr, flush=True)
 
-    # per-stage timing (separate instrumented run of the same K iterations)
-    solver.reset(Y)
-    solver.profile(True)
-    solver.iterate(args.steps)
-    st = solver.stage_times()
-    solver.profile(False)
-    ranks_prof = solver.slice_ranks()
-    model = stage_model(shapes, ranks_prof)
+    model = stage_model(shapes, leg["ranks_prof"])
     dom = max(st, key=lambda k: st[k][0])
     dom_ms, dom_n = st[dom]
     avg_ms = dom_ms / max(dom_n, 1)
@@ -290,11 +345,13 @@ def main():
                                                                   + 5 * 8 * min(h, w)) for b, h, w in shapes))
     roof["kernel"] = dom if dom != "tridiag" else f"tridiag (shape {shape_code})"
     roof["avg_launch_ms"] = avg_ms
+    roof["window"] = f"iterations {k_run - args.steps + 1}..{k_run} of {k_run}"
     svt_stages = ["gram", "tridiag", "trieig", "trivec", "backtrans", "bp1", "colnorm", "bp2"]
     svt_ms = sum(st[k][0] for k in svt_stages)
     n_slices = sum(3 * (s[0] // 2 + 1) for s in shapes)
     stages = {k: round(v[0] / args.steps, 4) for k, v in st.items()}
     kept_den = sum(3 * (s[0] // 2 + 1) * min(s[1], s[2]) for s in shapes)
+    gflop = gram_flops(shapes)
 
     out = {
         "metric": METRIC,
@@ -311,25 +368,39 @@ def main():
         "data": "synthetic",
         "config": {"workload": (f"{args.workload} {spec.h}x{spec.w}x{spec.b} single cube" if len(shapes) == 1 else
                                 f"{args.workload} batch of {len(shapes)} cubes (h, w in [48, 160], b in [31, 191])") +
-                               ", ADMM iterations from the initial state, tau=0.02 alpha=0.3 lambda=10/sqrt(hw) "
-                               "mu0=1e-2 rho=1.5",
+                               f", {k_run}-iteration ADMM solve from the initial state, the last {args.steps} "
+                               f"iterations ({k_run - args.steps + 1}..{k_run}) timed; tau=0.02 alpha=0.3 "
+                               "lambda=10/sqrt(hw) mu0=1e-2 rho=1.5",
                    "precision": args.precision, "launch": "eager" if args.eager else "hipGraph replay",
                    "voxels": int(Y.numel()), "parallelism": "single GPU",
-                   "tuning": tuning if tuning is not None else
+                   "tuning": leg["tuning"] if leg["tuning"] is not None else
                    (f"fixed shape {args.tri_shape}" if args.tri_shape is not None else "default shapes")},
         "tsvt_slices_per_s": n_slices * args.steps / (svt_ms * 1e-3) if svt_ms > 0 else None,
-        "kept_singular_value_fraction_last_iter": float(np.sum(ranks_last)) / kept_den,
+        "kept_singular_value_fraction_last_iter": float(np.sum(leg["ranks_last"])) / kept_den,
         "stage_ms_per_iter": stages,
+        "gram_tflops_fp32_equiv": gflop / (st["gram"][0] / args.steps * 1e-3) / 1e12 if st["gram"][0] > 0 else None,
         "roofline": roof,
     }
-    if args.workload == "wdc" and args.steps == 50:
-        gold = os.path.join(ROOT, "tests", "golden", "wdc_k50_oracle_samples.npz")
-        if os.path.exists(gold):
-            g = np.load(gold)
-            Xg = X.cpu().numpy().astype(np.float64)
-            idx = g["index"]
-            ref = g["values"]
-            out["rel_err_vs_oracle_sampled"] = float(np.linalg.norm(Xg[idx] - ref) / np.linalg.norm(ref))
+    out["rel_err_vs_oracle_sampled"] = sampled_error(X, args.workload, k_run)
+    del leg, solver
+    if not args.no_bf16_leg and prec == L.LRSTV_FP32 and len(shapes) == 1:
+        b16 = run_leg(L, shapes, Y, pkw, L.LRSTV_SPLIT_BF16, args.steps, args.warmup, args.eager, args.tri_shape,
+                      args.no_tune, k_run)
+        gms = b16["stages"]["gram"][0] / args.steps
+        hw_flops = 3.0 * gflop   # three BF16 products (hi*hi, hi*lo, lo*hi) per FP32-equivalent product
+        out["split_bf16"] = {
+            "value": args.steps / b16["elapsed"], "unit": "iters/s",
+            "ms_per_step": 1e3 * b16["elapsed"] / args.steps,
+            "rel_err_vs_oracle_sampled": sampled_error(b16["X"], args.workload, k_run),
+            "gram_ms_per_iter": gms,
+            "gram_tflops_fp32_equiv": gflop / (gms * 1e-3) / 1e12 if gms > 0 else None,
+            "gram_bf16_hw_tflops": hw_flops / (gms * 1e-3) / 1e12 if gms > 0 else None,
+            "gram_bf16_frac_of_peak": hw_flops / (gms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS if gms > 0 else None,
+            "stage_ms_per_iter": {k: round(v[0] / args.steps, 4) for k, v in b16["stages"].items()},
+            "window": f"iterations {k_run - args.steps + 1}..{k_run} of {k_run}, same as the FP32 line",
+        }
+        print("bench: split-BF16 leg done", file=sys.stderr, flush=True)
+        del b16
     if not args.no_adjoint and args.workload == "wdc":
         print("bench: timing the adjoint workload", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_bench()
