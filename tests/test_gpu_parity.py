@@ -260,6 +260,67 @@ def test_small_cube_full_run_matches_oracle():
     assert err <= 1e-4 and dpsnr <= 0.01
 
 
+def _kept_fraction_of_output(E):
+    """Fraction of Fourier singular values an E-step kept: the SVT output of a
+    slice has rank equal to the number of singular values above the
+    threshold, so count the non-negligible singular values of the
+    non-redundant Fourier slices of each tensor E_n."""
+    kept = tot = 0
+    for n in range(E.shape[0]):
+        Eh = np.fft.fft(E[n], axis=0)
+        for k in range(E.shape[1] // 2 + 1):
+            sv = np.linalg.svd(Eh[k], compute_uv=False)
+            kept += int((sv > 1e-9 * max(sv.max(), 1e-300)).sum())
+            tot += sv.size
+    return kept / tot
+
+
+def test_small_cube_full_run_in_the_thresholding_regime():
+    """32x32x16 cube, 20 iterations with alpha = 3 (the penalty schedule of the
+    other runs), so that at the last iteration the t-SVT keeps 5-50 % of the
+    Fourier singular values instead of nearly all of them: every element of
+    X, S, Z, F, E and the four multipliers against the oracle's.  X, S, Z, F
+    and Gamma1..3 within 1e-4 relative (Frobenius), E within 1e-4, Gamma4 on
+    the scale mu ||E|| of what it gains per iteration; |dMPSNR| <= 0.01 dB."""
+    L = _lib()
+    wl = synth.workload("small")
+    spec = wl.cubes[0]
+    clean, noisy = synth.make_cube(spec)
+    O = noisy.astype(np.float32).astype(np.float64)
+    p = oracle.default_params(spec.h, spec.w, tau=0.02, alpha=3.0)
+    say("thresholding regime, small cube, alpha", p.alpha)
+    Xr, Sr, st, hist = oracle.admm(O, p, wl.iters)
+    kept_ref = _kept_fraction_of_output(st.E)
+    solver = L.Solver([(spec.b, spec.h, spec.w)], L.Params(tau=p.tau, alpha=p.alpha, lam=p.lam))
+    Y = torch.from_numpy(noisy.astype(np.float32)).cuda().reshape(-1)
+    solver.reset(Y)
+    solver.iterate(wl.iters)
+    ranks = np.array(solver.slice_ranks())
+    got = {k: v.cpu().numpy().astype(np.float64) for k, v in solver.state().items()}
+    torch.cuda.synchronize()
+    kept = ranks.sum() / (ranks.size * min(spec.h, spec.w))
+    fnz = float(np.mean(got["F"] != 0))
+    snz = float(np.mean(got["S"] != 0))
+    say(f"  kept singular values {kept:.3f} (oracle {kept_ref:.3f}), nonzero F {fnz:.3f}, nonzero S {snz:.3f}")
+    assert 0.05 <= kept_ref <= 0.5 and 0.05 <= kept <= 0.5
+    assert abs(kept - kept_ref) <= 0.01
+    assert 0.01 < fnz < 0.99 and 0.01 < snz < 0.99
+    mu_last = st.mu / p.rho
+    refs = {"X": Xr, "S": st.S, "Z": st.Z, "F": st.F, "E": st.E, "G1": st.G1, "G2": st.G2, "G3": st.G3,
+            "G4": st.G4}
+    for k, ref in refs.items():
+        g = got[k].reshape(ref.shape)
+        if k == "G4":
+            err = float(np.linalg.norm(g - ref)) / (mu_last * np.linalg.norm(st.E))
+        else:
+            err = rel(g, ref)
+        say(f"  {k}: {err:.2e}")
+        assert err <= 1e-4, (k, err)
+    dpsnr = abs(oracle.mpsnr(got["X"].reshape(Xr.shape), clean) - oracle.mpsnr(Xr, clean))
+    say(f"  dMPSNR {dpsnr:.2e} dB")
+    assert dpsnr <= 0.01
+
+
 @pytest.mark.parametrize("name", ["pavia", "wdc"])
 def test_full_size_run_matches_stored_oracle_samples(name):
     """200x200x160 and 256x256x191 cubes, 50 iterations (the benchmark's launch
