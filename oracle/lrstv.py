@@ -30,7 +30,13 @@ notes):
   * the L-update at full Tucker rank is the unconstrained minimiser (HOOI of a
     full-rank Tucker model returns its input);
   * initial state: Z = O, every other variable 0, mu = mu0;
-  * the multipliers use the mu of the current iteration, then mu is raised.
+  * the multipliers use the mu of the current iteration, then mu is raised;
+  * the isotropic regulariser (Sec. III-A, eq. CRSSTV_iso) is read per voxel:
+    its l2 norm couples the three directional differences of one voxel, so
+    the F-update group-thresholds each voxel's 3-vector with the same tau/mu
+    (the print puts the square root over the whole tensor, which would not
+    promote sparse gradients; the paper introduces the isotropic form as the
+    l2 counterpart of the anisotropic l1 TV).
 
 Parity pins for every function live in tests/test_oracle_pins.py.
 """
@@ -52,6 +58,16 @@ AXIS = (1, 2, 0)
 def soft(x: np.ndarray, t: float) -> np.ndarray:
     """Soft-thresholding R_t (Sec. III-C, F-update): the prox of t*|.|."""
     return np.sign(x) * np.maximum(np.abs(x) - t, 0.0)
+
+
+def group_soft(U: np.ndarray, t: float) -> np.ndarray:
+    """Group soft-thresholding across the leading axis: each vector
+    u = U[:, i] becomes max(1 - t / ||u||_2, 0) u, the prox of t*||.||_2
+    (the F-update of the isotropic regulariser, Sec. III-A, eq. CRSSTV_iso,
+    read per voxel)."""
+    nrm = np.sqrt((U ** 2).sum(axis=0))
+    scale = np.where(nrm > t, 1.0 - t / np.where(nrm > 0, nrm, 1.0), 0.0)
+    return U * scale[None]
 
 
 def svt_matrix(M: np.ndarray, t: float) -> np.ndarray:
@@ -142,6 +158,7 @@ class Params:
     mu0: float = 1e-2
     rho: float = 1.5
     mu_max: float = 1e6
+    tv: str = "aniso"    # "aniso": l1 of the gradients; "iso": l2 over the 3 directions per voxel
 
 
 @dataclasses.dataclass
@@ -183,10 +200,17 @@ def z_rhs(L, st: State, w) -> np.ndarray:
 
 
 def f_update(Z, st: State, p: Params) -> np.ndarray:
-    """3rd step: F = R_{tau/mu}((T1 + T2)/2), T1 = D_w Z + Gamma3/mu, T2 = E + Gamma4/mu."""
+    """3rd step: F = R_{tau/mu}((T1 + T2)/2), T1 = D_w Z + Gamma3/mu, T2 = E + Gamma4/mu.
+
+    Isotropic regulariser: the same argument, group-thresholded per voxel
+    across the three directions (the block minimiser for 2 tau sum_v ||F_v||_2)."""
     mu = st.mu
     T1 = grad_w(Z, p.w) + st.G3 / mu
     T2 = st.E + st.G4 / mu
+    if p.tv == "iso":
+        return group_soft(0.5 * (T1 + T2), p.tau / mu)
+    if p.tv != "aniso":
+        raise ValueError(f"unknown regulariser {p.tv!r}")
     return soft(0.5 * (T1 + T2), p.tau / mu)
 
 
@@ -259,13 +283,15 @@ def admm(O: np.ndarray, p: Params, iters: int, eps: float = 0.0,
 # ---------------------------------------------------------------------------
 
 def objective(X: np.ndarray, O: np.ndarray, p: Params) -> float:
-    """2 tau ||D_w X||_1 + alpha sum_n TNN(w_n D_n X) + lambda ||O - X||_1.
+    """2 tau ||D_w X||_1 + alpha sum_n TNN(w_n D_n X) + lambda ||O - X||_1
+    (isotropic: 2 tau sum_v ||(D_w X)_v||_2 in place of the l1 term).
 
     The factor 2 on tau is the weight for which the printed F threshold tau/mu
     is the exact block minimiser.
     """
     DX = grad_w(X, p.w)
-    return float(2 * p.tau * np.abs(DX).sum() + p.alpha * sum(tnn(DX[n]) for n in range(3))
+    tv = np.sqrt((DX ** 2).sum(axis=0)).sum() if p.tv == "iso" else np.abs(DX).sum()
+    return float(2 * p.tau * tv + p.alpha * sum(tnn(DX[n]) for n in range(3))
                  + p.lam * np.abs(O - X).sum())
 
 

@@ -466,3 +466,103 @@ def test_noisy_psnr_matches_paper_table():
         spec = synth.CubeSpec(256, 256, 191, 60, synth.NoiseSpec(case["sigma"], case["sigma"], 0.0, 0.0), 21)
         clean, noisy = synth.make_cube(spec)
         assert abs(oracle.mpsnr(noisy, clean) - case["psnr_db"]) < 0.02
+
+
+# ------------------------------------------- isotropic regulariser (iso) ---
+
+def test_group_soft_is_prox_bruteforce():
+    """max(1 - t/||u||, 0) u minimises t ||x||_2 + 1/2 ||x - u||^2 over 3-vectors
+    (Nelder-Mead from several starts, and random perturbations)."""
+    rng = np.random.default_rng(21)
+    for _ in range(60):
+        u = rng.normal(size=3) * rng.uniform(0.1, 3.0)
+        t = rng.uniform(0.05, 2.0)
+        f = lambda x: t * np.linalg.norm(x) + 0.5 * ((x - u) ** 2).sum()
+        x = oracle.group_soft(u.reshape(3, 1), t).ravel()
+        f0 = f(x)
+        for x0 in (np.zeros(3), u, rng.normal(size=3)):
+            r = scipy.optimize.minimize(f, x0, method="Nelder-Mead",
+                                        options={"xatol": 1e-12, "fatol": 1e-14, "maxiter": 20000})
+            assert f0 <= r.fun + 1e-10
+        for scale in (1e-6, 1e-3, 1e-1):
+            for _ in range(20):
+                assert f(x + scale * rng.normal(size=3)) >= f0 - 1e-12
+
+
+def test_group_soft_special_cases():
+    # a vector along one axis is soft-thresholded like a scalar; zero stays zero;
+    # the direction is kept; norms at or below t give zero
+    v = np.array([[2.5, -0.3, 0.0], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    np.testing.assert_allclose(oracle.group_soft(v, 1.0)[0], oracle.soft(v[0], 1.0), atol=1e-15)
+    u = np.array([[3.0], [4.0], [0.0]])
+    np.testing.assert_allclose(oracle.group_soft(u, 2.0).ravel(), [1.8, 2.4, 0.0], atol=1e-15)
+    assert np.abs(oracle.group_soft(u, 5.0)).max() == 0.0
+    assert np.abs(oracle.group_soft(np.zeros((3, 4)), 0.5)).max() == 0.0
+
+
+def _iso_lagrangian(O, L, S, Z, F, E, G1, G2, G3, G4, mu, p, diffs):
+    """The augmented Lagrangian with 2 tau sum_v ||F_v||_2 in place of 2 tau ||F||_1."""
+    aniso = lagrangian(O, L, S, Z, F, E, G1, G2, G3, G4, mu, p, diffs)
+    return aniso - 2 * p.tau * np.abs(F).sum() + 2 * p.tau * np.sqrt((F ** 2).sum(axis=0)).sum()
+
+
+def test_iso_f_update_minimises_its_lagrangian_block_and_differs_from_aniso():
+    O, p, st = _tiny_problem(seed=22)
+    p.tv = "iso"
+    p.tau = 1.2      # threshold tau/mu = 0.7: some voxels shrink to zero
+    Dw = loop_grad_w(p.w)
+    mu = st.mu
+    L = oracle.l_update(O, st)
+    Z = oracle.z_solve(oracle.z_rhs(L, st, p.w), mu, p.w)
+    F = oracle.f_update(Z, st, p)
+    lag = lambda Fv: _iso_lagrangian(O, L, st.S, Z, Fv, st.E, st.G1, st.G2, st.G3, st.G4, mu, p, Dw)
+    f0 = lag(F)
+    rng = np.random.default_rng(23)
+    for scale in [1e-6, 1e-3, 1e-1, 1.0]:
+        for _ in range(40):
+            assert lag(F + scale * rng.normal(size=F.shape)) >= f0 - 1e-9 * max(1.0, abs(f0))
+    zero_vox = np.all(F == 0, axis=0)
+    assert 0 < zero_vox.mean() < 1          # some voxels are shrunk to zero, some are not
+    p.tv = "aniso"
+    assert np.abs(oracle.f_update(Z, st, p) - F).max() > 1e-3
+
+
+def test_iso_f_block_optimality_from_stored_states_and_objective_at_convergence():
+    """(a) Each iteration's F satisfies the isotropic block optimality exactly:
+    with mu the iteration's penalty, Gamma3' + Gamma4' - mu (E' - E) =
+    2 mu (U - F') lies in 2 tau times the subdifferential of ||F'_v||_2 at
+    every voxel (checked on stored states of a hand-driven run mid-way, where
+    some voxels are zero and some are not).  (b) The converged X is not beaten
+    by perturbations of the isotropic objective."""
+    clean, noisy = synth.make_cube(synth.CubeSpec(6, 5, 8, 4, synth.NOISE_SMALL, 13))
+    p = oracle.Params(tau=0.05, alpha=0.1, lam=0.25, mu0=0.1, rho=1.2, mu_max=1e4, tv="iso")
+    st = oracle.init_state(noisy, p.mu0)
+    checked = 0
+    for k in range(40):
+        new, L, _ = oracle.admm_step(noisy, st, p)
+        Y = new.G3 + new.G4 - st.mu * (new.E - st.E)
+        nF = np.sqrt((new.F ** 2).sum(axis=0))
+        nY = np.sqrt((Y ** 2).sum(axis=0))
+        nz = nF > 0
+        if 0.05 < nz.mean() < 0.95:
+            assert nY[~nz].max() <= 2 * p.tau * (1 + 1e-9)
+            np.testing.assert_allclose(Y[:, nz], 2 * p.tau * new.F[:, nz] / nF[nz], rtol=0, atol=1e-9 * p.tau)
+            checked += 1
+        st = new
+    assert checked >= 3
+    clean, noisy = synth.make_cube(synth.CubeSpec(4, 4, 5, 3, synth.NOISE_SMALL, 11))
+    X, S, st, hist = oracle.admm(noisy, p, 400)
+    assert hist[-1]["inf_OLS"] < 1e-6 and hist[-1]["inf_LZ"] < 1e-6
+    Dw = loop_grad_w(p.w)
+
+    def f(Yc):
+        DY = Dw(Yc)
+        return 2 * p.tau * np.sqrt((DY ** 2).sum(axis=0)).sum() \
+            + p.alpha * sum(tnn_bcirc(DY[n]) for n in range(3)) + p.lam * np.abs(noisy - Yc).sum()
+
+    f0 = f(X)
+    rng = np.random.default_rng(24)
+    for scale in [1e-4, 1e-3, 1e-2, 1e-1]:
+        for _ in range(60):
+            assert f(X + scale * rng.normal(size=X.shape)) >= f0 - 1e-6
+    assert abs(oracle.objective(X, noisy, p) - f0) < 1e-9
