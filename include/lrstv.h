@@ -254,6 +254,24 @@ int lrstv_zsolve_workspace_size(int32_t h, int32_t w, int32_t b, size_t* bytes);
 int lrstv_zsolve(const float* T, float* Z, int32_t h, int32_t w, int32_t b, double mu,
                  const double wts[3], void* ws, size_t ws_bytes, void* stream);
 
+/* Size of the built-in scratch of lrstv_zsolve_noalloc (64 MiB per device). */
+#define LRSTV_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* lrstv_zsolve for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same solve, with the half spectrum b h (w/2+1) complex (8 bytes each)
+ * held in a scratch array built into the library instead of a caller
+ * workspace.  No device memory is allocated or freed by the call.  T, Z
+ * (device, may alias), sizes, mu and wts as for lrstv_zsolve.  The scratch
+ * is one array per device, shared by every call on that device, and keeps
+ * the last call's contents: calls that overlap on one device (other
+ * streams, other threads) race and must be serialised by the caller.  The
+ * first call on a device looks up the array's address there.
+ * Errors: INVALID_ARG, UNSUPPORTED (a side above LRSTV_MAX_SIDE),
+ * WORKSPACE (b h (w/2+1) * 8 > LRSTV_NOALLOC_SCRATCH_BYTES), HIP. */
+int lrstv_zsolve_noalloc(const float* T, float* Z, int32_t h, int32_t w, int32_t b, double mu,
+                         const double wts[3], void* stream);
+
 /* ---- autotuner ---------------------------------------------------------- */
 
 /* Launch shapes chosen per handle.  The slice tridiagonalisation (the

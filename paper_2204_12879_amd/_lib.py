@@ -81,6 +81,7 @@ def load_library():
         "lrstv_svt": (C.c_int, [vp, vp, i32, i32, i32, i32, f32, i32, vp, C.c_size_t, vp]),
         "lrstv_zsolve_workspace_size": (C.c_int, [i32, i32, i32, sz]),
         "lrstv_zsolve": (C.c_int, [vp, vp, i32, i32, i32, f64, C.POINTER(C.c_double), vp, C.c_size_t, vp]),
+        "lrstv_zsolve_noalloc": (C.c_int, [vp, vp, i32, i32, i32, f64, C.POINTER(C.c_double), vp]),
         "lrstv_check": (C.c_int, [vp]),
         "lrstv_profile": (C.c_int, [vp, i32]),
         "lrstv_set_graph": (C.c_int, [vp, i32]),
@@ -404,6 +405,20 @@ def zsolve(T, mu: float, wts=(1.0, 1.0, 1.0), out=None, stream=None):
     wv = (C.c_double * 3)(*wts)
     _check(lib.lrstv_zsolve(C.c_void_p(_ptr(T)), C.c_void_p(_ptr(Z)), h, w, b, float(mu), wv,
                             C.c_void_p(ws.data_ptr()), C.c_size_t(int(n.value)), C.c_void_p(_stream(stream))))
+    return Z
+
+
+def zsolve_noalloc(T, mu: float, wts=(1.0, 1.0, 1.0), out=None, stream=None):
+    """zsolve with the library's built-in scratch (lrstv_zsolve_noalloc):
+    no device workspace is allocated for the call."""
+    import torch
+    lib = load_library()
+    b, h, w = T.shape
+    T = T.contiguous()
+    Z = torch.empty_like(T) if out is None else out
+    wv = (C.c_double * 3)(*wts)
+    _check(lib.lrstv_zsolve_noalloc(C.c_void_p(_ptr(T)), C.c_void_p(_ptr(Z)), h, w, b, float(mu), wv,
+                                    C.c_void_p(_stream(stream))))
     return Z
 
 

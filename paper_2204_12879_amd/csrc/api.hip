@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1092,6 +1093,64 @@ extern "C" int lrstv_zsolve(const float* T, float* Z, int32_t h, int32_t w, int3
   if (ws_bytes < need) return fail(LRSTV_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
   hipStream_t s = (hipStream_t)stream;
   float2* spec = (float2*)(((uintptr_t)wsp + 255) & ~(uintptr_t)255);
+  launch_rfft_w(T, spec, h, w, b, s);
+  launch_fft_h(spec, h, w, b, -1, s);
+  launch_tri_b(spec, h, w, b, wts, nullptr, mu, s);
+  launch_fft_h(spec, h, w, b, +1, s);
+  launch_irfft_w(spec, Z, h, w, b, nullptr, s);
+  HIPCHK(hipGetLastError());
+  return LRSTV_OK;
+}
+
+// ------------------------------------------- Z-solve without allocation ---
+// Scratch of lrstv_zsolve_noalloc: the half spectrum b h (w/2+1) complex of
+// one cube, in a file-scope device array (each device holds its own copy,
+// loaded with the code object, until the process ends).  Host code never
+// passes the array's name to a kernel: it is a host-side stand-in, and the
+// device address comes from hipGetSymbolAddress with that device current.
+static __device__ __align__(256) float2 scratch[LRSTV_NOALLOC_SCRATCH_BYTES / sizeof(float2)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of `scratch` on the current device, looked up on the first
+// call per device and kept.
+static int scratch_address(void** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(LRSTV_ERR_UNSUPPORTED, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(LRSTV_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LRSTV_OK;
+}
+
+extern "C" int lrstv_zsolve_noalloc(const float* T, float* Z, int32_t h, int32_t w, int32_t b, double mu,
+                                    const double wts[3], void* stream) {
+  int rc = check_dims(h, w, b);
+  if (rc) return rc;
+  if (!T || !Z || !wts) return fail(LRSTV_ERR_INVALID_ARG, "NULL pointer argument");
+  if (!(mu > 0)) return fail(LRSTV_ERR_INVALID_ARG, "mu must be > 0");
+  for (int i = 0; i < 3; ++i)
+    if (!(wts[i] >= 0)) return fail(LRSTV_ERR_INVALID_ARG, "weights must be >= 0");
+  const size_t need = (size_t)b * h * (w / 2 + 1) * sizeof(float2);
+  if (need > LRSTV_NOALLOC_SCRATCH_BYTES)
+    return fail(LRSTV_ERR_WORKSPACE, "cube %d x %d x %d needs %zu bytes of scratch, the built-in scratch holds %zu",
+                b, h, w, need, (size_t)LRSTV_NOALLOC_SCRATCH_BYTES);
+  void* p = nullptr;
+  rc = scratch_address(&p);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  float2* spec = (float2*)p;   // every element is written by the forward w transform before it is read
   launch_rfft_w(T, spec, h, w, b, s);
   launch_fft_h(spec, h, w, b, -1, s);
   launch_tri_b(spec, h, w, b, wts, nullptr, mu, s);
