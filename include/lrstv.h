@@ -9,7 +9,8 @@
  * noise and N = Y - X - S the remaining Gaussian part, by minimising
  *     2 tau ||D_w X||_1 + alpha sum_n TNN(w_n D_n X) + lambda ||S||_1
  * subject to Y = X + S (the factor 2 on tau is the weight for which the
- * paper's printed F-step threshold tau/mu is the exact block minimiser).
+ * paper's printed F-step threshold tau/mu is the exact block minimiser), or
+ * with the isotropic term 2 tau sum_v ||(D_w X)_v||_2 (lrstv_params.tv).
  *
  * Conventions shared by every call
  *   - Return value: 0 = success, > 0 = warning with valid outputs,
@@ -47,6 +48,11 @@ extern "C" {
 #define LRSTV_ERR_HIP             -4   /* a HIP runtime call failed           */
 #define LRSTV_ERR_NONFINITE       -5   /* NaN/Inf met in the input or state   */
 
+/* ---- gradient-sparsity term (Sec. III-A) ---------------------------------- */
+#define LRSTV_TV_ANISO    0   /* 2 tau ||D_w X||_1: soft-threshold per element     */
+#define LRSTV_TV_ISO      1   /* 2 tau sum_v ||(D_w X)_v||_2 over the three
+                                 directions of each voxel: group soft-threshold  */
+
 /* ---- precision of the slice Gram / back-projection products ------------ */
 #define LRSTV_FP32        0   /* plain FP32 products                           */
 #define LRSTV_SPLIT_BF16  1   /* 3-term split-BF16 MFMA products, FP32 accum   */
@@ -79,6 +85,7 @@ typedef struct lrstv_params {
   double rho;      /* penalty growth (>= 1): mu <- min(rho mu, mu_max)       */
   double mu_max;   /* penalty cap (>= mu0)                                   */
   int32_t precision;  /* LRSTV_FP32 or LRSTV_SPLIT_BF16                      */
+  int32_t tv;         /* LRSTV_TV_ANISO (the paper's TDLRSTV) or LRSTV_TV_ISO  */
 } lrstv_params;
 
 typedef struct lrstv_state_view {
@@ -152,13 +159,28 @@ int lrstv_set_graph(lrstv_handle hd, int32_t enable);
  * (copying nothing) when the non-finite latch is already known to be set. */
 int lrstv_read_output(lrstv_handle hd, float* X, float* S);
 
-/* reset + iterate until max{||Y-X-S||_inf, ||X-Z||_inf} <= eps for every
- * cube (Algorithm 1 stopping test; eps <= 0 runs exactly max_iter) + copy
- * X and S out (device, may be NULL).  Synchronises the stream to read the
- * residuals.  `rep` (host) may be NULL.  Returns WARN_NOT_CONVERGED if
- * eps > 0 was not met, ERR_NONFINITE if a residual is NaN/Inf. */
+/* reset + iterate until max{||Y-X-S||_inf, ||X-Z||_inf} <= eps (Algorithm 1's
+ * convergence check) + copy X and S out (device, may be NULL).  eps <= 0
+ * runs exactly max_iter iterations.  With eps > 0 the test is made on the
+ * device after every iteration, per cube: a cube that meets it halts (every
+ * later kernel of the iteration returns at once for it, so its state stays
+ * that of its stopping iteration), and iterations are replayed in chunks
+ * whose halt flags the host reads one chunk behind, so there is no host
+ * synchronisation per iteration.  X and S of every cube are those of the
+ * first iteration at which it met the test.  Afterwards the test is off
+ * again (later lrstv_iterate calls continue from the stopped state).
+ * Synchronises the stream.  `rep` (host, may be NULL): the largest
+ * per-cube iteration count, the residuals of each cube's last iteration
+ * (max over cubes), mu after the last iteration run.  Returns
+ * WARN_NOT_CONVERGED if eps > 0 was not met by every cube, ERR_NONFINITE
+ * (copying nothing) if a residual is NaN/Inf. */
 int lrstv_solve(lrstv_handle hd, const float* Y, float* X, float* S, int32_t max_iter,
                 double eps, lrstv_report* rep);
+
+/* Iterations each cube ran since the last reset (per-cube counts of the
+ * last lrstv_solve), host array iters[n], n >= n_cubes.  Synchronises the
+ * stream.  Returns n_cubes or an error. */
+int lrstv_cube_iterations(lrstv_handle hd, int32_t* iters, int32_t n);
 
 /* Device pointers to the state (checkpoint / resume / adjoint). */
 int lrstv_get_state(lrstv_handle hd, lrstv_state_view* view);

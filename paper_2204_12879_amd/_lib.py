@@ -11,6 +11,8 @@ _LIB_NAME = "liblrstv.so"
 
 LRSTV_FP32 = 0
 LRSTV_SPLIT_BF16 = 1
+LRSTV_TV_ANISO = 0
+LRSTV_TV_ISO = 1
 LRSTV_NRES = 7
 LRSTV_VJP_INITIAL = 1
 LRSTV_MAX_TRI_SHAPES = 8
@@ -32,7 +34,8 @@ class _Problem(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("tau", C.c_double), ("alpha", C.c_double), ("lam", C.c_double), ("w", C.c_double * 3),
-                ("mu0", C.c_double), ("rho", C.c_double), ("mu_max", C.c_double), ("precision", C.c_int32)]
+                ("mu0", C.c_double), ("rho", C.c_double), ("mu_max", C.c_double), ("precision", C.c_int32),
+                ("tv", C.c_int32)]
 
 
 class _StateView(C.Structure):
@@ -83,6 +86,7 @@ def load_library():
         "lrstv_zsolve": (C.c_int, [vp, vp, i32, i32, i32, f64, C.POINTER(C.c_double), vp, C.c_size_t, vp]),
         "lrstv_zsolve_noalloc": (C.c_int, [vp, vp, i32, i32, i32, f64, C.POINTER(C.c_double), vp]),
         "lrstv_check": (C.c_int, [vp]),
+        "lrstv_cube_iterations": (C.c_int, [vp, C.POINTER(C.c_int32), i32]),
         "lrstv_profile": (C.c_int, [vp, i32]),
         "lrstv_set_graph": (C.c_int, [vp, i32]),
         "lrstv_stage_times": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32), i32]),
@@ -141,10 +145,11 @@ class Params:
     rho: float = 1.5
     mu_max: float = 1e6
     precision: int = LRSTV_FP32
+    tv: int = LRSTV_TV_ANISO     # LRSTV_TV_ISO: isotropic gradient term (group shrink per voxel)
 
     def _c(self) -> _Params:
         return _Params(self.tau, self.alpha, self.lam, (C.c_double * 3)(*self.w), self.mu0, self.rho,
-                       self.mu_max, self.precision)
+                       self.mu_max, self.precision, self.tv)
 
 
 def _problem(shapes: Sequence[Tuple[int, int, int]]):
@@ -260,6 +265,15 @@ class Solver:
         _check(rc, allow_warn=True)
         return {"iters": rep.iters, "residuals": dict(zip(RESIDUAL_NAMES, list(rep.residuals))),
                 "mu": rep.mu, "converged": rc != WARN_NOT_CONVERGED}
+
+    def cube_iterations(self) -> list:
+        """Iterations each cube ran since the last reset (lrstv_cube_iterations)."""
+        n = len(self.shapes)
+        buf = (C.c_int32 * n)()
+        rc = self.lib.lrstv_cube_iterations(self.handle, buf, n)
+        if rc < 0:
+            _check(rc)
+        return list(buf)
 
     def autotune(self, reps: int = 3) -> dict:
         """Time the tridiagonalisation shapes on this batch's slice sizes and

@@ -134,6 +134,11 @@ struct lrstv_handle_s {
   float2 *spec, *gram;
   double *tri, *xs, *mu, *part, *res_last;
   int *rcount, *flag;
+  // on-device stopping test (Algorithm 1's convergence check)
+  int *halt, *iters, *ran;
+  double* eps;
+  int* poll_host = nullptr;          // pinned [2][nc + 1]: halt flags and the non-finite flag
+  hipEvent_t poll_ev[2] = {nullptr, nullptr};
   SliceDesc* desc;
   CubeGeo* geo;        // device [n_cubes]
   int* bstart;         // device [PH_COUNT][n_cubes + 1]
@@ -156,6 +161,9 @@ struct lrstv_handle_s {
   bool flag_pending = false;   // a copy has been enqueued since the last reset
   bool flag_known = false;     // a completed copy read 1
   ~lrstv_handle_s() {
+    for (hipEvent_t e : poll_ev)
+      if (e) (void)hipEventDestroy(e);
+    if (poll_host) (void)hipHostFree(poll_host);
     if (flag_ev) (void)hipEventDestroy(flag_ev);
     if (flag_host) (void)hipHostFree(flag_host);
     if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -177,6 +185,8 @@ static int check_params(const lrstv_params* p) {
   if (!(p->mu_max >= p->mu0)) return fail(LRSTV_ERR_INVALID_ARG, "mu_max must be >= mu0");
   if (p->precision != LRSTV_FP32 && p->precision != LRSTV_SPLIT_BF16)
     return fail(LRSTV_ERR_INVALID_ARG, "unknown precision %d", p->precision);
+  if (p->tv != LRSTV_TV_ANISO && p->tv != LRSTV_TV_ISO)
+    return fail(LRSTV_ERR_INVALID_ARG, "unknown gradient term %d", p->tv);
   return LRSTV_OK;
 }
 
@@ -250,6 +260,10 @@ static void carve_handle(lrstv_handle_s* H, void* base, size_t* used) {
   H->part = cv.take<double>(nc * R_COUNT * LRSTV_PARTS);
   H->res_last = cv.take<double>(nc * R_COUNT);
   H->flag = cv.take<int>(1);
+  H->halt = cv.take<int>(nc);
+  H->iters = cv.take<int>(nc);
+  H->ran = cv.take<int>(1);
+  H->eps = cv.take<double>(1);
   *used = cv.off + 256;
 }
 
@@ -330,6 +344,7 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
     bt.stockham_h = stockham_h;
     bt.reg_w_mask = reg_w_mask;
     bt.stockham_w = stockham_w;
+    bt.halt = H->halt;
   }
   hipError_t e = hipMemcpyAsync(H->desc, H->sl.desc.data(), H->sl.desc.size() * sizeof(SliceDesc),
                                 hipMemcpyHostToDevice, H->stream);
@@ -356,12 +371,18 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
   }
   e = hipHostMalloc((void**)&H->flag_host, sizeof(int), hipHostMallocDefault);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&H->flag_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&H->poll_host, 2 * (size_t)(nc + 1) * sizeof(int), hipHostMallocDefault);
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&H->poll_ev[i], hipEventDisableTiming);
   if (e != hipSuccess) {
     delete H;
     return fail(LRSTV_ERR_HIP, "creating the non-finite latch: %s", hipGetErrorString(e));
   }
   *H->flag_host = 0;
-  launch_fill((float*)H->flag, 1, 0.f, H->stream);   // the bit pattern of int 0
+  launch_fill_int(H->flag, 1, 0, H->stream);
+  launch_fill_int(H->halt, nc, 0, H->stream);
+  launch_fill_int(H->iters, nc, 0, H->stream);
+  launch_fill_int(H->ran, 1, 0, H->stream);
+  launch_set_double(H->eps, 0.0, H->stream);
   launch_set_mu(H->mu, par->mu0, H->stream);
   *out = H;
   return LRSTV_OK;
@@ -402,7 +423,13 @@ extern "C" int lrstv_reset(lrstv_handle H, const float* Y) {
   launch_fill(H->G3, 3 * T, 0.f, s);
   launch_fill(H->G4, 3 * T, 0.f, s);
   launch_set_mu(H->mu, H->par.mu0, s);
-  launch_fill((float*)H->flag, 1, 0.f, s);
+  launch_fill_int(H->flag, 1, 0, s);
+  // stopping state: no cube halted, no test until lrstv_solve sets eps
+  const int nc = (int)H->cubes.size();
+  launch_fill_int(H->halt, nc, 0, s);
+  launch_fill_int(H->iters, nc, 0, s);
+  launch_fill_int(H->ran, 1, 0, s);
+  launch_set_double(H->eps, 0.0, s);
   // copies enqueued before this reset are no longer looked at: the next
   // lrstv_iterate enqueues a copy behind them and re-records the event
   H->flag_pending = false;
@@ -440,6 +467,7 @@ static void run_iteration(lrstv_handle_s* H, double* res_user) {
   wt.alpha = H->par.alpha;
   wt.lam = H->par.lambda;
   for (int i = 0; i < 3; ++i) wt.w[i] = H->par.w[i];
+  wt.iso = H->par.tv == LRSTV_TV_ISO;
   const int nc = (int)H->cubes.size();
   const BatchPtrs bp = batch_ptrs(H);
   tm.begin(ST_LRHS);
@@ -487,13 +515,19 @@ static void run_iteration(lrstv_handle_s* H, double* res_user) {
   sv.thresh = 0.f;
   sv.precision = H->par.precision;
   sv.tri_variant = H->tri_variant;
+  sv.halt = H->halt;
   launch_svt(sv, s, &tm, &H->split);
   tm.begin(ST_BAND_IDFT);
   launch_band_idft_batch(H->bt[PH_PARTS], H->slices, H->E, H->total, H->F, H->G4, H->mu, H->part, s);
   tm.end(ST_BAND_IDFT);
   tm.begin(ST_FINISH);
-  launch_finish_iter(H->part, nc, H->mu, H->res_last, res_user, H->flag, s);
-  launch_mu_step(H->mu, H->par.rho, H->par.mu_max, s);               // 7th step
+  StopState stop;
+  stop.halt = H->halt;
+  stop.iters = H->iters;
+  stop.ran = H->ran;
+  stop.eps = H->eps;
+  launch_finish_iter(H->part, nc, H->mu, H->res_last, res_user, H->flag, &stop, s);   // convergence check
+  launch_mu_step(H->mu, H->par.rho, H->par.mu_max, H->ran, s);       // 7th step
   tm.end(ST_FINISH);
 }
 
@@ -577,55 +611,97 @@ extern "C" int lrstv_read_output(lrstv_handle H, float* X, float* S) {
   return LRSTV_OK;
 }
 
+// Iterations per chunk of lrstv_solve with a stopping test: the host looks at
+// the halt flags of chunk j - 1 while chunk j is queued, so the device never
+// waits for the host, and at most two chunks run after every cube has halted
+// (their kernels return at once for halted cubes).
+constexpr int kStopChunk = 4;
+
 extern "C" int lrstv_solve(lrstv_handle H, const float* Y, float* X, float* S, int32_t max_iter, double eps,
                            lrstv_report* rep) {
   if (!H || !Y) return fail(LRSTV_ERR_INVALID_ARG, "handle or Y is NULL");
   if (max_iter < 1) return fail(LRSTV_ERR_INVALID_ARG, "max_iter must be >= 1");
+  if (!(eps >= 0.0) && !(eps < 0.0)) return fail(LRSTV_ERR_INVALID_ARG, "eps is NaN");
   int rc = lrstv_reset(H, Y);
   if (rc) return rc;
   const int nc = (int)H->cubes.size();
-  std::vector<double> res(nc * R_COUNT);
-  int iters = 0, status = LRSTV_OK;
-  HIPCHK(hipMemsetAsync(H->flag, 0, sizeof(int), H->stream));
-  const int chunk = eps > 0 ? 1 : max_iter;
-  bool done = false;
-  while (iters < max_iter && !done) {
-    const int k = (max_iter - iters) < chunk ? (max_iter - iters) : chunk;
+  const bool test = eps > 0;
+  hipStream_t s = H->stream;
+  launch_set_double(H->eps, test ? eps : 0.0, s);
+  const int chunk = test ? kStopChunk : max_iter;
+  int issued = 0, polls = 0;
+  bool stop = false;
+  while (issued < max_iter && !stop) {
+    const int k = (max_iter - issued) < chunk ? (max_iter - issued) : chunk;
     rc = lrstv_iterate(H, k, nullptr);
     if (rc) return rc;
-    iters += k;
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(res.data(), H->res_last, res.size() * sizeof(double), hipMemcpyDeviceToHost, H->stream));
-    HIPCHK(hipStreamSynchronize(H->stream));
-    double worst = 0.0;
-    bool bad = false;
-    for (double v : res) bad |= !isfinite(v);
-    for (int c = 0; c < nc; ++c) {
-      worst = fmax(worst, res[c * R_COUNT + R_INF_OLS]);
-      worst = fmax(worst, res[c * R_COUNT + R_INF_LZ]);
+    issued += k;
+    if (!test) continue;
+    int* buf = H->poll_host + (size_t)(polls & 1) * (nc + 1);
+    HIPCHK(hipMemcpyAsync(buf, H->halt, nc * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(buf + nc, H->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(H->poll_ev[polls & 1], s));
+    if (polls > 0) {   // the previous chunk's flags, while this chunk runs
+      HIPCHK(hipEventSynchronize(H->poll_ev[(polls - 1) & 1]));
+      const int* prev = H->poll_host + (size_t)((polls - 1) & 1) * (nc + 1);
+      bool all = true;
+      for (int c = 0; c < nc; ++c) all = all && prev[c] != 0;
+      stop = all || prev[nc] != 0;
     }
-    if (bad) { status = fail(LRSTV_ERR_NONFINITE, "non-finite residual after %d iterations", iters); break; }
-    if (eps > 0 && worst <= eps) done = true;
+    ++polls;
   }
-  if (status == LRSTV_OK && eps > 0 && !done) {
-    status = LRSTV_WARN_NOT_CONVERGED;
-    g_err = "stopping test not met within max_iter";
+  std::vector<double> res((size_t)nc * R_COUNT);
+  std::vector<int> halted(nc, 0), its(nc, 0);
+  int nonfinite = 0;
+  HIPCHK(hipMemcpyAsync(res.data(), H->res_last, res.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(halted.data(), H->halt, nc * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(its.data(), H->iters, nc * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&nonfinite, H->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  // later lrstv_iterate calls continue from the stopped state without a test
+  launch_set_double(H->eps, 0.0, s);
+  launch_fill_int(H->halt, nc, 0, s);
+  int status = LRSTV_OK;
+  bool bad = nonfinite != 0;
+  for (double v : res) bad |= !isfinite(v);
+  if (bad) {
+    status = fail(LRSTV_ERR_NONFINITE, "non-finite residual within %d iterations", issued);
+  } else if (test) {
+    bool all = true;
+    for (int c = 0; c < nc; ++c) all = all && halted[c] != 0;
+    if (!all) {
+      status = LRSTV_WARN_NOT_CONVERGED;
+      g_err = "stopping test not met within max_iter";
+    }
   }
-  rc = lrstv_read_output(H, X, S);
-  if (rc) return rc;
+  if (status >= 0) {
+    rc = lrstv_read_output(H, X, S);
+    if (rc) return rc;
+  }
   if (rep) {
-    rep->iters = iters;
+    int mx = 0;
+    for (int c = 0; c < nc; ++c) mx = its[c] > mx ? its[c] : mx;
+    rep->iters = mx;
     for (int r = 0; r < R_COUNT; ++r) {
       double m = 0.0;
       for (int c = 0; c < nc; ++c) m = fmax(m, res[c * R_COUNT + r]);
       rep->residuals[r] = m;
     }
     double mu = 0.0;
-    HIPCHK(hipMemcpyAsync(&mu, H->mu, sizeof(double), hipMemcpyDeviceToHost, H->stream));
-    HIPCHK(hipStreamSynchronize(H->stream));
+    HIPCHK(hipMemcpyAsync(&mu, H->mu, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
     rep->mu = mu;
   }
   return status;
+}
+
+extern "C" int lrstv_cube_iterations(lrstv_handle H, int32_t* iters, int32_t n) {
+  if (!H || !iters) return fail(LRSTV_ERR_INVALID_ARG, "handle or iters is NULL");
+  const int nc = (int)H->cubes.size();
+  if (n < nc) return fail(LRSTV_ERR_INVALID_ARG, "need room for %d cubes", nc);
+  HIPCHK(hipMemcpyAsync(iters, H->iters, nc * sizeof(int), hipMemcpyDeviceToHost, H->stream));
+  HIPCHK(hipStreamSynchronize(H->stream));
+  return nc;
 }
 
 extern "C" int lrstv_get_state(lrstv_handle H, lrstv_state_view* v) {
@@ -725,6 +801,8 @@ extern "C" int lrstv_iterate_vjp(lrstv_handle H, const lrstv_state_view* before,
                                  lrstv_state_view* grad_before, double* grad_weights, float* grad_Y,
                                  int32_t flags, void* ws, size_t ws_bytes) {
   if (!H) return fail(LRSTV_ERR_INVALID_ARG, "handle is NULL");
+  if (H->par.tv != LRSTV_TV_ANISO)
+    return fail(LRSTV_ERR_UNSUPPORTED, "the adjoint covers the anisotropic gradient term only");
   if (!before || !before->G4 || !before->mu) return fail(LRSTV_ERR_INVALID_ARG, "before needs G4 and mu");
   if (!after || !after->S || !after->F) return fail(LRSTV_ERR_INVALID_ARG, "after needs S and F");
   if (grad_after && !full_view(grad_after))

@@ -960,6 +960,7 @@ __global__ void __launch_bounds__(256) k_rfft_w_batch(BatchTab bt, const float* 
                                                       float2* __restrict__ spec) {
   extern __shared__ float2 sm[];
   const CubeSel q = select_cube(bt);
+  if (cube_halted(bt, q.c)) return;
   const CubeGeo g = uniform_geo(bt.geo, q.c);
   if (fft_h_reg_bit(g.w) != 0) return;   // that cube runs the register transform
   rfft_w_body(q.bid, q.nblk, sm, T + g.off, spec + g.spec_off, g.h * g.b, g.w, g.nb_w);
@@ -969,6 +970,7 @@ __global__ void __launch_bounds__(kIrfftThreads) k_irfft_w_batch(BatchTab bt, co
                                                        float* __restrict__ Z, double* __restrict__ part) {
   extern __shared__ float2 sm[];
   const int c = blockIdx.x / LRSTV_PARTS;
+  if (cube_halted(bt, c)) return;
   const CubeGeo g = uniform_geo(bt.geo, c);
   if (fft_h_reg_bit(g.w) != 0) return;   // that cube runs the register transform
   irfft_w_body(blockIdx.x - c * LRSTV_PARTS, LRSTV_PARTS, sm, spec + g.spec_off, Z + g.off, g.h * g.b, g.w, g.nb_w,
@@ -978,6 +980,7 @@ __global__ void __launch_bounds__(kIrfftThreads) k_irfft_w_batch(BatchTab bt, co
 __global__ void __launch_bounds__(kFftHThreads) k_fft_h_batch(BatchTab bt, float2* __restrict__ spec, int sign) {
   extern __shared__ float2 sm[];
   const CubeSel q = select_cube(bt);
+  if (cube_halted(bt, q.c)) return;
   const CubeGeo g = uniform_geo(bt.geo, q.c);
   if (fft_h_reg_bit(g.h) != 0) return;   // that cube runs the register FFT
   fft_h_body(q.bid, q.nblk, sm, spec + g.spec_off, g.h, g.w / 2 + 1, g.b, g.cw_h, sign);
@@ -988,6 +991,7 @@ __global__ void __launch_bounds__(kTriCols * kTriChunks, MAXL <= 16 ? 4 : 2) k_t
                                                                        double w1, double w2, double w3,
                                                                        const double* __restrict__ mu_dev) {
   const CubeSel q = select_cube(bt);
+  if (cube_halted(bt, q.c)) return;
   const CubeGeo g = uniform_geo(bt.geo, q.c);
   tri_b_body<MAXL>(q.bid, q.nblk, spec + g.spec_off, g.h, g.w, g.b, w1, w2, w3, mu_dev, 0.0);
 }
@@ -996,6 +1000,7 @@ __global__ void __launch_bounds__(kTriCols * kTriChunks, MAXL <= 16 ? 4 : 2) k_t
 __global__ void __launch_bounds__(256, 4) k_band_dft_batch(BatchTab bt, const float* __restrict__ A, int64_t a_stride,
                                                         float* __restrict__ slices) {
   const CubeSel q = select_cube(bt);
+  if (cube_halted(bt, q.c)) return;
   const CubeGeo g = uniform_geo(bt.geo, q.c);
   band_dft_body(q.bid, q.nblk, A + g.off, a_stride, 3, slices + g.slice_base, g.h * g.w, g.b);
 }
@@ -1005,6 +1010,7 @@ __global__ void __launch_bounds__(256 * kIdftGroups) k_band_idft_batch(BatchTab 
                                                          const float* __restrict__ F, float* __restrict__ G4,
                                                          const double* __restrict__ mu_dev, double* __restrict__ part) {
   const int c = blockIdx.x / LRSTV_PARTS;
+  if (cube_halted(bt, c)) return;
   const CubeGeo g = uniform_geo(bt.geo, c);
   band_idft_body(blockIdx.x - c * LRSTV_PARTS, LRSTV_PARTS, slices + g.slice_base, 3, E + g.off, e_stride,
                  g.h * g.w, g.b, F + g.off, G4 + g.off, mu_dev, part + (int64_t)c * R_COUNT * LRSTV_PARTS);
@@ -1035,6 +1041,7 @@ template <int P, int Q>
 __global__ void __launch_bounds__(kRfftPairs * kPairThreads) k_rfft_w_reg_batch(BatchTab bt, const float* __restrict__ T,
                                                                              float2* __restrict__ spec) {
   const CubeSel q = select_cube(bt);
+  if (cube_halted(bt, q.c)) return;
   const CubeGeo g = uniform_geo(bt.geo, q.c);
   if (g.w != P * Q) return;   // another length (or the Stockham path) takes that cube
   rfft_w_reg_body<P, Q, kRfftPairs>(q.bid, q.nblk, T + g.off, spec + g.spec_off, g.h * g.b);
@@ -1051,6 +1058,7 @@ __global__ void __launch_bounds__(kIrfftPairs * kPairThreads) k_irfft_w_reg_batc
                                                                                float* __restrict__ Z,
                                                                                double* __restrict__ part) {
   const int c = blockIdx.x / LRSTV_PARTS;
+  if (cube_halted(bt, c)) return;
   const CubeGeo g = uniform_geo(bt.geo, c);
   if (g.w != P * Q) return;
   irfft_w_reg_body<P, Q, kIrfftPairs>(blockIdx.x - c * LRSTV_PARTS, LRSTV_PARTS, spec + g.spec_off, Z + g.off,
@@ -1119,6 +1127,7 @@ void launch_irfft_w(const float2* spec, float* Z, int h, int w, int b, double* p
 template <int P, int Q, int S>
 __global__ void __launch_bounds__(kFftRegCols * (P > Q ? P : Q)) k_fft_h_reg_batch(BatchTab bt, float2* __restrict__ spec) {
   const CubeSel q = select_cube(bt);
+  if (cube_halted(bt, q.c)) return;
   const CubeGeo g = uniform_geo(bt.geo, q.c);
   if (g.h != P * Q) return;   // another length (or the Stockham path) takes that cube
   fft_h_reg_body<P, Q, S>(q.bid, q.nblk, spec + g.spec_off, g.w / 2 + 1, g.b);

@@ -56,11 +56,12 @@ inline int xcd_grid(int ntile, int ns) { return ntile * ((ns + 7) / 8) * 8; }
 // lower 64 x 64 tile (placed by xcd_tile_slice).
 template <int MODE>
 __global__ void __launch_bounds__(256) k_gram(const SliceDesc* __restrict__ desc, const float* __restrict__ sl,
-                                              float2* __restrict__ gram, int ntile, int ns) {
+                                              float2* __restrict__ gram, int ntile, int ns, const int* __restrict__ halt) {
   __shared__ MfmaSmem sm;
   int tile, slice;
   if (!xcd_tile_slice(ntile, ns, tile, slice)) return;
   const SliceDesc d = desc[slice];
+  if (halt && halt[d.cube]) return;   // the cube has met its stopping test
   const int n = d.n1, T = (n + kMT - 1) / kMT;
   int ti = 0, rem = tile;
   while (rem > ti) { rem -= ti + 1; ++ti; }
@@ -127,12 +128,13 @@ __global__ void __launch_bounds__(256) k_gram(const SliceDesc* __restrict__ desc
 // and reflector i stored in column i of the packed triangle (below diag).
 template <bool ONCHIP>
 __global__ void __launch_bounds__(256) k_tridiag(const SliceDesc* __restrict__ desc, float2* __restrict__ gram,
-                                                 double* __restrict__ tri) {
+                                                 double* __restrict__ tri, const int* __restrict__ halt) {
   extern __shared__ float2 sm[];
   __shared__ double red[8];
   __shared__ double s_tau;
   __shared__ float2 s_beta, s_scale;
   const SliceDesc d = desc[blockIdx.x];
+  if (halt && halt[d.cube]) return;   // the cube has met its stopping test
   const int n = d.n1;
   const int64_t np = (int64_t)n * (n + 1) / 2;
   float2* gA = gram + d.g_off;
@@ -292,13 +294,14 @@ __global__ void __launch_bounds__(256) k_tridiag(const SliceDesc* __restrict__ d
 // norm; v = [1; scl * x] is applied on the fly from the unscaled column x.
 template <int JR, int NW>
 __global__ void __launch_bounds__(64 * NW) k_tridiag_reg(const SliceDesc* __restrict__ desc,
-                                                         float2* __restrict__ gram, double* __restrict__ tri) {
+                                                         float2* __restrict__ gram, double* __restrict__ tri, const int* __restrict__ halt) {
   extern __shared__ float2 sm[];
   // red_nx and s_dii are written for step i+1 while step i may still read them
   // (the no-reflection path has no barrier in between): double-buffered by parity.
   __shared__ double red_nx[2][NW], red_vav[NW];
   __shared__ double s_dii[2];
   const SliceDesc d = desc[blockIdx.x];
+  if (halt && halt[d.cube]) return;   // the cube has met its stopping test
   const int n = d.n1;
   const int RL = n > NW * JR ? n - NW * JR : 0;
   const int64_t npl = (int64_t)RL * (RL + 1) / 2;
@@ -763,7 +766,7 @@ LRSTV_DEV MtRefl mt_reflector(double nx2, float2 x0) {
 
 template <int NW, int TPW>
 __global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __restrict__ desc,
-                                                         float2* __restrict__ gram, double* __restrict__ tri) {
+                                                         float2* __restrict__ gram, double* __restrict__ tri, const int* __restrict__ halt) {
   constexpr int NMAX = 256, NDW = NMAX / 64;   // waves of D, one index per thread
   static_assert(NW * TPW >= 36, "the 36 lower tiles of a 256 x 256 Gram");
   static_assert(NW >= NDW, "one index per thread in D");
@@ -776,6 +779,7 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __res
   __shared__ double red_fro[NW];
   __shared__ double s_dii[2];
   const SliceDesc d = desc[blockIdx.x];
+  if (halt && halt[d.cube]) return;   // the cube has met its stopping test
   const int n = d.n1;
   if (n <= 0) return;
   const int NT = (n + 31) >> 5, ntile = NT * (NT + 1) / 2;
@@ -1290,7 +1294,7 @@ template <int PHASE>
 __global__ void __launch_bounds__(PHASE == 1 ? 64 : (PHASE == 0 ? 256 : 1024)) k_trieig(const SliceDesc* __restrict__ desc, double* __restrict__ tri,
                                                  double* __restrict__ xs, float* __restrict__ V,
                                                  int* __restrict__ rcount, const double* __restrict__ mu_dev,
-                                                 double alpha, float thresh, int probes) {
+                                                 double alpha, float thresh, int probes, const int* __restrict__ halt) {
   extern __shared__ double smd[];
   __shared__ double red[16];
   __shared__ int s_c0, s_nblk;
@@ -1298,6 +1302,7 @@ __global__ void __launch_bounds__(PHASE == 1 ? 64 : (PHASE == 0 ? 256 : 1024)) k
   // block per slice
   const int slice = PHASE == 2 ? blockIdx.x : blockIdx.y;
   const SliceDesc d = desc[slice];
+  if (halt && halt[d.cube]) return;   // the cube has met its stopping test
   const int n = d.n1;
   double* dg = tri + d.t_off;
   const double* eab = dg + n;
@@ -1629,7 +1634,7 @@ LRSTV_DEV float2 wy_y(const float2* __restrict__ g, int n, int i0, int nbk, int 
 // (reflector block, slice), so that the blocks of a slice share an L2).
 __global__ void __launch_bounds__(256) k_wy_t(const SliceDesc* __restrict__ desc, const float2* __restrict__ gram,
                                               const double* __restrict__ tri, float* __restrict__ Twy,
-                                              const int* __restrict__ rcount, int ntile, int ns) {
+                                              const int* __restrict__ rcount, int ntile, int ns, const int* __restrict__ halt) {
   // one LDS buffer (40 KB, four blocks per CU): the product's staging, then
   // S = Y^H Y and the in-place inversion (T below)
   __shared__ MfmaSmem sm;
@@ -1638,6 +1643,7 @@ __global__ void __launch_bounds__(256) k_wy_t(const SliceDesc* __restrict__ desc
   int b, slice;
   if (!xcd_tile_slice(ntile, ns, b, slice)) return;
   const SliceDesc d = desc[slice];
+  if (halt && halt[d.cube]) return;   // the cube has met its stopping test
   const int n = d.n1, nblk = (n - 1 + 63) / 64;
   if (b >= nblk || rcount[slice] == 0) return;
   const int i0 = 64 * b, m = n - 1 - i0, nbk = m < 64 ? m : 64;
@@ -1736,11 +1742,12 @@ struct WySmem {
 
 __global__ void __launch_bounds__(256, 4) k_wy_apply(const SliceDesc* __restrict__ desc, const float2* __restrict__ gram,
                                                      const float* __restrict__ Twy, float* __restrict__ V,
-                                                     const int* __restrict__ rcount, int ntile, int ns) {
+                                                     const int* __restrict__ rcount, int ntile, int ns, const int* __restrict__ halt) {
   __shared__ WySmem sm;
   int ct, slice;
   if (!xcd_tile_slice(ntile, ns, ct, slice)) return;
   const SliceDesc d = desc[slice];
+  if (halt && halt[d.cube]) return;   // the cube has met its stopping test
   const int n = d.n1, r = rcount[slice], c0 = 64 * ct;
   if (c0 >= r) return;
   const int nc = (r - c0) < 64 ? (r - c0) : 64;
@@ -1891,10 +1898,10 @@ void launch_backtrans(const SvtLaunch& L, hipStream_t s) {
   const int nblk = (n - 1 + 63) / 64;
   if (nblk == 0 || ns == 0) return;
   hipLaunchKernelGGL(k_wy_t, dim3(xcd_grid(nblk, ns)), dim3(256), 0, s, L.desc, L.gram, L.tri, L.Twy, L.rcount, nblk,
-                     ns);
+                     ns, L.halt);
   const int ncb = (n + 63) / 64;
   hipLaunchKernelGGL(k_wy_apply, dim3(xcd_grid(ncb, ns)), dim3(256), 0, s, L.desc, L.gram, L.Twy, L.V, L.rcount, ncb,
-                     ns);
+                     ns, L.halt);
 }
 
 // ----------------------------------------------------- back-projection ---
@@ -1902,12 +1909,13 @@ void launch_backtrans(const SvtLaunch& L, hipStream_t s) {
 template <int MODE>
 __global__ void __launch_bounds__(256) k_bp1(const SliceDesc* __restrict__ desc, const float* __restrict__ sl,
                                              const float* __restrict__ V, float* __restrict__ Bb,
-                                             const int* __restrict__ rcount, int tdim, int ns) {
+                                             const int* __restrict__ rcount, int tdim, int ns, const int* __restrict__ halt) {
   __shared__ MfmaSmem sm;
   int tile, slice;
   if (!xcd_tile_slice(tdim * tdim, ns, tile, slice)) return;
   const int bx = tile % tdim, by = tile / tdim;
   const SliceDesc d = desc[slice];
+  if (halt && halt[d.cube]) return;   // the cube has met its stopping test
   const int r = rcount[slice], n = d.n1, h = d.h, w = d.w;
   const float* mr = sl + d.a_off;
   const float* mi = mr + (int64_t)h * w;
@@ -1953,7 +1961,7 @@ __global__ void __launch_bounds__(256) k_bp1(const SliceDesc* __restrict__ desc,
 // sigma_c = ||B[:, c]|| (tall) or ||B[c, :]|| (wide); f_c = max(1 - t/sigma_c, 0)
 __global__ void __launch_bounds__(256) k_colnorm(const SliceDesc* __restrict__ desc, const float* __restrict__ Bb,
                                                  float* __restrict__ fval, const int* __restrict__ rcount,
-                                                 const double* __restrict__ mu_dev, double alpha, float thresh) {
+                                                 const double* __restrict__ mu_dev, double alpha, float thresh, const int* __restrict__ halt) {
   // Block (x, slice) takes the singular indices 64 x .. 64 x + 63; squares
   // are summed in FP64.  Tall: B is h x r at row stride n, thread t takes
   // column 64 x + t % 64 and rows t / 64 + 4 j, so each row read of a wave is
@@ -1961,6 +1969,7 @@ __global__ void __launch_bounds__(256) k_colnorm(const SliceDesc* __restrict__ d
   // 64 x + 16 q .. + 15, one contiguous row at a time.
   __shared__ double part[4][64];
   const SliceDesc d = desc[blockIdx.y];
+  if (halt && halt[d.cube]) return;   // the cube has met its stopping test
   const int r = rcount[blockIdx.y], c0 = 64 * blockIdx.x;
   if (c0 >= r) return;
   const int h = d.h, w = d.w, n = d.n1;
@@ -2005,12 +2014,13 @@ template <int MODE>
 __global__ void __launch_bounds__(256) k_bp2(const SliceDesc* __restrict__ desc, float* __restrict__ sl,
                                              const float* __restrict__ V, const float* __restrict__ Bb,
                                              const float* __restrict__ fval, const int* __restrict__ rcount, int tdim,
-                                             int ns) {
+                                             int ns, const int* __restrict__ halt) {
   __shared__ MfmaSmem sm;
   int tile, slice;
   if (!xcd_tile_slice(tdim * tdim, ns, tile, slice)) return;
   const int bx = tile % tdim, by = tile / tdim;
   const SliceDesc d = desc[slice];
+  if (halt && halt[d.cube]) return;   // the cube has met its stopping test
   const int r = rcount[slice], n = d.n1, h = d.h, w = d.w;
   const int m0 = by * kMT, n0 = bx * kMT;
   if (m0 >= h || n0 >= w) return;
@@ -2311,15 +2321,15 @@ void launch_svt_tridiag(const SvtLaunch& L, hipStream_t s) {
   if (tri_variant_onchip(v, n)) {
     const size_t lds = kTriShapes[v].kind == 0 ? tridiag_reg_lds(n, v) : 0;
     switch (v) {
-      case 0: hipLaunchKernelGGL((k_tridiag_reg<10, 8>), dim3(ns), dim3(512), lds, s, L.desc, L.gram, L.tri); break;
-      case 1: hipLaunchKernelGGL((k_tridiag_reg<7, 12>), dim3(ns), dim3(768), lds, s, L.desc, L.gram, L.tri); break;
-      case 2: hipLaunchKernelGGL((k_tridiag_reg<6, 16>), dim3(ns), dim3(1024), lds, s, L.desc, L.gram, L.tri); break;
-      case 3: hipLaunchKernelGGL((k_tridiag_mfma<12, 3>), dim3(ns), dim3(768), 0, s, L.desc, L.gram, L.tri); break;
-      default: hipLaunchKernelGGL((k_tridiag_mfma<8, 5>), dim3(ns), dim3(512), 0, s, L.desc, L.gram, L.tri); break;
+      case 0: hipLaunchKernelGGL((k_tridiag_reg<10, 8>), dim3(ns), dim3(512), lds, s, L.desc, L.gram, L.tri, L.halt); break;
+      case 1: hipLaunchKernelGGL((k_tridiag_reg<7, 12>), dim3(ns), dim3(768), lds, s, L.desc, L.gram, L.tri, L.halt); break;
+      case 2: hipLaunchKernelGGL((k_tridiag_reg<6, 16>), dim3(ns), dim3(1024), lds, s, L.desc, L.gram, L.tri, L.halt); break;
+      case 3: hipLaunchKernelGGL((k_tridiag_mfma<12, 3>), dim3(ns), dim3(768), 0, s, L.desc, L.gram, L.tri, L.halt); break;
+      default: hipLaunchKernelGGL((k_tridiag_mfma<8, 5>), dim3(ns), dim3(512), 0, s, L.desc, L.gram, L.tri, L.halt); break;
     }
   } else {
     hipLaunchKernelGGL(k_tridiag<false>, dim3(ns), dim3(256), (size_t)(2 + 4) * n * sizeof(float2), s, L.desc,
-                       L.gram, L.tri);
+                       L.gram, L.tri, L.halt);
   }
 }
 static void launch_tridiag(const SvtLaunch& L, hipStream_t s) { launch_svt_tridiag(L, s); }
@@ -2329,10 +2339,10 @@ void launch_svt_gram(const SvtLaunch& L, hipStream_t s) {
   const int TT = (n + kMT - 1) / kMT;
   if (L.precision == LRSTV_SPLIT_BF16)
     hipLaunchKernelGGL(k_gram<kBF16x3>, dim3(xcd_grid(TT * (TT + 1) / 2, ns)), dim3(256), 0, s, L.desc, L.slices, L.gram,
-                       TT * (TT + 1) / 2, ns);
+                       TT * (TT + 1) / 2, ns, L.halt);
   else
     hipLaunchKernelGGL(k_gram<kF32>, dim3(xcd_grid(TT * (TT + 1) / 2, ns)), dim3(256), 0, s, L.desc, L.slices, L.gram,
-                       TT * (TT + 1) / 2, ns);
+                       TT * (TT + 1) / 2, ns, L.halt);
 }
 
 void prepare_svt(int max_n1) {
@@ -2356,9 +2366,9 @@ static void launch_trivec(const SvtLaunch& L, hipStream_t s, size_t eig_lds, con
   const int ns = L.n_slices, n = L.max_n1;
   constexpr int VB = 64;
   hipLaunchKernelGGL(k_trieig<1>, dim3((n + VB - 1) / VB, ns), dim3(VB), eig_lds, s, L.desc, L.tri, L.xs, L.V,
-                     L.rcount, mu, L.alpha, thresh, 0);
+                     L.rcount, mu, L.alpha, thresh, 0, L.halt);
   hipLaunchKernelGGL(k_trieig<2>, dim3(ns), dim3(1024), eig_lds, s, L.desc, L.tri, L.xs, L.V, L.rcount, mu, L.alpha,
-                     thresh, 0);
+                     thresh, 0, L.halt);
 }
 
 static size_t tridiag_onchip_bytes(int n) {
@@ -2387,7 +2397,7 @@ static void svt_after_tridiag(const SvtLaunch& L, hipStream_t s, StageTimer& T) 
   T.begin(ST_TRIEIG);
   const int probes = eig_probes(ns, n), epb = 256 / probes;
   hipLaunchKernelGGL(k_trieig<0>, dim3((n + epb - 1) / epb, ns), dim3(256), eig_lds, s, L.desc, L.tri, L.xs, L.V,
-                     L.rcount, L.mu, L.alpha, L.thresh, probes);
+                     L.rcount, L.mu, L.alpha, L.thresh, probes, L.halt);
   T.end(ST_TRIEIG);
   T.begin(ST_TRIVEC);
   launch_trivec(L, s, eig_lds, L.mu, L.thresh);
@@ -2399,22 +2409,22 @@ static void svt_after_tridiag(const SvtLaunch& L, hipStream_t s, StageTimer& T) 
   T.begin(ST_BP1);
   if (bf)
     hipLaunchKernelGGL(k_bp1<kBF16x3>, dim3(xcd_grid(TM * TM, ns)), dim3(256), 0, s, L.desc, L.slices, L.V, L.B,
-                       L.rcount, TM, ns);
+                       L.rcount, TM, ns, L.halt);
   else
     hipLaunchKernelGGL(k_bp1<kF32>, dim3(xcd_grid(TM * TM, ns)), dim3(256), 0, s, L.desc, L.slices, L.V, L.B, L.rcount,
-                       TM, ns);
+                       TM, ns, L.halt);
   T.end(ST_BP1);
   T.begin(ST_COLNORM);
   hipLaunchKernelGGL(k_colnorm, dim3((n + 63) / 64, ns), dim3(256), 0, s, L.desc, L.B, L.fval, L.rcount, L.mu, L.alpha,
-                     L.thresh);
+                     L.thresh, L.halt);
   T.end(ST_COLNORM);
   T.begin(ST_BP2);
   if (bf)
     hipLaunchKernelGGL(k_bp2<kBF16x3>, dim3(xcd_grid(TM * TM, ns)), dim3(256), 0, s, L.desc, L.slices, L.V, L.B,
-                       L.fval, L.rcount, TM, ns);
+                       L.fval, L.rcount, TM, ns, L.halt);
   else
     hipLaunchKernelGGL(k_bp2<kF32>, dim3(xcd_grid(TM * TM, ns)), dim3(256), 0, s, L.desc, L.slices, L.V, L.B,
-                       L.fval, L.rcount, TM, ns);
+                       L.fval, L.rcount, TM, ns, L.halt);
   T.end(ST_BP2);
 }
 
@@ -2434,10 +2444,10 @@ void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm, const SvtSpli
   T.begin(ST_GRAM);
   if (bf)
     hipLaunchKernelGGL(k_gram<kBF16x3>, dim3(xcd_grid(TT * (TT + 1) / 2, ns)), dim3(256), 0, s, L.desc, L.slices, L.gram,
-                       TT * (TT + 1) / 2, ns);
+                       TT * (TT + 1) / 2, ns, L.halt);
   else
     hipLaunchKernelGGL(k_gram<kF32>, dim3(xcd_grid(TT * (TT + 1) / 2, ns)), dim3(256), 0, s, L.desc, L.slices, L.gram,
-                       TT * (TT + 1) / 2, ns);
+                       TT * (TT + 1) / 2, ns, L.halt);
   T.end(ST_GRAM);
   // per-stage timing keeps one stream (every stage times all the slices)
   if (sp && sp->s2 && sp->first > 0 && sp->first < ns && !T.on) {
@@ -2472,19 +2482,19 @@ void launch_svt_vjp(const SvtVjpLaunch& J, hipStream_t s) {
   const int TT = (n + kMT - 1) / kMT, TM = (m + kMT - 1) / kMT;
   // full eigendecomposition of every Gram (thresh < 0: all eigenpairs)
   hipLaunchKernelGGL(k_gram<kF32>, dim3(xcd_grid(TT * (TT + 1) / 2, ns)), dim3(256), 0, s, L.desc, L.slices, L.gram,
-                       TT * (TT + 1) / 2, ns);
+                       TT * (TT + 1) / 2, ns, L.halt);
   launch_tridiag(L, s);
   const size_t eig_lds = (size_t)5 * n * sizeof(double) + (size_t)(n + 1 + 1024) * sizeof(int);
   const int probes = eig_probes(ns, n), epb = 256 / probes;
   hipLaunchKernelGGL(k_trieig<0>, dim3((n + epb - 1) / epb, ns), dim3(256), eig_lds, s, L.desc, L.tri, L.xs, L.V,
-                     L.rcount, (const double*)nullptr, 0.0, -1.f, probes);
+                     L.rcount, (const double*)nullptr, 0.0, -1.f, probes, L.halt);
   launch_trivec(L, s, eig_lds, nullptr, -1.f);
   launch_backtrans(L, s);
   // B = M V, C = D V (or U^H M, U^H D)
   hipLaunchKernelGGL(k_bp1<kF32>, dim3(xcd_grid(TM * TM, ns)), dim3(256), 0, s, L.desc, L.slices, L.V, L.B, L.rcount,
-                       TM, ns);
+                       TM, ns, L.halt);
   hipLaunchKernelGGL(k_bp1<kF32>, dim3(xcd_grid(TM * TM, ns)), dim3(256), 0, s, L.desc, J.dsl, L.V, J.C, L.rcount, TM,
-                     ns);
+                     ns, L.halt);
   hipLaunchKernelGGL(k_vjp_sigma, dim3(n, ns), dim3(256), 0, s, L.desc, L.B, J.C, J.sig, L.fval, J.acon, L.rcount,
                      L.mu, L.alpha, L.thresh);
   hipLaunchKernelGGL(k_vjp_w<kF32>, dim3(TT, TT, ns), dim3(256), 0, s, L.desc, L.B, J.C, J.sig, J.W, L.rcount,
@@ -2493,7 +2503,7 @@ void launch_svt_vjp(const SvtVjpLaunch& J, hipStream_t s) {
                      L.rcount);
   // result (R V^H or U R) over the direction slices
   hipLaunchKernelGGL(k_bp2<kF32>, dim3(xcd_grid(TM * TM, ns)), dim3(256), 0, s, L.desc, J.dsl, L.V, J.R, J.ones,
-                     L.rcount, TM, ns);
+                     L.rcount, TM, ns, L.halt);
 }
 
 }  // namespace lrstv

@@ -81,6 +81,7 @@ LRSTV_DEV void lrhs_body(int bid, int nblk, const float* __restrict__ O, const f
 __global__ void __launch_bounds__(256) k_lrhs_batch(BatchTab bt, BatchPtrs p, float w1, float w2, float w3,
                                                     const double* __restrict__ mu_dev) {
   const int c = find_cube(bt.bstart, bt.nc, blockIdx.x);
+  if (cube_halted(bt, c)) return;
   const CubeGeo g = uniform_geo(bt.geo, c);
   const int64_t o = g.off;
   lrhs_body(blockIdx.x - bt.bstart[c], bt.bstart[c + 1] - bt.bstart[c], p.O + o, p.S + o, p.Z + o, p.G1 + o,
@@ -89,6 +90,8 @@ __global__ void __launch_bounds__(256) k_lrhs_batch(BatchTab bt, BatchPtrs p, fl
 
 // G_n = w_n D_n Z (forward, periodic)
 // F_n = R_{tau/mu}( 1/2 (G_n + Gamma3_n/mu + E_n + Gamma4_n/mu) )
+//   (isotropic: U_n = 1/2 (...), F = max(1 - (tau/mu) / ||U||_2, 0) U with
+//    the norm over the three directions of the voxel)
 // Gamma3_n += mu (G_n - F_n);   A_n = F_n - Gamma4_n / mu
 // Gamma2 += mu (L - Z)
 // S = R_{lambda/mu}(O - L + Gamma1/mu);   Gamma1 += mu (O - L - S)
@@ -98,7 +101,7 @@ LRSTV_DEV void grad_shrink_body(
     int bid, const float* __restrict__ O, const float* __restrict__ L, const float* __restrict__ Z,
     float* __restrict__ S, float* __restrict__ G1, float* __restrict__ G2, float* __restrict__ F,
     const float* __restrict__ E, float* __restrict__ G3, const float* __restrict__ G4, float* __restrict__ A,
-    int64_t ts, int64_t as, int h, int w, int b, float w1, float w2, float w3, float tau, float lam,
+    int64_t ts, int64_t as, int h, int w, int b, float w1, float w2, float w3, float tau, float lam, int iso,
     const double* __restrict__ mu_dev, double* __restrict__ part /* [R_COUNT][LRSTV_PARTS] of this cube */) {
   constexpr int nblk = LRSTV_PARTS;
   __shared__ double red[8];
@@ -119,12 +122,25 @@ LRSTV_DEV void grad_shrink_body(
     const float z = Z[q], l = L[q], o = O[q];
     const int64_t qn[3] = {(i == h - 1) ? q - (int64_t)(h - 1) * w : q + w, (x == w - 1) ? q - (w - 1) : q + 1,
                            (j == b - 1) ? q - (int64_t)(b - 1) * hw : q + hw};
+    float gv[3], g3v[3], g4v[3], uv[3];
 #pragma unroll
     for (int n = 0; n < 3; ++n) {
       const int64_t o3 = n * ts + q;
-      const float g = wn[n] * (Z[qn[n]] - z);
-      const float g3 = G3[o3], g4 = G4[o3];
-      const float f = soft_threshold(0.5f * (g + g3 * imu + E[o3] + g4 * imu), tmu);
+      gv[n] = wn[n] * (Z[qn[n]] - z);
+      g3v[n] = G3[o3];
+      g4v[n] = G4[o3];
+      uv[n] = 0.5f * (gv[n] + g3v[n] * imu + E[o3] + g4v[n] * imu);
+    }
+    float gscale = 0.f;   // isotropic: the common factor of the voxel's three components
+    if (iso) {
+      const float nrm = sqrtf(uv[0] * uv[0] + uv[1] * uv[1] + uv[2] * uv[2]);
+      gscale = nrm > tmu ? 1.0f - tmu / nrm : 0.f;
+    }
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      const int64_t o3 = n * ts + q;
+      const float g = gv[n], g3 = g3v[n], g4 = g4v[n];
+      const float f = iso ? uv[n] * gscale : soft_threshold(uv[n], tmu);
       F[o3] = f;
       G3[o3] = g3 + mu * (g - f);
       A[n * as + q] = f - g4 * imu;
@@ -164,24 +180,33 @@ LRSTV_DEV void grad_shrink_body(
 
 // Batch: LRSTV_PARTS blocks per cube, cube c's residual slots at part + c R_COUNT LRSTV_PARTS.
 __global__ void __launch_bounds__(512) k_grad_shrink_batch(BatchTab bt, BatchPtrs p, float w1, float w2, float w3,
-                                                           float tau, float lam, const double* __restrict__ mu_dev,
+                                                           float tau, float lam, int iso,
+                                                           const double* __restrict__ mu_dev,
                                                            double* __restrict__ part) {
   const int c = blockIdx.x / LRSTV_PARTS;
+  if (cube_halted(bt, c)) return;
   const CubeGeo g = uniform_geo(bt.geo, c);
   const int64_t o = g.off;
   grad_shrink_body(blockIdx.x - c * LRSTV_PARTS, p.O + o, p.L + o, p.Z + o, p.S + o, p.G1 + o, p.G2 + o, p.F + o,
-                   p.E + o, p.G3 + o, p.G4 + o, p.A + o, p.ts, p.ts, g.h, g.w, g.b, w1, w2, w3, tau, lam, mu_dev,
+                   p.E + o, p.G3 + o, p.G4 + o, p.A + o, p.ts, p.ts, g.h, g.w, g.b, w1, w2, w3, tau, lam, iso, mu_dev,
                    part + (int64_t)c * R_COUNT * LRSTV_PARTS);
 }
 
 // One block per cube: fixed-order reduction of the residual partials.
 // out[cube][R_COUNT] (and optionally res_user[cube][R_COUNT]); sets *flag to
-// 1 when a residual is not finite.
+// 1 when a residual is not finite.  With a stopping state (halt != NULL): a
+// halted cube is skipped (its residuals stay those of its last iteration);
+// otherwise the cube's iteration count is advanced, *ran is set, and the
+// cube halts when max(||O - L - S||_inf, ||L - Z||_inf) <= eps (eps > 0),
+// Algorithm 1's convergence check.
 __global__ void k_finish_iter(const double* __restrict__ part, int n_cubes, const double* __restrict__ mu_dev,
-                              double* __restrict__ out, double* __restrict__ res_user, int* __restrict__ flag) {
+                              double* __restrict__ out, double* __restrict__ res_user, int* __restrict__ flag,
+                              int* __restrict__ halt, int* __restrict__ iters, int* __restrict__ ran,
+                              const double* __restrict__ eps_dev) {
   __shared__ double red[8];
   const int c = blockIdx.x;
   if (c >= n_cubes) return;
+  if (halt && halt[c]) return;
   const double* p = part + (int64_t)c * R_COUNT * LRSTV_PARTS;
   double v[R_COUNT];
   double nbad = 0.0;
@@ -214,11 +239,31 @@ __global__ void k_finish_iter(const double* __restrict__ part, int n_cubes, cons
       bad |= !isfinite(o[r]);
     }
     if (bad) atomicExch(flag, 1);
+    if (halt) {
+      iters[c] += 1;
+      *ran = 1;
+      const double eps = *eps_dev;
+      if (eps > 0.0 && fmax(o[R_INF_OLS], o[R_INF_LZ]) <= eps) halt[c] = 1;
+    }
   }
 }
 
-__global__ void k_mu_step(double* mu, double rho, double mu_max) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *mu = fmin(rho * *mu, mu_max);
+// mu <- min(rho mu, mu_max) (7th step).  With a stopping state the step is
+// taken only when some cube ran this iteration, and the marker is cleared.
+__global__ void k_mu_step(double* mu, double rho, double mu_max, int* __restrict__ ran) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (!ran || *ran) *mu = fmin(rho * *mu, mu_max);
+    if (ran) *ran = 0;
+  }
+}
+
+__global__ void k_fill_int(int* __restrict__ p, int64_t n, int v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_set_double(double* p, double v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
 // ------------------------------------------------------------ launchers ---
@@ -251,12 +296,25 @@ void launch_set_mu(double* mu, double v, hipStream_t s) {
 
 
 void launch_finish_iter(const double* part, int n_cubes, const double* mu, double* out, double* res_user,
-                        int* flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish_iter, dim3(n_cubes), dim3(256), 0, s, part, n_cubes, mu, out, res_user, flag);
+                        int* flag, const StopState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_iter, dim3(n_cubes), dim3(256), 0, s, part, n_cubes, mu, out, res_user, flag,
+                     st ? st->halt : nullptr, st ? st->iters : nullptr, st ? st->ran : nullptr,
+                     st ? st->eps : nullptr);
 }
 
-void launch_mu_step(double* mu, double rho, double mu_max, hipStream_t s) {
-  hipLaunchKernelGGL(k_mu_step, dim3(1), dim3(64), 0, s, mu, rho, mu_max);
+void launch_mu_step(double* mu, double rho, double mu_max, int* ran, hipStream_t s) {
+  hipLaunchKernelGGL(k_mu_step, dim3(1), dim3(64), 0, s, mu, rho, mu_max, ran);
+}
+
+void launch_fill_int(int* p, int64_t n, int v, hipStream_t s) {
+  if (n <= 0) return;
+  int grid = (int)((n + 255) / 256);
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(k_fill_int, dim3(grid), dim3(256), 0, s, p, n, v);
+}
+
+void launch_set_double(double* p, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_double, dim3(1), dim3(64), 0, s, p, v);
 }
 
 void launch_lrhs_batch(const BatchTab& bt, const BatchPtrs& p, const Weights& wt, const double* mu, hipStream_t s) {
@@ -267,7 +325,7 @@ void launch_lrhs_batch(const BatchTab& bt, const BatchPtrs& p, const Weights& wt
 void launch_grad_shrink_batch(const BatchTab& bt, const BatchPtrs& p, const Weights& wt, const double* mu,
                               double* part, hipStream_t s) {
   hipLaunchKernelGGL(k_grad_shrink_batch, dim3(bt.nc * LRSTV_PARTS), dim3(512), 0, s, bt, p, (float)wt.w[0],
-                     (float)wt.w[1], (float)wt.w[2], (float)wt.tau, (float)wt.lam, mu, part);
+                     (float)wt.w[1], (float)wt.w[2], (float)wt.tau, (float)wt.lam, wt.iso, mu, part);
 }
 
 }  // namespace lrstv

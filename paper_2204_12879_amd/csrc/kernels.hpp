@@ -10,6 +10,7 @@ namespace lrstv {
 struct Weights {
   double tau, alpha, lam;
   double w[3];
+  int iso;   // 1: isotropic gradient term (group soft-threshold per voxel)
 };
 
 
@@ -34,7 +35,11 @@ struct BatchTab {
   int reg_h_mask;          // h FFT lengths present that run in registers (bit 0: 64, 1: 128, 2: 256)
   int stockham_h;          // 1 when some cube's h FFT runs through the LDS Stockham path
   int reg_w_mask, stockham_w;   // the same for the w transforms
+  const int* halt;         // device [nc] or NULL: a cube whose entry is non-zero
+                           // has met the stopping test; every phase skips it
 };
+// Block-uniform early exit of a batched phase for a halted cube.
+__device__ __forceinline__ bool cube_halted(const BatchTab& bt, int c) { return bt.halt && bt.halt[c] != 0; }
 // Bit of an FFT length that runs in registers (64, 128, 256), else 0.
 __host__ __device__ inline int fft_h_reg_bit(int h) { return h == 64 ? 1 : h == 128 ? 2 : h == 256 ? 4 : 0; }
 // Base pointers of the packed batch (gradient-shaped arrays and A: 3
@@ -93,9 +98,19 @@ void launch_fill(float* p, int64_t n, float v, hipStream_t s);
 void launch_copy(float* dst, const float* src, int64_t n, hipStream_t s);
 void launch_set_mu(double* mu, double v, hipStream_t s);
 void launch_fill_hash(float* p, int64_t n, uint32_t seed, hipStream_t s);
+// Per-cube stopping state of an iteration (all device arrays, or halt NULL
+// for runs without a stopping test).
+struct StopState {
+  int* halt;            // [nc] 1 once the cube met the stopping test
+  int* iters;           // [nc] iterations the cube has run since the reset
+  int* ran;             // [1] set when some cube ran this iteration (read by the mu step)
+  const double* eps;    // [1] stopping tolerance, <= 0: no test
+};
 void launch_finish_iter(const double* part, int n_cubes, const double* mu, double* out, double* res_user,
-                        int* flag, hipStream_t s);
-void launch_mu_step(double* mu, double rho, double mu_max, hipStream_t s);
+                        int* flag, const StopState* st, hipStream_t s);
+void launch_mu_step(double* mu, double rho, double mu_max, int* ran, hipStream_t s);
+void launch_fill_int(int* p, int64_t n, int v, hipStream_t s);
+void launch_set_double(double* p, double v, hipStream_t s);
 void launch_lrhs_batch(const BatchTab& bt, const BatchPtrs& p, const Weights& wt, const double* mu, hipStream_t s);
 void launch_grad_shrink_batch(const BatchTab& bt, const BatchPtrs& p, const Weights& wt, const double* mu,
                               double* part, hipStream_t s);
@@ -148,6 +163,7 @@ struct SvtLaunch {
   float thresh;            // fixed threshold when mu == NULL
   int precision;
   int tri_variant = kTriDefault;  // tridiagonalisation shape (autotuned)
+  const int* halt = nullptr;      // device [cubes] or NULL: slices of halted cubes are skipped
 };
 // Slices beyond the last full round of the one-block-per-slice kernels run
 // on a second stream from the tridiagonalisation on, after the first group's

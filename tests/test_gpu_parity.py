@@ -265,14 +265,15 @@ def _kept_fraction_of_output(E):
     slice has rank equal to the number of singular values above the
     threshold, so count the non-negligible singular values of the
     non-redundant Fourier slices of each tensor E_n."""
-    kept = tot = 0
+    svs = []
     for n in range(E.shape[0]):
         Eh = np.fft.fft(E[n], axis=0)
         for k in range(E.shape[1] // 2 + 1):
-            sv = np.linalg.svd(Eh[k], compute_uv=False)
-            kept += int((sv > 1e-9 * max(sv.max(), 1e-300)).sum())
-            tot += sv.size
-    return kept / tot
+            svs.append(np.linalg.svd(Eh[k], compute_uv=False))
+    sv = np.concatenate(svs)
+    # relative to the largest over all slices: a slice the SVT zeroed has
+    # only rounding-level singular values and keeps none
+    return float(np.mean(sv > 1e-9 * sv.max()))
 
 
 def test_small_cube_full_run_in_the_thresholding_regime():
