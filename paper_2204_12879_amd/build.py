@@ -16,6 +16,38 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-but-set-variable"]
 
 
+# Host-side AddressSanitizer and UndefinedBehaviorSanitizer for the ABI layer
+# (the device code is built as usual; GPU sanitizers are not used).
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined",
+            "-shared-libsan"]
+
+
+def build_sanitized(out: str, verbose: bool = False) -> str:
+    """Build the library with host ASan + UBSan into `out` (load it with the
+    clang ASan runtime preloaded, see asan_runtime())."""
+    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    flags = [f for f in FLAGS if f != "-O3"] + ["-O1", "-g"]
+    cmd = [HIPCC] + flags + SANITIZE + ["-o", out] + srcs
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True, capture_output=not verbose)
+    return out
+
+
+def asan_runtime() -> str:
+    """Path of clang's shared ASan runtime that a sanitized build needs."""
+    out = subprocess.run([HIPCC, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True,
+                         text=True).stdout.strip()
+    if out and os.path.exists(out):
+        return out
+    import glob
+    hits = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not hits:
+        raise FileNotFoundError("libclang_rt.asan-x86_64.so not found")
+    return hits[-1]
+
+
 def build(verbose: bool = True) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp"
