@@ -121,8 +121,8 @@ def admm_step_vjp(O: np.ndarray, st: State, p: Params, g_new: State,
     the L computed in this iteration (None = 0).
     Returns (g_st, g_O, g_tau, g_alpha, g_lambda).
     """
-    if p.tv != "aniso":
-        raise NotImplementedError("the adjoint covers the anisotropic regulariser only")
+    if p.tv != "aniso" or p.beta > 0:
+        raise NotImplementedError("the adjoint covers the anisotropic model without the noise term only")
     mu, w = st.mu, p.w
     # forward quantities of this iteration
     L = l_update(O, st)

@@ -31,6 +31,10 @@ notes):
     full-rank Tucker model returns its input);
   * initial state: Z = O, every other variable 0, mu = mu0;
   * the multipliers use the mu of the current iteration, then mu is raised;
+  * the explicit noise term: the complexity discussion of Sec. III-D speaks
+    of updates of S and N although the model has no N; the N variant adds
+    beta ||N||_F^2 with O = L + S + N and updates N after S by its exact
+    block minimiser (beta = 0 keeps the model without N);
   * the isotropic regulariser (Sec. III-A, eq. CRSSTV_iso) is read per voxel:
     its l2 norm couples the three directional differences of one voxel, so
     the F-update group-thresholds each voxel's 3-vector with the same tau/mu
@@ -159,6 +163,7 @@ class Params:
     rho: float = 1.5
     mu_max: float = 1e6
     tv: str = "aniso"    # "aniso": l1 of the gradients; "iso": l2 over the 3 directions per voxel
+    beta: float = 0.0    # > 0: explicit Gaussian term beta ||N||_F^2 with O = L + S + N; 0: no N
 
 
 @dataclasses.dataclass
@@ -172,6 +177,7 @@ class State:
     G3: np.ndarray     # (3, b, h, w)
     G4: np.ndarray     # (3, b, h, w)
     mu: float
+    N: Optional[np.ndarray] = None   # explicit noise term (None: the model without N)
 
     def copy(self) -> "State":
         return State(**{f.name: (getattr(self, f.name).copy()
@@ -188,9 +194,15 @@ def init_state(O: np.ndarray, mu0: float) -> State:
                  G3=t.copy(), G4=t.copy(), mu=float(mu0))
 
 
+def _n(st: State):
+    return 0.0 if st.N is None else st.N
+
+
 def l_update(O, st: State) -> np.ndarray:
-    """1st step: L = 1/2 (O - S + Z + (Gamma1 - Gamma2)/mu) (full Tucker rank)."""
-    return 0.5 * (O - st.S + st.Z + (st.G1 - st.G2) / st.mu)
+    """1st step: L = 1/2 (O - S + Z + (Gamma1 - Gamma2)/mu) (full Tucker rank);
+    with the explicit noise term the first constraint is O = L + S + N, so
+    O - S - N takes the place of O - S."""
+    return 0.5 * (O - st.S - _n(st) + st.Z + (st.G1 - st.G2) / st.mu)
 
 
 def z_rhs(L, st: State, w) -> np.ndarray:
@@ -221,8 +233,14 @@ def e_update(F, st: State, p: Params) -> np.ndarray:
 
 
 def s_update(O, L, st: State, p: Params) -> np.ndarray:
-    """5th step: S = R_{lambda/mu}(O - L + Gamma1/mu)."""
-    return soft(O - L + st.G1 / st.mu, p.lam / st.mu)
+    """5th step: S = R_{lambda/mu}(O - L + Gamma1/mu) (O - L - N with the noise term)."""
+    return soft(O - L - _n(st) + st.G1 / st.mu, p.lam / st.mu)
+
+
+def n_update(O, L, S, st: State, p: Params) -> np.ndarray:
+    """Noise step (after S): argmin_N beta ||N||^2 + <Gamma1, O-L-S-N> + mu/2 ||O-L-S-N||^2
+    = (mu (O - L - S) + Gamma1) / (mu + 2 beta)."""
+    return (st.mu * (O - L - S) + st.G1) / (st.mu + 2.0 * p.beta)
 
 
 def admm_step(O: np.ndarray, st: State, p: Params) -> Tuple[State, np.ndarray, Dict[str, float]]:
@@ -233,23 +251,27 @@ def admm_step(O: np.ndarray, st: State, p: Params) -> Tuple[State, np.ndarray, D
     F = f_update(Z, st, p)
     E = e_update(F, st, p)
     S = s_update(O, L, st, p)
+    N = n_update(O, L, S, st, p) if p.beta > 0 else None
     DZ = grad_w(Z, p.w)
+    R1 = O - L - S - (0.0 if N is None else N)
     new = State(Z=Z, S=S, F=F, E=E,
-                G1=st.G1 + mu * (O - L - S),
+                G1=st.G1 + mu * R1,
                 G2=st.G2 + mu * (L - Z),
                 G3=st.G3 + mu * (DZ - F),
                 G4=st.G4 + mu * (E - F),
-                mu=min(p.rho * mu, p.mu_max))
-    res = residuals(O, L, Z, S, F, E, DZ, st.Z, mu)
+                mu=min(p.rho * mu, p.mu_max), N=N)
+    res = residuals(O, L, Z, S, F, E, DZ, st.Z, mu, N)
     return new, L, res
 
 
-def residuals(O, L, Z, S, F, E, DZ, Z_prev, mu) -> Dict[str, float]:
-    """Stopping quantities of Algorithm 1 plus Frobenius primal/dual residuals."""
+def residuals(O, L, Z, S, F, E, DZ, Z_prev, mu, N=None) -> Dict[str, float]:
+    """Stopping quantities of Algorithm 1 plus Frobenius primal/dual residuals
+    (the first constraint's residual is O - L - S - N with the noise term)."""
+    R1 = O - L - S - (0.0 if N is None else N)
     return {
-        "inf_OLS": float(np.abs(O - L - S).max()),
+        "inf_OLS": float(np.abs(R1).max()),
         "inf_LZ": float(np.abs(L - Z).max()),
-        "fro_OLS": float(np.linalg.norm(O - L - S)),
+        "fro_OLS": float(np.linalg.norm(R1)),
         "fro_LZ": float(np.linalg.norm(L - Z)),
         "fro_DZF": float(np.linalg.norm(DZ - F)),
         "fro_EF": float(np.linalg.norm(E - F)),
@@ -284,15 +306,23 @@ def admm(O: np.ndarray, p: Params, iters: int, eps: float = 0.0,
 
 def objective(X: np.ndarray, O: np.ndarray, p: Params) -> float:
     """2 tau ||D_w X||_1 + alpha sum_n TNN(w_n D_n X) + lambda ||O - X||_1
-    (isotropic: 2 tau sum_v ||(D_w X)_v||_2 in place of the l1 term).
+    (isotropic: 2 tau sum_v ||(D_w X)_v||_2 in place of the l1 term; with the
+    noise term the fit is min_S lambda ||S||_1 + beta ||O - X - S||^2).
 
     The factor 2 on tau is the weight for which the printed F threshold tau/mu
     is the exact block minimiser.
     """
     DX = grad_w(X, p.w)
     tv = np.sqrt((DX ** 2).sum(axis=0)).sum() if p.tv == "iso" else np.abs(DX).sum()
-    return float(2 * p.tau * tv + p.alpha * sum(tnn(DX[n]) for n in range(3))
-                 + p.lam * np.abs(O - X).sum())
+    if p.beta > 0:
+        # min over S + N = O - X of lambda ||S||_1 + beta ||N||^2 (a Huber loss):
+        # S = R_{lambda / 2 beta}(O - X)
+        r = O - X
+        S = soft(r, p.lam / (2 * p.beta))
+        fit = p.lam * np.abs(S).sum() + p.beta * ((r - S) ** 2).sum()
+    else:
+        fit = p.lam * np.abs(O - X).sum()
+    return float(2 * p.tau * tv + p.alpha * sum(tnn(DX[n]) for n in range(3)) + fit)
 
 
 def mpsnr(x: np.ndarray, ref: np.ndarray) -> float:

@@ -566,3 +566,99 @@ def test_iso_f_block_optimality_from_stored_states_and_objective_at_convergence(
         for _ in range(60):
             assert f(X + scale * rng.normal(size=X.shape)) >= f0 - 1e-6
     assert abs(oracle.objective(X, noisy, p) - f0) < 1e-9
+
+
+# ------------------------------------------- explicit noise term (beta) ---
+
+def _n_lagrangian(O, L, S, N, Z, F, E, G1, G2, G3, G4, mu, p, diffs):
+    """Augmented Lagrangian of the model with the noise term: beta ||N||^2 is
+    added and the first constraint reads O = L + S + N."""
+    return lagrangian(O - N, L, S, Z, F, E, G1, G2, G3, G4, mu, p, diffs) + p.beta * (N ** 2).sum()
+
+
+def test_noise_term_blocks_minimise_their_lagrangian():
+    O, p, st = _tiny_problem(seed=31)
+    p.beta = 0.7
+    rng = np.random.default_rng(32)
+    st.N = rng.normal(size=O.shape) * 0.2
+    Dw = loop_grad_w(p.w)
+    mu = st.mu
+    cur = dict(L=oracle.l_update(O, st), S=st.S, N=st.N, Z=st.Z, F=st.F, E=st.E)
+
+    def lag(**kw):
+        v = dict(cur)
+        v.update(kw)
+        return _n_lagrangian(O, v["L"], v["S"], v["N"], v["Z"], v["F"], v["E"], st.G1, st.G2, st.G3, st.G4,
+                             mu, p, Dw)
+
+    def check_min(name, value, smooth):
+        f0 = lag(**{name: value})
+        for scale in [1e-6, 1e-3, 1e-1, 1.0]:
+            for _ in range(40):
+                f1 = lag(**{name: value + scale * rng.normal(size=value.shape)})
+                assert f1 >= f0 - 1e-9 * max(1.0, abs(f0)), (name, scale, f1 - f0)
+        if smooth:
+            for _ in range(5):
+                d = rng.normal(size=value.shape)
+                g = (lag(**{name: value + 1e-5 * d}) - lag(**{name: value - 1e-5 * d})) / 2e-5
+                assert abs(g) < 1e-5 * max(1.0, abs(f0))
+
+    check_min("L", cur["L"], smooth=True)
+    Z = oracle.z_solve(oracle.z_rhs(cur["L"], st, p.w), mu, p.w)
+    cur["Z"] = Z
+    F = oracle.f_update(Z, st, p)
+    cur["F"] = F
+    cur["E"] = oracle.e_update(F, st, p)
+    S = oracle.s_update(O, cur["L"], st, p)
+    check_min("S", S, smooth=False)
+    cur["S"] = S
+    N = oracle.n_update(O, cur["L"], S, st, p)
+    check_min("N", N, smooth=True)
+    # admm_step composes them, and the first multiplier gains mu (O - L - S - N)
+    new, L, res = oracle.admm_step(O, st, p)
+    np.testing.assert_allclose(new.N, N, atol=1e-14)
+    np.testing.assert_allclose(new.G1, st.G1 + mu * (O - L - new.S - new.N), atol=1e-12)
+    assert res["inf_OLS"] == pytest.approx(np.abs(new.G1 - st.G1).max() / mu, rel=1e-10)
+
+
+def test_noise_term_stationarity_and_objective_at_convergence():
+    clean, noisy = synth.make_cube(synth.CubeSpec(4, 4, 5, 3, synth.NOISE_SMALL, 11))
+    p = oracle.Params(tau=0.05, alpha=0.1, lam=0.5, mu0=0.1, rho=1.2, mu_max=1e4, beta=2.0)
+    X, S, st, hist = oracle.admm(noisy, p, 400)
+    assert hist[-1]["inf_OLS"] < 1e-6 and hist[-1]["inf_LZ"] < 1e-6
+    # stationarity in N: Gamma1 = 2 beta N; in S: Gamma1 in lambda d|S|
+    np.testing.assert_allclose(st.G1, 2 * p.beta * st.N, atol=1e-6)
+    assert np.abs(st.G1).max() <= p.lam + 1e-6
+    nz = np.abs(st.S) > 1e-5
+    assert nz.any() and (~nz).any() and np.abs(st.N).max() > 1e-3
+    # (up to mu times the last change of N, which the S-update does not see)
+    np.testing.assert_allclose(st.G1[nz], p.lam * np.sign(st.S[nz]), atol=1e-4)
+    Dw = loop_grad_w(p.w)
+
+    def f(Yc):
+        DY = Dw(Yc)
+        r = noisy - Yc
+        Sm = np.sign(r) * np.maximum(np.abs(r) - p.lam / (2 * p.beta), 0)   # the minimising S, by hand
+        return 2 * p.tau * np.abs(DY).sum() + p.alpha * sum(tnn_bcirc(DY[n]) for n in range(3)) \
+            + p.lam * np.abs(Sm).sum() + p.beta * ((r - Sm) ** 2).sum()
+
+    f0 = f(X)
+    rng = np.random.default_rng(34)
+    for scale in [1e-4, 1e-3, 1e-2, 1e-1]:
+        for _ in range(60):
+            assert f(X + scale * rng.normal(size=X.shape)) >= f0 - 1e-6
+    assert abs(oracle.objective(X, noisy, p) - f0) < 1e-9
+
+
+def test_large_beta_recovers_the_model_without_noise_term():
+    clean, noisy = synth.make_cube(synth.CubeSpec(6, 5, 8, 4, synth.NOISE_SMALL, 13))
+    p0 = oracle.Params(tau=0.05, alpha=0.2, lam=0.3, mu0=0.05, rho=1.3)
+    pb = oracle.Params(tau=0.05, alpha=0.2, lam=0.3, mu0=0.05, rho=1.3, beta=1e9)
+    X0, S0, st0, _ = oracle.admm(noisy, p0, 15)
+    Xb, Sb, stb, _ = oracle.admm(noisy, pb, 15)
+    assert np.abs(stb.N).max() < 1e-6
+    assert np.linalg.norm(Xb - X0) / np.linalg.norm(X0) < 1e-6
+    # a moderate beta gives a different, non-trivial N
+    pm = oracle.Params(tau=0.05, alpha=0.2, lam=0.3, mu0=0.05, rho=1.3, beta=3.0)
+    Xm, Sm, stm, _ = oracle.admm(noisy, pm, 15)
+    assert np.linalg.norm(Xm - X0) / np.linalg.norm(X0) > 1e-3 and np.abs(stm.N).max() > 1e-2
