@@ -121,7 +121,7 @@ def admm_step_vjp(O: np.ndarray, st: State, p: Params, g_new: State,
     the L computed in this iteration (None = 0).
     Returns (g_st, g_O, g_tau, g_alpha, g_lambda).
     """
-    if p.tv != "aniso" or p.beta > 0:
+    if p.tv != "aniso" or p.beta > 0 or p.tucker is not None:
         raise NotImplementedError("the adjoint covers the anisotropic model without the noise term only")
     mu, w = st.mu, p.w
     # forward quantities of this iteration

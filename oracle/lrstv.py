@@ -28,7 +28,10 @@ notes):
     DFT along the bands, so the t-SVT threshold of every Fourier slice is the
     SVT threshold itself;
   * the L-update at full Tucker rank is the unconstrained minimiser (HOOI of a
-    full-rank Tucker model returns its input);
+    full-rank Tucker model returns its input); with truncated ranks, HOOI
+    starts from the truncated HOSVD and runs a fixed number of sweeps
+    (the count is not stated; default one), each updating the three
+    modes in order from the latest factors;
   * initial state: Z = O, every other variable 0, mu = mu0;
   * the multipliers use the mu of the current iteration, then mu is raised;
   * the explicit noise term: the complexity discussion of Sec. III-D speaks
@@ -150,6 +153,65 @@ def z_solve(Tz: np.ndarray, mu: float, w: Sequence[float]) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
+# Truncated Tucker decomposition (HOOI) of the L-update
+# ---------------------------------------------------------------------------
+
+# array axis of the paper's Tucker modes 1 (height), 2 (width), 3 (bands)
+MODE_AXIS = (1, 2, 0)
+
+
+def mode_unfold(X: np.ndarray, n: int) -> np.ndarray:
+    """Mode-n matricisation X_(n): the mode's index runs down the rows."""
+    ax = MODE_AXIS[n]
+    return np.moveaxis(X, ax, 0).reshape(X.shape[ax], -1)
+
+
+def mode_product(X: np.ndarray, M: np.ndarray, n: int) -> np.ndarray:
+    """X x_n M: every mode-n fibre of X multiplied by the matrix M."""
+    ax = MODE_AXIS[n]
+    return np.moveaxis(np.tensordot(M, X, axes=([1], [ax])), 0, ax)
+
+
+def leading_subspace(G: np.ndarray, r: int) -> np.ndarray:
+    """Orthonormal basis (columns) of the eigenvectors of the r largest
+    eigenvalues of the symmetric matrix G."""
+    vals, vecs = np.linalg.eigh(G)
+    return vecs[:, ::-1][:, :r]
+
+
+def hooi(X: np.ndarray, ranks: Sequence[int], sweeps: int):
+    """Higher-order orthogonal iteration for the Tucker ranks (r1, r2, r3).
+
+    Start: the leading r_n left singular vectors of each unfolding X_(n)
+    (truncated HOSVD, from the eigenvectors of X_(n) X_(n)^T).  Each sweep
+    then updates the modes in order 1, 2, 3 from the latest factors: U_n =
+    leading r_n left singular vectors of (X x_{m != n} U_m^T)_(n).  Result:
+    the core C = X x_1 U1^T x_2 U2^T x_3 U3^T and L = C x_1 U1 x_2 U2 x_3 U3,
+    i.e. X projected by U_n U_n^T along every mode.  Returns (L, [U1, U2, U3]).
+    """
+    r = [min(int(ranks[n]), X.shape[MODE_AXIS[n]]) for n in range(3)]
+    U = []
+    for n in range(3):
+        Xn = mode_unfold(X, n)
+        U.append(leading_subspace(Xn @ Xn.T, r[n]))
+    for _ in range(sweeps):
+        for n in range(3):
+            Y = X
+            for m in range(3):
+                if m != n:
+                    Y = mode_product(Y, U[m].T, m)
+            Yn = mode_unfold(Y, n)
+            U[n] = leading_subspace(Yn @ Yn.T, r[n])
+    C = X
+    for n in range(3):
+        C = mode_product(C, U[n].T, n)
+    L = C
+    for n in range(3):
+        L = mode_product(L, U[n], n)
+    return L, U
+
+
+# ---------------------------------------------------------------------------
 # The ADMM
 # ---------------------------------------------------------------------------
 
@@ -164,6 +226,8 @@ class Params:
     mu_max: float = 1e6
     tv: str = "aniso"    # "aniso": l1 of the gradients; "iso": l2 over the 3 directions per voxel
     beta: float = 0.0    # > 0: explicit Gaussian term beta ||N||_F^2 with O = L + S + N; 0: no N
+    tucker: Optional[Tuple[int, int, int]] = None   # Tucker ranks (r1, r2, r3) of L; None: full rank
+    hooi_sweeps: int = 1                             # HOOI sweeps after the HOSVD start
 
 
 @dataclasses.dataclass
@@ -198,11 +262,16 @@ def _n(st: State):
     return 0.0 if st.N is None else st.N
 
 
-def l_update(O, st: State) -> np.ndarray:
-    """1st step: L = 1/2 (O - S + Z + (Gamma1 - Gamma2)/mu) (full Tucker rank);
-    with the explicit noise term the first constraint is O = L + S + N, so
-    O - S - N takes the place of O - S."""
-    return 0.5 * (O - st.S - _n(st) + st.Z + (st.G1 - st.G2) / st.mu)
+def l_update(O, st: State, p: Optional["Params"] = None) -> np.ndarray:
+    """1st step: L = argmin over Tucker rank (r1, r2, r3) of
+    ||L - 1/2 (O - S + Z + (Gamma1 - Gamma2)/mu)||_F by HOOI (eq.
+    X_solution); at full rank the projection is the identity and L is the
+    average itself.  With the explicit noise term the first constraint is
+    O = L + S + N, so O - S - N takes the place of O - S."""
+    Xa = 0.5 * (O - st.S - _n(st) + st.Z + (st.G1 - st.G2) / st.mu)
+    if p is None or p.tucker is None:
+        return Xa
+    return hooi(Xa, p.tucker, p.hooi_sweeps)[0]
 
 
 def z_rhs(L, st: State, w) -> np.ndarray:
@@ -246,7 +315,7 @@ def n_update(O, L, S, st: State, p: Params) -> np.ndarray:
 def admm_step(O: np.ndarray, st: State, p: Params) -> Tuple[State, np.ndarray, Dict[str, float]]:
     """One iteration of Algorithm 1; returns (new state, L, residuals)."""
     mu = st.mu
-    L = l_update(O, st)
+    L = l_update(O, st, p)
     Z = z_solve(z_rhs(L, st, p.w), mu, p.w)
     F = f_update(Z, st, p)
     E = e_update(F, st, p)
