@@ -86,6 +86,9 @@ typedef struct lrstv_params {
   double mu_max;   /* penalty cap (>= mu0)                                   */
   int32_t precision;  /* LRSTV_FP32 or LRSTV_SPLIT_BF16                      */
   int32_t tv;         /* LRSTV_TV_ANISO (the paper's TDLRSTV) or LRSTV_TV_ISO  */
+  double beta;        /* >= 0; > 0 adds the explicit Gaussian term beta ||N||_F^2
+                         with Y = X + S + N (N updated after S by its block
+                         minimiser); 0: no N variable, N = Y - X - S          */
 } lrstv_params;
 
 typedef struct lrstv_state_view {
@@ -103,6 +106,8 @@ typedef struct lrstv_state_view {
   float* E;     /* [3][batch] */
   float* G3;    /* [3][batch] */
   float* G4;    /* [3][batch] */
+  float* N;     /* explicit noise term (beta > 0); may be NULL in views
+                   passed to set_state / save_state: then left untouched  */
   double* mu;   /* device scalar: the penalty the next iteration uses     */
   int64_t total;   /* sum over cubes of b h w                             */
 } lrstv_state_view;

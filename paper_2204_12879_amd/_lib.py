@@ -35,11 +35,11 @@ class _Problem(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("tau", C.c_double), ("alpha", C.c_double), ("lam", C.c_double), ("w", C.c_double * 3),
                 ("mu0", C.c_double), ("rho", C.c_double), ("mu_max", C.c_double), ("precision", C.c_int32),
-                ("tv", C.c_int32)]
+                ("tv", C.c_int32), ("beta", C.c_double)]
 
 
 class _StateView(C.Structure):
-    _fields_ = [(n, C.c_void_p) for n in ("X", "Y", "Z", "S", "G1", "G2", "F", "E", "G3", "G4", "mu")] + \
+    _fields_ = [(n, C.c_void_p) for n in ("X", "Y", "Z", "S", "G1", "G2", "F", "E", "G3", "G4", "N", "mu")] + \
                [("total", C.c_int64)]
 
 
@@ -146,10 +146,11 @@ class Params:
     mu_max: float = 1e6
     precision: int = LRSTV_FP32
     tv: int = LRSTV_TV_ANISO     # LRSTV_TV_ISO: isotropic gradient term (group shrink per voxel)
+    beta: float = 0.0            # > 0: explicit noise term beta ||N||^2 (Y = X + S + N)
 
     def _c(self) -> _Params:
         return _Params(self.tau, self.alpha, self.lam, (C.c_double * 3)(*self.w), self.mu0, self.rho,
-                       self.mu_max, self.precision, self.tv)
+                       self.mu_max, self.precision, self.tv, self.beta)
 
 
 def _problem(shapes: Sequence[Tuple[int, int, int]]):
@@ -192,6 +193,7 @@ class StateBuffer:
             o += k
         v.X = None
         v.Y = None
+        v.N = None
         v.mu = self.mu.data_ptr() if with_mu else None
         v.total = self.total
         return v
@@ -204,7 +206,7 @@ class Solver:
     workspace is a torch tensor owned by this object.
     """
 
-    STATE_NAMES = ("X", "Y", "Z", "S", "G1", "G2", "F", "E", "G3", "G4")
+    STATE_NAMES = ("X", "Y", "Z", "S", "G1", "G2", "F", "E", "G3", "G4", "N")
 
     def __init__(self, shapes: Sequence[Tuple[int, int, int]], params: Params, stream=None):
         import torch

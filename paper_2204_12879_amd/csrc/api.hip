@@ -128,7 +128,7 @@ struct lrstv_handle_s {
   hipStream_t stream;
   SliceLayout sl;
   // state
-  float *O, *L, *Z, *S, *G1, *G2, *F, *E, *G3, *G4;
+  float *O, *L, *Z, *S, *G1, *G2, *F, *E, *G3, *G4, *N;
   // scratch
   float *T, *A, *slices, *V, *B, *fval, *Twy;
   float2 *spec, *gram;
@@ -187,6 +187,7 @@ static int check_params(const lrstv_params* p) {
     return fail(LRSTV_ERR_INVALID_ARG, "unknown precision %d", p->precision);
   if (p->tv != LRSTV_TV_ANISO && p->tv != LRSTV_TV_ISO)
     return fail(LRSTV_ERR_INVALID_ARG, "unknown gradient term %d", p->tv);
+  if (!(p->beta >= 0) || !isfinite(p->beta)) return fail(LRSTV_ERR_INVALID_ARG, "beta must be finite and >= 0");
   return LRSTV_OK;
 }
 
@@ -241,6 +242,7 @@ static void carve_handle(lrstv_handle_s* H, void* base, size_t* used) {
   H->E = cv.take<float>(3 * T);
   H->G3 = cv.take<float>(3 * T);
   H->G4 = cv.take<float>(3 * T);
+  H->N = cv.take<float>(T);
   H->T = cv.take<float>(T);
   H->A = cv.take<float>(3 * T);
   H->spec = cv.take<float2>(H->spec_total);
@@ -422,6 +424,7 @@ extern "C" int lrstv_reset(lrstv_handle H, const float* Y) {
   launch_fill(H->E, 3 * T, 0.f, s);
   launch_fill(H->G3, 3 * T, 0.f, s);
   launch_fill(H->G4, 3 * T, 0.f, s);
+  launch_fill(H->N, T, 0.f, s);
   launch_set_mu(H->mu, H->par.mu0, s);
   launch_fill_int(H->flag, 1, 0, s);
   // stopping state: no cube halted, no test until lrstv_solve sets eps
@@ -452,6 +455,7 @@ static BatchPtrs batch_ptrs(lrstv_handle_s* H) {
   p.G4 = H->G4;
   p.A = H->A;
   p.T = H->T;
+  p.N = H->par.beta > 0 ? H->N : nullptr;
   p.ts = H->total;
   return p;
 }
@@ -468,6 +472,7 @@ static void run_iteration(lrstv_handle_s* H, double* res_user) {
   wt.lam = H->par.lambda;
   for (int i = 0; i < 3; ++i) wt.w[i] = H->par.w[i];
   wt.iso = H->par.tv == LRSTV_TV_ISO;
+  wt.beta = H->par.beta;
   const int nc = (int)H->cubes.size();
   const BatchPtrs bp = batch_ptrs(H);
   tm.begin(ST_LRHS);
@@ -716,6 +721,7 @@ extern "C" int lrstv_get_state(lrstv_handle H, lrstv_state_view* v) {
   v->E = H->E;
   v->G3 = H->G3;
   v->G4 = H->G4;
+  v->N = H->N;
   v->mu = H->mu;
   v->total = H->total;
   return LRSTV_OK;
@@ -739,6 +745,7 @@ extern "C" int lrstv_set_state(lrstv_handle H, const lrstv_state_view* v) {
   launch_copy(H->E, v->E, 3 * T, s);
   launch_copy(H->G3, v->G3, 3 * T, s);
   launch_copy(H->G4, v->G4, 3 * T, s);
+  if (v->N) launch_copy(H->N, v->N, T, s);
   if (v->mu) HIPCHK(hipMemcpyAsync(H->mu, v->mu, sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(hipGetLastError());
   return LRSTV_OK;
@@ -801,8 +808,8 @@ extern "C" int lrstv_iterate_vjp(lrstv_handle H, const lrstv_state_view* before,
                                  lrstv_state_view* grad_before, double* grad_weights, float* grad_Y,
                                  int32_t flags, void* ws, size_t ws_bytes) {
   if (!H) return fail(LRSTV_ERR_INVALID_ARG, "handle is NULL");
-  if (H->par.tv != LRSTV_TV_ANISO)
-    return fail(LRSTV_ERR_UNSUPPORTED, "the adjoint covers the anisotropic gradient term only");
+  if (H->par.tv != LRSTV_TV_ANISO || H->par.beta > 0)
+    return fail(LRSTV_ERR_UNSUPPORTED, "the adjoint covers the anisotropic model without the noise term only");
   if (!before || !before->G4 || !before->mu) return fail(LRSTV_ERR_INVALID_ARG, "before needs G4 and mu");
   if (!after || !after->S || !after->F) return fail(LRSTV_ERR_INVALID_ARG, "after needs S and F");
   if (grad_after && !full_view(grad_after))
@@ -937,6 +944,7 @@ extern "C" int lrstv_save_state(lrstv_handle H, const lrstv_state_view* dst) {
   launch_copy(dst->E, H->E, 3 * T, s);
   launch_copy(dst->G3, H->G3, 3 * T, s);
   launch_copy(dst->G4, H->G4, 3 * T, s);
+  if (dst->N) launch_copy(dst->N, H->N, T, s);
   if (dst->X) launch_copy(dst->X, H->L, T, s);
   if (dst->Y) launch_copy(dst->Y, H->O, T, s);
   if (dst->mu) HIPCHK(hipMemcpyAsync(dst->mu, H->mu, sizeof(double), hipMemcpyDeviceToDevice, s));

@@ -44,11 +44,11 @@ __global__ void k_set_mu(double* mu, double v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *mu = v;
 }
 
-// L = 1/2 (O - S + Z + (Gamma1 - Gamma2)/mu)
+// L = 1/2 (O - S - N + Z + (Gamma1 - Gamma2)/mu)   (N = 0 without the noise term)
 // T_z = mu L + Gamma2 + sum_n w_n D_n^T (mu F_n - Gamma3_n),
 // (D_n^T y)[v] = y[v - e_n] - y[v].
 LRSTV_DEV void lrhs_body(int bid, int nblk, const float* __restrict__ O, const float* __restrict__ S,
-                         const float* __restrict__ Z, const float* __restrict__ G1, const float* __restrict__ G2,
+                         const float* __restrict__ Nz, const float* __restrict__ Z, const float* __restrict__ G1, const float* __restrict__ G2,
                          const float* __restrict__ F, const float* __restrict__ G3, int64_t ts,
                          float* __restrict__ L, float* __restrict__ Tz, int h, int w, int b, float w1, float w2,
                          float w3, const double* __restrict__ mu_dev) {
@@ -59,7 +59,8 @@ LRSTV_DEV void lrhs_body(int bid, int nblk, const float* __restrict__ O, const f
     const int x = (int)(q % w);
     const int i = (int)((q / w) % h);
     const int j = (int)(q / hw);
-    const float l = 0.5f * (O[q] - S[q] + Z[q] + (G1[q] - G2[q]) * imu);
+    const float nq = Nz ? Nz[q] : 0.f;
+    const float l = 0.5f * (O[q] - S[q] - nq + Z[q] + (G1[q] - G2[q]) * imu);
     L[q] = l;
     const int64_t qh = (i == 0) ? q + (int64_t)(h - 1) * w : q - w;
     const int64_t qw = (x == 0) ? q + (w - 1) : q - 1;
@@ -84,7 +85,8 @@ __global__ void __launch_bounds__(256) k_lrhs_batch(BatchTab bt, BatchPtrs p, fl
   if (cube_halted(bt, c)) return;
   const CubeGeo g = uniform_geo(bt.geo, c);
   const int64_t o = g.off;
-  lrhs_body(blockIdx.x - bt.bstart[c], bt.bstart[c + 1] - bt.bstart[c], p.O + o, p.S + o, p.Z + o, p.G1 + o,
+  lrhs_body(blockIdx.x - bt.bstart[c], bt.bstart[c + 1] - bt.bstart[c], p.O + o, p.S + o,
+            p.N ? p.N + o : nullptr, p.Z + o, p.G1 + o,
             p.G2 + o, p.F + o, p.G3 + o, p.ts, p.L + o, p.T + o, g.h, g.w, g.b, w1, w2, w3, mu_dev);
 }
 
@@ -94,21 +96,25 @@ __global__ void __launch_bounds__(256) k_lrhs_batch(BatchTab bt, BatchPtrs p, fl
 //    the norm over the three directions of the voxel)
 // Gamma3_n += mu (G_n - F_n);   A_n = F_n - Gamma4_n / mu
 // Gamma2 += mu (L - Z)
-// S = R_{lambda/mu}(O - L + Gamma1/mu);   Gamma1 += mu (O - L - S)
+// S = R_{lambda/mu}(O - L - N + Gamma1/mu);   with the noise term
+// N' = (mu (O - L - S) + Gamma1) / (mu + 2 beta);   Gamma1 += mu (O - L - S - N')
 // Residual partials (one per block, fixed grid of LRSTV_PARTS blocks):
 //   max|O-L-S|, max|L-Z|, sum (O-L-S)^2, sum (L-Z)^2, sum_n (G_n - F_n)^2.
 LRSTV_DEV void grad_shrink_body(
     int bid, const float* __restrict__ O, const float* __restrict__ L, const float* __restrict__ Z,
-    float* __restrict__ S, float* __restrict__ G1, float* __restrict__ G2, float* __restrict__ F,
+    float* __restrict__ S, float* __restrict__ Nz, float* __restrict__ G1, float* __restrict__ G2,
+    float* __restrict__ F,
     const float* __restrict__ E, float* __restrict__ G3, const float* __restrict__ G4, float* __restrict__ A,
     int64_t ts, int64_t as, int h, int w, int b, float w1, float w2, float w3, float tau, float lam, int iso,
-    const double* __restrict__ mu_dev, double* __restrict__ part /* [R_COUNT][LRSTV_PARTS] of this cube */) {
+    double beta, const double* __restrict__ mu_dev,
+    double* __restrict__ part /* [R_COUNT][LRSTV_PARTS] of this cube */) {
   constexpr int nblk = LRSTV_PARTS;
   __shared__ double red[8];
   const int64_t hw = (int64_t)h * w, N = hw * b;
   const double mud = *mu_dev;
   const float mu = (float)mud, imu = (float)(1.0 / mud);
   const float tmu = (float)(tau / mud), lmu = (float)(lam / mud);
+  const float inb = (float)(1.0 / (mud + 2.0 * beta));   // the noise step's divisor
   const float wn[3] = {w1, w2, w3};
   // maxima in FP32 (exact), sums of squares in FP64 from the first term on
   float m_ols = 0.f, m_lz = 0.f;
@@ -149,9 +155,15 @@ LRSTV_DEV void grad_shrink_body(
     }
     G2[q] = G2[q] + mu * (l - z);
     const float g1 = G1[q];
-    const float s = soft_threshold(o - l + g1 * imu, lmu);
+    const float nold = Nz ? Nz[q] : 0.f;
+    const float s = soft_threshold(o - l - nold + g1 * imu, lmu);
     S[q] = s;
-    const float r = o - l - s, dz2 = l - z;
+    float nn = 0.f;
+    if (Nz) {
+      nn = (mu * (o - l - s) + g1) * inb;
+      Nz[q] = nn;
+    }
+    const float r = o - l - s - nn, dz2 = l - z;
     G1[q] = g1 + mu * r;
     m_ols = fmaxf(m_ols, fabsf(r));
     m_lz = fmaxf(m_lz, fabsf(dz2));
@@ -180,15 +192,17 @@ LRSTV_DEV void grad_shrink_body(
 
 // Batch: LRSTV_PARTS blocks per cube, cube c's residual slots at part + c R_COUNT LRSTV_PARTS.
 __global__ void __launch_bounds__(512) k_grad_shrink_batch(BatchTab bt, BatchPtrs p, float w1, float w2, float w3,
-                                                           float tau, float lam, int iso,
+                                                           float tau, float lam, int iso, double beta,
                                                            const double* __restrict__ mu_dev,
                                                            double* __restrict__ part) {
   const int c = blockIdx.x / LRSTV_PARTS;
   if (cube_halted(bt, c)) return;
   const CubeGeo g = uniform_geo(bt.geo, c);
   const int64_t o = g.off;
-  grad_shrink_body(blockIdx.x - c * LRSTV_PARTS, p.O + o, p.L + o, p.Z + o, p.S + o, p.G1 + o, p.G2 + o, p.F + o,
-                   p.E + o, p.G3 + o, p.G4 + o, p.A + o, p.ts, p.ts, g.h, g.w, g.b, w1, w2, w3, tau, lam, iso, mu_dev,
+  grad_shrink_body(blockIdx.x - c * LRSTV_PARTS, p.O + o, p.L + o, p.Z + o, p.S + o, p.N ? p.N + o : nullptr,
+                   p.G1 + o, p.G2 + o, p.F + o,
+                   p.E + o, p.G3 + o, p.G4 + o, p.A + o, p.ts, p.ts, g.h, g.w, g.b, w1, w2, w3, tau, lam, iso, beta,
+                   mu_dev,
                    part + (int64_t)c * R_COUNT * LRSTV_PARTS);
 }
 
@@ -325,7 +339,7 @@ void launch_lrhs_batch(const BatchTab& bt, const BatchPtrs& p, const Weights& wt
 void launch_grad_shrink_batch(const BatchTab& bt, const BatchPtrs& p, const Weights& wt, const double* mu,
                               double* part, hipStream_t s) {
   hipLaunchKernelGGL(k_grad_shrink_batch, dim3(bt.nc * LRSTV_PARTS), dim3(512), 0, s, bt, p, (float)wt.w[0],
-                     (float)wt.w[1], (float)wt.w[2], (float)wt.tau, (float)wt.lam, wt.iso, mu, part);
+                     (float)wt.w[1], (float)wt.w[2], (float)wt.tau, (float)wt.lam, wt.iso, wt.beta, mu, part);
 }
 
 }  // namespace lrstv

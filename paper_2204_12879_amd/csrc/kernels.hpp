@@ -11,6 +11,7 @@ struct Weights {
   double tau, alpha, lam;
   double w[3];
   int iso;   // 1: isotropic gradient term (group soft-threshold per voxel)
+  double beta;   // > 0: explicit noise term beta ||N||^2 (N read and updated)
 };
 
 
@@ -47,6 +48,7 @@ __host__ __device__ inline int fft_h_reg_bit(int h) { return h == 64 ? 1 : h == 
 struct BatchPtrs {
   const float* O;
   float *L, *Z, *S, *G1, *G2, *F, *E, *G3, *G4, *A, *T;
+  float* N;     // explicit noise term, or NULL when the model has none
   int64_t ts;
 };
 int phase_blocks(int phase, int h, int w, int b);

@@ -33,7 +33,7 @@ def run_argument_checks():
     assert need > 16 * 32 * 32 * 4 * 18
     # every parameter check
     for field, val in [("mu0", 0.0), ("rho", 0.5), ("tau", -1.0), ("alpha", float("nan")), ("lam", -2.0),
-                       ("mu_max", 1e-9), ("precision", 7), ("tv", 5)]:
+                       ("mu_max", 1e-9), ("precision", 7), ("tv", 5), ("beta", -1.0), ("beta", float("inf"))]:
         bad = L.Params()._c()
         setattr(bad, field, val)
         rc = lib.lrstv_workspace_size(c.byref(prob), c.byref(bad), c.byref(n))
