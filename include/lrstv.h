@@ -89,6 +89,14 @@ typedef struct lrstv_params {
   double beta;        /* >= 0; > 0 adds the explicit Gaussian term beta ||N||_F^2
                          with Y = X + S + N (N updated after S by its block
                          minimiser); 0: no N variable, N = Y - X - S          */
+  double tucker[3];   /* Tucker ranks of X as fractions of the cube's sides,
+                         modes 1 (height), 2 (width), 3 (bands): r_n =
+                         floor(f_n d_n + 1/2) clipped to [1, d_n]; f_n <= 0 or
+                         >= 1 keeps mode n at full rank.  Any truncated mode
+                         turns the L-update into the HOOI Tucker approximation
+                         (Sec. III-C, eq. X_solution); the paper's choice is
+                         r1 = 0.8 h, r2 = 0.8 w, r3 tuned                       */
+  int32_t hooi_sweeps;  /* HOOI sweeps after its truncated-HOSVD start (>= 0) */
 } lrstv_params;
 
 typedef struct lrstv_state_view {
@@ -342,8 +350,9 @@ int lrstv_get_tuning(lrstv_handle hd, lrstv_tuning* t);
  * Gram, tridiagonalisation, tridiagonal eigenvalues, tridiagonal
  * eigenvectors, back-transform,
  * back-projection B, shrink factors, back-projection Ehat, inverse band DFT
- * + Gamma4, residual reduction + mu step. */
-#define LRSTV_NSTAGES 17
+ * + Gamma4, residual reduction + mu step, and the HOOI Tucker approximation
+ * of the L-update (with truncated Tucker ranks only). */
+#define LRSTV_NSTAGES 18
 
 /* Start (enable = 1, discarding what was recorded) or stop (0) recording a
  * pair of hipEvents around every stage launched by lrstv_iterate / solve,

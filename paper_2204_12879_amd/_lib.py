@@ -18,7 +18,7 @@ LRSTV_VJP_INITIAL = 1
 LRSTV_MAX_TRI_SHAPES = 8
 RESIDUAL_NAMES = ("inf_OLS", "inf_LZ", "fro_OLS", "fro_LZ", "fro_DZF", "fro_EF", "dual_Z")
 WARN_NOT_CONVERGED = 1
-NSTAGES = 17
+NSTAGES = 18
 
 
 class LrstvError(RuntimeError):
@@ -35,7 +35,7 @@ class _Problem(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("tau", C.c_double), ("alpha", C.c_double), ("lam", C.c_double), ("w", C.c_double * 3),
                 ("mu0", C.c_double), ("rho", C.c_double), ("mu_max", C.c_double), ("precision", C.c_int32),
-                ("tv", C.c_int32), ("beta", C.c_double)]
+                ("tv", C.c_int32), ("beta", C.c_double), ("tucker", C.c_double * 3), ("hooi_sweeps", C.c_int32)]
 
 
 class _StateView(C.Structure):
@@ -147,10 +147,13 @@ class Params:
     precision: int = LRSTV_FP32
     tv: int = LRSTV_TV_ANISO     # LRSTV_TV_ISO: isotropic gradient term (group shrink per voxel)
     beta: float = 0.0            # > 0: explicit noise term beta ||N||^2 (Y = X + S + N)
+    tucker: Tuple[float, float, float] = (0.0, 0.0, 0.0)   # Tucker rank fractions; 0: full rank
+    hooi_sweeps: int = 1
 
     def _c(self) -> _Params:
         return _Params(self.tau, self.alpha, self.lam, (C.c_double * 3)(*self.w), self.mu0, self.rho,
-                       self.mu_max, self.precision, self.tv, self.beta)
+                       self.mu_max, self.precision, self.tv, self.beta, (C.c_double * 3)(*self.tucker),
+                       self.hooi_sweeps)
 
 
 def _problem(shapes: Sequence[Tuple[int, int, int]]):

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblrstv.so")
-SOURCES = ["api.hip", "k_sweep.hip", "k_fft.hip", "k_svt.hip", "k_vjp.hip"]
+SOURCES = ["api.hip", "k_sweep.hip", "k_fft.hip", "k_svt.hip", "k_vjp.hip", "k_tucker.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("LRSTV_ARCH", "gfx950")
 

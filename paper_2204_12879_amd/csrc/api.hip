@@ -103,6 +103,7 @@ SliceLayout make_slices(std::vector<CubeInfo>& cubes, int nt) {
         d.x_off = L.xs_d;
         d.f_off = L.f_floats;
         d.y_off = L.wy_floats;
+        d.keep = 0;
         L.gram_c += (int64_t)n1 * (n1 + 1) / 2;
         L.v_floats += 2 * (int64_t)n1 * n1;
         L.b_floats += 2 * hw;
@@ -153,6 +154,22 @@ struct lrstv_handle_s {
   hipGraphExec_t gexec = nullptr;
   // second stream of the slice SVT (the slices beyond the last full round)
   SvtSplit split;
+  // truncated-Tucker L-update (HOOI): eigen-slices [mode][cube], projectors,
+  // Gram partials and the launch tables
+  bool tk_on = false;
+  bool tk_mode[3] = {false, false, false};   // some cube truncates this mode
+  SliceLayout tsl;
+  SliceDesc* tdesc = nullptr;
+  float2* tgram = nullptr;
+  float *tV = nullptr, *tTwy = nullptr, *tP = nullptr, *tpart = nullptr;
+  double *ttri = nullptr, *txs = nullptr;
+  int* trcount = nullptr;
+  TkGeo* tgeo = nullptr;
+  int* tbstart = nullptr;
+  TkTab ttab;
+  std::vector<TkGeo> tgeo_h;
+  std::vector<int> tbstart_h;
+  int64_t tp_total = 0, tpart_total = 0;
   // Non-finite latch: k_finish_iter sets *flag; after every lrstv_iterate
   // the flag is copied to pinned host memory asynchronously and the copy
   // marked by flag_ev, so that a later call can see it without a sync.
@@ -188,6 +205,9 @@ static int check_params(const lrstv_params* p) {
   if (p->tv != LRSTV_TV_ANISO && p->tv != LRSTV_TV_ISO)
     return fail(LRSTV_ERR_INVALID_ARG, "unknown gradient term %d", p->tv);
   if (!(p->beta >= 0) || !isfinite(p->beta)) return fail(LRSTV_ERR_INVALID_ARG, "beta must be finite and >= 0");
+  for (int i = 0; i < 3; ++i)
+    if (!isfinite(p->tucker[i])) return fail(LRSTV_ERR_INVALID_ARG, "Tucker rank fractions must be finite");
+  if (p->hooi_sweeps < 0 || p->hooi_sweeps > 100) return fail(LRSTV_ERR_INVALID_ARG, "hooi_sweeps must be in [0, 100]");
   return LRSTV_OK;
 }
 
@@ -229,6 +249,98 @@ static int build_cubes(const lrstv_problem* prob, std::vector<CubeInfo>& cubes, 
   return LRSTV_OK;
 }
 
+// Tucker rank of one mode: floor(f d + 1/2) clipped to [1, d]; d when the
+// fraction asks for no truncation.
+static int tucker_rank(double f, int d) {
+  if (!(f > 0.0) || f >= 1.0) return d;
+  int r = (int)floor(f * d + 0.5);
+  return r < 1 ? 1 : (r > d ? d : r);
+}
+
+// The HOOI eigen-slices (one per cube and mode, laid out [mode][cube]; a
+// mode a cube keeps at full rank gets no Gram and an identity projector),
+// the per-cube launch tables and the projector / partial sizes.  Sets
+// H->tk_on when some cube truncates some mode.
+static void plan_tucker(lrstv_handle_s* H) {
+  const int nc = (int)H->cubes.size();
+  H->tk_on = false;
+  for (int m = 0; m < 3; ++m) H->tk_mode[m] = false;
+  H->tgeo_h.assign(nc, TkGeo());
+  H->tbstart_h.assign((size_t)TK_KINDS * (nc + 1), 0);
+  for (int c = 0; c < nc; ++c) {
+    const CubeInfo& ci = H->cubes[c];
+    const int d[3] = {ci.h, ci.w, ci.b};
+    for (int m = 0; m < 3; ++m)
+      if (tucker_rank(H->par.tucker[m], d[m]) < d[m]) H->tk_mode[m] = H->tk_on = true;
+  }
+  H->tsl = SliceLayout();
+  H->tp_total = H->tpart_total = 0;
+  if (!H->tk_on) return;
+  SliceLayout& L = H->tsl;
+  for (int m = 0; m < 3; ++m)
+    for (int c = 0; c < nc; ++c) {
+      const CubeInfo& ci = H->cubes[c];
+      const int d[3] = {ci.h, ci.w, ci.b};
+      const int n = d[m];
+      SliceDesc sd;
+      memset(&sd, 0, sizeof sd);
+      sd.h = sd.w = sd.n1 = sd.m1 = n;
+      sd.tall = 1;
+      sd.cube = c;
+      sd.fw = 1.f;
+      sd.g_off = L.gram_c;
+      sd.v_off = L.v_floats;
+      sd.t_off = L.tri_d;
+      sd.x_off = L.xs_d;
+      sd.y_off = L.wy_floats;
+      sd.keep = tucker_rank(H->par.tucker[m], n);
+      L.gram_c += (int64_t)n * (n + 1) / 2;
+      L.v_floats += 2 * (int64_t)n * n;
+      L.tri_d += 6 * (int64_t)n;
+      L.xs_d += 3 * (int64_t)n * n;
+      L.wy_floats += wy_block_floats(n);
+      L.desc.push_back(sd);
+      if (n > L.max_n1) L.max_n1 = n;
+      if (n > L.max_m1) L.max_m1 = n;
+    }
+  for (int c = 0; c < nc; ++c) {
+    const CubeInfo& ci = H->cubes[c];
+    TkGeo& g = H->tgeo_h[c];
+    g.h = ci.h;
+    g.w = ci.w;
+    g.b = ci.b;
+    g.off = ci.off;
+    const int d[3] = {ci.h, ci.w, ci.b};
+    const int64_t K[3] = {(int64_t)ci.b * ci.w, (int64_t)ci.b * ci.h, (int64_t)ci.h * ci.w};
+    int nb[TK_KINDS];
+    for (int m = 0; m < 3; ++m) {
+      const int T = (d[m] + 63) / 64, ntile = T * (T + 1) / 2;
+      const bool trunc = tucker_rank(H->par.tucker[m], d[m]) < d[m];
+      // about 512 blocks per mode Gram: groups of the contraction, 32-multiples
+      int G = (512 + ntile - 1) / ntile;
+      int64_t kg = (K[m] + G - 1) / G;
+      kg = (kg + 31) / 32 * 32;
+      G = (int)((K[m] + kg - 1) / kg);
+      g.groups[m] = G;
+      g.kg[m] = kg;
+      g.p_off[m] = H->tp_total;
+      H->tp_total += (int64_t)d[m] * d[m];
+      g.part_off[m] = H->tpart_total;
+      if (trunc) H->tpart_total += (int64_t)ntile * G * 64 * 64;
+      nb[TK_GRAM0 + m] = trunc ? ntile * G : 0;
+      nb[TK_RED0 + m] = trunc ? (int)(((int64_t)d[m] * (d[m] + 1) / 2 + 255) / 256) : 0;
+      nb[TK_PROJ0 + m] = trunc ? T * T : 0;
+    }
+    const int TH = (ci.h + 63) / 64, TW = (ci.w + 63) / 64, TB = (ci.b + 63) / 64;
+    const int TN = (int)(((int64_t)ci.h * ci.w + 63) / 64);
+    nb[TK_PROD0] = ci.b * TH * TW;
+    nb[TK_PROD1] = ci.b * TH * TW;
+    nb[TK_PROD2] = TB * TN;
+    for (int k = 0; k < TK_KINDS; ++k)
+      H->tbstart_h[(size_t)k * (nc + 1) + c + 1] = H->tbstart_h[(size_t)k * (nc + 1) + c] + nb[k];
+  }
+}
+
 static void carve_handle(lrstv_handle_s* H, void* base, size_t* used) {
   Carve cv(base);
   const int64_t T = H->total, nc = (int64_t)H->cubes.size();
@@ -262,6 +374,20 @@ static void carve_handle(lrstv_handle_s* H, void* base, size_t* used) {
   H->part = cv.take<double>(nc * R_COUNT * LRSTV_PARTS);
   H->res_last = cv.take<double>(nc * R_COUNT);
   H->flag = cv.take<int>(1);
+  if (H->tk_on) {
+    const SliceLayout& L = H->tsl;
+    H->tdesc = cv.take<SliceDesc>(L.desc.size());
+    H->tgram = cv.take<float2>(L.gram_c);
+    H->tV = cv.take<float>(L.v_floats);
+    H->ttri = cv.take<double>(L.tri_d);
+    H->txs = cv.take<double>(L.xs_d);
+    H->tTwy = cv.take<float>(L.wy_floats);
+    H->trcount = cv.take<int>(L.desc.size());
+    H->tP = cv.take<float>(H->tp_total);
+    H->tpart = cv.take<float>(H->tpart_total);
+    H->tgeo = cv.take<TkGeo>(nc);
+    H->tbstart = cv.take<int>((int64_t)TK_KINDS * (nc + 1));
+  }
   H->halt = cv.take<int>(nc);
   H->iters = cv.take<int>(nc);
   H->ran = cv.take<int>(1);
@@ -277,6 +403,8 @@ extern "C" int lrstv_workspace_size(const lrstv_problem* prob, const lrstv_param
   rc = build_cubes(prob, H.cubes, H.total, H.nmax, H.specmax, H.spec_total);
   if (rc) return rc;
   H.sl = make_slices(H.cubes, 3);
+  H.par = *par;
+  plan_tucker(&H);
   carve_handle(&H, nullptr, bytes);
   return LRSTV_OK;
 }
@@ -297,6 +425,7 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
   H->stream = (hipStream_t)stream;
   H->timer.s = H->stream;
   H->sl = make_slices(H->cubes, 3);
+  plan_tucker(H);
   size_t need = 0;
   carve_handle(H, nullptr, &need);
   if (ws_bytes < need) {
@@ -359,7 +488,39 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
     delete H;
     return fail(LRSTV_ERR_HIP, "copying the slice table: %s", hipGetErrorString(e));
   }
-  prepare_svt(H->sl.max_n1);
+  if (e == hipSuccess && H->tk_on) {
+    // HOOI tables, eigen-slice descriptors, zero Grams (modes kept at full
+    // rank are never written) and identity projectors (overwritten each
+    // iteration for the truncated modes)
+    e = hipMemcpyAsync(H->tdesc, H->tsl.desc.data(), H->tsl.desc.size() * sizeof(SliceDesc),
+                       hipMemcpyHostToDevice, H->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(H->tgeo, H->tgeo_h.data(), nc * sizeof(TkGeo), hipMemcpyHostToDevice, H->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(H->tbstart, H->tbstart_h.data(), H->tbstart_h.size() * sizeof(int), hipMemcpyHostToDevice,
+                         H->stream);
+    std::vector<float> eye((size_t)H->tp_total, 0.f);
+    for (int c = 0; c < nc; ++c) {
+      const CubeInfo& ci = H->cubes[c];
+      const int d[3] = {ci.h, ci.w, ci.b};
+      for (int m = 0; m < 3; ++m)
+        for (int i = 0; i < d[m]; ++i) eye[(size_t)H->tgeo_h[c].p_off[m] + (size_t)i * d[m] + i] = 1.f;
+    }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(H->tP, eye.data(), eye.size() * sizeof(float), hipMemcpyHostToDevice, H->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(H->stream);
+    launch_fill((float*)H->tgram, 2 * H->tsl.gram_c, 0.f, H->stream);
+    H->ttab.geo = H->tgeo;
+    H->ttab.bstart = H->tbstart;
+    H->ttab.nc = nc;
+    H->ttab.halt = H->halt;
+    for (int k = 0; k < TK_KINDS; ++k) H->ttab.nblocks[k] = H->tbstart_h[(size_t)k * (nc + 1) + nc];
+    if (e != hipSuccess) {
+      delete H;
+      return fail(LRSTV_ERR_HIP, "copying the Tucker tables: %s", hipGetErrorString(e));
+    }
+  }
+  prepare_svt(H->tk_on && H->tsl.max_n1 > H->sl.max_n1 ? H->tsl.max_n1 : H->sl.max_n1);
   prepare_fft_h(lds_h);
   H->split.first = svt_split_point((int)H->sl.desc.size());
   if (H->split.first > 0) {
@@ -460,6 +621,67 @@ static BatchPtrs batch_ptrs(lrstv_handle_s* H) {
   return p;
 }
 
+// The eigen-solves of the HOOI slices of `mode` (0, 1, 2), or of all three
+// modes (mode < 0).
+static void tucker_eig(lrstv_handle_s* H, int mode, hipStream_t s) {
+  const int nc = (int)H->cubes.size();
+  SvtLaunch L;
+  L.desc = H->tdesc + (mode < 0 ? 0 : mode * nc);
+  L.n_slices = mode < 0 ? 3 * nc : nc;
+  L.max_n1 = H->tsl.max_n1;
+  L.max_m1 = H->tsl.max_m1;
+  L.slices = nullptr;
+  L.gram = H->tgram;
+  L.V = H->tV;
+  L.B = nullptr;
+  L.tri = H->ttri;
+  L.xs = H->txs;
+  L.Twy = H->tTwy;
+  L.fval = nullptr;
+  L.rcount = H->trcount + (mode < 0 ? 0 : mode * nc);
+  L.mu = nullptr;
+  L.alpha = 0.0;
+  L.thresh = -1.f;
+  L.precision = LRSTV_FP32;
+  L.tri_variant = H->tri_variant;
+  L.halt = H->halt;
+  launch_sym_eig(L, s);
+}
+
+// HOOI of the average the L-update wrote into L (Sec. III-C, eq.
+// X_solution): truncated-HOSVD start, H->par.hooi_sweeps sweeps over the
+// truncated modes, then L = X x_1 P_1 x_2 P_2 x_3 P_3, the last product
+// also moving T_z by mu (L - X).  The t-SVT input buffer A (free until the
+// F-update) holds the two intermediate tensors.
+static void run_hooi(lrstv_handle_s* H, hipStream_t s) {
+  const TkTab& tab = H->ttab;
+  float* X = H->L;
+  float* t0 = H->A;
+  float* t1 = H->A + H->total;
+  for (int m = 0; m < 3; ++m) {
+    if (!H->tk_mode[m]) continue;
+    launch_tk_gram(tab, m, X, H->tpart, s);
+    launch_tk_reduce(tab, m, H->tpart, H->tgram, H->tdesc, s);
+  }
+  tucker_eig(H, -1, s);
+  for (int m = 0; m < 3; ++m)
+    if (H->tk_mode[m]) launch_tk_proj(tab, m, H->tdesc, H->tV, H->trcount, H->tP, s);
+  for (int sw = 0; sw < H->par.hooi_sweeps; ++sw)
+    for (int m = 0; m < 3; ++m) {
+      if (!H->tk_mode[m]) continue;
+      const int a = m == 0 ? 1 : 0, b = m == 2 ? 1 : 2;   // the other two modes, in order
+      launch_tk_prod(tab, a, X, H->tP, t0, nullptr, nullptr, nullptr, false, s);
+      launch_tk_prod(tab, b, t0, H->tP, t1, nullptr, nullptr, nullptr, false, s);
+      launch_tk_gram(tab, m, t1, H->tpart, s);
+      launch_tk_reduce(tab, m, H->tpart, H->tgram, H->tdesc, s);
+      tucker_eig(H, m, s);
+      launch_tk_proj(tab, m, H->tdesc, H->tV, H->trcount, H->tP, s);
+    }
+  launch_tk_prod(tab, 0, X, H->tP, t0, nullptr, nullptr, nullptr, false, s);
+  launch_tk_prod(tab, 1, t0, H->tP, t1, nullptr, nullptr, nullptr, false, s);
+  launch_tk_prod(tab, 2, t1, H->tP, nullptr, H->L, H->T, H->mu, true, s);
+}
+
 // One iteration over the whole batch: every stencil, FFT and band-transform
 // phase is one launch over all cubes (per-cube block ranges), the slice SVT
 // one launch per kernel over all slices.
@@ -478,6 +700,11 @@ static void run_iteration(lrstv_handle_s* H, double* res_user) {
   tm.begin(ST_LRHS);
   launch_lrhs_batch(H->bt[PH_LRHS], bp, wt, H->mu, s);                  // 1st step + T_z
   tm.end(ST_LRHS);
+  if (H->tk_on) {                                                       // truncated Tucker ranks
+    tm.begin(ST_HOOI);
+    run_hooi(H, s);
+    tm.end(ST_HOOI);
+  }
   tm.begin(ST_RFFT_W);
   launch_rfft_w_batch(H->bt[PH_RFFT_W], H->T, H->spec, s);              // 2nd step: Z solve
   tm.end(ST_RFFT_W);
@@ -808,8 +1035,9 @@ extern "C" int lrstv_iterate_vjp(lrstv_handle H, const lrstv_state_view* before,
                                  lrstv_state_view* grad_before, double* grad_weights, float* grad_Y,
                                  int32_t flags, void* ws, size_t ws_bytes) {
   if (!H) return fail(LRSTV_ERR_INVALID_ARG, "handle is NULL");
-  if (H->par.tv != LRSTV_TV_ANISO || H->par.beta > 0)
-    return fail(LRSTV_ERR_UNSUPPORTED, "the adjoint covers the anisotropic model without the noise term only");
+  if (H->par.tv != LRSTV_TV_ANISO || H->par.beta > 0 || H->tk_on)
+    return fail(LRSTV_ERR_UNSUPPORTED,
+                "the adjoint covers the anisotropic full-rank model without the noise term only");
   if (!before || !before->G4 || !before->mu) return fail(LRSTV_ERR_INVALID_ARG, "before needs G4 and mu");
   if (!after || !after->S || !after->F) return fail(LRSTV_ERR_INVALID_ARG, "after needs S and F");
   if (grad_after && !full_view(grad_after))
@@ -1004,6 +1232,7 @@ __global__ void k_make_desc(SliceDesc* out, int n, int b, int h, int w, int s,
   d.x_off = (int64_t)i * xs_d;
   d.f_off = (int64_t)i * f_f;
   d.y_off = (int64_t)i * y_f;
+  d.keep = 0;
   out[i] = d;
 }
 
@@ -1355,7 +1584,7 @@ extern "C" int lrstv_get_tuning(lrstv_handle H, lrstv_tuning* t) {
 // --------------------------------------------------------- diagnostics ---
 static const char* kStageNames[ST_COUNT] = {"lrhs", "rfft_w", "fft_h", "tri_b", "irfft_w", "grad_shrink",
                                             "band_dft", "gram", "tridiag", "trieig", "trivec", "backtrans", "bp1",
-                                            "colnorm", "bp2", "band_idft", "finish"};
+                                            "colnorm", "bp2", "band_idft", "finish", "hooi"};
 
 extern "C" int lrstv_profile(lrstv_handle H, int32_t enable) {
   if (!H) return fail(LRSTV_ERR_INVALID_ARG, "handle is NULL");

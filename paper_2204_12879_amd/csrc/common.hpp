@@ -159,6 +159,8 @@ struct SliceDesc {
   int64_t f_off;     // float offset of the n1 shrink factors
   int64_t y_off;     // float offset of the block-reflector T factors
                      // (ceil((n1-1)/64) blocks of 64 x 64 complex, planar)
+  int keep;          // > 0: keep the `keep` largest eigenpairs of the matrix
+                     // (Tucker projectors) instead of those above the threshold
 };
 
 }  // namespace lrstv

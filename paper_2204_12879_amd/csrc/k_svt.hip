@@ -1347,7 +1347,7 @@ __global__ void __launch_bounds__(PHASE == 1 ? 64 : (PHASE == 0 ? 256 : 1024)) k
   const double delta = 1e-6 * tnorm;                    // FP32 resolution of the Gram
   // thresh < 0 without a device mu asks for every eigenpair (the t-SVT
   // derivative needs the full spectrum)
-  const bool all = mu_dev == nullptr && thresh < 0.f;
+  const bool all = (mu_dev == nullptr && thresh < 0.f) || d.keep > 0;
   const double lo_cut = all ? gl - 1.0 : fmax(t * t * sc - delta, 0.0);
   dg = ds;
   // unreduced blocks (starts after each zero off-diagonal) by a ballot scan
@@ -1370,7 +1370,8 @@ __global__ void __launch_bounds__(PHASE == 1 ? 64 : (PHASE == 0 ? 256 : 1024)) k
       // phase, which publishes r = n - c0 in rcount (the kernels after the
       // eigen-solve read the rank there); the later phases take it back
       if (PHASE == 0) {
-        const int c0v = all ? 0 : (tnorm == 0.0) ? n : sturm_count_fast(dg, e2, n, lo_cut, pivmin);
+        const int c0v = d.keep > 0 ? n - (d.keep < n ? d.keep : n)
+                      : all ? 0 : (tnorm == 0.0) ? n : sturm_count_fast(dg, e2, n, lo_cut, pivmin);
         s_c0 = c0v;
         if (blockIdx.x == 0) rcount[slice] = n - c0v;
       } else {
@@ -2474,6 +2475,18 @@ void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm, const SvtSpli
   svt_after_tridiag(L, s, T);
 }
 
+
+void launch_sym_eig(const SvtLaunch& L, hipStream_t s) {
+  const int ns = L.n_slices, n = L.max_n1;
+  if (ns == 0) return;
+  launch_tridiag(L, s);
+  const size_t eig_lds = (size_t)5 * n * sizeof(double) + (size_t)(n + 1 + 1024) * sizeof(int);
+  const int probes = eig_probes(ns, n), epb = 256 / probes;
+  hipLaunchKernelGGL(k_trieig<0>, dim3((n + epb - 1) / epb, ns), dim3(256), eig_lds, s, L.desc, L.tri, L.xs, L.V,
+                     L.rcount, (const double*)nullptr, 0.0, -1.f, probes, L.halt);
+  launch_trivec(L, s, eig_lds, nullptr, -1.f);
+  launch_backtrans(L, s);
+}
 
 void launch_svt_vjp(const SvtVjpLaunch& J, hipStream_t s) {
   const SvtLaunch& L = J.fw;

@@ -202,6 +202,38 @@ struct SvtVjpLaunch {
 };
 void launch_svt_vjp(const SvtVjpLaunch& J, hipStream_t s);
 
+// --- truncated-Tucker L-update (k_tucker.hip) -----------------------------
+// Launch kinds of the HOOI phases; block ranges per cube in TkTab.bstart.
+enum TkKind { TK_GRAM0 = 0, TK_GRAM1, TK_GRAM2, TK_RED0, TK_RED1, TK_RED2, TK_PROJ0, TK_PROJ1, TK_PROJ2,
+              TK_PROD0, TK_PROD1, TK_PROD2, TK_KINDS };
+struct TkGeo {
+  int h, w, b;
+  int groups[3];          // contraction groups of the mode Grams
+  int64_t kg[3];          // contraction length per group (multiple of 32)
+  int64_t off;            // element offset of the cube in the packed batch
+  int64_t p_off[3];       // float offsets of the mode projectors (d x d)
+  int64_t part_off[3];    // float offsets of the Gram partials [tile][group][64][64]
+};
+struct TkTab {
+  const TkGeo* geo;       // device [nc]
+  const int* bstart;      // device [TK_KINDS][nc + 1]
+  int nc;
+  int nblocks[TK_KINDS];
+  const int* halt;        // device [nc] or NULL: halted cubes are skipped
+  __host__ __device__ int kind_off(int k) const { return k * (nc + 1); }
+};
+void launch_tk_gram(const TkTab& tab, int M, const float* X, float* part, hipStream_t s);
+void launch_tk_reduce(const TkTab& tab, int M, const float* part, float2* gram, const SliceDesc* hdesc,
+                      hipStream_t s);
+void launch_tk_proj(const TkTab& tab, int M, const SliceDesc* hdesc, const float* V, const int* rcount, float* P,
+                    hipStream_t s);
+void launch_tk_prod(const TkTab& tab, int M, const float* X, const float* P, float* Y, float* L, float* T,
+                    const double* mu, bool fin, hipStream_t s);
+// Leading eigenpairs of the slices' packed Hermitian matrices: the SVT's
+// tridiagonalisation, eigenvalue, eigenvector and back-transform stages with
+// every slice keeping its SliceDesc::keep largest eigenpairs (V columns).
+void launch_sym_eig(const SvtLaunch& L, hipStream_t s);
+
 // --- adjoint of one iteration (k_vjp.hip) ---------------------------------
 void launch_vjp_post(const VjpCube& c, const double* mu, double* part_lam, hipStream_t s);
 void launch_vjp_shrinkf(const VjpCube& c, const float* gA, const double* mu, double* part_tau, hipStream_t s);

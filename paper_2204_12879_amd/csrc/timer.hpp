@@ -10,7 +10,7 @@ namespace lrstv {
 
 enum Stage {
   ST_LRHS = 0, ST_RFFT_W, ST_FFT_H, ST_TRI_B, ST_IRFFT_W, ST_GRAD_SHRINK, ST_BAND_DFT, ST_GRAM, ST_TRIDIAG,
-  ST_TRIEIG, ST_TRIVEC, ST_BACKTRANS, ST_BP1, ST_COLNORM, ST_BP2, ST_BAND_IDFT, ST_FINISH, ST_COUNT
+  ST_TRIEIG, ST_TRIVEC, ST_BACKTRANS, ST_BP1, ST_COLNORM, ST_BP2, ST_BAND_IDFT, ST_FINISH, ST_HOOI, ST_COUNT
 };
 
 struct StageTimer {
