@@ -74,8 +74,9 @@ __global__ void __launch_bounds__(256) k_gram(const SliceDesc* __restrict__ desc
   const int wv = threadIdx.x >> 6, r0 = m0 + 32 * (wv >> 1), c0 = n0 + 32 * (wv & 1);
   const bool active = r0 < n && c0 < n && r0 + 31 >= c0;
   float2* g = gram + d.g_off;
+  // the diagonal of a Gram is real (its computed imaginary part is rounding)
   auto st = [&](int r, int c, float2 v) {
-    if (r < n && c <= r) g[packed(r, c)] = v;
+    if (r < n && c <= r) g[packed(r, c)] = r == c ? make_float2(v.x, 0.f) : v;
   };
   if (d.tall) {  // contraction over the h rows
     if constexpr (MODE == kF32) {
@@ -831,7 +832,7 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __res
   for (int q = 0; q < NW; ++q) fro2 += red_fro[q];
   const int ex = fro2 > 0.0 ? ilogb(sqrt(fro2)) : 0;
   const float gsc = ldexpf(1.0f, -ex);
-  const double unsc = ldexp(1.0, ex);
+  const double unsc = uniform_d(ldexp(1.0, ex));
 #pragma unroll
   for (int s = 0; s < TPW; ++s)
 #pragma unroll
@@ -839,7 +840,7 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __res
       tre[s][r] *= gsc;
       tim[s][r] *= gsc;
     }
-  double ph_r = 1.0, ph_i = 0.0;   // running phase (thread 0)
+  double ph_r = 1.0, ph_i = 0.0;   // running phase (uniform in the waves of D)
   if (threadIdx.x == 0) { phr[0] = 1.0; phi[0] = 0.0; }
   // columns 0 and 1; ||x||^2 and x^H a of step 0; its reflector
   {
@@ -868,13 +869,6 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __res
     }
   }
   __syncthreads();
-  MtRefl f;
-  {
-    double nx2 = 0.0;
-#pragma unroll
-    for (int q = 0; q < NDW; ++q) nx2 += red_nx[0][q];
-    f = mt_reflector(uniform_d(nx2), make_float2(uniform_f(xb[0][1].x), uniform_f(xb[0][1].y)));
-  }
   for (int i = 0; i < n - 1; ++i) {
     const int par = i & 1;
     const float2* xv = xb[par];
@@ -882,9 +876,19 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __res
     // lane-derived indices are recomputed every step from this copy rather
     // than kept live across the loop next to the tiles
     const int lane = opaque_i(threadIdx.x & 63), li = lane & 31, h = lane >> 5;
-    const float tau = f.tau;
+    // ---- the reflector of step i, in the waves of D only (they have the
+    // fewest tiles, and compute it ahead of their share of C).  The other
+    // waves never need it: without a reflection D writes v = w = 0, so
+    // that C's products are discarded and E adds zeros.
+    MtRefl f{};
+    if (wv < NDW) {
+      double nx2 = 0.0;
+#pragma unroll
+      for (int q = 0; q < NDW; ++q) nx2 += red_nx[par][q];
+      f = mt_reflector(uniform_d(nx2), make_float2(uniform_f(xv[i + 1].x), uniform_f(xv[i + 1].y)));
+    }
     // ---- C: A x per wave, x^H A x ----------------------------------------
-    if (f.refl) {
+    {
       for (int t = lane; t < NMAX; t += 64) P[wv][t] = zero;
       float xaxd = 0.f, xaxo = 0.f;   // diagonal-tile and off-diagonal-tile parts
 #pragma unroll
@@ -976,7 +980,7 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __res
       const double sr = f.scl.x, si = f.scl.y;
       const double gd = f.gam, td = f.tau;
       const double vAv = (sr * sr + si * si) * xAx + 2.0 * gd * (sr * xar + si * xai) + gd * gd * (double)a1.x;
-      const float K = (float)(0.5 * td * td * vAv), g = f.gam;
+      const float K = (float)(0.5 * td * td * vAv), g = f.gam, tau = f.tau;
       // w_u = tau (scl S_u + gamma a_u) - K v_u
       auto w_of = [&](float2 S, float2 au, float2 vu) {
         const float2 pu = cadd(cmul(f.scl, S), make_float2(g * au.x, g * au.y));
@@ -1014,12 +1018,27 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __res
         red_xa[par ^ 1][wv][0] = xr;
         red_xa[par ^ 1][wv][1] = xi;
       }
+      // outputs of step i; beta = -phase ||x|| (reflection), x_0 (column
+      // already reduced) or 0 (deflated); the running phase is uniform
+      if (!f.defl) {
+        const double ur = f.refl ? -f.pr : f.pr, uq = f.refl ? -f.pim : f.pim;
+        const double nr = ph_r * ur - ph_i * uq, ni = ph_r * uq + ph_i * ur;
+        ph_r = uniform_d(nr);
+        ph_i = uniform_d(ni);
+      }
+      if (t == 0) {
+        dg[i] = s_dii[par] * unsc;
+        taus[i] = f.tau;
+        eab[i] = (double)(f.refl ? f.nx : f.defl ? 0.f : f.ax0) * unsc;
+        phr[i + 1] = ph_r;
+        phi[i + 1] = ph_i;
+      }
     }
     lds_barrier();
     // ---- E: A -= v w^H + w v^H on the matrix cores ------------------------
     // real part: [-v_R | -w_R] (re in half 0, im in half 1) times [w_C ; v_C];
     // imaginary part: [-Im v, Re v] and [-Im w, Re w] against the same B.
-    if (f.refl) {
+    {
       // every tile's v and w entries are read before the first product, so
       // that one LDS latency covers them all
       float2 vRs[TPW], wRs[TPW], vCs[TPW], wCs[TPW];
@@ -1044,28 +1063,6 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __res
         tim[s] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai0, b0, tim[s], 0, 0, 0);
         tim[s] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai1, b1, tim[s], 0, 0, 0);
       }
-    }
-    // outputs of step i; beta = -phase ||x|| (reflection), x_0 (column already
-    // reduced) or 0 (deflated)
-    if (threadIdx.x == 0) {
-      dg[i] = s_dii[par] * unsc;
-      taus[i] = f.tau;
-      eab[i] = (double)(f.refl ? f.nx : f.defl ? 0.f : f.ax0) * unsc;
-      if (!f.defl) {
-        const double ur = f.refl ? -f.pr : f.pr, uq = f.refl ? -f.pim : f.pim;
-        const double nr = ph_r * ur - ph_i * uq, ni = ph_r * uq + ph_i * ur;
-        ph_r = nr;
-        ph_i = ni;
-      }
-      phr[i + 1] = ph_r;
-      phi[i + 1] = ph_i;
-    }
-    // the next reflector, while the update runs
-    if (i + 2 < n) {
-      double nx2 = 0.0;
-#pragma unroll
-      for (int q = 0; q < NDW; ++q) nx2 += red_nx[par ^ 1][q];
-      f = mt_reflector(uniform_d(nx2), make_float2(uniform_f(xb[par ^ 1][i + 2].x), uniform_f(xb[par ^ 1][i + 2].y)));
     }
   }
   if (threadIdx.x == 0) {
@@ -1741,7 +1738,7 @@ struct WySmem {
   };
 };
 
-__global__ void __launch_bounds__(256, 4) k_wy_apply(const SliceDesc* __restrict__ desc, const float2* __restrict__ gram,
+__global__ void __launch_bounds__(256, 3) k_wy_apply(const SliceDesc* __restrict__ desc, const float2* __restrict__ gram,
                                                      const float* __restrict__ Twy, float* __restrict__ V,
                                                      const int* __restrict__ rcount, int ntile, int ns, const int* __restrict__ halt) {
   __shared__ WySmem sm;
@@ -1764,9 +1761,11 @@ __global__ void __launch_bounds__(256, 4) k_wy_apply(const SliceDesc* __restrict
     // ---- W = Y^H V[i0+1:, cols]: chunks of 32 rows, staged with the next
     // chunk's loads in flight.  Staged element e = t + 256 j: row e / 64,
     // column e % 64 (coalesced along the row).
-    f32x4 wr[4], wi[4];
+    // three real products per complex one (3M): with A = conj(Y), P1 = Yr Vr,
+    // P2 = Yi Vi, P3 = (Yr - Yi)(Vr + Vi); Re W = P1 + P2, Im W = P3 - P1 + P2
+    f32x4 w1[4], w2[4], w3[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) wr[q] = wi[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < 4; ++q) w1[q] = w2[q] = w3[q] = f32x4{0.f, 0.f, 0.f, 0.f};
     float2 ys[8], vs[8];
     auto load1 = [&](int k0) {
 #pragma unroll
@@ -1796,22 +1795,27 @@ __global__ void __launch_bounds__(256, 4) k_wy_apply(const SliceDesc* __restrict
 #pragma unroll 1
         for (int s = 0; s < 8; ++s) {
           const int kk = 4 * s + lg;
-          const float br = sm.a.vr[kk][ccol], bi = sm.a.vi[kk][ccol];
+          const float br = sm.a.vr[kk][ccol], bi = sm.a.vi[kk][ccol], bs = br + bi;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            // conj(Y) V: re += Yr Vr + Yi Vi, im += Yr Vi - Yi Vr
             const float ar = sm.a.yr[kk][16 * q + li], ai = sm.a.yi[kk][16 * q + li];
-            wr[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, wr[q], 0, 0, 0);
-            wi[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, wi[q], 0, 0, 0);
-            wr[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bi, wr[q], 0, 0, 0);
-            wi[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, br, wi[q], 0, 0, 0);
+            w1[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, w1[q], 0, 0, 0);
+            w2[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bi, w2[q], 0, 0, 0);
+            w3[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar - ai, bs, w3[q], 0, 0, 0);
           }
         }
       }
       __syncthreads();
     }
+    f32x4 wr[4], wi[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      wr[q] = w1[q] + w2[q];
+      wi[q] = w3[q] - w1[q] + w2[q];
+    }
     // ---- W' = T W (T upper triangular: row tile p of W' takes row tiles
-    // q >= p of W).  T is stored transposed, T(p, q) at [q][p].
+    // q >= p of W).  T is stored transposed, T(p, q) at [q][p].  3M again:
+    // P1 = Tr Wr, P2 = Ti Wi, P3 = (Tr + Ti)(Wr + Wi).
     {
       const float* Tt = Twy + d.y_off + (int64_t)b * 64 * 64 * 2;
 #pragma unroll 4
@@ -1822,30 +1826,36 @@ __global__ void __launch_bounds__(256, 4) k_wy_apply(const SliceDesc* __restrict
       }
     }
     __syncthreads();
-    f32x4 xr[4], xi[4];
+    f32x4 x1[4], x2[4], x3[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) xr[q] = xi[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < 4; ++q) x1[q] = x2[q] = x3[q] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (act) {
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
           const int row = 16 * q + 4 * lg + rr;
-          const float br = wr[q][rr], bi = wi[q][rr];
+          const float br = wr[q][rr], bi = wi[q][rr], bs = br + bi;
 #pragma unroll
           for (int p = 0; p <= q; ++p) {
             const float ar = sm.t.tr[row][16 * p + li], ai = sm.t.ti[row][16 * p + li];
-            xr[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, xr[p], 0, 0, 0);
-            xi[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, xi[p], 0, 0, 0);
-            xr[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, xr[p], 0, 0, 0);
-            xi[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, xi[p], 0, 0, 0);
+            x1[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, x1[p], 0, 0, 0);
+            x2[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bi, x2[p], 0, 0, 0);
+            x3[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar + ai, bs, x3[p], 0, 0, 0);
           }
           // keep the operand reads of one row step together (register budget)
           __builtin_amdgcn_sched_barrier(0);
         }
     }
+    f32x4 xr[4], xi[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      xr[q] = x1[q] - x2[q];
+      xi[q] = x3[q] - x1[q] - x2[q];
+    }
     __syncthreads();
-    // ---- V[i0+1:, cols] -= Y W': chunks of 64 rows.
+    // ---- V[i0+1:, cols] -= Y W': chunks of 64 rows; 3M with P1 = Yr W'r,
+    // P2 = Yi W'i, P3 = (Yr + Yi)(W'r + W'i).
     for (int k0 = 0; k0 < m; k0 += 64) {
 #pragma unroll 4
       for (int j = 0; j < 16; ++j) {
@@ -1856,22 +1866,21 @@ __global__ void __launch_bounds__(256, 4) k_wy_apply(const SliceDesc* __restrict
       }
       __syncthreads();
       if (act) {
-        f32x4 ur[4], ui[4];
+        f32x4 u1[4], u2[4], u3[4];
 #pragma unroll
-        for (int kt = 0; kt < 4; ++kt) ur[kt] = ui[kt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int kt = 0; kt < 4; ++kt) u1[kt] = u2[kt] = u3[kt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
           for (int rr = 0; rr < 4; ++rr) {
             const int p = 16 * q + 4 * lg + rr;
-            const float br = xr[q][rr], bi = xi[q][rr];
+            const float br = xr[q][rr], bi = xi[q][rr], bs = br + bi;
 #pragma unroll
             for (int kt = 0; kt < 4; ++kt) {
               const float ar = sm.y.yr[p][16 * kt + li], ai = sm.y.yi[p][16 * kt + li];
-              ur[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, ur[kt], 0, 0, 0);
-              ui[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, ui[kt], 0, 0, 0);
-              ur[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, ur[kt], 0, 0, 0);
-              ui[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, ui[kt], 0, 0, 0);
+              u1[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, u1[kt], 0, 0, 0);
+              u2[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bi, u2[kt], 0, 0, 0);
+              u3[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar + ai, bs, u3[kt], 0, 0, 0);
             }
             __builtin_amdgcn_sched_barrier(0);
           }
@@ -1883,8 +1892,8 @@ __global__ void __launch_bounds__(256, 4) k_wy_apply(const SliceDesc* __restrict
               const int k = k0 + 16 * kt + 4 * lg + rr;
               if (k < m) {
                 const int64_t q = (int64_t)(i0 + 1 + k) * n + c0 + ccol;
-                Vr[q] -= ur[kt][rr];
-                Vi[q] -= ui[kt][rr];
+                Vr[q] -= u1[kt][rr] - u2[kt][rr];
+                Vi[q] -= u3[kt][rr] - u1[kt][rr] - u2[kt][rr];
               }
             }
         }
@@ -2012,7 +2021,7 @@ __global__ void __launch_bounds__(256) k_colnorm(const SliceDesc* __restrict__ d
 
 // tall: Ehat (h x w) = B diag(f) V_r^H;  wide: Ehat = U_r diag(f) B.  Written over M.
 template <int MODE>
-__global__ void __launch_bounds__(256) k_bp2(const SliceDesc* __restrict__ desc, float* __restrict__ sl,
+__global__ void __launch_bounds__(256, MODE == kF32 ? 4 : 1) k_bp2(const SliceDesc* __restrict__ desc, float* __restrict__ sl,
                                              const float* __restrict__ V, const float* __restrict__ Bb,
                                              const float* __restrict__ fval, const int* __restrict__ rcount, int tdim,
                                              int ns, const int* __restrict__ halt) {

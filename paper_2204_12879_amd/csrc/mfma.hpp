@@ -5,15 +5,22 @@
 // (32 (q >> 1), 32 (q & 1)).  Operands are fetched through accessors
 // fa(m, k), fb(k, n) that return float2 (zero outside the matrix), staged
 // through LDS in chunks of 32 along k with a register prefetch of the next
-// chunk, and multiplied as four real products
-//   Re C += Re A Re B - Im A Im B,   Im C += Re A Im B + Im A Re B.
+// chunk.
 //
 // Two arithmetic modes:
-//   kF32   v_mfma_f32_32x32x2f32: FP32 operands, FP32 accumulation.
+//   kF32   v_mfma_f32_32x32x2f32: FP32 operands, FP32 accumulation, three
+//          real products per complex one (the 3M method: P1 = Re A Re B,
+//          P2 = Im A Im B, P3 = (Re A + Im A)(Re B + Im B); Re C = P1 - P2,
+//          Im C = P3 - P1 - P2), the sums formed as the operands are read.
+//          On CDNA4 the FP32 matrix instructions run at the packed-FP32
+//          vector rate and occupy the same pipeline, so a product saved is
+//          time saved.
 //   kBF16x3 split-BF16: every FP32 operand x is stored as hi = bf16(x),
 //          lo = bf16(x - hi); a real product is hi*hi + hi*lo + lo*hi
 //          (the lo*lo term, ~2^-16 relative, is dropped), each term a
-//          v_mfma_f32_32x32x16_bf16 with FP32 accumulation.
+//          v_mfma_f32_32x32x16_bf16 with FP32 accumulation, four real
+//          products per complex one
+//            Re C += Re A Re B - Im A Im B,   Im C += Re A Im B + Im A Re B.
 //
 // Lane layouts (checked on gfx950): for both instructions lane l holds
 // A(l % 32, k) and B(k, l % 32) with k = l / 32 (f32, K = 2) or
@@ -50,9 +57,16 @@ union MfmaSmem {
   MfmaSmemBF h;
 };
 
+// kF32: re, im, p3 accumulate P1, P2, P3 of the 3M method (combined by
+// cacc_result); kBF16x3: re and im are the result and p3 is unused.
 struct CAcc {
-  f32x16 re, im;
+  f32x16 re, im, p3;
 };
+template <int MODE, bool M3>
+LRSTV_DEV float2 cacc_result(const CAcc& c, int r) {
+  if (MODE == kF32 && M3) return make_float2(c.re[r] - c.im[r], c.p3[r] - c.re[r] - c.im[r]);
+  return make_float2(c.re[r], c.im[r]);
+}
 
 LRSTV_DEV bf16x8 bf_neg(bf16x8 x) {
   union {
@@ -107,7 +121,7 @@ LRSTV_DEV void stage_store(MfmaSmem& sm, bool isA, int row, int k0, const float2
   }
 }
 
-template <int MODE>
+template <int MODE, bool M3>
 LRSTV_DEV void chunk_mma(const MfmaSmem& sm, int wy, int wx, int lane, bool active, CAcc& c) {
   if (!active) return;
   const int li = lane & 31, lk = lane >> 5;
@@ -117,10 +131,16 @@ LRSTV_DEV void chunk_mma(const MfmaSmem& sm, int wy, int wx, int lane, bool acti
       const int k = 2 * kk + lk;
       const float ar = sm.f.ar[k][32 * wy + li], ai = sm.f.ai[k][32 * wy + li];
       const float br = sm.f.br[k][32 * wx + li], bi = sm.f.bi[k][32 * wx + li];
-      c.re = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, c.re, 0, 0, 0);
-      c.re = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bi, c.re, 0, 0, 0);
-      c.im = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, c.im, 0, 0, 0);
-      c.im = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, c.im, 0, 0, 0);
+      if (M3) {
+        c.re = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, c.re, 0, 0, 0);
+        c.im = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bi, c.im, 0, 0, 0);
+        c.p3 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar + ai, br + bi, c.p3, 0, 0, 0);
+      } else {
+        c.re = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, c.re, 0, 0, 0);
+        c.re = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bi, c.re, 0, 0, 0);
+        c.im = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, c.im, 0, 0, 0);
+        c.im = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, c.im, 0, 0, 0);
+      }
     }
   } else {
 #pragma unroll
@@ -186,7 +206,7 @@ LRSTV_DEV void load4(const float* p, int nvalid, float (&v)[4]) {
 // products of a wave whose sub-tile is not needed; every wave still takes
 // part in staging.  The result is handed to st(row, col, float2) for rows and
 // columns of the wave's sub-tile.
-template <int MODE, bool AK, bool BK, bool VA = false, bool VB = false, class FA, class FB, class ST>
+template <int MODE, bool AK, bool BK, bool VA = false, bool VB = false, bool M3 = true, class FA, class FB, class ST>
 LRSTV_DEV void mfma_ctile(int m0, int n0, int K, FA fa, FB fb, ST st, MfmaSmem& sm, bool active) {
   constexpr bool A4 = VA && !AK, B4 = VB && !BK;   // four-wide along the row / column index
   static_assert(MODE == kF32 || !(A4 || B4), "four-wide staging is for the FP32 layout");
@@ -204,7 +224,7 @@ LRSTV_DEV void mfma_ctile(int m0, int n0, int K, FA fa, FB fb, ST st, MfmaSmem& 
   }
   CAcc c;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) c.re[i] = c.im[i] = 0.f;
+  for (int i = 0; i < 16; ++i) c.re[i] = c.im[i] = c.p3[i] = 0.f;
   float2 va[8], vb[8];
   auto fetch = [&](int kc) {
     if constexpr (A4) {
@@ -244,7 +264,7 @@ LRSTV_DEV void mfma_ctile(int m0, int n0, int K, FA fa, FB fb, ST st, MfmaSmem& 
     else stage_store<MODE>(sm, false, rb, kb, vb);
     __syncthreads();
     if (k0 + kKC < K) fetch(k0 + kKC);
-    chunk_mma<MODE>(sm, wy, wx, lane, active, c);
+    chunk_mma<MODE, M3>(sm, wy, wx, lane, active, c);
     __syncthreads();
   }
   if (!active) return;
@@ -252,7 +272,7 @@ LRSTV_DEV void mfma_ctile(int m0, int n0, int K, FA fa, FB fb, ST st, MfmaSmem& 
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int row = m0 + 32 * wy + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-    st(row, col, make_float2(c.re[r], c.im[r]));
+    st(row, col, cacc_result<MODE, M3>(c, r));
   }
 }
 
