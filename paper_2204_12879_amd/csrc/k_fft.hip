@@ -738,189 +738,276 @@ __global__ void __launch_bounds__(kTriCols * kTriChunks, MAXL <= 16 ? 4 : 2) k_t
 }
 
 // ---------------------------------------------------------------------------
-// Band DFT of real tensors as a real matrix product on the matrix cores:
-//   X (2s x hw) = F (2s x b) A (b x hw),  s = b/2 + 1,
-//   F[2k][j] = cos(2 pi j k / b),  F[2k+1][j] = -sin(2 pi j k / b),
-// so row 2k / 2k+1 of X is the re / im plane of Fourier slice k: the planar
-// slice layout [t][k][re|im][hw] is X itself.
+// Band DFT of real tensors along the bands, on the matrix cores.  With
+// s = b/2 + 1 slices and the even / odd parts of A along the bands,
+//   P_0 = A_0,  P_j = A_j + A_{b-j},  Q_0 = 0,  Q_j = A_j - A_{b-j}   (0 < j < s)
+// (for even b, P_{b/2} = A_{b/2} and Q_{b/2} = 0: that row pairs with itself),
+//   Re X_k =  sum_{j < s} P_j cos(2 pi j k / b),
+//   Im X_k = -sum_{j < s} Q_j sin(2 pi j k / b),
+// two real products of s x s terms, half the work of the full (2s x b)
+// product.  Row 2k / 2k+1 of the output is the re / im plane of slice k: the
+// planar slice layout [t][k][re|im][hw].
 //
-// A block (4 waves, v_mfma_f32_32x32x2f32) takes a 64-column strip of A and
-// up to three 64-row tiles of X at once: the strip is staged through LDS in
-// chunks of 32 rows once and feeds all three tiles, and F is never staged:
-// each lane forms its operand F[m][j] from an LDS table of cos / sin
-// (2 pi i / b), its index (m/2) j mod b advanced by (m/2) 2 mod b per step.
+// A block (4 waves, v_mfma_f32_32x32x2f32) takes a 128-column strip of A;
+// wave q forms both parts for its 32 columns and up to 96 slices at a time
+// (three 32-row accumulators per part).  P and Q are formed as the strip is
+// staged through LDS in chunks of 32 rows j; the cos / sin operands come
+// from an LDS table of (2 pi i / b), their common index k j mod b advanced
+// by 2k mod b per step.
 constexpr int kDftRowTiles = 3;
-LRSTV_DEV void band_dft_body(int bid, int nblk, const float* __restrict__ A, int64_t a_stride, int n_t,
-                             float* __restrict__ out, int hw, int b) {
-  __shared__ float ct[LRSTV_MAX_SIDE_DEV], st[LRSTV_MAX_SIDE_DEV];
-  __shared__ __align__(16) float sB[kKC][kMT + 4];
+constexpr int kDftCols = 128;   // strip width of both band transforms
+struct DftSmem {
+  float ct[LRSTV_MAX_SIDE_DEV], st[LRSTV_MAX_SIDE_DEV];
+  union {
+    struct {
+      __align__(16) float p[kKC][kDftCols + 4], q[kKC][kDftCols + 4];
+    };
+    __align__(16) float et[2 * kKC][kDftCols + 4];   // inverse: E rows j, b - j of one 32-row block
+  };
+};
+
+// cos / sin (2 pi m / b) times scale, m < b, into the block's table
+LRSTV_DEV void dft_table(DftSmem& sm, int b, double scale) {
   for (int m = threadIdx.x; m < b; m += blockDim.x) {
     double sv, cv;
     sincospi(2.0 * (double)m / (double)b, &sv, &cv);
-    ct[m] = (float)cv;
-    st[m] = (float)sv;
+    sm.ct[m] = (float)(cv * scale);
+    sm.st[m] = (float)(sv * scale);
   }
+}
+
+// Staging coordinates of a 32 x 128 chunk: thread t holds four columns of
+// rows t / 32 + 8 e, e = 0..3.
+LRSTV_DEV void dft_stage_coords(int t, int& sc, int& sr) {
+  sc = 4 * (t & 31);
+  sr = t >> 5;
+}
+
+LRSTV_DEV void band_dft_body(int bid, int nblk, const float* __restrict__ A, int64_t a_stride, int n_t,
+                             float* __restrict__ out, int hw, int b) {
+  __shared__ DftSmem sm;
+  dft_table(sm, b, 1.0);
   __syncthreads();
-  const int M = 2 * (b / 2 + 1);
-  const int TM = (M + kMT - 1) / kMT, TN = (hw + kMT - 1) / kMT;
-  const int nstrips = n_t * TN;
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, wy = wv >> 1, wx = wv & 1, li = lane & 31, lk = lane >> 5;
-  const int sc = 4 * (t & 15), sr = t >> 4;   // staging: columns sc .. sc+3, rows sr and sr + 16
+  const int s = b / 2 + 1, M = 2 * s;
+  const int TN = (hw + kDftCols - 1) / kDftCols, nstrips = n_t * TN;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, li = lane & 31, lk = lane >> 5;
+  int sc, sr;
+  dft_stage_coords(t, sc, sr);
   for (int strip = bid; strip < nstrips; strip += nblk) {
-    const int tt = strip / TN, tn = strip - tt * TN, n0 = tn * kMT;
+    const int tt = strip / TN, tn = strip - tt * TN, n0 = tn * kDftCols;
     const float* src = A + tt * a_stride;
     float* dst = out + (int64_t)tt * M * hw;
     const int ncol = hw - n0 - sc;   // columns of this thread's four that exist
-    for (int tg = 0; tg < TM; tg += kDftRowTiles) {
-      f32x16 acc[kDftRowTiles];
+    for (int kb = 0; kb < s; kb += 32 * kDftRowTiles) {
+      f32x16 are[kDftRowTiles], aim[kDftRowTiles];
       int idx[kDftRowTiles], stp[kDftRowTiles];
-      bool rok[kDftRowTiles], odd[kDftRowTiles];
+      bool kok[kDftRowTiles];
 #pragma unroll
       for (int q = 0; q < kDftRowTiles; ++q) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) acc[q][e] = 0.f;
-        const int m = (tg + q) * kMT + 32 * wy + li, kq = m >> 1;
-        rok[q] = m < M;
-        odd[q] = m & 1;
-        idx[q] = (int)(((int64_t)kq * lk) % b);      // j = lk at the first step
-        stp[q] = (int)(((int64_t)2 * kq) % b);
+        for (int e = 0; e < 16; ++e) are[q][e] = aim[q][e] = 0.f;
+        const int k = kb + 32 * q + li;
+        kok[q] = k < s;
+        idx[q] = (k * lk) % b;   // j = lk at the first step
+        stp[q] = (2 * k) % b;
       }
-      float pre[2][4];
-      auto fetch = [&](int k0) {
+      // rows j and b - j of the next chunk, four columns each
+      float pa[4][4], pb[4][4];
+      auto fetch = [&](int j0) {
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const int k = k0 + sr + 16 * e;
-          load4(src + (int64_t)k * hw + n0 + sc, k < b ? ncol : 0, pre[e]);
+        for (int e = 0; e < 4; ++e) {
+          const int j = j0 + sr + 8 * e, jb = b - j;
+          const bool pair = j > 0 && j < s && jb != j;
+          load4(src + (int64_t)j * hw + n0 + sc, j < s ? ncol : 0, pa[e]);
+          load4(src + (int64_t)(pair ? jb : 0) * hw + n0 + sc, pair ? ncol : 0, pb[e]);
         }
       };
       fetch(0);
-      for (int k0 = 0; k0 < b; k0 += kKC) {
+      for (int j0 = 0; j0 < s; j0 += kKC) {
 #pragma unroll
-        for (int e = 0; e < 2; ++e)
-          *reinterpret_cast<float4*>(&sB[sr + 16 * e][sc]) = make_float4(pre[e][0], pre[e][1], pre[e][2], pre[e][3]);
+        for (int e = 0; e < 4; ++e) {
+          float pv[4], qv[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            pv[c] = pa[e][c] + pb[e][c];
+            qv[c] = pa[e][c] - pb[e][c];
+          }
+          *reinterpret_cast<float4*>(&sm.p[sr + 8 * e][sc]) = make_float4(pv[0], pv[1], pv[2], pv[3]);
+          *reinterpret_cast<float4*>(&sm.q[sr + 8 * e][sc]) = make_float4(qv[0], qv[1], qv[2], qv[3]);
+        }
         __syncthreads();
-        if (k0 + kKC < b) fetch(k0 + kKC);
+        if (j0 + kKC < s) fetch(j0 + kKC);
 #pragma unroll 4
         for (int kk = 0; kk < kKC / 2; ++kk) {
-          const int j = k0 + 2 * kk + lk;
-          const float bv = sB[2 * kk + lk][32 * wx + li];
+          const float bp = sm.p[2 * kk + lk][32 * wv + li], bq = sm.q[2 * kk + lk][32 * wv + li];
 #pragma unroll
           for (int q = 0; q < kDftRowTiles; ++q) {
-            const float f = odd[q] ? -st[idx[q]] : ct[idx[q]];
-            const float av = (rok[q] && j < b) ? f : 0.f;
-            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[q], 0, 0, 0);
+            const float c = kok[q] ? sm.ct[idx[q]] : 0.f, sn = kok[q] ? -sm.st[idx[q]] : 0.f;
+            are[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(c, bp, are[q], 0, 0, 0);
+            aim[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(sn, bq, aim[q], 0, 0, 0);
             idx[q] += stp[q];
             if (idx[q] >= b) idx[q] -= b;
           }
         }
         __syncthreads();
       }
-      const int n = n0 + 32 * wx + li;
+      const int n = n0 + 32 * wv + li;
 #pragma unroll
       for (int q = 0; q < kDftRowTiles; ++q)
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-          const int m = (tg + q) * kMT + 32 * wy + 8 * (e >> 2) + 4 * lk + (e & 3);
-          if (m < M && n < hw) dst[(int64_t)m * hw + n] = acc[q][e];
+          const int k = kb + 32 * q + 8 * (e >> 2) + 4 * lk + (e & 3);
+          if (k < s && n < hw) {
+            dst[(int64_t)(2 * k) * hw + n] = are[q][e];
+            dst[(int64_t)(2 * k + 1) * hw + n] = aim[q][e];
+          }
         }
     }
   }
 }
 
-__global__ void __launch_bounds__(256, 4) k_band_dft(const float* __restrict__ A, int64_t a_stride, int n_t,
+__global__ void __launch_bounds__(256, 2) k_band_dft(const float* __restrict__ A, int64_t a_stride, int n_t,
                                                   float* __restrict__ out, int hw, int b) {
   band_dft_body(blockIdx.x, gridDim.x, A, a_stride, n_t, out, hw, b);
 }
 
-// Inverse band DFT with Hermitian completion, as the real product
-//   E (b x hw) = G (b x 2s) X (2s x hw),
-//   G[j][2k] = c_k cos(2 pi j k / b) / b,  G[j][2k+1] = -c_k sin(2 pi j k / b) / b,
-// c_k = 1 for k = 0 and k = b/2, else 2 (slice k stands for k and b - k).
+// Inverse band DFT with Hermitian completion, as two real products over the
+// s slices:
+//   C_j = sum_{k < s} c_k Re X_k cos(2 pi j k / b) / b,
+//   S_j = sum_{k < s} c_k Im X_k sin(2 pi j k / b) / b,   0 <= j < s,
+//   E_j = C_j - S_j,   E_{b-j} = C_j + S_j   (0 < j, b - j != j),
+// c_k = 1 for k = 0 and k = b/2, else 2 (slice k stands for k and b - k):
+// cos and sin are even and odd in j around b, so that the s rows j give all
+// b rows, at half the work of the full (b x 2s) product.
 // Epilogue (optional): Gamma4 += mu (E - F) and FP64 partial sums of
 // (E - F)^2, one fixed slot per block (grid = LRSTV_PARTS when part != NULL).
-// kIdftGroups groups of 256 threads per block work on consecutive tiles, so
-// that the fixed grid keeps enough loads in flight.
-constexpr int kIdftGroups = 4;
+// Block shape as the forward transform: 128-column strips, wave q forms C and
+// S for its 32 columns and up to 96 rows j at a time, so that both outputs
+// E_j and E_{b-j} of an element come from one lane.  The outputs of each
+// 32-row block go through LDS, so that the memory-bound epilogue (read F and
+// Gamma4, write Gamma4 and E) runs on four-wide, row-contiguous accesses
+// with four rows per thread in flight.
 LRSTV_DEV void band_idft_body(int bid, int nblk, const float* __restrict__ X, int n_t, float* __restrict__ E,
-                                                   int64_t e_stride, int hw, int b,
-                                                   const float* __restrict__ F, float* __restrict__ G4,
-                                                   const double* __restrict__ mu_dev, double* __restrict__ part) {
-  constexpr int G = kIdftGroups;
-  __shared__ MfmaSmemR sm[G];
-  __shared__ float ct[LRSTV_MAX_SIDE_DEV], st[LRSTV_MAX_SIDE_DEV];
-  __shared__ double red[4 * G];
-  const float ib = 1.0f / (float)b;
-  for (int m = threadIdx.x; m < b; m += blockDim.x) {
-    double sv, cv;
-    sincospi(2.0 * (double)m / (double)b, &sv, &cv);
-    ct[m] = (float)cv * ib;
-    st[m] = (float)sv * ib;
-  }
+                              int64_t e_stride, int hw, int b, const float* __restrict__ F, float* __restrict__ G4,
+                              const double* __restrict__ mu_dev, double* __restrict__ part) {
+  __shared__ DftSmem sm;
+  __shared__ double red[4];
+  dft_table(sm, b, 1.0 / (double)b);
   __syncthreads();
   const float mu = G4 ? (float)(*mu_dev) : 0.f;
-  const int K2 = 2 * (b / 2 + 1);
-  const int TM = (b + kMT - 1) / kMT, TN = (hw + kMT - 1) / kMT;
-  const int ntiles = n_t * TM * TN;
-  const int grp = threadIdx.x >> 8, t = threadIdx.x & 255, wv = t >> 6;
+  const int s = b / 2 + 1, K2 = 2 * s;
+  const int TN = (hw + kDftCols - 1) / kDftCols, nstrips = n_t * TN;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, li = lane & 31, lk = lane >> 5;
+  int sc, sr;
+  dft_stage_coords(t, sc, sr);
   double acc = 0.0;   // per-thread partial of (E - F)^2 in FP64
-  for (int base = bid * G; base < ntiles; base += nblk * G) {   // same trip count in every group
-    const int tile = base + grp < ntiles ? base + grp : ntiles - 1;
-    const bool tv = base + grp < ntiles;
-    const int tt = tile / (TM * TN), rem = tile - tt * TM * TN;
-    const int tn = rem / TM, tm = rem - tn * TM;
-    const int m0 = tm * kMT, n0 = tn * kMT;
+  for (int strip = bid; strip < nstrips; strip += nblk) {
+    const int tt = strip / TN, tn = strip - tt * TN, n0 = tn * kDftCols;
     const float* src = X + (int64_t)tt * K2 * hw;
     float* dst = E + tt * e_stride;
     const float* Ft = F ? F + tt * e_stride : nullptr;
     float* G4t = G4 ? G4 + tt * e_stride : nullptr;
-    const bool active = tv && m0 + 32 * (wv >> 1) < b && n0 + 32 * (wv & 1) < hw;
-    auto fa = [&](int j, int kk0, float* v) {
-      // kk0 is a multiple of 8: four slices k = kk0/2 .. kk0/2 + 3, re and im each
-      const int k0 = kk0 >> 1;
-      int idx = (j * k0) % b;
+    const int ncol = hw - n0 - sc;
+    for (int jb = 0; jb < s; jb += 32 * kDftRowTiles) {
+      f32x16 cc[kDftRowTiles], ss[kDftRowTiles];
+      int idx[kDftRowTiles], stp[kDftRowTiles];
+      bool jok[kDftRowTiles];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int k = k0 + q;
-        const bool ok = j < b && 2 * k < K2;
-        const float ck = (k == 0 || 2 * k == b) ? 1.f : 2.f;
-        v[2 * q] = ok ? ck * ct[idx] : 0.f;
-        v[2 * q + 1] = ok ? -ck * st[idx] : 0.f;
-        idx += j;
-        if (idx >= b) idx -= b;
+      for (int q = 0; q < kDftRowTiles; ++q) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) cc[q][e] = ss[q][e] = 0.f;
+        const int j = jb + 32 * q + li;
+        jok[q] = j < s;
+        idx[q] = (j * lk) % b;   // k = lk at the first step
+        stp[q] = (2 * j) % b;
       }
-    };
-    auto fb = [&](int k, int n, float(&v)[4]) {   // four columns of slice row k
-      load4(src + (int64_t)k * hw + n, k < K2 ? hw - n : 0, v);
-    };
-    // F and Gamma4 of the tile's outputs (accumulator layout) are loaded
-    // before the product, so that their latency is hidden behind it
-    float fv[16], gv[16];
-    const int ocol = n0 + 32 * (wv & 1) + (t & 31);
-    if (G4t && active) {
+      // c_k Re X_k and c_k Im X_k of the next chunk of slices, four columns each
+      float pr[4][4], pi[4][4];
+      auto fetch = [&](int k0) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int orow = m0 + 32 * (wv >> 1) + 8 * (r >> 2) + 4 * ((t & 63) >> 5) + (r & 3);
-        const bool ok = orow < b && ocol < hw;
-        const int64_t q = (int64_t)orow * hw + ocol;
-        fv[r] = ok ? Ft[q] : 0.f;
-        gv[r] = ok ? G4t[q] : 0.f;
+        for (int e = 0; e < 4; ++e) {
+          const int k = k0 + sr + 8 * e;
+          load4(src + (int64_t)(2 * k) * hw + n0 + sc, k < s ? ncol : 0, pr[e]);
+          load4(src + (int64_t)(2 * k + 1) * hw + n0 + sc, k < s ? ncol : 0, pi[e]);
+        }
+      };
+      fetch(0);
+      for (int k0 = 0; k0 < s; k0 += kKC) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int k = k0 + sr + 8 * e;
+          const float ck = (k == 0 || 2 * k == b) ? 1.f : 2.f;
+          *reinterpret_cast<float4*>(&sm.p[sr + 8 * e][sc]) =
+              make_float4(ck * pr[e][0], ck * pr[e][1], ck * pr[e][2], ck * pr[e][3]);
+          *reinterpret_cast<float4*>(&sm.q[sr + 8 * e][sc]) =
+              make_float4(ck * pi[e][0], ck * pi[e][1], ck * pi[e][2], ck * pi[e][3]);
+        }
+        __syncthreads();
+        if (k0 + kKC < s) fetch(k0 + kKC);
+#pragma unroll 4
+        for (int kk = 0; kk < kKC / 2; ++kk) {
+          const float br = sm.p[2 * kk + lk][32 * wv + li], bi = sm.q[2 * kk + lk][32 * wv + li];
+#pragma unroll
+          for (int q = 0; q < kDftRowTiles; ++q) {
+            const float c = jok[q] ? sm.ct[idx[q]] : 0.f, sn = jok[q] ? sm.st[idx[q]] : 0.f;
+            cc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(c, br, cc[q], 0, 0, 0);
+            ss[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(sn, bi, ss[q], 0, 0, 0);
+            idx[q] += stp[q];
+            if (idx[q] >= b) idx[q] -= b;
+          }
+        }
+        __syncthreads();
+      }
+      // E_j = C_j - S_j (LDS row r) and E_{b-j} = C_j + S_j (row 32 + r) of
+      // each 32-row block, then the epilogue over the block's rows
+#pragma unroll
+      for (int q = 0; q < kDftRowTiles; ++q) {
+        if (jb + 32 * q >= s) break;   // uniform
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int r = 8 * (e >> 2) + 4 * lk + (e & 3);
+          sm.et[r][32 * wv + li] = cc[q][e] - ss[q][e];
+          sm.et[32 + r][32 * wv + li] = cc[q][e] + ss[q][e];
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int u = 0; u < 8; ++u) {
+          const int r = sr + 8 * u, j = jb + 32 * q + (r & 31);
+          const bool lo_half = r < 32;
+          if (j >= s || ncol <= 0 || (!lo_half && (j == 0 || b - j == j))) continue;
+          const int64_t o = (int64_t)(lo_half ? j : b - j) * hw + n0 + sc;
+          const float4 ev = *reinterpret_cast<const float4*>(&sm.et[r][sc]);
+          const float e4[4] = {ev.x, ev.y, ev.z, ev.w};
+          const int nv = ncol < 4 ? ncol : 4;
+          if (nv == 4 && ((hw & 3) == 0)) {
+            *reinterpret_cast<float4*>(dst + o) = ev;
+            if (G4t) {
+              const float4 f = *reinterpret_cast<const float4*>(Ft + o), g = *reinterpret_cast<const float4*>(G4t + o);
+              const float f4[4] = {f.x, f.y, f.z, f.w};
+              *reinterpret_cast<float4*>(G4t + o) =
+                  make_float4(g.x + mu * (e4[0] - f4[0]), g.y + mu * (e4[1] - f4[1]), g.z + mu * (e4[2] - f4[2]),
+                              g.w + mu * (e4[3] - f4[3]));
+#pragma unroll
+              for (int c = 0; c < 4; ++c) {
+                const double dd = (double)e4[c] - (double)f4[c];
+                acc += dd * dd;
+              }
+            }
+          } else {
+            for (int c = 0; c < nv; ++c) {
+              dst[o + c] = e4[c];
+              if (G4t) {
+                const float f = Ft[o + c];
+                G4t[o + c] = G4t[o + c] + mu * (e4[c] - f);
+                const double dd = (double)e4[c] - (double)f;
+                acc += dd * dd;
+              }
+            }
+          }
+        }
+        __syncthreads();
       }
     }
-    int ri = 0;   // the tile routine hands the outputs over in accumulator order
-    auto sto = [&](int j, int n, float e) {
-      if (j < b && n < hw) {
-        const int64_t q = (int64_t)j * hw + n;
-        dst[q] = e;
-        if (G4t) {
-          const float f = fv[ri];
-          G4t[q] = gv[ri] + mu * (e - f);
-          const double d = (double)e - (double)f;
-          acc += d * d;
-        }
-      }
-      ++ri;
-    };
-    mfma_rtile_t<true, false, true>(t, m0, n0, K2, fa, fb, sto, sm[grp], active);
   }
   if (part) {
     const double tot = block_sum(acc, red);
@@ -928,12 +1015,10 @@ LRSTV_DEV void band_idft_body(int bid, int nblk, const float* __restrict__ X, in
   }
 }
 
-__global__ void __launch_bounds__(256 * kIdftGroups) k_band_idft(const float* __restrict__ X, int n_t,
-                                                                 float* __restrict__ E, int64_t e_stride, int hw,
-                                                                 int b, const float* __restrict__ F,
-                                                                 float* __restrict__ G4,
-                                                                 const double* __restrict__ mu_dev,
-                                                                 double* __restrict__ part) {
+__global__ void __launch_bounds__(256, 2) k_band_idft(const float* __restrict__ X, int n_t, float* __restrict__ E,
+                                                   int64_t e_stride, int hw, int b, const float* __restrict__ F,
+                                                   float* __restrict__ G4, const double* __restrict__ mu_dev,
+                                                   double* __restrict__ part) {
   band_idft_body(blockIdx.x, gridDim.x, X, n_t, E, e_stride, hw, b, F, G4, mu_dev, part);
 }
 
@@ -997,7 +1082,7 @@ __global__ void __launch_bounds__(kTriCols * kTriChunks, MAXL <= 16 ? 4 : 2) k_t
 }
 
 // A: component stride a_stride from the cube's offset; slices at slice_base
-__global__ void __launch_bounds__(256, 4) k_band_dft_batch(BatchTab bt, const float* __restrict__ A, int64_t a_stride,
+__global__ void __launch_bounds__(256, 2) k_band_dft_batch(BatchTab bt, const float* __restrict__ A, int64_t a_stride,
                                                         float* __restrict__ slices) {
   const CubeSel q = select_cube(bt);
   if (cube_halted(bt, q.c)) return;
@@ -1005,7 +1090,7 @@ __global__ void __launch_bounds__(256, 4) k_band_dft_batch(BatchTab bt, const fl
   band_dft_body(q.bid, q.nblk, A + g.off, a_stride, 3, slices + g.slice_base, g.h * g.w, g.b);
 }
 
-__global__ void __launch_bounds__(256 * kIdftGroups) k_band_idft_batch(BatchTab bt, const float* __restrict__ slices,
+__global__ void __launch_bounds__(256, 2) k_band_idft_batch(BatchTab bt, const float* __restrict__ slices,
                                                          float* __restrict__ E, int64_t e_stride,
                                                          const float* __restrict__ F, float* __restrict__ G4,
                                                          const double* __restrict__ mu_dev, double* __restrict__ part) {
@@ -1200,19 +1285,17 @@ static int dft_tile(int b) {
 
 void launch_band_dft(const float* A, int64_t a_stride, int n_t, float* slices, int h, int w, int b, hipStream_t s) {
   const int hw = h * w;
-  const int64_t nstrips = (int64_t)n_t * ((hw + kMT - 1) / kMT);
-  const int grid = (int)(nstrips < 8192 ? nstrips : 8192);
+  const int64_t nstrips = (int64_t)n_t * ((hw + kDftCols - 1) / kDftCols);
+  const int grid = (int)(nstrips < 512 ? nstrips : 512);
   hipLaunchKernelGGL(k_band_dft, dim3(grid), dim3(256), 0, s, A, a_stride, n_t, slices, hw, b);
 }
 
 void launch_band_idft(const float* slices, int n_t, float* E, int64_t e_stride, int h, int w, int b,
                       const float* F, float* G4, const double* mu, double* part, hipStream_t s) {
   const int hw = h * w;
-  const int64_t ntiles = (int64_t)n_t * ((b + kMT - 1) / kMT) * ((hw + kMT - 1) / kMT);
-  const int64_t ng = (ntiles + kIdftGroups - 1) / kIdftGroups;
-  const int grid = part ? LRSTV_PARTS : (int)(ng < 2048 ? ng : 2048);
-  hipLaunchKernelGGL(k_band_idft, dim3(grid), dim3(256 * kIdftGroups), 0, s, slices, n_t, E, e_stride, hw, b, F, G4,
-                     mu, part);
+  const int64_t nstrips = (int64_t)n_t * ((hw + kDftCols - 1) / kDftCols);
+  const int grid = part ? LRSTV_PARTS : (int)(nstrips < 2048 ? nstrips : 2048);
+  hipLaunchKernelGGL(k_band_idft, dim3(grid), dim3(256), 0, s, slices, n_t, E, e_stride, hw, b, F, G4, mu, part);
 }
 
 // ---------------------------------------------------- batched launchers ---
@@ -1235,8 +1318,10 @@ int phase_blocks(int phase, int h, int w, int b) {
     }
     case PH_TRI_B: return tri_groups(h, w);
     case PH_BAND_DFT: {
-      const int64_t t = (int64_t)3 * (((int64_t)h * w + kMT - 1) / kMT);
-      return (int)(t < 8192 ? t : 8192);
+      // two blocks per CU (register budget): the strips of a 256 x 256 cube
+      // in one round of 512 blocks
+      const int64_t t = (int64_t)3 * (((int64_t)h * w + kDftCols - 1) / kDftCols);
+      return (int)(t < 512 ? t : 512);
     }
     default: return LRSTV_PARTS;
   }
@@ -1288,8 +1373,8 @@ void launch_band_dft_batch(const BatchTab& bt, const float* A, int64_t a_stride,
 
 void launch_band_idft_batch(const BatchTab& bt, const float* slices, float* E, int64_t e_stride, const float* F,
                             float* G4, const double* mu, double* part, hipStream_t s) {
-  hipLaunchKernelGGL(k_band_idft_batch, dim3(bt.nc * LRSTV_PARTS), dim3(256 * kIdftGroups), 0, s, bt, slices, E,
-                     e_stride, F, G4, mu, part);
+  hipLaunchKernelGGL(k_band_idft_batch, dim3(bt.nc * LRSTV_PARTS), dim3(256), 0, s, bt, slices, E, e_stride, F,
+                     G4, mu, part);
 }
 
 }  // namespace lrstv
