@@ -1719,11 +1719,13 @@ __global__ void __launch_bounds__(256) k_wy_t(const SliceDesc* __restrict__ desc
 // of row tile t is row 16 t + 4 (l / 16) + r, column l % 16, which is exactly
 // the B operand (row l / 16, column l % 16) of the step that contracts over
 // the rows {16 t + 4 g + r, g = 0..3}.  So W and W' never leave the registers;
-// only the A operands (Y^H, T, Y) and the V rows of the first product are
-// staged through LDS, shared by the four waves.  LDS row strides are chosen
-// so that the operand reads are free of bank conflicts: 80 where a lane's
-// row is 4 s + l / 16 (16 (l / 16) + l % 16 distinct mod 64), 68 where it is
-// 16 t + 4 (l / 16) + r (16 (l / 16) + l % 16 again).
+// only the operands Y, T and V are staged through LDS, shared by the four
+// waves, in chunks of 32 rows with the next chunk's loads in flight (one
+// loader for both passes over V).  The last product is added into the
+// staged V, which is written back coalesced.  LDS row strides are chosen so
+// that the operand reads are free of bank conflicts: 80 where a lane's row
+// is 4 s + l / 16 (16 (l / 16) + l % 16 distinct mod 64), 68 and 36 where it
+// is 16 t + 4 (l / 16) + r (16 (l / 16) + l % 16 again).
 struct WySmem {
   union {
     struct {
@@ -1733,8 +1735,9 @@ struct WySmem {
       float tr[64][68], ti[64][68];                           // T(p, q) at [q][p]
     } t;
     struct {
-      float yr[64][68], yi[64][68];                           // Y(k, p) at [p][k], k in the chunk
-    } y;
+      float yr[64][36], yi[64][36];                           // Y(k, p) at [p][k], k in the chunk
+      float vr[32][68], vi[32][68];                           // V(k, c)
+    } u;
   };
 };
 
@@ -1854,21 +1857,24 @@ __global__ void __launch_bounds__(256, 3) k_wy_apply(const SliceDesc* __restrict
       xi[q] = x3[q] - x1[q] - x2[q];
     }
     __syncthreads();
-    // ---- V[i0+1:, cols] -= Y W': chunks of 64 rows; 3M with P1 = Yr W'r,
+    // ---- V[i0+1:, cols] -= Y W': chunks of 32 rows; 3M with P1 = Yr W'r,
     // P2 = Yi W'i, P3 = (Yr + Yi)(W'r + W'i).
-    for (int k0 = 0; k0 < m; k0 += 64) {
-#pragma unroll 4
-      for (int j = 0; j < 16; ++j) {
-        const int e = t + 256 * j, kk = e >> 6, p = e & 63, k = k0 + kk;
-        const float2 y = k < m ? wy_y(g, n, i0, nbk, k, p) : make_float2(0.f, 0.f);
-        sm.y.yr[p][kk] = y.x;
-        sm.y.yi[p][kk] = y.y;
+    load1(0);
+    for (int k0 = 0; k0 < m; k0 += 32) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int e = t + 256 * j, kk = e >> 6, cc = e & 63;
+        sm.u.yr[cc][kk] = ys[j].x;
+        sm.u.yi[cc][kk] = ys[j].y;
+        sm.u.vr[kk][cc] = vs[j].x;
+        sm.u.vi[kk][cc] = vs[j].y;
       }
       __syncthreads();
+      if (k0 + 32 < m) load1(k0 + 32);
       if (act) {
-        f32x4 u1[4], u2[4], u3[4];
+        f32x4 u1[2], u2[2], u3[2];
 #pragma unroll
-        for (int kt = 0; kt < 4; ++kt) u1[kt] = u2[kt] = u3[kt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int kt = 0; kt < 2; ++kt) u1[kt] = u2[kt] = u3[kt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -1876,30 +1882,38 @@ __global__ void __launch_bounds__(256, 3) k_wy_apply(const SliceDesc* __restrict
             const int p = 16 * q + 4 * lg + rr;
             const float br = xr[q][rr], bi = xi[q][rr], bs = br + bi;
 #pragma unroll
-            for (int kt = 0; kt < 4; ++kt) {
-              const float ar = sm.y.yr[p][16 * kt + li], ai = sm.y.yi[p][16 * kt + li];
+            for (int kt = 0; kt < 2; ++kt) {
+              const float ar = sm.u.yr[p][16 * kt + li], ai = sm.u.yi[p][16 * kt + li];
               u1[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, u1[kt], 0, 0, 0);
               u2[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bi, u2[kt], 0, 0, 0);
               u3[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar + ai, bs, u3[kt], 0, 0, 0);
             }
             __builtin_amdgcn_sched_barrier(0);
           }
-        if (ccol < nc) {
+        // element rr of lane l of row tile kt: row 16 kt + 4 (l / 16) + rr
 #pragma unroll
-          for (int kt = 0; kt < 4; ++kt)
+        for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-              const int k = k0 + 16 * kt + 4 * lg + rr;
-              if (k < m) {
-                const int64_t q = (int64_t)(i0 + 1 + k) * n + c0 + ccol;
-                Vr[q] -= u1[kt][rr] - u2[kt][rr];
-                Vi[q] -= u3[kt][rr] - u1[kt][rr] - u2[kt][rr];
-              }
-            }
-        }
+          for (int rr = 0; rr < 4; ++rr) {
+            const int row = 16 * kt + 4 * lg + rr;
+            sm.u.vr[row][ccol] -= u1[kt][rr] - u2[kt][rr];
+            sm.u.vi[row][ccol] -= u3[kt][rr] - u1[kt][rr] - u2[kt][rr];
+          }
       }
       __syncthreads();
+      // each thread writes back the elements it staged (the next staging
+      // overwrites only those, so no barrier is needed before it)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int e = t + 256 * j, kk = e >> 6, cc = e & 63, k = k0 + kk;
+        if (k < m && cc < nc) {
+          const int64_t q = (int64_t)(i0 + 1 + k) * n + c0 + cc;
+          Vr[q] = sm.u.vr[kk][cc];
+          Vi[q] = sm.u.vi[kk][cc];
+        }
+      }
     }
+    __syncthreads();
   }
 }
 
