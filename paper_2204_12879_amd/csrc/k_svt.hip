@@ -869,6 +869,25 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __res
     }
   }
   __syncthreads();
+  // The reflector of a step is computed by the waves of D only (they have
+  // the fewest tiles): the other waves never need it, since without a
+  // reflection D writes v = w = 0, so that C's products are discarded and E
+  // adds zeros.  That of step i + 1 is formed right after the barrier that
+  // ends D of step i, before these waves issue their share of E, so that
+  // the waves with the most tiles issue theirs first.
+  MtRefl f{};
+  auto next_reflector = [&](int pr, int i1) {
+    double nx2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < NDW; ++q) nx2 += red_nx[pr][q];
+    return mt_reflector(uniform_d(nx2), make_float2(uniform_f(xb[pr][i1].x), uniform_f(xb[pr][i1].y)));
+  };
+  if (wv < NDW && n > 1) f = next_reflector(0, 1);
+  // Issue priority by share of tiles: the waves holding the most tiles set
+  // the length of the product and update phases, the waves of D have slack
+  // there (the tile dealing gives waves 8-11 the most).
+  if (wv >= 8) __builtin_amdgcn_s_setprio(2);
+  else if (wv >= NDW) __builtin_amdgcn_s_setprio(1);
   for (int i = 0; i < n - 1; ++i) {
     const int par = i & 1;
     const float2* xv = xb[par];
@@ -876,17 +895,6 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __res
     // lane-derived indices are recomputed every step from this copy rather
     // than kept live across the loop next to the tiles
     const int lane = opaque_i(threadIdx.x & 63), li = lane & 31, h = lane >> 5;
-    // ---- the reflector of step i, in the waves of D only (they have the
-    // fewest tiles, and compute it ahead of their share of C).  The other
-    // waves never need it: without a reflection D writes v = w = 0, so
-    // that C's products are discarded and E adds zeros.
-    MtRefl f{};
-    if (wv < NDW) {
-      double nx2 = 0.0;
-#pragma unroll
-      for (int q = 0; q < NDW; ++q) nx2 += red_nx[par][q];
-      f = mt_reflector(uniform_d(nx2), make_float2(uniform_f(xv[i + 1].x), uniform_f(xv[i + 1].y)));
-    }
     // ---- C: A x per wave, x^H A x ----------------------------------------
     {
       for (int t = lane; t < NMAX; t += 64) P[wv][t] = zero;
@@ -1035,6 +1043,7 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __res
       }
     }
     lds_barrier();
+    if (wv < NDW && i + 2 < n) f = next_reflector(par ^ 1, i + 2);
     // ---- E: A -= v w^H + w v^H on the matrix cores ------------------------
     // real part: [-v_R | -w_R] (re in half 0, im in half 1) times [w_C ; v_C];
     // imaginary part: [-Im v, Re v] and [-Im w, Re w] against the same B.
