@@ -120,6 +120,352 @@ __global__ void __launch_bounds__(256) k_gram(const SliceDesc* __restrict__ desc
   }
 }
 
+// Split-BF16 Gram on 128 x 128 tiles.  Each 32-wide k chunk of the tile's
+// row and column operands is split once into hi / lo BF16 planes in LDS,
+// and each wave computes a 64 x 64 block as 2 x 2 sub-tiles of
+// v_mfma_f32_32x32x16_bf16, so that every fragment read from LDS feeds two
+// products.  Products and terms as k_gram's split-BF16 mode.  A diagonal
+// tile has one operand panel, staged once (two of the three tiles of a
+// 256-wide slice).
+//
+// One block per CU (512 registers per lane), pipelined over the chunks:
+// step c reads chunk c's fragments into registers, and after the barrier
+// that frees the buffer issues the loads of chunk c + 2, splits chunk
+// c + 1 (loaded during step c - 1) into the buffer and runs chunk c's
+// products, the split and the products in one basic block so that the
+// vector and LDS work issues between the products.
+struct GramBfSmem {
+  // planes 0 re hi, 1 re lo, 2 im hi, 3 im lo; row = the tile's row / column
+  // index, the chunk's k contiguous (a lane's eight k are one 16-byte read)
+  __bf16 a[4][128][kKC + kBfPad];
+  __bf16 b[4][128][kKC + kBfPad];
+};
+
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+
+// hi = RNE_bf16(x) and lo = RNE_bf16(x - hi) (x - hi is exact in FP32) for a
+// pair of values, each pair packed in one dword: one packed conversion per
+// plane, the FP32 value of hi by a shift / mask of its bits.
+LRSTV_DEV void bf_split2(float x0, float x1, unsigned& hi, unsigned& lo) {
+  const f32x2v x = {x0, x1};
+  const unsigned u = __builtin_bit_cast(unsigned, __builtin_convertvector(x, bf16x2v));
+  const f32x2v r = {x0 - __uint_as_float(u << 16), x1 - __uint_as_float(u & 0xffff0000u)};
+  hi = u;
+  lo = __builtin_bit_cast(unsigned, __builtin_convertvector(r, bf16x2v));
+}
+
+// Split eight consecutive values (one k run of one row) into the four
+// planes at row `row`, k offset k0 of the chunk.
+LRSTV_DEV void bf_split_store(__bf16 (*p)[128][kKC + kBfPad], int row, int k0, const float (&re)[8],
+                              const float (&im)[8]) {
+  uint4 rh, rl, ih, il;
+  bf_split2(re[0], re[1], rh.x, rl.x);
+  bf_split2(re[2], re[3], rh.y, rl.y);
+  bf_split2(re[4], re[5], rh.z, rl.z);
+  bf_split2(re[6], re[7], rh.w, rl.w);
+  bf_split2(im[0], im[1], ih.x, il.x);
+  bf_split2(im[2], im[3], ih.y, il.y);
+  bf_split2(im[4], im[5], ih.z, il.z);
+  bf_split2(im[6], im[7], ih.w, il.w);
+  *(uint4*)&p[0][row][k0] = rh;
+  *(uint4*)&p[1][row][k0] = rl;
+  *(uint4*)&p[2][row][k0] = ih;
+  *(uint4*)&p[3][row][k0] = il;
+}
+
+// One thread's share of a chunk, 32 complex values.
+struct BfChunk { float r[32], i[32]; };
+
+// Chunk staging.  The planes hold Re M and Im M with no conjugation; an
+// operand panel is 128 rows (indices of the Gram) by the chunk's 32 k.
+//
+// FAST (w a multiple of 4, K a multiple of the chunk width, 16-byte aligned
+// planes): straight-line loads with clamped indices and no selects.  Rows
+// or columns past n only reach Gram entries past n, which are not stored,
+// and chunks past K are split into the buffer but never read, so the
+// clamped loads may return any data there.  On a diagonal tile (DIAG) the
+// two operands are one panel, staged once by all 256 threads (s = t);
+// otherwise threads 0-127 stage the row operand and 128-255 the column
+// operand (s = t mod 128).
+//   tall (panel rows = columns of M, k = rows of M): a lane holds two
+//     adjacent columns (float2 loads along a row of M) of DIAG ? 8 : 16
+//     rows, v[2 r + c] = M(k0 + kb + r, col + c), so that the 16-byte LDS
+//     stores of 16 lanes fall on distinct bank pairs (four columns per lane
+//     would put them on one bank quarter);
+//   wide (panel rows = rows of M, k contiguous): DIAG ? 2 : 4 runs of eight
+//     k, v[8 u + j] = M(row_u, k0 + 8 q_u + j).
+// Otherwise (SLOW) each load checks its range and reads zeros past it:
+// tall, four columns of eight rows (v[4 r + c]); wide as FAST.
+template <bool TALL, bool DIAG>
+LRSTV_DEV void bf_fetch_fast(BfChunk& v, const float* re, const float* im, int h, int w, int n, int base, int s,
+                             int k0) {
+  const int K = TALL ? h : w, kc = min(k0, K - kKC);
+  if (TALL) {
+    constexpr int NR = DIAG ? 8 : 16;
+    const int col = min(base + 2 * (s & 63), n - 2), r0 = kc + NR * (s >> 6);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int64_t o = (int64_t)(r0 + r) * w + col;
+      const float2 x = *reinterpret_cast<const float2*>(re + o), y = *reinterpret_cast<const float2*>(im + o);
+      v.r[2 * r] = x.x; v.r[2 * r + 1] = x.y;
+      v.i[2 * r] = y.x; v.i[2 * r + 1] = y.y;
+    }
+  } else {
+    constexpr int NU = DIAG ? 2 : 4, STEP = DIAG ? 256 : 128;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int e = s + STEP * u, mr = min(base + (e >> 2), n - 1);
+      const int64_t o = (int64_t)mr * w + kc + 8 * (e & 3);
+#pragma unroll
+      for (int hf = 0; hf < 2; ++hf) {
+        const float4 x = *reinterpret_cast<const float4*>(re + o + 4 * hf);
+        const float4 y = *reinterpret_cast<const float4*>(im + o + 4 * hf);
+        float* vr = &v.r[8 * u + 4 * hf];
+        float* vi = &v.i[8 * u + 4 * hf];
+        vr[0] = x.x; vr[1] = x.y; vr[2] = x.z; vr[3] = x.w;
+        vi[0] = y.x; vi[1] = y.y; vi[2] = y.z; vi[3] = y.w;
+      }
+    }
+  }
+}
+
+template <bool TALL, bool DIAG>
+LRSTV_DEV void bf_stage_fast(const BfChunk& v, __bf16 (*p)[128][kKC + kBfPad], int s) {
+  if (TALL) {
+    constexpr int NR = DIAG ? 8 : 16;
+    const int row = 2 * (s & 63), kb = NR * (s >> 6);
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int g = 0; g < NR / 8; ++g) {
+        float xr[8], xi[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          xr[j] = v.r[2 * (8 * g + j) + c];
+          xi[j] = v.i[2 * (8 * g + j) + c];
+        }
+        bf_split_store(p, row + c, kb + 8 * g, xr, xi);
+      }
+  } else {
+    constexpr int NU = DIAG ? 2 : 4, STEP = DIAG ? 256 : 128;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int e = s + STEP * u;
+      bf_split_store(p, e >> 2, 8 * (e & 3), *reinterpret_cast<const float(*)[8]>(&v.r[8 * u]),
+                     *reinterpret_cast<const float(*)[8]>(&v.i[8 * u]));
+    }
+  }
+}
+
+template <bool TALL>
+LRSTV_DEV void bf_fetch_slow(BfChunk& v, const float* re, const float* im, int h, int w, int n, int base, int s,
+                             int k0) {
+  if (TALL) {
+    // A(i, k) = conj(M(k, i)), B(k, j) = M(k, j): columns of M, rows k
+    const int col = base + 4 * (s & 31), q = s >> 5, nv = col < n ? n - col : 0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int k = k0 + 8 * q + r;
+      load4(re + (int64_t)k * w + col, k < h ? nv : 0, *reinterpret_cast<float(*)[4]>(&v.r[4 * r]));
+      load4(im + (int64_t)k * w + col, k < h ? nv : 0, *reinterpret_cast<float(*)[4]>(&v.i[4 * r]));
+    }
+  } else {
+    // A(i, k) = M(i, k), B(k, j) = conj(M(j, k)): rows of M, k contiguous
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = s + 128 * u, mr = base + (e >> 2), k = k0 + 8 * (e & 3);
+      const int nv = (mr < n && k < w) ? w - k : 0;
+      load8(re + (int64_t)mr * w + k, nv, *reinterpret_cast<float(*)[8]>(&v.r[8 * u]));
+      load8(im + (int64_t)mr * w + k, nv, *reinterpret_cast<float(*)[8]>(&v.i[8 * u]));
+    }
+  }
+}
+
+template <bool TALL>
+LRSTV_DEV void bf_stage_slow(const BfChunk& v, __bf16 (*p)[128][kKC + kBfPad], int s) {
+  if (TALL) {
+    const int c = 4 * (s & 31), q = s >> 5;
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+      float xr[8], xi[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        xr[r] = v.r[4 * r + cc];
+        xi[r] = v.i[4 * r + cc];
+      }
+      bf_split_store(p, c + cc, 8 * q, xr, xi);
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = s + 128 * u;
+      bf_split_store(p, e >> 2, 8 * (e & 3), *reinterpret_cast<const float(*)[8]>(&v.r[8 * u]),
+                     *reinterpret_cast<const float(*)[8]>(&v.i[8 * u]));
+    }
+  }
+}
+
+// FAST selects the straight-line staging, DIAG (FAST only) a diagonal tile.
+template <bool TALL, bool FAST, bool DIAG>
+LRSTV_DEV void bf_fetch(BfChunk& v, const float* re, const float* im, int h, int w, int n, int base, int s, int k0) {
+  if (FAST)
+    bf_fetch_fast<TALL, DIAG>(v, re, im, h, w, n, base, s, k0);
+  else
+    bf_fetch_slow<TALL>(v, re, im, h, w, n, base, s, k0);
+}
+template <bool TALL, bool FAST, bool DIAG>
+LRSTV_DEV void bf_stage(const BfChunk& v, __bf16 (*p)[128][kKC + kBfPad], int s) {
+  if (FAST)
+    bf_stage_fast<TALL, DIAG>(v, p, s);
+  else
+    bf_stage_slow<TALL>(v, p, s);
+}
+
+template <bool TALL, bool FAST, bool DIAG>
+LRSTV_DEV void gram_bf16_tile(GramBfSmem& sm, const SliceDesc& d, const float* sl, float2* gram, int ti, int tj) {
+  const int n = d.n1, h = d.h, w = d.w, K = TALL ? h : w;
+  const float* re = sl + d.a_off;
+  const float* im = re + (int64_t)h * w;
+  const int i0 = 128 * ti, j0 = 128 * tj;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, wy = wv >> 1, wx = wv & 1;
+  const int li = lane & 31, lk = lane >> 5;
+  f32x16 cre[2][2], cim[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) cre[a][b][e] = cim[a][b][e] = 0.f;
+  // staging: one panel by all threads on a diagonal tile, else threads
+  // 0-127 the row operand (A) and 128-255 the column operand (B)
+  const bool isA = DIAG || t < 128;
+  const int st = DIAG ? t : t & 127, base = isA ? i0 : j0;
+  __bf16(*dstp)[128][kKC + kBfPad] = isA ? sm.a : sm.b;
+  __bf16(*bsrc)[128][kKC + kBfPad] = DIAG ? sm.a : sm.b;
+  const int nch = (K + kKC - 1) / kKC;
+  BfChunk cur, nxt;
+  bf_fetch<TALL, FAST, DIAG>(cur, re, im, h, w, n, base, st, 0);
+  bf_stage<TALL, FAST, DIAG>(cur, dstp, st);
+  bf_fetch<TALL, FAST, DIAG>(cur, re, im, h, w, n, base, st, kKC);
+  // no load in flight at the loop entry, so that the waits inside the loop
+  // cover only the loads of the previous trip (s_waitcnt vmcnt(0), the
+  // other counters at their maxima in the gfx9 encoding)
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  __syncthreads();
+  // chunk c's products from registers, while chunk c + 2 is fetched into
+  // nxt and chunk c + 1 (held in cur) is split into the buffer (past the
+  // end the split is never read)
+  for (int c = 0; c < nch; ++c) {
+    bf16x8 ar[2][2][4], br[2][2][4];   // [ks][sub-tile][plane]
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const int ko = 16 * ks + 8 * lk;
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int ra = 64 * wy + 32 * a + li, rb = 64 * wx + 32 * a + li;
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl) {
+          ar[ks][a][pl] = *(const bf16x8*)&sm.a[pl][ra][ko];
+          br[ks][a][pl] = *(const bf16x8*)&bsrc[pl][rb][ko];
+        }
+      }
+    }
+    __syncthreads();   // the buffer is free: every wave holds chunk c in registers
+    bf_fetch<TALL, FAST, DIAG>(nxt, re, im, h, w, n, base, st, kKC * (c + 2));
+    __builtin_amdgcn_sched_barrier(0);   // the loads issue first
+    bf_stage<TALL, FAST, DIAG>(cur, dstp, st);
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      // The planes hold Re M and Im M as they are, with no conjugation.
+      // Tall (A = M^H, B = M): Re G = Re A Re B + Im A' Im B' and
+      // Im G = Re A Im B' - Im A' Re B (primes: the stored planes).  Wide
+      // (A = M, B = M^H): the same Re G, and Im G the negative of that
+      // accumulation, applied at the store.
+      bf16x8 na[2][2];   // -Im A' hi, -Im A' lo
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        na[a][0] = bf_neg(ar[ks][a][2]);
+        na[a][1] = bf_neg(ar[ks][a][3]);
+      }
+      // one term at a time over the four sub-tiles; small terms first
+#define LRSTV_BF_TERM(ACC, AOP, BPL)                                                       \
+  _Pragma("unroll") for (int a = 0; a < 2; ++a) _Pragma("unroll") for (int b = 0; b < 2; ++b) \
+      ACC[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AOP, br[ks][b][BPL], ACC[a][b], 0, 0, 0);
+      LRSTV_BF_TERM(cre, ar[ks][a][0], 1)
+      LRSTV_BF_TERM(cre, ar[ks][a][1], 0)
+      LRSTV_BF_TERM(cre, ar[ks][a][2], 3)
+      LRSTV_BF_TERM(cre, ar[ks][a][3], 2)
+      LRSTV_BF_TERM(cre, ar[ks][a][0], 0)
+      LRSTV_BF_TERM(cre, ar[ks][a][2], 2)
+      LRSTV_BF_TERM(cim, ar[ks][a][0], 3)
+      LRSTV_BF_TERM(cim, ar[ks][a][1], 2)
+      LRSTV_BF_TERM(cim, na[a][0], 1)
+      LRSTV_BF_TERM(cim, na[a][1], 0)
+      LRSTV_BF_TERM(cim, ar[ks][a][0], 2)
+      LRSTV_BF_TERM(cim, na[a][0], 0)
+#undef LRSTV_BF_TERM
+    }
+    // interleave: each product followed by three vector ops, an LDS store every sixth
+#pragma unroll
+    for (int i = 0; i < 96; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
+      if (i % 6 == 5) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+    }
+    // the copy waits for chunk c + 2's loads: keep it after the products
+    __builtin_amdgcn_sched_barrier(0);
+    cur = nxt;
+    __syncthreads();   // chunk c + 1 is in the buffer
+  }
+  // packed lower triangle; the diagonal is real
+  float2* g = gram + d.g_off;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int col = j0 + 64 * wx + 32 * b + li;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int row = i0 + 64 * wy + 32 * a + 8 * (e >> 2) + 4 * lk + (e & 3);
+        if (row < n && col <= row)
+          g[packed(row, col)] = make_float2(cre[a][b][e], row == col ? 0.f : TALL ? cim[a][b][e] : -cim[a][b][e]);
+      }
+    }
+}
+
+__global__ void __launch_bounds__(256, 1) k_gram_bf16(const SliceDesc* __restrict__ desc, const float* __restrict__ sl,
+                                                      float2* __restrict__ gram, int ntile, int ns,
+                                                      const int* __restrict__ halt) {
+  __shared__ GramBfSmem sm;
+  int tile, slice;
+  if (!xcd_tile_slice(ntile, ns, tile, slice)) return;
+  const SliceDesc d = desc[slice];
+  if (halt && halt[d.cube]) return;   // the cube has met its stopping test
+  const int T = (d.n1 + 127) / 128;
+  int ti = 0, rem = tile;
+  while (rem > ti) { rem -= ti + 1; ++ti; }
+  if (ti >= T) return;
+  const float* re = sl + d.a_off;
+  const bool fast = d.w % 4 == 0 && (d.tall ? d.h : d.w) % kKC == 0 && (reinterpret_cast<uintptr_t>(re) & 15) == 0;
+  const bool diag = ti == rem;
+  if (d.tall) {
+    if (fast && diag)
+      gram_bf16_tile<true, true, true>(sm, d, sl, gram, ti, rem);
+    else if (fast)
+      gram_bf16_tile<true, true, false>(sm, d, sl, gram, ti, rem);
+    else
+      gram_bf16_tile<true, false, false>(sm, d, sl, gram, ti, rem);
+  } else {
+    if (fast && diag)
+      gram_bf16_tile<false, true, true>(sm, d, sl, gram, ti, rem);
+    else if (fast)
+      gram_bf16_tile<false, true, false>(sm, d, sl, gram, ti, rem);
+    else
+      gram_bf16_tile<false, false, false>(sm, d, sl, gram, ti, rem);
+  }
+}
+
 // ---------------------------------------------------------- tridiagonal ---
 // Householder reduction of the packed Hermitian Gram, one block per slice.
 // Step i: x = A(i+1:, i); H = I - tau v v^H with H x = beta e_1,
@@ -2367,12 +2713,17 @@ void launch_svt_tridiag(const SvtLaunch& L, hipStream_t s) {
 }
 static void launch_tridiag(const SvtLaunch& L, hipStream_t s) { launch_svt_tridiag(L, s); }
 
+static void launch_gram_bf16(const SvtLaunch& L, hipStream_t s) {
+  const int ns = L.n_slices, T2 = (L.max_n1 + 127) / 128;
+  hipLaunchKernelGGL(k_gram_bf16, dim3(xcd_grid(T2 * (T2 + 1) / 2, ns)), dim3(256), 0, s, L.desc, L.slices, L.gram,
+                     T2 * (T2 + 1) / 2, ns, L.halt);
+}
+
 void launch_svt_gram(const SvtLaunch& L, hipStream_t s) {
   const int ns = L.n_slices, n = L.max_n1;
   const int TT = (n + kMT - 1) / kMT;
   if (L.precision == LRSTV_SPLIT_BF16)
-    hipLaunchKernelGGL(k_gram<kBF16x3>, dim3(xcd_grid(TT * (TT + 1) / 2, ns)), dim3(256), 0, s, L.desc, L.slices, L.gram,
-                       TT * (TT + 1) / 2, ns, L.halt);
+    launch_gram_bf16(L, s);
   else
     hipLaunchKernelGGL(k_gram<kF32>, dim3(xcd_grid(TT * (TT + 1) / 2, ns)), dim3(256), 0, s, L.desc, L.slices, L.gram,
                        TT * (TT + 1) / 2, ns, L.halt);
@@ -2476,8 +2827,7 @@ void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm, const SvtSpli
   const int TT = (n + kMT - 1) / kMT;
   T.begin(ST_GRAM);
   if (bf)
-    hipLaunchKernelGGL(k_gram<kBF16x3>, dim3(xcd_grid(TT * (TT + 1) / 2, ns)), dim3(256), 0, s, L.desc, L.slices, L.gram,
-                       TT * (TT + 1) / 2, ns, L.halt);
+    launch_gram_bf16(L, s);
   else
     hipLaunchKernelGGL(k_gram<kF32>, dim3(xcd_grid(TT * (TT + 1) / 2, ns)), dim3(256), 0, s, L.desc, L.slices, L.gram,
                        TT * (TT + 1) / 2, ns, L.halt);
