@@ -70,6 +70,7 @@ struct SliceLayout {
   int64_t slices_floats = 0, gram_c = 0, v_floats = 0, b_floats = 0, tri_d = 0, xs_d = 0, f_floats = 0,
           wy_floats = 0;
   int max_n1 = 0, max_m1 = 0;
+  int min_n1 = 0;   // 0 until a slice is added
 };
 
 // T factors of the blocked back-transform: one 64 x 64 complex block per 64
@@ -115,6 +116,7 @@ SliceLayout make_slices(std::vector<CubeInfo>& cubes, int nt) {
       }
     L.slices_floats += (int64_t)nt * s * 2 * hw;
     if (n1 > L.max_n1) L.max_n1 = n1;
+    if (L.min_n1 == 0 || n1 < L.min_n1) L.min_n1 = n1;
     if (m1 > L.max_m1) L.max_m1 = m1;
   }
   return L;
@@ -301,6 +303,7 @@ static void plan_tucker(lrstv_handle_s* H) {
       L.wy_floats += wy_block_floats(n);
       L.desc.push_back(sd);
       if (n > L.max_n1) L.max_n1 = n;
+      if (L.min_n1 == 0 || n < L.min_n1) L.min_n1 = n;
       if (n > L.max_m1) L.max_m1 = n;
     }
   for (int c = 0; c < nc; ++c) {
@@ -629,6 +632,7 @@ static void tucker_eig(lrstv_handle_s* H, int mode, hipStream_t s) {
   L.desc = H->tdesc + (mode < 0 ? 0 : mode * nc);
   L.n_slices = mode < 0 ? 3 * nc : nc;
   L.max_n1 = H->tsl.max_n1;
+  L.min_n1 = H->tsl.min_n1;
   L.max_m1 = H->tsl.max_m1;
   L.slices = nullptr;
   L.gram = H->tgram;
@@ -732,6 +736,7 @@ static void run_iteration(lrstv_handle_s* H, double* res_user) {
   sv.desc = H->desc;
   sv.n_slices = (int)H->sl.desc.size();
   sv.max_n1 = H->sl.max_n1;
+  sv.min_n1 = H->sl.min_n1;
   sv.max_m1 = H->sl.max_m1;
   sv.slices = H->slices;
   sv.gram = H->gram;
@@ -1114,6 +1119,7 @@ extern "C" int lrstv_iterate_vjp(lrstv_handle H, const lrstv_state_view* before,
   J.fw.desc = H->desc;
   J.fw.n_slices = (int)H->sl.desc.size();
   J.fw.max_n1 = H->sl.max_n1;
+  J.fw.min_n1 = H->sl.min_n1;
   J.fw.max_m1 = H->sl.max_m1;
   J.fw.slices = H->slices;
   J.fw.gram = H->gram;
@@ -1288,6 +1294,7 @@ extern "C" int lrstv_svt(const float* A, float* E, int32_t h, int32_t w, int32_t
   sv.desc = ws.desc;
   sv.n_slices = ns;
   sv.max_n1 = L.max_n1;
+  sv.min_n1 = L.min_n1;
   sv.max_m1 = L.max_m1;
   sv.slices = ws.slices;
   sv.gram = ws.gram;
@@ -1358,6 +1365,7 @@ extern "C" int lrstv_svt_vjp(const float* A, const float* G, float* gA, int32_t 
   J.fw.desc = sw.desc;
   J.fw.n_slices = ns;
   J.fw.max_n1 = L.max_n1;
+  J.fw.min_n1 = L.min_n1;
   J.fw.max_m1 = L.max_m1;
   J.fw.slices = sw.slices;
   J.fw.gram = sw.gram;
@@ -1488,6 +1496,7 @@ static SvtLaunch handle_svt(lrstv_handle_s* H) {
   sv.desc = H->desc;
   sv.n_slices = (int)H->sl.desc.size();
   sv.max_n1 = H->sl.max_n1;
+  sv.min_n1 = H->sl.min_n1;
   sv.max_m1 = H->sl.max_m1;
   sv.slices = H->slices;
   sv.gram = H->gram;

@@ -1111,11 +1111,15 @@ LRSTV_DEV MtRefl mt_reflector(double nx2, float2 x0) {
   return f;
 }
 
-template <int NW, int TPW>
-__global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __restrict__ desc,
-                                                         float2* __restrict__ gram, double* __restrict__ tri, const int* __restrict__ halt) {
-  constexpr int NMAX = 256, NDW = NMAX / 64;   // waves of D, one index per thread
-  static_assert(NW * TPW >= 36, "the 36 lower tiles of a 256 x 256 Gram");
+// NMAX: the largest n of the shape (256, or 128 for a 4-wave block of
+// which three fit a CU); the launch takes the slices with nmin < n <= NMAX.
+template <int NW, int TPW, int NMAX = 256>
+__global__ void __launch_bounds__(64 * NW, NMAX == 256 ? 1 : 3) k_tridiag_mfma(const SliceDesc* __restrict__ desc,
+                                                         float2* __restrict__ gram, double* __restrict__ tri,
+                                                         const int* __restrict__ halt, int nmin) {
+  constexpr int NDW = NMAX / 64;   // waves of D, one index per thread
+  constexpr int NTM = NMAX / 32;
+  static_assert(NMAX % 64 == 0 && NW * TPW >= NTM * (NTM + 1) / 2, "the lower 32 x 32 tiles of an NMAX x NMAX Gram");
   static_assert(NW >= NDW, "one index per thread in D");
   // columns i, i+1 (by step parity) and i+2 of the current matrix
   __shared__ float2 xb[2][NMAX], ab[2][NMAX], bb[NMAX];
@@ -1128,7 +1132,7 @@ __global__ void __launch_bounds__(64 * NW) k_tridiag_mfma(const SliceDesc* __res
   const SliceDesc d = desc[blockIdx.x];
   if (halt && halt[d.cube]) return;   // the cube has met its stopping test
   const int n = d.n1;
-  if (n <= 0) return;
+  if (n <= nmin || n > NMAX) return;   // another launch takes it (nmin >= 0)
   const int NT = (n + 31) >> 5, ntile = NT * (NT + 1) / 2;
   float2* gA = gram + d.g_off;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -2703,8 +2707,21 @@ void launch_svt_tridiag(const SvtLaunch& L, hipStream_t s) {
       case 0: hipLaunchKernelGGL((k_tridiag_reg<10, 8>), dim3(ns), dim3(512), lds, s, L.desc, L.gram, L.tri, L.halt); break;
       case 1: hipLaunchKernelGGL((k_tridiag_reg<7, 12>), dim3(ns), dim3(768), lds, s, L.desc, L.gram, L.tri, L.halt); break;
       case 2: hipLaunchKernelGGL((k_tridiag_reg<6, 16>), dim3(ns), dim3(1024), lds, s, L.desc, L.gram, L.tri, L.halt); break;
-      case 3: hipLaunchKernelGGL((k_tridiag_mfma<12, 3>), dim3(ns), dim3(768), 0, s, L.desc, L.gram, L.tri, L.halt); break;
-      default: hipLaunchKernelGGL((k_tridiag_mfma<8, 5>), dim3(ns), dim3(512), 0, s, L.desc, L.gram, L.tri, L.halt); break;
+      default: {
+        // Slices with n <= 128 take a 4-wave block (three per CU: their
+        // per-step latencies overlap), the others the tuned shape.
+        const bool small = L.min_n1 <= kTriSmallN;
+        if (small)
+          hipLaunchKernelGGL((k_tridiag_mfma<4, 3, kTriSmallN>), dim3(ns), dim3(256), 0, s, L.desc, L.gram, L.tri,
+                             L.halt, 0);
+        if (n <= kTriSmallN) break;
+        const int nmin = small ? kTriSmallN : 0;
+        if (v == 3)
+          hipLaunchKernelGGL((k_tridiag_mfma<12, 3>), dim3(ns), dim3(768), 0, s, L.desc, L.gram, L.tri, L.halt, nmin);
+        else
+          hipLaunchKernelGGL((k_tridiag_mfma<8, 5>), dim3(ns), dim3(512), 0, s, L.desc, L.gram, L.tri, L.halt, nmin);
+        break;
+      }
     }
   } else {
     hipLaunchKernelGGL(k_tridiag<false>, dim3(ns), dim3(256), (size_t)(2 + 4) * n * sizeof(float2), s, L.desc,

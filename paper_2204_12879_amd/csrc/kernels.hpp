@@ -144,6 +144,7 @@ void launch_band_idft(const float* slices, int n_t, float* E, int64_t e_stride, 
 // --- slice SVT ------------------------------------------------------------
 constexpr int kTriVariants = 5;   // tridiagonalisation shapes (codes 8, 12, 16, 112, 108)
 constexpr int kTriDefault = 3;   // 112: register tiles, 12 waves (the tuned shape at 256 x 256)
+constexpr int kTriSmallN = 128;  // slices up to this n take the 4-wave register-tile block
 int tri_variant_code(int v);      // 100 kind + waves
 bool tri_variant_onchip(int v, int n);
 // thresh: t = alpha / mu read on the device (mu != NULL) or the fixed value.
@@ -151,6 +152,7 @@ struct SvtLaunch {
   const SliceDesc* desc;   // device array [n_slices]
   int n_slices;
   int max_n1, max_m1;      // over slices
+  int min_n1 = 0;          // over slices (0: not known)
   float* slices;           // base of the slice planes (input M, output E_hat)
   float2* gram;            // packed Grams / reflectors
   float* V;                // eigenvectors (planar)

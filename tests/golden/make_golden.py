@@ -5,7 +5,9 @@ on the float32-rounded noisy cube and stores X = L^(K) at 20000 seeded voxel
 indices, the full-cube norms and MPSNR, so GPU runs at full size can be
 checked on samples the oracle computed.
 
-    python tests/golden/make_golden.py wdc pavia
+    python tests/golden/make_golden.py wdc pavia ragged
+
+(ragged: the three largest cubes of the 32-cube ragged workload.)
 """
 import os
 import sys
@@ -39,6 +41,32 @@ def make(name: str, nsamp: int = 20000) -> None:
           flush=True)
 
 
+def make_ragged(count: int = 3, nsamp: int = 20000) -> None:
+    """The `count` largest cubes of the 32-cube ragged workload, each run
+    alone by the oracle (a cube's iterates do not depend on the others of a
+    batch), with the batch's parameters (lambda = 10 / sqrt(100 * 100))."""
+    wl = synth.workload("ragged")
+    order = np.argsort([s.h * s.w * s.b for s in wl.cubes])[::-1][:count]
+    p = oracle.Params(tau=0.02, alpha=0.3, lam=10.0 / np.sqrt(100 * 100))
+    rng = np.random.Generator(np.random.PCG64(2025))
+    out = {"cube_index": np.asarray(order), "index": [], "values": [], "x_norm": [], "mpsnr": []}
+    for i in order:
+        spec = wl.cubes[int(i)]
+        clean, noisy = synth.make_cube(spec)
+        O = noisy.astype(np.float32).astype(np.float64)
+        t0 = time.time()
+        X, _, _, _ = oracle.admm(O, p, wl.iters)
+        idx = np.sort(rng.choice(X.size, size=nsamp, replace=False))
+        out["index"].append(idx)
+        out["values"].append(X.ravel()[idx])
+        out["x_norm"].append(np.linalg.norm(X))
+        out["mpsnr"].append(oracle.mpsnr(X, clean))
+        print(f"ragged cube {int(i)}: {spec.b}x{spec.h}x{spec.w} K={wl.iters} in {time.time() - t0:.0f} s, "
+              f"MPSNR {out['mpsnr'][-1]:.3f} dB", flush=True)
+    np.savez_compressed(os.path.join(HERE, f"ragged_k{wl.iters}_largest_oracle_samples.npz"),
+                        **{k: np.asarray(v) for k, v in out.items()})
+
+
 if __name__ == "__main__":
-    for n in sys.argv[1:] or ["wdc", "pavia"]:
-        make(n)
+    for n in sys.argv[1:] or ["wdc", "pavia", "ragged"]:
+        make_ragged() if n == "ragged" else make(n)

@@ -5,7 +5,8 @@
   cube or slice is independent of the others).
 * Iterations replayed from a captured hipGraph are bit-identical to eager
   launches, also when eager work and synchronisations run between replays.
-* A few cubes of the 32-cube ragged workload match the FP64 oracle.
+* A few cubes of the 32-cube ragged workload match the FP64 oracle: the three
+  smallest in full, the three largest (run in the whole batch) at stored samples.
 * The t-SVT of a cube is the same alone and in a larger batch, whose
   eigenvalue launch takes another search (trisection instead of 5-section):
   the eigenvalues are stored canonically, independent of the search path.
@@ -122,6 +123,27 @@ def test_ragged_cubes_match_oracle(idx):
     dps = abs(oracle.mpsnr(Xg.astype(np.float64), clean) - oracle.mpsnr(Xr, clean))
     say(f"rel err {err:.3e} dMPSNR {dps:.2e}")
     assert err <= 1e-4 and dps <= 0.01
+
+
+def test_ragged_workload_largest_cubes_match_stored_oracle_samples():
+    """The whole 32-cube ragged batch, 30 iterations in one handle: the three
+    largest cubes at the stored oracle voxels within 1e-4 relative and
+    |dMPSNR| <= 0.01 dB (samples written by tests/golden/make_golden.py)."""
+    import os
+    L = _lib()
+    gold = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                "ragged_k30_largest_oracle_samples.npz"))
+    wl = synth.workload("ragged")
+    pairs = [synth.make_cube(s) for s in wl.cubes]
+    Xs = _run(L, [nz for _, nz in pairs], wl.iters, (100, 100), graph=True)
+    for j, ci in enumerate(gold["cube_index"]):
+        spec = wl.cubes[int(ci)]
+        Xg = Xs[int(ci)].astype(np.float64)
+        err = float(np.linalg.norm(Xg.ravel()[gold["index"][j]] - gold["values"][j]) /
+                    np.linalg.norm(gold["values"][j]))
+        dps = abs(oracle.mpsnr(Xg, pairs[int(ci)][0]) - float(gold["mpsnr"][j]))
+        say(f"ragged cube {int(ci)} {spec.b}x{spec.h}x{spec.w}: sampled rel err {err:.3e}, dMPSNR {dps:.2e}")
+        assert err <= 1e-4 and dps <= 0.01
 
 
 def test_svt_same_alone_and_in_a_larger_launch():

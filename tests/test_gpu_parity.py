@@ -56,6 +56,8 @@ def say(*a):
     ((3, 17, 128), (1.0, 0.5, 1.0), 0.8),      # (odd row counts: the last row pair has one row)
     ((2, 12, 256), (1.0, 1.0, 1.0), 3.0),
     ((6, 64, 128), (1.0, 1.0, 1.0), 1.0),      # both axes in registers
+    ((4, 149, 97), (1.0, 1.0, 1.0), 1.2),      # large prime lengths on both spatial axes (direct stages)
+    ((3, 58, 146), (0.5, 1.0, 1.0), 0.9),      # twice a prime (a radix-2 stage, then a direct one)
 ])
 def test_zsolve_matches_oracle(shape, wts, mu):
     L = _lib()
