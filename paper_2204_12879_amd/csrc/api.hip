@@ -440,7 +440,7 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
   const int nc = (int)H->cubes.size();
   std::vector<CubeGeo> geo(nc);
   std::vector<int> bstart((size_t)PH_COUNT * (nc + 1), 0);
-  size_t lds_w = 0, lds_h = 0;
+  size_t lds_w = 0, lds_h = 0, lds_wi = 0;
   int max_b = 0, reg_h_mask = 0, stockham_h = 0, reg_w_mask = 0, stockham_w = 0;
   for (int c = 0; c < nc; ++c) {
     const CubeInfo& ci = H->cubes[c];
@@ -449,11 +449,14 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
     g.w = ci.w;
     g.b = ci.b;
     g.nb_w = geo_rows_nb(ci.w);
+    g.nb_wi = geo_rows_nb_inv(ci.w);
     g.cw_h = geo_cols_cw(ci.h);
     g.off = ci.off;
     g.spec_off = ci.spec_off;
     g.slice_base = ci.slice_base;
     const size_t lw = (size_t)(2 * g.nb_w + 1) * ci.w * sizeof(float2);
+    const size_t lwi = (size_t)(2 * g.nb_wi + 1) * ci.w * sizeof(float2);
+    if (lwi > lds_wi) lds_wi = lwi;
     const size_t lh = geo_fft_h_lds(ci.h);
     if (lw > lds_w) lds_w = lw;
     if (lh > lds_h) lds_h = lh;
@@ -472,6 +475,7 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
     bt.nc = nc;
     bt.nblocks = bstart[(size_t)ph * (nc + 1) + nc];
     bt.lds_w = lds_w;
+    bt.lds_wi = lds_wi;
     bt.lds_h = lds_h;
     bt.max_b = max_b;
     bt.reg_h_mask = reg_h_mask;

@@ -82,13 +82,17 @@ LRSTV_DEV void small_dft(float2* v, const float2* tw, int N, int sign) {
     v[1] = cadd(d02, rot);
     v[3] = csub(d02, rot);
   } else {
-    float2 o[R];
+    // the R-th roots read once; (q s) mod R is a constant of the unrolled loops
+    float2 wr[R];
     const int step = N / R;
+#pragma unroll
+    for (int j = 1; j < R; ++j) wr[j] = twid(tw, j * step, sign);
+    float2 o[R];
 #pragma unroll
     for (int s = 0; s < R; ++s) {
       float2 acc = v[0];
 #pragma unroll
-      for (int q = 1; q < R; ++q) acc = cadd(acc, cmul(v[q], twid(tw, ((q * s) % R) * step, sign)));
+      for (int q = 1; q < R; ++q) acc = (q * s) % R == 0 ? cadd(acc, v[q]) : cadd(acc, cmul(v[q], wr[(q * s) % R]));
       o[s] = acc;
     }
 #pragma unroll
@@ -118,26 +122,35 @@ LRSTV_DEV void stage_small(const float2* src, float2* dst, int N, int ld, int nb
   }
 }
 
-// Direct DFT stage for a prime factor R > 7: one output per thread.
+// Direct DFT stage for a prime factor R > 7.  Outputs so and R - so of one
+// butterfly share the input reads, the input twiddles and the root read
+// (w^(q (R - so)) = conj(w^(q so))): a thread forms both.
 LRSTV_DEV void stage_generic(const float2* src, float2* dst, int N, int ld, int nb, int Ns, int R, const float2* tw,
                              int sign) {
-  const int NR = N / R;
+  const int NR = N / R, H = (R + 1) / 2, per = NR * H;
   const int tstep = N / (Ns * R), ostep = N / R;
-  for (int t = threadIdx.x; t < nb * N; t += blockDim.x) {
-    const int f = t / N, o = t - f * N;
-    const int k = o % Ns, so = (o / Ns) % R, jd = o / (Ns * R);
-    const int j = jd * Ns + k;
+  for (int t = threadIdx.x; t < nb * per; t += blockDim.x) {
+    const int f = t / per, rem = t - f * per;
+    const int so = rem / NR, j = rem - so * NR;   // j = jd Ns + k
+    const int k = j % Ns, jd = j / Ns;
     const float2* s = src + f * ld;
-    float2 acc = make_float2(0.f, 0.f);
+    float2 p = make_float2(0.f, 0.f), m = make_float2(0.f, 0.f);   // X_so, X_(R-so)
     int oi = 0;  // (q * so) mod R
     for (int q = 0; q < R; ++q) {
       float2 a = s[j + q * NR];
       if (q > 0 && k > 0) a = cmul(a, twid(tw, q * k * tstep, sign));
-      acc = cadd(acc, cmul(a, twid(tw, oi * ostep, sign)));
+      const float2 w = twid(tw, oi * ostep, sign);
+      const float rr = a.x * w.x, ii = a.y * w.y, ri = a.x * w.y, ir = a.y * w.x;
+      p.x += rr - ii;
+      p.y += ri + ir;
+      m.x += rr + ii;
+      m.y += ir - ri;
       oi += so;
       if (oi >= R) oi -= R;
     }
-    dst[f * ld + o] = acc;
+    float2* d = dst + f * ld + jd * Ns * R + k;
+    d[so * Ns] = p;
+    if (so > 0) d[(R - so) * Ns] = m;
   }
 }
 
@@ -1058,7 +1071,7 @@ __global__ void __launch_bounds__(kIrfftThreads) k_irfft_w_batch(BatchTab bt, co
   if (cube_halted(bt, c)) return;
   const CubeGeo g = uniform_geo(bt.geo, c);
   if (fft_h_reg_bit(g.w) != 0) return;   // that cube runs the register transform
-  irfft_w_body(blockIdx.x - c * LRSTV_PARTS, LRSTV_PARTS, sm, spec + g.spec_off, Z + g.off, g.h * g.b, g.w, g.nb_w,
+  irfft_w_body(blockIdx.x - c * LRSTV_PARTS, LRSTV_PARTS, sm, spec + g.spec_off, Z + g.off, g.h * g.b, g.w, g.nb_wi,
                1.0f / ((float)g.h * (float)g.w), part ? part + (int64_t)c * R_COUNT * LRSTV_PARTS : nullptr);
 }
 
@@ -1104,6 +1117,14 @@ __global__ void __launch_bounds__(256, 2) k_band_idft_batch(BatchTab bt, const f
 static int rows_nb(int w) {
   int nb = 8;
   while (nb > 1 && (2 * nb + 1) * w * 8 > 48 * 1024) nb >>= 1;
+  return nb;
+}
+// The inverse runs LRSTV_PARTS blocks of 1024 threads per cube: up to 32
+// row pairs per pass (within 64 KB of LDS), so that a pass's butterflies
+// reach most of the block's threads.
+static int rows_nb_inv(int w) {
+  int nb = 32;
+  while (nb > 1 && (2 * nb + 1) * w * 8 > 64 * 1024) nb >>= 1;
   return nb;
 }
 
@@ -1201,7 +1222,7 @@ void launch_rfft_w(const float* T, float2* spec, int h, int w, int b, hipStream_
 }
 
 void launch_irfft_w(const float2* spec, float* Z, int h, int w, int b, double* part, hipStream_t s) {
-  const int nrows = h * b, nb = rows_nb(w);
+  const int nrows = h * b, nb = rows_nb_inv(w);
   const size_t lds = (size_t)(2 * nb + 1) * w * sizeof(float2);
   const float scale = 1.0f / ((float)h * (float)w);
   if (launch_irfft_w_reg(spec, Z, w, nrows, scale, part, nullptr, s)) return;
@@ -1328,6 +1349,7 @@ int phase_blocks(int phase, int h, int w, int b) {
 }
 
 int geo_rows_nb(int w) { return rows_nb(w); }
+int geo_rows_nb_inv(int w) { return rows_nb_inv(w); }
 int geo_cols_cw(int h) { return cols_cw(h); }
 size_t geo_fft_h_lds(int h) { return fft_h_lds_bytes(h, cols_cw(h)); }
 
@@ -1342,7 +1364,7 @@ void launch_irfft_w_batch(const BatchTab& bt, const float2* spec, float* Z, doub
   for (int w : {64, 128, 256})
     if (bt.reg_w_mask & fft_h_reg_bit(w)) launch_irfft_w_reg(spec, Z, w, 0, 0.f, part, &bt, s);
   if (bt.stockham_w)
-    hipLaunchKernelGGL(k_irfft_w_batch, dim3(bt.nc * LRSTV_PARTS), dim3(kIrfftThreads), bt.lds_w, s, bt, spec, Z,
+    hipLaunchKernelGGL(k_irfft_w_batch, dim3(bt.nc * LRSTV_PARTS), dim3(kIrfftThreads), bt.lds_wi, s, bt, spec, Z,
                        part);
 }
 

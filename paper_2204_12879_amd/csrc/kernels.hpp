@@ -21,6 +21,7 @@ struct SliceDesc;
 struct CubeGeo {
   int h, w, b;
   int nb_w, cw_h;          // rows per block of the w FFT, columns per block of the h FFT
+  int nb_wi;               // rows per block of the inverse w FFT
   int64_t off;             // element offset of the cube in the packed batch
   int64_t spec_off;        // complex offset of its half spectrum
   int64_t slice_base;      // float offset of its Fourier slices
@@ -32,6 +33,7 @@ struct BatchTab {
   const int* bstart;       // device [nc + 1]
   int nc, nblocks;
   size_t lds_w, lds_h;     // dynamic LDS of the w / h FFT phases (max over cubes)
+  size_t lds_wi;           // and of the inverse w FFT
   int max_b;               // largest band count over cubes
   int reg_h_mask;          // h FFT lengths present that run in registers (bit 0: 64, 1: 128, 2: 256)
   int stockham_h;          // 1 when some cube's h FFT runs through the LDS Stockham path
@@ -69,12 +71,14 @@ __device__ __forceinline__ CubeGeo uniform_geo(const CubeGeo* geo, int c) {
   u.b = __builtin_amdgcn_readfirstlane(g.b);
   u.nb_w = __builtin_amdgcn_readfirstlane(g.nb_w);
   u.cw_h = __builtin_amdgcn_readfirstlane(g.cw_h);
+  u.nb_wi = __builtin_amdgcn_readfirstlane(g.nb_wi);
   u.off = uniform_i64(g.off);
   u.spec_off = uniform_i64(g.spec_off);
   u.slice_base = uniform_i64(g.slice_base);
   return u;
 }
 int geo_rows_nb(int w);
+int geo_rows_nb_inv(int w);
 int geo_cols_cw(int h);
 size_t geo_fft_h_lds(int h);  // dynamic LDS bytes of the h FFT
 void prepare_fft_h(size_t lds);  // grants that LDS to the h FFT kernels
