@@ -105,6 +105,7 @@ SliceLayout make_slices(std::vector<CubeInfo>& cubes, int nt) {
         d.f_off = L.f_floats;
         d.y_off = L.wy_floats;
         d.keep = 0;
+        d.prio = 0;
         L.gram_c += (int64_t)n1 * (n1 + 1) / 2;
         L.v_floats += 2 * (int64_t)n1 * n1;
         L.b_floats += 2 * hw;
@@ -483,6 +484,12 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
     bt.reg_w_mask = reg_w_mask;
     bt.stockham_w = stockham_w;
     bt.halt = H->halt;
+  }
+  // slices beyond the last full round of compute units run their later
+  // stages beside the first group's (see the split below)
+  {
+    const int first = svt_split_point((int)H->sl.desc.size());
+    for (size_t i = first > 0 ? (size_t)first : H->sl.desc.size(); i < H->sl.desc.size(); ++i) H->sl.desc[i].prio = 1;
   }
   hipError_t e = hipMemcpyAsync(H->desc, H->sl.desc.data(), H->sl.desc.size() * sizeof(SliceDesc),
                                 hipMemcpyHostToDevice, H->stream);
@@ -1242,6 +1249,7 @@ __global__ void k_make_desc(SliceDesc* out, int n, int b, int h, int w, int s,
   d.x_off = (int64_t)i * xs_d;
   d.f_off = (int64_t)i * f_f;
   d.y_off = (int64_t)i * y_f;
+  d.prio = 0;
   d.keep = 0;
   out[i] = d;
 }

@@ -161,6 +161,9 @@ struct SliceDesc {
                      // (ceil((n1-1)/64) blocks of 64 x 64 complex, planar)
   int keep;          // > 0: keep the `keep` largest eigenpairs of the matrix
                      // (Tucker projectors) instead of those above the threshold
+  int prio;          // 1: a slice of the group that runs after the first round of
+                     // compute units; its eigen-solve and back-transform waves
+                     // issue at raised priority
 };
 
 }  // namespace lrstv

@@ -1658,6 +1658,7 @@ __global__ void __launch_bounds__(PHASE == 1 ? 64 : (PHASE == 0 ? 256 : 1024)) k
   // block per slice
   const int slice = PHASE == 2 ? blockIdx.x : blockIdx.y;
   const SliceDesc d = desc[slice];
+  if (d.prio) __builtin_amdgcn_s_setprio(3);   // the later group's chain issues first
   if (halt && halt[d.cube]) return;   // the cube has met its stopping test
   const int n = d.n1;
   double* dg = tri + d.t_off;
@@ -2000,6 +2001,7 @@ __global__ void __launch_bounds__(256) k_wy_t(const SliceDesc* __restrict__ desc
   int b, slice;
   if (!xcd_tile_slice(ntile, ns, b, slice)) return;
   const SliceDesc d = desc[slice];
+  if (d.prio) __builtin_amdgcn_s_setprio(3);   // the later group's chain issues first
   if (halt && halt[d.cube]) return;   // the cube has met its stopping test
   const int n = d.n1, nblk = (n - 1 + 63) / 64;
   if (b >= nblk || rcount[slice] == 0) return;
@@ -2107,6 +2109,7 @@ __global__ void __launch_bounds__(256, 3) k_wy_apply(const SliceDesc* __restrict
   int ct, slice;
   if (!xcd_tile_slice(ntile, ns, ct, slice)) return;
   const SliceDesc d = desc[slice];
+  if (d.prio) __builtin_amdgcn_s_setprio(3);   // the later group's chain issues first
   if (halt && halt[d.cube]) return;   // the cube has met its stopping test
   const int n = d.n1, r = rcount[slice], c0 = 64 * ct;
   if (c0 >= r) return;
@@ -2298,6 +2301,7 @@ __global__ void __launch_bounds__(256) k_bp1(const SliceDesc* __restrict__ desc,
   if (!xcd_tile_slice(tdim * tdim, ns, tile, slice)) return;
   const int bx = tile % tdim, by = tile / tdim;
   const SliceDesc d = desc[slice];
+  if (d.prio) __builtin_amdgcn_s_setprio(3);   // the later group's chain issues first
   if (halt && halt[d.cube]) return;   // the cube has met its stopping test
   const int r = rcount[slice], n = d.n1, h = d.h, w = d.w;
   const float* mr = sl + d.a_off;
@@ -2352,6 +2356,7 @@ __global__ void __launch_bounds__(256) k_colnorm(const SliceDesc* __restrict__ d
   // 64 x + 16 q .. + 15, one contiguous row at a time.
   __shared__ double part[4][64];
   const SliceDesc d = desc[blockIdx.y];
+  if (d.prio) __builtin_amdgcn_s_setprio(3);   // the later group's chain issues first
   if (halt && halt[d.cube]) return;   // the cube has met its stopping test
   const int r = rcount[blockIdx.y], c0 = 64 * blockIdx.x;
   if (c0 >= r) return;
@@ -2403,6 +2408,7 @@ __global__ void __launch_bounds__(256, MODE == kF32 ? 4 : 1) k_bp2(const SliceDe
   if (!xcd_tile_slice(tdim * tdim, ns, tile, slice)) return;
   const int bx = tile % tdim, by = tile / tdim;
   const SliceDesc d = desc[slice];
+  if (d.prio) __builtin_amdgcn_s_setprio(3);   // the later group's chain issues first
   if (halt && halt[d.cube]) return;   // the cube has met its stopping test
   const int r = rcount[slice], n = d.n1, h = d.h, w = d.w;
   const int m0 = by * kMT, n0 = bx * kMT;
