@@ -86,7 +86,11 @@ def _slice_sv(A):
 
 
 @pytest.mark.parametrize("shape", [(16, 32, 32), (9, 17, 12), (8, 12, 17), (1, 20, 20), (6, 33, 40),
-                                   (31, 48, 64), (4, 150, 160), (3, 200, 210), (3, 256, 256), (2, 81, 79)])
+                                   (31, 48, 64), (4, 150, 160), (3, 200, 210), (3, 256, 256), (2, 81, 79),
+                                   # the two tridiagonalisation shapes' boundary (n <= 128: 4-wave block)
+                                   (3, 128, 130), (3, 129, 129),
+                                   # slices of one and two rows
+                                   (2, 1, 7), (2, 40, 2)])
 def test_svt_matches_oracle(shape):
     L = _lib()
     A = _lowrank_tensor(shape, rank=4, seed=shape[1] * 7 + shape[2])
