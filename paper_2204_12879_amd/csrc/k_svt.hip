@@ -1219,12 +1219,16 @@ __global__ void __launch_bounds__(64 * NW, NMAX == 256 ? 1 : 3) k_tridiag_mfma(c
     }
   }
   __syncthreads();
-  // The reflector of a step is computed by the waves of D only (they have
-  // the fewest tiles): the other waves never need it, since without a
+  // The reflector of a step is needed by the waves of D only: without a
   // reflection D writes v = w = 0, so that C's products are discarded and E
   // adds zeros.  That of step i + 1 is formed right after the barrier that
-  // ends D of step i, before these waves issue their share of E, so that
-  // the waves with the most tiles issue theirs first.
+  // ends D of step i by one wave outside D that has slack in C (WR: with 12
+  // waves, wave 9, whose tiles include two diagonal ones) and passed to D
+  // through LDS, so that it is off the path of the waves of D (D, then
+  // their share of E and C); with every wave in D (4-wave shape) the waves
+  // of D form it themselves.
+  constexpr int WR = NW == 12 ? 9 : (NW > NDW ? NW - 1 : -1);
+  __shared__ MtRefl s_f;
   MtRefl f{};
   auto next_reflector = [&](int pr, int i1) {
     double nx2 = 0.0;
@@ -1232,7 +1236,15 @@ __global__ void __launch_bounds__(64 * NW, NMAX == 256 ? 1 : 3) k_tridiag_mfma(c
     for (int q = 0; q < NDW; ++q) nx2 += red_nx[pr][q];
     return mt_reflector(uniform_d(nx2), make_float2(uniform_f(xb[pr][i1].x), uniform_f(xb[pr][i1].y)));
   };
-  if (wv < NDW && n > 1) f = next_reflector(0, 1);
+  auto form_reflector = [&](int pr, int i1) {
+    if (WR < 0) {
+      if (wv < NDW) f = next_reflector(pr, i1);
+    } else if (wv == WR) {
+      const MtRefl g = next_reflector(pr, i1);
+      if ((threadIdx.x & 63) == 0) s_f = g;
+    }
+  };
+  if (n > 1) form_reflector(0, 1);
   // Issue priority by share of tiles: the waves holding the most tiles set
   // the length of the product and update phases, the waves of D have slack
   // there (the tile dealing gives waves 8-11 the most).
@@ -1310,6 +1322,18 @@ __global__ void __launch_bounds__(64 * NW, NMAX == 256 ? 1 : 3) k_tridiag_mfma(c
     // Without a reflection v and w are zero (selects, so that stale partial
     // sums do not enter).
     if (wv < NDW) {
+      if (WR >= 0) {
+        const MtRefl g = s_f;
+        f.ax0 = uniform_f(g.ax0);
+        f.pr = uniform_f(g.pr);
+        f.pim = uniform_f(g.pim);
+        f.nx = uniform_f(g.nx);
+        f.tau = uniform_f(g.tau);
+        f.gam = uniform_f(g.gam);
+        f.scl = make_float2(uniform_f(g.scl.x), uniform_f(g.scl.y));
+        f.refl = __builtin_amdgcn_readfirstlane((int)g.refl) != 0;
+        f.defl = __builtin_amdgcn_readfirstlane((int)g.defl) != 0;
+      }
       const int t = threadIdx.x;
       const int i1 = i + 1, i2 = i + 2 < n ? i + 2 : i + 1;
       // Values equal for every index (the reduced scalars, the partial sums at
@@ -1393,7 +1417,7 @@ __global__ void __launch_bounds__(64 * NW, NMAX == 256 ? 1 : 3) k_tridiag_mfma(c
       }
     }
     lds_barrier();
-    if (wv < NDW && i + 2 < n) f = next_reflector(par ^ 1, i + 2);
+    if (i + 2 < n) form_reflector(par ^ 1, i + 2);
     // ---- E: A -= v w^H + w v^H on the matrix cores ------------------------
     // real part: [-v_R | -w_R] (re in half 0, im in half 1) times [w_C ; v_C];
     // imaginary part: [-Im v, Re v] and [-Im w, Re w] against the same B.
