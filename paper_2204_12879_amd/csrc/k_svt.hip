@@ -1322,18 +1322,10 @@ __global__ void __launch_bounds__(64 * NW, NMAX == 256 ? 1 : 3) k_tridiag_mfma(c
     // Without a reflection v and w are zero (selects, so that stale partial
     // sums do not enter).
     if (wv < NDW) {
-      if (WR >= 0) {
-        const MtRefl g = s_f;
-        f.ax0 = uniform_f(g.ax0);
-        f.pr = uniform_f(g.pr);
-        f.pim = uniform_f(g.pim);
-        f.nx = uniform_f(g.nx);
-        f.tau = uniform_f(g.tau);
-        f.gam = uniform_f(g.gam);
-        f.scl = make_float2(uniform_f(g.scl.x), uniform_f(g.scl.y));
-        f.refl = __builtin_amdgcn_readfirstlane((int)g.refl) != 0;
-        f.defl = __builtin_amdgcn_readfirstlane((int)g.defl) != 0;
-      }
+      // the reflector formed outside D: read here, made uniform where it is
+      // first used (after the partial sums' reads are in flight)
+      MtRefl fs{};
+      if (WR >= 0) fs = s_f;
       const int t = threadIdx.x;
       const int i1 = i + 1, i2 = i + 2 < n ? i + 2 : i + 1;
       // Values equal for every index (the reduced scalars, the partial sums at
@@ -1359,6 +1351,17 @@ __global__ void __launch_bounds__(64 * NW, NMAX == 256 ? 1 : 3) k_tridiag_mfma(c
 #pragma unroll
       for (int q = 0; q < NW; ++q) St = cadd(St, P[q][t]);
       const float2 at = av[t], xt = xv[t], bt = bb[t];
+      if (WR >= 0) {
+        f.ax0 = uniform_f(fs.ax0);
+        f.pr = uniform_f(fs.pr);
+        f.pim = uniform_f(fs.pim);
+        f.nx = uniform_f(fs.nx);
+        f.tau = uniform_f(fs.tau);
+        f.gam = uniform_f(fs.gam);
+        f.scl = make_float2(uniform_f(fs.scl.x), uniform_f(fs.scl.y));
+        f.refl = __builtin_amdgcn_readfirstlane((int)fs.refl) != 0;
+        f.defl = __builtin_amdgcn_readfirstlane((int)fs.defl) != 0;
+      }
       const double sr = f.scl.x, si = f.scl.y;
       const double gd = f.gam, td = f.tau;
       const double vAv = (sr * sr + si * si) * xAx + 2.0 * gd * (sr * xar + si * xai) + gd * gd * (double)a1.x;
