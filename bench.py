@@ -388,6 +388,10 @@ def main():
                       args.no_tune, k_run)
         gms = b16["stages"]["gram"][0] / args.steps
         hw_flops = 3.0 * gflop   # three BF16 products (hi*hi, hi*lo, lo*hi) per FP32-equivalent product
+        # products the split-BF16 Gram issues: 128 x 128 tiles over the lower
+        # triangle, diagonal tiles whole (as rocprofv3's MFMA counters count them)
+        issued = sum(3 * (b // 2 + 1) * (-(-min(h, w) // 128)) * (-(-min(h, w) // 128) + 1) // 2
+                     * 3 * 8.0 * 128 * 128 * max(h, w) for b, h, w in shapes)
         out["split_bf16"] = {
             "value": args.steps / b16["elapsed"], "unit": "iters/s",
             "ms_per_step": 1e3 * b16["elapsed"] / args.steps,
@@ -396,6 +400,7 @@ def main():
             "gram_tflops_fp32_equiv": gflop / (gms * 1e-3) / 1e12 if gms > 0 else None,
             "gram_bf16_hw_tflops": hw_flops / (gms * 1e-3) / 1e12 if gms > 0 else None,
             "gram_bf16_frac_of_peak": hw_flops / (gms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS if gms > 0 else None,
+            "gram_bf16_issued_frac_of_peak": issued / (gms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS if gms > 0 else None,
             "stage_ms_per_iter": {k: round(v[0] / args.steps, 4) for k, v in b16["stages"].items()},
             "window": f"iterations {k_run - args.steps + 1}..{k_run} of {k_run}, same as the FP32 line",
         }
