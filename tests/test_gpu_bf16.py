@@ -57,7 +57,9 @@ def _slice_sv(A):
 @pytest.mark.parametrize("shape", [(16, 32, 32), (9, 17, 12), (8, 12, 17), (6, 33, 40), (31, 48, 64),
                                    (3, 200, 210), (3, 256, 256), (2, 81, 79), (3, 160, 192), (3, 224, 200),
                                    # one diagonal tile (tall, straight-line staging); wide with n = 96
-                                   (3, 128, 128), (3, 96, 256)])
+                                   (3, 128, 128), (3, 96, 256),
+                                   # tall, n = 160 (128 x 128 back-projections), ragged row tiles
+                                   (3, 200, 160)])
 def test_bf16_svt_matches_oracle(shape):
     L = _lib()
     A = _lowrank_tensor(shape, rank=4, seed=shape[1] * 5 + shape[2])
