@@ -6,7 +6,10 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblrstv.so")
-SOURCES = ["api.hip", "k_sweep.hip", "k_fft.hip", "k_svt.hip", "k_vjp.hip", "k_tucker.hip"]
+SOURCES = ["api.hip", "k_sweep.hip", "k_fft.hip", "k_svt.hip", "k_vjp.hip", "k_tucker.hip", "k_dftmm.hip"]
+# Sources compiled on their own with extra flags (then linked with the rest):
+# the DFT-matrix transforms keep their matrix-core accumulators in VGPRs.
+EXTRA = {"k_dftmm.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("LRSTV_ARCH", "gfx950")
 
@@ -23,15 +26,34 @@ SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=unde
             "-shared-libsan"]
 
 
+def _link(out: str, flags: list, verbose: bool, quiet: bool = False) -> None:
+    """Compile the sources with `flags` into the shared library `out`: those
+    with extra flags first into objects beside `out`, then one link."""
+    objs = []
+    for src, extra in EXTRA.items():
+        obj = out + "." + src.replace(".hip", ".o")
+        cmd = [HIPCC] + [f for f in flags if f != "-shared"] + extra + ["-c", "-o", obj, os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True, capture_output=quiet)
+        objs.append(obj)
+    srcs = [os.path.join(CSRC, s) for s in SOURCES if s not in EXTRA]
+    cmd = [HIPCC] + flags + ["-o", out] + srcs + (["-x", "none"] + objs if objs else [])
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    try:
+        subprocess.run(cmd, check=True, capture_output=quiet)
+    finally:
+        for obj in objs:
+            if os.path.exists(obj):
+                os.remove(obj)
+
+
 def build_sanitized(out: str, verbose: bool = False) -> str:
     """Build the library with host ASan + UBSan into `out` (load it with the
     clang ASan runtime preloaded, see asan_runtime())."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    flags = [f for f in FLAGS if f != "-O3"] + ["-O1", "-g"]
-    cmd = [HIPCC] + flags + SANITIZE + ["-o", out] + srcs
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True, capture_output=not verbose)
+    flags = [f for f in FLAGS if f != "-O3"] + ["-O1", "-g"] + SANITIZE
+    _link(out, flags, verbose, quiet=not verbose)
     return out
 
 
@@ -49,12 +71,8 @@ def asan_runtime() -> str:
 
 
 def build(verbose: bool = True) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-o", tmp] + srcs
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    _link(tmp, FLAGS, verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -441,8 +441,8 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
   const int nc = (int)H->cubes.size();
   std::vector<CubeGeo> geo(nc);
   std::vector<int> bstart((size_t)PH_COUNT * (nc + 1), 0);
-  size_t lds_w = 0, lds_h = 0, lds_wi = 0;
-  int max_b = 0, reg_h_mask = 0, stockham_h = 0, reg_w_mask = 0, stockham_w = 0;
+  size_t lds_w = 0, lds_h = 0, lds_wi = 0, lds_mm_h = 0, lds_mm_w = 0, lds_mm_wi = 0;
+  int max_b = 0, reg_h_mask = 0, stockham_h = 0, reg_w_mask = 0, stockham_w = 0, mm_h = 0, mm_w = 0;
   for (int c = 0; c < nc; ++c) {
     const CubeInfo& ci = H->cubes[c];
     CubeGeo& g = geo[c];
@@ -462,10 +462,23 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
     if (lw > lds_w) lds_w = lw;
     if (lh > lds_h) lds_h = lh;
     if (ci.b > max_b) max_b = ci.b;
+    const bool mh = dft_mm_len(ci.h, kMmMaxH), mw = dft_mm_len(ci.w, kMmMaxW);
+    g.mm = (mh ? 1 : 0) | (mw ? 2 : 0);
     reg_h_mask |= fft_h_reg_bit(ci.h);
-    if (fft_h_reg_bit(ci.h) == 0) stockham_h = 1;
     reg_w_mask |= fft_h_reg_bit(ci.w);
-    if (fft_h_reg_bit(ci.w) == 0) stockham_w = 1;
+    if (mh) {
+      mm_h = 1;
+      if (dftmm_lds_h(ci.h) > lds_mm_h) lds_mm_h = dftmm_lds_h(ci.h);
+    } else if (fft_h_reg_bit(ci.h) == 0) {
+      stockham_h = 1;
+    }
+    if (mw) {
+      mm_w = 1;
+      if (dftmm_lds_w(ci.w) > lds_mm_w) lds_mm_w = dftmm_lds_w(ci.w);
+      if (dftmm_lds_wi(ci.w) > lds_mm_wi) lds_mm_wi = dftmm_lds_wi(ci.w);
+    } else if (fft_h_reg_bit(ci.w) == 0) {
+      stockham_w = 1;
+    }
     for (int ph = 0; ph < PH_COUNT; ++ph)
       bstart[(size_t)ph * (nc + 1) + c + 1] = bstart[(size_t)ph * (nc + 1) + c] + phase_blocks(ph, ci.h, ci.w, ci.b);
   }
@@ -483,6 +496,11 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
     bt.stockham_h = stockham_h;
     bt.reg_w_mask = reg_w_mask;
     bt.stockham_w = stockham_w;
+    bt.mm_h = mm_h;
+    bt.mm_w = mm_w;
+    bt.lds_mm_h = lds_mm_h;
+    bt.lds_mm_w = lds_mm_w;
+    bt.lds_mm_wi = lds_mm_wi;
     bt.halt = H->halt;
   }
   // slices beyond the last full round of compute units run their later

@@ -1043,16 +1043,6 @@ __global__ void __launch_bounds__(256, 2) k_band_idft(const float* __restrict__ 
 // the cube it runs as block b - bstart[c] of a grid of bstart[c+1] - bstart[c]
 // blocks, the grid that cube would get alone (so its results, reductions
 // included, do not depend on the other cubes).
-struct CubeSel {
-  int c, bid, nblk;
-};
-LRSTV_DEV CubeSel select_cube(const BatchTab& bt) {
-  CubeSel r;
-  r.c = __builtin_amdgcn_readfirstlane(find_cube(bt.bstart, bt.nc, blockIdx.x));
-  r.bid = blockIdx.x - __builtin_amdgcn_readfirstlane(bt.bstart[r.c]);
-  r.nblk = __builtin_amdgcn_readfirstlane(bt.bstart[r.c + 1] - bt.bstart[r.c]);
-  return r;
-}
 
 __global__ void __launch_bounds__(256) k_rfft_w_batch(BatchTab bt, const float* __restrict__ T,
                                                       float2* __restrict__ spec) {
@@ -1060,7 +1050,7 @@ __global__ void __launch_bounds__(256) k_rfft_w_batch(BatchTab bt, const float* 
   const CubeSel q = select_cube(bt);
   if (cube_halted(bt, q.c)) return;
   const CubeGeo g = uniform_geo(bt.geo, q.c);
-  if (fft_h_reg_bit(g.w) != 0) return;   // that cube runs the register transform
+  if (fft_h_reg_bit(g.w) != 0 || (g.mm & 2)) return;   // the register or DFT-matrix transform takes it
   rfft_w_body(q.bid, q.nblk, sm, T + g.off, spec + g.spec_off, g.h * g.b, g.w, g.nb_w);
 }
 
@@ -1070,7 +1060,7 @@ __global__ void __launch_bounds__(kIrfftThreads) k_irfft_w_batch(BatchTab bt, co
   const int c = blockIdx.x / LRSTV_PARTS;
   if (cube_halted(bt, c)) return;
   const CubeGeo g = uniform_geo(bt.geo, c);
-  if (fft_h_reg_bit(g.w) != 0) return;   // that cube runs the register transform
+  if (fft_h_reg_bit(g.w) != 0 || (g.mm & 2)) return;   // the register or DFT-matrix transform takes it
   irfft_w_body(blockIdx.x - c * LRSTV_PARTS, LRSTV_PARTS, sm, spec + g.spec_off, Z + g.off, g.h * g.b, g.w, g.nb_wi,
                1.0f / ((float)g.h * (float)g.w), part ? part + (int64_t)c * R_COUNT * LRSTV_PARTS : nullptr);
 }
@@ -1080,7 +1070,7 @@ __global__ void __launch_bounds__(kFftHThreads) k_fft_h_batch(BatchTab bt, float
   const CubeSel q = select_cube(bt);
   if (cube_halted(bt, q.c)) return;
   const CubeGeo g = uniform_geo(bt.geo, q.c);
-  if (fft_h_reg_bit(g.h) != 0) return;   // that cube runs the register FFT
+  if (fft_h_reg_bit(g.h) != 0 || (g.mm & 1)) return;   // the register or DFT-matrix transform takes it
   fft_h_body(q.bid, q.nblk, sm, spec + g.spec_off, g.h, g.w / 2 + 1, g.b, g.cw_h, sign);
 }
 
@@ -1213,6 +1203,10 @@ static bool launch_irfft_w_reg(const float2* spec, float* Z, int w, int nrows, f
 }
 
 void launch_rfft_w(const float* T, float2* spec, int h, int w, int b, hipStream_t s) {
+  if (dft_mm_len(w, kMmMaxW)) {
+    launch_dftmm_rw(T, spec, h, w, b, s);
+    return;
+  }
   if (launch_rfft_w_reg(T, spec, w, h * b, nullptr, s)) return;
   const int nrows = h * b, nb = rows_nb(w);
   const size_t lds = (size_t)(2 * nb + 1) * w * sizeof(float2);
@@ -1222,6 +1216,10 @@ void launch_rfft_w(const float* T, float2* spec, int h, int w, int b, hipStream_
 }
 
 void launch_irfft_w(const float2* spec, float* Z, int h, int w, int b, double* part, hipStream_t s) {
+  if (dft_mm_len(w, kMmMaxW)) {
+    launch_dftmm_irw(spec, Z, h, w, b, part, s);
+    return;
+  }
   const int nrows = h * b, nb = rows_nb_inv(w);
   const size_t lds = (size_t)(2 * nb + 1) * w * sizeof(float2);
   const float scale = 1.0f / ((float)h * (float)w);
@@ -1270,6 +1268,10 @@ void prepare_fft_h(size_t lds) {
 }
 
 void launch_fft_h(float2* spec, int h, int w, int b, int sign, hipStream_t s) {
+  if (dft_mm_len(h, kMmMaxH)) {
+    launch_dftmm_h(spec, h, w, b, sign, s);
+    return;
+  }
   const int wc = w / 2 + 1;
   const int cw = cols_cw(h);
   const int64_t g = ((int64_t)b * wc + cw - 1) / cw;
@@ -1328,11 +1330,13 @@ int phase_blocks(int phase, int h, int w, int b) {
   switch (phase) {
     case PH_LRHS: { const int64_t g = (N + 255) / 256; return (int)(g < 8192 ? g : 8192); }
     case PH_RFFT_W: {
+      if (dft_mm_len(w, kMmMaxW)) return dftmm_blocks_w(h, w, b);
       const int nb = rows_nb(w);
       const int64_t g = ((int64_t)h * b + 2 * nb - 1) / (2 * nb);
       return (int)(g < 4096 ? g : 4096);
     }
     case PH_FFT_H: {
+      if (dft_mm_len(h, kMmMaxH)) return dftmm_blocks_h(h, w, b);
       const int cw = cols_cw(h);
       const int64_t g = ((int64_t)b * wc + cw - 1) / cw;
       return (int)(g < 8192 ? g : 8192);
@@ -1358,6 +1362,7 @@ void launch_rfft_w_batch(const BatchTab& bt, const float* T, float2* spec, hipSt
   for (int w : {64, 128, 256})
     if (bt.reg_w_mask & fft_h_reg_bit(w)) launch_rfft_w_reg(T, spec, w, 0, &bt, s);
   if (bt.stockham_w) hipLaunchKernelGGL(k_rfft_w_batch, dim3(bt.nblocks), dim3(256), bt.lds_w, s, bt, T, spec);
+  if (bt.mm_w) launch_dftmm_rw_batch(bt, T, spec, s);
 }
 
 void launch_irfft_w_batch(const BatchTab& bt, const float2* spec, float* Z, double* part, hipStream_t s) {
@@ -1366,6 +1371,7 @@ void launch_irfft_w_batch(const BatchTab& bt, const float2* spec, float* Z, doub
   if (bt.stockham_w)
     hipLaunchKernelGGL(k_irfft_w_batch, dim3(bt.nc * LRSTV_PARTS), dim3(kIrfftThreads), bt.lds_wi, s, bt, spec, Z,
                        part);
+  if (bt.mm_w) launch_dftmm_irw_batch(bt, spec, Z, part, s);
 }
 
 void launch_fft_h_batch(const BatchTab& bt, float2* spec, int sign, hipStream_t s) {
@@ -1378,6 +1384,7 @@ void launch_fft_h_batch(const BatchTab& bt, float2* spec, int sign, hipStream_t 
     }
   if (bt.stockham_h)
     hipLaunchKernelGGL(k_fft_h_batch, dim3(bt.nblocks), dim3(kFftHThreads), bt.lds_h, s, bt, spec, sign);
+  if (bt.mm_h) launch_dftmm_h_batch(bt, spec, sign, s);
 }
 
 void launch_tri_b_batch(const BatchTab& bt, float2* spec, const double wts[3], const double* mu, hipStream_t s) {

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "common.hpp"
 #include "timer.hpp"
 
 namespace lrstv {
@@ -22,6 +23,8 @@ struct CubeGeo {
   int h, w, b;
   int nb_w, cw_h;          // rows per block of the w FFT, columns per block of the h FFT
   int nb_wi;               // rows per block of the inverse w FFT
+  int mm;                  // bit 0: the h transforms, bit 1: the w transforms run as
+                           // DFT-matrix products (dft_mm_len)
   int64_t off;             // element offset of the cube in the packed batch
   int64_t spec_off;        // complex offset of its half spectrum
   int64_t slice_base;      // float offset of its Fourier slices
@@ -38,6 +41,8 @@ struct BatchTab {
   int reg_h_mask;          // h FFT lengths present that run in registers (bit 0: 64, 1: 128, 2: 256)
   int stockham_h;          // 1 when some cube's h FFT runs through the LDS Stockham path
   int reg_w_mask, stockham_w;   // the same for the w transforms
+  int mm_h, mm_w;          // 1 when some cube's h (w) transforms are DFT-matrix products
+  size_t lds_mm_h, lds_mm_w, lds_mm_wi;   // their dynamic LDS (max over those cubes)
   const int* halt;         // device [nc] or NULL: a cube whose entry is non-zero
                            // has met the stopping test; every phase skips it
 };
@@ -45,6 +50,25 @@ struct BatchTab {
 __device__ __forceinline__ bool cube_halted(const BatchTab& bt, int c) { return bt.halt && bt.halt[c] != 0; }
 // Bit of an FFT length that runs in registers (64, 128, 256), else 0.
 __host__ __device__ inline int fft_h_reg_bit(int h) { return h == 64 ? 1 : h == 128 ? 2 : h == 256 ? 4 : 0; }
+// Lengths whose transform along h (up to 192) or w (up to 256) runs as a
+// product with the DFT matrix on the matrix cores instead of the Stockham
+// FFT: those with a prime factor p >= 17, or p = 11, 13 and n <= 144 (the
+// Stockham direct-DFT stage costs O(p) LDS reads per element; the product
+// O(n) matrix-core flops).  Measured per length (Z-solve of 100 bands): the
+// product is faster for 77, 78, 88, 91, 110, 121, 143 and every p >= 17,
+// the FFT for smooth lengths from 80 up and for 156.
+constexpr int kMmMaxH = 192, kMmMaxW = 256, kMmMinPrime = 17, kMmMidPrime = 11, kMmMidMax = 144;
+inline bool dft_mm_len(int n, int nmax) {
+  if (n > nmax || fft_h_reg_bit(n) != 0) return false;
+  int p = 1, m = n;
+  for (int d = 2; d * d <= m; ++d)
+    while (m % d == 0) {
+      p = d;
+      m /= d;
+    }
+  if (m > 1) p = m;
+  return p >= kMmMinPrime || (p >= kMmMidPrime && n <= kMmMidMax);
+}
 // Base pointers of the packed batch (gradient-shaped arrays and A: 3
 // components spaced by ts).
 struct BatchPtrs {
@@ -72,15 +96,34 @@ __device__ __forceinline__ CubeGeo uniform_geo(const CubeGeo* geo, int c) {
   u.nb_w = __builtin_amdgcn_readfirstlane(g.nb_w);
   u.cw_h = __builtin_amdgcn_readfirstlane(g.cw_h);
   u.nb_wi = __builtin_amdgcn_readfirstlane(g.nb_wi);
+  u.mm = __builtin_amdgcn_readfirstlane(g.mm);
   u.off = uniform_i64(g.off);
   u.spec_off = uniform_i64(g.spec_off);
   u.slice_base = uniform_i64(g.slice_base);
   return u;
 }
+// The cube owning block blockIdx.x of a batched launch, and the block's index
+// within that cube's own grid.
+struct CubeSel {
+  int c, bid, nblk;
+};
+__device__ __forceinline__ CubeSel select_cube(const BatchTab& bt) {
+  CubeSel r;
+  r.c = __builtin_amdgcn_readfirstlane(find_cube(bt.bstart, bt.nc, blockIdx.x));
+  r.bid = blockIdx.x - __builtin_amdgcn_readfirstlane(bt.bstart[r.c]);
+  r.nblk = __builtin_amdgcn_readfirstlane(bt.bstart[r.c + 1] - bt.bstart[r.c]);
+  return r;
+}
 int geo_rows_nb(int w);
 int geo_rows_nb_inv(int w);
 int geo_cols_cw(int h);
 size_t geo_fft_h_lds(int h);  // dynamic LDS bytes of the h FFT
+// dynamic LDS bytes of the DFT-matrix transforms along h, w (forward), w (inverse)
+size_t dftmm_lds_h(int h);
+size_t dftmm_lds_w(int w);
+size_t dftmm_lds_wi(int w);
+int dftmm_blocks_h(int h, int w, int b);   // per-cube blocks of the h transform
+int dftmm_blocks_w(int h, int w, int b);   // and of the forward w transform
 void prepare_fft_h(size_t lds);  // grants that LDS to the h FFT kernels
 
 // One cube's pointers for the adjoint of an iteration (all offset to the
@@ -136,6 +179,14 @@ void launch_tri_b(float2* spec, int h, int w, int b, const double wts[3], const 
                   hipStream_t s);
 // Z <- irfft; if part != NULL also writes sum (Z_new - Z_old)^2 partials (slot R_DUAL_Z).
 void launch_irfft_w(const float2* spec, float* Z, int h, int w, int b, double* part, hipStream_t s);
+// The same transforms as DFT-matrix products (lengths with dft_mm_len); the
+// batched forms take the cubes whose CubeGeo::mm bit is set.
+void launch_dftmm_rw(const float* T, float2* spec, int h, int w, int b, hipStream_t s);
+void launch_dftmm_h(float2* spec, int h, int w, int b, int sign, hipStream_t s);
+void launch_dftmm_irw(const float2* spec, float* Z, int h, int w, int b, double* part, hipStream_t s);
+void launch_dftmm_rw_batch(const BatchTab& bt, const float* T, float2* spec, hipStream_t s);
+void launch_dftmm_h_batch(const BatchTab& bt, float2* spec, int sign, hipStream_t s);
+void launch_dftmm_irw_batch(const BatchTab& bt, const float2* spec, float* Z, double* part, hipStream_t s);
 
 // --- band DFT (t-SVT forward) and inverse (+ Gamma4 ascent) ---------------
 // A: n_t real cubes spaced by a_stride floats; slices: planar complex,

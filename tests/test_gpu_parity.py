@@ -56,8 +56,15 @@ def say(*a):
     ((3, 17, 128), (1.0, 0.5, 1.0), 0.8),      # (odd row counts: the last row pair has one row)
     ((2, 12, 256), (1.0, 1.0, 1.0), 3.0),
     ((6, 64, 128), (1.0, 1.0, 1.0), 1.0),      # both axes in registers
-    ((4, 149, 97), (1.0, 1.0, 1.0), 1.2),      # large prime lengths on both spatial axes (direct stages)
-    ((3, 58, 146), (0.5, 1.0, 1.0), 0.9),      # twice a prime (a radix-2 stage, then a direct one)
+    ((4, 149, 97), (1.0, 1.0, 1.0), 1.2),      # large prime lengths on both axes (DFT-matrix products)
+    ((3, 58, 146), (0.5, 1.0, 1.0), 0.9),      # twice a prime on both axes (DFT-matrix products)
+    ((3, 143, 121), (1.0, 1.0, 1.0), 1.1),     # primes 11 and 13 up to 144: DFT-matrix products
+    ((3, 156, 169), (1.0, 1.0, 1.0), 1.1),     # prime 13 above 144: the Stockham direct-DFT stages
+    ((3, 191, 40), (1.0, 0.5, 1.0), 0.6),      # h = 191: twelve row tiles in two passes
+    ((2, 197, 24), (1.0, 1.0, 1.0), 1.0),      # a prime h above the DFT-matrix limit (Stockham)
+    ((4, 34, 254), (1.0, 1.0, 1.0), 2.0),      # h = 2 * 17; w = 254: eight column tiles, even w
+    ((5, 48, 17), (1.0, 1.0, 0.5), 1.3),       # w = 17: one column tile, odd w
+    ((2, 19, 251), (0.7, 1.0, 1.0), 0.9),      # w = 251 prime, 38 rows (a ragged row strip)
 ])
 def test_zsolve_matches_oracle(shape, wts, mu):
     L = _lib()
