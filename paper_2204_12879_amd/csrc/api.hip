@@ -190,6 +190,7 @@ struct lrstv_handle_s {
     if (graph) (void)hipGraphDestroy(graph);
     if (split.fork) (void)hipEventDestroy(split.fork);
     if (split.join) (void)hipEventDestroy(split.join);
+    if (split.big) (void)hipEventDestroy(split.big);
     if (split.s2) (void)hipStreamDestroy(split.s2);
   }
 };
@@ -559,6 +560,7 @@ extern "C" int lrstv_create(lrstv_handle* out, const lrstv_problem* prob, const 
     e = hipStreamCreateWithFlags(&H->split.s2, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&H->split.fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&H->split.join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&H->split.big, hipEventDisableTiming);
     if (e != hipSuccess) {
       delete H;
       return fail(LRSTV_ERR_HIP, "creating the second stream: %s", hipGetErrorString(e));

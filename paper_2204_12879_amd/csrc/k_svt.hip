@@ -2731,7 +2731,17 @@ bool tri_variant_onchip(int v, int n) {
   return tridiag_reg_lds(n, v) <= g_tri_granted[v];
 }
 
-void launch_svt_tridiag(const SvtLaunch& L, hipStream_t s) {
+// With the register-tile kernels, slices with n <= kTriSmallN and larger
+// ones are reduced by two launches (a 4-wave shape of which three blocks fit a
+// CU, and the tuned shape of one block per CU).
+static bool tridiag_two_classes(const SvtLaunch& L) {
+  const int v = (L.tri_variant >= 0 && L.tri_variant < kTriVariants) ? L.tri_variant : kTriDefault;
+  return v >= 3 && tri_variant_onchip(v, L.max_n1) && L.min_n1 <= kTriSmallN && L.max_n1 > kTriSmallN;
+}
+
+// which: bit 0 the slices with n <= kTriSmallN, bit 1 the larger ones (the
+// register-tile kernels; other shapes take every slice either way).
+void launch_svt_tridiag(const SvtLaunch& L, hipStream_t s, int which) {
   const int n = L.max_n1, ns = L.n_slices;
   const int v = (L.tri_variant >= 0 && L.tri_variant < kTriVariants) ? L.tri_variant : kTriDefault;
   if (tri_variant_onchip(v, n)) {
@@ -2744,10 +2754,10 @@ void launch_svt_tridiag(const SvtLaunch& L, hipStream_t s) {
         // Slices with n <= 128 take a 4-wave block (three per CU: their
         // per-step latencies overlap), the others the tuned shape.
         const bool small = L.min_n1 <= kTriSmallN;
-        if (small)
+        if (small && (which & 1))
           hipLaunchKernelGGL((k_tridiag_mfma<4, 3, kTriSmallN>), dim3(ns), dim3(256), 0, s, L.desc, L.gram, L.tri,
                              L.halt, 0);
-        if (n <= kTriSmallN) break;
+        if (n <= kTriSmallN || !(which & 2)) break;
         const int nmin = small ? kTriSmallN : 0;
         if (v == 3)
           hipLaunchKernelGGL((k_tridiag_mfma<12, 3>), dim3(ns), dim3(768), 0, s, L.desc, L.gram, L.tri, L.halt, nmin);
@@ -2761,7 +2771,7 @@ void launch_svt_tridiag(const SvtLaunch& L, hipStream_t s) {
                        L.gram, L.tri, L.halt);
   }
 }
-static void launch_tridiag(const SvtLaunch& L, hipStream_t s) { launch_svt_tridiag(L, s); }
+static void launch_tridiag(const SvtLaunch& L, hipStream_t s) { launch_svt_tridiag(L, s, 3); }
 
 static void launch_gram_bf16(const SvtLaunch& L, hipStream_t s) {
   const int ns = L.n_slices, T2 = (L.max_n1 + 127) / 128;
@@ -2889,9 +2899,22 @@ void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm, const SvtSpli
     B.desc = L.desc + sp->first;
     B.rcount = L.rcount + sp->first;
     B.n_slices = ns - sp->first;
-    launch_tridiag(A, s);
-    (void)hipEventRecord(sp->fork, s);
-    (void)hipStreamWaitEvent(sp->s2, sp->fork, 0);
+    if (sp->big && tridiag_two_classes(A)) {
+      // the first group's slices above kTriSmallN (one block per CU) on the
+      // second stream beside its smaller ones (three per CU), so that the
+      // last round of either launch finds the other's blocks to run; the
+      // second group follows them there
+      (void)hipEventRecord(sp->fork, s);
+      (void)hipStreamWaitEvent(sp->s2, sp->fork, 0);
+      launch_svt_tridiag(A, sp->s2, 2);
+      launch_svt_tridiag(A, s, 1);
+      (void)hipEventRecord(sp->big, sp->s2);
+      (void)hipStreamWaitEvent(s, sp->big, 0);
+    } else {
+      launch_tridiag(A, s);
+      (void)hipEventRecord(sp->fork, s);
+      (void)hipStreamWaitEvent(sp->s2, sp->fork, 0);
+    }
     // the second group's tridiagonalisation is queued before the first
     // group's next stage, so that its blocks are placed first
     launch_tridiag(B, sp->s2);

@@ -231,6 +231,7 @@ struct SvtLaunch {
 struct SvtSplit {
   hipStream_t s2 = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
+  hipEvent_t big = nullptr;   // the first group's slices above kTriSmallN reduced (on s2)
   int first = 0;   // slices [0, first) on the main stream, the rest on s2; 0: no split
 };
 // The first group's size for n_slices slices (0: no split), from the
@@ -239,7 +240,7 @@ int svt_split_point(int n_slices);
 void launch_svt(const SvtLaunch& L, hipStream_t s, StageTimer* tm = nullptr, const SvtSplit* sp = nullptr);
 // Single stages of launch_svt (the autotuner times them in isolation).
 void launch_svt_gram(const SvtLaunch& L, hipStream_t s);
-void launch_svt_tridiag(const SvtLaunch& L, hipStream_t s);
+void launch_svt_tridiag(const SvtLaunch& L, hipStream_t s, int which = 3);
 // Host-side kernel attributes for slices up to max_n1 (call before capture).
 void prepare_svt(int max_n1);
 
