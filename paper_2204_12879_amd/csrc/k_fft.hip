@@ -796,6 +796,85 @@ LRSTV_DEV void dft_stage_coords(int t, int& sc, int& sr) {
   sr = t >> 5;
 }
 
+// One pass over the rows k in [kb, kb + 32 NQ) of a 128-column strip (NQ
+// row tiles: the passes of a short band axis take only the tiles that hold
+// slices, and the contraction stops at the last row pair j < s).
+template <int NQ>
+LRSTV_DEV void band_dft_pass(DftSmem& sm, const float* __restrict__ src, float* __restrict__ dst, int kb, int s, int b,
+                             int hw, int n0, int sc, int sr, int ncol, int wv, int li, int lk) {
+  f32x16 are[NQ], aim[NQ];
+  int idx[NQ], stp[NQ];
+  bool kok[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) are[q][e] = aim[q][e] = 0.f;
+    const int k = kb + 32 * q + li;
+    kok[q] = k < s;
+    idx[q] = (k * lk) % b;   // j = lk at the first step
+    stp[q] = (2 * k) % b;
+  }
+  // rows j and b - j of the next chunk, four columns each
+  float pa[4][4], pb[4][4];
+  auto fetch = [&](int j0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int j = j0 + sr + 8 * e, jb = b - j;
+      const bool pair = j > 0 && j < s && jb != j;
+      load4(src + (int64_t)j * hw + n0 + sc, j < s ? ncol : 0, pa[e]);
+      load4(src + (int64_t)(pair ? jb : 0) * hw + n0 + sc, pair ? ncol : 0, pb[e]);
+    }
+  };
+  fetch(0);
+  for (int j0 = 0; j0 < s; j0 += kKC) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      float pv[4], qv[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        pv[c] = pa[e][c] + pb[e][c];
+        qv[c] = pa[e][c] - pb[e][c];
+      }
+      *reinterpret_cast<float4*>(&sm.p[sr + 8 * e][sc]) = make_float4(pv[0], pv[1], pv[2], pv[3]);
+      *reinterpret_cast<float4*>(&sm.q[sr + 8 * e][sc]) = make_float4(qv[0], qv[1], qv[2], qv[3]);
+    }
+    __syncthreads();
+    if (j0 + kKC < s) fetch(j0 + kKC);
+    auto step = [&](int kk) {
+      const float bp = sm.p[2 * kk + lk][32 * wv + li], bq = sm.q[2 * kk + lk][32 * wv + li];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const float c = kok[q] ? sm.ct[idx[q]] : 0.f, sn = kok[q] ? -sm.st[idx[q]] : 0.f;
+        are[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(c, bp, are[q], 0, 0, 0);
+        aim[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(sn, bq, aim[q], 0, 0, 0);
+        idx[q] += stp[q];
+        if (idx[q] >= b) idx[q] -= b;
+      }
+    };
+    const int nkk = s - j0 < kKC ? (s - j0 + 1) >> 1 : kKC / 2;   // row pairs holding j < s
+    int kk = 0;
+    for (; kk + 4 <= nkk; kk += 4) {
+      step(kk);
+      step(kk + 1);
+      step(kk + 2);
+      step(kk + 3);
+    }
+    for (; kk < nkk; ++kk) step(kk);
+    __syncthreads();
+  }
+  const int n = n0 + 32 * wv + li;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int k = kb + 32 * q + 8 * (e >> 2) + 4 * lk + (e & 3);
+      if (k < s && n < hw) {
+        dst[(int64_t)(2 * k) * hw + n] = are[q][e];
+        dst[(int64_t)(2 * k + 1) * hw + n] = aim[q][e];
+      }
+    }
+}
+
 LRSTV_DEV void band_dft_body(int bid, int nblk, const float* __restrict__ A, int64_t a_stride, int n_t,
                              float* __restrict__ out, int hw, int b) {
   __shared__ DftSmem sm;
@@ -812,69 +891,10 @@ LRSTV_DEV void band_dft_body(int bid, int nblk, const float* __restrict__ A, int
     float* dst = out + (int64_t)tt * M * hw;
     const int ncol = hw - n0 - sc;   // columns of this thread's four that exist
     for (int kb = 0; kb < s; kb += 32 * kDftRowTiles) {
-      f32x16 are[kDftRowTiles], aim[kDftRowTiles];
-      int idx[kDftRowTiles], stp[kDftRowTiles];
-      bool kok[kDftRowTiles];
-#pragma unroll
-      for (int q = 0; q < kDftRowTiles; ++q) {
-#pragma unroll
-        for (int e = 0; e < 16; ++e) are[q][e] = aim[q][e] = 0.f;
-        const int k = kb + 32 * q + li;
-        kok[q] = k < s;
-        idx[q] = (k * lk) % b;   // j = lk at the first step
-        stp[q] = (2 * k) % b;
-      }
-      // rows j and b - j of the next chunk, four columns each
-      float pa[4][4], pb[4][4];
-      auto fetch = [&](int j0) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int j = j0 + sr + 8 * e, jb = b - j;
-          const bool pair = j > 0 && j < s && jb != j;
-          load4(src + (int64_t)j * hw + n0 + sc, j < s ? ncol : 0, pa[e]);
-          load4(src + (int64_t)(pair ? jb : 0) * hw + n0 + sc, pair ? ncol : 0, pb[e]);
-        }
-      };
-      fetch(0);
-      for (int j0 = 0; j0 < s; j0 += kKC) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          float pv[4], qv[4];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            pv[c] = pa[e][c] + pb[e][c];
-            qv[c] = pa[e][c] - pb[e][c];
-          }
-          *reinterpret_cast<float4*>(&sm.p[sr + 8 * e][sc]) = make_float4(pv[0], pv[1], pv[2], pv[3]);
-          *reinterpret_cast<float4*>(&sm.q[sr + 8 * e][sc]) = make_float4(qv[0], qv[1], qv[2], qv[3]);
-        }
-        __syncthreads();
-        if (j0 + kKC < s) fetch(j0 + kKC);
-#pragma unroll 4
-        for (int kk = 0; kk < kKC / 2; ++kk) {
-          const float bp = sm.p[2 * kk + lk][32 * wv + li], bq = sm.q[2 * kk + lk][32 * wv + li];
-#pragma unroll
-          for (int q = 0; q < kDftRowTiles; ++q) {
-            const float c = kok[q] ? sm.ct[idx[q]] : 0.f, sn = kok[q] ? -sm.st[idx[q]] : 0.f;
-            are[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(c, bp, are[q], 0, 0, 0);
-            aim[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(sn, bq, aim[q], 0, 0, 0);
-            idx[q] += stp[q];
-            if (idx[q] >= b) idx[q] -= b;
-          }
-        }
-        __syncthreads();
-      }
-      const int n = n0 + 32 * wv + li;
-#pragma unroll
-      for (int q = 0; q < kDftRowTiles; ++q)
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const int k = kb + 32 * q + 8 * (e >> 2) + 4 * lk + (e & 3);
-          if (k < s && n < hw) {
-            dst[(int64_t)(2 * k) * hw + n] = are[q][e];
-            dst[(int64_t)(2 * k + 1) * hw + n] = aim[q][e];
-          }
-        }
+      const int nq = (s - kb + 31) >> 5;   // row tiles holding slices
+      if (nq >= 3) band_dft_pass<3>(sm, src, dst, kb, s, b, hw, n0, sc, sr, ncol, wv, li, lk);
+      else if (nq == 2) band_dft_pass<2>(sm, src, dst, kb, s, b, hw, n0, sc, sr, ncol, wv, li, lk);
+      else band_dft_pass<1>(sm, src, dst, kb, s, b, hw, n0, sc, sr, ncol, wv, li, lk);
     }
   }
 }
@@ -900,6 +920,121 @@ __global__ void __launch_bounds__(256, 2) k_band_dft(const float* __restrict__ A
 // 32-row block go through LDS, so that the memory-bound epilogue (read F and
 // Gamma4, write Gamma4 and E) runs on four-wide, row-contiguous accesses
 // with four rows per thread in flight.
+// One pass over the rows j in [jb, jb + 32 NQ) of a 128-column strip (as
+// band_dft_pass: only the tiles holding rows j < s, the contraction up to
+// the last slice pair); adds to the thread's FP64 partial of (E - F)^2.
+template <int NQ>
+LRSTV_DEV void band_idft_pass(DftSmem& sm, const float* __restrict__ src, float* __restrict__ dst,
+                              const float* __restrict__ Ft, float* __restrict__ G4t, float mu, int jb, int s, int b,
+                              int hw, int n0, int sc, int sr, int ncol, int wv, int li, int lk, double& acc) {
+  f32x16 cc[NQ], ss[NQ];
+  int idx[NQ], stp[NQ];
+  bool jok[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) cc[q][e] = ss[q][e] = 0.f;
+    const int j = jb + 32 * q + li;
+    jok[q] = j < s;
+    idx[q] = (j * lk) % b;   // k = lk at the first step
+    stp[q] = (2 * j) % b;
+  }
+  // c_k Re X_k and c_k Im X_k of the next chunk of slices, four columns each
+  float pr[4][4], pi[4][4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = k0 + sr + 8 * e;
+      load4(src + (int64_t)(2 * k) * hw + n0 + sc, k < s ? ncol : 0, pr[e]);
+      load4(src + (int64_t)(2 * k + 1) * hw + n0 + sc, k < s ? ncol : 0, pi[e]);
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < s; k0 += kKC) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = k0 + sr + 8 * e;
+      const float ck = (k == 0 || 2 * k == b) ? 1.f : 2.f;
+      *reinterpret_cast<float4*>(&sm.p[sr + 8 * e][sc]) =
+          make_float4(ck * pr[e][0], ck * pr[e][1], ck * pr[e][2], ck * pr[e][3]);
+      *reinterpret_cast<float4*>(&sm.q[sr + 8 * e][sc]) =
+          make_float4(ck * pi[e][0], ck * pi[e][1], ck * pi[e][2], ck * pi[e][3]);
+    }
+    __syncthreads();
+    if (k0 + kKC < s) fetch(k0 + kKC);
+    auto step = [&](int kk) {
+      const float br = sm.p[2 * kk + lk][32 * wv + li], bi = sm.q[2 * kk + lk][32 * wv + li];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const float c = jok[q] ? sm.ct[idx[q]] : 0.f, sn = jok[q] ? sm.st[idx[q]] : 0.f;
+        cc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(c, br, cc[q], 0, 0, 0);
+        ss[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(sn, bi, ss[q], 0, 0, 0);
+        idx[q] += stp[q];
+        if (idx[q] >= b) idx[q] -= b;
+      }
+    };
+    const int nkk = s - k0 < kKC ? (s - k0 + 1) >> 1 : kKC / 2;   // row pairs holding k < s
+    int kk = 0;
+    for (; kk + 4 <= nkk; kk += 4) {
+      step(kk);
+      step(kk + 1);
+      step(kk + 2);
+      step(kk + 3);
+    }
+    for (; kk < nkk; ++kk) step(kk);
+    __syncthreads();
+  }
+  // E_j = C_j - S_j (LDS row r) and E_{b-j} = C_j + S_j (row 32 + r) of
+  // each 32-row block, then the epilogue over the block's rows
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    if (jb + 32 * q >= s) break;   // uniform
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int r = 8 * (e >> 2) + 4 * lk + (e & 3);
+      sm.et[r][32 * wv + li] = cc[q][e] - ss[q][e];
+      sm.et[32 + r][32 * wv + li] = cc[q][e] + ss[q][e];
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int u = 0; u < 8; ++u) {
+      const int r = sr + 8 * u, j = jb + 32 * q + (r & 31);
+      const bool lo_half = r < 32;
+      if (j >= s || ncol <= 0 || (!lo_half && (j == 0 || b - j == j))) continue;
+      const int64_t o = (int64_t)(lo_half ? j : b - j) * hw + n0 + sc;
+      const float4 ev = *reinterpret_cast<const float4*>(&sm.et[r][sc]);
+      const float e4[4] = {ev.x, ev.y, ev.z, ev.w};
+      const int nv = ncol < 4 ? ncol : 4;
+      if (nv == 4 && ((hw & 3) == 0)) {
+        *reinterpret_cast<float4*>(dst + o) = ev;
+        if (G4t) {
+          const float4 f = *reinterpret_cast<const float4*>(Ft + o), g = *reinterpret_cast<const float4*>(G4t + o);
+          const float f4[4] = {f.x, f.y, f.z, f.w};
+          *reinterpret_cast<float4*>(G4t + o) =
+              make_float4(g.x + mu * (e4[0] - f4[0]), g.y + mu * (e4[1] - f4[1]), g.z + mu * (e4[2] - f4[2]),
+                          g.w + mu * (e4[3] - f4[3]));
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const double dd = (double)e4[c] - (double)f4[c];
+            acc += dd * dd;
+          }
+        }
+      } else {
+        for (int c = 0; c < nv; ++c) {
+          dst[o + c] = e4[c];
+          if (G4t) {
+            const float f = Ft[o + c];
+            G4t[o + c] = G4t[o + c] + mu * (e4[c] - f);
+            const double dd = (double)e4[c] - (double)f;
+            acc += dd * dd;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 LRSTV_DEV void band_idft_body(int bid, int nblk, const float* __restrict__ X, int n_t, float* __restrict__ E,
                               int64_t e_stride, int hw, int b, const float* __restrict__ F, float* __restrict__ G4,
                               const double* __restrict__ mu_dev, double* __restrict__ part) {
@@ -922,104 +1057,10 @@ LRSTV_DEV void band_idft_body(int bid, int nblk, const float* __restrict__ X, in
     float* G4t = G4 ? G4 + tt * e_stride : nullptr;
     const int ncol = hw - n0 - sc;
     for (int jb = 0; jb < s; jb += 32 * kDftRowTiles) {
-      f32x16 cc[kDftRowTiles], ss[kDftRowTiles];
-      int idx[kDftRowTiles], stp[kDftRowTiles];
-      bool jok[kDftRowTiles];
-#pragma unroll
-      for (int q = 0; q < kDftRowTiles; ++q) {
-#pragma unroll
-        for (int e = 0; e < 16; ++e) cc[q][e] = ss[q][e] = 0.f;
-        const int j = jb + 32 * q + li;
-        jok[q] = j < s;
-        idx[q] = (j * lk) % b;   // k = lk at the first step
-        stp[q] = (2 * j) % b;
-      }
-      // c_k Re X_k and c_k Im X_k of the next chunk of slices, four columns each
-      float pr[4][4], pi[4][4];
-      auto fetch = [&](int k0) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int k = k0 + sr + 8 * e;
-          load4(src + (int64_t)(2 * k) * hw + n0 + sc, k < s ? ncol : 0, pr[e]);
-          load4(src + (int64_t)(2 * k + 1) * hw + n0 + sc, k < s ? ncol : 0, pi[e]);
-        }
-      };
-      fetch(0);
-      for (int k0 = 0; k0 < s; k0 += kKC) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int k = k0 + sr + 8 * e;
-          const float ck = (k == 0 || 2 * k == b) ? 1.f : 2.f;
-          *reinterpret_cast<float4*>(&sm.p[sr + 8 * e][sc]) =
-              make_float4(ck * pr[e][0], ck * pr[e][1], ck * pr[e][2], ck * pr[e][3]);
-          *reinterpret_cast<float4*>(&sm.q[sr + 8 * e][sc]) =
-              make_float4(ck * pi[e][0], ck * pi[e][1], ck * pi[e][2], ck * pi[e][3]);
-        }
-        __syncthreads();
-        if (k0 + kKC < s) fetch(k0 + kKC);
-#pragma unroll 4
-        for (int kk = 0; kk < kKC / 2; ++kk) {
-          const float br = sm.p[2 * kk + lk][32 * wv + li], bi = sm.q[2 * kk + lk][32 * wv + li];
-#pragma unroll
-          for (int q = 0; q < kDftRowTiles; ++q) {
-            const float c = jok[q] ? sm.ct[idx[q]] : 0.f, sn = jok[q] ? sm.st[idx[q]] : 0.f;
-            cc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(c, br, cc[q], 0, 0, 0);
-            ss[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(sn, bi, ss[q], 0, 0, 0);
-            idx[q] += stp[q];
-            if (idx[q] >= b) idx[q] -= b;
-          }
-        }
-        __syncthreads();
-      }
-      // E_j = C_j - S_j (LDS row r) and E_{b-j} = C_j + S_j (row 32 + r) of
-      // each 32-row block, then the epilogue over the block's rows
-#pragma unroll
-      for (int q = 0; q < kDftRowTiles; ++q) {
-        if (jb + 32 * q >= s) break;   // uniform
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const int r = 8 * (e >> 2) + 4 * lk + (e & 3);
-          sm.et[r][32 * wv + li] = cc[q][e] - ss[q][e];
-          sm.et[32 + r][32 * wv + li] = cc[q][e] + ss[q][e];
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int u = 0; u < 8; ++u) {
-          const int r = sr + 8 * u, j = jb + 32 * q + (r & 31);
-          const bool lo_half = r < 32;
-          if (j >= s || ncol <= 0 || (!lo_half && (j == 0 || b - j == j))) continue;
-          const int64_t o = (int64_t)(lo_half ? j : b - j) * hw + n0 + sc;
-          const float4 ev = *reinterpret_cast<const float4*>(&sm.et[r][sc]);
-          const float e4[4] = {ev.x, ev.y, ev.z, ev.w};
-          const int nv = ncol < 4 ? ncol : 4;
-          if (nv == 4 && ((hw & 3) == 0)) {
-            *reinterpret_cast<float4*>(dst + o) = ev;
-            if (G4t) {
-              const float4 f = *reinterpret_cast<const float4*>(Ft + o), g = *reinterpret_cast<const float4*>(G4t + o);
-              const float f4[4] = {f.x, f.y, f.z, f.w};
-              *reinterpret_cast<float4*>(G4t + o) =
-                  make_float4(g.x + mu * (e4[0] - f4[0]), g.y + mu * (e4[1] - f4[1]), g.z + mu * (e4[2] - f4[2]),
-                              g.w + mu * (e4[3] - f4[3]));
-#pragma unroll
-              for (int c = 0; c < 4; ++c) {
-                const double dd = (double)e4[c] - (double)f4[c];
-                acc += dd * dd;
-              }
-            }
-          } else {
-            for (int c = 0; c < nv; ++c) {
-              dst[o + c] = e4[c];
-              if (G4t) {
-                const float f = Ft[o + c];
-                G4t[o + c] = G4t[o + c] + mu * (e4[c] - f);
-                const double dd = (double)e4[c] - (double)f;
-                acc += dd * dd;
-              }
-            }
-          }
-        }
-        __syncthreads();
-      }
+      const int nq = (s - jb + 31) >> 5;   // row tiles holding rows j < s
+      if (nq >= 3) band_idft_pass<3>(sm, src, dst, Ft, G4t, mu, jb, s, b, hw, n0, sc, sr, ncol, wv, li, lk, acc);
+      else if (nq == 2) band_idft_pass<2>(sm, src, dst, Ft, G4t, mu, jb, s, b, hw, n0, sc, sr, ncol, wv, li, lk, acc);
+      else band_idft_pass<1>(sm, src, dst, Ft, G4t, mu, jb, s, b, hw, n0, sc, sr, ncol, wv, li, lk, acc);
     }
   }
   if (part) {
