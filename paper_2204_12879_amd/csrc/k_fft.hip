@@ -379,7 +379,7 @@ LRSTV_DEV void dft_reg(float2 (&v)[R]) {
   }
 }
 
-constexpr int kFftRegCols = 16;   // columns per block (one 128-byte row segment)
+constexpr int kFftRegCols = 32;   // columns per block (two 128-byte row segments)
 template <int P, int Q>
 constexpr int fft_reg_threads() { return kFftRegCols * (P > Q ? P : Q); }
 
@@ -1314,7 +1314,7 @@ void launch_fft_h(float2* spec, int h, int w, int b, int sign, hipStream_t s) {
     return;
   }
   const int wc = w / 2 + 1;
-  const int cw = cols_cw(h);
+  const int cw = fft_h_reg_bit(h) ? kFftRegCols : cols_cw(h);
   const int64_t g = ((int64_t)b * wc + cw - 1) / cw;
   const int grid = (int)(g < 8192 ? g : 8192);
   if (sign < 0 ? launch_fft_h_reg<-1>(spec, h, wc, b, grid, nullptr, s) : launch_fft_h_reg<1>(spec, h, wc, b, grid, nullptr, s))
@@ -1378,7 +1378,7 @@ int phase_blocks(int phase, int h, int w, int b) {
     }
     case PH_FFT_H: {
       if (dft_mm_len(h, kMmMaxH)) return dftmm_blocks_h(h, w, b);
-      const int cw = cols_cw(h);
+      const int cw = fft_h_reg_bit(h) ? kFftRegCols : cols_cw(h);
       const int64_t g = ((int64_t)b * wc + cw - 1) / cw;
       return (int)(g < 8192 ? g : 8192);
     }
