@@ -65,6 +65,7 @@ def say(*a):
     ((4, 34, 254), (1.0, 1.0, 1.0), 2.0),      # h = 2 * 17; w = 254: eight column tiles, even w
     ((5, 48, 17), (1.0, 1.0, 0.5), 1.3),       # w = 17: one column tile, odd w
     ((2, 19, 251), (0.7, 1.0, 1.0), 0.9),      # w = 251 prime, 38 rows (a ragged row strip)
+    ((2, 6, 263), (1.0, 1.0, 1.0), 1.0),       # a prime w above the DFT-matrix limit (Stockham)
 ])
 def test_zsolve_matches_oracle(shape, wts, mu):
     L = _lib()
