@@ -110,7 +110,7 @@ LRSTV_DEV void dftmm_h_body(int bid, int nblk, float* sm, float2* __restrict__ s
   const int nrt = (h + 15) >> 4, ntw = wv < nrt ? (nrt - wv + 3) >> 2 : 0;
   const int64_t ncol = (int64_t)b * wc, plane = (int64_t)h * wc;
   const int64_t nstrip = (ncol + 15) >> 4;
-  for (int64_t st = bid; st < nstrip; st += nblk) {
+  for (int64_t st = xcd_block(bid, nblk); st < nstrip; st += nblk) {
     const int64_t g = st * 16 + cl;
     const bool ok = g < ncol;
     const int64_t j = ok ? g / wc : 0;

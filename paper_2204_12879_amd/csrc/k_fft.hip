@@ -310,7 +310,7 @@ LRSTV_DEV void fft_h_body(int bid, int nblk, float2* sm, float2* __restrict__ sp
   const int64_t nchunk = (ncol + cw - 1) / cw;
   // blockDim is a multiple of cw, so a thread keeps its column f
   const int f = threadIdx.x % cw, i0 = threadIdx.x / cw, di = blockDim.x / cw;
-  for (int64_t blk = bid; blk < nchunk; blk += nblk) {
+  for (int64_t blk = xcd_block(bid, nblk); blk < nchunk; blk += nblk) {
     const int64_t g = blk * cw + f;
     const bool ok = g < ncol;
     const int64_t j = ok ? g / wc : 0;
@@ -396,7 +396,7 @@ LRSTV_DEV void fft_h_reg_body(int bid, int nblk, float2* __restrict__ spec, int 
   const int c = threadIdx.x % C, rr = threadIdx.x / C;
   const int64_t ncol = (int64_t)b * wc, plane = (int64_t)N * wc;
   const int64_t nchunk = (ncol + C - 1) / C;
-  for (int64_t blk = bid; blk < nchunk; blk += nblk) {
+  for (int64_t blk = xcd_block(bid, nblk); blk < nchunk; blk += nblk) {
     const int64_t g = blk * C + c;
     const bool ok = g < ncol;
     const int64_t j = ok ? g / wc : 0;

@@ -114,6 +114,16 @@ __device__ __forceinline__ CubeSel select_cube(const BatchTab& bt) {
   r.nblk = __builtin_amdgcn_readfirstlane(bt.bstart[r.c + 1] - bt.bstart[r.c]);
   return r;
 }
+// XCD-aware order of a cube's blocks over its column chunks.  Blocks are
+// dispatched to the 8 XCDs in turn, so the blocks of one residue class mod 8
+// share an XCD and its L2; they take consecutive chunks, and the cache lines
+// that two neighbouring chunks share are fetched into one L2 instead of two.
+// A bijection of [0, nblk): the chunks bid', bid' + nblk, ... of the returned
+// bid' still cover every chunk once.
+__device__ __forceinline__ int xcd_block(int bid, int nblk) {
+  const int c = bid & 7, full = nblk >> 3, rem = nblk & 7;
+  return c * full + (c < rem ? c : rem) + (bid >> 3);
+}
 int geo_rows_nb(int w);
 int geo_rows_nb_inv(int w);
 int geo_cols_cw(int h);
