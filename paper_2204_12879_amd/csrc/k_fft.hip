@@ -765,12 +765,14 @@ __global__ void __launch_bounds__(kTriCols * kTriChunks, MAXL <= 16 ? 4 : 2) k_t
 // wave q forms both parts for its 32 columns and up to 96 slices at a time
 // (three 32-row accumulators per part).  P and Q are formed as the strip is
 // staged through LDS in chunks of 32 rows j; the cos / sin operands come
-// from an LDS table of (2 pi i / b), their common index k j mod b advanced
-// by 2k mod b per step.
+// from an LDS table of (2 pi m / b) as (cos, sin) pairs (one read for both
+// products), their common index m = k j mod b advanced by 2k mod b per step.
 constexpr int kDftRowTiles = 3;
 constexpr int kDftCols = 128;   // strip width of both band transforms
 struct DftSmem {
-  float ct[LRSTV_MAX_SIDE_DEV], st[LRSTV_MAX_SIDE_DEV];
+  // (cos, -sin)(2 pi m / b) (forward) or (cos, sin)(2 pi m / b) / b (inverse)
+  // for m < b, and (0, 0) at m = b: the entry of the rows past the last slice
+  float2 cs[LRSTV_MAX_SIDE_DEV + 1];
   union {
     struct {
       __align__(16) float p[kKC][kDftCols + 4], q[kKC][kDftCols + 4];
@@ -778,16 +780,6 @@ struct DftSmem {
     __align__(16) float et[2 * kKC][kDftCols + 4];   // inverse: E rows j, b - j of one 32-row block
   };
 };
-
-// cos / sin (2 pi m / b) times scale, m < b, into the block's table
-LRSTV_DEV void dft_table(DftSmem& sm, int b, double scale) {
-  for (int m = threadIdx.x; m < b; m += blockDim.x) {
-    double sv, cv;
-    sincospi(2.0 * (double)m / (double)b, &sv, &cv);
-    sm.ct[m] = (float)(cv * scale);
-    sm.st[m] = (float)(sv * scale);
-  }
-}
 
 // Staging coordinates of a 32 x 128 chunk: thread t holds four columns of
 // rows t / 32 + 8 e, e = 0..3.
@@ -804,15 +796,14 @@ LRSTV_DEV void band_dft_pass(DftSmem& sm, const float* __restrict__ src, float* 
                              int hw, int n0, int sc, int sr, int ncol, int wv, int li, int lk) {
   f32x16 are[NQ], aim[NQ];
   int idx[NQ], stp[NQ];
-  bool kok[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) are[q][e] = aim[q][e] = 0.f;
     const int k = kb + 32 * q + li;
-    kok[q] = k < s;
-    idx[q] = (k * lk) % b;   // j = lk at the first step
-    stp[q] = (2 * k) % b;
+    // rows k >= s read the zero entry b, which the step b keeps in place
+    idx[q] = k < s ? (k * lk) % b : b;   // j = lk at the first step
+    stp[q] = k < s ? (2 * k) % b : b;
   }
   // rows j and b - j of the next chunk, four columns each
   float pa[4][4], pb[4][4];
@@ -844,9 +835,9 @@ LRSTV_DEV void band_dft_pass(DftSmem& sm, const float* __restrict__ src, float* 
       const float bp = sm.p[2 * kk + lk][32 * wv + li], bq = sm.q[2 * kk + lk][32 * wv + li];
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const float c = kok[q] ? sm.ct[idx[q]] : 0.f, sn = kok[q] ? -sm.st[idx[q]] : 0.f;
-        are[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(c, bp, are[q], 0, 0, 0);
-        aim[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(sn, bq, aim[q], 0, 0, 0);
+        const float2 cs = sm.cs[idx[q]];
+        are[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(cs.x, bp, are[q], 0, 0, 0);
+        aim[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(cs.y, bq, aim[q], 0, 0, 0);
         idx[q] += stp[q];
         if (idx[q] >= b) idx[q] -= b;
       }
@@ -878,7 +869,11 @@ LRSTV_DEV void band_dft_pass(DftSmem& sm, const float* __restrict__ src, float* 
 LRSTV_DEV void band_dft_body(int bid, int nblk, const float* __restrict__ A, int64_t a_stride, int n_t,
                              float* __restrict__ out, int hw, int b) {
   __shared__ DftSmem sm;
-  dft_table(sm, b, 1.0);
+  for (int m = threadIdx.x; m <= b; m += blockDim.x) {
+    double sv = 0.0, cv = 0.0;
+    if (m < b) sincospi(2.0 * (double)m / (double)b, &sv, &cv);
+    sm.cs[m] = make_float2((float)cv, (float)-sv);
+  }
   __syncthreads();
   const int s = b / 2 + 1, M = 2 * s;
   const int TN = (hw + kDftCols - 1) / kDftCols, nstrips = n_t * TN;
@@ -929,15 +924,14 @@ LRSTV_DEV void band_idft_pass(DftSmem& sm, const float* __restrict__ src, float*
                               int hw, int n0, int sc, int sr, int ncol, int wv, int li, int lk, double& acc) {
   f32x16 cc[NQ], ss[NQ];
   int idx[NQ], stp[NQ];
-  bool jok[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) cc[q][e] = ss[q][e] = 0.f;
     const int j = jb + 32 * q + li;
-    jok[q] = j < s;
-    idx[q] = (j * lk) % b;   // k = lk at the first step
-    stp[q] = (2 * j) % b;
+    // rows j >= s read the zero entry b, which the step b keeps in place
+    idx[q] = j < s ? (j * lk) % b : b;   // k = lk at the first step
+    stp[q] = j < s ? (2 * j) % b : b;
   }
   // c_k Re X_k and c_k Im X_k of the next chunk of slices, four columns each
   float pr[4][4], pi[4][4];
@@ -966,7 +960,8 @@ LRSTV_DEV void band_idft_pass(DftSmem& sm, const float* __restrict__ src, float*
       const float br = sm.p[2 * kk + lk][32 * wv + li], bi = sm.q[2 * kk + lk][32 * wv + li];
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const float c = jok[q] ? sm.ct[idx[q]] : 0.f, sn = jok[q] ? sm.st[idx[q]] : 0.f;
+        const float2 cs = sm.cs[idx[q]];
+        const float c = cs.x, sn = cs.y;
         cc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(c, br, cc[q], 0, 0, 0);
         ss[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(sn, bi, ss[q], 0, 0, 0);
         idx[q] += stp[q];
@@ -1040,7 +1035,11 @@ LRSTV_DEV void band_idft_body(int bid, int nblk, const float* __restrict__ X, in
                               const double* __restrict__ mu_dev, double* __restrict__ part) {
   __shared__ DftSmem sm;
   __shared__ double red[4];
-  dft_table(sm, b, 1.0 / (double)b);
+  for (int m = threadIdx.x; m <= b; m += blockDim.x) {
+    double sv = 0.0, cv = 0.0;
+    if (m < b) sincospi(2.0 * (double)m / (double)b, &sv, &cv);
+    sm.cs[m] = make_float2((float)(cv * (1.0 / (double)b)), (float)(sv * (1.0 / (double)b)));
+  }
   __syncthreads();
   const float mu = G4 ? (float)(*mu_dev) : 0.f;
   const int s = b / 2 + 1, K2 = 2 * s;
