@@ -1373,7 +1373,7 @@ int phase_blocks(int phase, int h, int w, int b) {
     case PH_LRHS: {
       // one element per thread up to 16.7 M voxels: more loads in flight than
       // a grid-stride loop over fewer blocks (8192 blocks took 0.147 ms at
-      // 256 x 256 x 191, 48,896 take 0.135)
+      // 256 x 256 x 191, 48,896 take 0.132)
       const int64_t g = (N + 255) / 256;
       return (int)(g < 65536 ? g : 65536);
     }
